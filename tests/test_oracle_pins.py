@@ -1,0 +1,387 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself:
+textbook closed forms, values printed in the paper, dense / brute-force
+references on tiny inputs, library routines for textbook problems, and
+invariants.  CPU only."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import workloads as wl
+from oracle import exact, linalg, operators, solvers, ttn, ttno
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_facts.json")))
+
+
+# ------------------------------------------------------------------ operators
+
+@pytest.mark.parametrize("d", [1, 2, 5, 9, 14])
+def test_fbr_harmonic_is_exactly_diagonal(d):
+    # textbook: omega/2 (p^2 + q^2) = omega (n + 1/2) in the HO eigenbasis
+    q2 = operators.ho_qpow(d, 2)
+    p2 = operators.ho_p2(d)
+    np.testing.assert_allclose(0.5 * (p2 + q2), np.diag(np.arange(d) + 0.5), atol=1e-13)
+
+
+def test_q_moments_and_projection():
+    # Gaussian ground-state moments <q^2> = 1/2, <q^4> = 3/4, <q^6> = 15/8
+    for n, ref in ((2, 0.5), (4, 0.75), (6, 15.0 / 8.0)):
+        assert abs(operators.ho_qpow(7, n)[0, 0] - ref) < 1e-13
+    # exact projection: the d x d block of q^n does not change with a bigger host basis
+    big = np.linalg.matrix_power(operators.ho_q(60), 3)[:8, :8]
+    np.testing.assert_allclose(operators.ho_qpow(8, 3), big, atol=1e-12)
+    # odd powers are off-diagonal-parity, all are symmetric
+    q3 = operators.ho_qpow(6, 3)
+    assert np.allclose(q3, q3.T) and np.allclose(np.diag(q3), 0)
+
+
+def test_dvr_hand_values():
+    for N, key in ((1, "dvr_kinetic_N1"), (2, "dvr_kinetic_N2")):
+        np.testing.assert_allclose(operators.dvr_kinetic(N), np.array(GOLD[key]["value"]), atol=1e-14)
+
+
+@pytest.mark.parametrize("N", [3, 6, 8, 9, 14])
+def test_dvr_spectrum_law(N):
+    # omega/2 (T + X^2) has omega (n + 1/2), n < N-1, plus one level at omega (3N-2)/4
+    x = operators.hermite_nodes(N)
+    ev = np.sort(np.linalg.eigvalsh(0.5 * (operators.dvr_kinetic(N) + np.diag(x ** 2))))
+    ref = np.sort(np.concatenate([np.arange(N - 1) + 0.5, [(3 * N - 2) / 4.0]]))
+    np.testing.assert_allclose(ev, ref, atol=1e-11)
+
+
+# ------------------------------------------------------------------ TTNO
+
+def _tiny_model():
+    m = wl.coupled_oscillators(4, 5, 500, 3000, 3, n_cubic=2, name="tiny")
+    m.monomials.append(((1, 4),))
+    m.coefs = np.append(m.coefs, 2.5)
+    m.monomials.append(((0, 1), (2, 2), (3, 1)))
+    m.coefs = np.append(m.coefs, -1.25)
+    return m
+
+
+def _tiny_trees(dims):
+    return [wl.mps_tree(dims, 1), wl.mps_tree(dims, 0), wl.binary_tree(dims), wl.fork_tree(dims, 2, 1)]
+
+
+@pytest.mark.parametrize("ti", range(4))
+@pytest.mark.parametrize("compress", [False, True])
+def test_ttno_equals_kronecker_sop(ti, compress):
+    m = _tiny_model()
+    tree = _tiny_trees(m.dims)[ti]
+    W = ttno.build_ttno(tree, m, compress=compress)
+    H = ttno.ttno_to_dense(tree, W)
+    Hs = exact.sop_dense_matrix(m)
+    assert np.abs(H - Hs).max() <= 1e-12 * np.abs(Hs).max()
+
+
+def _schmidt_rank(H, dims, inside):
+    L = len(dims)
+    T = H.reshape(list(dims) + list(dims))
+    outside = [i for i in range(L) if i not in inside]
+    axes = [i for i in inside] + [L + i for i in inside] + [i for i in outside] + [L + i for i in outside]
+    M = np.transpose(T, axes).reshape(int(np.prod([dims[i] ** 2 for i in inside])), -1)
+    s = np.linalg.svd(M, compute_uv=False)
+    return int(np.sum(s > 1e-12 * s[0]))
+
+
+@pytest.mark.parametrize("ti", range(4))
+def test_ttno_bonds_are_operator_schmidt_ranks(ti):
+    m = _tiny_model()
+    tree = _tiny_trees(m.dims)[ti]
+    W = ttno.build_ttno(tree, m)
+    Hs = exact.sop_dense_matrix(m)
+    bonds = ttno.ttno_bonds(tree, W)
+    for u in range(tree.n):
+        if tree.parent[u] < 0:
+            continue
+        inside = sorted(tree.mode[x] for x in tree.subtree(u) if tree.mode[x] >= 0)
+        assert bonds[u] == _schmidt_rank(Hs, m.dims, inside)
+
+
+def test_paper_64d_model_bond_and_terms():
+    m = wl.paper_64d_model()
+    assert m.n_terms == GOLD["coupled64_terms"]["value"]
+    for tree in (wl.mps_tree(m.dims, 31), wl.binary_tree(m.dims)):
+        W = ttno.build_ttno(tree, m)
+        assert max(ttno.ttno_bonds(tree, W)) == GOLD["coupled64_max_ttno_bond"]["value"]
+
+
+def test_c3_term_split_matches_paper_shape():
+    m = wl.make_config_model("c3")
+    n3 = sum(1 for mono in m.monomials if sum(p for _, p in mono) == 3)
+    n4 = sum(1 for mono in m.monomials if sum(p for _, p in mono) == 4)
+    assert [m.n_modes, n3, n4] == GOLD["ch3cn_terms"]["value"]
+
+
+def _product_state(tree, bonds, vecs):
+    st = []
+    for u in range(tree.n):
+        shp = wl.node_shape(tree, bonds, u)
+        t = np.zeros(shp)
+        idx = tuple([0] * (len(shp) - 1))
+        if tree.mode[u] >= 0:
+            t[idx] = vecs[tree.mode[u]]
+        else:
+            t[idx + (0,)] = 1.0
+        st.append(t)
+    return st
+
+
+@pytest.mark.parametrize("cfg", ["c2", "c3"])
+def test_ttno_product_state_expectation_full_scale(cfg):
+    m = wl.make_config_model(cfg)
+    tree = wl.binary_tree(m.dims) if cfg == "c2" else wl.fork_tree(m.dims, 4, 1)
+    W = ttno.build_ttno(tree, m)
+    rng = np.random.default_rng(11)
+    vecs = [rng.normal(size=d) for d in m.dims]
+    vecs = [v / np.linalg.norm(v) for v in vecs]
+    st = _product_state(tree, [1] * tree.n, vecs)
+    got = ttn.expectation(tree, st, W, st)
+    ref = 0.0
+    for i in range(m.n_modes):
+        on, _ = operators.mode_operators(m.dims[i], float(m.omega[i]))
+        ref += vecs[i] @ on @ vecs[i]
+    for mono, c in zip(m.monomials, m.coefs):
+        t = c
+        for i, p in mono:
+            t *= vecs[i] @ operators.ho_qpow(m.dims[i], p) @ vecs[i]
+        ref += t
+    assert abs(got - ref) <= 1e-10 * max(1.0, abs(ref))
+
+
+# ------------------------------------------------------------------ environments, H_eff
+
+def _c3_small():
+    m = wl.quartic_force_field(8, 21, 20, 30, name="small-qff")
+    tree = wl.fork_tree(m.dims, 4, 1)
+    return m, tree
+
+
+def test_closure_independent_of_node_and_edge():
+    m, tree = _c3_small()
+    W = ttno.build_ttno(tree, m)
+    bonds = wl.bond_dims(tree, 6)
+    blk = wl.random_block(tree, bonds, 2, 5)
+    vals = [ttn.expectation(tree, blk[0], W, blk[1], at=u) for u in range(tree.n)]
+    assert np.ptp(vals) <= 1e-12 * abs(vals[0])
+    # on every edge: sum E_{u->v} E_{v->u}
+    for u in range(tree.n):
+        v = tree.parent[u]
+        if v < 0:
+            continue
+        Eu = ttn.all_envs_toward(tree, v, blk[0], W, blk[1])[(u, v)]
+        Ev = ttn.all_envs_toward(tree, u, blk[0], W, blk[1])[(v, u)]
+        assert abs(np.sum(Eu * Ev) - vals[0]) <= 1e-12 * abs(vals[0])
+
+
+def test_identity_environment_of_canonical_state():
+    m, tree = _c3_small()
+    bonds = wl.bond_dims(tree, 6)
+    st = ttn.canonicalize(tree, wl.random_block(tree, bonds, 1, 3)[0], tree.root)
+    envs = ttn.all_envs_toward(tree, tree.root, st, None, st)
+    for (u, v), E in envs.items():
+        np.testing.assert_allclose(E[:, 0, :], np.eye(E.shape[0]), atol=1e-13)
+
+
+@pytest.mark.parametrize("ti", range(4))
+def test_expectation_matches_dense(ti):
+    m = _tiny_model()
+    tree = _tiny_trees(m.dims)[ti]
+    W = ttno.build_ttno(tree, m)
+    bonds = wl.bond_dims(tree, 4)
+    blk = wl.random_block(tree, bonds, 2, 9)
+    Hs = exact.sop_dense_matrix(m)
+    v0, v1 = ttn.to_dense(tree, blk[0]), ttn.to_dense(tree, blk[1])
+    assert abs(ttn.expectation(tree, blk[0], W, blk[1]) - v0 @ Hs @ v1) <= 1e-11 * np.abs(Hs).max() * np.linalg.norm(v0) * np.linalg.norm(v1)
+    assert abs(ttn.expectation(tree, blk[0], None, blk[1]) - v0 @ v1) <= 1e-12 * np.linalg.norm(v0) * np.linalg.norm(v1)
+
+
+def test_heff_is_projected_hamiltonian_c1():
+    m = wl.make_config_model("c1")
+    tree = wl.mps_tree(m.dims, 2)
+    W = ttno.build_ttno(tree, m)
+    bonds = wl.bond_dims(tree, 8)
+    u = 3
+    st = ttn.canonicalize(tree, wl.random_block(tree, bonds, 1, 4)[0], u)
+    envs = ttn.all_envs_toward(tree, u, st, W, st)
+    ein = {c: envs[(c, u)] for c in ttn.nbrs(tree, u)}
+    Heff = ttn.heff_dense(tree, u, W[u], ein)
+    P = ttn.isometry_at(tree, st, u)
+    np.testing.assert_allclose(P.T @ P, np.eye(P.shape[1]), atol=1e-12)
+    HP = np.stack([exact.sop_apply_dense(m, P[:, i]) for i in range(P.shape[1])], axis=1)
+    ref = P.T @ HP
+    assert np.abs(Heff - ref).max() <= 1e-10 * np.abs(ref).max()
+    assert np.abs(Heff - Heff.T).max() <= 1e-12 * np.abs(Heff).max()
+    diag = ttn.heff_diag(tree, u, W[u], ein).ravel()
+    np.testing.assert_allclose(diag, np.diag(Heff), atol=1e-10 * np.abs(Heff).max())
+
+
+# ------------------------------------------------------------------ dense solvers
+
+def test_rayleigh_ritz_matches_generalized_eigh():
+    rng = np.random.default_rng(2)
+    m = 24
+    A = rng.normal(size=(m, m))
+    H = A + A.T
+    B = rng.normal(size=(m, m))
+    S = B @ B.T + m * np.eye(m)
+    lam, V, rank = linalg.rayleigh_ritz(H, S, 8)
+    ref = scipy.linalg.eigh(H, S, eigvals_only=True)[:8]
+    np.testing.assert_allclose(lam, ref, atol=1e-11)
+    np.testing.assert_allclose(V.T @ S @ V, np.eye(8), atol=1e-11)
+    np.testing.assert_allclose(V.T @ H @ V, np.diag(lam), atol=1e-10)
+    assert rank == m
+    for j in range(8):
+        assert V[np.argmax(np.abs(V[:, j])), j] > 0
+
+
+def test_rayleigh_ritz_svqb_on_rank_deficient_overlap():
+    rng = np.random.default_rng(3)
+    n, m = 40, 10
+    Hbig = rng.normal(size=(n, n))
+    Hbig = Hbig + Hbig.T
+    X = rng.normal(size=(n, m))
+    X[:, 9] = X[:, 2]  # duplicated direction -> singular S
+    H, S = X.T @ Hbig @ X, X.T @ X
+    lam, V, rank = linalg.rayleigh_ritz(H, S, 5)
+    assert rank == 9
+    Q, _ = np.linalg.qr(X[:, :9])
+    ref = np.linalg.eigvalsh(Q.T @ Hbig @ Q)[:5]
+    np.testing.assert_allclose(lam, ref, atol=1e-9)
+
+
+def _krylov_minimizer(A, b, k):
+    K = np.zeros((len(b), k))
+    v = b.copy()
+    for i in range(k):
+        K[:, i] = v
+        v = A @ v
+    Q, _ = np.linalg.qr(K)
+    y, *_ = np.linalg.lstsq(A @ Q, b, rcond=None)
+    return Q @ y
+
+
+def test_minres_iterates_are_krylov_minimizers():
+    rng = np.random.default_rng(4)
+    n = 120
+    Z = rng.normal(size=(n, n))
+    A = Z + Z.T + 0.5 * np.diag(rng.normal(size=n))  # symmetric indefinite
+    b = rng.normal(size=n)
+    for k in (1, 2, 5, 12):
+        x, it, res = linalg.minres(lambda v: A @ v, b, np.zeros(n), 0.0, k)
+        xref = _krylov_minimizer(A, b, k)
+        assert it == k
+        assert np.linalg.norm(x - xref) <= 1e-8 * np.linalg.norm(xref)
+        assert abs(res - np.linalg.norm(b - A @ x)) <= 1e-8 * np.linalg.norm(b)
+
+
+def test_minres_solves_indefinite_system():
+    rng = np.random.default_rng(5)
+    n = 200
+    Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    ev = np.concatenate([rng.uniform(-3, -0.5, 80), rng.uniform(0.5, 4, 120)])
+    A = Q @ np.diag(ev) @ Q.T
+    b = rng.normal(size=n)
+    x, it, res = linalg.minres(lambda v: A @ v, b, np.zeros(n), 1e-12, 2000)
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=1e-8, atol=1e-9)
+    # warm start from the solution: no iteration needed
+    x2, it2, _ = linalg.minres(lambda v: A @ v, b, x, 1e-6, 10)
+    assert it2 == 0
+
+
+def test_lanczos_c1_matches_normal_modes():
+    m = wl.make_config_model("c1")
+    n = int(np.prod(m.dims))
+    ev = linalg.lanczos_lowest(lambda v: exact.sop_apply_dense(m, v), n, 10, maxdim=600, tol=1e-12)
+    ex = exact.normal_mode_levels(m, 10)
+    assert np.max(np.abs(ev - ex)) < 1e-6
+
+
+def test_normal_modes_match_dense_diagonalisation():
+    # 3 modes, large FBR basis: the truncated spectrum converges to the closed form
+    m = wl.coupled_oscillators(3, 7, 500, 3000, 18, coupling_scale=0.1)
+    H = exact.sop_dense_matrix(m)
+    ev = np.linalg.eigvalsh(H)[:10]
+    np.testing.assert_allclose(ev, exact.normal_mode_levels(m, 10), atol=1e-6)
+
+
+# ------------------------------------------------------------------ ALS / fitting
+
+def test_fit_state_to_itself():
+    m, tree = _c3_small()
+    bonds = wl.bond_dims(tree, 6)
+    st = solvers.normalized(tree, wl.random_block(tree, bonds, 1, 8)[0])
+    init = solvers.normalized(tree, wl.random_block(tree, bonds, 1, 9)[0])
+    y = solvers.fit(tree, [(1.0, None, st)], init, sweeps=2)
+    ov = ttn.expectation(tree, y, None, st)
+    assert abs(ov - 1.0) < 1e-10
+    assert abs(ttn.expectation(tree, y, None, y) - 1.0) < 1e-10
+
+
+def test_fit_linear_combination_full_bond_is_exact():
+    m = _tiny_model()
+    tree = wl.binary_tree(m.dims)
+    bonds = wl.bond_dims(tree, 100)  # full bonds: the fit is exact
+    blk = wl.random_block(tree, bonds, 3, 12)
+    W = ttno.build_ttno(tree, m)
+    src = [(0.7, W, blk[0]), (-1.3, None, blk[1]), (0.25, None, blk[2])]
+    y = solvers.fit(tree, src, blk[2], sweeps=2)
+    Hs = exact.sop_dense_matrix(m)
+    ref = 0.7 * Hs @ ttn.to_dense(tree, blk[0]) - 1.3 * ttn.to_dense(tree, blk[1]) + 0.25 * ttn.to_dense(tree, blk[2])
+    got = ttn.to_dense(tree, y)
+    assert np.linalg.norm(got - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_als_full_bond_matches_dense_solve():
+    m = _tiny_model()
+    tree = wl.mps_tree(m.dims, 1)
+    W = ttno.build_ttno(tree, m)
+    bonds = wl.bond_dims(tree, 100)
+    phi = wl.random_block(tree, bonds, 1, 14)[0]
+    Hs = exact.sop_dense_matrix(m)
+    s = float(np.linalg.eigvalsh(Hs)[0]) - 300.0  # positive-definite shift
+    y = solvers.als_solve(tree, W, s, phi, phi, sweeps=6, maxiter=500, rtol=1e-13)
+    ref = np.linalg.solve(Hs - s * np.eye(len(Hs)), ttn.to_dense(tree, phi))
+    assert np.linalg.norm(ttn.to_dense(tree, y) - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+# ------------------------------------------------------------------ eigensolvers
+
+def test_clusters_single_linkage():
+    lam = np.array([10.0, 3.0, 4.0, 30.0, 8.9, 33.5])
+    cl = solvers.clusters_of(lam, 5.0)
+    assert [sorted(c) for c in cl] == [[1, 2, 4, 0], [3, 5]] or [sorted(c) for c in cl] == [[0, 1, 2, 4], [3, 5]]
+
+
+def test_uncoupled_product_states_are_exact_at_bond_one():
+    # c = 0: the lowest product states are exact eigenstates; their energies
+    # sum_i omega_i n_i (shifted frame) come out of the TTNO expectation
+    m = wl.make_config_model("c1")
+    m.monomials, m.coefs = [], np.zeros(0)
+    tree = wl.mps_tree(m.dims, 2)
+    W = ttno.build_ttno(tree, m)
+    occ = wl.lowest_product_states(m.omega, m.dims, 6)
+    for n in occ:
+        vecs = [np.eye(d)[n[i]] for i, d in enumerate(m.dims)]
+        st = _product_state(tree, [1] * tree.n, vecs)
+        assert abs(ttn.expectation(tree, st, W, st) - float(np.dot(m.omega, n))) < 1e-10
+
+
+@pytest.mark.slow
+def test_lobpcg_c1_reaches_closed_form():
+    m = wl.make_config_model("c1")
+    tree = wl.mps_tree(m.dims, 2)
+    W = ttno.build_ttno(tree, m)
+    bonds = wl.bond_dims(tree, 8)
+    x0 = wl.initial_block(tree, bonds, m.omega, m.dims, 10, m.seed + 17)
+    lam0 = solvers.rayleigh_quotients(tree, W, [solvers.normalized(tree, x) for x in x0])
+    opts = solvers.LobpcgOptions(n_iter=7, shift=float(np.min(lam0)) - 837.0)
+    xs, lam = solvers.lobpcg(tree, W, x0, opts)
+    ex = exact.normal_mode_levels(m, 10)
+    lam = np.sort(lam)
+    assert np.max(np.abs(lam - ex)) < 1e-3
+    assert np.all(lam >= ex - 1e-9)  # variational (Galerkin) bound
