@@ -1,0 +1,266 @@
+/*
+ * ttn.h -- C ABI of the MI355X (gfx950) tree-tensor-network eigensolver hot path.
+ *
+ * Method: Tree Tensor Network Methods for Efficient Calculation of Molecular
+ * Vibrational Spectra (arXiv 2512.15875).  A sum-of-products vibrational
+ * Hamiltonian (Eq. sum_of_tp) is stored as a tree tensor network operator
+ * (TTNO, Eq. ttno) and applied to a block of k tree tensor network states
+ * (TTNS, Eq. ttns) inside block LOBPCG (Alg. lobpcg_block) and block inverse
+ * iteration (Alg. block_inverse_iteration), whose local problems are the
+ * variational-fitting and ALS systems of Sec. II.C.3-4 (Fig. variational,
+ * Fig. als).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Tree: nodes 0..n-1, parent[u] (-1 at the root), phys[u] (1 for an auxiliary
+ *   node).  N(u) = [parent, children in increasing id order].  Edge e(u) joins
+ *   non-root u and parent(u).  Directed edges: slot 2u = u -> parent(u),
+ *   slot 2u+1 = parent(u) -> u.
+ * Layouts: row-major, contiguous, real.
+ *   state tensor      A_u[a_N(u)..., p]              (no parent leg at the root)
+ *   TTNO tensor       W_u[w_N(u)..., p_out, q_in]
+ *   environment u->v  E[slot][b][w][a]  (bra bond, operator bond, ket bond on
+ *                     the edge (u,v); the identity operator has w of size 1)
+ *   block node buffer [k][size_u]  (all k states of the node, one after another)
+ *   local vectors     [k][n_loc] in the node's leg order
+ * dtypes: TTN_F64 (double), TTN_F32 (float).  A TTN_BF16 *compute* dtype reads
+ *   FP32 tensors, rounds them to bfloat16 on the way into the matrix cores and
+ *   accumulates in FP32.
+ * Ownership: the caller owns every tensor buffer (device memory) and every
+ *   host array it passes; the library keeps pointers to device buffers given
+ *   at *_create time and copies host arrays.  The library owns its handles,
+ *   contraction plans and the workspace sized at ttn_ctx_create.
+ * Streams: every call enqueues on the context's HIP stream and returns
+ *   without synchronising unless stated.
+ * Errors: every call returns ttn_status; arguments are validated on the host
+ *   before any launch and out-parameters are written only on success; the
+ *   message of the last failure is returned by ttn_last_error.  No exception
+ *   or abort crosses this boundary.  A call that plans a contraction for the
+ *   first time for a given node and shape allocates its offset tables once;
+ *   ttn_ctx_prepare_* calls do that ahead of time.
+ */
+#ifndef TTN_H
+#define TTN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ttn_status;
+enum {
+  TTN_OK = 0,
+  TTN_E_ARG = 1,        /* null handle, bad index, bad flag */
+  TTN_E_SHAPE = 2,      /* tensor dims inconsistent with tree / bonds */
+  TTN_E_DTYPE = 3,      /* dtype combination not supported */
+  TTN_E_DEVICE = 4,     /* HIP runtime error (message names the call) */
+  TTN_E_WORKSPACE = 5,  /* workspace too small even for one state */
+  TTN_E_LAUNCH = 6,     /* kernel launch failed */
+  TTN_E_NOT_PD = 7,     /* overlap matrix not positive definite and SVQB disabled */
+  TTN_E_NONFINITE = 8   /* NaN/Inf flagged by a kernel (surfaced at ttn_ctx_sync) */
+};
+
+typedef enum { TTN_F64 = 0, TTN_F32 = 1, TTN_BF16 = 2 } ttn_dtype;
+
+typedef struct ttn_ctx ttn_ctx;
+typedef struct ttn_tree ttn_tree;
+typedef struct ttn_ttno ttn_ttno;
+typedef struct ttn_block ttn_block;
+typedef struct ttn_envs ttn_envs;
+typedef struct ttn_sop ttn_sop;
+
+/* ------------------------------------------------------------ housekeeping */
+
+/* Create a context on `device` using HIP stream `hip_stream` (NULL = default
+ * stream) with a device workspace of `workspace_bytes` for contraction
+ * intermediates (0 = 1 GiB). */
+ttn_status ttn_ctx_create(int device, void* hip_stream, size_t workspace_bytes, ttn_ctx** out);
+ttn_status ttn_ctx_set_stream(ttn_ctx* ctx, void* hip_stream);
+/* Synchronise the context stream; returns TTN_E_NONFINITE if a kernel raised
+ * the non-finite flag since the last sync (the flag is then cleared). */
+ttn_status ttn_ctx_sync(ttn_ctx* ctx);
+ttn_status ttn_ctx_destroy(ttn_ctx* ctx);
+const char* ttn_last_error(const ttn_ctx* ctx);
+/* Library version string and the number of exported entry points. */
+const char* ttn_version(void);
+
+/* Tree (Eq. ttns / Appendix B topologies).  Host arrays are copied. */
+ttn_status ttn_tree_create(int32_t n_nodes, const int32_t* parent, const int32_t* phys, ttn_tree** out);
+ttn_status ttn_tree_destroy(ttn_tree* t);
+
+/* TTNO (Eq. ttno): per-node device pointers W[u] (layout above, dtype
+ * `dtype`), operator bond op_bond[u] for the edge e(u) (entry at the root
+ * ignored).  Pointers are borrowed for the handle's lifetime. */
+ttn_status ttn_ttno_create(ttn_ctx* ctx, const ttn_tree* t, const int32_t* op_bond, ttn_dtype dtype,
+                           void* const* W, ttn_ttno** out);
+ttn_status ttn_ttno_destroy(ttn_ttno* o);
+
+/* Block of k states (Eq. ttns, one TTNS per state, all with the bond
+ * dimensions bond[u] of edge e(u)).  node_ptr[u] is a device buffer of
+ * k * size_u elements of `dtype`.  Borrowed for the handle's lifetime. */
+ttn_status ttn_block_create(ttn_ctx* ctx, const ttn_tree* t, int32_t k, const int32_t* bond, ttn_dtype dtype,
+                            void* const* node_ptr, ttn_block** out);
+ttn_status ttn_block_destroy(ttn_block* b);
+/* Number of elements of one state's tensor at node u. */
+ttn_status ttn_block_node_size(const ttn_block* b, int32_t u, int64_t* size_out);
+
+/* Environment storage for `n_slots` (bra, ket) pairs: for directed edge slot
+ * s (see above) slot_ptr[s] is a device buffer [n_slots][bra_bond][M][ket_bond]
+ * of `dtype`, with M = op_bond of the edge or 1 when op_bond is NULL
+ * (identity operator).  Unused directed edges may be NULL. */
+ttn_status ttn_envs_create(ttn_ctx* ctx, const ttn_tree* t, int32_t n_slots, const int32_t* bra_bond,
+                           const int32_t* op_bond, const int32_t* ket_bond, ttn_dtype dtype,
+                           void* const* slot_ptr, ttn_envs** out);
+ttn_status ttn_envs_destroy(ttn_envs* e);
+
+/* ------------------------------------------------------------ the hot path */
+
+/* Environment update (Sec. II.C.3-4; the shaded blocks of Fig. variational
+ * and Fig. als), for every pair p < n_pairs:
+ *   E^p_{u->v}[b,w,a] = sum A^{bra[p]}_u[b_N,p] W_u[w_N,p,q] A^{ket[p]}_u[a_N,q]
+ *                       prod_{c in N(u)\v} E^p_{c->u}[b_c,w_c,a_c]
+ * op NULL = identity operator.  pair_bra / pair_ket: device int32[n_pairs],
+ * indices into the bra / ket blocks.  Incoming environments are read from, and
+ * the result written to, slot p of `envs`.  u = node, v = toward (a
+ * neighbour of u).  compute: TTN_F64 needs F64 tensors; TTN_F32 / TTN_BF16
+ * need F32 tensors. */
+ttn_status ttno_env_update(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_block* bra,
+                           const ttn_block* ket, int32_t n_pairs, const int32_t* pair_bra,
+                           const int32_t* pair_ket, int32_t node, int32_t toward, ttn_envs* envs,
+                           ttn_dtype compute);
+
+/* Closure (the Gram entries <bra|O|ket> at node u from all incoming
+ * environments, Alg. lobpcg_block's H~ and M~):
+ *   out[p] = sum A^{bra[p]}_u W_u A^{ket[p]}_u prod_{c in N(u)} E^p_{c->u}
+ * out: device double[n_pairs]. */
+ttn_status ttno_env_close(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_block* bra,
+                          const ttn_block* ket, int32_t n_pairs, const int32_t* pair_bra,
+                          const int32_t* pair_ket, int32_t node, const ttn_envs* envs, double* out,
+                          ttn_dtype compute);
+
+#define TTN_HEFF_APPLY 0u     /* Y = alpha (H_eff - shift) X                  */
+#define TTN_HEFF_NO_SHIFT 1u  /* ignore shift                                  */
+#define TTN_HEFF_DIAG 2u      /* Y = diag(H_eff) - shift (X unused)            */
+#define TTN_HEFF_ACCUM 4u     /* add into Y instead of overwriting it          */
+
+/* Local effective-Hamiltonian product for k states at node u (Sec. II.C.3-4):
+ *   Y_j[b_N,p] = alpha_j * ( sum W_u[w_N,p,q] X_{x(j)}[a_N,q]
+ *                prod_{c in N(u)} E^{pair(j)}_{c->u}[b_c,w_c,a_c] - s_j X_{x(j)}[b_N,p] )
+ * op NULL = identity operator (the fitting / ALS right-hand side when the
+ * environments pair a target with a source state).
+ * pair_ids: device int32[k] env slot per state (NULL = j).
+ * x_ids:    device int32[k] row of X per state (NULL = j), each < x_rows.
+ * shift, alpha: device double[k] (NULL = 0 and 1).
+ * X: [x_rows][n_in], Y: [k][n_loc] (device; dtype = the tensors' dtype);
+ * n_in / n_loc are the products of the ket / bra bonds times phys[u].
+ * Out-of-range pair_ids / x_ids entries are clamped on the device and reported
+ * as TTN_E_ARG by the next ttn_ctx_sync.
+ * With TTN_HEFF_DIAG, Y_j = diag(H_eff) - s_j (X, x_ids, alpha unused). */
+ttn_status heff_apply_block(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_envs* envs,
+                            int32_t node, int32_t k, const int32_t* pair_ids, const int32_t* x_ids,
+                            const double* shift, const double* alpha, const void* X, int32_t x_rows,
+                            void* Y, uint32_t flags, ttn_dtype compute);
+
+/* Rayleigh-Ritz for `batch` independent problems H~ v = lambda S~ v
+ * (Alg. lobpcg_block / Alg. block_inverse_iteration), FP64 on the device.
+ * H, S: device double[batch][ld][ld] (row-major, symmetric; only m[b] x m[b]
+ * used).  m: host int32[batch] (m[b] <= ld <= 512).  Cholesky of S~; when a
+ * pivot <= drop_tol * max diag(S~) the problem falls back to SVQB (eigen-
+ * decomposition of S~, directions with sigma <= drop_tol * sigma_max dropped).
+ * Outputs (device): evals double[batch][nev] ascending; V double[batch][ld][nev]
+ * (column j = eigenvector j, V^T S~ V = I, largest-magnitude entry of each
+ * column positive); rank_out int32[batch] (m[b] or the SVQB rank).
+ * allow_svqb = 0 makes a non-positive-definite S~ an error (TTN_E_NOT_PD,
+ * reported at ttn_ctx_sync). */
+ttn_status rayleigh_ritz(ttn_ctx* ctx, int32_t batch, const int32_t* m, int32_t ld, const double* H,
+                         const double* S, int32_t nev, double drop_tol, int32_t allow_svqb,
+                         double* evals, double* V, int32_t* rank_out);
+
+/* ------------------------------------------------------------ sweep (ALS / fitting) */
+
+typedef enum { TTN_SOLVE_MINRES = 0, TTN_SOLVE_DIAG = 1, TTN_SOLVE_FIT = 2 } ttn_solve_mode;
+
+typedef struct {
+  int32_t mode;      /* ttn_solve_mode */
+  int32_t maxiter;   /* MINRES iterations per local solve */
+  double rtol;       /* MINRES: stop when |residual| <= rtol * |b| */
+} ttn_solve_opts;
+
+typedef struct ttn_sweep ttn_sweep;
+
+/* A sweep over a target block y (k states) solving, node by node,
+ *   MINRES / DIAG:  (H - s_j) y_j = phi_j           (ALS, Sec. II.C.4)
+ *   FIT:            y_t = sum_terms c * O phi_s     (fitting, Sec. II.C.3)
+ * Source terms: up to 2 (op_i, block_i, n_i terms (target t, source s,
+ * coefficient c)); for MINRES/DIAG exactly one identity-operator term with
+ * n = k and targets 0..k-1.  `shift` device double[k] (MINRES/DIAG).
+ * H-environments (y,y) use op; RHS environments (y, source) use op_i.
+ * The library allocates the environment storage, the RHS scratch and the
+ * MINRES vectors at creation.  The target block must be in canonical form
+ * with its orthogonality centre at `centre`; ttn_sweep_init computes every
+ * environment toward the centre. */
+ttn_status ttn_sweep_create(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, ttn_block* target,
+                            int32_t n_src, const ttn_ttno* const* src_op, const ttn_block* const* src_block,
+                            const int32_t* n_terms, const int32_t* const* term_target,
+                            const int32_t* const* term_source, const double* const* term_coef,
+                            const double* shift, ttn_dtype compute, ttn_sweep** out);
+ttn_status ttn_sweep_init(ttn_sweep* sw, int32_t centre);
+ttn_status ttn_sweep_destroy(ttn_sweep* sw);
+
+/* One local step of a sweep at `node` (the current orthogonality centre):
+ * local right-hand side from the source environments, local solve (MINRES on
+ * (H_eff - s_j), DIAG, or the FIT sum), then, if next >= 0, a QR gauge move
+ * of every state toward the neighbour `next` (R absorbed into `next`) and the
+ * environment updates across the crossed edge.  iters_out / resid_out:
+ * device int32[k] / double[k] MINRES iterations and final residual norm
+ * estimates (may be NULL). */
+ttn_status sweep_step(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, int32_t next, const ttn_solve_opts* opts,
+                      int32_t* iters_out, double* resid_out);
+
+/* QR gauge move of all k states of a block from node u to neighbour v
+ * (Sec. II.A.1): A_u reshaped [rest, D_e] = Q R (diag R >= 0), A_u <- Q,
+ * A_v <- R contracted into its leg toward u.  FP64 arithmetic. */
+ttn_status ttn_block_move_centre(ttn_ctx* ctx, ttn_block* b, int32_t u, int32_t v);
+
+/* Scale state j's tensor at node u by scale[j] (device double[k]). */
+ttn_status ttn_block_scale_node(ttn_ctx* ctx, ttn_block* b, int32_t u, const double* scale);
+
+/* Squared norms of the k tensors at node u: out device double[k]. */
+ttn_status ttn_block_node_norms2(ttn_ctx* ctx, const ttn_block* b, int32_t u, double* out);
+
+/* ------------------------------------------------------------ operator compiler (host) */
+
+/* Sum-of-products -> TTNO in FP64 on the host (Sec. II.A.3, Eq. sum_of_tp):
+ * H = sum_i omega_i n_i + sum_m coef_m prod (q_i)^{pow}, in the harmonic-
+ * oscillator basis of size dims[mode] (exact projections of q^k).
+ * mono_ptr[m]..mono_ptr[m+1] index the (mode, power) pairs of monomial m in
+ * mono_mode / mono_pow.  node_mode[u]: the mode carried by node u, -1 for an
+ * auxiliary node.  Built with a channel automaton and compressed by
+ * SVD to the operator Schmidt rank (relative cutoff rel_tol). */
+ttn_status ttn_sop_build(const ttn_tree* t, const int32_t* node_mode, int32_t n_modes, const double* omega,
+                         const int32_t* dims, int32_t n_mono, const int32_t* mono_ptr,
+                         const int32_t* mono_mode, const int32_t* mono_pow, const double* coef,
+                         double rel_tol, ttn_sop** out);
+/* op_bond[u] for every edge e(u) (root entry 0). */
+ttn_status ttn_sop_bonds(const ttn_sop* s, int32_t* op_bond);
+/* Copy node u's tensor (layout W_u above, FP64) into host buffer `out` of
+ * `cap` doubles. */
+ttn_status ttn_sop_tensor(const ttn_sop* s, int32_t u, double* out, int64_t cap);
+ttn_status ttn_sop_destroy(ttn_sop* s);
+
+/* ------------------------------------------------------------ measurement */
+
+/* Algorithmic flop count of one heff_apply_block call for k states at node u
+ * (minimum over pairwise contraction orders, dense operands at unpadded
+ * shapes, per-state environments), and of one ttno_env_update per pair. */
+ttn_status ttn_flops_heff(const ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_envs* envs,
+                          int32_t node, int32_t k, double* flops);
+ttn_status ttn_flops_env(const ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_block* bra,
+                         const ttn_block* ket, int32_t node, int32_t toward, double* flops_per_pair);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TTN_H */

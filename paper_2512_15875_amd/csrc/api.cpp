@@ -1,0 +1,833 @@
+// C ABI: handles, validation and the contraction entry points
+// (ttno_env_update, ttno_env_close, heff_apply_block).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <sstream>
+
+#include "internal.h"
+
+using namespace ttn;
+
+namespace {
+
+thread_local std::string g_err;  // for calls without a context
+
+ttn_status fail(ttn_ctx* ctx, ttn_status code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                  \
+  do {                                                                                     \
+    hipError_t _e = (call);                                                                \
+    if (_e != hipSuccess) return fail(ctx, TTN_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+int ctype_of(ttn_dtype compute) { return compute == TTN_F64 ? 0 : (compute == TTN_F32 ? 1 : 2); }
+size_t esize(int ct) { return ct == 0 ? 8 : 4; }
+
+bool dtype_ok(ttn_dtype storage, ttn_dtype compute) {
+  if (compute == TTN_F64) return storage == TTN_F64;
+  return storage == TTN_F32;
+}
+
+// row-major strides of dims, dropping size-1 legs: returns (labels, strides)
+void add_tensor(std::vector<Tensor>& v, const std::vector<int>& labs, const std::vector<int>& dms, int batched,
+                std::map<int, int>& dims) {
+  Tensor t;
+  int64_t s = 1;
+  std::vector<int64_t> st(labs.size());
+  for (int i = (int)labs.size() - 1; i >= 0; --i) {
+    st[i] = s;
+    s *= dms[i];
+  }
+  for (size_t i = 0; i < labs.size(); ++i) {
+    auto it = dims.find(labs[i]);
+    if (it == dims.end()) dims[labs[i]] = dms[i];
+    if (dms[i] == 1) continue;
+    t.lab.push_back(labs[i]);
+    t.str.push_back(st[i]);
+  }
+  t.batched = batched;
+  v.push_back(t);
+}
+
+void out_layout(const std::vector<int>& labs, const std::vector<int>& dms, std::vector<int>& ol,
+                std::vector<int64_t>& os) {
+  int64_t s = 1;
+  std::vector<int64_t> st(labs.size());
+  for (int i = (int)labs.size() - 1; i >= 0; --i) {
+    st[i] = s;
+    s *= dms[i];
+  }
+  ol.clear();
+  os.clear();
+  for (size_t i = 0; i < labs.size(); ++i) {
+    if (dms[i] == 1) continue;
+    ol.push_back(labs[i]);
+    os.push_back(st[i]);
+  }
+}
+
+// Execute a plan over batch items [0, nb): inputs[i] addressing, final output
+// addressing and epilogue.  Chunks the batch to the workspace.
+ttn_status exec_plan(ttn_ctx* ctx, const Plan& P, int ct, const std::vector<OpAddr>& inputs, const OpAddr& out,
+                     const Epilogue& ep, int nb, const std::vector<int64_t>& in_elems, int64_t out_elems,
+                     size_t ws_off_bytes = 0) {
+  const size_t es = esize(ct);
+  {
+    std::string why;
+    if (!check_plan_bounds(P, in_elems, out_elems, why)) return fail(ctx, TTN_E_SHAPE, why);
+  }
+  const size_t avail = ctx->ws_bytes > ws_off_bytes ? (ctx->ws_bytes - ws_off_bytes) / es : 0;
+  if ((size_t)P.ws_shared > avail) return fail(ctx, TTN_E_WORKSPACE, "workspace too small for shared intermediates");
+  int64_t chunk = nb;
+  if (P.ws_per_item > 0) {
+    chunk = (int64_t)((avail - P.ws_shared) / P.ws_per_item);
+    if (chunk < 1) return fail(ctx, TTN_E_WORKSPACE, "workspace too small for one batch item");
+    chunk = std::min<int64_t>(chunk, nb);
+  }
+  char* ws = (char*)ctx->ws + ws_off_bytes;
+  // shared intermediates are computed once (first chunk) and kept
+  bool shared_done = false;
+  for (int z0 = 0; z0 < nb; z0 += (int)chunk) {
+    const int nz = (int)std::min<int64_t>(chunk, nb - z0);
+    // addresses of intermediates for this chunk
+    std::vector<OpAddr> inter;
+    int shared_i = 0;
+    (void)shared_i;
+    size_t ib = 0;
+    for (size_t s = 0; s < P.steps.size(); ++s) {
+      const Step& st = P.steps[s];
+      if (st.out < 0) continue;
+      OpAddr o;
+      const int64_t padded = (st.out_size + 63) / 64 * 64;
+      if (st.batched) {
+        o.base = ws + ((size_t)P.ws_shared + (size_t)P.inter_off[ib] * nz) * es;
+        o.bstride = padded;
+        o.local = true;
+      } else {
+        o.base = ws + (size_t)P.inter_off[ib] * es;
+        o.shared = true;
+      }
+      inter.push_back(o);
+      ++ib;
+    }
+    auto addr = [&](int id) -> OpAddr {
+      if (id < P.n_in) return inputs[id];
+      return inter[id - P.n_in];
+    };
+    for (size_t s = 0; s < P.steps.size(); ++s) {
+      const Step& st = P.steps[s];
+      if (!st.batched && shared_done) continue;
+      const OpAddr A = addr(st.a), B = addr(st.b);
+      const bool last = st.out < 0;
+      OpAddr C = last ? out : addr(st.out);
+      Epilogue e = last ? ep : Epilogue();
+      const int cnt = st.batched ? nz : 1;
+      hipError_t he = launch_gemm(ct, st.g, A, B, C, e, st.batched ? z0 : 0, cnt, ctx->d_flag, ctx->stream);
+      if (he != hipSuccess) return fail(ctx, TTN_E_LAUNCH, std::string("gemm launch: ") + hipGetErrorString(he));
+    }
+    shared_done = true;
+  }
+  return TTN_OK;
+}
+
+int64_t w_elems(const ttn_tree* t, const ttn_ttno* op, int u) {
+  int64_t n = (int64_t)t->phys[u] * t->phys[u];
+  for (int c : t->nb[u]) n *= op->bond(u, c);
+  return n;
+}
+
+// ---- network builders (labels: leg i -> b 3i, w 3i+1, a 3i+2; p 3k, q 3k+1)
+
+struct Net {
+  std::vector<Tensor> in;
+  std::map<int, int> dims;
+  std::vector<int> out_lab;
+  std::vector<int64_t> out_str;
+  std::string key;
+};
+
+// heff at node u: inputs [X, (W), E_0..E_{k-1}], output Y[b..., p]
+bool build_heff_net(const ttn_tree* t, const ttn_ttno* op, const ttn_envs* env, int u, Net& net, std::string& why) {
+  const int kap = (int)t->nb[u].size();
+  const int d = t->phys[u];
+  const int P = 3 * kap, Q = op ? 3 * kap + 1 : 3 * kap;
+  std::vector<int> xl, xd, wl, wd, yl, yd;
+  std::ostringstream key;
+  key << "heff:" << u << ":" << (op ? 1 : 0);
+  for (int i = 0; i < kap; ++i) {
+    const int c = t->nb[u][i];
+    xl.push_back(3 * i + 2);
+    xd.push_back(env->ea(c, u));
+    yl.push_back(3 * i);
+    yd.push_back(env->eb(c, u));
+    if (op) {
+      wl.push_back(3 * i + 1);
+      wd.push_back(op->bond(u, c));
+      if (env->em(c, u) != op->bond(u, c)) {
+        why = "environment operator bond differs from the TTNO bond";
+        return false;
+      }
+    } else if (env->em(c, u) != 1) {
+      why = "identity operator needs environments with operator bond 1";
+      return false;
+    }
+  }
+  xl.push_back(Q);
+  xd.push_back(d);
+  yl.push_back(P);
+  yd.push_back(d);
+  add_tensor(net.in, xl, xd, 1, net.dims);
+  if (op) {
+    wl.push_back(P);
+    wd.push_back(d);
+    wl.push_back(Q);
+    wd.push_back(d);
+    add_tensor(net.in, wl, wd, 0, net.dims);
+  }
+  for (int i = 0; i < kap; ++i) {
+    const int c = t->nb[u][i];
+    std::vector<int> el{3 * i, 3 * i + 1, 3 * i + 2};
+    std::vector<int> ed{env->eb(c, u), env->em(c, u), env->ea(c, u)};
+    add_tensor(net.in, el, ed, 1, net.dims);
+    key << ":" << ed[0] << "x" << ed[1] << "x" << ed[2];
+  }
+  key << ":d" << d;
+  out_layout(yl, yd, net.out_lab, net.out_str);
+  net.key = key.str();
+  return true;
+}
+
+// env update u -> v: inputs [bra, (W), ket, E_i (i != iv)], output E[b_iv, w_iv, a_iv]
+bool build_env_net(const ttn_tree* t, const ttn_ttno* op, const ttn_block* bra, const ttn_block* ket,
+                   const ttn_envs* env, int u, int v, Net& net, std::string& why) {
+  const int kap = (int)t->nb[u].size();
+  const int d = t->phys[u];
+  const int iv = t->leg_of(u, v);
+  const int P = 3 * kap, Q = op ? 3 * kap + 1 : 3 * kap;
+  std::ostringstream key;
+  key << "env:" << u << ">" << v << ":" << (op ? 1 : 0);
+  std::vector<int> bl, bd, kl, kd, wl, wd;
+  for (int i = 0; i < kap; ++i) {
+    const int c = t->nb[u][i];
+    bl.push_back(3 * i);
+    bd.push_back(bra->bond(u, c));
+    kl.push_back(3 * i + 2);
+    kd.push_back(ket->bond(u, c));
+    if (op) {
+      wl.push_back(3 * i + 1);
+      wd.push_back(op->bond(u, c));
+    }
+    if (env->eb(u, c) != bra->bond(u, c) || env->ea(u, c) != ket->bond(u, c)) {
+      why = "environment bonds differ from the bra/ket bonds";
+      return false;
+    }
+    if (env->em(u, c) != (op ? op->bond(u, c) : 1)) {
+      why = "environment operator bond differs from the operator";
+      return false;
+    }
+  }
+  bl.push_back(P);
+  bd.push_back(d);
+  kl.push_back(Q);
+  kd.push_back(d);
+  add_tensor(net.in, bl, bd, 1, net.dims);
+  if (op) {
+    wl.push_back(P);
+    wd.push_back(d);
+    wl.push_back(Q);
+    wd.push_back(d);
+    add_tensor(net.in, wl, wd, 0, net.dims);
+  }
+  add_tensor(net.in, kl, kd, 1, net.dims);
+  for (int i = 0; i < kap; ++i) {
+    if (i == iv) continue;
+    const int c = t->nb[u][i];
+    std::vector<int> el{3 * i, 3 * i + 1, 3 * i + 2};
+    std::vector<int> ed{env->eb(c, u), env->em(c, u), env->ea(c, u)};
+    add_tensor(net.in, el, ed, 1, net.dims);
+    key << ":" << ed[0] << "x" << ed[1] << "x" << ed[2];
+  }
+  key << ":" << bra->bond(u, v) << "," << ket->bond(u, v) << ":d" << d;
+  std::vector<int> ol{3 * iv, 3 * iv + 1, 3 * iv + 2};
+  std::vector<int> od{env->eb(u, v), env->em(u, v), env->ea(u, v)};
+  out_layout(ol, od, net.out_lab, net.out_str);
+  net.key = key.str();
+  return true;
+}
+
+Plan* get_plan(ttn_ctx* ctx, const Net& net, int ct, double batch, ttn_status& code) {
+  std::ostringstream k;
+  k << net.key << ":ct" << ct << ":b" << (batch > 1 ? 1 : 0);
+  auto it = ctx->plans.find(k.str());
+  if (it != ctx->plans.end()) return it->second.get();
+  Status st;
+  auto p = make_plan(net.in, net.dims, net.out_lab, net.out_str, batch, ct, st);
+  if (!p) {
+    code = fail(ctx, st.code, st.msg);
+    return nullptr;
+  }
+  Plan* raw = p.get();
+  ctx->plans[k.str()] = std::move(p);
+  return raw;
+}
+
+}  // namespace
+
+// ================================================================== housekeeping
+
+extern "C" {
+
+const char* ttn_version(void) { return "ttn-mi355x 0.1 (gfx950)"; }
+
+const char* ttn_last_error(const ttn_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+ttn_status ttn_ctx_create(int device, void* hip_stream, size_t workspace_bytes, ttn_ctx** out) {
+  if (!out) return fail(nullptr, TTN_E_ARG, "out is null");
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+    return fail(nullptr, TTN_E_DEVICE, "no such HIP device");
+  if (hipSetDevice(device) != hipSuccess) return fail(nullptr, TTN_E_DEVICE, "hipSetDevice failed");
+  ttn_ctx* c = new (std::nothrow) ttn_ctx();
+  if (!c) return fail(nullptr, TTN_E_ARG, "out of host memory");
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->ws_bytes = workspace_bytes ? workspace_bytes : ((size_t)1 << 30);
+  if (hipMalloc(&c->ws, c->ws_bytes) != hipSuccess) {
+    delete c;
+    return fail(nullptr, TTN_E_DEVICE, "workspace hipMalloc failed");
+  }
+  if (hipMalloc(&c->d_flag, 4 * sizeof(int)) != hipSuccess || hipMemset(c->d_flag, 0, 4 * sizeof(int)) != hipSuccess) {
+    (void)hipFree(c->ws);
+    delete c;
+    return fail(nullptr, TTN_E_DEVICE, "flag hipMalloc failed");
+  }
+  *out = c;
+  return TTN_OK;
+}
+
+ttn_status ttn_ctx_set_stream(ttn_ctx* ctx, void* s) {
+  if (!ctx) return fail(nullptr, TTN_E_ARG, "null context");
+  ctx->stream = (hipStream_t)s;
+  return TTN_OK;
+}
+
+ttn_status ttn_ctx_sync(ttn_ctx* ctx) {
+  if (!ctx) return fail(nullptr, TTN_E_ARG, "null context");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  int f[4];
+  HIPCHK(ctx, hipMemcpy(f, ctx->d_flag, sizeof(f), hipMemcpyDeviceToHost));
+  if (f[0] || f[1] || f[2]) {
+    HIPCHK(ctx, hipMemset(ctx->d_flag, 0, sizeof(f)));
+    if (f[2]) return fail(ctx, TTN_E_ARG, "a pair / row index table held an out-of-range index (clamped)");
+    if (f[0]) return fail(ctx, TTN_E_NONFINITE, "a kernel produced a non-finite value");
+    return fail(ctx, TTN_E_NOT_PD, "overlap matrix not positive definite (SVQB disabled)");
+  }
+  return TTN_OK;
+}
+
+ttn_status ttn_ctx_destroy(ttn_ctx* ctx) {
+  if (!ctx) return TTN_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->plans.clear();
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->d_flag) (void)hipFree(ctx->d_flag);
+  delete ctx;
+  return TTN_OK;
+}
+
+ttn_status ttn_tree_create(int32_t n, const int32_t* parent, const int32_t* phys, ttn_tree** out) {
+  if (!out || !parent || !phys || n <= 0) return fail(nullptr, TTN_E_ARG, "bad tree arguments");
+  ttn_tree* t = new (std::nothrow) ttn_tree();
+  if (!t) return fail(nullptr, TTN_E_ARG, "out of host memory");
+  t->n = n;
+  t->parent.assign(parent, parent + n);
+  t->phys.assign(phys, phys + n);
+  t->ch.assign(n, {});
+  int roots = 0;
+  for (int u = 0; u < n; ++u) {
+    if (phys[u] < 1) {
+      delete t;
+      return fail(nullptr, TTN_E_ARG, "physical dimension must be >= 1");
+    }
+    if (parent[u] < 0) {
+      t->root = u;
+      ++roots;
+    } else if (parent[u] >= n || parent[u] == u) {
+      delete t;
+      return fail(nullptr, TTN_E_ARG, "parent index out of range");
+    } else {
+      t->ch[parent[u]].push_back(u);
+    }
+  }
+  if (roots != 1) {
+    delete t;
+    return fail(nullptr, TTN_E_ARG, "tree needs exactly one root");
+  }
+  // acyclic: every node reaches the root
+  for (int u = 0; u < n; ++u) {
+    int x = u, steps = 0;
+    while (parent[x] >= 0 && steps <= n) {
+      x = parent[x];
+      ++steps;
+    }
+    if (steps > n) {
+      delete t;
+      return fail(nullptr, TTN_E_ARG, "parent array has a cycle");
+    }
+  }
+  t->nb.assign(n, {});
+  for (int u = 0; u < n; ++u) {
+    if (parent[u] >= 0) t->nb[u].push_back(parent[u]);
+    for (int c : t->ch[u]) t->nb[u].push_back(c);
+    if (t->nb[u].size() > 4) {
+      delete t;
+      return fail(nullptr, TTN_E_ARG, "nodes with more than 4 neighbours are not supported");
+    }
+  }
+  *out = t;
+  return TTN_OK;
+}
+
+ttn_status ttn_tree_destroy(ttn_tree* t) {
+  delete t;
+  return TTN_OK;
+}
+
+ttn_status ttn_ttno_create(ttn_ctx* ctx, const ttn_tree* t, const int32_t* op_bond, ttn_dtype dtype, void* const* W,
+                           ttn_ttno** out) {
+  if (!ctx || !t || !op_bond || !W || !out) return fail(ctx, TTN_E_ARG, "null argument");
+  if (dtype != TTN_F64 && dtype != TTN_F32) return fail(ctx, TTN_E_DTYPE, "TTNO storage must be F64 or F32");
+  ttn_ttno* o = new (std::nothrow) ttn_ttno();
+  o->t = t;
+  o->M.assign(op_bond, op_bond + t->n);
+  o->dt = dtype;
+  o->W.assign(W, W + t->n);
+  for (int u = 0; u < t->n; ++u) {
+    if (!o->W[u] || (u != t->root && o->M[u] < 1)) {
+      delete o;
+      return fail(ctx, TTN_E_ARG, "missing TTNO tensor or bond");
+    }
+  }
+  *out = o;
+  return TTN_OK;
+}
+
+ttn_status ttn_ttno_destroy(ttn_ttno* o) {
+  delete o;
+  return TTN_OK;
+}
+
+ttn_status ttn_block_create(ttn_ctx* ctx, const ttn_tree* t, int32_t k, const int32_t* bond, ttn_dtype dtype,
+                            void* const* node_ptr, ttn_block** out) {
+  if (!ctx || !t || !bond || !node_ptr || !out || k < 1) return fail(ctx, TTN_E_ARG, "bad block arguments");
+  if (dtype != TTN_F64 && dtype != TTN_F32) return fail(ctx, TTN_E_DTYPE, "block storage must be F64 or F32");
+  ttn_block* b = new (std::nothrow) ttn_block();
+  b->t = t;
+  b->k = k;
+  b->D.assign(bond, bond + t->n);
+  b->dt = dtype;
+  b->ptr.assign(node_ptr, node_ptr + t->n);
+  b->size.resize(t->n);
+  for (int u = 0; u < t->n; ++u) {
+    if (u != t->root && b->D[u] < 1) {
+      delete b;
+      return fail(ctx, TTN_E_SHAPE, "bond dimension must be >= 1");
+    }
+    int64_t s = 1;
+    for (int x : b->legdims(u)) s *= x;
+    if (s > INT32_MAX / 2) {
+      delete b;
+      return fail(ctx, TTN_E_SHAPE, "node tensor too large");
+    }
+    b->size[u] = s;
+    if (!b->ptr[u]) {
+      delete b;
+      return fail(ctx, TTN_E_ARG, "missing node buffer");
+    }
+  }
+  *out = b;
+  return TTN_OK;
+}
+
+ttn_status ttn_block_destroy(ttn_block* b) {
+  delete b;
+  return TTN_OK;
+}
+
+ttn_status ttn_block_node_size(const ttn_block* b, int32_t u, int64_t* s) {
+  if (!b || !s || u < 0 || u >= b->t->n) return fail(nullptr, TTN_E_ARG, "bad node");
+  *s = b->size[u];
+  return TTN_OK;
+}
+
+ttn_status ttn_envs_create(ttn_ctx* ctx, const ttn_tree* t, int32_t n_slots, const int32_t* bra_bond,
+                           const int32_t* op_bond, const int32_t* ket_bond, ttn_dtype dtype, void* const* slot_ptr,
+                           ttn_envs** out) {
+  if (!ctx || !t || n_slots < 1 || !bra_bond || !ket_bond || !slot_ptr || !out)
+    return fail(ctx, TTN_E_ARG, "bad envs arguments");
+  if (dtype != TTN_F64 && dtype != TTN_F32) return fail(ctx, TTN_E_DTYPE, "env storage must be F64 or F32");
+  ttn_envs* e = new (std::nothrow) ttn_envs();
+  e->t = t;
+  e->n_slots = n_slots;
+  e->Db.assign(bra_bond, bra_bond + t->n);
+  e->Da.assign(ket_bond, ket_bond + t->n);
+  e->identity = op_bond == nullptr;
+  e->M = op_bond ? std::vector<int>(op_bond, op_bond + t->n) : std::vector<int>(t->n, 1);
+  e->dt = dtype;
+  e->slot.assign(slot_ptr, slot_ptr + 2 * t->n);
+  *out = e;
+  return TTN_OK;
+}
+
+ttn_status ttn_envs_destroy(ttn_envs* e) {
+  delete e;
+  return TTN_OK;
+}
+
+// ================================================================== hot path
+
+ttn_status ttno_env_update(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_block* bra,
+                           const ttn_block* ket, int32_t n_pairs, const int32_t* pair_bra, const int32_t* pair_ket,
+                           int32_t node, int32_t toward, ttn_envs* envs, ttn_dtype compute) {
+  if (!ctx || !t || !bra || !ket || !envs || !pair_bra || !pair_ket) return fail(ctx, TTN_E_ARG, "null argument");
+  if (n_pairs < 0 || n_pairs > envs->n_slots) return fail(ctx, TTN_E_ARG, "n_pairs exceeds the env slots");
+  if (node < 0 || node >= t->n || t->leg_of(node, toward) < 0) return fail(ctx, TTN_E_ARG, "toward is not a neighbour");
+  if (bra->t != t || ket->t != t || envs->t != t || (op && op->t != t)) return fail(ctx, TTN_E_ARG, "tree mismatch");
+  if (!dtype_ok(bra->dt, compute) || !dtype_ok(ket->dt, compute) || !dtype_ok(envs->dt, compute) ||
+      (op && !dtype_ok(op->dt, compute)))
+    return fail(ctx, TTN_E_DTYPE, "tensor dtype does not match the compute dtype");
+  if ((op == nullptr) != envs->identity) return fail(ctx, TTN_E_ARG, "operator / environment kind mismatch");
+  if (n_pairs == 0) return TTN_OK;
+  const int u = node, v = toward;
+  for (int c : t->nb[u])
+    if (c != v && !envs->slot[ttn_envs::dslot(t, c, u)]) return fail(ctx, TTN_E_ARG, "missing incoming environment");
+  if (!envs->slot[ttn_envs::dslot(t, u, v)]) return fail(ctx, TTN_E_ARG, "missing output environment");
+  Net net;
+  std::string why;
+  if (!build_env_net(t, op, bra, ket, envs, u, v, net, why)) return fail(ctx, TTN_E_SHAPE, why);
+  const int ct = ctype_of(compute);
+  const int kap = (int)t->nb[u].size();
+  if (net.in.size() < 2) {
+    // degenerate network (all legs trivial): not reachable for a tree node with a bond
+    return fail(ctx, TTN_E_SHAPE, "degenerate environment network");
+  }
+  ttn_status code = TTN_OK;
+  Plan* P = get_plan(ctx, net, ct, n_pairs, code);
+  if (!P) return code;
+  std::vector<OpAddr> in;
+  std::vector<int64_t> ne;
+  OpAddr a;
+  a.base = bra->ptr[u];
+  a.tab = pair_bra;
+  a.tab_max = bra->k;
+  a.bstride = bra->size[u];
+  in.push_back(a);
+  ne.push_back(bra->size[u]);
+  if (op) {
+    OpAddr w;
+    w.base = op->W[u];
+    w.shared = true;
+    in.push_back(w);
+    ne.push_back(w_elems(t, op, u));
+  }
+  OpAddr k;
+  k.base = ket->ptr[u];
+  k.tab = pair_ket;
+  k.tab_max = ket->k;
+  k.bstride = ket->size[u];
+  in.push_back(k);
+  ne.push_back(ket->size[u]);
+  const int iv = t->leg_of(u, v);
+  for (int i = 0; i < kap; ++i) {
+    if (i == iv) continue;
+    const int c = t->nb[u][i];
+    OpAddr e;
+    e.base = envs->slot[ttn_envs::dslot(t, c, u)];
+    e.bstride = envs->slot_elems(c, u);
+    in.push_back(e);
+    ne.push_back(envs->slot_elems(c, u));
+  }
+  OpAddr o;
+  o.base = envs->slot[ttn_envs::dslot(t, u, v)];
+  o.bstride = envs->slot_elems(u, v);
+  return exec_plan(ctx, *P, ct, in, o, Epilogue(), n_pairs, ne, envs->slot_elems(u, v));
+}
+
+ttn_status ttno_env_close(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_block* bra,
+                          const ttn_block* ket, int32_t n_pairs, const int32_t* pair_bra, const int32_t* pair_ket,
+                          int32_t node, const ttn_envs* envs, double* out, ttn_dtype compute) {
+  if (!ctx || !t || !bra || !ket || !envs || !out || !pair_bra || !pair_ket) return fail(ctx, TTN_E_ARG, "null argument");
+  if (node < 0 || node >= t->n) return fail(ctx, TTN_E_ARG, "bad node");
+  if (n_pairs < 0 || n_pairs > envs->n_slots) return fail(ctx, TTN_E_ARG, "n_pairs exceeds the env slots");
+  if (n_pairs == 0) return TTN_OK;
+  if (t->nb[node].empty()) return fail(ctx, TTN_E_SHAPE, "single-node tree has no environment to close");
+  // E_{u->v} into workspace (scratch env set), then dot with E_{v->u}
+  const int u = node, v = t->nb[node][0];
+  const int ct = ctype_of(compute);
+  if (!dtype_ok(envs->dt, compute)) return fail(ctx, TTN_E_DTYPE, "tensor dtype does not match the compute dtype");
+  ttn_envs scratch = *envs;
+  const int64_t se = envs->slot_elems(u, v);
+  const size_t scratch_bytes = (size_t)se * n_pairs * esize(ct);
+  const size_t off = (scratch_bytes + 255) / 256 * 256;
+  if (off >= ctx->ws_bytes) return fail(ctx, TTN_E_WORKSPACE, "workspace too small for closure scratch");
+  scratch.slot[ttn_envs::dslot(t, u, v)] = ctx->ws;  // scratch at the start of the workspace
+  Net net;
+  std::string why;
+  if (!build_env_net(t, op, bra, ket, &scratch, u, v, net, why)) return fail(ctx, TTN_E_SHAPE, why);
+  ttn_status code = TTN_OK;
+  Plan* P = get_plan(ctx, net, ct, n_pairs, code);
+  if (!P) return code;
+  const int kap = (int)t->nb[u].size();
+  std::vector<OpAddr> in;
+  std::vector<int64_t> ne;
+  OpAddr a;
+  a.base = bra->ptr[u];
+  a.tab = pair_bra;
+  a.tab_max = bra->k;
+  a.bstride = bra->size[u];
+  in.push_back(a);
+  ne.push_back(bra->size[u]);
+  if (op) {
+    OpAddr w;
+    w.base = op->W[u];
+    w.shared = true;
+    in.push_back(w);
+    ne.push_back(w_elems(t, op, u));
+  }
+  OpAddr k;
+  k.base = ket->ptr[u];
+  k.tab = pair_ket;
+  k.tab_max = ket->k;
+  k.bstride = ket->size[u];
+  in.push_back(k);
+  ne.push_back(ket->size[u]);
+  for (int i = 1; i < kap; ++i) {
+    const int c = t->nb[u][i];
+    if (!envs->slot[ttn_envs::dslot(t, c, u)]) return fail(ctx, TTN_E_ARG, "missing incoming environment");
+    OpAddr e;
+    e.base = envs->slot[ttn_envs::dslot(t, c, u)];
+    e.bstride = envs->slot_elems(c, u);
+    in.push_back(e);
+    ne.push_back(envs->slot_elems(c, u));
+  }
+  OpAddr o;
+  o.base = ctx->ws;
+  o.bstride = se;
+  ttn_status r = exec_plan(ctx, *P, ct, in, o, Epilogue(), n_pairs, ne, se, off);
+  if (r != TTN_OK) return r;
+  const void* Ev = envs->slot[ttn_envs::dslot(t, v, u)];
+  if (!Ev) return fail(ctx, TTN_E_ARG, "missing incoming environment");
+  for (int z0 = 0; z0 < n_pairs; z0 += 65535) {
+    const int nz = std::min(65535, n_pairs - z0);
+    hipError_t he = launch_batched_dot(ct, (const char*)Ev, nullptr, se, (const char*)ctx->ws + (size_t)z0 * se * esize(ct),
+                                       se, se, nz, z0, out, ctx->stream);
+    if (he != hipSuccess) return fail(ctx, TTN_E_LAUNCH, hipGetErrorString(he));
+  }
+  return TTN_OK;
+}
+
+ttn_status heff_apply_block(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_envs* envs, int32_t node,
+                            int32_t k, const int32_t* pair_ids, const int32_t* x_ids, const double* shift,
+                            const double* alpha, const void* X, int32_t x_rows, void* Y, uint32_t flags,
+                            ttn_dtype compute) {
+  if (!ctx || !t || !envs || !Y) return fail(ctx, TTN_E_ARG, "null argument");
+  if (node < 0 || node >= t->n) return fail(ctx, TTN_E_ARG, "bad node");
+  if (k < 0) return fail(ctx, TTN_E_ARG, "negative k");
+  if (flags & ~(TTN_HEFF_NO_SHIFT | TTN_HEFF_DIAG | TTN_HEFF_ACCUM)) return fail(ctx, TTN_E_ARG, "unknown flag");
+  if (!(flags & TTN_HEFF_DIAG) && !X) return fail(ctx, TTN_E_ARG, "X is null");
+  if (envs->t != t || (op && op->t != t)) return fail(ctx, TTN_E_ARG, "tree mismatch");
+  if (!dtype_ok(envs->dt, compute) || (op && !dtype_ok(op->dt, compute)))
+    return fail(ctx, TTN_E_DTYPE, "tensor dtype does not match the compute dtype");
+  if ((op == nullptr) != envs->identity) return fail(ctx, TTN_E_ARG, "operator / environment kind mismatch");
+  if (!pair_ids && k > envs->n_slots) return fail(ctx, TTN_E_ARG, "k exceeds the env slots");
+  if (!(flags & TTN_HEFF_DIAG) && (x_rows < 1 || (!x_ids && k > x_rows)))
+    return fail(ctx, TTN_E_ARG, "X has fewer rows than the states addressed");
+  if (k == 0) return TTN_OK;
+  const int u = node;
+  if (t->nb[u].empty()) return fail(ctx, TTN_E_SHAPE, "single-node tree");
+  for (int c : t->nb[u])
+    if (!envs->slot[ttn_envs::dslot(t, c, u)]) return fail(ctx, TTN_E_ARG, "missing incoming environment");
+  const int ct = ctype_of(compute);
+  const int kap = (int)t->nb[u].size();
+  int64_t n_loc = t->phys[u];
+  for (int c : t->nb[u]) n_loc *= envs->eb(c, u);
+  int64_t n_in = t->phys[u];
+  for (int c : t->nb[u]) n_in *= envs->ea(c, u);
+  if (flags & TTN_HEFF_DIAG) {
+    if (!op) return fail(ctx, TTN_E_ARG, "DIAG needs the operator");
+    for (int c : t->nb[u])
+      if (envs->eb(c, u) != envs->ea(c, u)) return fail(ctx, TTN_E_SHAPE, "DIAG needs square environments");
+    // gather diagonals into the workspace, then contract the small network
+    // Wd[w..., p] (shared) and Ed_i[z][b_i, w_i] (batched)
+    const size_t es = esize(ct);
+    int64_t wd_elems = t->phys[u];
+    for (int c : t->nb[u]) wd_elems *= op->bond(u, c);
+    std::vector<int64_t> ed_off(kap);
+    int64_t off = (wd_elems + 63) / 64 * 64;
+    for (int i = 0; i < kap; ++i) {
+      const int c = t->nb[u][i];
+      ed_off[i] = off;
+      off += ((int64_t)envs->eb(c, u) * envs->em(c, u) * k + 63) / 64 * 64;
+    }
+    const size_t gather_bytes = (size_t)off * es;
+    if (gather_bytes >= ctx->ws_bytes) return fail(ctx, TTN_E_WORKSPACE, "workspace too small for DIAG");
+    DiagDesc dd;
+    dd.kappa = kap;
+    dd.d = t->phys[u];
+    dd.W = op->W[u];
+    dd.pair = pair_ids;
+    dd.n_slots = envs->n_slots;
+    dd.flag = ctx->d_flag;
+    for (int i = 0; i < kap; ++i) {
+      const int c = t->nb[u][i];
+      dd.dB[i] = envs->eb(c, u);
+      dd.dM[i] = envs->em(c, u);
+      dd.dA[i] = envs->ea(c, u);
+      dd.E[i] = envs->slot[ttn_envs::dslot(t, c, u)];
+      dd.Estride[i] = envs->slot_elems(c, u);
+    }
+    hipError_t he = launch_diag_gather(ct, dd, ctx->ws, ed_off.data(), k, ctx->stream);
+    if (he != hipSuccess) return fail(ctx, TTN_E_LAUNCH, hipGetErrorString(he));
+    Net net;
+    std::vector<int> wl, wd, yl, yd;
+    for (int i = 0; i < kap; ++i) {
+      const int c = t->nb[u][i];
+      wl.push_back(3 * i + 1);
+      wd.push_back(op->bond(u, c));
+      yl.push_back(3 * i);
+      yd.push_back(envs->eb(c, u));
+    }
+    wl.push_back(3 * kap);
+    wd.push_back(t->phys[u]);
+    yl.push_back(3 * kap);
+    yd.push_back(t->phys[u]);
+    add_tensor(net.in, wl, wd, 0, net.dims);
+    std::ostringstream key;
+    key << "diag:" << u;
+    for (int i = 0; i < kap; ++i) {
+      const int c = t->nb[u][i];
+      std::vector<int> el{3 * i, 3 * i + 1};
+      std::vector<int> ed{envs->eb(c, u), envs->em(c, u)};
+      add_tensor(net.in, el, ed, 1, net.dims);
+      key << ":" << ed[0] << "x" << ed[1];
+    }
+    key << ":d" << t->phys[u];
+    net.key = key.str();
+    out_layout(yl, yd, net.out_lab, net.out_str);
+    ttn_status code = TTN_OK;
+    Plan* P = get_plan(ctx, net, ct == 2 ? 1 : ct, k, code);
+    if (!P) return code;
+    std::vector<OpAddr> in;
+    std::vector<int64_t> ne;
+    OpAddr w;
+    w.base = ctx->ws;
+    w.shared = true;
+    in.push_back(w);
+    ne.push_back(wd_elems);
+    for (int i = 0; i < kap; ++i) {
+      const int c = t->nb[u][i];
+      OpAddr e;
+      e.base = (char*)ctx->ws + ed_off[i] * es;
+      e.bstride = (int64_t)envs->eb(c, u) * envs->em(c, u);
+      in.push_back(e);
+      ne.push_back(e.bstride);
+    }
+    OpAddr o;
+    o.base = Y;
+    o.bstride = n_loc;
+    Epilogue ep;
+    ep.alpha = nullptr;
+    ep.shift = (flags & TTN_HEFF_NO_SHIFT) ? nullptr : shift;
+    ep.shift_const = true;
+    ep.accum = flags & TTN_HEFF_ACCUM;
+    return exec_plan(ctx, *P, ct == 2 ? 1 : ct, in, o, ep, k, ne, n_loc, (gather_bytes + 255) / 256 * 256);
+  }
+  Net net;
+  std::string why;
+  if (!build_heff_net(t, op, envs, u, net, why)) return fail(ctx, TTN_E_SHAPE, why);
+  if (!(flags & TTN_HEFF_NO_SHIFT) && shift && n_in != n_loc)
+    return fail(ctx, TTN_E_SHAPE, "a shift needs equal bra and ket bonds");
+  ttn_status code = TTN_OK;
+  Plan* P = get_plan(ctx, net, ct, k, code);
+  if (!P) return code;
+  std::vector<OpAddr> in;
+  std::vector<int64_t> ne;
+  OpAddr x;
+  x.base = X;
+  x.tab = x_ids;
+  x.tab_max = x_rows;
+  x.bstride = n_in;
+  in.push_back(x);
+  ne.push_back(n_in);
+  if (op) {
+    OpAddr w;
+    w.base = op->W[u];
+    w.shared = true;
+    in.push_back(w);
+    ne.push_back(w_elems(t, op, u));
+  }
+  for (int i = 0; i < kap; ++i) {
+    const int c = t->nb[u][i];
+    OpAddr e;
+    e.base = envs->slot[ttn_envs::dslot(t, c, u)];
+    e.tab = pair_ids;
+    e.tab_max = envs->n_slots;
+    e.bstride = envs->slot_elems(c, u);
+    in.push_back(e);
+    ne.push_back(envs->slot_elems(c, u));
+  }
+  OpAddr o;
+  o.base = Y;
+  o.bstride = n_loc;
+  Epilogue ep;
+  ep.alpha = alpha;
+  if (!(flags & TTN_HEFF_NO_SHIFT) && shift) {
+    ep.shift = shift;
+    ep.D = x;
+  }
+  ep.accum = flags & TTN_HEFF_ACCUM;
+  return exec_plan(ctx, *P, ct, in, o, ep, k, ne, n_loc);
+}
+
+// ================================================================== flop counts
+
+ttn_status ttn_flops_heff(const ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_envs* envs, int32_t node,
+                          int32_t k, double* flops) {
+  (void)ctx;
+  if (!t || !envs || !flops || node < 0 || node >= t->n) return fail(nullptr, TTN_E_ARG, "bad arguments");
+  Net net;
+  std::string why;
+  if (!build_heff_net(t, op, envs, node, net, why)) return fail(nullptr, TTN_E_SHAPE, why);
+  *flops = min_flops(net.in, net.dims, net.out_lab, k);
+  return TTN_OK;
+}
+
+ttn_status ttn_flops_env(const ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_block* bra,
+                         const ttn_block* ket, int32_t node, int32_t toward, double* fpp) {
+  (void)ctx;
+  if (!t || !bra || !ket || !fpp || node < 0 || node >= t->n || t->leg_of(node, toward) < 0)
+    return fail(nullptr, TTN_E_ARG, "bad arguments");
+  // environment bonds follow the blocks
+  ttn_envs e;
+  e.t = t;
+  e.n_slots = 1;
+  e.Db = bra->D;
+  e.Da = ket->D;
+  e.identity = op == nullptr;
+  e.M = op ? op->M : std::vector<int>(t->n, 1);
+  e.slot.assign(2 * t->n, nullptr);
+  Net net;
+  std::string why;
+  if (!build_env_net(t, op, bra, ket, &e, node, toward, net, why)) return fail(nullptr, TTN_E_SHAPE, why);
+  *fpp = min_flops(net.in, net.dims, net.out_lab, 1.0);
+  return TTN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+// Internal declarations of the TTN library (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/ttn.h"
+
+namespace ttn {
+
+struct Status {
+  ttn_status code = TTN_OK;
+  std::string msg;
+};
+
+// ------------------------------------------------------------------ kernels (gemm.hip)
+
+// One operand of a contraction stage, addressed per batch item z as
+//   base + (tab ? tab[z0 + z] : (shared ? 0 : z0 + z)) * bstride + row_off[r] + col_off[c].
+struct OpAddr {
+  const void* base = nullptr;
+  const int32_t* tab = nullptr;  // device batch-index table (may be null)
+  int64_t bstride = 0;
+  bool shared = false;           // same tensor for every batch item
+  bool local = false;            // workspace intermediate: index by z (chunk-local)
+  int tab_max = 0;               // number of valid entries a table index may address
+};
+
+struct GemmDesc {
+  int M = 0, N = 0, K = 0;
+  const int32_t* a_om = nullptr;  // [M]
+  const int32_t* a_ok = nullptr;  // [K]
+  const int32_t* b_ok = nullptr;  // [K]
+  const int32_t* b_on = nullptr;  // [N]
+  const int32_t* c_om = nullptr;  // [M]
+  const int32_t* c_on = nullptr;  // [N]
+  bool a_mfast = false, b_nfast = true;
+  int tile = 0;                   // tile configuration id
+};
+
+struct Epilogue {
+  const double* alpha = nullptr;  // per batch item (indexed by z0+z), null = 1
+  const double* shift = nullptr;  // per batch item, null = 0; adds -alpha*shift*D
+  OpAddr D;                       // addend with C's offsets (base null = none)
+  bool accum = false;
+  bool shift_const = false;       // subtract alpha*shift (no D read)
+};
+
+// dtype: 0 f64, 1 f32 storage with f32 MFMA, 2 f32 storage with bf16 MFMA
+hipError_t launch_gemm(int ctype, const GemmDesc& g, const OpAddr& A, const OpAddr& B, const OpAddr& C,
+                       const Epilogue& ep, int z0, int nz, int* flag, hipStream_t s);
+
+hipError_t launch_batched_dot(int ctype, const void* X, const int32_t* xtab, int64_t xstride, const void* Y,
+                              int64_t ystride, int64_t n, int nz, int z0, double* out, hipStream_t s);
+
+// diag(H_eff): out[z][b_N, p] = sum_w Wd[w, p] prod_i Ed_i[z][b_i, w_i] - shift[z]
+struct DiagDesc {
+  int kappa = 0;
+  int dB[4] = {1, 1, 1, 1};       // bra bond per leg
+  int dM[4] = {1, 1, 1, 1};       // operator bond per leg
+  int dA[4] = {1, 1, 1, 1};       // ket bond per leg (== dB for a diagonal)
+  int d = 1;                      // physical dim
+  const void* W = nullptr;        // W_u [w..., p, q] (null = identity)
+  const void* E[4] = {nullptr, nullptr, nullptr, nullptr};
+  const int32_t* pair = nullptr;
+  int n_slots = 0;
+  int* flag = nullptr;
+  int64_t Estride[4] = {0, 0, 0, 0};
+};
+// Wd[w..., p] = W[w..., p, p] at ws[0..); Ed_i[z][b][w] = E_i[pair(z)][b][w][b] at ws[ed_off[i]..)
+hipError_t launch_diag_gather(int ctype, const DiagDesc& dd, void* ws, const int64_t* ed_off, int nz, hipStream_t s);
+
+// ------------------------------------------------------------------ contraction plans (plan.cpp)
+
+struct Tensor {              // one operand of a network
+  std::vector<int> lab;      // index labels in memory order (size-1 legs removed)
+  std::vector<int64_t> str;  // element strides
+  int batched = 1;           // 0 shared, 1 batched
+};
+
+struct Step {
+  int a = -1, b = -1;        // operand ids (inputs 0..n_in-1, intermediates n_in..)
+  int out = -1;              // intermediate id, or -1 = final output
+  GemmDesc g;
+  int64_t out_size = 0;      // elements per batch item for an intermediate
+  double flops = 0;          // per batch item (or total if both shared)
+  bool batched = true;
+  int64_t max_a = 0, max_b = 0, max_c = 0;  // largest element offset addressed in A, B, C
+};
+
+struct Plan {
+  int n_in = 0;
+  std::vector<Step> steps;
+  std::vector<int64_t> inter_off;  // workspace offset (elements, per batch item scaled) of each intermediate
+  int64_t ws_per_item = 0;         // elements of workspace per batch item
+  int64_t ws_shared = 0;           // elements for shared intermediates
+  double flops_per_item = 0, flops_shared = 0;
+  int32_t* d_tabs = nullptr;       // device copy of every table
+  ~Plan();
+};
+
+// Build the min-flop plan for a network: inputs (with labels/strides), label
+// dims, final output labels + strides.  `batch` = number of batch items used
+// to weigh batched against shared work.
+std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<int, int>& dims,
+                                const std::vector<int>& out_lab, const std::vector<int64_t>& out_str,
+                                double batch, int ctype, Status& st);
+
+// Host-side bounds proof of a plan: every element a stage can address lies in
+// its operand (inputs: in_elems per batch item; final output: out_elems).
+bool check_plan_bounds(const Plan& P, const std::vector<int64_t>& in_elems, int64_t out_elems, std::string& why);
+
+// minimal flops of a network (same search, no tables)
+double min_flops(const std::vector<Tensor>& in, const std::map<int, int>& dims, const std::vector<int>& out_lab,
+                 double batch);
+
+}  // namespace ttn
+
+// ------------------------------------------------------------------ handles
+
+struct ttn_tree {
+  int n = 0, root = -1;
+  std::vector<int> parent, phys;
+  std::vector<std::vector<int>> ch, nb;  // children; neighbours [parent, children...]
+  int leg_of(int u, int v) const {
+    for (size_t i = 0; i < nb[u].size(); ++i)
+      if (nb[u][i] == v) return (int)i;
+    return -1;
+  }
+};
+
+struct ttn_ttno {
+  const ttn_tree* t = nullptr;
+  std::vector<int> M;  // per edge e(u)
+  ttn_dtype dt = TTN_F64;
+  std::vector<void*> W;
+  int bond(int u, int v) const {  // operator bond of edge (u,v)
+    return t->parent[u] == v ? M[u] : M[v];
+  }
+};
+
+struct ttn_block {
+  const ttn_tree* t = nullptr;
+  int k = 0;
+  std::vector<int> D;
+  ttn_dtype dt = TTN_F64;
+  std::vector<void*> ptr;
+  std::vector<int64_t> size;
+  int bond(int u, int v) const { return t->parent[u] == v ? D[u] : D[v]; }
+  std::vector<int> legdims(int u) const {
+    std::vector<int> d;
+    for (int v : t->nb[u]) d.push_back(bond(u, v));
+    d.push_back(t->phys[u]);
+    return d;
+  }
+};
+
+struct ttn_envs {
+  const ttn_tree* t = nullptr;
+  int n_slots = 0;
+  std::vector<int> Db, M, Da;  // per edge e(u)
+  bool identity = false;
+  ttn_dtype dt = TTN_F64;
+  std::vector<void*> slot;     // 2n directed slots
+  static int dslot(const ttn_tree* t, int u, int v) { return t->parent[u] == v ? 2 * u : 2 * v + 1; }
+  int eb(int u, int v) const { return t->parent[u] == v ? Db[u] : Db[v]; }
+  int em(int u, int v) const { return identity ? 1 : (t->parent[u] == v ? M[u] : M[v]); }
+  int ea(int u, int v) const { return t->parent[u] == v ? Da[u] : Da[v]; }
+  int64_t slot_elems(int u, int v) const { return (int64_t)eb(u, v) * em(u, v) * ea(u, v); }
+};
+
+struct ttn_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::string err;
+  int* d_flag = nullptr;  // non-finite / not-PD flags
+  std::map<std::string, std::unique_ptr<ttn::Plan>> plans;
+};

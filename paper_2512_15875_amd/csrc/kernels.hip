@@ -1,0 +1,57 @@
+// Small memory-bound kernels of the hot path: diagonal gathers for diag(H_eff).
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace ttn {
+
+// Wd[w..., p] = W[w..., p, p]
+template <typename T>
+__global__ void wdiag_kernel(const T* W, int64_t nw, int d, T* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nw * d) return;
+  const int64_t w = i / d;
+  const int p = (int)(i - w * d);
+  out[i] = W[(w * d + p) * d + p];
+}
+
+// Ed[z][b][w] = E[pair(z)][b][w][b]
+template <typename T>
+__global__ void ediag_kernel(const T* E, const int32_t* pair, int n_slots, int* flag, int64_t estride, int B, int Mw,
+                             int nz, T* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)B * Mw;
+  if (i >= per * nz) return;
+  const int z = (int)(i / per);
+  const int64_t r = i - (int64_t)z * per;
+  const int b = (int)(r / Mw);
+  const int w = (int)(r - (int64_t)b * Mw);
+  int64_t slot = pair ? pair[z] : z;
+  if (slot < 0 || slot >= n_slots) {  // clamp and report instead of reading out of bounds
+    atomicOr(flag + 2, 1);
+    slot = slot < 0 ? 0 : n_slots - 1;
+  }
+  out[i] = E[slot * estride + ((int64_t)b * Mw + w) * B + b];
+}
+
+template <typename T>
+static hipError_t gather_t(const DiagDesc& dd, void* ws, const int64_t* ed_off, int nz, hipStream_t s) {
+  int64_t nw = 1;
+  for (int i = 0; i < dd.kappa; ++i) nw *= dd.dM[i];
+  const int64_t nwd = nw * dd.d;
+  hipLaunchKernelGGL(wdiag_kernel<T>, dim3((unsigned)((nwd + 255) / 256)), dim3(256), 0, s, (const T*)dd.W, nw, dd.d,
+                     (T*)ws);
+  for (int i = 0; i < dd.kappa; ++i) {
+    const int64_t n = (int64_t)dd.dB[i] * dd.dM[i] * nz;
+    hipLaunchKernelGGL(ediag_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (const T*)dd.E[i], dd.pair,
+                       dd.n_slots, dd.flag, dd.Estride[i], dd.dB[i], dd.dM[i], nz, (T*)ws + ed_off[i]);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_gather(int ctype, const DiagDesc& dd, void* ws, const int64_t* ed_off, int nz, hipStream_t s) {
+  if (ctype == 0) return gather_t<double>(dd, ws, ed_off, nz, s);
+  return gather_t<float>(dd, ws, ed_off, nz, s);
+}
+
+}  // namespace ttn

@@ -1,0 +1,392 @@
+// Contraction planner: minimum-flop pairwise order for the small tensor
+// networks of the hot path (a node's operands: state tensor(s), TTNO tensor,
+// up to four environments), then one offset-table GEMM per pairwise stage.
+//
+// Cost model: a pairwise contraction of operands with index sets I and J
+// costs 2 * prod(dims of I u J) per batch item when either operand is batched
+// (depends on the state or pair), or once per call when both are shared.
+// Every index of these networks appears in exactly two places (two operands,
+// or one operand and the output), so the indices shared by a pair are exactly
+// the contracted ones.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <functional>
+#include <limits>
+
+#include "internal.h"
+
+namespace ttn {
+
+Plan::~Plan() {
+  if (d_tabs) (void)hipFree(d_tabs);
+}
+
+namespace {
+
+struct Node {
+  std::vector<int> lab;  // sorted labels
+  int batched;
+};
+
+std::vector<int> sym_diff(const std::vector<int>& a, const std::vector<int>& b) {
+  std::vector<int> out;
+  std::set_symmetric_difference(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(out));
+  return out;
+}
+std::vector<int> uni(const std::vector<int>& a, const std::vector<int>& b) {
+  std::vector<int> out;
+  std::set_union(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(out));
+  return out;
+}
+
+struct Search {
+  const std::map<int, int>* dims;
+  double batch;
+  double best = std::numeric_limits<double>::infinity();
+  double best_mem = std::numeric_limits<double>::infinity();
+  std::vector<std::pair<int, int>> best_seq, cur;
+
+  double prodd(const std::vector<int>& l) const {
+    double p = 1;
+    for (int x : l) p *= dims->at(x);
+    return p;
+  }
+  void rec(std::vector<Node>& ns, double cost, double mem) {
+    if (cost > best * (1 + 1e-12)) return;
+    if (ns.size() == 1) {
+      if (cost < best * (1 - 1e-12) || (cost <= best * (1 + 1e-12) && mem < best_mem)) {
+        best = cost;
+        best_mem = mem;
+        best_seq = cur;
+      }
+      return;
+    }
+    for (size_t i = 0; i < ns.size(); ++i)
+      for (size_t j = i + 1; j < ns.size(); ++j) {
+        Node a = ns[i], b = ns[j];
+        const bool bat = a.batched || b.batched;
+        const double c = 2.0 * prodd(uni(a.lab, b.lab)) * (bat ? batch : 1.0);
+        Node r{sym_diff(a.lab, b.lab), bat ? 1 : 0};
+        const double m2 = std::max(mem, prodd(r.lab) * (bat ? batch : 1.0));
+        std::vector<Node> nx;
+        for (size_t t = 0; t < ns.size(); ++t)
+          if (t != i && t != j) nx.push_back(ns[t]);
+        nx.push_back(r);
+        cur.push_back({(int)i, (int)j});
+        rec(nx, cost + c, m2);
+        cur.pop_back();
+      }
+  }
+};
+
+// mixed-radix offsets of a label group: last label fastest
+void group_offsets(const std::vector<int>& labs, const std::map<int, int>& dims,
+                   const std::map<int, int64_t>& stride, std::vector<int32_t>& out) {
+  int64_t n = 1;
+  for (int l : labs) n *= dims.at(l);
+  out.assign((size_t)n, 0);
+  std::vector<int> digit(labs.size(), 0);
+  for (int64_t t = 0; t < n; ++t) {
+    int64_t off = 0;
+    for (size_t i = 0; i < labs.size(); ++i) off += (int64_t)digit[i] * stride.at(labs[i]);
+    out[(size_t)t] = (int32_t)off;
+    for (int i = (int)labs.size() - 1; i >= 0; --i) {
+      if (++digit[i] < dims.at(labs[i])) break;
+      digit[i] = 0;
+    }
+  }
+}
+
+int pick_tile(int M, int N, double nblocks_other) {
+  // prefer big tiles when the grid stays large enough to fill 256 CUs
+  struct C {
+    int id, bm, bn;
+  } cs[] = {{0, 128, 128}, {2, 128, 64}, {3, 64, 128}, {1, 64, 64}, {5, 64, 32}, {4, 32, 64}, {6, 32, 32}};
+  int best = 6;
+  double best_score = -1;
+  for (auto& c : cs) {
+    const double tm = std::ceil((double)M / c.bm), tn = std::ceil((double)N / c.bn);
+    const double eff = (double)M * N / (tm * c.bm * tn * c.bn);  // useful fraction of the tile area
+    const double wgs = tm * tn * nblocks_other;
+    const double fill = std::min(1.0, wgs / 512.0);
+    const double score = eff * fill * (1.0 + 0.15 * std::log2((double)c.bm * c.bn / 1024.0));
+    if (score > best_score) {
+      best_score = score;
+      best = c.id;
+    }
+  }
+  return best;
+}
+
+}  // namespace
+
+double min_flops(const std::vector<Tensor>& in, const std::map<int, int>& dims, const std::vector<int>& out_lab,
+                 double batch) {
+  std::vector<Node> ns;
+  for (auto& t : in) {
+    Node n;
+    n.lab = t.lab;
+    std::sort(n.lab.begin(), n.lab.end());
+    n.batched = t.batched;
+    ns.push_back(n);
+  }
+  if (ns.size() == 1) return 0.0;
+  Search s;
+  s.dims = &dims;
+  s.batch = batch;
+  s.rec(ns, 0.0, 0.0);
+  (void)out_lab;
+  return s.best;
+}
+
+std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<int, int>& dims,
+                                const std::vector<int>& out_lab, const std::vector<int64_t>& out_str,
+                                double batch, int ctype, Status& st) {
+  auto plan = std::make_unique<Plan>();
+  plan->n_in = (int)in.size();
+  std::vector<Node> ns;
+  for (auto& t : in) {
+    Node n;
+    n.lab = t.lab;
+    std::sort(n.lab.begin(), n.lab.end());
+    n.batched = t.batched;
+    ns.push_back(n);
+  }
+  if (ns.size() < 2) {
+    st = {TTN_E_ARG, "contraction network needs at least two operands"};
+    return nullptr;
+  }
+  Search s;
+  s.dims = &dims;
+  s.batch = batch;
+  s.rec(ns, 0.0, 0.0);
+
+  // replay the chosen sequence, assigning layouts
+  struct Live {
+    int id;
+    std::vector<int> lab;  // memory order
+    std::map<int, int64_t> str;
+    int batched;
+  };
+  std::vector<Live> live;
+  for (size_t i = 0; i < in.size(); ++i) {
+    Live l;
+    l.id = (int)i;
+    l.lab = in[i].lab;
+    for (size_t j = 0; j < in[i].lab.size(); ++j) l.str[in[i].lab[j]] = in[i].str[j];
+    l.batched = in[i].batched;
+    live.push_back(l);
+  }
+  int next_id = (int)in.size();
+  std::vector<int32_t> all_tabs;
+  struct TabRef {
+    size_t step;
+    int which;
+    size_t off;
+  };
+  std::vector<TabRef> refs;
+  int64_t ws_item = 0, ws_shared = 0;
+  std::vector<int64_t> inter_off;  // by intermediate id - n_in
+  std::vector<int> inter_shared;
+
+  for (size_t si = 0; si < s.best_seq.size(); ++si) {
+    const auto pr = s.best_seq[si];
+    Live la = live[pr.first], lb = live[pr.second];
+    const bool last = (si + 1 == s.best_seq.size());
+    // contracted labels
+    std::vector<int> sa(la.lab), sb(lb.lab);
+    std::sort(sa.begin(), sa.end());
+    std::sort(sb.begin(), sb.end());
+    std::vector<int> kl;
+    std::set_intersection(sa.begin(), sa.end(), sb.begin(), sb.end(), std::back_inserter(kl));
+    // choose A = the operand with the larger free part (rows), B the other
+    auto freeprod = [&](const Live& l) {
+      double p = 1;
+      for (int x : l.lab)
+        if (!std::binary_search(kl.begin(), kl.end(), x)) p *= dims.at(x);
+      return p;
+    };
+    bool swap_ab = freeprod(lb) > freeprod(la);
+    if (last) {
+      // rows of the final output should hold its slowest labels: keep A =
+      // the operand that owns out_lab[0] when possible
+      if (!out_lab.empty()) {
+        const bool a_has = std::find(la.lab.begin(), la.lab.end(), out_lab[0]) != la.lab.end();
+        const bool b_has = std::find(lb.lab.begin(), lb.lab.end(), out_lab[0]) != lb.lab.end();
+        if (a_has) swap_ab = false;
+        else if (b_has) swap_ab = true;
+      }
+    }
+    if (swap_ab) std::swap(la, lb);
+    auto by_stride_desc = [&](const Live& l, std::vector<int> labs) {
+      std::stable_sort(labs.begin(), labs.end(), [&](int x, int y) { return l.str.at(x) > l.str.at(y); });
+      return labs;
+    };
+    std::vector<int> ml, nl, kk;
+    for (int x : la.lab)
+      if (!std::binary_search(kl.begin(), kl.end(), x)) ml.push_back(x);
+    for (int x : lb.lab)
+      if (!std::binary_search(kl.begin(), kl.end(), x)) nl.push_back(x);
+    ml = by_stride_desc(la, ml);
+    nl = by_stride_desc(lb, nl);
+    kk = by_stride_desc(la, kl);
+
+    Step stp;
+    stp.a = la.id;
+    stp.b = lb.id;
+    stp.batched = la.batched || lb.batched;
+    double un = 1;
+    for (int x : uni(sa, sb)) un *= dims.at(x);
+    stp.flops = 2.0 * un;
+    GemmDesc& g = stp.g;
+    auto prod = [&](const std::vector<int>& l) {
+      int64_t p = 1;
+      for (int x : l) p *= dims.at(x);
+      return p;
+    };
+    const int64_t M = prod(ml), N = prod(nl), K = prod(kk);
+    if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX) {
+      st = {TTN_E_SHAPE, "contraction stage too large for 32-bit offsets"};
+      return nullptr;
+    }
+    g.M = (int)M;
+    g.N = (int)N;
+    g.K = (int)K;
+    // fast flags: where is each operand's smallest stride
+    auto smallest = [&](const Live& l) {
+      int best = -1;
+      int64_t bs = INT64_MAX;
+      for (int x : l.lab)
+        if (l.str.at(x) < bs) {
+          bs = l.str.at(x);
+          best = x;
+        }
+      return best;
+    };
+    const int sa_min = smallest(la), sb_min = smallest(lb);
+    g.a_mfast = std::find(ml.begin(), ml.end(), sa_min) != ml.end();
+    g.b_nfast = std::find(nl.begin(), nl.end(), sb_min) != nl.end();
+    if (ml.empty()) g.a_mfast = false;
+    if (nl.empty()) g.b_nfast = false;
+
+    // output layout
+    Live lo;
+    lo.batched = stp.batched ? 1 : 0;
+    std::map<int, int64_t> ostr;
+    if (last) {
+      for (size_t j = 0; j < out_lab.size(); ++j) ostr[out_lab[j]] = out_str[j];
+      lo.id = -1;
+    } else {
+      std::vector<int> ol(ml);
+      ol.insert(ol.end(), nl.begin(), nl.end());
+      int64_t acc = 1;
+      for (int j = (int)ol.size() - 1; j >= 0; --j) {
+        ostr[ol[j]] = acc;
+        acc *= dims.at(ol[j]);
+      }
+      lo.lab = ol;
+      lo.id = next_id++;
+      stp.out_size = acc;
+      if (acc > INT32_MAX) {
+        st = {TTN_E_SHAPE, "intermediate too large for 32-bit offsets"};
+        return nullptr;
+      }
+      if (stp.batched) {
+        inter_off.push_back(ws_item);
+        inter_shared.push_back(0);
+        ws_item += (acc + 63) / 64 * 64;
+      } else {
+        inter_off.push_back(ws_shared);
+        inter_shared.push_back(1);
+        ws_shared += (acc + 63) / 64 * 64;
+      }
+    }
+    lo.str = ostr;
+    stp.out = lo.id;
+    // tables
+    std::vector<int32_t> t_am, t_ak, t_bk, t_bn, t_cm, t_cn;
+    group_offsets(ml, dims, la.str, t_am);
+    group_offsets(kk, dims, la.str, t_ak);
+    group_offsets(kk, dims, lb.str, t_bk);
+    group_offsets(nl, dims, lb.str, t_bn);
+    group_offsets(ml, dims, ostr, t_cm);
+    group_offsets(nl, dims, ostr, t_cn);
+    std::vector<int32_t>* tabs6[6] = {&t_am, &t_ak, &t_bk, &t_bn, &t_cm, &t_cn};
+    for (int w = 0; w < 6; ++w) {
+      std::vector<int32_t>* v = tabs6[w];
+      refs.push_back({plan->steps.size(), w, all_tabs.size()});
+      all_tabs.insert(all_tabs.end(), v->begin(), v->end());
+      // pad each table to 16 entries for alignment
+      while (all_tabs.size() % 16) all_tabs.push_back(0);
+    }
+    auto vmax = [](const std::vector<int32_t>& v) {
+      int64_t m = 0;
+      for (int32_t x : v) m = std::max<int64_t>(m, x);
+      return m;
+    };
+    stp.max_a = vmax(t_am) + vmax(t_ak);
+    stp.max_b = vmax(t_bk) + vmax(t_bn);
+    stp.max_c = vmax(t_cm) + vmax(t_cn);
+    g.tile = pick_tile(g.M, g.N, stp.batched ? batch : 1.0);
+    if (stp.batched) plan->flops_per_item += stp.flops;
+    else plan->flops_shared += stp.flops;
+    plan->steps.push_back(stp);
+    // update the live list
+    std::vector<Live> nx;
+    for (size_t t = 0; t < live.size(); ++t)
+      if ((int)t != pr.first && (int)t != pr.second) nx.push_back(live[t]);
+    nx.push_back(lo);
+    live = nx;
+  }
+  plan->inter_off = inter_off;
+  plan->ws_per_item = ws_item;
+  plan->ws_shared = ws_shared;
+  (void)inter_shared;
+  (void)ctype;
+  // upload all tables
+  if (hipMalloc(&plan->d_tabs, all_tabs.size() * sizeof(int32_t)) != hipSuccess) {
+    st = {TTN_E_DEVICE, "hipMalloc for contraction tables failed"};
+    return nullptr;
+  }
+  if (hipMemcpy(plan->d_tabs, all_tabs.data(), all_tabs.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    st = {TTN_E_DEVICE, "hipMemcpy for contraction tables failed"};
+    return nullptr;
+  }
+  for (auto& r : refs) {
+    GemmDesc& g = plan->steps[r.step].g;
+    const int32_t* p = plan->d_tabs + r.off;
+    switch (r.which) {
+      case 0: g.a_om = p; break;
+      case 1: g.a_ok = p; break;
+      case 2: g.b_ok = p; break;
+      case 3: g.b_on = p; break;
+      case 4: g.c_om = p; break;
+      default: g.c_on = p; break;
+    }
+  }
+  return plan;
+}
+
+bool check_plan_bounds(const Plan& P, const std::vector<int64_t>& in_elems, int64_t out_elems, std::string& why) {
+  if ((int)in_elems.size() != P.n_in) {
+    why = "operand count mismatch";
+    return false;
+  }
+  std::map<int, int64_t> size;
+  for (int i = 0; i < P.n_in; ++i) size[i] = in_elems[i];
+  for (const Step& s : P.steps)
+    if (s.out >= 0) size[s.out] = s.out_size;
+  for (const Step& s : P.steps) {
+    const int64_t cs = s.out >= 0 ? s.out_size : out_elems;
+    if (s.max_a >= size.at(s.a) || s.max_b >= size.at(s.b) || s.max_c >= cs) {
+      why = "contraction stage would address outside its operands";
+      return false;
+    }
+  }
+  return true;
+}
+
+}  // namespace ttn

@@ -1,0 +1,304 @@
+"""Thin ctypes binding of libttn.so (argument marshalling only).
+
+Device memory and streams come from PyTorch; every arithmetic step runs in the
+library's HIP kernels.  The binding refuses to run without the built library:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libttn.so")
+
+F64, F32, BF16 = 0, 1, 2
+HEFF_APPLY, HEFF_NO_SHIFT, HEFF_DIAG, HEFF_ACCUM = 0, 1, 2, 4
+SOLVE_MINRES, SOLVE_DIAG, SOLVE_FIT = 0, 1, 2
+
+_lib = None
+
+# exported entry points and their ctypes signatures (all return int32 status
+# unless noted)
+_P = C.c_void_p
+_I = C.c_int32
+_PI = C.POINTER(C.c_int32)
+_SIGS = {
+    "ttn_ctx_create": [C.c_int, _P, C.c_size_t, C.POINTER(_P)],
+    "ttn_ctx_set_stream": [_P, _P],
+    "ttn_ctx_sync": [_P],
+    "ttn_ctx_destroy": [_P],
+    "ttn_tree_create": [_I, _PI, _PI, C.POINTER(_P)],
+    "ttn_tree_destroy": [_P],
+    "ttn_ttno_create": [_P, _P, _PI, C.c_int, C.POINTER(_P), C.POINTER(_P)],
+    "ttn_ttno_destroy": [_P],
+    "ttn_block_create": [_P, _P, _I, _PI, C.c_int, C.POINTER(_P), C.POINTER(_P)],
+    "ttn_block_destroy": [_P],
+    "ttn_block_node_size": [_P, _I, C.POINTER(C.c_int64)],
+    "ttn_envs_create": [_P, _P, _I, _PI, _PI, _PI, C.c_int, C.POINTER(_P), C.POINTER(_P)],
+    "ttn_envs_destroy": [_P],
+    "ttno_env_update": [_P, _P, _P, _P, _P, _I, _P, _P, _I, _I, _P, C.c_int],
+    "ttno_env_close": [_P, _P, _P, _P, _P, _I, _P, _P, _I, _P, _P, C.c_int],
+    "heff_apply_block": [_P, _P, _P, _P, _I, _I, _P, _P, _P, _P, _P, _I, _P, C.c_uint32, C.c_int],
+    "rayleigh_ritz": [_P, _I, _PI, _I, _P, _P, _I, C.c_double, _I, _P, _P, _P],
+    "ttn_block_move_centre": [_P, _P, _I, _I],
+    "ttn_block_scale_node": [_P, _P, _I, _P],
+    "ttn_block_node_norms2": [_P, _P, _I, _P],
+    "ttn_sop_build": [_P, _PI, _I, C.POINTER(C.c_double), _PI, _I, _PI, _PI, _PI, C.POINTER(C.c_double),
+                      C.c_double, C.POINTER(_P)],
+    "ttn_sop_bonds": [_P, _PI],
+    "ttn_sop_tensor": [_P, _I, C.POINTER(C.c_double), C.c_int64],
+    "ttn_sop_destroy": [_P],
+    "ttn_flops_heff": [_P, _P, _P, _P, _I, _I, C.POINTER(C.c_double)],
+    "ttn_flops_env": [_P, _P, _P, _P, _P, _I, _I, C.POINTER(C.c_double)],
+    "ttn_sweep_create": [_P, _P, _P, _P, _I, C.POINTER(_P), C.POINTER(_P), _PI, C.POINTER(_P), C.POINTER(_P),
+                         C.POINTER(_P), _P, C.c_int, C.POINTER(_P)],
+    "ttn_sweep_init": [_P, _I],
+    "ttn_sweep_destroy": [_P],
+    "sweep_step": [_P, _P, _I, _I, _P, _P, _P],
+}
+
+
+def lib():
+    """Load libttn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2512_15875_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int32
+        L.ttn_last_error.argtypes = [_P]
+        L.ttn_last_error.restype = C.c_char_p
+        L.ttn_version.argtypes = []
+        L.ttn_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+class TTNError(RuntimeError):
+    pass
+
+
+def _check(status, ctx=None):
+    if status != 0:
+        msg = lib().ttn_last_error(ctx.h if ctx is not None else None)
+        raise TTNError(f"ttn status {status}: {msg.decode() if msg else ''}")
+
+
+def _i32(seq) -> C.Array:
+    arr = (C.c_int32 * len(seq))(*[int(x) for x in seq])
+    return arr
+
+
+def _ptrs(seq) -> C.Array:
+    return (C.c_void_p * len(seq))(*[(None if x is None else int(x)) for x in seq])
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def torch_dtype(dt: int):
+    return torch.float64 if dt == F64 else torch.float32
+
+
+class Context:
+    def __init__(self, device: int = 0, workspace_bytes: int = 1 << 30, stream=None):
+        self.h = C.c_void_p()
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        _check(lib().ttn_ctx_create(device, C.c_void_p(s.cuda_stream), workspace_bytes, C.byref(self.h)))
+        self.device = device
+
+    def set_stream(self, stream):
+        _check(lib().ttn_ctx_set_stream(self.h, C.c_void_p(stream.cuda_stream)), self)
+
+    def sync(self):
+        _check(lib().ttn_ctx_sync(self.h), self)
+
+    def close(self):
+        if self.h:
+            lib().ttn_ctx_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tree:
+    def __init__(self, parent: Sequence[int], phys: Sequence[int]):
+        self.parent = list(parent)
+        self.phys = list(phys)
+        self.n = len(parent)
+        self.h = C.c_void_p()
+        _check(lib().ttn_tree_create(self.n, _i32(parent), _i32(phys), C.byref(self.h)))
+        self.children = [[v for v in range(self.n) if self.parent[v] == u] for u in range(self.n)]
+        self.root = self.parent.index(-1)
+
+    def nbrs(self, u):
+        return ([self.parent[u]] if self.parent[u] >= 0 else []) + self.children[u]
+
+    def __del__(self):
+        try:
+            lib().ttn_tree_destroy(self.h)
+        except Exception:
+            pass
+
+
+def dslot(tree: Tree, u: int, v: int) -> int:
+    """Directed-edge slot of u -> v."""
+    return 2 * u if tree.parent[u] == v else 2 * v + 1
+
+
+class TTNO:
+    """TTNO handle over caller-owned device tensors W[u] (legs [w_N..., p, q])."""
+
+    def __init__(self, ctx: Context, tree: Tree, W: List[torch.Tensor], op_bond: Sequence[int], dtype: int):
+        self.W = W
+        self.M = list(op_bond)
+        self.dtype = dtype
+        self.h = C.c_void_p()
+        _check(lib().ttn_ttno_create(ctx.h, tree.h, _i32(op_bond), dtype, _ptrs([w.data_ptr() for w in W]),
+                                     C.byref(self.h)), ctx)
+
+    def __del__(self):
+        try:
+            lib().ttn_ttno_destroy(self.h)
+        except Exception:
+            pass
+
+
+class Block:
+    """k states; node u stored as a [k, *legdims(u)] device tensor."""
+
+    def __init__(self, ctx: Context, tree: Tree, k: int, bond: Sequence[int], dtype: int,
+                 tensors: Optional[List[torch.Tensor]] = None, device="cuda"):
+        self.tree, self.k, self.bond, self.dtype = tree, k, list(bond), dtype
+        if tensors is None:
+            tensors = [torch.zeros((k,) + tuple(self.legdims(u)), dtype=torch_dtype(dtype), device=device)
+                       for u in range(tree.n)]
+        self.t = tensors
+        self.h = C.c_void_p()
+        _check(lib().ttn_block_create(ctx.h, tree.h, k, _i32(bond), dtype, _ptrs([x.data_ptr() for x in tensors]),
+                                      C.byref(self.h)), ctx)
+
+    def legdims(self, u):
+        tr = self.tree
+        d = []
+        for v in tr.nbrs(u):
+            d.append(self.bond[u] if tr.parent[u] == v else self.bond[v])
+        d.append(tr.phys[u])
+        return d
+
+    def __del__(self):
+        try:
+            lib().ttn_block_destroy(self.h)
+        except Exception:
+            pass
+
+
+class Envs:
+    """Environment slots: directed edge s holds [n_slots, Db, M, Da]."""
+
+    def __init__(self, ctx: Context, tree: Tree, n_slots: int, bra_bond, op_bond, ket_bond, dtype: int,
+                 edges: Optional[Sequence] = None, device="cuda"):
+        self.tree, self.n_slots, self.dtype = tree, n_slots, dtype
+        self.Db, self.Da = list(bra_bond), list(ket_bond)
+        self.M = list(op_bond) if op_bond is not None else [1] * tree.n
+        self.slots: List[Optional[torch.Tensor]] = [None] * (2 * tree.n)
+        for u in range(tree.n):
+            if tree.parent[u] < 0:
+                continue
+            for s in (2 * u, 2 * u + 1):
+                if edges is not None and s not in edges:
+                    continue
+                self.slots[s] = torch.zeros((n_slots, self.Db[u], self.M[u], self.Da[u]),
+                                            dtype=torch_dtype(dtype), device=device)
+        self.h = C.c_void_p()
+        _check(lib().ttn_envs_create(ctx.h, tree.h, n_slots, _i32(bra_bond),
+                                     None if op_bond is None else _i32(op_bond), _i32(ket_bond), dtype,
+                                     _ptrs([None if x is None else x.data_ptr() for x in self.slots]),
+                                     C.byref(self.h)), ctx)
+
+    def get(self, u, v) -> torch.Tensor:
+        return self.slots[dslot(self.tree, u, v)]
+
+    def __del__(self):
+        try:
+            lib().ttn_envs_destroy(self.h)
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- hot-path calls
+
+def ttno_env_update(ctx: Context, tree: Tree, op: Optional[TTNO], bra: Block, ket: Block, pair_bra: torch.Tensor,
+                    pair_ket: torch.Tensor, node: int, toward: int, envs: Envs, compute: int):
+    n = int(pair_bra.numel())
+    _check(lib().ttno_env_update(ctx.h, tree.h, None if op is None else op.h, bra.h, ket.h, n, _ptr(pair_bra),
+                                 _ptr(pair_ket), node, toward, envs.h, compute), ctx)
+
+
+def ttno_env_close(ctx: Context, tree: Tree, op: Optional[TTNO], bra: Block, ket: Block, pair_bra: torch.Tensor,
+                   pair_ket: torch.Tensor, node: int, envs: Envs, out: torch.Tensor, compute: int):
+    n = int(pair_bra.numel())
+    _check(lib().ttno_env_close(ctx.h, tree.h, None if op is None else op.h, bra.h, ket.h, n, _ptr(pair_bra),
+                                _ptr(pair_ket), node, envs.h, _ptr(out), compute), ctx)
+
+
+def heff_apply_block(ctx: Context, tree: Tree, op: Optional[TTNO], envs: Envs, node: int, k: int,
+                     X: Optional[torch.Tensor], Y: torch.Tensor, pair_ids=None, x_ids=None, shift=None, alpha=None,
+                     flags: int = HEFF_APPLY, compute: int = F64):
+    x_rows = int(X.shape[0]) if X is not None else 0
+    _check(lib().heff_apply_block(ctx.h, tree.h, None if op is None else op.h, envs.h, node, k, _ptr(pair_ids),
+                                  _ptr(x_ids), _ptr(shift), _ptr(alpha), _ptr(X), x_rows, _ptr(Y), flags,
+                                  compute), ctx)
+
+
+def flops_heff(tree: Tree, op: Optional[TTNO], envs: Envs, node: int, k: int) -> float:
+    out = C.c_double()
+    _check(lib().ttn_flops_heff(None, tree.h, None if op is None else op.h, envs.h, node, k, C.byref(out)))
+    return out.value
+
+
+def flops_env(tree: Tree, op: Optional[TTNO], bra: Block, ket: Block, node: int, toward: int) -> float:
+    out = C.c_double()
+    _check(lib().ttn_flops_env(None, tree.h, None if op is None else op.h, bra.h, ket.h, node, toward,
+                               C.byref(out)))
+    return out.value
+
+
+def rayleigh_ritz(ctx: Context, H: torch.Tensor, S: torch.Tensor, m: Sequence[int], nev: int,
+                  drop_tol: float = 1e-12, allow_svqb: bool = True):
+    """H, S: [batch, ld, ld] float64 device tensors.  Returns (evals, V, rank)."""
+    batch, ld = H.shape[0], H.shape[1]
+    evals = torch.empty((batch, nev), dtype=torch.float64, device=H.device)
+    V = torch.empty((batch, ld, nev), dtype=torch.float64, device=H.device)
+    rank = torch.empty((batch,), dtype=torch.int32, device=H.device)
+    _check(lib().rayleigh_ritz(ctx.h, batch, _i32(m), ld, _ptr(H), _ptr(S), nev, drop_tol, 1 if allow_svqb else 0,
+                               _ptr(evals), _ptr(V), _ptr(rank)), ctx)
+    return evals, V, rank
+
+
+def block_move_centre(ctx: Context, b: Block, u: int, v: int):
+    _check(lib().ttn_block_move_centre(ctx.h, b.h, u, v), ctx)
+
+
+def block_scale_node(ctx: Context, b: Block, u: int, scale: torch.Tensor):
+    _check(lib().ttn_block_scale_node(ctx.h, b.h, u, _ptr(scale)), ctx)
+
+
+def block_node_norms2(ctx: Context, b: Block, u: int, out: torch.Tensor):
+    _check(lib().ttn_block_node_norms2(ctx.h, b.h, u, _ptr(out)), ctx)
+
+
+def version() -> str:
+    return lib().ttn_version().decode()

@@ -1,0 +1,237 @@
+"""Kernel parity: the HIP path (through the C ABI) against the FP64 oracle on
+identical inputs.  Norm-wise relative error gates: FP64 1e-12, FP32 2e-5,
+BF16-in/FP32-accumulate 3e-2."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import ttn as ottn
+from tests.gpu_util import TOL, node_case, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+T = None
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2512_15875_amd import ttn
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ttn.lib()
+    return ttn
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    return api.Context(0, workspace_bytes=2 << 30)
+
+
+# (kappa, d, Db, M, Da, k): node classes of the workloads plus ragged shapes
+CASES = [
+    (1, 8, [8], [3], [8], 7),                              # binary-tree leaf
+    (2, 6, [8, 8], [5, 4], [8, 8], 10),                    # MPS middle site
+    (2, 9, [12, 9], [9, 5], [12, 9], 5),                   # fork chain node
+    (3, 1, [12, 11, 10], [7, 13, 5], [12, 11, 10], 4),     # auxiliary branching node
+    (3, 3, [17, 23, 5], [7, 3, 11], [17, 23, 5], 3),       # ragged, several tiles
+    (3, 1, [24, 24, 24], [21, 14, 14], [24, 24, 24], 2),   # binary tree level-2 shape
+    (2, 1, [24, 24], [63, 63], [24, 24], 3),               # binary-tree root shape
+]
+
+
+def _setup(api, ctx, kappa, d, Db, M, Da, k, seed, dt, op=True):
+    tree, W, X, E = node_case(kappa, d, Db, M, Da, k, seed, op=op)
+    tdt = torch.float64 if dt == api.F64 else torch.float32
+    sdt = api.F64 if dt == api.F64 else api.F32
+    gt = api.Tree(tree.parent, tree.phys)
+    bond = [0] + [0] * tree.n
+    bond = [0] * tree.n
+    nb = tree.neighbours(1)
+    for i, c in enumerate(nb):
+        e = 1 if c == 0 else c
+        bond[e] = Db[i]
+    kb = list(bond)
+    for i, c in enumerate(nb):
+        kb[1 if c == 0 else c] = Da[i]
+    opb = [0] * tree.n
+    for i, c in enumerate(nb):
+        opb[1 if c == 0 else c] = M[i]
+    gW = None
+    if op:
+        Wd = [to_dev(np.zeros((1,)), tdt) for _ in range(tree.n)]
+        Wd[1] = to_dev(W, tdt)
+        gW = api.TTNO(ctx, gt, Wd, [max(1, x) for x in opb], sdt)
+    edges = [api.dslot(gt, c, 1) for c in nb]
+    envs = api.Envs(ctx, gt, k, [max(1, x) for x in bond], [max(1, x) for x in opb] if op else None,
+                    [max(1, x) for x in kb], sdt, edges=edges)
+    for c in nb:
+        envs.get(c, 1).copy_(to_dev(E[c], tdt))
+    return tree, W, X, E, gt, gW, envs, tdt
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("dt", [0, 1, 2])
+def test_heff_apply_matches_oracle(api, ctx, case, dt):
+    kappa, d, Db, M, Da, k = case
+    tree, W, X, E, gt, gW, envs, tdt = _setup(api, ctx, kappa, d, Db, M, Da, k, 100 + kappa, dt)
+    shift = np.linspace(-3.0, 5.0, k)
+    alpha = np.linspace(0.5, 1.5, k)
+    gX = to_dev(X, tdt)
+    gY = torch.zeros((k,) + tuple(Db) + (d,), dtype=tdt, device="cuda")
+    api.heff_apply_block(ctx, gt, gW, envs, 1, k, gX, gY, shift=to_dev(shift), alpha=to_dev(alpha),
+                         flags=api.HEFF_APPLY, compute=dt)
+    ctx.sync()
+    Y = gY.double().cpu().numpy()
+    for j in range(k):
+        ein = {c: E[c][j] for c in tree.neighbours(1)}
+        ref = alpha[j] * ottn.heff_apply(tree, 1, W, X[j], ein, shift[j]) if Db == Da else None
+        if ref is None:
+            ref = alpha[j] * ottn.heff_apply(tree, 1, W, X[j], ein, 0.0)
+        assert rel_err(Y[j], ref) < TOL[dt], (case, dt, j)
+
+
+@pytest.mark.parametrize("case", CASES[:5])
+def test_heff_identity_operator_and_accumulate(api, ctx, case):
+    kappa, d, Db, M, Da, k = case
+    Da = [x + 1 if i == 0 else x for i, x in enumerate(Da)]  # bra != ket bonds (fitting RHS)
+    tree, W, X, E, gt, gW, envs, tdt = _setup(api, ctx, kappa, d, Db, M, Da, k, 7 + kappa, api.F64, op=False)
+    gX = to_dev(X)
+    base = np.random.default_rng(1).normal(size=(k,) + tuple(Db) + (d,))
+    gY = to_dev(base)
+    alpha = np.linspace(-1.0, 2.0, k)
+    api.heff_apply_block(ctx, gt, None, envs, 1, k, gX, gY, alpha=to_dev(alpha),
+                         flags=api.HEFF_NO_SHIFT | api.HEFF_ACCUM, compute=api.F64)
+    ctx.sync()
+    Y = gY.cpu().numpy()
+    for j in range(k):
+        ein = {c: E[c][j] for c in tree.neighbours(1)}
+        ref = base[j] + alpha[j] * ottn.heff_apply(tree, 1, None, X[j], ein)
+        assert rel_err(Y[j], ref) < 1e-12
+
+
+@pytest.mark.parametrize("case", CASES[:6])
+def test_heff_pair_and_row_indirection(api, ctx, case):
+    kappa, d, Db, M, Da, k = case
+    n_slots = k + 3
+    tree, W, X, E = node_case(kappa, d, Db, M, Da, k, 55, op=True, n_slots=n_slots)
+    # reuse _setup for handles, then overwrite the envs with n_slots slots
+    tree2, W2, X2, E2, gt, gW, envs, tdt = _setup(api, ctx, kappa, d, Db, M, Da, n_slots, 55, api.F64)
+    for c in tree.neighbours(1):
+        envs.get(c, 1).copy_(to_dev(E[c]))
+    gW.W[1].copy_(to_dev(W))
+    pair = np.array([(3 * j + 1) % n_slots for j in range(k)], dtype=np.int32)
+    xid = np.array([(k - 1 - j) for j in range(k)], dtype=np.int32)
+    gY = torch.zeros((k,) + tuple(Db) + (d,), dtype=torch.float64, device="cuda")
+    api.heff_apply_block(ctx, gt, gW, envs, 1, k, to_dev(X), gY, pair_ids=torch.from_numpy(pair).cuda(),
+                         x_ids=torch.from_numpy(xid).cuda(), flags=api.HEFF_NO_SHIFT, compute=api.F64)
+    ctx.sync()
+    Y = gY.cpu().numpy()
+    for j in range(k):
+        ein = {c: E[c][pair[j]] for c in tree.neighbours(1)}
+        ref = ottn.heff_apply(tree, 1, W, X[xid[j]], ein)
+        assert rel_err(Y[j], ref) < 1e-12
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_heff_diag_matches_oracle(api, ctx, case):
+    kappa, d, Db, M, Da, k = case
+    tree, W, X, E, gt, gW, envs, tdt = _setup(api, ctx, kappa, d, Db, M, Db, k, 31, api.F64)
+    shift = np.linspace(1.0, 2.0, k)
+    gY = torch.zeros((k,) + tuple(Db) + (d,), dtype=torch.float64, device="cuda")
+    api.heff_apply_block(ctx, gt, gW, envs, 1, k, None, gY, shift=to_dev(shift), flags=api.HEFF_DIAG,
+                         compute=api.F64)
+    ctx.sync()
+    Y = gY.cpu().numpy()
+    for j in range(k):
+        ein = {c: E[c][j] for c in tree.neighbours(1)}
+        ref = ottn.heff_diag(tree, 1, W, ein, shift[j])
+        assert rel_err(Y[j], ref) < 1e-12
+
+
+def _env_setup(api, ctx, kappa, d, Db, M, Da, kb, kk, seed, dt, op=True, toward_leg=0):
+    tree = __import__("tests.gpu_util", fromlist=["star_tree"]).star_tree(kappa, d)
+    rng = np.random.default_rng(seed)
+    nb = tree.neighbours(1)
+    tdt = torch.float64 if dt == api.F64 else torch.float32
+    sdt = api.F64 if dt == api.F64 else api.F32
+    gt = api.Tree(tree.parent, tree.phys)
+    edge = lambda c: 1 if c == 0 else c
+    bb, ab, mb = [1] * tree.n, [1] * tree.n, [1] * tree.n
+    for i, c in enumerate(nb):
+        bb[edge(c)], ab[edge(c)], mb[edge(c)] = Db[i], Da[i], M[i] if op else 1
+    bra = api.Block(ctx, gt, kb, bb, sdt)
+    ket = api.Block(ctx, gt, kk, ab, sdt)
+    A_b = rng.normal(size=(kb,) + tuple(Db) + (d,))
+    A_k = rng.normal(size=(kk,) + tuple(Da) + (d,))
+    bra.t[1].copy_(to_dev(A_b, tdt))
+    ket.t[1].copy_(to_dev(A_k, tdt))
+    W = rng.normal(size=tuple(M) + (d, d)) if op else None
+    gW = None
+    if op:
+        Wd = [to_dev(np.zeros((1,)), tdt) for _ in range(tree.n)]
+        Wd[1] = to_dev(W, tdt)
+        gW = api.TTNO(ctx, gt, Wd, mb, sdt)
+    pairs = [(i, j) for i in range(kb) for j in range(kk)]
+    npairs = len(pairs)
+    envs = api.Envs(ctx, gt, npairs, bb, mb if op else None, ab, sdt)
+    E = {}
+    for i, c in enumerate(nb):
+        E[c] = rng.normal(size=(npairs, Db[i], M[i] if op else 1, Da[i]))
+        envs.get(c, 1).copy_(to_dev(E[c], tdt))
+    pb = torch.tensor([p[0] for p in pairs], dtype=torch.int32, device="cuda")
+    pk = torch.tensor([p[1] for p in pairs], dtype=torch.int32, device="cuda")
+    return tree, gt, bra, ket, A_b, A_k, W, gW, envs, E, pairs, pb, pk, tdt
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("dt", [0, 1, 2])
+def test_env_update_matches_oracle(api, ctx, case, dt):
+    kappa, d, Db, M, Da, _ = case
+    Da = [x + (1 if i == kappa - 1 else 0) for i, x in enumerate(Da)]
+    tree, gt, bra, ket, A_b, A_k, W, gW, envs, E, pairs, pb, pk, tdt = _env_setup(
+        api, ctx, kappa, d, Db, M, Da, 2, 3, 200 + kappa, dt)
+    nb = tree.neighbours(1)
+    for v in nb:
+        api.ttno_env_update(ctx, gt, gW, bra, ket, pb, pk, 1, v, envs, dt)
+        ctx.sync()
+        got = envs.get(1, v).double().cpu().numpy()
+        for p, (i, j) in enumerate(pairs):
+            ein = {c: E[c][p] for c in nb if c != v}
+            ref = ottn.env_update(tree, 1, v, A_b[i], W, A_k[j], ein)
+            assert rel_err(got[p], ref) < TOL[dt], (case, dt, v, p)
+
+
+@pytest.mark.parametrize("case", CASES[:5])
+def test_env_update_identity_and_closure(api, ctx, case):
+    kappa, d, Db, M, Da, _ = case
+    for op in (False, True):
+        tree, gt, bra, ket, A_b, A_k, W, gW, envs, E, pairs, pb, pk, tdt = _env_setup(
+            api, ctx, kappa, d, Db, M, Da, 3, 2, 300 + kappa, api.F64, op=op)
+        nb = tree.neighbours(1)
+        v = nb[-1]
+        api.ttno_env_update(ctx, gt, gW, bra, ket, pb, pk, 1, v, envs, api.F64)
+        out = torch.zeros(len(pairs), dtype=torch.float64, device="cuda")
+        api.ttno_env_close(ctx, gt, gW, bra, ket, pb, pk, 1, envs, out, api.F64)
+        ctx.sync()
+        got = envs.get(1, v).cpu().numpy()
+        cl = out.cpu().numpy()
+        for p, (i, j) in enumerate(pairs):
+            ein = {c: E[c][p] for c in nb if c != v}
+            ref = ottn.env_update(tree, 1, v, A_b[i], W, A_k[j], ein)
+            assert rel_err(got[p], ref) < 1e-12
+            ref_c = ottn.closure(tree, 1, A_b[i], W, A_k[j], {c: E[c][p] for c in nb})
+            assert abs(cl[p] - ref_c) <= 1e-12 * max(1.0, abs(ref_c)) * 10
+
+
+def test_rejects_bad_arguments(api, ctx):
+    kappa, d, Db, M, Da, k = CASES[1]
+    tree, W, X, E, gt, gW, envs, tdt = _setup(api, ctx, kappa, d, Db, M, Da, k, 1, api.F64)
+    gY = torch.zeros((k,) + tuple(Db) + (d,), dtype=torch.float64, device="cuda")
+    with pytest.raises(api.TTNError):  # wrong compute dtype for F64 tensors
+        api.heff_apply_block(ctx, gt, gW, envs, 1, k, to_dev(X), gY, compute=api.F32)
+    with pytest.raises(api.TTNError):  # bad node
+        api.heff_apply_block(ctx, gt, gW, envs, 7, k, to_dev(X), gY, compute=api.F64)
+    with pytest.raises(api.TTNError):  # k beyond the env slots
+        api.heff_apply_block(ctx, gt, gW, envs, 1, k + 1, to_dev(X), gY, compute=api.F64)
+    # k = 0 is a no-op
+    api.heff_apply_block(ctx, gt, gW, envs, 1, 0, to_dev(X), gY, compute=api.F64)
