@@ -252,6 +252,16 @@ ttn_status ttn_sop_destroy(ttn_sop* s);
 
 /* ------------------------------------------------------------ measurement */
 
+/* Per-stage timing: with profiling on, every contraction stage launch is
+ * bracketed by HIP events on the context stream.  The report (synchronises
+ * the stream, then clears the records) is text, one line per (plan, stage):
+ * "plan-key|stage|kernel|launches|total_ms|algorithmic_flops".  `needed`
+ * receives the size including the terminating NUL; the text is written to
+ * `buf` and then cleared only when cap >= needed (call once with buf NULL to
+ * size the buffer). */
+ttn_status ttn_ctx_profile(ttn_ctx* ctx, int32_t on);
+ttn_status ttn_ctx_profile_report(ttn_ctx* ctx, char* buf, int64_t cap, int64_t* needed);
+
 /* Algorithmic flop count of one heff_apply_block call for k states at node u
  * (minimum over pairwise contraction orders, dense operands at unpadded
  * shapes, per-state environments), and of one ttno_env_update per pair. */

@@ -129,8 +129,21 @@ ttn_status exec_plan(ttn_ctx* ctx, const Plan& P, int ct, const std::vector<OpAd
       OpAddr C = last ? out : addr(st.out);
       Epilogue e = last ? ep : Epilogue();
       const int cnt = st.batched ? nz : 1;
+      ttn_prof_rec* rec = nullptr;
+      if (ctx->profile && ctx->prof.size() < 200000) {
+        ctx->prof.emplace_back();
+        rec = &ctx->prof.back();
+        rec->key = P.key;
+        rec->step = (int)s;
+        rec->kernel = gemm_kernel_name(ct, st.g);
+        rec->flops = st.flops * cnt;
+        if (hipEventCreate(&rec->a) != hipSuccess || hipEventCreate(&rec->b) != hipSuccess)
+          return fail(ctx, TTN_E_DEVICE, "hipEventCreate failed");
+        (void)hipEventRecord(rec->a, ctx->stream);
+      }
       hipError_t he = launch_gemm(ct, st.g, A, B, C, e, st.batched ? z0 : 0, cnt, ctx->d_flag, ctx->stream);
       if (he != hipSuccess) return fail(ctx, TTN_E_LAUNCH, std::string("gemm launch: ") + hipGetErrorString(he));
+      if (rec) (void)hipEventRecord(rec->b, ctx->stream);
     }
     shared_done = true;
   }
@@ -274,6 +287,7 @@ Plan* get_plan(ttn_ctx* ctx, const Net& net, int ct, double batch, ttn_status& c
     return nullptr;
   }
   Plan* raw = p.get();
+  raw->key = k.str();
   ctx->plans[k.str()] = std::move(p);
   return raw;
 }
@@ -794,6 +808,49 @@ ttn_status heff_apply_block(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
   }
   ep.accum = flags & TTN_HEFF_ACCUM;
   return exec_plan(ctx, *P, ct, in, o, ep, k, ne, n_loc);
+}
+
+// ================================================================== profiling
+
+ttn_status ttn_ctx_profile(ttn_ctx* ctx, int32_t on) {
+  if (!ctx) return fail(nullptr, TTN_E_ARG, "null context");
+  ctx->profile = on != 0;
+  return TTN_OK;
+}
+
+ttn_status ttn_ctx_profile_report(ttn_ctx* ctx, char* buf, int64_t cap, int64_t* needed) {
+  if (!ctx || !needed) return fail(ctx, TTN_E_ARG, "null argument");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  struct Agg {
+    std::string kernel;
+    int64_t count = 0;
+    double ms = 0, flops = 0;
+  };
+  std::map<std::pair<std::string, int>, Agg> agg;
+  for (auto& r : ctx->prof) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) ms = 0;
+    Agg& a = agg[{r.key, r.step}];
+    a.kernel = r.kernel;
+    a.count += 1;
+    a.ms += ms;
+    a.flops += r.flops;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  ctx->prof.clear();
+  std::ostringstream o;
+  for (auto& kv : agg)
+    o << kv.first.first << "|" << kv.first.second << "|" << kv.second.kernel << "|" << kv.second.count << "|"
+      << kv.second.ms << "|" << kv.second.flops << "\n";
+  ctx->prof_text += o.str();
+  const std::string& s = ctx->prof_text;
+  *needed = (int64_t)s.size() + 1;
+  if (buf && cap >= *needed) {
+    std::memcpy(buf, s.c_str(), s.size() + 1);
+    ctx->prof_text.clear();
+  }
+  return TTN_OK;
 }
 
 // ================================================================== flop counts

@@ -295,6 +295,15 @@ static hipError_t launch_ct(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s)
   }
 }
 
+std::string gemm_kernel_name(int ctype, const GemmDesc& gd) {
+  static const int bm[] = {128, 64, 128, 64, 32, 64, 32};
+  static const int bn[] = {128, 64, 64, 128, 64, 32, 32};
+  const int t = gd.tile < 0 || gd.tile > 6 ? 6 : gd.tile;
+  const int bk = ctype == 2 ? 32 : 16;
+  return "ogemm_kernel<" + std::to_string(ctype) + ", " + std::to_string(bm[t]) + ", " + std::to_string(bn[t]) + ", " +
+         std::to_string(bk) + ", " + (gd.a_mfast ? "true" : "false") + ", " + (gd.b_nfast ? "true" : "false") + ">";
+}
+
 hipError_t launch_gemm(int ctype, const GemmDesc& gd, const OpAddr& A, const OpAddr& B, const OpAddr& C,
                        const Epilogue& ep, int z0, int nz, int* flag, hipStream_t s) {
   KArgs a;

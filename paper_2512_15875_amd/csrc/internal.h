@@ -54,6 +54,8 @@ struct Epilogue {
 hipError_t launch_gemm(int ctype, const GemmDesc& g, const OpAddr& A, const OpAddr& B, const OpAddr& C,
                        const Epilogue& ep, int z0, int nz, int* flag, hipStream_t s);
 
+std::string gemm_kernel_name(int ctype, const GemmDesc& g);
+
 hipError_t launch_batched_dot(int ctype, const void* X, const int32_t* xtab, int64_t xstride, const void* Y,
                               int64_t ystride, int64_t n, int nz, int z0, double* out, hipStream_t s);
 
@@ -93,6 +95,7 @@ struct Step {
 };
 
 struct Plan {
+  std::string key;
   int n_in = 0;
   std::vector<Step> steps;
   std::vector<int64_t> inter_off;  // workspace offset (elements, per batch item scaled) of each intermediate
@@ -173,7 +176,18 @@ struct ttn_envs {
   int64_t slot_elems(int u, int v) const { return (int64_t)eb(u, v) * em(u, v) * ea(u, v); }
 };
 
+struct ttn_prof_rec {
+  std::string key;     // plan key
+  int step = 0;        // stage index in the plan
+  std::string kernel;  // kernel instantiation
+  double flops = 0;    // algorithmic flops of this launch
+  hipEvent_t a = nullptr, b = nullptr;
+};
+
 struct ttn_ctx {
+  bool profile = false;
+  std::vector<ttn_prof_rec> prof;
+  std::string prof_text;  // aggregated, not yet returned
   int device = 0;
   hipStream_t stream = nullptr;
   void* ws = nullptr;

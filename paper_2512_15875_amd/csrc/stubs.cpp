@@ -12,8 +12,4 @@ TTN_UNIMPL(ttn_status sweep_step(ttn_ctx*, ttn_sweep*, int32_t, int32_t, const t
 TTN_UNIMPL(ttn_status ttn_block_move_centre(ttn_ctx*, ttn_block*, int32_t, int32_t))
 TTN_UNIMPL(ttn_status ttn_block_scale_node(ttn_ctx*, ttn_block*, int32_t, const double*))
 TTN_UNIMPL(ttn_status ttn_block_node_norms2(ttn_ctx*, const ttn_block*, int32_t, double*))
-TTN_UNIMPL(ttn_status ttn_sop_build(const ttn_tree*, const int32_t*, int32_t, const double*, const int32_t*, int32_t, const int32_t*, const int32_t*, const int32_t*, const double*, double, ttn_sop**))
-TTN_UNIMPL(ttn_status ttn_sop_bonds(const ttn_sop*, int32_t*))
-TTN_UNIMPL(ttn_status ttn_sop_tensor(const ttn_sop*, int32_t, double*, int64_t))
-TTN_UNIMPL(ttn_status ttn_sop_destroy(ttn_sop*))
 }

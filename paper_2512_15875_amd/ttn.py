@@ -59,6 +59,8 @@ _SIGS = {
     "ttn_sweep_init": [_P, _I],
     "ttn_sweep_destroy": [_P],
     "sweep_step": [_P, _P, _I, _I, _P, _P, _P],
+    "ttn_ctx_profile": [_P, _I],
+    "ttn_ctx_profile_report": [_P, C.c_char_p, C.c_int64, C.POINTER(C.c_int64)],
 }
 
 
@@ -298,6 +300,57 @@ def block_scale_node(ctx: Context, b: Block, u: int, scale: torch.Tensor):
 
 def block_node_norms2(ctx: Context, b: Block, u: int, out: torch.Tensor):
     _check(lib().ttn_block_node_norms2(ctx.h, b.h, u, _ptr(out)), ctx)
+
+
+def sop_build(tree: Tree, node_mode: Sequence[int], omega, dims, monomials, coefs, rel_tol: float = 1e-13):
+    """Compile a sum-of-products Hamiltonian to TTNO tensors on the host (FP64).
+    Returns (list of numpy arrays W[u], op_bond list)."""
+    import numpy as np
+    n_modes = len(omega)
+    ptr, mm, pw = [0], [], []
+    for mono in monomials:
+        for m, p in mono:
+            mm.append(m)
+            pw.append(p)
+        ptr.append(len(mm))
+    h = C.c_void_p()
+    om = (C.c_double * n_modes)(*[float(x) for x in omega])
+    cf = (C.c_double * max(1, len(coefs)))(*[float(x) for x in coefs])
+    _check(lib().ttn_sop_build(tree.h, _i32(node_mode), n_modes, om, _i32(dims), len(monomials), _i32(ptr),
+                               _i32(mm if mm else [0]), _i32(pw if pw else [0]), cf, rel_tol, C.byref(h)))
+    try:
+        bonds = (C.c_int32 * tree.n)()
+        _check(lib().ttn_sop_bonds(h, bonds))
+        bonds = list(bonds)
+        W = []
+        for u in range(tree.n):
+            shp = []
+            for v in tree.nbrs(u):
+                shp.append(bonds[u] if tree.parent[u] == v else bonds[v])
+            shp += [tree.phys[u], tree.phys[u]]
+            buf = np.zeros(int(np.prod(shp)), dtype=np.float64)
+            _check(lib().ttn_sop_tensor(h, u, buf.ctypes.data_as(C.POINTER(C.c_double)), buf.size))
+            W.append(buf.reshape(shp))
+        return W, bonds
+    finally:
+        lib().ttn_sop_destroy(h)
+
+
+def profile(ctx: Context, on: bool):
+    _check(lib().ttn_ctx_profile(ctx.h, 1 if on else 0), ctx)
+
+
+def profile_report(ctx: Context):
+    """[(plan_key, stage, kernel, launches, total_ms, flops)] since the last report."""
+    need = C.c_int64()
+    _check(lib().ttn_ctx_profile_report(ctx.h, None, 0, C.byref(need)), ctx)
+    buf = C.create_string_buffer(int(need.value) + 1024)
+    _check(lib().ttn_ctx_profile_report(ctx.h, buf, len(buf), C.byref(need)), ctx)
+    out = []
+    for line in buf.value.decode().splitlines():
+        k, st, kern, cnt, ms, fl = line.split("|")
+        out.append((k, int(st), kern, int(cnt), float(ms), float(fl)))
+    return out
 
 
 def version() -> str:
