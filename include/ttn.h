@@ -180,7 +180,10 @@ ttn_status rayleigh_ritz(ttn_ctx* ctx, int32_t batch, const int32_t* m, int32_t 
 
 /* ------------------------------------------------------------ sweep (ALS / fitting) */
 
-typedef enum { TTN_SOLVE_MINRES = 0, TTN_SOLVE_DIAG = 1, TTN_SOLVE_FIT = 2 } ttn_solve_mode;
+/* MINRES: local MINRES on (H_eff - s_j); DIAG: y = b / (diag(H_eff) - s_j);
+ * FIT: y_u = the fitting sum; SKIP: no local solve (only the centre move, as
+ * on the later visits of a node during an Euler tour). */
+typedef enum { TTN_SOLVE_MINRES = 0, TTN_SOLVE_DIAG = 1, TTN_SOLVE_FIT = 2, TTN_SOLVE_SKIP = 3 } ttn_solve_mode;
 
 typedef struct {
   int32_t mode;      /* ttn_solve_mode */
@@ -201,6 +204,9 @@ typedef struct ttn_sweep ttn_sweep;
  * MINRES vectors at creation.  The target block must be in canonical form
  * with its orthogonality centre at `centre`; ttn_sweep_init computes every
  * environment toward the centre. */
+/* term_target / term_source are HOST int32 arrays (copied); term_coef are
+ * DEVICE double arrays read at every FIT step (so coefficients may change
+ * between sweeps, e.g. the Rayleigh-Ritz vectors of an LOBPCG iteration). */
 ttn_status ttn_sweep_create(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, ttn_block* target,
                             int32_t n_src, const ttn_ttno* const* src_op, const ttn_block* const* src_block,
                             const int32_t* n_terms, const int32_t* const* term_target,

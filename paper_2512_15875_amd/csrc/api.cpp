@@ -294,6 +294,10 @@ Plan* get_plan(ttn_ctx* ctx, const Net& net, int ct, double batch, ttn_status& c
 
 }  // namespace
 
+namespace ttn {
+ttn_status api_fail(ttn_ctx* ctx, ttn_status code, const std::string& msg) { return fail(ctx, code, msg); }
+}  // namespace ttn
+
 // ================================================================== housekeeping
 
 extern "C" {
@@ -350,6 +354,8 @@ ttn_status ttn_ctx_destroy(ttn_ctx* ctx) {
   if (!ctx) return TTN_OK;
   (void)hipStreamSynchronize(ctx->stream);
   ctx->plans.clear();
+  for (auto& kv : ctx->tables) (void)hipFree(kv.second);
+  ctx->tables.clear();
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->d_flag) (void)hipFree(ctx->d_flag);
   delete ctx;
@@ -651,6 +657,17 @@ ttn_status heff_apply_block(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
                             int32_t k, const int32_t* pair_ids, const int32_t* x_ids, const double* shift,
                             const double* alpha, const void* X, int32_t x_rows, void* Y, uint32_t flags,
                             ttn_dtype compute) {
+  return ttn::heff_apply_rows(ctx, t, op, envs, node, k, pair_ids, x_ids, nullptr, k, shift, alpha, X, x_rows, Y,
+                              flags, compute);
+}
+
+}  // extern "C"
+
+namespace ttn {
+ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_envs* envs, int32_t node,
+                           int32_t k, const int32_t* pair_ids, const int32_t* x_ids, const int32_t* y_ids,
+                           int32_t y_rows, const double* shift, const double* alpha, const void* X, int32_t x_rows,
+                           void* Y, uint32_t flags, ttn_dtype compute) {
   if (!ctx || !t || !envs || !Y) return fail(ctx, TTN_E_ARG, "null argument");
   if (node < 0 || node >= t->n) return fail(ctx, TTN_E_ARG, "bad node");
   if (k < 0) return fail(ctx, TTN_E_ARG, "negative k");
@@ -661,6 +678,7 @@ ttn_status heff_apply_block(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
     return fail(ctx, TTN_E_DTYPE, "tensor dtype does not match the compute dtype");
   if ((op == nullptr) != envs->identity) return fail(ctx, TTN_E_ARG, "operator / environment kind mismatch");
   if (!pair_ids && k > envs->n_slots) return fail(ctx, TTN_E_ARG, "k exceeds the env slots");
+  if (!y_ids && k > y_rows) return fail(ctx, TTN_E_ARG, "Y has fewer rows than the states");
   if (!(flags & TTN_HEFF_DIAG) && (x_rows < 1 || (!x_ids && k > x_rows)))
     return fail(ctx, TTN_E_ARG, "X has fewer rows than the states addressed");
   if (k == 0) return TTN_OK;
@@ -756,6 +774,8 @@ ttn_status heff_apply_block(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
     OpAddr o;
     o.base = Y;
     o.bstride = n_loc;
+    o.tab = y_ids;
+    o.tab_max = y_rows;
     Epilogue ep;
     ep.alpha = nullptr;
     ep.shift = (flags & TTN_HEFF_NO_SHIFT) ? nullptr : shift;
@@ -800,6 +820,8 @@ ttn_status heff_apply_block(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
   OpAddr o;
   o.base = Y;
   o.bstride = n_loc;
+  o.tab = y_ids;
+  o.tab_max = y_rows;
   Epilogue ep;
   ep.alpha = alpha;
   if (!(flags & TTN_HEFF_NO_SHIFT) && shift) {
@@ -809,6 +831,10 @@ ttn_status heff_apply_block(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
   ep.accum = flags & TTN_HEFF_ACCUM;
   return exec_plan(ctx, *P, ct, in, o, ep, k, ne, n_loc);
 }
+
+}  // namespace ttn
+
+extern "C" {
 
 // ================================================================== profiling
 

@@ -76,6 +76,12 @@ struct DiagDesc {
 // Wd[w..., p] = W[w..., p, p] at ws[0..); Ed_i[z][b][w] = E_i[pair(z)][b][w][b] at ws[ed_off[i]..)
 hipError_t launch_diag_gather(int ctype, const DiagDesc& dd, void* ws, const int64_t* ed_off, int nz, hipStream_t s);
 
+// per-state scalar recurrence of the batched MINRES (minres.hip)
+struct MinresState {
+  double beta, c1, s1, c2, s2, phibar, tol;
+  int done, iters;
+};
+
 // ------------------------------------------------------------------ contraction plans (plan.cpp)
 
 struct Tensor {              // one operand of a network
@@ -124,6 +130,16 @@ double min_flops(const std::vector<Tensor>& in, const std::map<int, int>& dims, 
 }  // namespace ttn
 
 // ------------------------------------------------------------------ handles
+
+struct ttn_ctx;
+namespace ttn {
+// heff_apply_block with an output-row table (y_ids[j] = row of Y written by state j)
+ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_envs* envs, int32_t node,
+                           int32_t k, const int32_t* pair_ids, const int32_t* x_ids, const int32_t* y_ids,
+                           int32_t y_rows, const double* shift, const double* alpha, const void* X, int32_t x_rows,
+                           void* Y, uint32_t flags, ttn_dtype compute);
+ttn_status api_fail(ttn_ctx* ctx, ttn_status code, const std::string& msg);
+}  // namespace ttn
 
 struct ttn_tree {
   int n = 0, root = -1;
@@ -195,4 +211,5 @@ struct ttn_ctx {
   std::string err;
   int* d_flag = nullptr;  // non-finite / not-PD flags
   std::map<std::string, std::unique_ptr<ttn::Plan>> plans;
+  std::map<std::string, int32_t*> tables;  // device offset tables (QR rows etc.)
 };

@@ -1,0 +1,493 @@
+// FP64 dense linear algebra of the hot path, on the device:
+//  * Rayleigh-Ritz for the LOBPCG / inverse-iteration subspaces (one
+//    workgroup per problem): Cholesky of the overlap (SVQB fallback through a
+//    Jacobi eigendecomposition of the overlap), reduction to a standard
+//    symmetric problem, cyclic parallel Jacobi eigensolver, back-transform;
+//  * the QR gauge move of a block (one workgroup per state, Householder);
+//  * per-state norms and scaling of node tensors.
+// Everything accumulates in double, whatever the storage dtype.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace ttn {
+
+#define NT 1024  // threads per workgroup of the dense kernels
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Cyclic Jacobi on the symmetric n x n matrix A (row-major, leading dim ld) in
+// global memory; V (n x n, ld) receives the eigenvectors (columns).  Parallel
+// ordering: round-robin tournament of n' = n rounded up to even players.
+__device__ void jacobi_eig(double* A, double* V, int n, int ld, double* sh_c, double* sh_s, int* sh_p, int* sh_q,
+                           double* red) {
+  const int t = threadIdx.x;
+  for (int i = t; i < n * n; i += blockDim.x) {
+    const int r = i / n, c = i - r * n;
+    V[r * ld + c] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int np = (n + 1) & ~1;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0, tot = 0;
+    for (int i = t; i < n * n; i += blockDim.x) {
+      const int r = i / n, c = i - r * n;
+      const double a = A[r * ld + c];
+      if (r != c) off += a * a;
+      tot += a * a;
+    }
+    off = block_sum(off, red);
+    tot = block_sum(tot, red);
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int round = 0; round < np - 1; ++round) {
+      // pairing: player 0 fixed, the rest rotate
+      for (int i = t; i < np / 2; i += blockDim.x) {
+        int a = (i == 0) ? 0 : 1 + (i - 1 + round) % (np - 1);
+        int b = 1 + (np - 2 - i + round) % (np - 1);
+        if (a > b) {
+          const int x = a;
+          a = b;
+          b = x;
+        }
+        sh_p[i] = a;
+        sh_q[i] = b;
+        double c = 1.0, s = 0.0;
+        if (b < n) {
+          const double apq = A[a * ld + b];
+          if (apq != 0.0) {
+            const double app = A[a * ld + a], aqq = A[b * ld + b];
+            const double theta = (aqq - app) / (2.0 * apq);
+            const double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+          }
+        }
+        sh_c[i] = c;
+        sh_s[i] = s;
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int e = t; e < (np / 2) * n; e += blockDim.x) {
+        const int i = e / n, col = e - i * n;
+        const int p = sh_p[i], q = sh_q[i];
+        if (q >= n) continue;
+        const double c = sh_c[i], s = sh_s[i];
+        const double ap = A[p * ld + col], aq = A[q * ld + col];
+        A[p * ld + col] = c * ap - s * aq;
+        A[q * ld + col] = s * ap + c * aq;
+      }
+      __syncthreads();
+      // columns: A <- A J ; V <- V J
+      for (int e = t; e < (np / 2) * n; e += blockDim.x) {
+        const int i = e / n, row = e - i * n;
+        const int p = sh_p[i], q = sh_q[i];
+        if (q >= n) continue;
+        const double c = sh_c[i], s = sh_s[i];
+        const double ap = A[row * ld + p], aq = A[row * ld + q];
+        A[row * ld + p] = c * ap - s * aq;
+        A[row * ld + q] = s * ap + c * aq;
+        const double vp = V[row * ld + p], vq = V[row * ld + q];
+        V[row * ld + p] = c * vp - s * vq;
+        V[row * ld + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// One problem per workgroup.  Scratch per problem: 4 ld^2 doubles.
+__global__ __launch_bounds__(NT) void rr_kernel(const int32_t* m_arr, int ld, const double* H, const double* S,
+                                                int nev, double drop_tol, int allow_svqb, double* evals, double* Vout,
+                                                int32_t* rank_out, double* scratch, int* flag) {
+  __shared__ double red[NT];
+  __shared__ double sh_c[512], sh_s[512];
+  __shared__ int sh_p[512], sh_q[512];
+  __shared__ double piv[512];
+  __shared__ int sh_ord[512];
+  __shared__ int use_chol, rank_sh;
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int m = m_arr[b];
+  const size_t L2 = (size_t)ld * ld;
+  const double* Hb = H + b * L2;
+  const double* Sb = S + b * L2;
+  double* L = scratch + (size_t)b * 4 * L2;  // Cholesky factor / basis B
+  double* C = L + L2;                         // reduced matrix
+  double* Y = C + L2;                         // eigenvectors of C
+  double* T = Y + L2;                         // temporary
+  // symmetrised copies
+  for (int i = t; i < m * m; i += NT) {
+    const int r = i / m, c = i - r * m;
+    L[r * ld + c] = 0.5 * (Sb[r * ld + c] + Sb[c * ld + r]);
+    T[r * ld + c] = 0.5 * (Hb[r * ld + c] + Hb[c * ld + r]);
+  }
+  __syncthreads();
+  double dmax = 0;
+  for (int i = t; i < m; i += NT) dmax = fmax(dmax, L[i * ld + i]);
+  red[t] = dmax;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (t < w) red[t] = fmax(red[t], red[t + w]);
+    __syncthreads();
+  }
+  dmax = red[0];
+  __syncthreads();
+  if (t == 0) use_chol = 1;
+  __syncthreads();
+  // Cholesky in place (lower triangle of L), column by column
+  for (int j = 0; j < m; ++j) {
+    if (t == 0) {
+      double d = L[j * ld + j];
+      for (int k = 0; k < j; ++k) d -= L[j * ld + k] * L[j * ld + k];
+      if (!(d > drop_tol * dmax)) use_chol = 0;
+      piv[j] = d > 0 ? sqrt(d) : 0.0;
+      L[j * ld + j] = piv[j];
+    }
+    __syncthreads();
+    if (!use_chol) break;
+    for (int i = j + 1 + t; i < m; i += NT) {
+      double s = L[i * ld + j];
+      for (int k = 0; k < j; ++k) s -= L[i * ld + k] * L[j * ld + k];
+      L[i * ld + j] = s / piv[j];
+    }
+    __syncthreads();
+  }
+  int r;
+  if (use_chol) {
+    r = m;
+    // C = L^{-1} Hs L^{-T}: X = L^{-1} Hs (forward substitution per column), then C = L^{-1} X^T
+    for (int c = t; c < m; c += NT) {
+      for (int i = 0; i < m; ++i) {
+        double s = T[i * ld + c];
+        for (int k = 0; k < i; ++k) s -= L[i * ld + k] * Y[k * ld + c];
+        Y[i * ld + c] = s / L[i * ld + i];
+      }
+    }
+    __syncthreads();
+    for (int c = t; c < m; c += NT) {
+      for (int i = 0; i < m; ++i) {
+        double s = Y[c * ld + i];  // X^T[i][c] = X[c][i]
+        for (int k = 0; k < i; ++k) s -= L[i * ld + k] * C[k * ld + c];
+        C[i * ld + c] = s / L[i * ld + i];
+      }
+    }
+    __syncthreads();
+    // symmetrise
+    for (int i = t; i < m * m; i += NT) {
+      const int a = i / m, c = i - a * m;
+      if (a < c) {
+        const double v = 0.5 * (C[a * ld + c] + C[c * ld + a]);
+        C[a * ld + c] = v;
+        C[c * ld + a] = v;
+      }
+    }
+    __syncthreads();
+  } else {
+    if (!allow_svqb) {
+      if (t == 0) atomicOr(flag + 1, 1);
+      for (int i = t; i < nev; i += NT) evals[b * nev + i] = NAN;
+      if (t == 0) rank_out[b] = 0;
+      return;
+    }
+    // SVQB: S = U Sigma U^T (Jacobi), keep sigma > drop_tol sigma_max, B = U_r Sigma_r^{-1/2}
+    for (int i = t; i < m * m; i += NT) {
+      const int a = i / m, c = i - a * m;
+      C[a * ld + c] = 0.5 * (Sb[a * ld + c] + Sb[c * ld + a]);
+    }
+    __syncthreads();
+    jacobi_eig(C, Y, m, ld, sh_c, sh_s, sh_p, sh_q, red);
+    // eigenvalues on the diagonal of C; select kept columns (in index order)
+    if (t == 0) {
+      double smax = 0;
+      for (int i = 0; i < m; ++i) smax = fmax(smax, C[i * ld + i]);
+      int cnt = 0;
+      for (int i = 0; i < m; ++i)
+        if (C[i * ld + i] > drop_tol * smax) {
+          sh_ord[cnt] = i;
+          piv[cnt] = 1.0 / sqrt(C[i * ld + i]);
+          ++cnt;
+        }
+      rank_sh = cnt;
+    }
+    __syncthreads();
+    r = rank_sh;
+    // L <- B (m x r)
+    for (int i = t; i < m * r; i += NT) {
+      const int a = i / r, j = i - a * r;
+      L[a * ld + j] = Y[a * ld + sh_ord[j]] * piv[j];
+    }
+    __syncthreads();
+    // Y <- Hs B (m x r), then C <- B^T Y (r x r)
+    for (int i = t; i < m * r; i += NT) {
+      const int a = i / r, j = i - a * r;
+      double s = 0;
+      for (int k = 0; k < m; ++k) s += T[a * ld + k] * L[k * ld + j];
+      Y[a * ld + j] = s;
+    }
+    __syncthreads();
+    for (int i = t; i < r * r; i += NT) {
+      const int a = i / r, j = i - a * r;
+      double s = 0;
+      for (int k = 0; k < m; ++k) s += L[k * ld + a] * Y[k * ld + j];
+      C[a * ld + j] = s;
+    }
+    __syncthreads();
+    for (int i = t; i < r * r; i += NT) {
+      const int a = i / r, c = i - a * r;
+      if (a < c) {
+        const double v = 0.5 * (C[a * ld + c] + C[c * ld + a]);
+        C[a * ld + c] = v;
+        C[c * ld + a] = v;
+      }
+    }
+    __syncthreads();
+  }
+  // eigen-decomposition of the reduced r x r problem: C -> diag, Y eigenvectors
+  jacobi_eig(C, Y, r, ld, sh_c, sh_s, sh_p, sh_q, red);
+  // order eigenvalues ascending
+  if (t == 0) {
+    for (int i = 0; i < r; ++i) sh_ord[i] = i;
+    for (int i = 1; i < r; ++i) {  // insertion sort (r <= 512)
+      const int x = sh_ord[i];
+      const double vx = C[x * ld + x];
+      int j = i - 1;
+      while (j >= 0 && C[sh_ord[j] * ld + sh_ord[j]] > vx) {
+        sh_ord[j + 1] = sh_ord[j];
+        --j;
+      }
+      sh_ord[j + 1] = x;
+    }
+    rank_out[b] = r;
+  }
+  __syncthreads();
+  const int ne = nev < r ? nev : r;
+  for (int i = t; i < nev; i += NT) evals[b * nev + i] = i < ne ? C[sh_ord[i] * ld + sh_ord[i]] : NAN;
+  // back-transform: V = B Y  (B = L^{-T} in the Cholesky case)
+  double* Vb = Vout + (size_t)b * ld * nev;
+  if (use_chol) {
+    // solve L^T V = Y_sel  (back substitution per column)
+    for (int j = t; j < ne; j += NT) {
+      const int col = sh_ord[j];
+      for (int i = m - 1; i >= 0; --i) {
+        double s = Y[i * ld + col];
+        for (int k = i + 1; k < m; ++k) s -= L[k * ld + i] * T[k * ld + j];
+        T[i * ld + j] = s / L[i * ld + i];
+      }
+    }
+  } else {
+    for (int e = t; e < m * ne; e += NT) {
+      const int i = e / ne, j = e - i * ne;
+      const int col = sh_ord[j];
+      double s = 0;
+      for (int k = 0; k < r; ++k) s += L[i * ld + k] * Y[k * ld + col];
+      T[i * ld + j] = s;
+    }
+  }
+  __syncthreads();
+  // sign convention: entry of largest magnitude positive
+  for (int j = t; j < ne; j += NT) {
+    int im = 0;
+    double vm = 0;
+    for (int i = 0; i < m; ++i)
+      if (fabs(T[i * ld + j]) > vm) {
+        vm = fabs(T[i * ld + j]);
+        im = i;
+      }
+    piv[j] = T[im * ld + j] < 0 ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  for (int e = t; e < ld * nev; e += NT) {
+    const int i = e / nev, j = e - i * nev;
+    Vb[i * nev + j] = (i < m && j < ne) ? piv[j] * T[i * ld + j] : 0.0;
+  }
+}
+
+hipError_t launch_rr(int batch, const int32_t* d_m, int ld, const double* H, const double* S, int nev, double drop_tol,
+                     int allow_svqb, double* evals, double* V, int32_t* rank, double* scratch, int* flag,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(rr_kernel, dim3(batch), dim3(NT), 0, s, d_m, ld, H, S, nev, drop_tol, allow_svqb, evals, V, rank,
+                     scratch, flag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- QR gauge move
+// Per state z (one workgroup): the node tensor viewed as the matrix
+// A[r][j] = X[z*size + roff[r] + j*cstride] (rows = all other legs, columns =
+// the leg toward the new centre), Householder QR in double with diag(R) >= 0.
+// Q overwrites the tensor; R (n x n) goes to Rout[z].  m x n with m >= n.
+template <typename T>
+__global__ __launch_bounds__(256) void qr_kernel(T* X, int64_t size, const int32_t* roff, int m, int n,
+                                                 int64_t cstride, double* work, double* Rout, int* flag) {
+  __shared__ double red[256];
+  __shared__ double sh_tau, sh_alpha;
+  const int z = blockIdx.x, t = threadIdx.x;
+  T* Xz = X + (int64_t)z * size;
+  double* A = work + (size_t)z * ((size_t)m * n + (size_t)m * n);  // m x n working copy (column-major)
+  double* Vh = A + (size_t)m * n;                                  // Householder vectors (column-major)
+  for (int i = t; i < m * n; i += 256) {
+    const int j = i / m, r = i - j * m;
+    A[i] = (double)Xz[roff[r] + (int64_t)j * cstride];
+  }
+  __syncthreads();
+  double* R = Rout + (size_t)z * n * n;
+  for (int k = 0; k < n; ++k) {
+    double* a = A + (size_t)k * m;
+    double ss = 0;
+    for (int i = k + t; i < m; i += 256) ss += a[i] * a[i];
+    ss = block_sum(ss, red);
+    const double nrm = sqrt(ss);
+    double* v = Vh + (size_t)k * m;
+    if (t == 0) {
+      const double x0 = a[k];
+      const double alpha = nrm == 0.0 ? 0.0 : (x0 >= 0 ? -nrm : nrm);
+      const double v0 = x0 - alpha;
+      const double vn2 = ss - x0 * x0 + v0 * v0;
+      sh_tau = vn2 > 0 ? 2.0 / vn2 : 0.0;
+      sh_alpha = alpha;
+    }
+    __syncthreads();
+    for (int i = t; i < m; i += 256) v[i] = i < k ? 0.0 : (i == k ? a[k] - sh_alpha : a[i]);
+    __syncthreads();
+    const double tau = sh_tau;
+    // apply to columns k..n-1: a_j -= tau (v . a_j) v
+    for (int j = k; j < n; ++j) {
+      double* aj = A + (size_t)j * m;
+      double d = 0;
+      for (int i = k + t; i < m; i += 256) d += v[i] * aj[i];
+      d = block_sum(d, red) * tau;
+      for (int i = k + t; i < m; i += 256) aj[i] -= d * v[i];
+      __syncthreads();
+    }
+  }
+  // R (upper triangle of A) with signs fixed
+  for (int i = t; i < n * n; i += 256) {
+    const int r = i / n, c = i - r * n;
+    R[i] = (c >= r) ? A[(size_t)c * m + r] : 0.0;
+  }
+  __syncthreads();
+  // Q = H_0 ... H_{n-1} applied to the first n unit columns; build in A
+  for (int i = t; i < m * n; i += 256) {
+    const int j = i / m, r = i - j * m;
+    A[i] = (r == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int k = n - 1; k >= 0; --k) {
+    const double* v = Vh + (size_t)k * m;
+    double vn2 = 0;
+    for (int i = k + t; i < m; i += 256) vn2 += v[i] * v[i];
+    vn2 = block_sum(vn2, red);
+    const double tau = vn2 > 0 ? 2.0 / vn2 : 0.0;
+    for (int j = 0; j < n; ++j) {
+      double* qj = A + (size_t)j * m;
+      double d = 0;
+      for (int i = k + t; i < m; i += 256) d += v[i] * qj[i];
+      d = block_sum(d, red) * tau;
+      for (int i = k + t; i < m; i += 256) qj[i] -= d * v[i];
+      __syncthreads();
+    }
+  }
+  // sign fix: diag(R) >= 0
+  __shared__ double sg[512];
+  for (int i = t; i < n; i += 256) sg[i] = R[i * n + i] < 0 ? -1.0 : 1.0;
+  __syncthreads();
+  for (int i = t; i < n * n; i += 256) {
+    const int r = i / n;
+    R[i] *= sg[r];
+  }
+  for (int i = t; i < m * n; i += 256) {
+    const int j = i / m, r = i - j * m;
+    const double q = A[i] * sg[j];
+    if (!isfinite(q)) atomicOr(flag, 1);
+    Xz[roff[r] + (int64_t)j * cstride] = (T)q;
+  }
+}
+
+// Y[z][roff[r] + i*cstride] = sum_j R[z][i][j] X[z][roff[r] + j*cstride]   (into a separate buffer)
+template <typename T>
+__global__ void absorb_kernel(const T* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride,
+                              const double* R, T* Y, int nz) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)m * n;
+  if (e >= per * nz) return;
+  const int z = (int)(e / per);
+  const int64_t rem = e - (int64_t)z * per;
+  const int r = (int)(rem / n), i = (int)(rem - (int64_t)r * n);
+  const T* Xz = X + (int64_t)z * size;
+  const double* Rz = R + (size_t)z * n * n;
+  double s = 0;
+  for (int j = 0; j < n; ++j) s += Rz[i * n + j] * (double)Xz[roff[r] + (int64_t)j * cstride];
+  Y[(int64_t)z * size + roff[r] + (int64_t)i * cstride] = (T)s;
+}
+
+template <typename T>
+static hipError_t qr_t(void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride, double* work,
+                       double* R, int nz, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(qr_kernel<T>, dim3(nz), dim3(256), 0, s, (T*)X, size, roff, m, n, cstride, work, R, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr(int ctype, void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride, double* work,
+                     double* R, int nz, int* flag, hipStream_t s) {
+  if (ctype == 0) return qr_t<double>(X, size, roff, m, n, cstride, work, R, nz, flag, s);
+  return qr_t<float>(X, size, roff, m, n, cstride, work, R, nz, flag, s);
+}
+
+hipError_t launch_absorb(int ctype, const void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride,
+                         const double* R, void* Y, int nz, hipStream_t s) {
+  const int64_t tot = (int64_t)m * n * nz;
+  const unsigned g = (unsigned)((tot + 255) / 256);
+  if (ctype == 0)
+    hipLaunchKernelGGL(absorb_kernel<double>, dim3(g), dim3(256), 0, s, (const double*)X, size, roff, m, n, cstride, R,
+                       (double*)Y, nz);
+  else
+    hipLaunchKernelGGL(absorb_kernel<float>, dim3(g), dim3(256), 0, s, (const float*)X, size, roff, m, n, cstride, R,
+                       (float*)Y, nz);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- norms / scaling
+template <typename T>
+__global__ __launch_bounds__(256) void norms2_kernel(const T* X, int64_t n, double* out) {
+  __shared__ double red[256];
+  const int z = blockIdx.x;
+  const T* x = X + (int64_t)z * n;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += (double)x[i] * (double)x[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[z] = s;
+}
+
+template <typename T>
+__global__ void scale_kernel(T* X, int64_t n, const double* sc, int nz) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * nz) return;
+  const int z = (int)(e / n);
+  X[e] = (T)((double)X[e] * sc[z]);
+}
+
+hipError_t launch_norms2(int ctype, const void* X, int64_t n, int nz, double* out, hipStream_t s) {
+  if (ctype == 0) hipLaunchKernelGGL(norms2_kernel<double>, dim3(nz), dim3(256), 0, s, (const double*)X, n, out);
+  else hipLaunchKernelGGL(norms2_kernel<float>, dim3(nz), dim3(256), 0, s, (const float*)X, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(int ctype, void* X, int64_t n, int nz, const double* sc, hipStream_t s) {
+  const unsigned g = (unsigned)((n * nz + 255) / 256);
+  if (ctype == 0) hipLaunchKernelGGL(scale_kernel<double>, dim3(g), dim3(256), 0, s, (double*)X, n, sc, nz);
+  else hipLaunchKernelGGL(scale_kernel<float>, dim3(g), dim3(256), 0, s, (float*)X, n, sc, nz);
+  return hipGetLastError();
+}
+
+}  // namespace ttn

@@ -1,0 +1,376 @@
+// C ABI: sweeps of local solves over the tree (ALS for (H - s) y = phi,
+// Sec. II.C.4, and variational fitting of sums sum_i c_i O_i phi_i,
+// Sec. II.C.3), one local step per sweep_step call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+using namespace ttn;
+
+namespace ttn {
+ttn_status api_fail(ttn_ctx* ctx, ttn_status code, const std::string& msg);
+ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_envs* envs, int32_t node,
+                           int32_t k, const int32_t* pair_ids, const int32_t* x_ids, const int32_t* y_ids,
+                           int32_t y_rows, const double* shift, const double* alpha, const void* X, int32_t x_rows,
+                           void* Y, uint32_t flags, ttn_dtype compute);
+hipError_t launch_minres_init(int ctype, const void* b, const void* Ax, void* v, void* vprev, void* d1, void* d2,
+                              int64_t n, int k, double rtol, MinresState* st, hipStream_t s);
+hipError_t launch_minres_step(int ctype, void* x, void* v, void* vprev, void* p, const void* dp, void* dpp, int64_t n,
+                              int k, MinresState* st, hipStream_t s);
+hipError_t launch_minres_report(const MinresState* st, int k, int32_t* iters, double* resid, int32_t* n_active,
+                                hipStream_t s);
+hipError_t launch_diag_solve(int ctype, const void* b, const void* dg, void* y, int64_t n, hipStream_t s);
+hipError_t launch_gather_coef(const double* coef, const int32_t* perm, int n, double* out, hipStream_t s);
+}  // namespace ttn
+
+struct ttn_sweep_src {
+  const ttn_ttno* op = nullptr;
+  const ttn_block* blk = nullptr;
+  int n = 0;
+  std::vector<int> tgt, src;          // host copies
+  int32_t* d_tgt = nullptr;           // device [n]
+  int32_t* d_src = nullptr;           // device [n]
+  const double* coef = nullptr;       // device [n] (caller-owned)
+  std::vector<std::vector<int>> rounds;  // term ids per round (unique targets)
+  int32_t* d_perm = nullptr;          // device concatenation of rounds (term ids)
+  int32_t* d_rtgt = nullptr;          // targets in round order
+  int32_t* d_rsrc = nullptr;          // sources in round order
+  double* d_rcoef = nullptr;          // coefficients in round order (gathered per step)
+  ttn_envs* envs = nullptr;
+  std::vector<void*> mem;
+};
+
+struct ttn_sweep {
+  ttn_ctx* ctx = nullptr;
+  const ttn_tree* t = nullptr;
+  const ttn_ttno* op = nullptr;
+  ttn_block* y = nullptr;
+  ttn_dtype compute = TTN_F64;
+  int ct = 0;
+  int k = 0;
+  std::vector<ttn_sweep_src> src;
+  ttn_envs* henv = nullptr;
+  std::vector<void*> hmem;
+  int32_t* d_iota = nullptr;
+  const double* shift = nullptr;
+  // MINRES work: 7 vectors [k][n_loc_max] + state
+  void* vec = nullptr;
+  int64_t nmax = 0;
+  MinresState* st = nullptr;
+  int32_t* d_active = nullptr;
+  ~ttn_sweep() {
+    for (auto& s : src) {
+      for (void* p : s.mem) (void)hipFree(p);
+      (void)hipFree(s.d_tgt);
+      (void)hipFree(s.d_src);
+      (void)hipFree(s.d_perm);
+      (void)hipFree(s.d_rtgt);
+      (void)hipFree(s.d_rsrc);
+      (void)hipFree(s.d_rcoef);
+      delete s.envs;
+    }
+    for (void* p : hmem) (void)hipFree(p);
+    delete henv;
+    (void)hipFree(d_iota);
+    (void)hipFree(vec);
+    (void)hipFree(st);
+    (void)hipFree(d_active);
+  }
+};
+
+namespace {
+
+template <typename T>
+bool dmalloc(T** p, size_t bytes) {
+  return hipMalloc((void**)p, bytes ? bytes : 16) == hipSuccess;
+}
+
+// environment set for (bra = target block, ket = other) with op (nullable)
+ttn_envs* make_envs(const ttn_tree* t, const ttn_block* bra, const ttn_ttno* op, const ttn_block* ket, int n_slots,
+                    ttn_dtype dt, std::vector<void*>& mem, bool& ok) {
+  ttn_envs* e = new ttn_envs();
+  e->t = t;
+  e->n_slots = n_slots;
+  e->Db = bra->D;
+  e->Da = ket->D;
+  e->identity = op == nullptr;
+  e->M = op ? op->M : std::vector<int>(t->n, 1);
+  e->dt = dt;
+  e->slot.assign(2 * t->n, nullptr);
+  const size_t es = dt == TTN_F64 ? 8 : 4;
+  ok = true;
+  for (int u = 0; u < t->n; ++u) {
+    if (u == t->root) continue;
+    const size_t bytes = (size_t)n_slots * e->Db[u] * e->M[u] * e->Da[u] * es;
+    for (int s = 0; s < 2; ++s) {
+      void* p = nullptr;
+      if (hipMalloc(&p, bytes) != hipSuccess) {
+        ok = false;
+        return e;
+      }
+      mem.push_back(p);
+      e->slot[2 * u + s] = p;
+    }
+  }
+  return e;
+}
+
+ttn_status update_envs_across(ttn_sweep* sw, int u, int v) {
+  ttn_ctx* ctx = sw->ctx;
+  if (sw->henv) {
+    ttn_status r = ttno_env_update(ctx, sw->t, sw->op, sw->y, sw->y, sw->k, sw->d_iota, sw->d_iota, u, v, sw->henv,
+                                   sw->compute);
+    if (r != TTN_OK) return r;
+  }
+  for (auto& s : sw->src) {
+    ttn_status r = ttno_env_update(ctx, sw->t, s.op, sw->y, s.blk, s.n, s.d_tgt, s.d_src, u, v, s.envs, sw->compute);
+    if (r != TTN_OK) return r;
+  }
+  return TTN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ttn_status ttn_sweep_create(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, ttn_block* target, int32_t n_src,
+                            const ttn_ttno* const* src_op, const ttn_block* const* src_block, const int32_t* n_terms,
+                            const int32_t* const* term_target, const int32_t* const* term_source,
+                            const double* const* term_coef, const double* shift, ttn_dtype compute, ttn_sweep** out) {
+  if (!ctx || !t || !target || !out || n_src < 0 || n_src > 2 || (n_src > 0 && (!src_block || !n_terms)))
+    return api_fail(ctx, TTN_E_ARG, "bad sweep arguments");
+  if (target->t != t) return api_fail(ctx, TTN_E_ARG, "tree mismatch");
+  const bool f64 = compute == TTN_F64;
+  if ((f64 && target->dt != TTN_F64) || (!f64 && target->dt != TTN_F32))
+    return api_fail(ctx, TTN_E_DTYPE, "target dtype does not match the compute dtype");
+  ttn_sweep* sw = new (std::nothrow) ttn_sweep();
+  if (!sw) return api_fail(ctx, TTN_E_ARG, "out of host memory");
+  sw->ctx = ctx;
+  sw->t = t;
+  sw->op = op;
+  sw->y = target;
+  sw->compute = compute;
+  sw->ct = f64 ? 0 : 1;
+  sw->k = target->k;
+  sw->shift = shift;
+  const size_t es = f64 ? 8 : 4;
+  bool ok = true;
+  std::vector<int32_t> iota(sw->k);
+  for (int i = 0; i < sw->k; ++i) iota[i] = i;
+  if (!dmalloc(&sw->d_iota, iota.size() * 4) ||
+      hipMemcpy(sw->d_iota, iota.data(), iota.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    delete sw;
+    return api_fail(ctx, TTN_E_DEVICE, "allocation failed");
+  }
+  if (op) {
+    if (op->t != t) {
+      delete sw;
+      return api_fail(ctx, TTN_E_ARG, "tree mismatch");
+    }
+    sw->henv = make_envs(t, target, op, target, sw->k, target->dt, sw->hmem, ok);
+    if (!ok) {
+      delete sw;
+      return api_fail(ctx, TTN_E_DEVICE, "environment allocation failed");
+    }
+  }
+  for (int i = 0; i < n_src; ++i) {
+    ttn_sweep_src s;
+    s.op = src_op ? src_op[i] : nullptr;
+    s.blk = src_block[i];
+    s.n = n_terms[i];
+    if (!s.blk || s.blk->t != t || s.n < 1 || !term_target || !term_source || !term_target[i] || !term_source[i]) {
+      delete sw;
+      return api_fail(ctx, TTN_E_ARG, "bad source term list");
+    }
+    if (s.blk->dt != target->dt) {
+      delete sw;
+      return api_fail(ctx, TTN_E_DTYPE, "source dtype differs from the target");
+    }
+    s.tgt.assign(term_target[i], term_target[i] + s.n);
+    s.src.assign(term_source[i], term_source[i] + s.n);
+    for (int j = 0; j < s.n; ++j)
+      if (s.tgt[j] < 0 || s.tgt[j] >= sw->k || s.src[j] < 0 || s.src[j] >= s.blk->k) {
+        delete sw;
+        return api_fail(ctx, TTN_E_ARG, "term target/source out of range");
+      }
+    s.coef = term_coef ? term_coef[i] : nullptr;
+    // rounds with unique targets (greedy)
+    std::vector<std::vector<char>> used;
+    for (int j = 0; j < s.n; ++j) {
+      size_t r = 0;
+      while (r < s.rounds.size() && used[r][s.tgt[j]]) ++r;
+      if (r == s.rounds.size()) {
+        s.rounds.push_back({});
+        used.push_back(std::vector<char>(sw->k, 0));
+      }
+      s.rounds[r].push_back(j);
+      used[r][s.tgt[j]] = 1;
+    }
+    std::vector<int32_t> perm, rt, rs;
+    for (auto& r : s.rounds)
+      for (int j : r) {
+        perm.push_back(j);
+        rt.push_back(s.tgt[j]);
+        rs.push_back(s.src[j]);
+      }
+    const size_t nb = (size_t)s.n * 4;
+    if (!dmalloc(&s.d_tgt, nb) || !dmalloc(&s.d_src, nb) || !dmalloc(&s.d_perm, nb) || !dmalloc(&s.d_rtgt, nb) ||
+        !dmalloc(&s.d_rsrc, nb) || !dmalloc(&s.d_rcoef, (size_t)s.n * 8) ||
+        hipMemcpy(s.d_tgt, s.tgt.data(), nb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s.d_src, s.src.data(), nb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s.d_perm, perm.data(), nb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s.d_rtgt, rt.data(), nb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s.d_rsrc, rs.data(), nb, hipMemcpyHostToDevice) != hipSuccess) {
+      sw->src.push_back(s);
+      delete sw;
+      return api_fail(ctx, TTN_E_DEVICE, "allocation failed");
+    }
+    s.envs = make_envs(t, target, s.op, s.blk, s.n, target->dt, s.mem, ok);
+    sw->src.push_back(s);
+    if (!ok) {
+      delete sw;
+      return api_fail(ctx, TTN_E_DEVICE, "environment allocation failed");
+    }
+  }
+  // MINRES work vectors
+  int64_t nmax = 1;
+  for (int u = 0; u < t->n; ++u) nmax = std::max(nmax, target->size[u]);
+  sw->nmax = nmax;
+  if (!dmalloc(&sw->vec, (size_t)8 * sw->k * nmax * es) || !dmalloc(&sw->st, (size_t)sw->k * sizeof(MinresState)) ||
+      !dmalloc(&sw->d_active, 16)) {
+    delete sw;
+    return api_fail(ctx, TTN_E_DEVICE, "allocation failed");
+  }
+  *out = sw;
+  return TTN_OK;
+}
+
+ttn_status ttn_sweep_destroy(ttn_sweep* sw) {
+  if (sw) (void)hipStreamSynchronize(sw->ctx->stream);
+  delete sw;
+  return TTN_OK;
+}
+
+ttn_status ttn_sweep_init(ttn_sweep* sw, int32_t centre) {
+  if (!sw || centre < 0 || centre >= sw->t->n) return api_fail(sw ? sw->ctx : nullptr, TTN_E_ARG, "bad centre");
+  const ttn_tree* t = sw->t;
+  // post-order of the tree rooted at `centre`: every edge toward the centre
+  std::vector<std::pair<int, int>> order;
+  std::vector<std::pair<int, int>> stk{{centre, -1}};
+  std::vector<std::pair<int, int>> visit;
+  while (!stk.empty()) {
+    auto [u, frm] = stk.back();
+    stk.pop_back();
+    visit.push_back({u, frm});
+    for (int w : t->nb[u])
+      if (w != frm) stk.push_back({w, u});
+  }
+  for (auto it = visit.rbegin(); it != visit.rend(); ++it)
+    if (it->second >= 0) order.push_back(*it);
+  for (auto& e : order) {
+    ttn_status r = update_envs_across(sw, e.first, e.second);
+    if (r != TTN_OK) return r;
+  }
+  return TTN_OK;
+}
+
+ttn_status sweep_step(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, int32_t next, const ttn_solve_opts* opts,
+                      int32_t* iters_out, double* resid_out) {
+  if (!ctx || !sw || !opts || sw->ctx != ctx) return api_fail(ctx, TTN_E_ARG, "bad arguments");
+  const ttn_tree* t = sw->t;
+  if (node < 0 || node >= t->n || (next >= 0 && t->leg_of(node, next) < 0))
+    return api_fail(ctx, TTN_E_ARG, "next is not a neighbour of node");
+  const int u = node, k = sw->k, ct = sw->ct;
+  const size_t es = ct == 0 ? 8 : 4;
+  const int64_t n = sw->y->size[u];
+  char* base = (char*)sw->vec;
+  auto vbuf = [&](int i) { return (void*)(base + (size_t)i * k * sw->nmax * es); };
+  void* y_u = sw->y->ptr[u];
+  ttn_status r = TTN_OK;
+  const int mode = opts->mode;
+  if (mode == TTN_SOLVE_MINRES || mode == TTN_SOLVE_DIAG) {
+    if (!sw->henv || sw->src.size() != 1 || sw->src[0].op != nullptr || sw->src[0].n != k)
+      return api_fail(ctx, TTN_E_ARG, "ALS sweep needs an operator and one identity source term per state");
+    auto& s = sw->src[0];
+    // local right-hand side b_j = (y_j, phi_s(j)) identity environment contracted with phi_u
+    void* b = vbuf(0);
+    r = heff_apply_rows(ctx, t, nullptr, s.envs, u, k, nullptr, s.d_src, nullptr, k, nullptr, nullptr, s.blk->ptr[u],
+                        s.blk->k, b, TTN_HEFF_NO_SHIFT, sw->compute);
+    if (r != TTN_OK) return r;
+    if (mode == TTN_SOLVE_DIAG) {
+      void* dg = vbuf(1);
+      r = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, nullptr, 0, dg,
+                           TTN_HEFF_DIAG, sw->compute == TTN_BF16 ? TTN_F32 : sw->compute);
+      if (r != TTN_OK) return r;
+      hipError_t e = launch_diag_solve(ct, b, dg, y_u, n * k, ctx->stream);
+      if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+    } else {
+      if (opts->maxiter < 0 || !(opts->rtol >= 0)) return api_fail(ctx, TTN_E_ARG, "bad MINRES options");
+      void *v = vbuf(1), *vp = vbuf(2), *p = vbuf(3), *d1 = vbuf(4), *d2 = vbuf(5);
+      // p = (H_eff - s) y_u  (warm start)
+      r = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, y_u, k, p,
+                           TTN_HEFF_APPLY, sw->compute);
+      if (r != TTN_OK) return r;
+      hipError_t e = launch_minres_init(ct, b, p, v, vp, d1, d2, n, k, opts->rtol, sw->st, ctx->stream);
+      if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+      void* dp = d1;
+      void* dpp = d2;
+      const int check_every = 25;
+      for (int it = 0; it < opts->maxiter; ++it) {
+        r = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, v, k, p,
+                             TTN_HEFF_APPLY, sw->compute);
+        if (r != TTN_OK) return r;
+        e = launch_minres_step(ct, y_u, v, vp, p, dp, dpp, n, k, sw->st, ctx->stream);
+        if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+        std::swap(v, vp);
+        std::swap(dp, dpp);
+        if ((it + 1) % check_every == 0 && it + 1 < opts->maxiter) {
+          int32_t act = 0;
+          if (hipMemsetAsync(sw->d_active, 0, 4, ctx->stream) != hipSuccess) return api_fail(ctx, TTN_E_DEVICE, "memset");
+          e = launch_minres_report(sw->st, k, nullptr, nullptr, sw->d_active, ctx->stream);
+          if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+          if (hipMemcpyAsync(&act, sw->d_active, 4, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+              hipStreamSynchronize(ctx->stream) != hipSuccess)
+            return api_fail(ctx, TTN_E_DEVICE, "convergence check failed");
+          if (act == 0) break;
+        }
+      }
+      if (iters_out || resid_out) {
+        e = launch_minres_report(sw->st, k, iters_out, resid_out, nullptr, ctx->stream);
+        if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+      }
+    }
+  } else if (mode == TTN_SOLVE_FIT) {
+    if (hipMemsetAsync(y_u, 0, (size_t)k * n * es, ctx->stream) != hipSuccess)
+      return api_fail(ctx, TTN_E_DEVICE, "memset failed");
+    for (auto& s : sw->src) {
+      if (!s.coef) return api_fail(ctx, TTN_E_ARG, "FIT needs coefficients");
+      hipError_t e = launch_gather_coef(s.coef, s.d_perm, s.n, s.d_rcoef, ctx->stream);
+      if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+      int off = 0;
+      for (auto& rd : s.rounds) {
+        const int cnt = (int)rd.size();
+        r = heff_apply_rows(ctx, t, s.op, s.envs, u, cnt, s.d_perm + off, s.d_rsrc + off, s.d_rtgt + off, k, nullptr,
+                            s.d_rcoef + off, s.blk->ptr[u], s.blk->k, y_u, TTN_HEFF_NO_SHIFT | TTN_HEFF_ACCUM,
+                            sw->compute);
+        if (r != TTN_OK) return r;
+        off += cnt;
+      }
+    }
+  } else if (mode != 3) {
+    return api_fail(ctx, TTN_E_ARG, "unknown solve mode");
+  }
+  if (next >= 0) {
+    r = ttn_block_move_centre(ctx, sw->y, u, next);
+    if (r != TTN_OK) return r;
+    r = update_envs_across(sw, u, next);
+    if (r != TTN_OK) return r;
+  }
+  return TTN_OK;
+}
+
+}  // extern "C"

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libttn.so")
 
 F64, F32, BF16 = 0, 1, 2
 HEFF_APPLY, HEFF_NO_SHIFT, HEFF_DIAG, HEFF_ACCUM = 0, 1, 2, 4
-SOLVE_MINRES, SOLVE_DIAG, SOLVE_FIT = 0, 1, 2
+SOLVE_MINRES, SOLVE_DIAG, SOLVE_FIT, SOLVE_SKIP = 0, 1, 2, 3
 
 _lib = None
 
@@ -334,6 +334,72 @@ def sop_build(tree: Tree, node_mode: Sequence[int], omega, dims, monomials, coef
         return W, bonds
     finally:
         lib().ttn_sop_destroy(h)
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("maxiter", C.c_int32), ("rtol", C.c_double)]
+
+
+class Sweep:
+    """A sweep of local solves over a target block (see ttn_sweep_create).
+
+    sources: list of (op or None, Block, targets, sources, coef device tensor or None)."""
+
+    def __init__(self, ctx: Context, tree: Tree, op: Optional[TTNO], target: Block, sources, shift=None,
+                 compute: int = F64):
+        self.ctx, self.tree, self.target = ctx, tree, target
+        self._keep = [op, target, sources, shift]
+        n = len(sources)
+        ops = (C.c_void_p * max(1, n))(*[(s[0].h.value if s[0] is not None else None) for s in sources])
+        blks = (C.c_void_p * max(1, n))(*[s[1].h.value for s in sources])
+        nt = _i32([len(s[2]) for s in sources] or [0])
+        tg = [_i32(s[2]) for s in sources]
+        sr = [_i32(s[3]) for s in sources]
+        self._arrs = (tg, sr)
+        tgp = (C.c_void_p * max(1, n))(*[C.cast(a, C.c_void_p).value for a in tg])
+        srp = (C.c_void_p * max(1, n))(*[C.cast(a, C.c_void_p).value for a in sr])
+        cfp = (C.c_void_p * max(1, n))(*[(s[4].data_ptr() if s[4] is not None else None) for s in sources])
+        self.h = C.c_void_p()
+        _check(lib().ttn_sweep_create(ctx.h, tree.h, None if op is None else op.h, target.h, n, ops, blks, nt, tgp,
+                                      srp, cfp, _ptr(shift), compute, C.byref(self.h)), ctx)
+
+    def init(self, centre: int):
+        _check(lib().ttn_sweep_init(self.h, centre), self.ctx)
+
+    def step(self, node: int, nxt: int, mode: int, maxiter: int = 0, rtol: float = 0.0, iters=None, resid=None):
+        o = SolveOpts(mode, maxiter, rtol)
+        _check(lib().sweep_step(self.ctx.h, self.h, node, nxt, C.byref(o), _ptr(iters), _ptr(resid)), self.ctx)
+
+    def __del__(self):
+        try:
+            lib().ttn_sweep_destroy(self.h)
+        except Exception:
+            pass
+
+
+def euler_tour(tree: Tree):
+    out = []
+
+    def rec(u):
+        out.append(u)
+        for c in tree.children[u]:
+            rec(c)
+            out.append(u)
+
+    rec(tree.root)
+    return out
+
+
+def run_sweep(sw: Sweep, tree: Tree, mode: int, maxiter: int = 0, rtol: float = 0.0, iters=None, resid=None):
+    """One sweep: a depth-first Euler tour from the root; a node is solved on
+    its first visit, later visits only move the orthogonality centre."""
+    tour = euler_tour(tree)
+    seen = set()
+    for t, u in enumerate(tour):
+        nxt = tour[t + 1] if t + 1 < len(tour) else -1
+        m = mode if u not in seen else SOLVE_SKIP
+        seen.add(u)
+        sw.step(u, nxt, m, maxiter, rtol, iters, resid)
 
 
 def profile(ctx: Context, on: bool):

@@ -1,0 +1,120 @@
+"""GPU Rayleigh-Ritz, QR gauge move and node norms against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import linalg as olin
+from oracle import ttn as ottn
+from tests.gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2512_15875_amd import ttn
+    ttn.lib()
+    return ttn
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    return api.Context(0, workspace_bytes=1 << 30)
+
+
+@pytest.mark.parametrize("m,nev", [(6, 3), (30, 10), (97, 20), (252, 84)])
+def test_rayleigh_ritz_cholesky_matches_oracle(api, ctx, m, nev):
+    rng = np.random.default_rng(m)
+    batch = 3
+    ld = m + 3
+    H = np.zeros((batch, ld, ld))
+    S = np.zeros((batch, ld, ld))
+    ms = [m, max(1, m - 2), m]
+    for b in range(batch):
+        mm = ms[b]
+        A = rng.normal(size=(mm, mm)) * 100
+        B = rng.normal(size=(mm, mm))
+        H[b, :mm, :mm] = A + A.T
+        S[b, :mm, :mm] = B @ B.T / mm + np.eye(mm)
+    ev, V, rank = api.rayleigh_ritz(ctx, to_dev(H), to_dev(S), ms, nev)
+    ctx.sync()
+    ev, V, rank = ev.cpu().numpy(), V.cpu().numpy(), rank.cpu().numpy()
+    for b in range(batch):
+        mm = ms[b]
+        ne = min(nev, mm)
+        lam, Vr, rk = olin.rayleigh_ritz(H[b, :mm, :mm], S[b, :mm, :mm], ne)
+        assert rank[b] == rk == mm
+        np.testing.assert_allclose(ev[b, :ne], lam, rtol=0, atol=1e-10 * np.abs(lam).max())
+        # eigenvectors: unique up to sign for simple eigenvalues; same sign convention
+        np.testing.assert_allclose(V[b, :mm, :ne], Vr, atol=1e-8)
+        G = V[b, :mm, :ne].T @ S[b, :mm, :mm] @ V[b, :mm, :ne]
+        np.testing.assert_allclose(G, np.eye(ne), atol=1e-10)
+
+
+def test_rayleigh_ritz_svqb_rank_deficient(api, ctx):
+    rng = np.random.default_rng(3)
+    n, m = 40, 12
+    Hbig = rng.normal(size=(n, n))
+    Hbig = Hbig + Hbig.T
+    X = rng.normal(size=(n, m))
+    X[:, 11] = X[:, 2]
+    H, S = X.T @ Hbig @ X, X.T @ X
+    ev, V, rank = api.rayleigh_ritz(ctx, to_dev(H[None]), to_dev(S[None]), [m], 5)
+    ctx.sync()
+    lam, _, rk = olin.rayleigh_ritz(H, S, 5)
+    assert int(rank.cpu()[0]) == rk == 11
+    np.testing.assert_allclose(ev.cpu().numpy()[0], lam, atol=1e-8)
+
+
+def test_rayleigh_ritz_not_pd_reports_error(api, ctx):
+    H = np.eye(4)[None]
+    S = np.diag([1.0, 1.0, 0.0, 1.0])[None]
+    api.rayleigh_ritz(ctx, to_dev(H), to_dev(S), [4], 2, allow_svqb=False)
+    with pytest.raises(api.TTNError):
+        ctx.sync()
+
+
+@pytest.mark.parametrize("dt", [0, 1])
+def test_qr_move_matches_oracle(api, ctx, dt):
+    m = wl.quartic_force_field(8, 21, 20, 30)
+    tree = wl.fork_tree(m.dims, 4, 1)
+    bonds = wl.bond_dims(tree, 7)
+    k = 3
+    blk_np = wl.random_block(tree, bonds, k, 44)
+    gt = api.Tree(tree.parent, tree.phys)
+    tdt = torch.float64 if dt == 0 else torch.float32
+    blk = api.Block(ctx, gt, k, [max(1, b) for b in bonds], dt)
+    for u in range(tree.n):
+        blk.t[u].copy_(to_dev(np.stack([blk_np[j][u] for j in range(k)]), tdt))
+    moves = [(5, 4), (4, 0), (0, 1), (1, 2), (2, 3), (3, 10), (10, 11)]
+    for (u, v) in moves:
+        api.block_move_centre(ctx, blk, u, v)
+        for j in range(k):
+            ottn.move_centre(tree, blk_np[j], u, v)
+    ctx.sync()
+    tol = 1e-11 if dt == 0 else 2e-4
+    for u in range(tree.n):
+        got = blk.t[u].double().cpu().numpy()
+        for j in range(k):
+            ref = blk_np[j][u]
+            assert np.linalg.norm(got[j] - ref) <= tol * max(1.0, np.linalg.norm(ref)), (u, j)
+
+
+def test_node_norms_and_scale(api, ctx):
+    tree = wl.binary_tree([3, 4, 5])
+    bonds = wl.bond_dims(tree, 4)
+    gt = api.Tree(tree.parent, tree.phys)
+    blk = api.Block(ctx, gt, 4, [max(1, b) for b in bonds], api.F64)
+    for u in range(tree.n):
+        blk.t[u].normal_()
+    out = torch.zeros(4, dtype=torch.float64, device="cuda")
+    api.block_node_norms2(ctx, blk, 0, out)
+    ref = (blk.t[0].reshape(4, -1) ** 2).sum(1)
+    ctx.sync()
+    np.testing.assert_allclose(out.cpu().numpy(), ref.cpu().numpy(), rtol=1e-13)
+    sc = torch.tensor([1.0, 2.0, 0.5, -1.0], dtype=torch.float64, device="cuda")
+    before = blk.t[0].clone()
+    api.block_scale_node(ctx, blk, 0, sc)
+    ctx.sync()
+    np.testing.assert_allclose(blk.t[0].cpu().numpy(), (before * sc.view(4, 1, 1, 1)).cpu().numpy(), rtol=1e-15)

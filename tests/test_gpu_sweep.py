@@ -1,0 +1,117 @@
+"""GPU sweeps (ALS with batched MINRES, variational fitting) against the
+oracle's ALS and fitting on identical inputs (same TTNO tensors, same initial
+states, fixed iteration counts)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import solvers as osol
+from oracle import ttn as ottn
+from oracle import ttno as ottno
+from tests.gpu_util import rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2512_15875_amd import ttn
+    ttn.lib()
+    return ttn
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    return api.Context(0, workspace_bytes=1 << 30)
+
+
+def _setup(api, ctx, k=3, D=6, seed=5, tree_kind="fork"):
+    m = wl.quartic_force_field(8, 21, 20, 30)
+    tree = wl.fork_tree(m.dims, 4, 1) if tree_kind == "fork" else wl.mps_tree(m.dims, 3)
+    W = ottno.build_ttno(tree, m)
+    M = ottno.ttno_bonds(tree, W)
+    bonds = wl.bond_dims(tree, D)
+    gt = api.Tree(tree.parent, tree.phys)
+    op = api.TTNO(ctx, gt, [to_dev(w) for w in W], [max(1, x) for x in M], api.F64)
+    phi = wl.random_block(tree, bonds, k, seed)
+    return m, tree, W, M, bonds, gt, op, phi
+
+
+def _upload(api, ctx, gt, tree, bonds, states, k):
+    blk = api.Block(ctx, gt, k, [max(1, b) for b in bonds], api.F64)
+    for u in range(tree.n):
+        blk.t[u].copy_(to_dev(np.stack([states[j][u] for j in range(k)])))
+    return blk
+
+
+@pytest.mark.parametrize("tree_kind", ["fork", "mps"])
+def test_als_sweep_matches_oracle(api, ctx, tree_kind):
+    k = 3
+    m, tree, W, M, bonds, gt, op, phi = _setup(api, ctx, k=k, tree_kind=tree_kind)
+    y0 = [ottn.canonicalize(tree, p, tree.root) for p in phi]
+    shifts = [-200.0, 50.0, 900.0]
+    Y = _upload(api, ctx, gt, tree, bonds, y0, k)
+    P = _upload(api, ctx, gt, tree, bonds, phi, k)
+    sh = to_dev(np.array(shifts))
+    sw = api.Sweep(ctx, gt, op, Y, [(None, P, list(range(k)), list(range(k)), None)], shift=sh, compute=api.F64)
+    sw.init(tree.root)
+    iters = torch.zeros(k, dtype=torch.int32, device="cuda")
+    api.run_sweep(sw, gt, api.SOLVE_MINRES, maxiter=6, rtol=0.0, iters=iters)
+    ctx.sync()
+    for j in range(k):
+        ref = osol.als_solve(tree, W, shifts[j], phi[j], phi[j], sweeps=1, maxiter=6, rtol=0.0)
+        for u in range(tree.n):
+            assert rel_err(Y.t[u][j].cpu().numpy(), ref[u]) < 1e-8, (j, u)
+    assert int(iters.max()) == 6
+
+
+def test_als_sweep_converges_with_rtol(api, ctx):
+    k = 2
+    m, tree, W, M, bonds, gt, op, phi = _setup(api, ctx, k=k)
+    y0 = [ottn.canonicalize(tree, p, tree.root) for p in phi]
+    shifts = [-500.0, -300.0]
+    Y = _upload(api, ctx, gt, tree, bonds, y0, k)
+    P = _upload(api, ctx, gt, tree, bonds, phi, k)
+    sw = api.Sweep(ctx, gt, op, Y, [(None, P, [0, 1], [0, 1], None)], shift=to_dev(np.array(shifts)),
+                   compute=api.F64)
+    sw.init(tree.root)
+    iters = torch.zeros(k, dtype=torch.int32, device="cuda")
+    resid = torch.zeros(k, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        api.run_sweep(sw, gt, api.SOLVE_MINRES, maxiter=400, rtol=1e-10, iters=iters, resid=resid)
+    ctx.sync()
+    for j in range(k):
+        ref = osol.als_solve(tree, W, shifts[j], phi[j], phi[j], sweeps=2, maxiter=400, rtol=1e-10)
+        got = [Y.t[u][j].cpu().numpy() for u in range(tree.n)]
+        # compare the represented vectors through overlaps (gauge-free)
+        ov = ottn.expectation(tree, got, None, ref)
+        n1 = ottn.expectation(tree, got, None, got)
+        n2 = ottn.expectation(tree, ref, None, ref)
+        assert abs(ov / np.sqrt(n1 * n2) - 1.0) < 1e-9
+        assert abs(n1 / n2 - 1.0) < 1e-7
+
+
+def test_fit_sweep_matches_oracle(api, ctx):
+    k = 2
+    m, tree, W, M, bonds, gt, op, phi = _setup(api, ctx, k=k, seed=8)
+    src = wl.random_block(tree, bonds, 3, 9)
+    init = [ottn.canonicalize(tree, src[j], tree.root) for j in range(k)]
+    Y = _upload(api, ctx, gt, tree, bonds, init, k)
+    S = _upload(api, ctx, gt, tree, bonds, src, 3)
+    # target 0: 0.5 H s0 - 2 s1 + s2 ; target 1: H s2 + 0.25 s0
+    t1, s1, c1 = [0, 1], [0, 2], [0.5, 1.0]
+    t2, s2, c2 = [0, 0, 1], [1, 2, 0], [-2.0, 1.0, 0.25]
+    sw = api.Sweep(ctx, gt, None, Y, [(op, S, t1, s1, to_dev(np.array(c1))), (None, S, t2, s2, to_dev(np.array(c2)))],
+                   compute=api.F64)
+    sw.init(tree.root)
+    for _ in range(2):
+        api.run_sweep(sw, gt, api.SOLVE_FIT)
+    ctx.sync()
+    refs = [
+        osol.fit(tree, [(0.5, W, src[0]), (-2.0, None, src[1]), (1.0, None, src[2])], src[0], sweeps=2),
+        osol.fit(tree, [(1.0, W, src[2]), (0.25, None, src[0])], src[1], sweeps=2),
+    ]
+    for j in range(k):
+        for u in range(tree.n):
+            assert rel_err(Y.t[u][j].cpu().numpy(), refs[j][u]) < 1e-9, (j, u)
