@@ -236,6 +236,19 @@ ttn_status ttn_block_scale_node(ttn_ctx* ctx, ttn_block* b, int32_t u, const dou
 /* Squared norms of the k tensors at node u: out device double[k]. */
 ttn_status ttn_block_node_norms2(ttn_ctx* ctx, const ttn_block* b, int32_t u, double* out);
 
+/* Scale each of the k tensors at node u to unit norm (the state's norm when u
+ * is its orthogonality centre); norms_out: device double[k] of the norms
+ * before scaling (may be NULL). */
+ttn_status ttn_block_normalize_node(ttn_ctx* ctx, ttn_block* b, int32_t u, double* norms_out);
+
+/* Symmetric scatter used to assemble Gram matrices from pair values:
+ * out[idx_a[i]] = out[idx_b[i]] = vals[i] (all device arrays, linear indices). */
+ttn_status ttn_scatter_sym(ttn_ctx* ctx, int32_t n, const int32_t* idx_a, const int32_t* idx_b, const double* vals,
+                           double* out);
+
+/* y = alpha * x for device double vectors of length n. */
+ttn_status ttn_vec_scale(ttn_ctx* ctx, int32_t n, const double* x, double alpha, double* y);
+
 /* ------------------------------------------------------------ operator compiler (host) */
 
 /* Sum-of-products -> TTNO in FP64 on the host (Sec. II.A.3, Eq. sum_of_tp):

@@ -18,6 +18,9 @@ hipError_t launch_absorb(int ctype, const void* X, int64_t size, const int32_t* 
                          const double* R, void* Y, int nz, hipStream_t s);
 hipError_t launch_norms2(int ctype, const void* X, int64_t n, int nz, double* out, hipStream_t s);
 hipError_t launch_scale(int ctype, void* X, int64_t n, int nz, const double* sc, hipStream_t s);
+hipError_t launch_scatter2(int n, const int32_t* ia, const int32_t* ib, const double* vals, double* out, hipStream_t s);
+hipError_t launch_vscale(int n, const double* x, double a, double* y, hipStream_t s);
+hipError_t launch_normalize(int ctype, void* X, int64_t n, int nz, double* norms, hipStream_t s);
 
 ttn_status api_fail(ttn_ctx* ctx, ttn_status code, const std::string& msg);
 
@@ -131,6 +134,28 @@ ttn_status ttn_block_scale_node(ttn_ctx* ctx, ttn_block* b, int32_t u, const dou
 ttn_status ttn_block_node_norms2(ttn_ctx* ctx, const ttn_block* b, int32_t u, double* out) {
   if (!ctx || !b || !out || u < 0 || u >= b->t->n) return api_fail(ctx, TTN_E_ARG, "bad arguments");
   hipError_t e = launch_norms2(b->dt == TTN_F64 ? 0 : 1, b->ptr[u], b->size[u], b->k, out, ctx->stream);
+  if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+  return TTN_OK;
+}
+
+ttn_status ttn_block_normalize_node(ttn_ctx* ctx, ttn_block* b, int32_t u, double* norms_out) {
+  if (!ctx || !b || u < 0 || u >= b->t->n) return api_fail(ctx, TTN_E_ARG, "bad arguments");
+  hipError_t e = launch_normalize(b->dt == TTN_F64 ? 0 : 1, b->ptr[u], b->size[u], b->k, norms_out, ctx->stream);
+  if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+  return TTN_OK;
+}
+
+ttn_status ttn_scatter_sym(ttn_ctx* ctx, int32_t n, const int32_t* idx_a, const int32_t* idx_b, const double* vals,
+                           double* out) {
+  if (!ctx || n < 0 || (n > 0 && (!idx_a || !idx_b || !vals || !out))) return api_fail(ctx, TTN_E_ARG, "bad arguments");
+  hipError_t e = launch_scatter2(n, idx_a, idx_b, vals, out, ctx->stream);
+  if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+  return TTN_OK;
+}
+
+ttn_status ttn_vec_scale(ttn_ctx* ctx, int32_t n, const double* x, double alpha, double* y) {
+  if (!ctx || n < 0 || (n > 0 && (!x || !y))) return api_fail(ctx, TTN_E_ARG, "bad arguments");
+  hipError_t e = launch_vscale(n, x, alpha, y, ctx->stream);
   if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
   return TTN_OK;
 }

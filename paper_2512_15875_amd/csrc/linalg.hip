@@ -491,3 +491,53 @@ hipError_t launch_scale(int ctype, void* X, int64_t n, int nz, const double* sc,
 }
 
 }  // namespace ttn
+
+namespace ttn {
+
+// out[ia[i]] = out[ib[i]] = vals[i]
+__global__ void scatter2_kernel(int n, const int32_t* ia, const int32_t* ib, const double* vals, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[ia[i]] = vals[i];
+  out[ib[i]] = vals[i];
+}
+
+__global__ void vscale_kernel(int n, const double* x, double a, double* y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i];
+}
+
+// per state: norm of the node tensor, then scale it to unit norm
+template <typename T>
+__global__ __launch_bounds__(256) void normalize_kernel(T* X, int64_t n, double* norms) {
+  __shared__ double red[256];
+  const int z = blockIdx.x;
+  T* x = X + (int64_t)z * n;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += (double)x[i] * (double)x[i];
+  s = block_sum(s, red);
+  const double nr = sqrt(s);
+  const double inv = nr > 0 ? 1.0 / nr : 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) x[i] = (T)((double)x[i] * inv);
+  if (threadIdx.x == 0 && norms) norms[z] = nr;
+}
+
+hipError_t launch_scatter2(int n, const int32_t* ia, const int32_t* ib, const double* vals, double* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter2_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, ia, ib, vals, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_vscale(int n, const double* x, double a, double* y, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vscale_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, x, a, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(int ctype, void* X, int64_t n, int nz, double* norms, hipStream_t s) {
+  if (ctype == 0) hipLaunchKernelGGL(normalize_kernel<double>, dim3(nz), dim3(256), 0, s, (double*)X, n, norms);
+  else hipLaunchKernelGGL(normalize_kernel<float>, dim3(nz), dim3(256), 0, s, (float*)X, n, norms);
+  return hipGetLastError();
+}
+
+}  // namespace ttn

@@ -1,0 +1,371 @@
+"""Block LOBPCG and block inverse iteration on the GPU path.
+
+Host-side control only: every tensor operation (environment updates, H_eff
+products, MINRES, QR gauge moves, fitting sums, Gram closures, Rayleigh-Ritz,
+normalisation) runs in libttn's HIP kernels through the C ABI.  The host
+reads back scalars (Rayleigh quotients, residual norms) to decide clusters and
+stopping; PyTorch provides device buffers and plain copies between them.
+
+Algorithms: Alg. lobpcg_block with the three-term recurrence (Eq. lobpcg
+update) and Alg. block_inverse_iteration, with the readings listed in
+the design doc (subspace {x, w} on the first iteration, x_j = sum over all 3n
+basis states, clusters fixed after LOBPCG, a final global Rayleigh-Ritz).
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from . import ttn
+
+
+@dataclasses.dataclass
+class LobpcgOpts:
+    n_iter: int = 5
+    shift: Optional[float] = None     # preconditioner shift; None -> min RQ(x0) - 837 cm^-1
+    als_sweeps: int = 2
+    minres_maxiter: int = 10
+    minres_rtol: float = 1e-6
+    fit_sweeps: int = 2
+    drop_tol: float = 1e-12
+    resid_tol: Optional[float] = None
+
+
+@dataclasses.dataclass
+class IIOpts:
+    n_iter: int = 5
+    sweeps: int = 1
+    minres_maxiter: int = 10000
+    minres_rtol: float = 1e-10
+    fit_sweeps: int = 2
+    gap: float = 5.0
+    drop_tol: float = 1e-12
+    dlam_tol: Optional[float] = None
+
+
+def post_order_edges(tree: ttn.Tree):
+    """Edges u -> parent(u) with every child before its parent."""
+    out = []
+
+    def rec(u):
+        for c in tree.children[u]:
+            rec(c)
+        if tree.parent[u] >= 0:
+            out.append((u, tree.parent[u]))
+
+    rec(tree.root)
+    return out
+
+
+class TTNEigensolver:
+    """GPU block eigensolver for one Hamiltonian on one tree.
+
+    tree: workloads.Tree; model: workloads.SOPModel; the initial block comes
+    as [state][node] host arrays (seeded input, not yet canonical).
+    precision: "fp64" (plain) or "fp32" / "bf16" (contractions in FP32 / BF16
+    matrix cores, FP32 storage; Rayleigh-Ritz always FP64).
+    """
+
+    def __init__(self, ctx: ttn.Context, tree, model, D: int, k: int, precision: str = "fp64",
+                 workspace_pairs: int = 4096):
+        import workloads as wl
+        self.ctx, self.k = ctx, k
+        self.wtree = tree
+        self.gt = ttn.Tree(tree.parent, tree.phys)
+        W, M = ttn.sop_build(self.gt, tree.mode, model.omega, model.dims, model.monomials, model.coefs)
+        self.M = [max(1, m) for m in M]
+        self.sdt = ttn.F64 if precision == "fp64" else ttn.F32
+        self.compute = {"fp64": ttn.F64, "fp32": ttn.F32, "bf16": ttn.BF16}[precision]
+        self.tdt = ttn.torch_dtype(self.sdt)
+        self.Wd = [torch.from_numpy(np.ascontiguousarray(w)).to(device="cuda", dtype=self.tdt) for w in W]
+        self.op = ttn.TTNO(ctx, self.gt, self.Wd, self.M, self.sdt)
+        self.bonds = [max(1, b) for b in wl.bond_dims(tree, D)]
+        self.zpe = model.zpe_harmonic
+        n = tree.n
+        self.root = tree.root
+        self.B = ttn.Block(ctx, self.gt, 3 * k, self.bonds, self.sdt)     # basis [x | w | p]
+        self.R = ttn.Block(ctx, self.gt, k, self.bonds, self.sdt)         # residuals
+        self.Wp = ttn.Block(ctx, self.gt, k, self.bonds, self.sdt)        # preconditioned residuals
+        self.XN = ttn.Block(ctx, self.gt, k, self.bonds, self.sdt)        # recombined x
+        self.PN = ttn.Block(ctx, self.gt, k, self.bonds, self.sdt)        # recombined p
+        self.Y = ttn.Block(ctx, self.gt, k, self.bonds, self.sdt)         # inverse-iteration target
+        self.up_edges = post_order_edges(self.gt)
+        self.pair_cap = workspace_pairs
+        dev = "cuda"
+        up_slots = [2 * u for (u, _) in self.up_edges]
+        self.genv_H = ttn.Envs(ctx, self.gt, self.pair_cap, self.bonds, self.M, self.bonds, self.sdt, edges=up_slots)
+        self.genv_I = ttn.Envs(ctx, self.gt, self.pair_cap, self.bonds, None, self.bonds, self.sdt, edges=up_slots)
+        self.norms = torch.zeros(3 * k, dtype=torch.float64, device=dev)
+        # residual fit: r_j = H x_j - lambda_j x_j
+        self.lam_d = torch.zeros(k, dtype=torch.float64, device=dev)
+        self.neglam_d = torch.zeros(k, dtype=torch.float64, device=dev)
+        ones = torch.ones(k, dtype=torch.float64, device=dev)
+        self._ones = ones
+        idx = list(range(k))
+        self.sw_res = ttn.Sweep(ctx, self.gt, None, self.R,
+                                [(self.op, self.B, idx, idx, ones), (None, self.B, idx, idx, self.neglam_d)],
+                                compute=self.compute)
+        self.shift_d = torch.zeros(k, dtype=torch.float64, device=dev)
+        self.sw_pre = ttn.Sweep(ctx, self.gt, self.op, self.Wp, [(None, self.R, idx, idx, None)], shift=self.shift_d,
+                                compute=self.compute)
+        # recombination fits: x_j = sum_l V[l, j] B_l ; p_j = sum_{l >= k} V[l, j] B_l
+        m3 = 3 * k
+        self.cx_t = [j for j in range(k) for l in range(m3)]
+        self.cx_s = [l for j in range(k) for l in range(m3)]
+        self.cp_t = [j for j in range(k) for l in range(k, m3)]
+        self.cp_s = [l for j in range(k) for l in range(k, m3)]
+        self.cx_d = torch.zeros(len(self.cx_t), dtype=torch.float64, device=dev)
+        self.cp_d = torch.zeros(len(self.cp_t), dtype=torch.float64, device=dev)
+        self.sw_x = ttn.Sweep(ctx, self.gt, None, self.XN, [(None, self.B, self.cx_t, self.cx_s, self.cx_d)],
+                              compute=self.compute)
+        self.sw_p = ttn.Sweep(ctx, self.gt, None, self.PN, [(None, self.B, self.cp_t, self.cp_s, self.cp_d)],
+                              compute=self.compute)
+        self.ix_gather = torch.tensor([l * k + j for j, l in zip(self.cx_t, self.cx_s)], device=dev)
+        self.ip_gather = torch.tensor([l * k + j for j, l in zip(self.cp_t, self.cp_s)], device=dev)
+        self.history: List[dict] = []
+        self._sw_ii = None
+
+    # ------------------------------------------------------------ block plumbing
+
+    def _copy_rows(self, dst: ttn.Block, d0: int, src: ttn.Block, s0: int, cnt: int):
+        for u in range(self.gt.n):
+            dst.t[u][d0:d0 + cnt].copy_(src.t[u][s0:s0 + cnt])
+
+    def load_block(self, states):
+        """Upload host states into rows [0, k) of the basis, canonicalise at
+        the root (QR moves on the device) and normalise."""
+        k = self.k
+        for u in range(self.gt.n):
+            arr = np.stack([states[j][u] for j in range(k)])
+            self.B.t[u][:k].copy_(torch.from_numpy(arr).to(self.tdt))
+            self.B.t[u][k:].zero_()
+        self._canonicalize(self.B)
+        ttn.block_normalize_node(self.ctx, self.B, self.root, self.norms)
+
+    def _canonicalize(self, blk: ttn.Block):
+        for (u, p) in self.up_edges:
+            ttn.block_move_centre(self.ctx, blk, u, p)
+
+    # ------------------------------------------------------------ Gram / Rayleigh quotients
+
+    def gram(self, blk: ttn.Block, pairs_a: List[int], pairs_b: List[int], with_H=True, with_S=True):
+        """Closures <a|H|b> and <a|b> for the listed pairs (device double arrays)."""
+        n = len(pairs_a)
+        outH = torch.zeros(n, dtype=torch.float64, device="cuda")
+        outS = torch.zeros(n, dtype=torch.float64, device="cuda")
+        for c0 in range(0, n, self.pair_cap):
+            c1 = min(n, c0 + self.pair_cap)
+            pa = torch.tensor(pairs_a[c0:c1], dtype=torch.int32, device="cuda")
+            pb = torch.tensor(pairs_b[c0:c1], dtype=torch.int32, device="cuda")
+            for (op, env, out) in ((self.op, self.genv_H, outH), (None, self.genv_I, outS)):
+                if (op is not None and not with_H) or (op is None and not with_S):
+                    continue
+                for (u, p) in self.up_edges:
+                    ttn.ttno_env_update(self.ctx, self.gt, op, blk, blk, pa, pb, u, p, env, self.compute)
+                ttn.ttno_env_close(self.ctx, self.gt, op, blk, blk, pa, pb, self.root, env, out[c0:c1],
+                                   self.compute)
+        return outH, outS
+
+    def rayleigh_quotients(self, blk: ttn.Block, rows: List[int]) -> torch.Tensor:
+        H, _ = self.gram(blk, rows, rows, with_S=False)
+        return H  # states are normalised
+
+    def _assemble(self, vals: torch.Tensor, ia: List[int], ib: List[int], size: int):
+        out = torch.zeros(size, dtype=torch.float64, device="cuda")
+        ta = torch.tensor(ia, dtype=torch.int32, device="cuda")
+        tb = torch.tensor(ib, dtype=torch.int32, device="cuda")
+        ttn.scatter_sym(self.ctx, ta, tb, vals, out)
+        return out
+
+    # ------------------------------------------------------------ LOBPCG
+
+    def lobpcg(self, opts: LobpcgOpts, exact=None, log=None):
+        ctx, k, root = self.ctx, self.k, self.root
+        t_start = time.perf_counter()
+        lam = self.rayleigh_quotients(self.B, list(range(k)))
+        self.lam_d.copy_(lam)
+        if opts.shift is None:
+            s = float(lam.min().item()) - 837.0
+        else:
+            s = opts.shift
+        self.shift_d.fill_(s)
+        have_p = False
+        for it in range(opts.n_iter):
+            # residual r_j = H x_j - lambda_j x_j by fitting
+            ttn.vec_scale(ctx, self.lam_d, -1.0, self.neglam_d)
+            self._copy_rows(self.R, 0, self.B, 0, k)
+            self.sw_res.init(root)
+            for _ in range(opts.fit_sweeps):
+                ttn.run_sweep(self.sw_res, self.gt, ttn.SOLVE_FIT)
+            rn = torch.zeros(k, dtype=torch.float64, device="cuda")
+            ttn.block_node_norms2(ctx, self.R, root, rn)
+            # preconditioned residual: (H - s) w = r by ALS
+            self._copy_rows(self.Wp, 0, self.R, 0, k)
+            self.sw_pre.init(root)
+            for _ in range(opts.als_sweeps):
+                ttn.run_sweep(self.sw_pre, self.gt, ttn.SOLVE_MINRES, opts.minres_maxiter, opts.minres_rtol)
+            ttn.block_normalize_node(ctx, self.Wp, root)
+            self._copy_rows(self.B, k, self.Wp, 0, k)
+            rnorm = torch.sqrt(rn).cpu().numpy()
+            lam_h = self.lam_d.cpu().numpy()
+            rec = {"iter": it, "t": time.perf_counter() - t_start, "lam": lam_h + self.zpe, "resid": rnorm}
+            self.history.append(rec)
+            if log:
+                log(rec)
+            if opts.resid_tol is not None and rnorm.max() <= opts.resid_tol:
+                break
+            m = 3 * k if have_p else 2 * k
+            ia, ib = [], []
+            for a in range(m):
+                for b in range(a, m):
+                    ia.append(a)
+                    ib.append(b)
+            hv, sv = self.gram(self.B, ia, ib)
+            ld = 3 * k
+            Hm = self._assemble(hv, [a * ld + b for a, b in zip(ia, ib)], [b * ld + a for a, b in zip(ia, ib)], ld * ld)
+            Sm = self._assemble(sv, [a * ld + b for a, b in zip(ia, ib)], [b * ld + a for a, b in zip(ia, ib)], ld * ld)
+            if m < ld:  # unit diagonal in the unused block keeps the padding inert
+                pass
+            ev, V, rank = ttn.rayleigh_ritz(ctx, Hm.view(1, ld, ld), Sm.view(1, ld, ld), [m], k, opts.drop_tol)
+            Vf = V[0].reshape(-1)  # [ld][k] row-major: V[l, j] at l*k + j
+            self.cx_d.copy_(Vf[self.ix_gather])
+            self.cp_d.copy_(Vf[self.ip_gather])
+            # p_j = sum_{l >= k} V[l, j] s_l ; x_j = sum_l V[l, j] s_l
+            self._copy_rows(self.PN, 0, self.B, k, k)
+            self.sw_p.init(root)
+            for _ in range(opts.fit_sweeps):
+                ttn.run_sweep(self.sw_p, self.gt, ttn.SOLVE_FIT)
+            self._copy_rows(self.XN, 0, self.B, 0, k)
+            self.sw_x.init(root)
+            for _ in range(opts.fit_sweeps):
+                ttn.run_sweep(self.sw_x, self.gt, ttn.SOLVE_FIT)
+            ttn.block_normalize_node(ctx, self.PN, root)
+            ttn.block_normalize_node(ctx, self.XN, root)
+            self._copy_rows(self.B, 0, self.XN, 0, k)
+            self._copy_rows(self.B, 2 * k, self.PN, 0, k)
+            have_p = True
+            lam = self.rayleigh_quotients(self.B, list(range(k)))
+            self.lam_d.copy_(lam)
+        lam_h = self.lam_d.cpu().numpy()
+        return lam_h + self.zpe
+
+    # ------------------------------------------------------------ inverse iteration
+
+    @staticmethod
+    def clusters_of(lam: np.ndarray, gap: float):
+        order = list(np.argsort(lam))
+        out = [[order[0]]]
+        for a, b in zip(order[:-1], order[1:]):
+            if lam[b] - lam[a] >= gap:
+                out.append([b])
+            else:
+                out[-1].append(b)
+        return out
+
+    def inverse_iteration(self, opts: IIOpts, log=None):
+        ctx, k, root = self.ctx, self.k, self.root
+        t_start = time.perf_counter()
+        lam = self.lam_d.cpu().numpy().copy()
+        cl = self.clusters_of(lam, opts.gap)
+        idx = list(range(k))
+        if self._sw_ii is None:
+            # target Y, source x (rows [0, k) of the basis)
+            self._sw_ii = ttn.Sweep(ctx, self.gt, self.op, self.Y, [(None, self.B, idx, idx, None)],
+                                    shift=self.shift_d, compute=self.compute)
+            # recombination inside clusters: x_j = sum_{l in c(j)} V_c[l, j] x_l
+            self.ci_t = [j for c in cl for j in c for l in c]
+            self.ci_s = [l for c in cl for j in c for l in c]
+            self.ci_d = torch.zeros(len(self.ci_t), dtype=torch.float64, device="cuda")
+            self._sw_rec = ttn.Sweep(ctx, self.gt, None, self.XN, [(None, self.B, self.ci_t, self.ci_s, self.ci_d)],
+                                     compute=self.compute)
+            self._clusters = cl
+        cl = self._clusters
+        big = [c for c in cl if len(c) > 1]
+        for it in range(opts.n_iter):
+            old = lam.copy()
+            shifts = np.zeros(k)
+            for c in cl:
+                shifts[c] = float(np.mean(lam[c]))
+            self.shift_d.copy_(torch.from_numpy(shifts))
+            self._copy_rows(self.Y, 0, self.B, 0, k)
+            self._sw_ii.init(root)
+            for _ in range(opts.sweeps):
+                ttn.run_sweep(self._sw_ii, self.gt, ttn.SOLVE_MINRES, opts.minres_maxiter, opts.minres_rtol)
+            ttn.block_normalize_node(ctx, self.Y, root)
+            self._copy_rows(self.B, 0, self.Y, 0, k)
+            if big:
+                self._cluster_rr(big, opts)
+            lam = self.rayleigh_quotients(self.B, idx).cpu().numpy()
+            self.lam_d.copy_(torch.from_numpy(lam))
+            rec = {"iter": it, "t": time.perf_counter() - t_start, "lam": lam + self.zpe}
+            self.history.append(rec)
+            if log:
+                log(rec)
+            if opts.dlam_tol is not None and np.max(np.abs(lam - old)) < opts.dlam_tol:
+                break
+        return self.final_rr(opts.drop_tol)
+
+    def _cluster_rr(self, big, opts: IIOpts):
+        ctx, k, root = self.ctx, self.k, self.root
+        ld = max(len(c) for c in big)
+        ia, ib, la, lb = [], [], [], []
+        for ci, c in enumerate(big):
+            for a in range(len(c)):
+                for b in range(a, len(c)):
+                    ia.append(c[a])
+                    ib.append(c[b])
+                    la.append(ci * ld * ld + a * ld + b)
+                    lb.append(ci * ld * ld + b * ld + a)
+        hv, sv = self.gram(self.B, ia, ib)
+        Hm = self._assemble(hv, la, lb, len(big) * ld * ld)
+        Sm = self._assemble(sv, la, lb, len(big) * ld * ld)
+        ev, V, rank = ttn.rayleigh_ritz(ctx, Hm.view(len(big), ld, ld), Sm.view(len(big), ld, ld),
+                                        [len(c) for c in big], ld, opts.drop_tol)
+        # coefficients for the recombination fit (identity for singleton clusters)
+        coef = torch.zeros(len(self.ci_t), dtype=torch.float64, device="cuda")
+        pos = 0
+        Vh = V  # [nb][ld][ld]
+        big_index = {tuple(c): i for i, c in enumerate(big)}
+        gather_src, gather_dst, ones_dst = [], [], []
+        for c in self._clusters:
+            if len(c) == 1:
+                ones_dst.append(pos)
+                pos += 1
+                continue
+            ci = big_index[tuple(c)]
+            for jj in range(len(c)):
+                for ll in range(len(c)):
+                    gather_src.append(ci * ld * ld + ll * ld + jj)
+                    gather_dst.append(pos)
+                    pos += 1
+        flat = Vh.reshape(-1)
+        if gather_dst:
+            coef[torch.tensor(gather_dst, device="cuda")] = flat[torch.tensor(gather_src, device="cuda")]
+        if ones_dst:
+            coef[torch.tensor(ones_dst, device="cuda")] = 1.0
+        self.ci_d.copy_(coef)
+        self._copy_rows(self.XN, 0, self.B, 0, k)
+        self._sw_rec.init(root)
+        for _ in range(opts.fit_sweeps):
+            ttn.run_sweep(self._sw_rec, self.gt, ttn.SOLVE_FIT)
+        ttn.block_normalize_node(ctx, self.XN, root)
+        self._copy_rows(self.B, 0, self.XN, 0, k)
+
+    def final_rr(self, drop_tol: float = 1e-12) -> np.ndarray:
+        """One global Rayleigh-Ritz over the k states (removes the
+        non-orthogonality of separately solved states)."""
+        k = self.k
+        ia, ib = [], []
+        for a in range(k):
+            for b in range(a, k):
+                ia.append(a)
+                ib.append(b)
+        hv, sv = self.gram(self.B, ia, ib)
+        Hm = self._assemble(hv, [a * k + b for a, b in zip(ia, ib)], [b * k + a for a, b in zip(ia, ib)], k * k)
+        Sm = self._assemble(sv, [a * k + b for a, b in zip(ia, ib)], [b * k + a for a, b in zip(ia, ib)], k * k)
+        ev, V, rank = ttn.rayleigh_ritz(self.ctx, Hm.view(1, k, k), Sm.view(1, k, k), [k], k, drop_tol)
+        return ev[0].cpu().numpy() + self.zpe

@@ -59,6 +59,9 @@ _SIGS = {
     "ttn_sweep_init": [_P, _I],
     "ttn_sweep_destroy": [_P],
     "sweep_step": [_P, _P, _I, _I, _P, _P, _P],
+    "ttn_block_normalize_node": [_P, _P, _I, _P],
+    "ttn_scatter_sym": [_P, _I, _P, _P, _P, _P],
+    "ttn_vec_scale": [_P, _I, _P, C.c_double, _P],
     "ttn_ctx_profile": [_P, _I],
     "ttn_ctx_profile_report": [_P, C.c_char_p, C.c_int64, C.POINTER(C.c_int64)],
 }
@@ -417,6 +420,18 @@ def profile_report(ctx: Context):
         k, st, kern, cnt, ms, fl = line.split("|")
         out.append((k, int(st), kern, int(cnt), float(ms), float(fl)))
     return out
+
+
+def block_normalize_node(ctx: Context, b: Block, u: int, norms=None):
+    _check(lib().ttn_block_normalize_node(ctx.h, b.h, u, _ptr(norms)), ctx)
+
+
+def scatter_sym(ctx: Context, idx_a: torch.Tensor, idx_b: torch.Tensor, vals: torch.Tensor, out: torch.Tensor):
+    _check(lib().ttn_scatter_sym(ctx.h, int(idx_a.numel()), _ptr(idx_a), _ptr(idx_b), _ptr(vals), _ptr(out)), ctx)
+
+
+def vec_scale(ctx: Context, x: torch.Tensor, alpha: float, y: torch.Tensor):
+    _check(lib().ttn_vec_scale(ctx.h, int(x.numel()), _ptr(x), float(alpha), _ptr(y)), ctx)
 
 
 def version() -> str:

@@ -1,0 +1,66 @@
+"""The GPU eigensolvers (block LOBPCG, block inverse iteration) against the
+stored oracle runs (tests/golden/c1_oracle_runs.json, written by
+tests/golden/make_golden.py from the oracle only) and against the closed form."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c1_oracle_runs.json")))
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2512_15875_amd import ttn
+    ttn.lib()
+    return ttn
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    return api.Context(0, workspace_bytes=1 << 30)
+
+
+def _solver(api, ctx, precision="fp64"):
+    from paper_2512_15875_amd.solver import TTNEigensolver
+    m = wl.make_config_model("c1")
+    tree = wl.mps_tree(m.dims, 2)
+    bonds = wl.bond_dims(tree, 8)
+    x0 = wl.initial_block(tree, bonds, m.omega, m.dims, 10, m.seed + 17)
+    s = TTNEigensolver(ctx, tree, m, D=8, k=10, precision=precision)
+    s.load_block(x0)
+    return s, m
+
+
+def test_lobpcg_c1_matches_oracle_and_closed_form(api, ctx):
+    from paper_2512_15875_amd.solver import LobpcgOpts
+    s, m = _solver(api, ctx)
+    lam = s.lobpcg(LobpcgOpts(n_iter=7, shift=GOLD["shift"]))
+    zpe = GOLD["zpe"]
+    for it, h in enumerate(s.history):
+        ref = np.array(GOLD["lam_history"][it]) + zpe
+        assert np.max(np.abs(h["lam"] - ref)) < 1e-4, it
+        np.testing.assert_allclose(h["resid"], GOLD["resid_history"][it], rtol=1e-3, atol=1e-6)
+    ref = np.array(GOLD["lam_final"]) + zpe
+    assert np.max(np.abs(lam - ref)) < 1e-4
+    exact = np.array(GOLD["exact"]) + zpe
+    assert np.max(np.abs(np.sort(lam) - exact)) < 1e-3
+    assert np.all(np.sort(lam) >= exact - 1e-7)
+
+
+def test_lobpcg_then_inverse_iteration_c1(api, ctx):
+    from paper_2512_15875_amd.solver import IIOpts, LobpcgOpts
+    s, m = _solver(api, ctx)
+    lam3 = s.lobpcg(LobpcgOpts(n_iter=3, shift=GOLD["shift"]))
+    zpe = GOLD["zpe"]
+    assert np.max(np.abs(lam3 - (np.array(GOLD["lobpcg3_lam"]) + zpe))) < 1e-4
+    theta = s.inverse_iteration(IIOpts(n_iter=2))
+    ref = np.array(GOLD["ii2_final_rr"]) + zpe
+    assert np.max(np.abs(theta - ref)) < 1e-4
+    exact = np.array(GOLD["exact"]) + zpe
+    assert np.max(np.abs(theta - exact)) < 1e-3
