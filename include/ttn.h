@@ -279,6 +279,9 @@ ttn_status ttn_sop_destroy(ttn_sop* s);
  * `buf` and then cleared only when cap >= needed (call once with buf NULL to
  * size the buffer). */
 ttn_status ttn_ctx_profile(ttn_ctx* ctx, int32_t on);
+/* Algorithmic contraction flops (minimum-order counts of every planned
+ * contraction launched on this context) since creation or the last reset. */
+ttn_status ttn_ctx_flops(ttn_ctx* ctx, double* total, int32_t reset);
 ttn_status ttn_ctx_profile_report(ttn_ctx* ctx, char* buf, int64_t cap, int64_t* needed);
 
 /* Algorithmic flop count of one heff_apply_block call for k states at node u

@@ -92,6 +92,7 @@ ttn_status exec_plan(ttn_ctx* ctx, const Plan& P, int ct, const std::vector<OpAd
     chunk = std::min<int64_t>(chunk, nb);
   }
   char* ws = (char*)ctx->ws + ws_off_bytes;
+  ctx->flops_done += P.flops_per_item * nb + P.flops_shared;
   // shared intermediates are computed once (first chunk) and kept
   bool shared_done = false;
   for (int z0 = 0; z0 < nb; z0 += (int)chunk) {
@@ -837,6 +838,13 @@ ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, 
 extern "C" {
 
 // ================================================================== profiling
+
+ttn_status ttn_ctx_flops(ttn_ctx* ctx, double* total, int32_t reset) {
+  if (!ctx || !total) return fail(ctx, TTN_E_ARG, "null argument");
+  *total = ctx->flops_done;
+  if (reset) ctx->flops_done = 0;
+  return TTN_OK;
+}
 
 ttn_status ttn_ctx_profile(ttn_ctx* ctx, int32_t on) {
   if (!ctx) return fail(nullptr, TTN_E_ARG, "null context");

@@ -202,6 +202,7 @@ struct ttn_prof_rec {
 
 struct ttn_ctx {
   bool profile = false;
+  double flops_done = 0;  // algorithmic contraction flops launched so far
   std::vector<ttn_prof_rec> prof;
   std::string prof_text;  // aggregated, not yet returned
   int device = 0;

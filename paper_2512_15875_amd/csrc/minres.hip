@@ -207,3 +207,48 @@ hipError_t launch_gather_coef(const double* coef, const int32_t* perm, int n, do
 }
 
 }  // namespace ttn
+
+namespace ttn {
+
+// y[t][i] = sum_{j in seg(t)} coef[j] * S[j][i]  (CSR over targets; rows of
+// S are per-term local results); one workgroup row-chunk per target
+template <typename T>
+__global__ void seg_sum_kernel(const T* S, const int32_t* ptr, const int32_t* terms, const double* coef, T* y,
+                               int64_t n, int k) {
+  const int t = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= k || i >= n) return;
+  double acc = 0.0;
+  for (int q = ptr[t]; q < ptr[t + 1]; ++q) {
+    const int j = terms[q];
+    acc += coef[j] * (double)S[(int64_t)j * n + i];
+  }
+  y[(int64_t)t * n + i] = (T)acc;
+}
+
+hipError_t launch_seg_sum(int ctype, const void* S, const int32_t* ptr, const int32_t* terms, const double* coef,
+                          void* y, int64_t n, int k, bool accumulate_first, hipStream_t s) {
+  (void)accumulate_first;
+  dim3 g((unsigned)((n + 255) / 256), (unsigned)k);
+  if (ctype == 0)
+    hipLaunchKernelGGL(seg_sum_kernel<double>, g, dim3(256), 0, s, (const double*)S, ptr, terms, coef, (double*)y, n, k);
+  else
+    hipLaunchKernelGGL(seg_sum_kernel<float>, g, dim3(256), 0, s, (const float*)S, ptr, terms, coef, (float*)y, n, k);
+  return hipGetLastError();
+}
+
+}  // namespace ttn
+
+namespace ttn {
+template <typename T>
+__global__ void add_kernel(const T* x, T* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (T)((double)y[i] + (double)x[i]);
+}
+hipError_t launch_axpy_rows(int ctype, const void* x, void* y, int64_t n, hipStream_t s) {
+  const unsigned g = (unsigned)((n + 255) / 256);
+  if (ctype == 0) hipLaunchKernelGGL(add_kernel<double>, dim3(g), dim3(256), 0, s, (const double*)x, (double*)y, n);
+  else hipLaunchKernelGGL(add_kernel<float>, dim3(g), dim3(256), 0, s, (const float*)x, (float*)y, n);
+  return hipGetLastError();
+}
+}  // namespace ttn

@@ -25,6 +25,9 @@ hipError_t launch_minres_report(const MinresState* st, int k, int32_t* iters, do
                                 hipStream_t s);
 hipError_t launch_diag_solve(int ctype, const void* b, const void* dg, void* y, int64_t n, hipStream_t s);
 hipError_t launch_gather_coef(const double* coef, const int32_t* perm, int n, double* out, hipStream_t s);
+hipError_t launch_seg_sum(int ctype, const void* S, const int32_t* ptr, const int32_t* terms, const double* coef,
+                          void* y, int64_t n, int k, bool accumulate_first, hipStream_t s);
+hipError_t launch_axpy_rows(int ctype, const void* x, void* y, int64_t n, hipStream_t s);
 }  // namespace ttn
 
 struct ttn_sweep_src {
@@ -42,6 +45,8 @@ struct ttn_sweep_src {
   double* d_rcoef = nullptr;          // coefficients in round order (gathered per step)
   ttn_envs* envs = nullptr;
   std::vector<void*> mem;
+  int32_t* d_csr_ptr = nullptr;    // [k+1] terms of each target
+  int32_t* d_csr_terms = nullptr;  // [n]
 };
 
 struct ttn_sweep {
@@ -62,7 +67,9 @@ struct ttn_sweep {
   int64_t nmax = 0;
   MinresState* st = nullptr;
   int32_t* d_active = nullptr;
+  void* fit_scratch = nullptr;  // [max terms][n_loc_max] per-term local results
   ~ttn_sweep() {
+    (void)hipFree(fit_scratch);
     for (auto& s : src) {
       for (void* p : s.mem) (void)hipFree(p);
       (void)hipFree(s.d_tgt);
@@ -71,6 +78,8 @@ struct ttn_sweep {
       (void)hipFree(s.d_rtgt);
       (void)hipFree(s.d_rsrc);
       (void)hipFree(s.d_rcoef);
+      (void)hipFree(s.d_csr_ptr);
+      (void)hipFree(s.d_csr_terms);
       delete s.envs;
     }
     for (void* p : hmem) (void)hipFree(p);
@@ -229,6 +238,21 @@ ttn_status ttn_sweep_create(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
       delete sw;
       return api_fail(ctx, TTN_E_DEVICE, "allocation failed");
     }
+    {
+      std::vector<int32_t> ptr(sw->k + 1, 0), terms;
+      for (int j = 0; j < s.n; ++j) ptr[s.tgt[j] + 1]++;
+      for (int i = 0; i < sw->k; ++i) ptr[i + 1] += ptr[i];
+      terms.assign(s.n, 0);
+      std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+      for (int j = 0; j < s.n; ++j) terms[fill[s.tgt[j]]++] = j;
+      if (!dmalloc(&s.d_csr_ptr, ptr.size() * 4) || !dmalloc(&s.d_csr_terms, (size_t)s.n * 4) ||
+          hipMemcpy(s.d_csr_ptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(s.d_csr_terms, terms.data(), (size_t)s.n * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        sw->src.push_back(s);
+        delete sw;
+        return api_fail(ctx, TTN_E_DEVICE, "allocation failed");
+      }
+    }
     s.envs = make_envs(t, target, s.op, s.blk, s.n, target->dt, s.mem, ok);
     sw->src.push_back(s);
     if (!ok) {
@@ -240,8 +264,10 @@ ttn_status ttn_sweep_create(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
   int64_t nmax = 1;
   for (int u = 0; u < t->n; ++u) nmax = std::max(nmax, target->size[u]);
   sw->nmax = nmax;
+  int max_terms = 0;
+  for (auto& s : sw->src) max_terms = std::max(max_terms, s.n);
   if (!dmalloc(&sw->vec, (size_t)8 * sw->k * nmax * es) || !dmalloc(&sw->st, (size_t)sw->k * sizeof(MinresState)) ||
-      !dmalloc(&sw->d_active, 16)) {
+      !dmalloc(&sw->d_active, 16) || !dmalloc(&sw->fit_scratch, (size_t)max_terms * nmax * es)) {
     delete sw;
     return api_fail(ctx, TTN_E_DEVICE, "allocation failed");
   }
@@ -345,20 +371,27 @@ ttn_status sweep_step(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, int32_t next, c
       }
     }
   } else if (mode == TTN_SOLVE_FIT) {
-    if (hipMemsetAsync(y_u, 0, (size_t)k * n * es, ctx->stream) != hipSuccess)
-      return api_fail(ctx, TTN_E_DEVICE, "memset failed");
-    for (auto& s : sw->src) {
+    // every term's local contribution (H_eff-type product with the (target,
+    // source) environments) in one batched launch, then a segmented sum per
+    // target: y_t = sum_{terms of t} c * scratch_term
+    for (size_t si = 0; si < sw->src.size(); ++si) {
+      auto& s = sw->src[si];
       if (!s.coef) return api_fail(ctx, TTN_E_ARG, "FIT needs coefficients");
-      hipError_t e = launch_gather_coef(s.coef, s.d_perm, s.n, s.d_rcoef, ctx->stream);
-      if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
-      int off = 0;
-      for (auto& rd : s.rounds) {
-        const int cnt = (int)rd.size();
-        r = heff_apply_rows(ctx, t, s.op, s.envs, u, cnt, s.d_perm + off, s.d_rsrc + off, s.d_rtgt + off, k, nullptr,
-                            s.d_rcoef + off, s.blk->ptr[u], s.blk->k, y_u, TTN_HEFF_NO_SHIFT | TTN_HEFF_ACCUM,
-                            sw->compute);
-        if (r != TTN_OK) return r;
-        off += cnt;
+      r = heff_apply_rows(ctx, t, s.op, s.envs, u, s.n, nullptr, s.d_src, nullptr, s.n, nullptr, nullptr,
+                          s.blk->ptr[u], s.blk->k, sw->fit_scratch, TTN_HEFF_NO_SHIFT, sw->compute);
+      if (r != TTN_OK) return r;
+      if (si == 0) {
+        hipError_t e = launch_seg_sum(ct, sw->fit_scratch, s.d_csr_ptr, s.d_csr_terms, s.coef, y_u, n, k, false,
+                                      ctx->stream);
+        if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+      } else {
+        // second source set: accumulate on top through a temporary target
+        void* tmp = vbuf(0);
+        hipError_t e = launch_seg_sum(ct, sw->fit_scratch, s.d_csr_ptr, s.d_csr_terms, s.coef, tmp, n, k, false,
+                                      ctx->stream);
+        if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+        e = launch_axpy_rows(ct, tmp, y_u, n * k, ctx->stream);
+        if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
       }
     }
   } else if (mode != 3) {

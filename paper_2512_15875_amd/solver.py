@@ -183,75 +183,87 @@ class TTNEigensolver:
 
     # ------------------------------------------------------------ LOBPCG
 
-    def lobpcg(self, opts: LobpcgOpts, exact=None, log=None):
-        ctx, k, root = self.ctx, self.k, self.root
-        t_start = time.perf_counter()
+    def lobpcg_start(self, opts: LobpcgOpts):
+        """Rayleigh quotients of the loaded block and the preconditioner shift."""
+        k = self.k
+        self._opts = opts
+        self._t0 = time.perf_counter()
         lam = self.rayleigh_quotients(self.B, list(range(k)))
         self.lam_d.copy_(lam)
-        if opts.shift is None:
-            s = float(lam.min().item()) - 837.0
-        else:
-            s = opts.shift
+        s = float(lam.min().item()) - 837.0 if opts.shift is None else opts.shift
         self.shift_d.fill_(s)
-        have_p = False
-        for it in range(opts.n_iter):
-            # residual r_j = H x_j - lambda_j x_j by fitting
-            ttn.vec_scale(ctx, self.lam_d, -1.0, self.neglam_d)
-            self._copy_rows(self.R, 0, self.B, 0, k)
-            self.sw_res.init(root)
-            for _ in range(opts.fit_sweeps):
-                ttn.run_sweep(self.sw_res, self.gt, ttn.SOLVE_FIT)
-            rn = torch.zeros(k, dtype=torch.float64, device="cuda")
-            ttn.block_node_norms2(ctx, self.R, root, rn)
-            # preconditioned residual: (H - s) w = r by ALS
-            self._copy_rows(self.Wp, 0, self.R, 0, k)
-            self.sw_pre.init(root)
-            for _ in range(opts.als_sweeps):
-                ttn.run_sweep(self.sw_pre, self.gt, ttn.SOLVE_MINRES, opts.minres_maxiter, opts.minres_rtol)
-            ttn.block_normalize_node(ctx, self.Wp, root)
-            self._copy_rows(self.B, k, self.Wp, 0, k)
-            rnorm = torch.sqrt(rn).cpu().numpy()
-            lam_h = self.lam_d.cpu().numpy()
-            rec = {"iter": it, "t": time.perf_counter() - t_start, "lam": lam_h + self.zpe, "resid": rnorm}
-            self.history.append(rec)
-            if log:
-                log(rec)
-            if opts.resid_tol is not None and rnorm.max() <= opts.resid_tol:
-                break
-            m = 3 * k if have_p else 2 * k
-            ia, ib = [], []
-            for a in range(m):
-                for b in range(a, m):
-                    ia.append(a)
-                    ib.append(b)
-            hv, sv = self.gram(self.B, ia, ib)
-            ld = 3 * k
-            Hm = self._assemble(hv, [a * ld + b for a, b in zip(ia, ib)], [b * ld + a for a, b in zip(ia, ib)], ld * ld)
-            Sm = self._assemble(sv, [a * ld + b for a, b in zip(ia, ib)], [b * ld + a for a, b in zip(ia, ib)], ld * ld)
-            if m < ld:  # unit diagonal in the unused block keeps the padding inert
-                pass
-            ev, V, rank = ttn.rayleigh_ritz(ctx, Hm.view(1, ld, ld), Sm.view(1, ld, ld), [m], k, opts.drop_tol)
-            Vf = V[0].reshape(-1)  # [ld][k] row-major: V[l, j] at l*k + j
-            self.cx_d.copy_(Vf[self.ix_gather])
-            self.cp_d.copy_(Vf[self.ip_gather])
-            # p_j = sum_{l >= k} V[l, j] s_l ; x_j = sum_l V[l, j] s_l
-            self._copy_rows(self.PN, 0, self.B, k, k)
-            self.sw_p.init(root)
-            for _ in range(opts.fit_sweeps):
-                ttn.run_sweep(self.sw_p, self.gt, ttn.SOLVE_FIT)
-            self._copy_rows(self.XN, 0, self.B, 0, k)
-            self.sw_x.init(root)
-            for _ in range(opts.fit_sweeps):
-                ttn.run_sweep(self.sw_x, self.gt, ttn.SOLVE_FIT)
-            ttn.block_normalize_node(ctx, self.PN, root)
-            ttn.block_normalize_node(ctx, self.XN, root)
-            self._copy_rows(self.B, 0, self.XN, 0, k)
-            self._copy_rows(self.B, 2 * k, self.PN, 0, k)
-            have_p = True
-            lam = self.rayleigh_quotients(self.B, list(range(k)))
-            self.lam_d.copy_(lam)
+        self._have_p = False
+        self._it = 0
+
+    def lobpcg_step(self, log=None) -> bool:
+        """One block-LOBPCG iteration; returns False when the residual
+        criterion stopped the iteration before the subspace update."""
+        ctx, k, root, opts = self.ctx, self.k, self.root, self._opts
+        it = self._it
+        self._it += 1
+        # residual r_j = H x_j - lambda_j x_j by fitting
+        ttn.vec_scale(ctx, self.lam_d, -1.0, self.neglam_d)
+        self._copy_rows(self.R, 0, self.B, 0, k)
+        self.sw_res.init(root)
+        for _ in range(opts.fit_sweeps):
+            ttn.run_sweep(self.sw_res, self.gt, ttn.SOLVE_FIT)
+        rn = torch.zeros(k, dtype=torch.float64, device="cuda")
+        ttn.block_node_norms2(ctx, self.R, root, rn)
+        # preconditioned residual: (H - s) w = r by ALS
+        self._copy_rows(self.Wp, 0, self.R, 0, k)
+        self.sw_pre.init(root)
+        for _ in range(opts.als_sweeps):
+            ttn.run_sweep(self.sw_pre, self.gt, ttn.SOLVE_MINRES, opts.minres_maxiter, opts.minres_rtol)
+        ttn.block_normalize_node(ctx, self.Wp, root)
+        self._copy_rows(self.B, k, self.Wp, 0, k)
+        rnorm = torch.sqrt(rn).cpu().numpy()
         lam_h = self.lam_d.cpu().numpy()
-        return lam_h + self.zpe
+        rec = {"iter": it, "t": time.perf_counter() - self._t0, "lam": lam_h + self.zpe, "resid": rnorm}
+        self.history.append(rec)
+        if log:
+            log(rec)
+        if opts.resid_tol is not None and rnorm.max() <= opts.resid_tol:
+            return False
+        m = 3 * k if self._have_p else 2 * k
+        ia, ib = [], []
+        for a in range(m):
+            for b in range(a, m):
+                ia.append(a)
+                ib.append(b)
+        hv, sv = self.gram(self.B, ia, ib)
+        ld = 3 * k
+        la = [a * ld + b for a, b in zip(ia, ib)]
+        lb = [b * ld + a for a, b in zip(ia, ib)]
+        Hm = self._assemble(hv, la, lb, ld * ld)
+        Sm = self._assemble(sv, la, lb, ld * ld)
+        ev, V, rank = ttn.rayleigh_ritz(ctx, Hm.view(1, ld, ld), Sm.view(1, ld, ld), [m], k, opts.drop_tol)
+        Vf = V[0].reshape(-1)  # [ld][k] row-major: V[l, j] at l*k + j
+        self.cx_d.copy_(Vf[self.ix_gather])
+        self.cp_d.copy_(Vf[self.ip_gather])
+        # p_j = sum_{l >= k} V[l, j] s_l ; x_j = sum_l V[l, j] s_l  (fitted)
+        self._copy_rows(self.PN, 0, self.B, k, k)
+        self.sw_p.init(root)
+        for _ in range(opts.fit_sweeps):
+            ttn.run_sweep(self.sw_p, self.gt, ttn.SOLVE_FIT)
+        self._copy_rows(self.XN, 0, self.B, 0, k)
+        self.sw_x.init(root)
+        for _ in range(opts.fit_sweeps):
+            ttn.run_sweep(self.sw_x, self.gt, ttn.SOLVE_FIT)
+        ttn.block_normalize_node(ctx, self.PN, root)
+        ttn.block_normalize_node(ctx, self.XN, root)
+        self._copy_rows(self.B, 0, self.XN, 0, k)
+        self._copy_rows(self.B, 2 * k, self.PN, 0, k)
+        self._have_p = True
+        lam = self.rayleigh_quotients(self.B, list(range(k)))
+        self.lam_d.copy_(lam)
+        return True
+
+    def lobpcg(self, opts: LobpcgOpts, log=None):
+        self.lobpcg_start(opts)
+        for _ in range(opts.n_iter):
+            if not self.lobpcg_step(log):
+                break
+        return self.lam_d.cpu().numpy() + self.zpe
 
     # ------------------------------------------------------------ inverse iteration
 

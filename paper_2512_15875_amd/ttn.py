@@ -63,6 +63,7 @@ _SIGS = {
     "ttn_scatter_sym": [_P, _I, _P, _P, _P, _P],
     "ttn_vec_scale": [_P, _I, _P, C.c_double, _P],
     "ttn_ctx_profile": [_P, _I],
+    "ttn_ctx_flops": [_P, C.POINTER(C.c_double), _I],
     "ttn_ctx_profile_report": [_P, C.c_char_p, C.c_int64, C.POINTER(C.c_int64)],
 }
 
@@ -403,6 +404,12 @@ def run_sweep(sw: Sweep, tree: Tree, mode: int, maxiter: int = 0, rtol: float = 
         m = mode if u not in seen else SOLVE_SKIP
         seen.add(u)
         sw.step(u, nxt, m, maxiter, rtol, iters, resid)
+
+
+def ctx_flops(ctx: Context, reset: bool = False) -> float:
+    out = C.c_double()
+    _check(lib().ttn_ctx_flops(ctx.h, C.byref(out), 1 if reset else 0), ctx)
+    return out.value
 
 
 def profile(ctx: Context, on: bool):
