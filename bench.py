@@ -166,11 +166,24 @@ def main():
     rep = api.profile_report(ctx)
     api.profile(ctx, False)
     by_kernel = {}
-    for key, st, kern, cnt, tms, fl in rep:
+    for key, st, kern, cnt, tms, fl, *_ in rep:
         a = by_kernel.setdefault(kern, [0, 0.0, 0.0])
         a[0] += cnt
         a[1] += tms
         a[2] += fl
+    for r in sorted(rep, key=lambda r: -r[4])[:12]:
+        key, st, kern, cnt, tms, fl, Mm, Nn, Kk, nz = r
+        print(f"  stage {key}#{st} {kern} M={Mm} N={Nn} K={Kk} items={nz} launches={cnt}: {tms:.1f} ms, "
+              f"{fl / tms / 1e9:.1f} TFLOP/s", file=sys.stderr)
+    by_class = {}
+    for key, st, kern, cnt, tms, fl, Mm, Nn, Kk, nz in rep:
+        cls = key.split(":")[0] + (":H" if key.split(":")[2] == "1" else ":I") + f":{kern.split('<')[1].split(',')[1].strip()}x{kern.split(',')[2].strip()}"
+        a = by_class.setdefault(cls, [0, 0.0, 0.0])
+        a[0] += cnt
+        a[1] += tms
+        a[2] += fl
+    for cls, (cnt, tms, fl) in sorted(by_class.items(), key=lambda kv: -kv[1][1])[:10]:
+        print(f"  class {cls}: {cnt} launches {tms:.1f} ms {fl / tms / 1e9:.1f} TFLOP/s", file=sys.stderr)
     dkern, (dcnt, dms, dfl) = max(by_kernel.items(), key=lambda kv: kv[1][1])
     achieved = dfl / (dms * 1e-3) / 1e12
     tot_ms = sum(v[1] for v in by_kernel.values())

@@ -274,7 +274,7 @@ ttn_status ttn_sop_destroy(ttn_sop* s);
 /* Per-stage timing: with profiling on, every contraction stage launch is
  * bracketed by HIP events on the context stream.  The report (synchronises
  * the stream, then clears the records) is text, one line per (plan, stage):
- * "plan-key|stage|kernel|launches|total_ms|algorithmic_flops".  `needed`
+ * "plan-key|stage|kernel|launches|total_ms|algorithmic_flops|M|N|K|batch_items".  `needed`
  * receives the size including the terminating NUL; the text is written to
  * `buf` and then cleared only when cap >= needed (call once with buf NULL to
  * size the buffer). */

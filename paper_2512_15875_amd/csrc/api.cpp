@@ -138,6 +138,10 @@ ttn_status exec_plan(ttn_ctx* ctx, const Plan& P, int ct, const std::vector<OpAd
         rec->step = (int)s;
         rec->kernel = gemm_kernel_name(ct, st.g);
         rec->flops = st.flops * cnt;
+        rec->M = st.g.M;
+        rec->N = st.g.N;
+        rec->K = st.g.K;
+        rec->nz = cnt;
         if (hipEventCreate(&rec->a) != hipSuccess || hipEventCreate(&rec->b) != hipSuccess)
           return fail(ctx, TTN_E_DEVICE, "hipEventCreate failed");
         (void)hipEventRecord(rec->a, ctx->stream);
@@ -278,7 +282,7 @@ bool build_env_net(const ttn_tree* t, const ttn_ttno* op, const ttn_block* bra, 
 
 Plan* get_plan(ttn_ctx* ctx, const Net& net, int ct, double batch, ttn_status& code) {
   std::ostringstream k;
-  k << net.key << ":ct" << ct << ":b" << (batch > 1 ? 1 : 0);
+  k << net.key << ":ct" << ct << ":b" << (batch <= 1 ? 0 : (batch < 256 ? 1 : 2));
   auto it = ctx->plans.find(k.str());
   if (it != ctx->plans.end()) return it->second.get();
   Status st;
@@ -859,6 +863,8 @@ ttn_status ttn_ctx_profile_report(ttn_ctx* ctx, char* buf, int64_t cap, int64_t*
     std::string kernel;
     int64_t count = 0;
     double ms = 0, flops = 0;
+    int M = 0, N = 0, K = 0;
+    int64_t nz = 0;
   };
   std::map<std::pair<std::string, int>, Agg> agg;
   for (auto& r : ctx->prof) {
@@ -869,6 +875,10 @@ ttn_status ttn_ctx_profile_report(ttn_ctx* ctx, char* buf, int64_t cap, int64_t*
     a.count += 1;
     a.ms += ms;
     a.flops += r.flops;
+    a.M = r.M;
+    a.N = r.N;
+    a.K = r.K;
+    a.nz += r.nz;
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
   }
@@ -876,7 +886,8 @@ ttn_status ttn_ctx_profile_report(ttn_ctx* ctx, char* buf, int64_t cap, int64_t*
   std::ostringstream o;
   for (auto& kv : agg)
     o << kv.first.first << "|" << kv.first.second << "|" << kv.second.kernel << "|" << kv.second.count << "|"
-      << kv.second.ms << "|" << kv.second.flops << "\n";
+      << kv.second.ms << "|" << kv.second.flops << "|" << kv.second.M << "|" << kv.second.N << "|" << kv.second.K
+      << "|" << kv.second.nz << "\n";
   ctx->prof_text += o.str();
   const std::string& s = ctx->prof_text;
   *needed = (int64_t)s.size() + 1;

@@ -108,7 +108,7 @@ ttn_status ttn_block_move_centre(ttn_ctx* ctx, ttn_block* b, int32_t u, int32_t 
   if (m_u < n) return api_fail(ctx, TTN_E_SHAPE, "QR needs rows >= bond (bond exceeds the tensor's other legs)");
   const int k = b->k;
   const size_t work = (size_t)k * 2 * m_u * n * sizeof(double);
-  const size_t rbytes = (size_t)k * n * n * sizeof(double);
+  const size_t rbytes = (size_t)k * (n * n + n) * sizeof(double);  // R blocks, then tau per reflector
   const size_t ybytes = (size_t)k * b->size[v] * es;
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   if (al(work) + al(rbytes) + al(ybytes) > ctx->ws_bytes) return api_fail(ctx, TTN_E_WORKSPACE, "workspace too small for QR");

@@ -15,6 +15,8 @@
 // The bf16 form reads FP32 tensors and rounds to bfloat16 when staging to LDS.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "internal.h"
 
 namespace ttn {
@@ -37,6 +39,7 @@ struct KArgs {
   const double* alpha;
   const double* shift;
   int M, N, K, z0, accum, tiles_n, has_d, d_const;
+  int tiles, nz, xcd_remap;
   int* flag;  // flag[2] is raised when a batch table holds an out-of-range index
 };
 
@@ -77,8 +80,12 @@ struct Types<2> {
   typedef floatx4 Acc;
 };
 
+// k-offset tables up to this many entries are staged in LDS
+#define KCAP 1536
+
+// occupancy floor: 3 waves / SIMD for FP32 tiles, 2 for FP64 and bf16 tiles
 template <int CT, int BM, int BN, int BK, bool AMF, bool BNF>
-__global__ __launch_bounds__(256) void ogemm_kernel(KArgs g) {
+__global__ __launch_bounds__(256, (CT == 1) ? 3 : 2) void ogemm_kernel(KArgs g) {
   typedef typename Types<CT>::T T;
   typedef typename Types<CT>::L L;
   typedef typename Types<CT>::Acc Acc;
@@ -86,12 +93,20 @@ __global__ __launch_bounds__(256) void ogemm_kernel(KArgs g) {
   constexpr int EB = BN * BK / 256;
   constexpr int WTM = BM / 2, WTN = BN / 2;
   constexpr int TM = WTM / 16, TN = WTN / 16;
-  // LDS: f64/f32 keep k-major slices (a row of 16 m for one k is contiguous);
-  // bf16 keeps m-major rows so that 8 consecutive k are one 16-byte read.
-  constexpr int PADA = (CT == 2) ? 8 : 16 / (int)sizeof(L) * ((CT == 0) ? 1 : 4);
-  constexpr int PADB = PADA;
-  constexpr int LA = (CT == 2) ? BM * (BK + PADA) : BK * (BM + PADA);
-  constexpr int LB = (CT == 2) ? BN * (BK + PADB) : BK * (BN + PADB);
+  // LDS layout per operand follows its fast global dimension, so that both the
+  // staging stores and the MFMA fragment reads avoid bank conflicts:
+  //  * m-fast (n-fast) operands: k-major slices [k][m + PM]; a fragment read
+  //    takes 16 consecutive m of two adjacent k rows, PM puts those rows 16
+  //    banks apart;
+  //  * k-fast operands: m-major rows [m][k + PK]; PK makes the row stride 2
+  //    modulo 32 banks so 16 rows x 2 k of a fragment read hit 32 banks.
+  // bf16 always uses m-major rows (8 consecutive k per lane = one 16-byte read).
+  constexpr bool A_KMAJOR = (CT != 2) && AMF;
+  constexpr bool B_KMAJOR = (CT != 2) && BNF;
+  constexpr int PM = (CT == 0) ? 2 : 16;
+  constexpr int PK = (CT == 2) ? 8 : ((CT == 0) ? 1 : 2);
+  constexpr int LA = A_KMAJOR ? BK * (BM + PM) : BM * (BK + PK);
+  constexpr int LB = B_KMAJOR ? BK * (BN + PM) : BN * (BK + PK);
   __shared__ L As[2][LA];
   __shared__ L Bs[2][LB];
 
@@ -99,68 +114,127 @@ __global__ __launch_bounds__(256) void ogemm_kernel(KArgs g) {
   const int lane = tid & 63;
   const int wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
-  const int z = blockIdx.y;
-  const int tmi = blockIdx.x / g.tiles_n;
-  const int tni = blockIdx.x - tmi * g.tiles_n;
+  // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+  // L2).  With many batch items, linear id g runs on XCD g % 8, so items are
+  // dealt to XCDs (item = 8 * (local / tiles) + g % 8) and every tile of one
+  // item shares one L2; with few items the tiles of an item spread instead.
+  int z, tile;
+  if (g.xcd_remap) {
+    const int gid = blockIdx.x;
+    const int local = gid >> 3;
+    const int grp = local / g.tiles;
+    tile = local - grp * g.tiles;
+    z = grp * 8 + (gid & 7);
+    if (z >= g.nz) return;
+  } else {
+    z = blockIdx.y;
+    tile = blockIdx.x;
+  }
+  const int tmi = tile / g.tiles_n;
+  const int tni = tile - tmi * g.tiles_n;
   const int m0 = tmi * BM, n0 = tni * BN;
   const int M = g.M, N = g.N, K = g.K;
 
   const T* __restrict__ A = (const T*)g.A.base + batch_off(g.A, z, g.z0, g.flag);
   const T* __restrict__ B = (const T*)g.B.base + batch_off(g.B, z, g.z0, g.flag);
 
-  // ---- fixed per-thread offsets
+  // ---- k-offset tables staged in LDS once (K <= KCAP), so the per-tile
+  // address of an element costs an LDS read instead of a dependent global load
+  __shared__ int sk_a[KCAP], sk_b[KCAP];
+  const bool k_in_lds = K <= KCAP;
+  if (k_in_lds) {
+    for (int i = tid; i < K; i += 256) {
+      sk_a[i] = g.a_ok[i];
+      sk_b[i] = g.b_ok[i];
+    }
+  }
+
+  // ---- fixed per-thread offsets (rows / columns owned by this thread);
+  // invalid entries are clamped to offset 0 (always addressable) and masked
   int a_fix[AMF ? 1 : EA];
   int b_fix[BNF ? 1 : EB];
+  bool a_ok_row[AMF ? 1 : EA], b_ok_col[BNF ? 1 : EB];
   if (AMF) {
     const int mg = m0 + tid % BM;
-    a_fix[0] = (mg < M) ? g.a_om[mg] : -1;
+    a_ok_row[0] = mg < M;
+    a_fix[0] = a_ok_row[0] ? g.a_om[mg] : 0;
   } else {
 #pragma unroll
     for (int i = 0; i < EA; ++i) {
       const int mg = m0 + tid / BK + i * (256 / BK);
-      a_fix[i] = (mg < M) ? g.a_om[mg] : -1;
+      a_ok_row[i] = mg < M;
+      a_fix[i] = a_ok_row[i] ? g.a_om[mg] : 0;
     }
   }
   if (BNF) {
     const int ng = n0 + tid % BN;
-    b_fix[0] = (ng < N) ? g.b_on[ng] : -1;
+    b_ok_col[0] = ng < N;
+    b_fix[0] = b_ok_col[0] ? g.b_on[ng] : 0;
   } else {
 #pragma unroll
     for (int i = 0; i < EB; ++i) {
       const int ng = n0 + tid / BK + i * (256 / BK);
-      b_fix[i] = (ng < N) ? g.b_on[ng] : -1;
+      b_ok_col[i] = ng < N;
+      b_fix[i] = b_ok_col[i] ? g.b_on[ng] : 0;
     }
   }
+  __syncthreads();
+  auto koff_a = [&](int kg) { return k_in_lds ? sk_a[kg] : g.a_ok[kg]; };
+  auto koff_b = [&](int kg) { return k_in_lds ? sk_b[kg] : g.b_ok[kg]; };
 
   T ra[EA], rb[EB];
   auto load = [&](int k0) {
     if (AMF) {
+      int ko[EA];
+      bool kv[EA];
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
         const int kg = k0 + tid / BM + i * (256 / BM);
-        ra[i] = (a_fix[0] >= 0 && kg < K) ? A[a_fix[0] + g.a_ok[kg]] : (T)0;
+        kv[i] = kg < K;
+        ko[i] = kv[i] ? koff_a(kg) : 0;
+      }
+#pragma unroll
+      for (int i = 0; i < EA; ++i) {
+        const T v = A[a_fix[0] + ko[i]];
+        ra[i] = (a_ok_row[0] && kv[i]) ? v : (T)0;
       }
     } else {
       const int kg = k0 + tid % BK;
-      const int ko = (kg < K) ? g.a_ok[kg] : -1;
+      const bool kv = kg < K;
+      const int ko = kv ? koff_a(kg) : 0;
 #pragma unroll
-      for (int i = 0; i < EA; ++i) ra[i] = (ko >= 0 && a_fix[i] >= 0) ? A[a_fix[i] + ko] : (T)0;
+      for (int i = 0; i < EA; ++i) {
+        const T v = A[a_fix[i] + ko];
+        ra[i] = (kv && a_ok_row[i]) ? v : (T)0;
+      }
     }
     if (BNF) {
+      int ko[EB];
+      bool kv[EB];
 #pragma unroll
       for (int i = 0; i < EB; ++i) {
         const int kg = k0 + tid / BN + i * (256 / BN);
-        rb[i] = (b_fix[0] >= 0 && kg < K) ? B[b_fix[0] + g.b_ok[kg]] : (T)0;
+        kv[i] = kg < K;
+        ko[i] = kv[i] ? koff_b(kg) : 0;
+      }
+#pragma unroll
+      for (int i = 0; i < EB; ++i) {
+        const T v = B[b_fix[0] + ko[i]];
+        rb[i] = (b_ok_col[0] && kv[i]) ? v : (T)0;
       }
     } else {
       const int kg = k0 + tid % BK;
-      const int ko = (kg < K) ? g.b_ok[kg] : -1;
+      const bool kv = kg < K;
+      const int ko = kv ? koff_b(kg) : 0;
 #pragma unroll
-      for (int i = 0; i < EB; ++i) rb[i] = (ko >= 0 && b_fix[i] >= 0) ? B[b_fix[i] + ko] : (T)0;
+      for (int i = 0; i < EB; ++i) {
+        const T v = B[b_fix[i] + ko];
+        rb[i] = (kv && b_ok_col[i]) ? v : (T)0;
+      }
     }
   };
-  auto aidx = [&](int m, int k) { return (CT == 2) ? m * (BK + PADA) + k : k * (BM + PADA) + m; };
-  auto bidx = [&](int n, int k) { return (CT == 2) ? n * (BK + PADB) + k : k * (BN + PADB) + n; };
+  auto aidx = [&](int m, int k) { return A_KMAJOR ? k * (BM + PM) + m : m * (BK + PK) + k; };
+  auto bidx = [&](int n, int k) { return B_KMAJOR ? k * (BN + PM) + n : n * (BK + PK) + k; };
   auto store = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < EA; ++i) {
@@ -227,31 +301,148 @@ __global__ __launch_bounds__(256) void ogemm_kernel(KArgs g) {
     __syncthreads();
   }
 
-  // ---- epilogue: C = alpha (acc - shift * D) (+ C)
+  // ---- epilogue: C = alpha (acc - shift * D) (+ C); output offsets loaded in
+  // one batch, then branch-free stores (masked rows / columns skipped)
   T* __restrict__ C = (T*)g.C.base + batch_off(g.C, z, g.z0, g.flag);
   const T* __restrict__ Dp = g.has_d ? (const T*)g.D.base + batch_off(g.D, z, g.z0, g.flag) : nullptr;
   const double alpha = g.alpha ? g.alpha[g.z0 + z] : 1.0;
   const double sh = g.shift ? g.shift[g.z0 + z] : 0.0;
+  int cm[TM][4], cn[TN];
+  bool rv[TM][4], cv[TN];
 #pragma unroll
-  for (int a = 0; a < TM; ++a) {
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = wm * WTM + a * 16 + ((CT == 0) ? ((lane >> 4) + 4 * i) : (4 * (lane >> 4) + i));
       const int mg = m0 + row;
-      if (mg >= M) continue;
-      const int64_t cm = g.c_om[mg];
+      rv[a][i] = mg < M;
+      cm[a][i] = rv[a][i] ? g.c_om[mg] : 0;
+    }
 #pragma unroll
-      for (int b = 0; b < TN; ++b) {
-        const int ng = n0 + wn * WTN + b * 16 + (lane & 15);
-        if (ng >= N) continue;
-        const int64_t co = cm + g.c_on[ng];
-        double v = (double)acc[a][b][i];
-        if (Dp) v -= sh * (double)Dp[co];
-        else if (g.d_const) v -= sh;
-        v *= alpha;
-        if (g.accum) v += (double)C[co];
-        C[co] = (T)v;
+  for (int b = 0; b < TN; ++b) {
+    const int ng = n0 + wn * WTN + b * 16 + (lane & 15);
+    cv[b] = ng < N;
+    cn[b] = cv[b] ? g.c_on[ng] : 0;
+  }
+  const bool plain = !Dp && !g.d_const && !g.accum;
+  if (plain) {
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+          if (rv[a][i] && cv[b]) C[cm[a][i] + cn[b]] = (T)(alpha * (double)acc[a][b][i]);
+  } else {
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        double dv[TN], cvv[TN];
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          const int o = cm[a][i] + cn[b];
+          dv[b] = Dp ? (double)Dp[o] : (g.d_const ? 1.0 : 0.0);
+          cvv[b] = g.accum ? (double)C[o] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+          if (rv[a][i] && cv[b]) C[cm[a][i] + cn[b]] = (T)(alpha * ((double)acc[a][b][i] - sh * dv[b]) + cvv[b]);
       }
+  }
+}
+
+// Wave-per-item variant for many tiny contractions (the identity-operator
+// environments and local sums of a fitting sweep: thousands of (target,
+// source) pairs with M, N of a few tens).  Each wave64 owns one batch item
+// and walks its output in 16*TMW x 16*TNW tiles, feeding the matrix cores
+// straight from global memory (no LDS staging, no workgroup barriers); the
+// four waves of a workgroup take four consecutive items.
+template <int CT, int TMW, int TNW>
+__global__ __launch_bounds__(256) void ogemm_wave_kernel(KArgs g) {
+  typedef typename Types<CT == 2 ? 1 : CT>::T T;
+  typedef typename Types<CT == 2 ? 1 : CT>::Acc Acc;
+  const int lane = threadIdx.x & 63;
+  const int z = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (z >= g.nz) return;  // wave-uniform; the kernel has no barriers
+  const int M = g.M, N = g.N, K = g.K;
+  const T* __restrict__ A = (const T*)g.A.base + batch_off(g.A, z, g.z0, g.flag);
+  const T* __restrict__ B = (const T*)g.B.base + batch_off(g.B, z, g.z0, g.flag);
+  T* __restrict__ C = (T*)g.C.base + batch_off(g.C, z, g.z0, g.flag);
+  const T* __restrict__ Dp = g.has_d ? (const T*)g.D.base + batch_off(g.D, z, g.z0, g.flag) : nullptr;
+  const double alpha = g.alpha ? g.alpha[g.z0 + z] : 1.0;
+  const double sh = g.shift ? g.shift[g.z0 + z] : 0.0;
+  const int l16 = lane & 15, lk = lane >> 4;
+  for (int mt = 0; mt < M; mt += 16 * TMW) {
+    int aoff[TMW];
+    bool av_ok[TMW];
+#pragma unroll
+    for (int a = 0; a < TMW; ++a) {
+      const int r = mt + a * 16 + l16;
+      av_ok[a] = r < M;
+      aoff[a] = av_ok[a] ? g.a_om[r] : 0;
+    }
+    for (int nt = 0; nt < N; nt += 16 * TNW) {
+      int boff[TNW];
+      bool bv_ok[TNW];
+#pragma unroll
+      for (int b = 0; b < TNW; ++b) {
+        const int c = nt + b * 16 + l16;
+        bv_ok[b] = c < N;
+        boff[b] = bv_ok[b] ? g.b_on[c] : 0;
+      }
+      Acc acc[TMW][TNW];
+#pragma unroll
+      for (int a = 0; a < TMW; ++a)
+#pragma unroll
+        for (int b = 0; b < TNW; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+      for (int k0 = 0; k0 < K; k0 += 4) {
+        const int kk = k0 + lk;
+        const bool kv = kk < K;
+        const int ak = kv ? g.a_ok[kk] : 0;
+        const int bk = kv ? g.b_ok[kk] : 0;
+        T af[TMW], bf[TNW];
+#pragma unroll
+        for (int a = 0; a < TMW; ++a) {
+          const T v = A[aoff[a] + ak];
+          af[a] = (kv && av_ok[a]) ? v : (T)0;
+        }
+#pragma unroll
+        for (int b = 0; b < TNW; ++b) {
+          const T v = B[bk + boff[b]];
+          bf[b] = (kv && bv_ok[b]) ? v : (T)0;
+        }
+#pragma unroll
+        for (int a = 0; a < TMW; ++a)
+#pragma unroll
+          for (int b = 0; b < TNW; ++b) {
+            if constexpr (CT == 0)
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+            else
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a], bf[b], acc[a][b], 0, 0, 0);
+          }
+      }
+      // epilogue for this tile
+#pragma unroll
+      for (int a = 0; a < TMW; ++a)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = mt + a * 16 + ((CT == 0) ? (lk + 4 * i) : (4 * lk + i));
+          const bool rok = row < M;
+          const int cm = rok ? g.c_om[row] : 0;
+#pragma unroll
+          for (int b = 0; b < TNW; ++b) {
+            const int col = nt + b * 16 + l16;
+            if (!rok || col >= N) continue;
+            const int o = cm + g.c_on[col];
+            double v = (double)acc[a][b][i];
+            if (Dp) v -= sh * (double)Dp[o];
+            else if (g.d_const) v -= sh;
+            v *= alpha;
+            if (g.accum) v += (double)C[o];
+            C[o] = (T)v;
+          }
+        }
     }
   }
 }
@@ -269,11 +460,20 @@ static KOp kop(const OpAddr& o, int default_mode) {
   return k;
 }
 
+static int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  return v ? atoi(v) : dflt;
+}
+
 template <int CT, int BM, int BN, int BK>
 static hipError_t launch_cfg(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s) {
   const int tm = (gd.M + BM - 1) / BM, tn = (gd.N + BN - 1) / BN;
   a.tiles_n = tn;
-  dim3 grid(tm * tn, nz);
+  a.tiles = tm * tn;
+  a.nz = nz;
+  static const int remap_min = env_int("TTN_XCD_REMAP_MIN", 256);
+  a.xcd_remap = nz >= remap_min ? 1 : 0;
+  dim3 grid = a.xcd_remap ? dim3((unsigned)(((nz + 7) / 8) * 8 * a.tiles), 1) : dim3(tm * tn, nz);
   if (gd.a_mfast && gd.b_nfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, true, true>), grid, dim3(256), 0, s, a);
   else if (gd.a_mfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, true, false>), grid, dim3(256), 0, s, a);
   else if (gd.b_nfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, false, true>), grid, dim3(256), 0, s, a);
@@ -281,9 +481,8 @@ static hipError_t launch_cfg(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s
   return hipGetLastError();
 }
 
-template <int CT>
-static hipError_t launch_ct(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s) {
-  constexpr int BK = (CT == 2) ? 32 : 16;
+template <int CT, int BK>
+static hipError_t launch_tile(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s) {
   switch (gd.tile) {
     case 0: return launch_cfg<CT, 128, 128, BK>(gd, a, nz, s);
     case 1: return launch_cfg<CT, 64, 64, BK>(gd, a, nz, s);
@@ -295,11 +494,52 @@ static hipError_t launch_ct(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s)
   }
 }
 
+// k-slice depth: 16 for FP32 and FP64 (measured on the hot-path shapes: the
+// deeper FP32 slice costs occupancy and never paid), 32 for bf16 (one MFMA).
+static int pick_bk(int ctype, const GemmDesc& gd) {
+  if (ctype == 0) return 16;
+  if (ctype == 2) return 32;
+  static const int mode = env_int("TTN_BK_MODE", 16);  // measured: 16 is as good or better everywhere
+  (void)gd;
+  return mode == 32 ? 32 : 16;
+}
+
+template <int CT>
+static hipError_t launch_wave(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s) {
+  a.nz = nz;
+  a.xcd_remap = 0;
+  dim3 grid((unsigned)((nz + 3) / 4));
+  constexpr int C2 = (CT == 2) ? 1 : CT;  // tiny stages of a bf16 contraction run on FP32 matrix cores
+  if (gd.M <= 16 && gd.N <= 16) hipLaunchKernelGGL((ogemm_wave_kernel<C2, 1, 1>), grid, dim3(256), 0, s, a);
+  else if (gd.M <= 16) hipLaunchKernelGGL((ogemm_wave_kernel<C2, 1, 2>), grid, dim3(256), 0, s, a);
+  else if (gd.N <= 16) hipLaunchKernelGGL((ogemm_wave_kernel<C2, 2, 1>), grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((ogemm_wave_kernel<C2, 2, 2>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int CT>
+static hipError_t launch_ct(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s) {
+  if (gd.tile == 7) return launch_wave<CT>(gd, a, nz, s);
+  if constexpr (CT == 1) {
+    if (pick_bk(CT, gd) == 16) return launch_tile<CT, 16>(gd, a, nz, s);
+    return launch_tile<CT, 32>(gd, a, nz, s);
+  } else {
+    return launch_tile<CT, (CT == 0) ? 16 : 32>(gd, a, nz, s);
+  }
+}
+
+static int pick_bk(int ctype, const GemmDesc& gd);
+
 std::string gemm_kernel_name(int ctype, const GemmDesc& gd) {
   static const int bm[] = {128, 64, 128, 64, 32, 64, 32};
   static const int bn[] = {128, 64, 64, 128, 64, 32, 32};
+  if (gd.tile == 7) {
+    const int tmw = gd.M <= 16 ? 1 : 2, tnw = gd.N <= 16 ? 1 : 2;
+    return "ogemm_wave_kernel<" + std::to_string(ctype == 2 ? 1 : ctype) + ", " + std::to_string(tmw) + ", " +
+           std::to_string(tnw) + ">";
+  }
   const int t = gd.tile < 0 || gd.tile > 6 ? 6 : gd.tile;
-  const int bk = ctype == 2 ? 32 : 16;
+  const int bk = pick_bk(ctype, gd);
   return "ogemm_kernel<" + std::to_string(ctype) + ", " + std::to_string(bm[t]) + ", " + std::to_string(bn[t]) + ", " +
          std::to_string(bk) + ", " + (gd.a_mfast ? "true" : "false") + ", " + (gd.b_nfast ? "true" : "false") + ">";
 }

@@ -323,19 +323,30 @@ hipError_t launch_rr(int batch, const int32_t* d_m, int ld, const double* H, con
 }
 
 // ---------------------------------------------------------------- QR gauge move
-// Per state z (one workgroup): the node tensor viewed as the matrix
-// A[r][j] = X[z*size + roff[r] + j*cstride] (rows = all other legs, columns =
-// the leg toward the new centre), Householder QR in double with diag(R) >= 0.
-// Q overwrites the tensor; R (n x n) goes to Rout[z].  m x n with m >= n.
+// Per state z (one workgroup of 4 wave64s): the node tensor viewed as the
+// matrix A[r][j] = X[z*size + roff[r] + j*cstride] (rows = all other legs,
+// columns = the leg toward the new centre), Householder QR in double with
+// diag(R) >= 0.  Q overwrites the tensor; R (n x n) goes to Rout[z]; m >= n.
+// For each reflector the dot products with all remaining columns are done at
+// once: columns are dealt to the 4 waves, rows to the 64 lanes, each dot is a
+// wave reduction, so a reflector costs two workgroup barriers.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void qr_kernel(T* X, int64_t size, const int32_t* roff, int m, int n,
                                                  int64_t cstride, double* work, double* Rout, int* flag) {
   __shared__ double red[256];
+  __shared__ double wdot[512];
   __shared__ double sh_tau, sh_alpha;
   const int z = blockIdx.x, t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
   T* Xz = X + (int64_t)z * size;
   double* A = work + (size_t)z * ((size_t)m * n + (size_t)m * n);  // m x n working copy (column-major)
   double* Vh = A + (size_t)m * n;                                  // Householder vectors (column-major)
+  double* tauv = Rout + (size_t)gridDim.x * n * n + (size_t)z * n;  // tau per reflector
   for (int i = t; i < m * n; i += 256) {
     const int j = i / m, r = i - j * m;
     A[i] = (double)Xz[roff[r] + (int64_t)j * cstride];
@@ -343,7 +354,7 @@ __global__ __launch_bounds__(256) void qr_kernel(T* X, int64_t size, const int32
   __syncthreads();
   double* R = Rout + (size_t)z * n * n;
   for (int k = 0; k < n; ++k) {
-    double* a = A + (size_t)k * m;
+    const double* a = A + (size_t)k * m;
     double ss = 0;
     for (int i = k + t; i < m; i += 256) ss += a[i] * a[i];
     ss = block_sum(ss, red);
@@ -356,22 +367,29 @@ __global__ __launch_bounds__(256) void qr_kernel(T* X, int64_t size, const int32
       const double vn2 = ss - x0 * x0 + v0 * v0;
       sh_tau = vn2 > 0 ? 2.0 / vn2 : 0.0;
       sh_alpha = alpha;
+      tauv[k] = sh_tau;
     }
     __syncthreads();
     for (int i = t; i < m; i += 256) v[i] = i < k ? 0.0 : (i == k ? a[k] - sh_alpha : a[i]);
     __syncthreads();
-    const double tau = sh_tau;
-    // apply to columns k..n-1: a_j -= tau (v . a_j) v
-    for (int j = k; j < n; ++j) {
-      double* aj = A + (size_t)j * m;
+    // w_j = v . a_j for j = k..n-1 (columns dealt to waves, rows to lanes)
+    for (int j = k + wv; j < n; j += 4) {
+      const double* aj = A + (size_t)j * m;
       double d = 0;
-      for (int i = k + t; i < m; i += 256) d += v[i] * aj[i];
-      d = block_sum(d, red) * tau;
-      for (int i = k + t; i < m; i += 256) aj[i] -= d * v[i];
-      __syncthreads();
+      for (int i = k + lane; i < m; i += 64) d += v[i] * aj[i];
+      d = wave_sum(d);
+      if (lane == 0) wdot[j] = d;
     }
+    __syncthreads();
+    const double tau = sh_tau;
+    for (int e = t; e < (n - k) * (m - k); e += 256) {
+      const int jj = e / (m - k), i = k + (e - jj * (m - k));
+      const int j = k + jj;
+      A[(size_t)j * m + i] -= tau * wdot[j] * v[i];
+    }
+    __syncthreads();
   }
-  // R (upper triangle of A) with signs fixed
+  // R (upper triangle of A)
   for (int i = t; i < n * n; i += 256) {
     const int r = i / n, c = i - r * n;
     R[i] = (c >= r) ? A[(size_t)c * m + r] : 0.0;
@@ -385,18 +403,20 @@ __global__ __launch_bounds__(256) void qr_kernel(T* X, int64_t size, const int32
   __syncthreads();
   for (int k = n - 1; k >= 0; --k) {
     const double* v = Vh + (size_t)k * m;
-    double vn2 = 0;
-    for (int i = k + t; i < m; i += 256) vn2 += v[i] * v[i];
-    vn2 = block_sum(vn2, red);
-    const double tau = vn2 > 0 ? 2.0 / vn2 : 0.0;
-    for (int j = 0; j < n; ++j) {
-      double* qj = A + (size_t)j * m;
+    const double tau = tauv[k];
+    for (int j = wv; j < n; j += 4) {
+      const double* qj = A + (size_t)j * m;
       double d = 0;
-      for (int i = k + t; i < m; i += 256) d += v[i] * qj[i];
-      d = block_sum(d, red) * tau;
-      for (int i = k + t; i < m; i += 256) qj[i] -= d * v[i];
-      __syncthreads();
+      for (int i = k + lane; i < m; i += 64) d += v[i] * qj[i];
+      d = wave_sum(d);
+      if (lane == 0) wdot[j] = d;
     }
+    __syncthreads();
+    for (int e = t; e < n * (m - k); e += 256) {
+      const int j = e / (m - k), i = k + (e - j * (m - k));
+      A[(size_t)j * m + i] -= tau * wdot[j] * v[i];
+    }
+    __syncthreads();
   }
   // sign fix: diag(R) >= 0
   __shared__ double sg[512];

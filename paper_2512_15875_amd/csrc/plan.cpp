@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <functional>
+#include <cstdlib>
 #include <limits>
 
 #include "internal.h"
@@ -99,7 +100,13 @@ void group_offsets(const std::vector<int>& labs, const std::map<int, int>& dims,
   }
 }
 
-int pick_tile(int M, int N, double nblocks_other) {
+int pick_tile(int M, int N, int K, double nblocks_other) {
+  // tiny per-item products over many items: one wave per item (tile id 7).
+  // Measured on the fitting environments it does not beat the 32x32 tile
+  // (those stages are bound by their intermediates' memory traffic), so it is
+  // only used when requested.
+  static const int wave_on = getenv("TTN_WAVE_KERNEL") ? 1 : 0;
+  if (wave_on && nblocks_other >= 256 && (double)M * N <= 64.0 * 64.0 && K <= 4096) return 7;
   // prefer big tiles when the grid stays large enough to fill 256 CUs
   struct C {
     int id, bm, bn;
@@ -329,7 +336,7 @@ std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<in
     stp.max_a = vmax(t_am) + vmax(t_ak);
     stp.max_b = vmax(t_bk) + vmax(t_bn);
     stp.max_c = vmax(t_cm) + vmax(t_cn);
-    g.tile = pick_tile(g.M, g.N, stp.batched ? batch : 1.0);
+    g.tile = pick_tile(g.M, g.N, g.K, stp.batched ? batch : 1.0);
     if (stp.batched) plan->flops_per_item += stp.flops;
     else plan->flops_shared += stp.flops;
     plan->steps.push_back(stp);

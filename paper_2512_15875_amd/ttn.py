@@ -417,15 +417,15 @@ def profile(ctx: Context, on: bool):
 
 
 def profile_report(ctx: Context):
-    """[(plan_key, stage, kernel, launches, total_ms, flops)] since the last report."""
+    """[(plan_key, stage, kernel, launches, total_ms, flops, M, N, K, batch_items)] since the last report."""
     need = C.c_int64()
     _check(lib().ttn_ctx_profile_report(ctx.h, None, 0, C.byref(need)), ctx)
     buf = C.create_string_buffer(int(need.value) + 1024)
     _check(lib().ttn_ctx_profile_report(ctx.h, buf, len(buf), C.byref(need)), ctx)
     out = []
     for line in buf.value.decode().splitlines():
-        k, st, kern, cnt, ms, fl = line.split("|")
-        out.append((k, int(st), kern, int(cnt), float(ms), float(fl)))
+        k, st, kern, cnt, ms, fl, M, N, K, nz = line.split("|")
+        out.append((k, int(st), kern, int(cnt), float(ms), float(fl), int(M), int(N), int(K), int(nz)))
     return out
 
 
