@@ -182,13 +182,31 @@ ttn_status rayleigh_ritz(ttn_ctx* ctx, int32_t batch, const int32_t* m, int32_t 
 
 /* MINRES: local MINRES on (H_eff - s_j); DIAG: y = b / (diag(H_eff) - s_j);
  * FIT: y_u = the fitting sum; SKIP: no local solve (only the centre move, as
- * on the later visits of a node during an Euler tour). */
-typedef enum { TTN_SOLVE_MINRES = 0, TTN_SOLVE_DIAG = 1, TTN_SOLVE_FIT = 2, TTN_SOLVE_SKIP = 3 } ttn_solve_mode;
+ * on the later visits of a node during an Euler tour).
+ * LEARNED (the learned local preconditioner; not in the paper, which names
+ * better preconditioners as future work in its outlook): the MLP of
+ * ttn_mlp_forward maps the tile features of (b, diag(H_eff) - s_j) to a
+ * candidate y_L; the DIAG solution y_D stays the fallback and the judge: the
+ * local result is the minimal-residual combination a y_D + c y_L (2x2 least
+ * squares on |(H_eff - s_j)(a y_D + c y_L) - b|, FP64), and c = 0 whenever
+ * that system is singular or not finite, so a local step never leaves a
+ * larger residual than the DIAG step scaled by its own best factor. */
+typedef enum {
+  TTN_SOLVE_MINRES = 0,
+  TTN_SOLVE_DIAG = 1,
+  TTN_SOLVE_FIT = 2,
+  TTN_SOLVE_SKIP = 3,
+  TTN_SOLVE_LEARNED = 4
+} ttn_solve_mode;
 
 typedef struct {
-  int32_t mode;      /* ttn_solve_mode */
-  int32_t maxiter;   /* MINRES iterations per local solve */
-  double rtol;       /* MINRES: stop when |residual| <= rtol * |b| */
+  int32_t mode;              /* ttn_solve_mode */
+  int32_t maxiter;           /* MINRES iterations per local solve */
+  double rtol;               /* MINRES: stop when |residual| <= rtol * |b| */
+  const float* mlp_params;   /* LEARNED: device FP32 parameters (ttn_mlp_num_params() floats) */
+  int32_t mlp_compute;       /* LEARNED: TTN_BF16 or TTN_F32 matrix-core arithmetic */
+  int32_t pad_;
+  double* learned_coef;      /* LEARNED, optional: device double[k][2], (a, c) of the last local step */
 } ttn_solve_opts;
 
 typedef struct ttn_sweep ttn_sweep;
@@ -283,6 +301,55 @@ ttn_status ttn_ctx_profile(ttn_ctx* ctx, int32_t on);
  * contraction launched on this context) since creation or the last reset. */
 ttn_status ttn_ctx_flops(ttn_ctx* ctx, double* total, int32_t reset);
 ttn_status ttn_ctx_profile_report(ttn_ctx* ctx, char* buf, int64_t cap, int64_t* needed);
+
+/* ------------------------------------------------------------ learned local preconditioner
+ *
+ * A 3-layer perceptron 128 -> 256 -> 256 -> 64 with SiLU after the two hidden
+ * layers, applied to tiles of T = 64 consecutive entries of a local vector.
+ * Parameters: one device FP32 array of ttn_mlp_num_params() floats, row-major
+ * W1[128][256], b1[256], W2[256][256], b2[256], W3[256][64], b3[64]; a layer
+ * computes out = in W + b.  compute = TTN_BF16 rounds both GEMM operands to
+ * bfloat16 as they are staged (FP32 master weights, FP32 accumulation);
+ * TTN_F32 keeps FP32 operands.  All pointers are device pointers owned by the
+ * caller; every call is asynchronous on the context stream.
+ *
+ * Features of state j's tile t: [b_tile / |b_j|, (d_tile) / sigma_j] with
+ * d = diag(H_eff) - s_j, sigma_j = mean |d| over the node, zero past the
+ * vector's end; the network output is the correction tile in units of
+ * |b_j| / sigma_j. */
+int64_t ttn_mlp_num_params(void);
+
+/* Y[n][64] = MLP(X[n][128]); acts (nullable): float[4][n][256] receives the
+ * pre- and post-activation of both hidden layers for ttn_mlp_backward (null:
+ * context workspace, 4 KiB per row, TTN_E_WORKSPACE if too small). */
+ttn_status ttn_mlp_forward(ttn_ctx* ctx, const float* params, int32_t n, const float* X, float* Y, float* acts,
+                           ttn_dtype compute);
+/* grads (ttn_mlp_num_params floats, overwritten) of sum over the rows of
+ * <dY, Y> for the forward pass recorded in acts.  Uses 2 KiB of workspace per
+ * row. */
+ttn_status ttn_mlp_backward(ttn_ctx* ctx, const float* params, int32_t n, const float* X, const float* acts,
+                            const float* dY, float* grads, ttn_dtype compute);
+/* Mean-squared error over n x 64 outputs: loss (device double, overwritten)
+ * and its gradient dY = 2 (Y - T) / (64 n). */
+ttn_status ttn_mlp_loss(ttn_ctx* ctx, int32_t n, const float* Y, const float* T, float* dY, double* loss);
+/* One Adam step (bias-corrected, step >= 1) on all parameters. */
+ttn_status ttn_mlp_adam(ttn_ctx* ctx, float* params, float* m, float* v, const float* grads, float lr, float beta1,
+                        float beta2, float eps, int32_t step);
+/* Tile features of k local vectors b[k][n] with diagonals d[k][n] (storage
+ * TTN_F64 or TTN_F32): X[k * ceil(n/64)][128]; scales double[k][2] receives
+ * (|b_j|, sigma_j). */
+ttn_status ttn_precond_features(ttn_ctx* ctx, int32_t k, int64_t n, ttn_dtype storage, const void* b, const void* d,
+                                double* scales, float* X);
+/* Training targets: the solution tiles y[k][n] in network units
+ * (y * sigma_j / |b_j|), T[k * ceil(n/64)][64]. */
+ttn_status ttn_precond_targets(ttn_ctx* ctx, int32_t k, int64_t n, ttn_dtype storage, const void* y,
+                               const double* scales, float* T);
+/* Training pairs of the current local problems of a sweep at `node` (the
+ * sweep's orthogonality centre): features of (b_j, diag(H_eff) - s_j) into
+ * X[k * ceil(n/64)][128] and targets of the current local tensors (the
+ * solution a MINRES step just left there) into T[k * ceil(n/64)][64];
+ * scales double[k][2]. */
+ttn_status ttn_sweep_harvest(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, float* X, float* T, double* scales);
 
 /* Algorithmic flop count of one heff_apply_block call for k states at node u
  * (minimum over pairwise contraction orders, dense operands at unpadded

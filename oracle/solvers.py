@@ -23,7 +23,7 @@ from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
-from . import ttn
+from . import mlp, ttn
 from .linalg import minres, rayleigh_ritz
 
 
@@ -56,8 +56,11 @@ class SolveStats:
 
 
 def als_solve(tree, W, shift: float, phi, y0, sweeps: int, maxiter: int, rtol: float,
-              stats: Optional[SolveStats] = None):
-    """Approximate y with (H - shift) y = phi (Sec. II.C.4, Fig. als)."""
+              stats: Optional[SolveStats] = None, local="minres"):
+    """Approximate y with (H - shift) y = phi (Sec. II.C.4, Fig. als).
+
+    local: the local map -- "minres" (the paper's), "diag" (y = b / (diag(H_eff)
+    - s)), or ("learned", params) for the learned map of ``oracle.mlp``."""
     root = tree.root
     y = ttn.canonicalize(tree, y0, root)
     phi_c = phi
@@ -72,11 +75,21 @@ def als_solve(tree, W, shift: float, phi, y0, sweeps: int, maxiter: int, rtol: f
                 b = ttn.heff_apply(tree, u, None, phi_c[u], Rc.incoming(u))
                 Hin = Hc.incoming(u)
                 Wu = W[u]
-                x, it, res = minres(lambda v: ttn.heff_apply(tree, u, Wu, v, Hin, shift), b, y[u], rtol, maxiter)
+                if local == "minres":
+                    x, it, res = minres(lambda v: ttn.heff_apply(tree, u, Wu, v, Hin, shift), b, y[u], rtol, maxiter)
+                    if stats is not None:
+                        stats.iters.append(it)
+                        stats.resid.append(res)
+                else:
+                    dg = ttn.heff_diag(tree, u, Wu, Hin, shift)
+                    if local == "diag":
+                        x = b / dg
+                    else:
+                        shp = b.shape
+                        A = lambda v: ttn.heff_apply(tree, u, Wu, v.reshape(shp), Hin, shift).ravel()
+                        x, _ = mlp.learned_local(local[1], A, b.ravel(), dg.ravel())
+                        x = x.reshape(shp)
                 y[u] = x
-                if stats is not None:
-                    stats.iters.append(it)
-                    stats.resid.append(res)
             if t + 1 < len(tour):
                 v = tour[t + 1]
                 ttn.move_centre(tree, y, u, v)

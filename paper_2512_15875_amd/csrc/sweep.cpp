@@ -28,6 +28,14 @@ hipError_t launch_gather_coef(const double* coef, const int32_t* perm, int n, do
 hipError_t launch_seg_sum(int ctype, const void* S, const int32_t* ptr, const int32_t* terms, const double* coef,
                           void* y, int64_t n, int k, bool accumulate_first, hipStream_t s);
 hipError_t launch_axpy_rows(int ctype, const void* x, void* y, int64_t n, hipStream_t s);
+hipError_t launch_features(int ctype, const void* b, const void* d, int64_t n, int nz, double* scales, float* X,
+                           hipStream_t s);
+hipError_t launch_targets(int ctype, const void* y, int64_t n, int nz, const double* scales, float* Yt, hipStream_t s);
+hipError_t launch_untile(int ctype, const float* Yn, int64_t n, int nz, const double* scales, void* y, hipStream_t s);
+hipError_t launch_mr2(int ctype, const void* Pd, const void* Pl, const void* b, int64_t n, int nz, double* coef,
+                      hipStream_t s);
+hipError_t launch_mr2_combine(int ctype, const void* yd, const void* yl, const double* coef, void* y, int64_t n,
+                              int nz, hipStream_t s);
 }  // namespace ttn
 
 struct ttn_sweep_src {
@@ -68,8 +76,17 @@ struct ttn_sweep {
   MinresState* st = nullptr;
   int32_t* d_active = nullptr;
   void* fit_scratch = nullptr;  // [max terms][n_loc_max] per-term local results
+  // learned local map: candidate bookkeeping for 2k states (DIAG + MLP)
+  int32_t* d_pair2 = nullptr;   // [2k] environment slot of each candidate (j mod k)
+  double* d_shift2 = nullptr;   // [2k]
+  double* d_coef = nullptr;     // [k][2] minimal-residual coefficients
+  double* d_scales = nullptr;   // [k][2] (|b_j|, sigma_j)
   ~ttn_sweep() {
     (void)hipFree(fit_scratch);
+    (void)hipFree(d_pair2);
+    (void)hipFree(d_shift2);
+    (void)hipFree(d_coef);
+    (void)hipFree(d_scales);
     for (auto& s : src) {
       for (void* p : s.mem) (void)hipFree(p);
       (void)hipFree(s.d_tgt);
@@ -126,6 +143,79 @@ ttn_envs* make_envs(const ttn_tree* t, const ttn_block* bra, const ttn_ttno* op,
     }
   }
   return e;
+}
+
+#define HIPCHK(ctx, e)                                                                 \
+  do {                                                                                 \
+    hipError_t _e = (e);                                                               \
+    if (_e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(_e));   \
+  } while (0)
+
+bool als_shape(const ttn_sweep* sw) {
+  return sw->henv && sw->src.size() == 1 && sw->src[0].op == nullptr && sw->src[0].n == sw->k;
+}
+
+// local right-hand sides b_j = <y_j-environment | phi_s(j)> at node u (identity environments)
+ttn_status local_rhs(ttn_sweep* sw, int u, void* b) {
+  auto& s = sw->src[0];
+  return heff_apply_rows(sw->ctx, sw->t, nullptr, s.envs, u, sw->k, nullptr, s.d_src, nullptr, sw->k, nullptr, nullptr,
+                         s.blk->ptr[u], s.blk->k, b, TTN_HEFF_NO_SHIFT, sw->compute);
+}
+
+// diag(H_eff) - s_j at node u
+ttn_status local_diag(ttn_sweep* sw, int u, void* dg) {
+  return heff_apply_block(sw->ctx, sw->t, sw->op, sw->henv, u, sw->k, nullptr, nullptr, sw->shift, nullptr, nullptr, 0,
+                          dg, TTN_HEFF_DIAG, sw->compute == TTN_BF16 ? TTN_F32 : sw->compute);
+}
+
+// LEARNED local step: y_D = b / d, y_L = MLP tiles, y_u = a y_D + c y_L with
+// (a, c) minimising the local residual of the shifted system.
+ttn_status learned_step(ttn_sweep* sw, int u, const ttn_solve_opts* opts, void* b, void* dg, void* cand, void* img) {
+  ttn_ctx* ctx = sw->ctx;
+  const int k = sw->k, ct = sw->ct;
+  const int64_t n = sw->y->size[u];
+  const size_t es = ct == 0 ? 8 : 4;
+  if (!opts->mlp_params) return api_fail(ctx, TTN_E_ARG, "LEARNED needs MLP parameters");
+  if (opts->mlp_compute != TTN_BF16 && opts->mlp_compute != TTN_F32)
+    return api_fail(ctx, TTN_E_DTYPE, "MLP computes in BF16 or FP32");
+  void* yD = cand;
+  void* yL = (char*)cand + (size_t)k * n * es;
+  HIPCHK(ctx, launch_diag_solve(ct, b, dg, yD, n * k, ctx->stream));
+  // network inference in groups of states that fit the workspace:
+  // per tile row 4x256 activations + 128 features + 64 outputs (FP32)
+  const int64_t ntiles = (n + 63) / 64;
+  const int64_t row_bytes = (4 * 256 + 128 + 64) * 4;
+  const int64_t cap_rows = std::min<int64_t>((int64_t)(ctx->ws_bytes / row_bytes), INT32_MAX / 1024);
+  if (cap_rows < ntiles) return api_fail(ctx, TTN_E_WORKSPACE, "workspace too small for the learned preconditioner");
+  const int g = (int)std::max<int64_t>(1, std::min<int64_t>(k, cap_rows / ntiles));
+  float* acts = (float*)ctx->ws;
+  for (int z0 = 0; z0 < k; z0 += g) {
+    const int gz = std::min(g, k - z0);
+    const int64_t rows = ntiles * gz;
+    float* X = acts + rows * 1024;
+    float* Yn = X + rows * 128;
+    HIPCHK(ctx, launch_features(ct, (const char*)b + (size_t)z0 * n * es, (const char*)dg + (size_t)z0 * n * es, n, gz,
+                                sw->d_scales + 2 * z0, X, ctx->stream));
+    ttn_status r = ttn_mlp_forward(ctx, opts->mlp_params, (int32_t)rows, X, Yn, acts, (ttn_dtype)opts->mlp_compute);
+    if (r != TTN_OK) return r;
+    HIPCHK(ctx, launch_untile(ct, Yn, n, gz, sw->d_scales + 2 * z0, (char*)yL + (size_t)z0 * n * es, ctx->stream));
+  }
+  // images of both candidates in one batched H_eff launch over 2k states
+  const double* sh2 = nullptr;
+  if (sw->shift) {
+    HIPCHK(ctx, launch_gather_coef(sw->shift, sw->d_pair2, 2 * k, sw->d_shift2, ctx->stream));
+    sh2 = sw->d_shift2;
+  }
+  ttn_status r = heff_apply_block(ctx, sw->t, sw->op, sw->henv, u, 2 * k, sw->d_pair2, nullptr, sh2, nullptr, cand,
+                                  2 * k, img, TTN_HEFF_APPLY, sw->compute);
+  if (r != TTN_OK) return r;
+  HIPCHK(ctx, launch_mr2(ct, img, (char*)img + (size_t)k * n * es, b, n, k, sw->d_coef, ctx->stream));
+  HIPCHK(ctx, launch_mr2_combine(ct, yD, yL, sw->d_coef, sw->y->ptr[u], n, k, ctx->stream));
+  if (opts->learned_coef &&
+      hipMemcpyAsync(opts->learned_coef, sw->d_coef, (size_t)2 * k * 8, hipMemcpyDeviceToDevice, ctx->stream) !=
+          hipSuccess)
+    return api_fail(ctx, TTN_E_DEVICE, "copy of the combination coefficients failed");
+  return TTN_OK;
 }
 
 ttn_status update_envs_across(ttn_sweep* sw, int u, int v) {
@@ -271,7 +361,35 @@ ttn_status ttn_sweep_create(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
     delete sw;
     return api_fail(ctx, TTN_E_DEVICE, "allocation failed");
   }
+  {
+    std::vector<int32_t> pair2(2 * sw->k);
+    for (int i = 0; i < 2 * sw->k; ++i) pair2[i] = i % sw->k;
+    if (!dmalloc(&sw->d_pair2, pair2.size() * 4) || !dmalloc(&sw->d_shift2, (size_t)2 * sw->k * 8) ||
+        !dmalloc(&sw->d_coef, (size_t)2 * sw->k * 8) || !dmalloc(&sw->d_scales, (size_t)2 * sw->k * 8) ||
+        hipMemcpy(sw->d_pair2, pair2.data(), pair2.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      delete sw;
+      return api_fail(ctx, TTN_E_DEVICE, "allocation failed");
+    }
+  }
   *out = sw;
+  return TTN_OK;
+}
+
+ttn_status ttn_sweep_harvest(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, float* X, float* T, double* scales) {
+  if (!ctx || !sw || sw->ctx != ctx || !X || !T || !scales) return api_fail(ctx, TTN_E_ARG, "bad harvest arguments");
+  if (node < 0 || node >= sw->t->n) return api_fail(ctx, TTN_E_ARG, "bad node");
+  if (!als_shape(sw)) return api_fail(ctx, TTN_E_ARG, "harvest needs an ALS sweep");
+  const int k = sw->k;
+  const size_t es = sw->ct == 0 ? 8 : 4;
+  const int64_t n = sw->y->size[node];
+  void* b = sw->vec;
+  void* dg = (char*)sw->vec + (size_t)k * sw->nmax * es;
+  ttn_status r = local_rhs(sw, node, b);
+  if (r != TTN_OK) return r;
+  r = local_diag(sw, node, dg);
+  if (r != TTN_OK) return r;
+  HIPCHK(ctx, launch_features(sw->ct, b, dg, n, k, scales, X, ctx->stream));
+  HIPCHK(ctx, launch_targets(sw->ct, sw->y->ptr[node], n, k, scales, T, ctx->stream));
   return TTN_OK;
 }
 
@@ -318,22 +436,25 @@ ttn_status sweep_step(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, int32_t next, c
   void* y_u = sw->y->ptr[u];
   ttn_status r = TTN_OK;
   const int mode = opts->mode;
-  if (mode == TTN_SOLVE_MINRES || mode == TTN_SOLVE_DIAG) {
-    if (!sw->henv || sw->src.size() != 1 || sw->src[0].op != nullptr || sw->src[0].n != k)
+  if (mode == TTN_SOLVE_MINRES || mode == TTN_SOLVE_DIAG || mode == TTN_SOLVE_LEARNED) {
+    if (!als_shape(sw))
       return api_fail(ctx, TTN_E_ARG, "ALS sweep needs an operator and one identity source term per state");
-    auto& s = sw->src[0];
     // local right-hand side b_j = (y_j, phi_s(j)) identity environment contracted with phi_u
     void* b = vbuf(0);
-    r = heff_apply_rows(ctx, t, nullptr, s.envs, u, k, nullptr, s.d_src, nullptr, k, nullptr, nullptr, s.blk->ptr[u],
-                        s.blk->k, b, TTN_HEFF_NO_SHIFT, sw->compute);
+    r = local_rhs(sw, u, b);
     if (r != TTN_OK) return r;
-    if (mode == TTN_SOLVE_DIAG) {
+    if (mode == TTN_SOLVE_DIAG || mode == TTN_SOLVE_LEARNED) {
       void* dg = vbuf(1);
-      r = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, nullptr, 0, dg,
-                           TTN_HEFF_DIAG, sw->compute == TTN_BF16 ? TTN_F32 : sw->compute);
+      r = local_diag(sw, u, dg);
       if (r != TTN_OK) return r;
-      hipError_t e = launch_diag_solve(ct, b, dg, y_u, n * k, ctx->stream);
-      if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+      if (mode == TTN_SOLVE_DIAG) {
+        hipError_t e = launch_diag_solve(ct, b, dg, y_u, n * k, ctx->stream);
+        if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+      } else {
+        // candidates [2k][n] span vbuf(2..3), their images vbuf(4..5)
+        r = learned_step(sw, u, opts, b, dg, vbuf(2), vbuf(4));
+        if (r != TTN_OK) return r;
+      }
     } else {
       if (opts->maxiter < 0 || !(opts->rtol >= 0)) return api_fail(ctx, TTN_E_ARG, "bad MINRES options");
       void *v = vbuf(1), *vp = vbuf(2), *p = vbuf(3), *d1 = vbuf(4), *d2 = vbuf(5);
@@ -394,7 +515,7 @@ ttn_status sweep_step(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, int32_t next, c
         if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
       }
     }
-  } else if (mode != 3) {
+  } else if (mode != TTN_SOLVE_SKIP) {
     return api_fail(ctx, TTN_E_ARG, "unknown solve mode");
   }
   if (next >= 0) {

@@ -305,15 +305,18 @@ class TTNEigensolver:
             self.shift_d.copy_(torch.from_numpy(shifts))
             self._copy_rows(self.Y, 0, self.B, 0, k)
             self._sw_ii.init(root)
+            col = []
             for _ in range(opts.sweeps):
-                ttn.run_sweep(self._sw_ii, self.gt, ttn.SOLVE_MINRES, opts.minres_maxiter, opts.minres_rtol)
+                ttn.run_sweep(self._sw_ii, self.gt, ttn.SOLVE_MINRES, opts.minres_maxiter, opts.minres_rtol,
+                              collect=col)
             ttn.block_normalize_node(ctx, self.Y, root)
             self._copy_rows(self.B, 0, self.Y, 0, k)
             if big:
                 self._cluster_rr(big, opts)
             lam = self.rayleigh_quotients(self.B, idx).cpu().numpy()
             self.lam_d.copy_(torch.from_numpy(lam))
-            rec = {"iter": it, "t": time.perf_counter() - t_start, "lam": lam + self.zpe}
+            rec = {"iter": it, "t": time.perf_counter() - t_start, "lam": lam + self.zpe,
+                   "minres_iters": {int(u): int(t.max().item()) for u, t in col}}
             self.history.append(rec)
             if log:
                 log(rec)
@@ -381,3 +384,36 @@ class TTNEigensolver:
         Sm = self._assemble(sv, [a * k + b for a, b in zip(ia, ib)], [b * k + a for a, b in zip(ia, ib)], k * k)
         ev, V, rank = ttn.rayleigh_ritz(self.ctx, Hm.view(1, k, k), Sm.view(1, k, k), [k], k, drop_tol)
         return ev[0].cpu().numpy() + self.zpe
+
+
+class MixedEigensolver:
+    """Mixed-precision form: block LOBPCG with FP32 storage and FP32 (or
+    BF16) matrix-core contractions as the warm start, then the block is
+    promoted to FP64 and refined by FP64 iterations (LOBPCG and / or inverse
+    iteration) whose Rayleigh quotients, Gram matrices, Rayleigh-Ritz and
+    shifted solves are all FP64 — the FP32 phase only has to get the
+    eigenvectors close, the FP64 phase recovers full accuracy."""
+
+    def __init__(self, ctx: ttn.Context, tree, model, D: int, k: int, low: str = "fp32"):
+        self.lo = TTNEigensolver(ctx, tree, model, D, k, precision=low)
+        self.hi = TTNEigensolver(ctx, tree, model, D, k, precision="fp64")
+        self.k = k
+        self.history: List[dict] = []
+
+    def load_block(self, states):
+        self.lo.load_block(states)
+
+    def promote(self):
+        """Copy the x and p parts of the low-precision basis into the FP64
+        solver (a cast, on the device) and continue from there."""
+        k = self.k
+        for u in range(self.lo.gt.n):
+            self.hi.B.t[u].copy_(self.lo.B.t[u].to(torch.float64))
+        self.hi.lam_d.copy_(self.lo.lam_d)
+        self.hi.shift_d.copy_(self.lo.shift_d)
+        self.hi._opts = self.lo._opts
+        self.hi._have_p = self.lo._have_p
+        self.hi._it = self.lo._it
+        self.hi._t0 = self.lo._t0
+        # refresh the Rayleigh quotients in FP64
+        self.hi.lam_d.copy_(self.hi.rayleigh_quotients(self.hi.B, list(range(k))))

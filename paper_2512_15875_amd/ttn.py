@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libttn.so")
 
 F64, F32, BF16 = 0, 1, 2
 HEFF_APPLY, HEFF_NO_SHIFT, HEFF_DIAG, HEFF_ACCUM = 0, 1, 2, 4
-SOLVE_MINRES, SOLVE_DIAG, SOLVE_FIT, SOLVE_SKIP = 0, 1, 2, 3
+SOLVE_MINRES, SOLVE_DIAG, SOLVE_FIT, SOLVE_SKIP, SOLVE_LEARNED = 0, 1, 2, 3, 4
 
 _lib = None
 
@@ -65,6 +65,13 @@ _SIGS = {
     "ttn_ctx_profile": [_P, _I],
     "ttn_ctx_flops": [_P, C.POINTER(C.c_double), _I],
     "ttn_ctx_profile_report": [_P, C.c_char_p, C.c_int64, C.POINTER(C.c_int64)],
+    "ttn_mlp_forward": [_P, _P, _I, _P, _P, _P, C.c_int],
+    "ttn_mlp_backward": [_P, _P, _I, _P, _P, _P, _P, C.c_int],
+    "ttn_mlp_loss": [_P, _I, _P, _P, _P, _P],
+    "ttn_mlp_adam": [_P, _P, _P, _P, _P, C.c_float, C.c_float, C.c_float, C.c_float, _I],
+    "ttn_precond_features": [_P, _I, C.c_int64, C.c_int, _P, _P, _P, _P],
+    "ttn_precond_targets": [_P, _I, C.c_int64, C.c_int, _P, _P, _P],
+    "ttn_sweep_harvest": [_P, _P, _I, _P, _P, _P],
 }
 
 
@@ -83,6 +90,8 @@ def lib():
         L.ttn_last_error.restype = C.c_char_p
         L.ttn_version.argtypes = []
         L.ttn_version.restype = C.c_char_p
+        L.ttn_mlp_num_params.argtypes = []
+        L.ttn_mlp_num_params.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -341,7 +350,8 @@ def sop_build(tree: Tree, node_mode: Sequence[int], omega, dims, monomials, coef
 
 
 class SolveOpts(C.Structure):
-    _fields_ = [("mode", C.c_int32), ("maxiter", C.c_int32), ("rtol", C.c_double)]
+    _fields_ = [("mode", C.c_int32), ("maxiter", C.c_int32), ("rtol", C.c_double), ("mlp_params", C.c_void_p),
+                ("mlp_compute", C.c_int32), ("pad_", C.c_int32), ("learned_coef", C.c_void_p)]
 
 
 class Sweep:
@@ -370,9 +380,15 @@ class Sweep:
     def init(self, centre: int):
         _check(lib().ttn_sweep_init(self.h, centre), self.ctx)
 
-    def step(self, node: int, nxt: int, mode: int, maxiter: int = 0, rtol: float = 0.0, iters=None, resid=None):
-        o = SolveOpts(mode, maxiter, rtol)
+    def step(self, node: int, nxt: int, mode: int, maxiter: int = 0, rtol: float = 0.0, iters=None, resid=None,
+             mlp: Optional[torch.Tensor] = None, mlp_compute: int = BF16, learned_coef=None):
+        o = SolveOpts(mode, maxiter, rtol, None if mlp is None else mlp.data_ptr(), mlp_compute, 0,
+                      None if learned_coef is None else learned_coef.data_ptr())
         _check(lib().sweep_step(self.ctx.h, self.h, node, nxt, C.byref(o), _ptr(iters), _ptr(resid)), self.ctx)
+
+    def harvest(self, node: int, X: torch.Tensor, T: torch.Tensor, scales: torch.Tensor):
+        """Training pairs of the current local problems at `node` (see ttn_sweep_harvest)."""
+        _check(lib().ttn_sweep_harvest(self.ctx.h, self.h, node, _ptr(X), _ptr(T), _ptr(scales)), self.ctx)
 
     def __del__(self):
         try:
@@ -394,16 +410,30 @@ def euler_tour(tree: Tree):
     return out
 
 
-def run_sweep(sw: Sweep, tree: Tree, mode: int, maxiter: int = 0, rtol: float = 0.0, iters=None, resid=None):
+def run_sweep(sw: Sweep, tree: Tree, mode: int, maxiter: int = 0, rtol: float = 0.0, iters=None, resid=None,
+              collect=None, mlp=None, mlp_compute: int = BF16, on_solved=None):
     """One sweep: a depth-first Euler tour from the root; a node is solved on
-    its first visit, later visits only move the orthogonality centre."""
+    its first visit, later visits only move the orthogonality centre.
+    collect: optional list receiving (node, iters tensor) per local solve.
+    on_solved(u): optional callback after a node's local solve, before the
+    centre moves on (harvesting reads the local problem there)."""
     tour = euler_tour(tree)
     seen = set()
     for t, u in enumerate(tour):
         nxt = tour[t + 1] if t + 1 < len(tour) else -1
         m = mode if u not in seen else SOLVE_SKIP
+        if on_solved is not None and m != SOLVE_SKIP:
+            sw.step(u, -1, m, maxiter, rtol, iters, resid, mlp, mlp_compute)
+            on_solved(u)
+            m, nxt_solve = SOLVE_SKIP, nxt
+            sw.step(u, nxt_solve, m)
+        elif collect is not None and m == SOLVE_MINRES:
+            it = torch.zeros(sw.target.k, dtype=torch.int32, device="cuda")
+            sw.step(u, nxt, m, maxiter, rtol, it, resid)
+            collect.append((u, it))
+        else:
+            sw.step(u, nxt, m, maxiter, rtol, iters, resid, mlp, mlp_compute)
         seen.add(u)
-        sw.step(u, nxt, m, maxiter, rtol, iters, resid)
 
 
 def ctx_flops(ctx: Context, reset: bool = False) -> float:
@@ -443,3 +473,43 @@ def vec_scale(ctx: Context, x: torch.Tensor, alpha: float, y: torch.Tensor):
 
 def version() -> str:
     return lib().ttn_version().decode()
+
+
+# ---------------------------------------------------------------- learned local preconditioner
+
+MLP_IN, MLP_HID, MLP_OUT, MLP_TILE = 128, 256, 64, 64
+
+
+def mlp_num_params() -> int:
+    return int(lib().ttn_mlp_num_params())
+
+
+def mlp_forward(ctx: Context, params: torch.Tensor, X: torch.Tensor, Y: torch.Tensor, acts=None, compute: int = BF16):
+    _check(lib().ttn_mlp_forward(ctx.h, _ptr(params), X.shape[0], _ptr(X), _ptr(Y), _ptr(acts), compute), ctx)
+
+
+def mlp_backward(ctx: Context, params: torch.Tensor, X: torch.Tensor, acts: torch.Tensor, dY: torch.Tensor,
+                 grads: torch.Tensor, compute: int = BF16):
+    _check(lib().ttn_mlp_backward(ctx.h, _ptr(params), X.shape[0], _ptr(X), _ptr(acts), _ptr(dY), _ptr(grads),
+                                  compute), ctx)
+
+
+def mlp_loss(ctx: Context, Y: torch.Tensor, T: torch.Tensor, dY: torch.Tensor, loss: torch.Tensor):
+    _check(lib().ttn_mlp_loss(ctx.h, Y.shape[0], _ptr(Y), _ptr(T), _ptr(dY), _ptr(loss)), ctx)
+
+
+def mlp_adam(ctx: Context, params, m, v, grads, lr: float, step: int, beta1: float = 0.9, beta2: float = 0.999,
+             eps: float = 1e-8):
+    _check(lib().ttn_mlp_adam(ctx.h, _ptr(params), _ptr(m), _ptr(v), _ptr(grads), lr, beta1, beta2, eps, step), ctx)
+
+
+def precond_features(ctx: Context, b: torch.Tensor, d: torch.Tensor, scales: torch.Tensor, X: torch.Tensor):
+    k, n = b.shape
+    st = F64 if b.dtype == torch.float64 else F32
+    _check(lib().ttn_precond_features(ctx.h, k, n, st, _ptr(b), _ptr(d), _ptr(scales), _ptr(X)), ctx)
+
+
+def precond_targets(ctx: Context, y: torch.Tensor, scales: torch.Tensor, T: torch.Tensor):
+    k, n = y.shape
+    st = F64 if y.dtype == torch.float64 else F32
+    _check(lib().ttn_precond_targets(ctx.h, k, n, st, _ptr(y), _ptr(scales), _ptr(T)), ctx)
