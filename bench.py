@@ -34,11 +34,46 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}  # dense MFMA TFLOP/s (vendor)
+HBM_TBS = 8.0  # HBM3E TB/s (vendor)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2512_15875_amd", "csrc", "gemm.hip")
 
 
-def make_solver(api, ctx, workload: str, precision: str, k: int, D: int):
+def gemm_source_hash() -> str:
+    import hashlib
+    return hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when there is none for this kernel or the GEMM source changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("traffic|"):
+            _, kern, h, val = line.rstrip("\n").split("|")
+            rec[kern] = (h, float(val))
+    if kernel not in rec or rec[kernel][0] != gemm_source_hash():
+        return None
+    return rec[kernel][1]
+
+
+def calibrate_copy():
+    """A plain device copy of known size (for scaling FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+    n = 64 << 20  # 64 Mi floats = 256 MiB each way
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
+
+
+def make_problem(workload: str, k: int, D: int):
     import workloads as wl
-    from paper_2512_15875_amd.solver import TTNEigensolver
 
     if workload == "c2":
         model = wl.make_config_model("c2")
@@ -51,33 +86,141 @@ def make_solver(api, ctx, workload: str, precision: str, k: int, D: int):
         tree = wl.mps_tree(model.dims, 2)
     bonds = wl.bond_dims(tree, D)
     x0 = wl.initial_block(tree, bonds, model.omega, model.dims, k, model.seed + 17)
+    return model, tree, x0
+
+
+def make_solver(api, ctx, workload: str, precision: str, k: int, D: int):
+    from paper_2512_15875_amd.solver import TTNEigensolver
+
+    model, tree, x0 = make_problem(workload, k, D)
     s = TTNEigensolver(ctx, tree, model, D=D, k=k, precision=precision)
     s.load_block(x0)
     return s, model, tree
 
 
-def time_to_all_states(api, ctx, precision: str, tol: float = 1e-3, max_iter: int = 12):
+def time_to_all_states(api, ctx, precision: str, tol: float = 1e-3, max_iter: int = 12, switch_tol: float = 1e-2):
     """Solver start (block on the device) to the first LOBPCG iteration whose
     Rayleigh quotients all lie within tol of the exact levels (6-mode
-    workload, MPS, D=8, k=10)."""
+    workload, MPS, D=8, k=10).  precision "mixed": FP32 LOBPCG until the
+    largest change of a Rayleigh quotient between iterations drops below
+    switch_tol, then promotion to FP64 and FP64 LOBPCG."""
     import torch
-    from paper_2512_15875_amd.solver import LobpcgOpts
+    from paper_2512_15875_amd.solver import LobpcgOpts, MixedEigensolver
 
     # exact normal-mode levels stored with the oracle runs (tests/golden/make_golden.py)
     gold = json.load(open(os.path.join(ROOT, "tests", "golden", "c1_oracle_runs.json")))
-    s, model, tree = make_solver(api, ctx, "c1", precision, 10, 8)
     ref = np.array(gold["exact"]) + gold["zpe"]
+    opts = LobpcgOpts(n_iter=max_iter)
+    if precision == "mixed":
+        model, tree, x0 = make_problem("c1", 10, 8)
+        ms = MixedEigensolver(ctx, tree, model, D=8, k=10, low="fp32")
+        ms.load_block(x0)
+        s = ms.lo
+    else:
+        s, model, tree = make_solver(api, ctx, "c1", precision, 10, 8)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s.lobpcg_start(LobpcgOpts(n_iter=max_iter))
-    hit = None
+    s.lobpcg_start(opts)
+    prev = None
     for it in range(max_iter):
         s.lobpcg_step()
         lam = np.sort(s.lam_d.cpu().numpy() + s.zpe)
         if np.max(np.abs(lam - ref)) <= tol:
-            hit = (it + 1, time.perf_counter() - t0, float(np.max(np.abs(lam - ref))))
-            break
-    return hit
+            return it + 1, time.perf_counter() - t0, float(np.max(np.abs(lam - ref)))
+        if precision == "mixed" and s is ms.lo and prev is not None and np.max(np.abs(lam - prev)) < switch_tol:
+            ms.promote()
+            s = ms.hi
+        prev = lam
+    return None
+
+
+def learned_experiment(args):
+    """The learned local preconditioner end to end: harvest (b, diag - s) -> y
+    pairs from plain FP64 MINRES solves of the ALS preconditioner's systems
+    on seeded force fields of the 12-mode generator (seeds 5000...), train the
+    network on the GPU, then run block LOBPCG on the held-out 12-mode
+    workload (seed 3) with the DIAG, LEARNED and MINRES local maps and report
+    iterations and time against a longer FP64 MINRES-preconditioned run."""
+    import torch
+    import workloads as wl
+    from paper_2512_15875_amd import ttn as api
+    from paper_2512_15875_amd.learned import Trainer, TrainOpts
+    from paper_2512_15875_amd.solver import LobpcgOpts, TTNEigensolver
+
+    ctx = api.Context(0, workspace_bytes=8 << 30)
+    out = {"experiment": "learned local preconditioner", "train": {}, "test": {}}
+    t0 = time.perf_counter()
+    Xs, Ts = [], []
+    for f in range(args.fields):
+        seed = 5000 + f
+        model = wl.make_config_model("c3", seed=seed)
+        tree = wl.fork_tree(model.dims, 4, 1)
+        bonds = wl.bond_dims(tree, args.train_bond)
+        x0 = wl.initial_block(tree, bonds, model.omega, model.dims, args.train_k, seed + 17)
+        s = TTNEigensolver(ctx, tree, model, D=args.train_bond, k=args.train_k, precision="fp64")
+        s.load_block(x0)
+        s.lobpcg_start(LobpcgOpts(n_iter=2))
+        s.lobpcg_step()
+        s.lobpcg_step()
+        X, T = s.harvest(rows_per_node=-(-args.rows_per_field // tree.n), maxiter=args.harvest_maxiter,
+                         rtol=1e-10, seed=seed)
+        Xs.append(X)
+        Ts.append(T)
+        del s
+        print(f"field {seed}: {X.shape[0]} pairs ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    X = torch.cat(Xs)
+    T = torch.cat(Ts)
+    t_h = time.perf_counter() - t0
+    tr = Trainer(ctx, seed=0)
+    t1 = time.perf_counter()
+    hist = tr.fit(X, T, TrainOpts(epochs=args.epochs, batch=4096, lr=1e-3),
+                  log=lambda r: print(f"  epoch {r['epoch']}: train {r['train_mse']:.4e} val {r['val_mse']:.4e} "
+                                      f"(DIAG alone {r['val_mse_diag']:.4e})", file=sys.stderr, flush=True))
+    ctx.sync()
+    n_pairs = int(X.shape[0])
+    del X, T, Xs, Ts
+    out["train"] = {"fields": args.fields, "pairs": n_pairs, "bond": args.train_bond, "k": args.train_k,
+                    "harvest_s": round(t_h, 1), "train_s": round(time.perf_counter() - t1, 1),
+                    "final": hist[-1]}
+    np.save(os.path.join(args.out_dir, "learned_params.npy"), tr.p.cpu().numpy())
+
+    # held-out test: LOBPCG on the 12-mode workload (seed 3)
+    model = wl.make_config_model("c3")
+    tree = wl.fork_tree(model.dims, 4, 1)
+    k, D = args.k or 84, args.bond or 40
+    bonds = wl.bond_dims(tree, D)
+    x0 = wl.initial_block(tree, bonds, model.omega, model.dims, k, model.seed + 17)
+    runs = {}
+    plan = [("reference_fp64_minres", "fp64", "minres", args.ref_iters)] + [
+        (f"{pc}_{args.precision}", args.precision, pc, args.test_iters) for pc in ("diag", "learned", "minres")]
+    for name, prec, pc, iters in plan:
+        s = TTNEigensolver(ctx, tree, model, D=D, k=k, precision=prec)
+        s.load_block(x0)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        s.lobpcg_start(LobpcgOpts(n_iter=iters, precond=pc, mlp=tr.p if pc == "learned" else None))
+        lam_hist, t_hist = [], []
+        for it in range(iters):
+            s.lobpcg_step()
+            lam_hist.append(np.sort(s.lam_d.cpu().numpy() + s.zpe))
+            t_hist.append(time.perf_counter() - ts)
+            print(f"  {name} iteration {it + 1}: {t_hist[-1]:.1f} s, lam[0]={lam_hist[-1][0]:.4f}", file=sys.stderr,
+                  flush=True)
+        runs[name] = (lam_hist, t_hist)
+        print(f"{name}: {iters} iterations in {t_hist[-1]:.1f} s; lam[0]={lam_hist[-1][0]:.4f} "
+              f"lam[-1]={lam_hist[-1][-1]:.4f}", file=sys.stderr, flush=True)
+        del s
+    ref = runs["reference_fp64_minres"][0][-1]
+    for name, (lh, th) in runs.items():
+        err = [float(np.max(np.abs(l - ref))) for l in lh]
+        hit = next((i for i, e in enumerate(err) if e <= 1e-3), None)
+        out["test"][name] = {"iters": len(lh), "seconds": round(th[-1], 2), "s_per_iter": round(th[-1] / len(lh), 3),
+                             "max_err_per_iter": [round(e, 5) for e in err],
+                             "states_within_1e-3_per_iter": [int(np.sum(np.abs(l - ref) <= 1e-3)) for l in lh],
+                             "iters_to_1e-3": None if hit is None else hit + 1,
+                             "seconds_to_1e-3": None if hit is None else round(th[hit], 2)}
+    out["test"]["workload"] = f"12-mode quartic force field (seed 3), fork-4 comb, D={D}, k={k}"
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(s, k: int, budget_s: float = 12.0):
@@ -123,11 +266,33 @@ def main():
     ap.add_argument("--bond", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tts", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true", help="only run the copy kernel used to scale counters")
+    ap.add_argument("--learned", action="store_true", help="run the learned-preconditioner experiment instead")
+    ap.add_argument("--fields", type=int, default=32)
+    ap.add_argument("--train-bond", type=int, default=24)
+    ap.add_argument("--train-k", type=int, default=12)
+    ap.add_argument("--rows-per-field", type=int, default=3000)
+    ap.add_argument("--harvest-maxiter", type=int, default=300)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--test-iters", type=int, default=12)
+    ap.add_argument("--ref-iters", type=int, default=24)
+    ap.add_argument("--out-dir", default=os.path.join(ROOT, "gpurun_out"))
+    ap.add_argument("--gemm-hash", action="store_true", help="print the GEMM source hash and exit")
     args = ap.parse_args()
+    if args.gemm_hash:
+        print(gemm_source_hash())
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (DESIGN.md describes how the "
               "hot path would shard)", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    if args.learned:
+        os.makedirs(args.out_dir, exist_ok=True)
+        learned_experiment(args)
+        return
     k = args.k or (50 if args.workload == "c2" else 84)
     D = args.bond or (24 if args.workload == "c2" else 40)
 
@@ -160,35 +325,42 @@ def main():
     ms = (t1 - t0) * 1e3 / args.steps
     value = flops / (t1 - t0) / 1e9
 
-    # dominant contraction stage of one more step, timed with HIP events on the library stream
+    # per-kernel totals of one more step, timed with HIP events on the library stream
     api.profile(ctx, True)
     s.lobpcg_step()
     rep = api.profile_report(ctx)
     api.profile(ctx, False)
     by_kernel = {}
-    for key, st, kern, cnt, tms, fl, *_ in rep:
-        a = by_kernel.setdefault(kern, [0, 0.0, 0.0])
+    for key, st, kern, cnt, tms, fl, Mm, Nn, Kk, nz, by in rep:
+        a = by_kernel.setdefault(kern, [0, 0.0, 0.0, 0.0])
         a[0] += cnt
         a[1] += tms
         a[2] += fl
+        a[3] += by
     for r in sorted(rep, key=lambda r: -r[4])[:12]:
-        key, st, kern, cnt, tms, fl, Mm, Nn, Kk, nz = r
+        key, st, kern, cnt, tms, fl, Mm, Nn, Kk, nz, by = r
         print(f"  stage {key}#{st} {kern} M={Mm} N={Nn} K={Kk} items={nz} launches={cnt}: {tms:.1f} ms, "
-              f"{fl / tms / 1e9:.1f} TFLOP/s", file=sys.stderr)
-    by_class = {}
-    for key, st, kern, cnt, tms, fl, Mm, Nn, Kk, nz in rep:
-        cls = key.split(":")[0] + (":H" if key.split(":")[2] == "1" else ":I") + f":{kern.split('<')[1].split(',')[1].strip()}x{kern.split(',')[2].strip()}"
-        a = by_class.setdefault(cls, [0, 0.0, 0.0])
-        a[0] += cnt
-        a[1] += tms
-        a[2] += fl
-    for cls, (cnt, tms, fl) in sorted(by_class.items(), key=lambda kv: -kv[1][1])[:10]:
-        print(f"  class {cls}: {cnt} launches {tms:.1f} ms {fl / tms / 1e9:.1f} TFLOP/s", file=sys.stderr)
-    dkern, (dcnt, dms, dfl) = max(by_kernel.items(), key=lambda kv: kv[1][1])
-    achieved = dfl / (dms * 1e-3) / 1e12
+              f"{fl / tms / 1e9:.1f} TFLOP/s, {by / tms / 1e6:.0f} GB/s", file=sys.stderr)
+    for kern, (cnt, tms, fl, by) in sorted(by_kernel.items(), key=lambda kv: -kv[1][1])[:8]:
+        print(f"  kernel {kern}: {cnt} launches {tms:.1f} ms {fl / tms / 1e9:.1f} TFLOP/s "
+              f"{by / tms / 1e6:.0f} GB/s intensity {fl / max(by, 1):.1f} flop/B", file=sys.stderr)
+    dkern, (dcnt, dms, dfl, dby) = max(by_kernel.items(), key=lambda kv: kv[1][1])
     tot_ms = sum(v[1] for v in by_kernel.values())
-    print(f"dominant kernel {dkern}: {dcnt} launches, {dms:.1f} ms total ({dms / dcnt:.4f} ms avg), "
-          f"{achieved:.2f} TFLOP/s; all contraction stages {tot_ms:.1f} ms", file=sys.stderr, flush=True)
+    peak_tf = PEAK[args.precision]
+    ridge = peak_tf * 1e12 / (HBM_TBS * 1e12)
+    if dfl / max(dby, 1.0) >= ridge:
+        roof = {"bound": "mfma", "achieved": round(dfl / (dms * 1e-3) / 1e12, 3), "peak": peak_tf,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": round(dby / (dms * 1e-3) / 1e9, 1), "peak": HBM_TBS * 1e3,
+                "unit": "GB/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["traffic"] = measured_traffic(dkern)
+    roof.update({"kernel": dkern, "launches": dcnt, "avg_ms": round(dms / dcnt, 5),
+                 "algorithmic_flop_per_launch": dfl / dcnt, "algorithmic_bytes_per_launch": dby / dcnt,
+                 "share_of_contraction_time": round(dms / tot_ms, 3)})
+    print(f"dominant kernel {dkern}: {dcnt} launches, {dms:.1f} ms total ({dms / dcnt:.4f} ms avg); all "
+          f"contraction stages {tot_ms:.1f} ms", file=sys.stderr, flush=True)
 
     workload_name = ("64-mode coupled oscillators + 200 cubic terms, binary leaf-only tree (127 nodes)"
                      if args.workload == "c2" else
@@ -210,13 +382,11 @@ def main():
                                f"preconditioner 2 sweeps x MINRES<=10, 3k-subspace Gram + Rayleigh-Ritz, fitted "
                                f"recombination)",
                    "precision": args.precision, "gflop_per_step": round(flops / args.steps / 1e9, 2)},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[args.precision],
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK[args.precision], 4), "traffic": None,
-                     "kernel": dkern, "launches": dcnt, "avg_ms": round(dms / dcnt, 5)},
+        "roofline": roof,
     }
     if not args.no_tts:
         tts = {}
-        for prec in ("fp64", "fp32"):
+        for prec in ("fp64", "fp32", "mixed"):
             c2 = api.Context(0, workspace_bytes=1 << 30)
             hit = time_to_all_states(api, c2, prec)
             tts[prec] = None if hit is None else {"iters": hit[0], "seconds": round(hit[1], 3),

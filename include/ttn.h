@@ -187,7 +187,8 @@ ttn_status rayleigh_ritz(ttn_ctx* ctx, int32_t batch, const int32_t* m, int32_t 
  * better preconditioners as future work in its outlook): the MLP of
  * ttn_mlp_forward maps the tile features of (b, diag(H_eff) - s_j) to a
  * candidate y_L; the DIAG solution y_D stays the fallback and the judge: the
- * local result is the minimal-residual combination a y_D + c y_L (2x2 least
+ * local result is the minimal-residual combination a y_D + c y_L, y_L the
+ * network's correction (2x2 least
  * squares on |(H_eff - s_j)(a y_D + c y_L) - b|, FP64), and c = 0 whenever
  * that system is singular or not finite, so a local step never leaves a
  * larger residual than the DIAG step scaled by its own best factor. */
@@ -292,7 +293,9 @@ ttn_status ttn_sop_destroy(ttn_sop* s);
 /* Per-stage timing: with profiling on, every contraction stage launch is
  * bracketed by HIP events on the context stream.  The report (synchronises
  * the stream, then clears the records) is text, one line per (plan, stage):
- * "plan-key|stage|kernel|launches|total_ms|algorithmic_flops|M|N|K|batch_items".  `needed`
+ * "plan-key|stage|kernel|launches|total_ms|algorithmic_flops|M|N|K|batch_items|compulsory_bytes"
+ * (compulsory bytes: every batched operand read once per item, shared operands
+ * once, the output written once and read when accumulating).  `needed`
  * receives the size including the terminating NUL; the text is written to
  * `buf` and then cleared only when cap >= needed (call once with buf NULL to
  * size the buffer). */
@@ -315,8 +318,8 @@ ttn_status ttn_ctx_profile_report(ttn_ctx* ctx, char* buf, int64_t cap, int64_t*
  *
  * Features of state j's tile t: [b_tile / |b_j|, (d_tile) / sigma_j] with
  * d = diag(H_eff) - s_j, sigma_j = mean |d| over the node, zero past the
- * vector's end; the network output is the correction tile in units of
- * |b_j| / sigma_j. */
+ * vector's end; the network output is the correction to the DIAG step b / d
+ * in units of |b_j| / sigma_j (a zero output leaves the DIAG step). */
 int64_t ttn_mlp_num_params(void);
 
 /* Y[n][64] = MLP(X[n][128]); acts (nullable): float[4][n][256] receives the
@@ -340,10 +343,11 @@ ttn_status ttn_mlp_adam(ttn_ctx* ctx, float* params, float* m, float* v, const f
  * (|b_j|, sigma_j). */
 ttn_status ttn_precond_features(ttn_ctx* ctx, int32_t k, int64_t n, ttn_dtype storage, const void* b, const void* d,
                                 double* scales, float* X);
-/* Training targets: the solution tiles y[k][n] in network units
- * (y * sigma_j / |b_j|), T[k * ceil(n/64)][64]. */
-ttn_status ttn_precond_targets(ttn_ctx* ctx, int32_t k, int64_t n, ttn_dtype storage, const void* y,
-                               const double* scales, float* T);
+/* Training targets: the correction of the solution tiles y[k][n] over the
+ * DIAG step, in network units ((y - b / d) * sigma_j / |b_j|, 0 where d = 0),
+ * T[k * ceil(n/64)][64]; scales from ttn_precond_features. */
+ttn_status ttn_precond_targets(ttn_ctx* ctx, int32_t k, int64_t n, ttn_dtype storage, const void* y, const void* b,
+                               const void* d, const double* scales, float* T);
 /* Training pairs of the current local problems of a sweep at `node` (the
  * sweep's orthogonality centre): features of (b_j, diag(H_eff) - s_j) into
  * X[k * ceil(n/64)][128] and targets of the current local tensors (the

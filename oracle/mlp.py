@@ -13,7 +13,8 @@ future work, and this network is one.  What it computes:
 * network: x -> silu(x W1 + b1) -> silu(. W2 + b2) -> . W3 + b3, widths
   128 -> 256 -> 256 -> 64, silu(z) = z / (1 + exp(-z)); parameters packed
   row-major as W1[128][256], b1, W2[256][256], b2, W3[256][64], b3;
-* output: the correction tile in units of |b_j| / sigma_j;
+* output: the correction to the DIAG step b / d, in units of |b_j| / sigma_j
+  (training targets (y - b/d) sigma_j / |b_j| for a MINRES solution y);
 * loss: mean squared error over all outputs; optimiser: Adam with bias
   correction;
 * local step (LEARNED): y_D = b / d (the diagonal preconditioner), y_L the
@@ -124,14 +125,16 @@ def features(b: np.ndarray, d: np.ndarray):
     return np.concatenate([bp.reshape(nt, T_TILE), dp.reshape(nt, T_TILE)], axis=1), (nb, sg)
 
 
-def targets(y: np.ndarray, scales) -> np.ndarray:
-    """Solution tiles in network units: y * sigma / |b|."""
+def targets(y: np.ndarray, b: np.ndarray, d: np.ndarray, scales) -> np.ndarray:
+    """Training target of a solution y: its correction over the DIAG step in
+    network units, (y - b / d) * sigma / |b| (0 where d = 0)."""
     nb, sg = scales
     n = y.size
     nt = -(-n // T_TILE)
     yp = np.zeros(nt * T_TILE)
     if nb > 0:
-        yp[:n] = y * sg / nb
+        yd = np.divide(b, d, out=np.zeros(n), where=d != 0)
+        yp[:n] = (y - yd) * sg / nb
     return yp.reshape(nt, T_TILE)
 
 

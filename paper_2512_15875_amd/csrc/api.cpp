@@ -138,6 +138,12 @@ ttn_status exec_plan(ttn_ctx* ctx, const Plan& P, int ct, const std::vector<OpAd
         rec->step = (int)s;
         rec->kernel = gemm_kernel_name(ct, st.g);
         rec->flops = st.flops * cnt;
+        {
+          const double mk = (double)st.g.M * st.g.K, kn = (double)st.g.K * st.g.N, mn = (double)st.g.M * st.g.N;
+          const double per = (A.shared ? 0.0 : mk) + (B.shared ? 0.0 : kn) +
+                             mn * (1.0 + (e.accum ? 1.0 : 0.0) + (e.D.base ? 1.0 : 0.0));
+          rec->bytes = (double)es * (per * cnt + (A.shared ? mk : 0.0) + (B.shared ? kn : 0.0));
+        }
         rec->M = st.g.M;
         rec->N = st.g.N;
         rec->K = st.g.K;
@@ -272,7 +278,7 @@ bool build_env_net(const ttn_tree* t, const ttn_ttno* op, const ttn_block* bra, 
     add_tensor(net.in, el, ed, 1, net.dims);
     key << ":" << ed[0] << "x" << ed[1] << "x" << ed[2];
   }
-  key << ":" << bra->bond(u, v) << "," << ket->bond(u, v) << ":d" << d;
+  key << ":" << bra->bond(u, v) << "," << env->em(u, v) << "," << ket->bond(u, v) << ":d" << d;
   std::vector<int> ol{3 * iv, 3 * iv + 1, 3 * iv + 2};
   std::vector<int> od{env->eb(u, v), env->em(u, v), env->ea(u, v)};
   out_layout(ol, od, net.out_lab, net.out_str);
@@ -862,7 +868,7 @@ ttn_status ttn_ctx_profile_report(ttn_ctx* ctx, char* buf, int64_t cap, int64_t*
   struct Agg {
     std::string kernel;
     int64_t count = 0;
-    double ms = 0, flops = 0;
+    double ms = 0, flops = 0, bytes = 0;
     int M = 0, N = 0, K = 0;
     int64_t nz = 0;
   };
@@ -875,6 +881,7 @@ ttn_status ttn_ctx_profile_report(ttn_ctx* ctx, char* buf, int64_t cap, int64_t*
     a.count += 1;
     a.ms += ms;
     a.flops += r.flops;
+    a.bytes += r.bytes;
     a.M = r.M;
     a.N = r.N;
     a.K = r.K;
@@ -887,7 +894,7 @@ ttn_status ttn_ctx_profile_report(ttn_ctx* ctx, char* buf, int64_t cap, int64_t*
   for (auto& kv : agg)
     o << kv.first.first << "|" << kv.first.second << "|" << kv.second.kernel << "|" << kv.second.count << "|"
       << kv.second.ms << "|" << kv.second.flops << "|" << kv.second.M << "|" << kv.second.N << "|" << kv.second.K
-      << "|" << kv.second.nz << "\n";
+      << "|" << kv.second.nz << "|" << kv.second.bytes << "\n";
   ctx->prof_text += o.str();
   const std::string& s = ctx->prof_text;
   *needed = (int64_t)s.size() + 1;

@@ -197,6 +197,7 @@ struct ttn_prof_rec {
   int step = 0;        // stage index in the plan
   std::string kernel;  // kernel instantiation
   double flops = 0;    // algorithmic flops of this launch
+  double bytes = 0;    // compulsory bytes of this launch (batched operands once per item, shared ones once)
   int M = 0, N = 0, K = 0, nz = 0;
   hipEvent_t a = nullptr, b = nullptr;
 };

@@ -131,9 +131,11 @@ __global__ void feat_kernel(const T* b, const T* d, int64_t n, int ntiles, const
   X[e] = v;
 }
 
-// target tiles of a solution y in network units: y * sigma / |b|
+// target tiles in network units: the correction to the DIAG step,
+// (y - b / d) * sigma / |b| (zero past the end and where d = 0)
 template <typename T>
-__global__ void target_kernel(const T* y, int64_t n, int ntiles, const double* scales, float* Yt, int nz) {
+__global__ void target_kernel(const T* y, const T* b, const T* d, int64_t n, int ntiles, const double* scales, float* Yt,
+                              int nz) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t per = (int64_t)ntiles * 64;
   if (e >= per * nz) return;
@@ -141,7 +143,12 @@ __global__ void target_kernel(const T* y, int64_t n, int ntiles, const double* s
   const int64_t i = e - (int64_t)z * per;
   const double nb = scales[2 * z], sg = scales[2 * z + 1];
   float v = 0.0f;
-  if (i < n && nb > 0) v = (float)((double)y[(int64_t)z * n + i] * sg / nb);
+  if (i < n && nb > 0) {
+    const int64_t o = (int64_t)z * n + i;
+    const double dd = (double)d[o];
+    const double yd = dd != 0.0 ? (double)b[o] / dd : 0.0;
+    v = (float)(((double)y[o] - yd) * sg / nb);
+  }
   Yt[e] = v;
 }
 
@@ -253,14 +260,15 @@ hipError_t launch_features(int ctype, const void* b, const void* d, int64_t n, i
   }
   return hipGetLastError();
 }
-hipError_t launch_targets(int ctype, const void* y, int64_t n, int nz, const double* scales, float* Yt, hipStream_t s) {
+hipError_t launch_targets(int ctype, const void* y, const void* b, const void* d, int64_t n, int nz,
+                          const double* scales, float* Yt, hipStream_t s) {
   const int ntiles = (int)((n + 63) / 64);
   if (ctype == 0)
     hipLaunchKernelGGL(target_kernel<double>, dim3(nb256((int64_t)ntiles * 64 * nz)), dim3(256), 0, s,
-                       (const double*)y, n, ntiles, scales, Yt, nz);
+                       (const double*)y, (const double*)b, (const double*)d, n, ntiles, scales, Yt, nz);
   else
     hipLaunchKernelGGL(target_kernel<float>, dim3(nb256((int64_t)ntiles * 64 * nz)), dim3(256), 0, s,
-                       (const float*)y, n, ntiles, scales, Yt, nz);
+                       (const float*)y, (const float*)b, (const float*)d, n, ntiles, scales, Yt, nz);
   return hipGetLastError();
 }
 hipError_t launch_untile(int ctype, const float* Yn, int64_t n, int nz, const double* scales, void* y, hipStream_t s) {

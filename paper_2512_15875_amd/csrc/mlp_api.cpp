@@ -20,7 +20,8 @@ hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, 
                        int step, hipStream_t s);
 hipError_t launch_features(int ctype, const void* b, const void* d, int64_t n, int nz, double* scales, float* X,
                            hipStream_t s);
-hipError_t launch_targets(int ctype, const void* y, int64_t n, int nz, const double* scales, float* Yt, hipStream_t s);
+hipError_t launch_targets(int ctype, const void* y, const void* b, const void* d, int64_t n, int nz,
+                          const double* scales, float* Yt, hipStream_t s);
 
 // C[M][N] (+)= op(A) op(B), row-major; ta: A stored [K][M]; tb: B stored [N][K]
 ttn_status dense_gemm(ttn_ctx* ctx, int ct, int M, int N, int K, const float* A, bool ta, const float* B, bool tb,
@@ -182,11 +183,12 @@ ttn_status ttn_precond_features(ttn_ctx* ctx, int32_t k, int64_t n, ttn_dtype st
   return TTN_OK;
 }
 
-ttn_status ttn_precond_targets(ttn_ctx* ctx, int32_t k, int64_t n, ttn_dtype storage, const void* y,
-                               const double* scales, float* T) {
-  if (!ctx || !y || !scales || !T || k < 0 || n < 1) return api_fail(ctx, TTN_E_ARG, "bad target arguments");
+ttn_status ttn_precond_targets(ttn_ctx* ctx, int32_t k, int64_t n, ttn_dtype storage, const void* y, const void* b,
+                               const void* d, const double* scales, float* T) {
+  if (!ctx || !y || !b || !d || !scales || !T || k < 0 || n < 1)
+    return api_fail(ctx, TTN_E_ARG, "bad target arguments");
   if (k == 0) return TTN_OK;
-  HIPL(ctx, launch_targets(storage == TTN_F64 ? 0 : 1, y, n, k, scales, T, ctx->stream));
+  HIPL(ctx, launch_targets(storage == TTN_F64 ? 0 : 1, y, b, d, n, k, scales, T, ctx->stream));
   return TTN_OK;
 }
 

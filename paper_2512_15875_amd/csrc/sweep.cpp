@@ -30,7 +30,8 @@ hipError_t launch_seg_sum(int ctype, const void* S, const int32_t* ptr, const in
 hipError_t launch_axpy_rows(int ctype, const void* x, void* y, int64_t n, hipStream_t s);
 hipError_t launch_features(int ctype, const void* b, const void* d, int64_t n, int nz, double* scales, float* X,
                            hipStream_t s);
-hipError_t launch_targets(int ctype, const void* y, int64_t n, int nz, const double* scales, float* Yt, hipStream_t s);
+hipError_t launch_targets(int ctype, const void* y, const void* b, const void* d, int64_t n, int nz,
+                          const double* scales, float* Yt, hipStream_t s);
 hipError_t launch_untile(int ctype, const float* Yn, int64_t n, int nz, const double* scales, void* y, hipStream_t s);
 hipError_t launch_mr2(int ctype, const void* Pd, const void* Pl, const void* b, int64_t n, int nz, double* coef,
                       hipStream_t s);
@@ -389,7 +390,7 @@ ttn_status ttn_sweep_harvest(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, float* X
   r = local_diag(sw, node, dg);
   if (r != TTN_OK) return r;
   HIPCHK(ctx, launch_features(sw->ct, b, dg, n, k, scales, X, ctx->stream));
-  HIPCHK(ctx, launch_targets(sw->ct, sw->y->ptr[node], n, k, scales, T, ctx->stream));
+  HIPCHK(ctx, launch_targets(sw->ct, sw->y->ptr[node], b, dg, n, k, scales, T, ctx->stream));
   return TTN_OK;
 }
 

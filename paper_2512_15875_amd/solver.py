@@ -33,6 +33,9 @@ class LobpcgOpts:
     fit_sweeps: int = 2
     drop_tol: float = 1e-12
     resid_tol: Optional[float] = None
+    precond: str = "minres"           # local map of the ALS preconditioner: "minres", "diag" or "learned"
+    mlp: Optional[torch.Tensor] = None  # learned map parameters (device FP32)
+    mlp_compute: int = ttn.BF16
 
 
 @dataclasses.dataclass
@@ -212,8 +215,10 @@ class TTNEigensolver:
         # preconditioned residual: (H - s) w = r by ALS
         self._copy_rows(self.Wp, 0, self.R, 0, k)
         self.sw_pre.init(root)
+        mode = {"minres": ttn.SOLVE_MINRES, "diag": ttn.SOLVE_DIAG, "learned": ttn.SOLVE_LEARNED}[opts.precond]
         for _ in range(opts.als_sweeps):
-            ttn.run_sweep(self.sw_pre, self.gt, ttn.SOLVE_MINRES, opts.minres_maxiter, opts.minres_rtol)
+            ttn.run_sweep(self.sw_pre, self.gt, mode, opts.minres_maxiter, opts.minres_rtol, mlp=opts.mlp,
+                          mlp_compute=opts.mlp_compute)
         ttn.block_normalize_node(ctx, self.Wp, root)
         self._copy_rows(self.B, k, self.Wp, 0, k)
         rnorm = torch.sqrt(rn).cpu().numpy()
@@ -257,6 +262,34 @@ class TTNEigensolver:
         lam = self.rayleigh_quotients(self.B, list(range(k)))
         self.lam_d.copy_(lam)
         return True
+
+    def harvest(self, rows_per_node: int, maxiter: int = 300, rtol: float = 1e-10, seed: int = 0):
+        """Training pairs for the learned local map: one ALS sweep of plain
+        MINRES solves (H - s) w = r on the current residual block (the
+        preconditioner's own systems, solved to rtol), recording at each node,
+        right after its solve, the tile features of (b, diag(H_eff) - s) and
+        the solution tiles.  Returns device tensors X [n][128], T [n][64]
+        with up to rows_per_node tile rows per node (sampled)."""
+        k, root = self.k, self.root
+        g = torch.Generator(device="cpu")
+        g.manual_seed(seed)
+        self._copy_rows(self.Wp, 0, self.R, 0, k)
+        self.sw_pre.init(root)
+        xs, ts = [], []
+
+        def on_solved(u):
+            n = int(np.prod(self.Wp.legdims(u)))
+            nt = -(-n // 64)
+            X = torch.empty(k * nt, 128, dtype=torch.float32, device="cuda")
+            T = torch.empty(k * nt, 64, dtype=torch.float32, device="cuda")
+            sc = torch.empty(k, 2, dtype=torch.float64, device="cuda")
+            self.sw_pre.harvest(u, X, T, sc)
+            sel = torch.randperm(k * nt, generator=g)[:rows_per_node].to("cuda")
+            xs.append(X[sel])
+            ts.append(T[sel])
+
+        ttn.run_sweep(self.sw_pre, self.gt, ttn.SOLVE_MINRES, maxiter, rtol, on_solved=on_solved)
+        return torch.cat(xs), torch.cat(ts)
 
     def lobpcg(self, opts: LobpcgOpts, log=None):
         self.lobpcg_start(opts)

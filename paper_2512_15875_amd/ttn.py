@@ -70,7 +70,7 @@ _SIGS = {
     "ttn_mlp_loss": [_P, _I, _P, _P, _P, _P],
     "ttn_mlp_adam": [_P, _P, _P, _P, _P, C.c_float, C.c_float, C.c_float, C.c_float, _I],
     "ttn_precond_features": [_P, _I, C.c_int64, C.c_int, _P, _P, _P, _P],
-    "ttn_precond_targets": [_P, _I, C.c_int64, C.c_int, _P, _P, _P],
+    "ttn_precond_targets": [_P, _I, C.c_int64, C.c_int, _P, _P, _P, _P, _P],
     "ttn_sweep_harvest": [_P, _P, _I, _P, _P, _P],
 }
 
@@ -425,8 +425,7 @@ def run_sweep(sw: Sweep, tree: Tree, mode: int, maxiter: int = 0, rtol: float = 
         if on_solved is not None and m != SOLVE_SKIP:
             sw.step(u, -1, m, maxiter, rtol, iters, resid, mlp, mlp_compute)
             on_solved(u)
-            m, nxt_solve = SOLVE_SKIP, nxt
-            sw.step(u, nxt_solve, m)
+            sw.step(u, nxt, SOLVE_SKIP)
         elif collect is not None and m == SOLVE_MINRES:
             it = torch.zeros(sw.target.k, dtype=torch.int32, device="cuda")
             sw.step(u, nxt, m, maxiter, rtol, it, resid)
@@ -447,15 +446,16 @@ def profile(ctx: Context, on: bool):
 
 
 def profile_report(ctx: Context):
-    """[(plan_key, stage, kernel, launches, total_ms, flops, M, N, K, batch_items)] since the last report."""
+    """[(plan_key, stage, kernel, launches, total_ms, flops, M, N, K, batch_items, bytes)] since the last
+    report (bytes: compulsory bytes, see ttn_ctx_profile_report)."""
     need = C.c_int64()
     _check(lib().ttn_ctx_profile_report(ctx.h, None, 0, C.byref(need)), ctx)
     buf = C.create_string_buffer(int(need.value) + 1024)
     _check(lib().ttn_ctx_profile_report(ctx.h, buf, len(buf), C.byref(need)), ctx)
     out = []
     for line in buf.value.decode().splitlines():
-        k, st, kern, cnt, ms, fl, M, N, K, nz = line.split("|")
-        out.append((k, int(st), kern, int(cnt), float(ms), float(fl), int(M), int(N), int(K), int(nz)))
+        k, st, kern, cnt, ms, fl, M, N, K, nz, by = line.split("|")
+        out.append((k, int(st), kern, int(cnt), float(ms), float(fl), int(M), int(N), int(K), int(nz), float(by)))
     return out
 
 
@@ -509,7 +509,8 @@ def precond_features(ctx: Context, b: torch.Tensor, d: torch.Tensor, scales: tor
     _check(lib().ttn_precond_features(ctx.h, k, n, st, _ptr(b), _ptr(d), _ptr(scales), _ptr(X)), ctx)
 
 
-def precond_targets(ctx: Context, y: torch.Tensor, scales: torch.Tensor, T: torch.Tensor):
+def precond_targets(ctx: Context, y: torch.Tensor, b: torch.Tensor, d: torch.Tensor, scales: torch.Tensor,
+                    T: torch.Tensor):
     k, n = y.shape
     st = F64 if y.dtype == torch.float64 else F32
-    _check(lib().ttn_precond_targets(ctx.h, k, n, st, _ptr(y), _ptr(scales), _ptr(T)), ctx)
+    _check(lib().ttn_precond_targets(ctx.h, k, n, st, _ptr(y), _ptr(b), _ptr(d), _ptr(scales), _ptr(T)), ctx)

@@ -121,13 +121,13 @@ def test_features_and_targets_match_oracle(api, ctx, dt):
     T = torch.empty(k * nt, 64, dtype=torch.float32, device="cuda")
     sc = torch.empty(k, 2, dtype=torch.float64, device="cuda")
     api.precond_features(ctx, to_dev(b, tdt), to_dev(d, tdt), sc, X)
-    api.precond_targets(ctx, to_dev(y, tdt), sc, T)
+    api.precond_targets(ctx, to_dev(y, tdt), to_dev(b, tdt), to_dev(d, tdt), sc, T)
     ctx.sync()
     for j in range(k):
         Xr, scr = omlp.features(b[j], d[j])
         assert np.allclose(sc[j].cpu().numpy(), scr, rtol=1e-12, atol=0)
         assert rel_err(X[j * nt:(j + 1) * nt].cpu().numpy(), Xr) < 1e-7
-        assert rel_err(T[j * nt:(j + 1) * nt].cpu().numpy(), omlp.targets(y[j], scr)) < 1e-7
+        assert rel_err(T[j * nt:(j + 1) * nt].cpu().numpy(), omlp.targets(y[j], b[j], d[j], scr)) < 1e-7
 
 
 def test_training_reduces_loss(api, ctx):
@@ -209,7 +209,7 @@ def test_harvest_matches_oracle(api, ctx):
         Xr, scr = omlp.features(b, d)
         assert np.allclose(sc[j].cpu().numpy(), scr, rtol=1e-10, atol=0)
         assert rel_err(X[j * nt:(j + 1) * nt].cpu().numpy(), Xr) < 1e-7
-        assert rel_err(T[j * nt:(j + 1) * nt].cpu().numpy(), omlp.targets(y0[j][r].ravel(), scr)) < 1e-7
+        assert rel_err(T[j * nt:(j + 1) * nt].cpu().numpy(), omlp.targets(y0[j][r].ravel(), b, d, scr)) < 1e-7
 
 
 @pytest.mark.parametrize("local", ["diag", "learned"])

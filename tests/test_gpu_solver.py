@@ -64,3 +64,27 @@ def test_lobpcg_then_inverse_iteration_c1(api, ctx):
     assert np.max(np.abs(theta - ref)) < 1e-4
     exact = np.array(GOLD["exact"]) + zpe
     assert np.max(np.abs(theta - exact)) < 1e-3
+
+
+def test_two_hamiltonians_on_one_context(api, ctx):
+    """Contraction plans are cached per context by shape: two force fields
+    whose trees differ only in some operator bonds must each get their own
+    plans (regression: the environment-update key once missed the outgoing
+    operator bond).  Rayleigh quotients against the oracle."""
+    from oracle import ttn as ottn
+    from oracle import ttno as ottno
+    from paper_2512_15875_amd.solver import TTNEigensolver
+    for seed in (5000, 5001):
+        m = wl.make_config_model("c3", seed=seed)
+        tree = wl.fork_tree(m.dims, 4, 1)
+        bonds = wl.bond_dims(tree, 6)
+        x0 = wl.initial_block(tree, bonds, m.omega, m.dims, 2, seed + 17)
+        s = TTNEigensolver(ctx, tree, m, D=6, k=2, precision="fp64")
+        s.load_block(x0)
+        lam = s.rayleigh_quotients(s.B, [0, 1]).cpu().numpy()
+        W = ottno.build_ttno(tree, m)
+        for j in range(2):
+            x = ottn.canonicalize(tree, x0[j], tree.root)
+            ref = ottn.expectation(tree, x, W, x) / ottn.expectation(tree, x, None, x)
+            # both sides work in the zero-point-shifted frame
+            assert abs(lam[j] - ref) < 1e-8 * max(1.0, abs(ref)), (seed, j)

@@ -128,9 +128,11 @@ def test_features_invariants(n):
     assert np.count_nonzero(bf[n:]) == 0 and np.count_nonzero(df[n:]) == 0
     assert abs(nb - np.linalg.norm(b)) < 1e-12
     y = rng.normal(size=n)
-    Tt = mlp.targets(y, (nb, sg))
+    Tt = mlp.targets(y, b, d, (nb, sg))
     assert Tt.shape == (nt, 64)
-    assert np.max(np.abs(mlp.untile(Tt, n, (nb, sg)) - y)) < 1e-13
+    # the target is the correction over the DIAG step: DIAG + untiled target = y
+    assert np.max(np.abs(b / d + mlp.untile(Tt, n, (nb, sg)) - y)) < 1e-12
+    assert np.count_nonzero(mlp.targets(b / d, b, d, (nb, sg))) == 0
 
 
 def _spd(n, seed):
