@@ -223,6 +223,127 @@ def learned_experiment(args):
     print(json.dumps(out), flush=True)
 
 
+def ensemble_experiment(args):
+    """Batched serving-style ensemble: independent seeded Hamiltonians (even
+    seeds: coupled oscillators on binary trees, odd: quartic force fields on
+    fork-4 combs), each run for a few FP32 LOBPCG iterations plus FP64
+    refinement.  Concurrent (own stream per member, thread pool, graph-replayed
+    sweeps, autotuned tiles) against one-at-a-time (one stream, eager, default
+    tiles); both run twice and the second (warm) run is timed."""
+    import torch
+    import workloads as wl
+    from paper_2512_15875_amd.ensemble import Ensemble, EnsembleOpts
+
+    from paper_2512_15875_amd import ttn as api
+    from paper_2512_15875_amd.solver import build_ttno
+
+    members = wl.ensemble_members(args.members, D_range=(args.ens_dmin, args.ens_dmax),
+                                  k_range=(args.ens_kmin, args.ens_kmax), L_range=(8, args.ens_lmax))
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for m in members:  # host TTNO compilation, once per member
+        model = m["model"]
+        tree = wl.binary_tree(model.dims) if m["kind"] == "c4-binary" else wl.fork_tree(model.dims, 4, 1)
+        m["ttno"] = build_ttno(api.Tree(tree.parent, tree.phys), tree, model)
+        log(f"TTNO of member {m['seed']} ({m['kind']}, L={m['L']}): {time.perf_counter() - t0:.1f} s")
+    out = {"experiment": "ensemble", "members": len(members),
+           "recipe": f"seeds 4000-{4000 + len(members) - 1}, L 8-{args.ens_lmax}, D {args.ens_dmin}-{args.ens_dmax}, "
+                     f"k {args.ens_kmin}-{args.ens_kmax}, {args.ens_iters} FP32 LOBPCG iterations + 1 FP64"}
+    res = {}
+    for name, conc in (("one_at_a_time", False), ("concurrent", True)):
+        o = EnsembleOpts(low="fp32", iters_low=args.ens_iters, iters_fp64=1, concurrent=conc, threads=8,
+                         graphs=conc, autotune=conc, workspace_bytes=512 << 20)
+        t0 = time.perf_counter()
+        ens = Ensemble(members, o, log=log)
+        t_setup = time.perf_counter() - t0
+        lam1, dt1, fl1 = ens.run()
+        print(f"{name}: first run {dt1:.2f} s", file=sys.stderr, flush=True)
+        lam2, dt2, fl2 = ens.run()
+        print(f"{name}: second run {dt2:.2f} s ({fl2 / dt2 / 1e12:.2f} TFLOP/s)", file=sys.stderr, flush=True)
+        res[name] = {"setup_s": round(t_setup, 2), "first_run_s": round(dt1, 3), "warm_run_s": round(dt2, 3),
+                     "algorithmic_tflop": round(fl2 / 1e12, 3), "tflop_per_s": round(fl2 / dt2 / 1e12, 3)}
+        res[name + "_lam"] = lam2
+        ens.close()
+        del ens
+        torch.cuda.synchronize()
+    dev = max(float(np.max(np.abs(a - b))) for a, b in zip(res["one_at_a_time_lam"], res["concurrent_lam"]))
+    out["one_at_a_time"] = res["one_at_a_time"]
+    out["concurrent"] = res["concurrent"]
+    out["speedup"] = round(res["one_at_a_time"]["warm_run_s"] / res["concurrent"]["warm_run_s"], 3)
+    out["max_eigenvalue_difference_cm-1"] = dev
+    print(json.dumps(out), flush=True)
+
+
+def tts_experiment(args):
+    """Time to all states at 1e-3 cm^-1 on a large workload: plain FP64 block
+    LOBPCG for ref_iters iterations (its last iterate is the reference), then
+    the mixed form (FP32 iterations until the largest change of a Rayleigh
+    quotient between iterations drops below switch_tol, promotion, FP64
+    iterations) from the same initial block; both timed from solver start."""
+    import torch
+    from paper_2512_15875_amd import ttn as api
+    from paper_2512_15875_amd.solver import LobpcgOpts, MixedEigensolver, TTNEigensolver, build_ttno
+
+    wl_name = args.workload
+    k = args.k or (50 if wl_name == "c2" else 84)
+    D = args.bond or (24 if wl_name == "c2" else 40)
+    model, tree, x0 = make_problem(wl_name, k, D)
+    ctx = api.Context(0, workspace_bytes=8 << 30)
+    ttno = build_ttno(api.Tree(tree.parent, tree.phys), tree, model)
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
+    # plain FP64
+    s = TTNEigensolver(ctx, tree, model, D=D, k=k, precision="fp64", ttno=ttno)
+    s.load_block(x0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.lobpcg_start(LobpcgOpts(n_iter=args.ref_iters))
+    plain = []
+    for it in range(args.ref_iters):
+        s.lobpcg_step()
+        plain.append((time.perf_counter() - t0, np.sort(s.lam_d.cpu().numpy() + s.zpe)))
+        log(f"  plain fp64 iteration {it + 1}: {plain[-1][0]:.1f} s")
+    del s
+    ref = plain[-1][1]
+    # mixed
+    ms = MixedEigensolver(ctx, tree, model, D=D, k=k, low=args.precision, ttno=ttno)
+    ms.load_block(x0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cur = ms.lo
+    cur.lobpcg_start(LobpcgOpts(n_iter=args.ref_iters))
+    mixed, prev, switched = [], None, None
+    for it in range(args.ref_iters):
+        cur.lobpcg_step()
+        lam = np.sort(cur.lam_d.cpu().numpy() + cur.zpe)
+        mixed.append((time.perf_counter() - t0, lam, "lo" if cur is ms.lo else "fp64"))
+        log(f"  mixed iteration {it + 1} ({mixed[-1][2]}): {mixed[-1][0]:.1f} s, max err {np.max(np.abs(lam - ref)):.4f}")
+        if np.max(np.abs(lam - ref)) <= 1e-3 and cur is ms.hi:
+            break
+        if cur is ms.lo and prev is not None and np.max(np.abs(lam - prev)) < args.switch_tol:
+            ms.promote()
+            cur = ms.hi
+            switched = it + 1
+        prev = lam
+
+    def first_hit(traj):
+        for i, t in enumerate(traj):
+            if np.max(np.abs(t[1] - ref)) <= 1e-3 and (len(t) < 3 or t[2] == "fp64"):
+                return i + 1, round(t[0], 2)
+        return None, None
+
+    pi, pt = first_hit(plain)
+    mi, mt = first_hit(mixed)
+    out = {"experiment": "time to all states", "workload": f"{wl_name}, D={D}, k={k}", "tol_cm-1": 1e-3,
+           "reference": f"plain FP64 LOBPCG iterate {args.ref_iters}",
+           "plain_fp64": {"iters": pi, "seconds": pt, "s_per_iter": round(plain[-1][0] / len(plain), 3),
+                          "max_err_per_iter": [round(float(np.max(np.abs(t[1] - ref))), 5) for t in plain]},
+           "mixed": {"low": args.precision, "switch_at_iter": switched, "iters": mi, "seconds": mt,
+                     "max_err_per_iter": [round(float(np.max(np.abs(t[1] - ref))), 5) for t in mixed]}}
+    if pt and mt:
+        out["speedup"] = round(pt / mt, 3)
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(s, k: int, budget_s: float = 12.0):
     """The FP64 oracle's H_eff apply at the heaviest node, timed on the host."""
     from oracle import ttn as ottn
@@ -277,6 +398,16 @@ def main():
     ap.add_argument("--test-iters", type=int, default=12)
     ap.add_argument("--ref-iters", type=int, default=24)
     ap.add_argument("--out-dir", default=os.path.join(ROOT, "gpurun_out"))
+    ap.add_argument("--ensemble", action="store_true", help="run the many-Hamiltonian ensemble experiment instead")
+    ap.add_argument("--members", type=int, default=64)
+    ap.add_argument("--ens-dmin", type=int, default=12)
+    ap.add_argument("--ens-dmax", type=int, default=24)
+    ap.add_argument("--ens-kmin", type=int, default=10)
+    ap.add_argument("--ens-kmax", type=int, default=32)
+    ap.add_argument("--ens-iters", type=int, default=3)
+    ap.add_argument("--ens-lmax", type=int, default=32)
+    ap.add_argument("--tts", action="store_true", help="run the plain-vs-mixed time-to-all-states experiment")
+    ap.add_argument("--switch-tol", type=float, default=0.05)
     ap.add_argument("--gemm-hash", action="store_true", help="print the GEMM source hash and exit")
     args = ap.parse_args()
     if args.gemm_hash:
@@ -288,6 +419,12 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.tts:
+        tts_experiment(args)
+        return
+    if args.ensemble:
+        ensemble_experiment(args)
         return
     if args.learned:
         os.makedirs(args.out_dir, exist_ok=True)

@@ -232,6 +232,8 @@ ttn_status ttn_sweep_create(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
                             const int32_t* const* term_source, const double* const* term_coef,
                             const double* shift, ttn_dtype compute, ttn_sweep** out);
 ttn_status ttn_sweep_init(ttn_sweep* sw, int32_t centre);
+/* Synchronises the sweep's context stream, then frees the sweep.  A sweep
+ * keeps a pointer to its context: destroy every sweep before its context. */
 ttn_status ttn_sweep_destroy(ttn_sweep* sw);
 
 /* One local step of a sweep at `node` (the current orthogonality centre):
@@ -300,10 +302,34 @@ ttn_status ttn_sop_destroy(ttn_sop* s);
  * `buf` and then cleared only when cap >= needed (call once with buf NULL to
  * size the buffer). */
 ttn_status ttn_ctx_profile(ttn_ctx* ctx, int32_t on);
+/* Tile autotuner.  on = 1: the first launch of every contraction stage that
+ * overwrites its output runs each tile shape (128x128, 64x64, 128x64,
+ * 64x128, 32x64, 64x32, 32x32) twice, times the second run with HIP events (synchronising), and keeps the
+ * fastest for the plan; on = 0 stops tuning new stages (tuned choices stay);
+ * on < 0 leaves the setting.  The log (one line per tuned stage: "plan-key|
+ * stage|M|N|K|items|heuristic->chosen|tile:microseconds...") is copied to buf
+ * when cap >= *needed (needed may be NULL).  Tuning never runs under stream
+ * capture or profiling. */
+ttn_status ttn_ctx_autotune(ttn_ctx* ctx, int32_t on, char* buf, int64_t cap, int64_t* needed);
 /* Algorithmic contraction flops (minimum-order counts of every planned
  * contraction launched on this context) since creation or the last reset. */
 ttn_status ttn_ctx_flops(ttn_ctx* ctx, double* total, int32_t reset);
 ttn_status ttn_ctx_profile_report(ttn_ctx* ctx, char* buf, int64_t cap, int64_t* needed);
+
+/* Sweep executor: n_sweeps sweeps, each a depth-first Euler tour from the
+ * root (children in index order) with the node's local solve on its first
+ * visit and only centre moves on later visits; init_first = 1 rebuilds every
+ * environment toward the root first (ttn_sweep_init).  use_graph = 1 replays
+ * the whole sequence as one HIP graph on the context stream: the first call
+ * with an option set runs eagerly (building plans and tables), the second
+ * captures and launches, later ones replay.  Graphs need a non-null context
+ * stream and are skipped under profiling and for MINRES with maxiter > 25
+ * (host-side convergence checks); the algorithmic flop counter is advanced
+ * by the captured amount on each replay.  Every pointer reachable from the
+ * sweep (blocks, coefficients, shifts, opts' device arrays, iters/resid) must
+ * keep its address between replays. */
+ttn_status ttn_sweep_run(ttn_ctx* ctx, ttn_sweep* sw, const ttn_solve_opts* opts, int32_t n_sweeps,
+                         int32_t init_first, int32_t use_graph, int32_t* iters, double* resid);
 
 /* ------------------------------------------------------------ learned local preconditioner
  *

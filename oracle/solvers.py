@@ -212,18 +212,26 @@ class IIOptions:
     gap: float = 5.0
     drop_tol: float = 1e-12
     dlam_tol: Optional[float] = None  # stop when every |d lambda| < tol
+    monotone: bool = True             # keep a cluster's previous states when its update raised a Rayleigh quotient
+    mono_tol: float = 1e-7            # cm^-1
 
 
 def inverse_iteration(tree, W, xs, lam, opts: IIOptions, history: Optional[list] = None):
     """Block inverse iteration (Alg. block_inverse_iteration), clusters fixed
     from the input Rayleigh quotients, shift = cluster mean, followed by one
-    global Rayleigh-Ritz over all states.  Returns (states, Ritz values)."""
+    global Rayleigh-Ritz over all states.  Returns (states, Ritz values).
+
+    With opts.monotone (a safeguard, not in the paper): at a fixed bond
+    dimension the ALS solve of a nearly singular shifted system can move a
+    state away from its eigenvector, so a cluster whose update raised any
+    Rayleigh quotient by more than mono_tol keeps its previous states."""
     xs = [normalized(tree, x) for x in xs]
     lam = np.array(lam, dtype=np.float64)
     cl = clusters_of(lam, opts.gap)
     for it in range(opts.n_iter):
         old = lam.copy()
         for c in cl:
+            prev = {j: xs[j] for j in c}
             s = float(np.mean(lam[c]))
             for j in c:
                 y = als_solve(tree, W, s, xs[j], xs[j], opts.sweeps, opts.minres_maxiter, opts.minres_rtol)
@@ -240,6 +248,10 @@ def inverse_iteration(tree, W, xs, lam, opts: IIOptions, history: Optional[list]
                     xs[j] = newx[jj]
             for j in c:
                 lam[j] = ttn.expectation(tree, xs[j], W, xs[j])
+            if opts.monotone and max(lam[j] - old[j] for j in c) > opts.mono_tol:
+                for j in c:
+                    xs[j] = prev[j]
+                    lam[j] = old[j]
         if history is not None:
             history.append({"iter": it, "lam": lam.copy()})
         if opts.dlam_tol is not None and np.max(np.abs(lam - old)) < opts.dlam_tol:

@@ -75,7 +75,53 @@ void out_layout(const std::vector<int>& labs, const std::vector<int>& dms, std::
 
 // Execute a plan over batch items [0, nb): inputs[i] addressing, final output
 // addressing and epilogue.  Chunks the batch to the workspace.
-ttn_status exec_plan(ttn_ctx* ctx, const Plan& P, int ct, const std::vector<OpAddr>& inputs, const OpAddr& out,
+// Autotuner: run one stage with every tile shape (the stage overwrites its
+// output, so repeats are harmless), time each with events, keep the fastest.
+ttn_status tune_stage(ttn_ctx* ctx, Plan& P, size_t s, int ct, const OpAddr& A, const OpAddr& B, const OpAddr& C,
+                      const Epilogue& e, int z0, int cnt) {
+  Step& st = P.steps[s];
+  std::vector<int> cand{0, 1, 2, 3, 4, 5, 6};
+  if (splitk_eligible(st.g, ct)) cand.push_back(8);
+  if (narrow_eligible(st.g, ct)) cand.push_back(9);
+  hipEvent_t ev[2];
+  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
+    return fail(ctx, TTN_E_DEVICE, "hipEventCreate failed");
+  const int orig = st.g.tile;
+  int best = orig;
+  float best_ms = 1e30f;
+  std::ostringstream log;
+  log << P.key << "|" << s << "|" << st.g.M << "|" << st.g.N << "|" << st.g.K << "|" << cnt;
+  std::ostringstream times;
+  for (int c : cand) {
+    st.g.tile = c;
+    float ms = 0;
+    for (int rep = 0; rep < 2; ++rep) {  // the first launch warms caches and code
+      (void)hipEventRecord(ev[0], ctx->stream);
+      hipError_t he = launch_gemm(ct, st.g, A, B, C, e, z0, cnt, ctx->d_flag, ctx->stream);
+      (void)hipEventRecord(ev[1], ctx->stream);
+      if (he != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+        return fail(ctx, TTN_E_LAUNCH, "autotune launch failed");
+      }
+      (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+    }
+    times << "|" << c << ":" << (int)(ms * 1000.0f);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  st.g.tile = best;
+  st.tuned = true;
+  log << "|" << orig << "->" << best << times.str() << "\n";
+  ctx->tune_log += log.str();
+  return TTN_OK;
+}
+
+ttn_status exec_plan(ttn_ctx* ctx, Plan& P, int ct, const std::vector<OpAddr>& inputs, const OpAddr& out,
                      const Epilogue& ep, int nb, const std::vector<int64_t>& in_elems, int64_t out_elems,
                      size_t ws_off_bytes = 0) {
   const size_t es = esize(ct);
@@ -130,6 +176,13 @@ ttn_status exec_plan(ttn_ctx* ctx, const Plan& P, int ct, const std::vector<OpAd
       OpAddr C = last ? out : addr(st.out);
       Epilogue e = last ? ep : Epilogue();
       const int cnt = st.batched ? nz : 1;
+      if (ctx->autotune && !st.tuned && !e.accum && !ctx->profile) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(ctx->stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+          ttn_status tr = tune_stage(ctx, P, s, ct, A, B, C, e, st.batched ? z0 : 0, cnt);
+          if (tr != TTN_OK) return tr;
+        }
+      }
       ttn_prof_rec* rec = nullptr;
       if (ctx->profile && ctx->prof.size() < 200000) {
         ctx->prof.emplace_back();
@@ -853,6 +906,16 @@ ttn_status ttn_ctx_flops(ttn_ctx* ctx, double* total, int32_t reset) {
   if (!ctx || !total) return fail(ctx, TTN_E_ARG, "null argument");
   *total = ctx->flops_done;
   if (reset) ctx->flops_done = 0;
+  return TTN_OK;
+}
+
+ttn_status ttn_ctx_autotune(ttn_ctx* ctx, int32_t on, char* buf, int64_t cap, int64_t* needed) {
+  if (!ctx) return fail(nullptr, TTN_E_ARG, "null context");
+  if (on >= 0) ctx->autotune = on != 0;
+  if (needed) {
+    *needed = (int64_t)ctx->tune_log.size() + 1;
+    if (buf && cap >= *needed) std::memcpy(buf, ctx->tune_log.c_str(), ctx->tune_log.size() + 1);
+  }
   return TTN_OK;
 }
 

@@ -447,6 +447,173 @@ __global__ __launch_bounds__(256) void ogemm_wave_kernel(KArgs g) {
   }
 }
 
+// Split-K kernel for skinny products: M, N <= 32 with a long contraction whose
+// operands both run contiguously along k (unit k stride, row offsets multiples
+// of 4 elements: the identity-environment and fitting stages that reduce a
+// whole node tensor to a bond x bond matrix).  One workgroup per batch item;
+// its four waves take interleaved 16-wide k-chunks, every lane loads one
+// 16-byte run of 4 consecutive k per operand row straight from global memory
+// into f32 matrix-core operands (lane group q = l/16 supplies k = 4q + t to the
+// t-th MFMA of a chunk, the same for A and B, so the sum over k is complete),
+// the next chunk's loads are issued before the current chunk's MFMAs, and the
+// four partial 32 x 32 accumulators are summed through LDS.  FP32 storage;
+// the arithmetic is FP32 also for the bf16 compute type.
+__global__ __launch_bounds__(256) void ogemm_splitk_kernel(KArgs g) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int z = blockIdx.x;
+  if (z >= g.nz) return;  // uniform per workgroup, before any barrier
+  const int M = g.M, N = g.N, K = g.K;
+  const float* __restrict__ A = (const float*)g.A.base + batch_off(g.A, z, g.z0, g.flag);
+  const float* __restrict__ B = (const float*)g.B.base + batch_off(g.B, z, g.z0, g.flag);
+  const int r = lane & 15, q = lane >> 4;
+  // operand rows owned by this lane (rows past M / N read row 0 and are zeroed)
+  const bool av0 = r < M, av1 = r + 16 < M, bv0 = r < N, bv1 = r + 16 < N;
+  const float* a0p = A + (av0 ? g.a_om[r] : 0);
+  const float* a1p = A + (av1 ? g.a_om[r + 16] : 0);
+  const float* b0p = B + (bv0 ? g.b_on[r] : 0);
+  const float* b1p = B + (bv1 ? g.b_on[r + 16] : 0);
+  floatx4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+  auto ld = [&](const float* p, bool row_ok, int k) -> floatx4 {
+    // K % 4 == 0: a quad is either wholly inside [0, K) or wholly outside
+    return (row_ok && k < K) ? *(const floatx4*)(p + k) : zero;
+  };
+  int c = wid;
+  floatx4 x0 = ld(a0p, av0, c * 16 + 4 * q), x1 = ld(a1p, av1, c * 16 + 4 * q);
+  floatx4 y0 = ld(b0p, bv0, c * 16 + 4 * q), y1 = ld(b1p, bv1, c * 16 + 4 * q);
+  for (; c * 16 < K; c += 4) {
+    const int kn = (c + 4) * 16 + 4 * q;
+    const floatx4 nx0 = ld(a0p, av0, kn), nx1 = ld(a1p, av1, kn);
+    const floatx4 ny0 = ld(b0p, bv0, kn), ny1 = ld(b1p, bv1, kn);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x0[t], y0[t], acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(x0[t], y1[t], acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x1[t], y0[t], acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(x1[t], y1[t], acc[1][1], 0, 0, 0);
+    }
+    x0 = nx0;
+    x1 = nx1;
+    y0 = ny0;
+    y1 = ny1;
+  }
+  // partial sums of the four waves: red[w][block][i][lane]
+  __shared__ float red[4][4][4][64];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) red[wid][2 * i + j][e][lane] = acc[i][j][e];
+  __syncthreads();
+  // thread -> (block = wid, lane): its 4 output elements
+  const int blk = wid, bi = blk >> 1, bj = blk & 1;
+  float* __restrict__ C = (float*)g.C.base + batch_off(g.C, z, g.z0, g.flag);
+  const float* __restrict__ Dp = g.has_d ? (const float*)g.D.base + batch_off(g.D, z, g.z0, g.flag) : nullptr;
+  const double alpha = g.alpha ? g.alpha[g.z0 + z] : 1.0;
+  const double sh = g.shift ? g.shift[g.z0 + z] : 0.0;
+  const int col = bj * 16 + (lane & 15);
+  const bool cok = col < N;
+  const int cn = cok ? g.c_on[col] : 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int row = bi * 16 + 4 * (lane >> 4) + e;
+    const float v = red[0][blk][e][lane] + red[1][blk][e][lane] + red[2][blk][e][lane] + red[3][blk][e][lane];
+    if (row < M && cok) {
+      const int o = g.c_om[row] + cn;
+      const double dv = Dp ? (double)Dp[o] : (g.d_const ? 1.0 : 0.0);
+      const double cv = g.accum ? (double)C[o] : 0.0;
+      C[o] = (float)(alpha * ((double)v - sh * dv) + cv);
+    }
+  }
+}
+
+// Narrow kernel: tall M, N <= 32 and a short unit-stride contraction
+// (K <= 32), both operands contiguous along k (the first stages of identity
+// environments: one bond of a node tensor contracted with a bond x bond
+// matrix).  One workgroup per batch item; every lane keeps its B fragments
+// (N <= 32 columns x K <= 32) in registers for the whole item, the four waves
+// walk the M rows in 16-row blocks, loading each lane's A row as 16-byte runs
+// of k (next block prefetched before the current block's MFMAs), and write C
+// through the output offset tables.  FP32 arithmetic.
+__global__ __launch_bounds__(256) void ogemm_narrow_kernel(KArgs g) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int z = blockIdx.x;
+  if (z >= g.nz) return;
+  const int M = g.M, N = g.N, K = g.K;
+  const float* __restrict__ A = (const float*)g.A.base + batch_off(g.A, z, g.z0, g.flag);
+  const float* __restrict__ B = (const float*)g.B.base + batch_off(g.B, z, g.z0, g.flag);
+  float* __restrict__ C = (float*)g.C.base + batch_off(g.C, z, g.z0, g.flag);
+  const float* __restrict__ Dp = g.has_d ? (const float*)g.D.base + batch_off(g.D, z, g.z0, g.flag) : nullptr;
+  const double alpha = g.alpha ? g.alpha[g.z0 + z] : 1.0;
+  const double sh = g.shift ? g.shift[g.z0 + z] : 0.0;
+  const int r = lane & 15, q = lane >> 4;
+  const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+  // B fragments: column r (+16), k = 16 h + 4 q .. +3
+  floatx4 bq[2][2];
+  int cn[2];
+  bool cok[2];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const int col = nb * 16 + r;
+    cok[nb] = col < N;
+    cn[nb] = cok[nb] ? g.c_on[col] : 0;
+    const float* bp = B + (cok[nb] ? g.b_on[col] : 0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = 16 * h + 4 * q;
+      bq[nb][h] = (cok[nb] && k < K) ? *(const floatx4*)(bp + k) : zero;
+    }
+  }
+  auto load_a = [&](int mb, floatx4* aq) {
+    const int row = mb * 16 + r;
+    const bool ok = row < M;
+    const float* ap = A + (ok ? g.a_om[row] : 0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = 16 * h + 4 * q;
+      aq[h] = (ok && k < K) ? *(const floatx4*)(ap + k) : zero;
+    }
+  };
+  const int nmb = (M + 15) / 16;
+  floatx4 aq[2], an[2];
+  int mb = wid;
+  if (mb < nmb) load_a(mb, aq);
+  for (; mb < nmb; mb += 4) {
+    if (mb + 4 < nmb) load_a(mb + 4, an);
+    floatx4 acc[2] = {zero, zero};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (16 * h >= K) break;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[h][t], bq[0][h][t], acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[h][t], bq[1][h][t], acc[1], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = mb * 16 + 4 * q + e;
+      if (row >= M) continue;
+      const int cm = g.c_om[row];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        if (!cok[nb]) continue;
+        const int o = cm + cn[nb];
+        const double dv = Dp ? (double)Dp[o] : (g.d_const ? 1.0 : 0.0);
+        const double cv = g.accum ? (double)C[o] : 0.0;
+        C[o] = (float)(alpha * ((double)acc[nb][e] - sh * dv) + cv);
+      }
+    }
+    aq[0] = an[0];
+    aq[1] = an[1];
+  }
+}
+
 static KOp kop(const OpAddr& o, int default_mode) {
   KOp k;
   k.base = o.base;
@@ -517,8 +684,34 @@ static hipError_t launch_wave(const GemmDesc& gd, KArgs& a, int nz, hipStream_t 
   return hipGetLastError();
 }
 
+static bool aligned16(const KOp& o) {
+  return ((uintptr_t)o.base % 16) == 0 && (o.mode == 0 || o.bs % 4 == 0);
+}
+
 template <int CT>
 static hipError_t launch_ct(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s) {
+  if (gd.tile == 8) {
+    if (CT != 0 && splitk_eligible(gd, CT) && aligned16(a.A) && aligned16(a.B)) {
+      a.nz = nz;
+      a.xcd_remap = 0;
+      hipLaunchKernelGGL(ogemm_splitk_kernel, dim3((unsigned)nz), dim3(256), 0, s, a);
+      return hipGetLastError();
+    }
+    GemmDesc g2 = gd;
+    g2.tile = 6;  // operands not 16-byte aligned: the general 32 x 32 tile
+    return launch_ct<CT>(g2, a, nz, s);
+  }
+  if (gd.tile == 9) {
+    if (CT != 0 && narrow_eligible(gd, CT) && aligned16(a.A) && aligned16(a.B)) {
+      a.nz = nz;
+      a.xcd_remap = 0;
+      hipLaunchKernelGGL(ogemm_narrow_kernel, dim3((unsigned)nz), dim3(256), 0, s, a);
+      return hipGetLastError();
+    }
+    GemmDesc g2 = gd;
+    g2.tile = 5;  // operands not 16-byte aligned: the general 64 x 32 tile
+    return launch_ct<CT>(g2, a, nz, s);
+  }
   if (gd.tile == 7) return launch_wave<CT>(gd, a, nz, s);
   if constexpr (CT == 1) {
     if (pick_bk(CT, gd) == 16) return launch_tile<CT, 16>(gd, a, nz, s);
@@ -533,6 +726,8 @@ static int pick_bk(int ctype, const GemmDesc& gd);
 std::string gemm_kernel_name(int ctype, const GemmDesc& gd) {
   static const int bm[] = {128, 64, 128, 64, 32, 64, 32};
   static const int bn[] = {128, 64, 64, 128, 64, 32, 32};
+  if (gd.tile == 8) return "ogemm_splitk_kernel";
+  if (gd.tile == 9) return "ogemm_narrow_kernel";
   if (gd.tile == 7) {
     const int tmw = gd.M <= 16 ? 1 : 2, tnw = gd.N <= 16 ? 1 : 2;
     return "ogemm_wave_kernel<" + std::to_string(ctype == 2 ? 1 : ctype) + ", " + std::to_string(tmw) + ", " +

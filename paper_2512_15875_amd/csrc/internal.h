@@ -39,8 +39,25 @@ struct GemmDesc {
   const int32_t* c_om = nullptr;  // [M]
   const int32_t* c_on = nullptr;  // [N]
   bool a_mfast = false, b_nfast = true;
-  int tile = 0;                   // tile configuration id
+  int tile = 0;                   // tile configuration id (8: split-K skinny kernel, 9: narrow kernel)
+  // host facts about the tables, for the split-K skinny kernel: k offsets are
+  // exactly k (a_ok[k] == k, b_ok[k] == k) and every row (column) offset of A
+  // (B) is a multiple of 4 elements
+  bool k_unit = false;
+  bool rows_al4 = false;
 };
+
+// the split-K skinny kernel (tile 8) applies: M, N <= 32, long unit-stride k (K % 4 == 0)
+inline bool splitk_eligible(const GemmDesc& g, int ctype) {
+  return ctype != 0 && g.M <= 32 && g.N <= 32 && g.K >= 64 && g.K % 4 == 0 && !g.a_mfast && !g.b_nfast &&
+         g.k_unit && g.rows_al4;
+}
+
+// the narrow kernel (tile 9) applies: tall M, N <= 32, short unit-stride k (K <= 32, K % 4 == 0)
+inline bool narrow_eligible(const GemmDesc& g, int ctype) {
+  return ctype != 0 && g.M >= 64 && g.N <= 32 && g.K <= 32 && g.K % 4 == 0 && !g.a_mfast && !g.b_nfast &&
+         g.k_unit && g.rows_al4;
+}
 
 struct Epilogue {
   const double* alpha = nullptr;  // per batch item (indexed by z0+z), null = 1
@@ -98,6 +115,7 @@ struct Step {
   double flops = 0;          // per batch item (or total if both shared)
   bool batched = true;
   int64_t max_a = 0, max_b = 0, max_c = 0;  // largest element offset addressed in A, B, C
+  bool tuned = false;        // tile picked by measurement (autotuner)
 };
 
 struct Plan {
@@ -204,6 +222,8 @@ struct ttn_prof_rec {
 
 struct ttn_ctx {
   bool profile = false;
+  bool autotune = false;  // time every tile shape on a stage's first launch and keep the fastest
+  std::string tune_log;   // "plan-key|stage|M|N|K|items|chosen tile|us per tile..." lines
   double flops_done = 0;  // algorithmic contraction flops launched so far
   std::vector<ttn_prof_rec> prof;
   std::string prof_text;  // aggregated, not yet returned

@@ -187,6 +187,35 @@ std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<in
     live.push_back(l);
   }
   int next_id = (int)in.size();
+  // Lookahead: which step consumes each intermediate, and with which other
+  // operand.  An intermediate stores the legs its consumer contracts last, in
+  // the other operand's order, so both operands of the consumer run
+  // contiguously along k (what the split-K and narrow kernels need).
+  std::map<int, int> consumer_other;           // intermediate id -> id of the other operand of its consumer
+  std::map<int, std::vector<int>> label_set;  // id -> sorted labels
+  {
+    std::vector<int> ids;
+    for (size_t i = 0; i < in.size(); ++i) {
+      ids.push_back((int)i);
+      label_set[(int)i] = ns[i].lab;
+    }
+    int nid = (int)in.size();
+    for (size_t si = 0; si < s.best_seq.size(); ++si) {
+      const int ia = ids[s.best_seq[si].first], ib = ids[s.best_seq[si].second];
+      if (ia >= (int)in.size()) consumer_other[ia] = ib;
+      if (ib >= (int)in.size()) consumer_other[ib] = ia;
+      // output labels: symmetric difference of the operands' labels
+      const auto &xa = label_set[ia], &xb = label_set[ib];
+      std::vector<int> o;
+      std::set_symmetric_difference(xa.begin(), xa.end(), xb.begin(), xb.end(), std::back_inserter(o));
+      label_set[nid] = o;
+      std::vector<int> nx;
+      for (size_t t = 0; t < ids.size(); ++t)
+        if ((int)t != s.best_seq[si].first && (int)t != s.best_seq[si].second) nx.push_back(ids[t]);
+      nx.push_back(nid++);
+      ids = nx;
+    }
+  }
   std::vector<int32_t> all_tabs;
   struct TabRef {
     size_t step;
@@ -288,6 +317,35 @@ std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<in
     } else {
       std::vector<int> ol(ml);
       ol.insert(ol.end(), nl.begin(), nl.end());
+      static const bool lookahead = !getenv("TTN_PLAN_NO_LOOKAHEAD");
+      auto co = consumer_other.find(next_id);
+      if (lookahead && co != consumer_other.end()) {
+        // labels the consumer contracts = shared with its other operand
+        const Live* other = nullptr;
+        for (auto& l : live)
+          if (l.id == co->second) other = &l;
+        std::vector<int> kc;
+        if (other) {
+          // other operand already laid out: its memory order (slowest first)
+          std::vector<int> ord = other->lab;
+          std::stable_sort(ord.begin(), ord.end(),
+                           [&](int x, int y) { return other->str.at(x) > other->str.at(y); });
+          for (int x : ord)
+            if (std::find(ol.begin(), ol.end(), x) != ol.end()) kc.push_back(x);
+        } else {
+          // produced later: ascending label order; that operand will then
+          // follow this one's order
+          for (int x : label_set[co->second])
+            if (std::find(ol.begin(), ol.end(), x) != ol.end()) kc.push_back(x);
+        }
+        if (!kc.empty()) {
+          std::vector<int> re;
+          for (int x : ol)
+            if (std::find(kc.begin(), kc.end(), x) == kc.end()) re.push_back(x);
+          re.insert(re.end(), kc.begin(), kc.end());
+          ol = re;
+        }
+      }
       int64_t acc = 1;
       for (int j = (int)ol.size() - 1; j >= 0; --j) {
         ostr[ol[j]] = acc;
@@ -336,7 +394,17 @@ std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<in
     stp.max_a = vmax(t_am) + vmax(t_ak);
     stp.max_b = vmax(t_bk) + vmax(t_bn);
     stp.max_c = vmax(t_cm) + vmax(t_cn);
-    g.tile = pick_tile(g.M, g.N, g.K, stp.batched ? batch : 1.0);
+    {
+      bool ku = true, al = true;
+      for (int i = 0; i < (int)t_ak.size() && ku; ++i) ku = t_ak[i] == i && t_bk[i] == i;
+      for (int32_t x : t_am) al = al && x % 4 == 0;
+      for (int32_t x : t_bn) al = al && x % 4 == 0;
+      g.k_unit = ku;
+      g.rows_al4 = al;
+    }
+    g.tile = splitk_eligible(g, ctype)   ? 8
+             : narrow_eligible(g, ctype) ? 9
+                                         : pick_tile(g.M, g.N, g.K, stp.batched ? batch : 1.0);
     if (stp.batched) plan->flops_per_item += stp.flops;
     else plan->flops_shared += stp.flops;
     plan->steps.push_back(stp);

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <sstream>
 
 #include "internal.h"
 
@@ -82,7 +83,17 @@ struct ttn_sweep {
   double* d_shift2 = nullptr;   // [2k]
   double* d_coef = nullptr;     // [k][2] minimal-residual coefficients
   double* d_scales = nullptr;   // [k][2] (|b_j|, sigma_j)
+  // sweep executor: Euler tour and captured graphs (one per option set)
+  std::vector<int> tour;
+  struct GraphRec {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
+    double flops = 0;  // algorithmic flops of one replay
+  };
+  std::vector<GraphRec> graphs;
+  std::vector<std::string> warm;  // option sets already run eagerly (plans and tables built)
   ~ttn_sweep() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
     (void)hipFree(fit_scratch);
     (void)hipFree(d_pair2);
     (void)hipFree(d_shift2);
@@ -373,6 +384,97 @@ ttn_status ttn_sweep_create(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
     }
   }
   *out = sw;
+  return TTN_OK;
+}
+
+ttn_status ttn_sweep_run(ttn_ctx* ctx, ttn_sweep* sw, const ttn_solve_opts* opts, int32_t n_sweeps,
+                         int32_t init_first, int32_t use_graph, int32_t* iters_out, double* resid_out) {
+  if (!ctx || !sw || !opts || sw->ctx != ctx || n_sweeps < 0) return api_fail(ctx, TTN_E_ARG, "bad sweep arguments");
+  const ttn_tree* t = sw->t;
+  if (sw->tour.empty()) {
+    // depth-first Euler tour from the root, children in index order
+    std::vector<std::pair<int, size_t>> stk{{t->root, 0}};
+    sw->tour.push_back(t->root);
+    while (!stk.empty()) {
+      auto& top = stk.back();
+      const int u = top.first;
+      if (top.second < t->ch[u].size()) {
+        const int c = t->ch[u][top.second++];
+        sw->tour.push_back(c);
+        stk.push_back({c, 0});
+      } else {
+        stk.pop_back();
+        if (!stk.empty()) sw->tour.push_back(stk.back().first);
+      }
+    }
+  }
+  auto run = [&]() -> ttn_status {
+    if (init_first) {
+      ttn_status r = ttn_sweep_init(sw, t->root);
+      if (r != TTN_OK) return r;
+    }
+    ttn_solve_opts skip = *opts;
+    skip.mode = TTN_SOLVE_SKIP;
+    std::vector<char> seen(t->n);
+    for (int s = 0; s < n_sweeps; ++s) {
+      std::fill(seen.begin(), seen.end(), 0);
+      for (size_t i = 0; i < sw->tour.size(); ++i) {
+        const int u = sw->tour[i];
+        const int nxt = i + 1 < sw->tour.size() ? sw->tour[i + 1] : -1;
+        const ttn_solve_opts* o = seen[u] ? &skip : opts;
+        seen[u] = 1;
+        ttn_status r = sweep_step(ctx, sw, u, nxt, o, iters_out, resid_out);
+        if (r != TTN_OK) return r;
+      }
+    }
+    return TTN_OK;
+  };
+  // graphs: not under profiling (events), not on the legacy null stream, and
+  // not for MINRES runs long enough to take host-side convergence checks
+  const bool capturable = use_graph && !ctx->profile && ctx->stream != nullptr &&
+                          !(opts->mode == TTN_SOLVE_MINRES && opts->maxiter > 25);
+  if (!capturable) return run();
+  std::ostringstream key;
+  key << opts->mode << ":" << opts->maxiter << ":" << opts->rtol << ":" << (const void*)opts->mlp_params << ":"
+      << opts->mlp_compute << ":" << (const void*)opts->learned_coef << ":" << n_sweeps << ":" << init_first << ":"
+      << (const void*)iters_out << ":" << (const void*)resid_out;
+  const std::string k = key.str();
+  for (auto& g : sw->graphs)
+    if (g.key == k) {
+      if (hipGraphLaunch(g.exec, ctx->stream) != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, "graph launch failed");
+      ctx->flops_done += g.flops;
+      return TTN_OK;
+    }
+  if (std::find(sw->warm.begin(), sw->warm.end(), k) == sw->warm.end()) {
+    // first run of this option set: eager, so that every plan, table and
+    // workspace the sweep needs exists before a capture
+    ttn_status r = run();
+    if (r == TTN_OK) sw->warm.push_back(k);
+    return r;
+  }
+  const double f0 = ctx->flops_done;
+  if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return api_fail(ctx, TTN_E_DEVICE, "stream capture could not start");
+  ttn_status r = run();
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(ctx->stream, &graph);
+  if (r != TTN_OK || ec != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    ctx->flops_done = f0;
+    return r != TTN_OK ? r : api_fail(ctx, TTN_E_DEVICE, "stream capture failed");
+  }
+  ttn_sweep::GraphRec rec;
+  rec.key = k;
+  rec.flops = ctx->flops_done - f0;
+  const hipError_t ei = hipGraphInstantiate(&rec.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    ctx->flops_done = f0;
+    return api_fail(ctx, TTN_E_DEVICE, "graph instantiation failed");
+  }
+  sw->graphs.push_back(rec);
+  // the capture recorded the work without running it: run it now
+  if (hipGraphLaunch(rec.exec, ctx->stream) != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, "graph launch failed");
   return TTN_OK;
 }
 

@@ -48,6 +48,8 @@ class IIOpts:
     gap: float = 5.0
     drop_tol: float = 1e-12
     dlam_tol: Optional[float] = None
+    monotone: bool = True   # a cluster whose update raised a Rayleigh quotient keeps its previous states
+    mono_tol: float = 1e-7  # cm^-1
 
 
 def post_order_edges(tree: ttn.Tree):
@@ -64,6 +66,11 @@ def post_order_edges(tree: ttn.Tree):
     return out
 
 
+def build_ttno(gt: ttn.Tree, tree, model):
+    """Site tensors and operator bonds of the model's TTNO (library host compiler)."""
+    return ttn.sop_build(gt, tree.mode, model.omega, model.dims, model.monomials, model.coefs)
+
+
 class TTNEigensolver:
     """GPU block eigensolver for one Hamiltonian on one tree.
 
@@ -74,12 +81,15 @@ class TTNEigensolver:
     """
 
     def __init__(self, ctx: ttn.Context, tree, model, D: int, k: int, precision: str = "fp64",
-                 workspace_pairs: int = 4096):
+                 workspace_pairs: int = 4096, graphs: bool = False, ttno=None,
+                 env_budget_bytes: Optional[int] = None):
         import workloads as wl
         self.ctx, self.k = ctx, k
+        self.graphs = graphs  # replay the sweeps as HIP graphs (needs a non-null context stream)
         self.wtree = tree
         self.gt = ttn.Tree(tree.parent, tree.phys)
-        W, M = ttn.sop_build(self.gt, tree.mode, model.omega, model.dims, model.monomials, model.coefs)
+        # the host compiler's TTNO (or a prebuilt one: (site tensors, operator bonds))
+        W, M = ttno if ttno is not None else build_ttno(self.gt, tree, model)
         self.M = [max(1, m) for m in M]
         self.sdt = ttn.F64 if precision == "fp64" else ttn.F32
         self.compute = {"fp64": ttn.F64, "fp32": ttn.F32, "bf16": ttn.BF16}[precision]
@@ -97,7 +107,13 @@ class TTNEigensolver:
         self.PN = ttn.Block(ctx, self.gt, k, self.bonds, self.sdt)        # recombined p
         self.Y = ttn.Block(ctx, self.gt, k, self.bonds, self.sdt)         # inverse-iteration target
         self.up_edges = post_order_edges(self.gt)
+        # Gram environments are kept for pair_cap pairs at a time; a byte
+        # budget caps it (bigger chunks: fewer, fuller launches)
+        es = 8 if self.sdt == ttn.F64 else 4
+        per_pair = es * sum(self.bonds[u] * (self.M[u] + 1) * self.bonds[u] for (u, _) in post_order_edges(self.gt))
         self.pair_cap = workspace_pairs
+        if env_budget_bytes is not None:
+            self.pair_cap = int(max(16, min(workspace_pairs, env_budget_bytes // max(per_pair, 1))))
         dev = "cuda"
         up_slots = [2 * u for (u, _) in self.up_edges]
         self.genv_H = ttn.Envs(ctx, self.gt, self.pair_cap, self.bonds, self.M, self.bonds, self.sdt, edges=up_slots)
@@ -207,18 +223,14 @@ class TTNEigensolver:
         # residual r_j = H x_j - lambda_j x_j by fitting
         ttn.vec_scale(ctx, self.lam_d, -1.0, self.neglam_d)
         self._copy_rows(self.R, 0, self.B, 0, k)
-        self.sw_res.init(root)
-        for _ in range(opts.fit_sweeps):
-            ttn.run_sweep(self.sw_res, self.gt, ttn.SOLVE_FIT)
+        self.sw_res.run(ttn.SOLVE_FIT, opts.fit_sweeps, init=True, graph=self.graphs)
         rn = torch.zeros(k, dtype=torch.float64, device="cuda")
         ttn.block_node_norms2(ctx, self.R, root, rn)
         # preconditioned residual: (H - s) w = r by ALS
         self._copy_rows(self.Wp, 0, self.R, 0, k)
-        self.sw_pre.init(root)
         mode = {"minres": ttn.SOLVE_MINRES, "diag": ttn.SOLVE_DIAG, "learned": ttn.SOLVE_LEARNED}[opts.precond]
-        for _ in range(opts.als_sweeps):
-            ttn.run_sweep(self.sw_pre, self.gt, mode, opts.minres_maxiter, opts.minres_rtol, mlp=opts.mlp,
-                          mlp_compute=opts.mlp_compute)
+        self.sw_pre.run(mode, opts.als_sweeps, init=True, graph=self.graphs, maxiter=opts.minres_maxiter,
+                        rtol=opts.minres_rtol, mlp=opts.mlp, mlp_compute=opts.mlp_compute)
         ttn.block_normalize_node(ctx, self.Wp, root)
         self._copy_rows(self.B, k, self.Wp, 0, k)
         rnorm = torch.sqrt(rn).cpu().numpy()
@@ -247,13 +259,9 @@ class TTNEigensolver:
         self.cp_d.copy_(Vf[self.ip_gather])
         # p_j = sum_{l >= k} V[l, j] s_l ; x_j = sum_l V[l, j] s_l  (fitted)
         self._copy_rows(self.PN, 0, self.B, k, k)
-        self.sw_p.init(root)
-        for _ in range(opts.fit_sweeps):
-            ttn.run_sweep(self.sw_p, self.gt, ttn.SOLVE_FIT)
+        self.sw_p.run(ttn.SOLVE_FIT, opts.fit_sweeps, init=True, graph=self.graphs)
         self._copy_rows(self.XN, 0, self.B, 0, k)
-        self.sw_x.init(root)
-        for _ in range(opts.fit_sweeps):
-            ttn.run_sweep(self.sw_x, self.gt, ttn.SOLVE_FIT)
+        self.sw_x.run(ttn.SOLVE_FIT, opts.fit_sweeps, init=True, graph=self.graphs)
         ttn.block_normalize_node(ctx, self.PN, root)
         ttn.block_normalize_node(ctx, self.XN, root)
         self._copy_rows(self.B, 0, self.XN, 0, k)
@@ -336,6 +344,8 @@ class TTNEigensolver:
             for c in cl:
                 shifts[c] = float(np.mean(lam[c]))
             self.shift_d.copy_(torch.from_numpy(shifts))
+            if opts.monotone:
+                self._copy_rows(self.B, k, self.B, 0, k)  # previous states (basis rows k..2k are free here)
             self._copy_rows(self.Y, 0, self.B, 0, k)
             self._sw_ii.init(root)
             col = []
@@ -347,8 +357,16 @@ class TTNEigensolver:
             if big:
                 self._cluster_rr(big, opts)
             lam = self.rayleigh_quotients(self.B, idx).cpu().numpy()
+            reverted = []
+            if opts.monotone:
+                for c in cl:
+                    if max(lam[j] - old[j] for j in c) > opts.mono_tol:
+                        for j in c:
+                            self._copy_rows(self.B, j, self.B, k + j, 1)
+                            lam[j] = old[j]
+                        reverted += list(c)
             self.lam_d.copy_(torch.from_numpy(lam))
-            rec = {"iter": it, "t": time.perf_counter() - t_start, "lam": lam + self.zpe,
+            rec = {"iter": it, "t": time.perf_counter() - t_start, "lam": lam + self.zpe, "reverted": reverted,
                    "minres_iters": {int(u): int(t.max().item()) for u, t in col}}
             self.history.append(rec)
             if log:
@@ -397,9 +415,7 @@ class TTNEigensolver:
             coef[torch.tensor(ones_dst, device="cuda")] = 1.0
         self.ci_d.copy_(coef)
         self._copy_rows(self.XN, 0, self.B, 0, k)
-        self._sw_rec.init(root)
-        for _ in range(opts.fit_sweeps):
-            ttn.run_sweep(self._sw_rec, self.gt, ttn.SOLVE_FIT)
+        self._sw_rec.run(ttn.SOLVE_FIT, opts.fit_sweeps, init=True, graph=self.graphs)
         ttn.block_normalize_node(ctx, self.XN, root)
         self._copy_rows(self.B, 0, self.XN, 0, k)
 
@@ -427,9 +443,13 @@ class MixedEigensolver:
     shifted solves are all FP64 — the FP32 phase only has to get the
     eigenvectors close, the FP64 phase recovers full accuracy."""
 
-    def __init__(self, ctx: ttn.Context, tree, model, D: int, k: int, low: str = "fp32"):
-        self.lo = TTNEigensolver(ctx, tree, model, D, k, precision=low)
-        self.hi = TTNEigensolver(ctx, tree, model, D, k, precision="fp64")
+    def __init__(self, ctx: ttn.Context, tree, model, D: int, k: int, low: str = "fp32", ttno=None,
+                 env_budget_bytes: Optional[int] = None):
+        if ttno is None:
+            ttno = build_ttno(ttn.Tree(tree.parent, tree.phys), tree, model)
+        self.lo = TTNEigensolver(ctx, tree, model, D, k, precision=low, ttno=ttno, env_budget_bytes=env_budget_bytes)
+        self.hi = TTNEigensolver(ctx, tree, model, D, k, precision="fp64", ttno=ttno,
+                                 env_budget_bytes=env_budget_bytes)
         self.k = k
         self.history: List[dict] = []
 

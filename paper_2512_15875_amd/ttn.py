@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 from typing import List, Optional, Sequence
 
 import torch
@@ -72,6 +73,8 @@ _SIGS = {
     "ttn_precond_features": [_P, _I, C.c_int64, C.c_int, _P, _P, _P, _P],
     "ttn_precond_targets": [_P, _I, C.c_int64, C.c_int, _P, _P, _P, _P, _P],
     "ttn_sweep_harvest": [_P, _P, _I, _P, _P, _P],
+    "ttn_sweep_run": [_P, _P, _P, _I, _I, _I, _P, _P],
+    "ttn_ctx_autotune": [_P, _I, C.c_char_p, C.c_int64, C.POINTER(C.c_int64)],
 }
 
 
@@ -129,6 +132,7 @@ class Context:
         s = stream if stream is not None else torch.cuda.current_stream(device)
         _check(lib().ttn_ctx_create(device, C.c_void_p(s.cuda_stream), workspace_bytes, C.byref(self.h)))
         self.device = device
+        self._sweeps = weakref.WeakSet()
 
     def set_stream(self, stream):
         _check(lib().ttn_ctx_set_stream(self.h, C.c_void_p(stream.cuda_stream)), self)
@@ -137,7 +141,11 @@ class Context:
         _check(lib().ttn_ctx_sync(self.h), self)
 
     def close(self):
+        """Destroy the context; sweeps created on it are destroyed first (a
+        sweep keeps a pointer to its context)."""
         if self.h:
+            for sw in list(self._sweeps):
+                sw.close()
             lib().ttn_ctx_destroy(self.h)
             self.h = C.c_void_p()
 
@@ -376,6 +384,7 @@ class Sweep:
         self.h = C.c_void_p()
         _check(lib().ttn_sweep_create(ctx.h, tree.h, None if op is None else op.h, target.h, n, ops, blks, nt, tgp,
                                       srp, cfp, _ptr(shift), compute, C.byref(self.h)), ctx)
+        ctx._sweeps.add(self)
 
     def init(self, centre: int):
         _check(lib().ttn_sweep_init(self.h, centre), self.ctx)
@@ -386,13 +395,25 @@ class Sweep:
                       None if learned_coef is None else learned_coef.data_ptr())
         _check(lib().sweep_step(self.ctx.h, self.h, node, nxt, C.byref(o), _ptr(iters), _ptr(resid)), self.ctx)
 
+    def run(self, mode: int, n_sweeps: int = 1, init: bool = False, graph: bool = False, maxiter: int = 0,
+            rtol: float = 0.0, iters=None, resid=None, mlp: Optional[torch.Tensor] = None, mlp_compute: int = BF16):
+        """n_sweeps native sweeps (see ttn_sweep_run), optionally replayed as a HIP graph."""
+        o = SolveOpts(mode, maxiter, rtol, None if mlp is None else mlp.data_ptr(), mlp_compute, 0, None)
+        _check(lib().ttn_sweep_run(self.ctx.h, self.h, C.byref(o), n_sweeps, int(init), int(graph), _ptr(iters),
+                                   _ptr(resid)), self.ctx)
+
     def harvest(self, node: int, X: torch.Tensor, T: torch.Tensor, scales: torch.Tensor):
         """Training pairs of the current local problems at `node` (see ttn_sweep_harvest)."""
         _check(lib().ttn_sweep_harvest(self.ctx.h, self.h, node, _ptr(X), _ptr(T), _ptr(scales)), self.ctx)
 
+    def close(self):
+        if self.h:
+            lib().ttn_sweep_destroy(self.h)
+            self.h = C.c_void_p()
+
     def __del__(self):
         try:
-            lib().ttn_sweep_destroy(self.h)
+            self.close()
         except Exception:
             pass
 
@@ -417,6 +438,9 @@ def run_sweep(sw: Sweep, tree: Tree, mode: int, maxiter: int = 0, rtol: float = 
     collect: optional list receiving (node, iters tensor) per local solve.
     on_solved(u): optional callback after a node's local solve, before the
     centre moves on (harvesting reads the local problem there)."""
+    if collect is None and on_solved is None:
+        sw.run(mode, 1, maxiter=maxiter, rtol=rtol, iters=iters, resid=resid, mlp=mlp, mlp_compute=mlp_compute)
+        return
     tour = euler_tour(tree)
     seen = set()
     for t, u in enumerate(tour):
@@ -514,3 +538,13 @@ def precond_targets(ctx: Context, y: torch.Tensor, b: torch.Tensor, d: torch.Ten
     k, n = y.shape
     st = F64 if y.dtype == torch.float64 else F32
     _check(lib().ttn_precond_targets(ctx.h, k, n, st, _ptr(y), _ptr(b), _ptr(d), _ptr(scales), _ptr(T)), ctx)
+
+
+def autotune(ctx: Context, on: Optional[bool] = True) -> str:
+    """Switch the tile autotuner (None: leave it) and return its log so far."""
+    need = C.c_int64()
+    flag = -1 if on is None else int(bool(on))
+    _check(lib().ttn_ctx_autotune(ctx.h, flag, None, 0, C.byref(need)), ctx)
+    buf = C.create_string_buffer(int(need.value) + 16)
+    _check(lib().ttn_ctx_autotune(ctx.h, -1, buf, len(buf), C.byref(need)), ctx)
+    return buf.value.decode()

@@ -235,3 +235,29 @@ def test_rejects_bad_arguments(api, ctx):
         api.heff_apply_block(ctx, gt, gW, envs, 1, k + 1, to_dev(X), gY, compute=api.F64)
     # k = 0 is a no-op
     api.heff_apply_block(ctx, gt, gW, envs, 1, 0, to_dev(X), gY, compute=api.F64)
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("dt", [1, 2])
+def test_identity_env_update_fp32_paths(api, ctx, case, dt):
+    """Identity-operator environment updates (the overlap environments of the
+    Gram step and of fitting) in FP32 / BF16 compute, every direction, against
+    the oracle; the binary-tree node shape goes through the split-K skinny
+    kernel (checked in the stage profile)."""
+    kappa, d, Db, M, Da, _ = case
+    tree, gt, bra, ket, A_b, A_k, W, gW, envs, E, pairs, pb, pk, tdt = _env_setup(
+        api, ctx, kappa, d, Db, M, Db, 3, 4, 400 + kappa, dt, op=False)
+    nb = tree.neighbours(1)
+    api.profile(ctx, True)
+    for v in nb:
+        api.ttno_env_update(ctx, gt, None, bra, ket, pb, pk, 1, v, envs, dt)
+        ctx.sync()
+        got = envs.get(1, v).double().cpu().numpy()
+        for p, (i, j) in enumerate(pairs):
+            ein = {c: E[c][p] for c in nb if c != v}
+            ref = ottn.env_update(tree, 1, v, A_b[i], None, A_k[j], ein)
+            assert rel_err(got[p], ref) < TOL[dt], (case, dt, v, p)
+    kernels = {r[2] for r in api.profile_report(ctx)}
+    api.profile(ctx, False)
+    if Db == [24, 24, 24]:  # the binary-tree node: a 24 x 24 x 576 closing stage
+        assert "ogemm_splitk_kernel" in kernels, kernels

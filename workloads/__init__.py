@@ -6,6 +6,7 @@ random tensors.  It holds none of the eigensolver's arithmetic (no operator
 matrices, no TTNO construction, no contraction, no decomposition), so the
 oracle and the HIP path can both read it without sharing any of the method.
 """
-from .hamiltonians import SOPModel, make_config_model, coupled_oscillators, quartic_force_field, paper_64d_model
+from .hamiltonians import (SOPModel, make_config_model, coupled_oscillators, quartic_force_field, paper_64d_model,
+                           ensemble_members)
 from .trees import Tree, mps_tree, binary_tree, fork_tree, bond_dims
 from .states import node_shape, lowest_product_states, initial_block, random_block, random_tensor

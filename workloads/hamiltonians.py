@@ -216,3 +216,22 @@ def make_config_model(config: str, seed: int | None = None, L: int | None = None
         assert L is not None and seed is not None
         return quartic_force_field(L, seed, 9 * L, 16 * L, name=f"c4f_L{L}_s{seed}")
     raise ValueError(config)
+
+
+def ensemble_members(n: int, seed0: int = 4000, D_range=(12, 48), k_range=(10, 84), L_range=(8, 64)):
+    """Seeded ensemble of independent workloads: member i uses seed seed0 + i;
+    even seeds take the coupled-oscillator generator on a balanced binary
+    tree, odd seeds the quartic force-field generator on a fork-4 comb; the
+    mode count L, bond dimension D and block size k are drawn uniformly
+    (integers, inclusive ranges) from the member's own seed."""
+    out = []
+    for i in range(n):
+        seed = seed0 + i
+        rng = np.random.default_rng(seed)
+        L = int(rng.integers(L_range[0], L_range[1] + 1))
+        D = int(rng.integers(D_range[0], D_range[1] + 1))
+        k = int(rng.integers(k_range[0], k_range[1] + 1))
+        kind = "c4-binary" if seed % 2 == 0 else "c4-fork"
+        out.append({"seed": seed, "kind": kind, "L": L, "D": D, "k": k,
+                    "model": make_config_model(kind, seed=seed, L=L)})
+    return out
