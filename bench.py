@@ -250,9 +250,10 @@ def ensemble_experiment(args):
            "recipe": f"seeds 4000-{4000 + len(members) - 1}, L 8-{args.ens_lmax}, D {args.ens_dmin}-{args.ens_dmax}, "
                      f"k {args.ens_kmin}-{args.ens_kmax}, {args.ens_iters} FP32 LOBPCG iterations + 1 FP64"}
     res = {}
-    for name, conc in (("one_at_a_time", False), ("concurrent", True)):
+    modes = (("one_at_a_time", False, False), ("concurrent_untuned", True, False), ("concurrent", True, True))
+    for name, conc, tune in modes:
         o = EnsembleOpts(low="fp32", iters_low=args.ens_iters, iters_fp64=1, concurrent=conc, threads=8,
-                         graphs=conc, autotune=conc, workspace_bytes=512 << 20)
+                         graphs=conc, autotune=tune, workspace_bytes=512 << 20)
         t0 = time.perf_counter()
         ens = Ensemble(members, o, log=log)
         t_setup = time.perf_counter() - t0
@@ -266,11 +267,15 @@ def ensemble_experiment(args):
         ens.close()
         del ens
         torch.cuda.synchronize()
-    dev = max(float(np.max(np.abs(a - b))) for a, b in zip(res["one_at_a_time_lam"], res["concurrent_lam"]))
-    out["one_at_a_time"] = res["one_at_a_time"]
-    out["concurrent"] = res["concurrent"]
+    dev = lambda x, y: max(float(np.max(np.abs(a - b))) for a, b in zip(res[x + "_lam"], res[y + "_lam"]))
+    for name, _, _ in modes:
+        out[name] = res[name]
     out["speedup"] = round(res["one_at_a_time"]["warm_run_s"] / res["concurrent"]["warm_run_s"], 3)
-    out["max_eigenvalue_difference_cm-1"] = dev
+    out["speedup_untuned"] = round(res["one_at_a_time"]["warm_run_s"] / res["concurrent_untuned"]["warm_run_s"], 3)
+    # streams and graphs do not change the arithmetic: bitwise-equal eigenvalues expected
+    out["max_eigenvalue_difference_untuned_cm-1"] = dev("one_at_a_time", "concurrent_untuned")
+    # tuned tiles change FP32 summation order (amplified by the unconverged early iterations)
+    out["max_eigenvalue_difference_tuned_cm-1"] = dev("one_at_a_time", "concurrent")
     print(json.dumps(out), flush=True)
 
 
@@ -407,9 +412,14 @@ def main():
     ap.add_argument("--ens-iters", type=int, default=3)
     ap.add_argument("--ens-lmax", type=int, default=32)
     ap.add_argument("--tts", action="store_true", help="run the plain-vs-mixed time-to-all-states experiment")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the heuristic tiles (default: measured tile choice on each stage's first launch)")
+    ap.add_argument("--graphs", action="store_true", help="replay the sweeps as HIP graphs (own stream)")
     ap.add_argument("--switch-tol", type=float, default=0.05)
     ap.add_argument("--gemm-hash", action="store_true", help="print the GEMM source hash and exit")
     args = ap.parse_args()
+    if args.graphs and args.warmup < 2:
+        args.warmup = 2  # first step runs eagerly, the second captures: keep both untimed
     if args.gemm_hash:
         print(gemm_source_hash())
         return
@@ -440,8 +450,23 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    ctx = api.Context(0, workspace_bytes=8 << 30)
+    if args.graphs:
+        # graphs need a non-null stream: the whole run goes on one of its own
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            run_bench(args, api, k, D, stream)
+    else:
+        run_bench(args, api, k, D, None)
+
+
+def run_bench(args, api, k, D, stream):
+    import torch
+    from paper_2512_15875_amd.solver import LobpcgOpts
+
+    ctx = api.Context(0, workspace_bytes=8 << 30, stream=stream)
+    api.autotune(ctx, args.autotune)
     s, model, tree = make_solver(api, ctx, args.workload, args.precision, k, D)
+    s.graphs = args.graphs
     s.lobpcg_start(LobpcgOpts(n_iter=args.warmup + args.steps + 1))
     print(f"setup done: {tree.n} nodes, k={k}, D={D}, precision={args.precision}", file=sys.stderr, flush=True)
     for i in range(args.warmup):
@@ -518,7 +543,8 @@ def main():
         "config": {"workload": f"{workload_name}, D={D}, k={k}: one block-LOBPCG iteration (residual fit, ALS "
                                f"preconditioner 2 sweeps x MINRES<=10, 3k-subspace Gram + Rayleigh-Ritz, fitted "
                                f"recombination)",
-                   "precision": args.precision, "gflop_per_step": round(flops / args.steps / 1e9, 2)},
+                   "precision": args.precision, "gflop_per_step": round(flops / args.steps / 1e9, 2),
+                   "autotune": bool(args.autotune), "graphs": bool(args.graphs)},
         "roofline": roof,
     }
     if not args.no_tts:

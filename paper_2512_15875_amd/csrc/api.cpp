@@ -345,7 +345,7 @@ Plan* get_plan(ttn_ctx* ctx, const Net& net, int ct, double batch, ttn_status& c
   auto it = ctx->plans.find(k.str());
   if (it != ctx->plans.end()) return it->second.get();
   Status st;
-  auto p = make_plan(net.in, net.dims, net.out_lab, net.out_str, batch, ct, st);
+  auto p = make_plan(net.in, net.dims, net.out_lab, net.out_str, batch, ct, st, ctx->stream);
   if (!p) {
     code = fail(ctx, st.code, st.msg);
     return nullptr;
@@ -385,7 +385,9 @@ ttn_status ttn_ctx_create(int device, void* hip_stream, size_t workspace_bytes, 
     delete c;
     return fail(nullptr, TTN_E_DEVICE, "workspace hipMalloc failed");
   }
-  if (hipMalloc(&c->d_flag, 4 * sizeof(int)) != hipSuccess || hipMemset(c->d_flag, 0, 4 * sizeof(int)) != hipSuccess) {
+  if (hipMalloc(&c->d_flag, 4 * sizeof(int)) != hipSuccess ||
+      hipMemsetAsync(c->d_flag, 0, 4 * sizeof(int), c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
     (void)hipFree(c->ws);
     delete c;
     return fail(nullptr, TTN_E_DEVICE, "flag hipMalloc failed");
@@ -404,9 +406,11 @@ ttn_status ttn_ctx_sync(ttn_ctx* ctx) {
   if (!ctx) return fail(nullptr, TTN_E_ARG, "null context");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   int f[4];
-  HIPCHK(ctx, hipMemcpy(f, ctx->d_flag, sizeof(f), hipMemcpyDeviceToHost));
+  HIPCHK(ctx, hipMemcpyAsync(f, ctx->d_flag, sizeof(f), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   if (f[0] || f[1] || f[2]) {
-    HIPCHK(ctx, hipMemset(ctx->d_flag, 0, sizeof(f)));
+    HIPCHK(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(f), ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     if (f[2]) return fail(ctx, TTN_E_ARG, "a pair / row index table held an out-of-range index (clamped)");
     if (f[0]) return fail(ctx, TTN_E_NONFINITE, "a kernel produced a non-finite value");
     return fail(ctx, TTN_E_NOT_PD, "overlap matrix not positive definite (SVQB disabled)");

@@ -56,7 +56,7 @@ const int32_t* leg_rows_table(ttn_ctx* ctx, const std::vector<int>& dims, int le
   }
   int32_t* d = nullptr;
   if (hipMalloc(&d, off.size() * sizeof(int32_t)) != hipSuccess ||
-      hipMemcpy(d, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+      !upload_sync(d, off.data(), off.size() * sizeof(int32_t), ctx->stream)) {
     code = api_fail(ctx, TTN_E_DEVICE, "row table upload failed");
     return nullptr;
   }

@@ -135,7 +135,15 @@ struct Plan {
 // to weigh batched against shared work.
 std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<int, int>& dims,
                                 const std::vector<int>& out_lab, const std::vector<int64_t>& out_str,
-                                double batch, int ctype, Status& st);
+                                double batch, int ctype, Status& st, hipStream_t stream);
+
+// Host-to-device upload ordered on `stream` and waited for.  Used instead of
+// the legacy synchronous copy, which also waits on the null stream and so
+// fails while another thread captures a graph on a blocking stream.
+inline bool upload_sync(void* dst, const void* src, size_t bytes, hipStream_t stream) {
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream) == hipSuccess &&
+         hipStreamSynchronize(stream) == hipSuccess;
+}
 
 // Host-side bounds proof of a plan: every element a stage can address lies in
 // its operand (inputs: in_elems per batch item; final output: out_elems).

@@ -47,7 +47,7 @@ ttn_status dense_gemm(ttn_ctx* ctx, int ct, int M, int N, int K, const float* A,
     if ((int64_t)M * K >= INT32_MAX || (int64_t)K * N >= INT32_MAX || (int64_t)M * N >= INT32_MAX)
       return api_fail(ctx, TTN_E_SHAPE, "dense GEMM too large for 32-bit offsets");
     if (hipMalloc(&tab, h.size() * 4) != hipSuccess ||
-        hipMemcpy(tab, h.data(), h.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+        !upload_sync(tab, h.data(), h.size() * 4, ctx->stream))
       return api_fail(ctx, TTN_E_DEVICE, "table upload failed");
     ctx->tables[key.str()] = tab;
   }

@@ -150,7 +150,7 @@ double min_flops(const std::vector<Tensor>& in, const std::map<int, int>& dims, 
 
 std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<int, int>& dims,
                                 const std::vector<int>& out_lab, const std::vector<int64_t>& out_str,
-                                double batch, int ctype, Status& st) {
+                                double batch, int ctype, Status& st, hipStream_t stream) {
   auto plan = std::make_unique<Plan>();
   plan->n_in = (int)in.size();
   std::vector<Node> ns;
@@ -425,9 +425,8 @@ std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<in
     st = {TTN_E_DEVICE, "hipMalloc for contraction tables failed"};
     return nullptr;
   }
-  if (hipMemcpy(plan->d_tabs, all_tabs.data(), all_tabs.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
-      hipSuccess) {
-    st = {TTN_E_DEVICE, "hipMemcpy for contraction tables failed"};
+  if (!upload_sync(plan->d_tabs, all_tabs.data(), all_tabs.size() * sizeof(int32_t), stream)) {
+    st = {TTN_E_DEVICE, "upload of the contraction tables failed"};
     return nullptr;
   }
   for (auto& r : refs) {

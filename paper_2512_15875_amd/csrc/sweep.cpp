@@ -273,7 +273,7 @@ ttn_status ttn_sweep_create(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
   std::vector<int32_t> iota(sw->k);
   for (int i = 0; i < sw->k; ++i) iota[i] = i;
   if (!dmalloc(&sw->d_iota, iota.size() * 4) ||
-      hipMemcpy(sw->d_iota, iota.data(), iota.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      !upload_sync(sw->d_iota, iota.data(), iota.size() * 4, ctx->stream)) {
     delete sw;
     return api_fail(ctx, TTN_E_DEVICE, "allocation failed");
   }
@@ -331,11 +331,11 @@ ttn_status ttn_sweep_create(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
     const size_t nb = (size_t)s.n * 4;
     if (!dmalloc(&s.d_tgt, nb) || !dmalloc(&s.d_src, nb) || !dmalloc(&s.d_perm, nb) || !dmalloc(&s.d_rtgt, nb) ||
         !dmalloc(&s.d_rsrc, nb) || !dmalloc(&s.d_rcoef, (size_t)s.n * 8) ||
-        hipMemcpy(s.d_tgt, s.tgt.data(), nb, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(s.d_src, s.src.data(), nb, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(s.d_perm, perm.data(), nb, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(s.d_rtgt, rt.data(), nb, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(s.d_rsrc, rs.data(), nb, hipMemcpyHostToDevice) != hipSuccess) {
+        !upload_sync(s.d_tgt, s.tgt.data(), nb, ctx->stream) ||
+        !upload_sync(s.d_src, s.src.data(), nb, ctx->stream) ||
+        !upload_sync(s.d_perm, perm.data(), nb, ctx->stream) ||
+        !upload_sync(s.d_rtgt, rt.data(), nb, ctx->stream) ||
+        !upload_sync(s.d_rsrc, rs.data(), nb, ctx->stream)) {
       sw->src.push_back(s);
       delete sw;
       return api_fail(ctx, TTN_E_DEVICE, "allocation failed");
@@ -348,8 +348,8 @@ ttn_status ttn_sweep_create(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
       std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
       for (int j = 0; j < s.n; ++j) terms[fill[s.tgt[j]]++] = j;
       if (!dmalloc(&s.d_csr_ptr, ptr.size() * 4) || !dmalloc(&s.d_csr_terms, (size_t)s.n * 4) ||
-          hipMemcpy(s.d_csr_ptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-          hipMemcpy(s.d_csr_terms, terms.data(), (size_t)s.n * 4, hipMemcpyHostToDevice) != hipSuccess) {
+          !upload_sync(s.d_csr_ptr, ptr.data(), ptr.size() * 4, ctx->stream) ||
+          !upload_sync(s.d_csr_terms, terms.data(), (size_t)s.n * 4, ctx->stream)) {
         sw->src.push_back(s);
         delete sw;
         return api_fail(ctx, TTN_E_DEVICE, "allocation failed");
@@ -378,7 +378,7 @@ ttn_status ttn_sweep_create(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
     for (int i = 0; i < 2 * sw->k; ++i) pair2[i] = i % sw->k;
     if (!dmalloc(&sw->d_pair2, pair2.size() * 4) || !dmalloc(&sw->d_shift2, (size_t)2 * sw->k * 8) ||
         !dmalloc(&sw->d_coef, (size_t)2 * sw->k * 8) || !dmalloc(&sw->d_scales, (size_t)2 * sw->k * 8) ||
-        hipMemcpy(sw->d_pair2, pair2.data(), pair2.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        !upload_sync(sw->d_pair2, pair2.data(), pair2.size() * 4, ctx->stream)) {
       delete sw;
       return api_fail(ctx, TTN_E_DEVICE, "allocation failed");
     }

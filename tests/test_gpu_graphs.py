@@ -122,5 +122,8 @@ def test_autotuned_solver_matches_untuned(api, prec):
         assert (len(log.splitlines()) > 10) == tune
         del s
         ctx.close()  # also destroys any sweep still alive on it
-    tol = 1e-9 if prec == "fp64" else 1e-3
+    # tile shapes change the order of the FP32 partial sums (the split-K kernel
+    # sums four k-interleaved partials), so FP32 runs agree to FP32 rounding
+    # amplified by two LOBPCG iterations: 5e-6 relative (about 0.05 cm^-1 at 1e4)
+    tol = 1e-9 if prec == "fp64" else 5e-6 * np.max(np.abs(lams[0]))
     assert np.max(np.abs(lams[0] - lams[1])) < tol
