@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}  # dense MFMA TFLOP/s (vendor)
 HBM_TBS = 8.0  # HBM3E TB/s (vendor)
+MARKER_N = 12345  # doubles scaled before and after the profiled step (grid of 49 x 256 threads)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")
 GEMM_SOURCE = os.path.join(ROOT, "paper_2512_15875_amd", "csrc", "gemm.hip")
 
@@ -45,19 +46,20 @@ def gemm_source_hash() -> str:
 
 
 def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
-    when there is none for this kernel or the GEMM source changed since."""
+    """(measured HBM bytes, compulsory bytes) per launch of `kernel` from the
+    committed counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated, on
+    the Gram launches of this workload), or None when there is none for this
+    kernel or the GEMM source changed since it was taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     rec = {}
     for line in open(TRAFFIC_FILE):
         if line.startswith("traffic|"):
-            _, kern, h, val = line.rstrip("\n").split("|")
-            rec[kern] = (h, float(val))
+            _, kern, h, meas, comp = line.rstrip("\n").split("|")
+            rec[kern] = (h, float(meas), float(comp))
     if kernel not in rec or rec[kernel][0] != gemm_source_hash():
         return None
-    return rec[kernel][1]
+    return rec[kernel][1], rec[kernel][2]
 
 
 def calibrate_copy():
@@ -89,11 +91,14 @@ def make_problem(workload: str, k: int, D: int):
     return model, tree, x0
 
 
+ENV_BUDGET = 16 << 30  # bytes of Gram environments kept at once (the pair chunk follows from it)
+
+
 def make_solver(api, ctx, workload: str, precision: str, k: int, D: int):
     from paper_2512_15875_amd.solver import TTNEigensolver
 
     model, tree, x0 = make_problem(workload, k, D)
-    s = TTNEigensolver(ctx, tree, model, D=D, k=k, precision=precision)
+    s = TTNEigensolver(ctx, tree, model, D=D, k=k, precision=precision, env_budget_bytes=ENV_BUDGET)
     s.load_block(x0)
     return s, model, tree
 
@@ -349,6 +354,46 @@ def tts_experiment(args):
     print(json.dumps(out), flush=True)
 
 
+def gram_probe(args):
+    """The Gram step of one LOBPCG iteration alone (environment updates and
+    closures over all pairs of the 3k basis) at the bench workload, bracketed
+    by the same markers as the profiled step; prints the per-kernel
+    algorithmic flops and bytes per launch (for the counter passes, which
+    rocprofv3 cannot take over a whole step)."""
+    import torch
+    from paper_2512_15875_amd import ttn as api
+    from paper_2512_15875_amd.solver import LobpcgOpts
+
+    k = args.k or 50
+    D = args.bond or 24
+    ctx = api.Context(0, workspace_bytes=8 << 30)
+    s, model, tree = make_solver(api, ctx, "c2", args.precision, k, D)
+    s.lobpcg_start(LobpcgOpts(n_iter=1))
+    m = 3 * k
+    ia = [a for a in range(m) for b in range(a, m)]
+    ib = [b for a in range(m) for b in range(a, m)]
+    s.gram(s.B, ia, ib)  # warm: plans and tables
+    ctx.sync()
+    mark = torch.zeros(MARKER_N, dtype=torch.float64, device="cuda")
+    api.vec_scale(ctx, mark, 1.0, mark)
+    api.profile(ctx, True)
+    s.gram(s.B, ia, ib)
+    rep = api.profile_report(ctx)
+    api.profile(ctx, False)
+    api.vec_scale(ctx, mark, 1.0, mark)
+    ctx.sync()
+    by = {}
+    for key, st, kern, cnt, tms, fl, *_rest in rep:
+        a = by.setdefault(kern, [0, 0.0, 0.0, 0.0])
+        a[0] += cnt
+        a[1] += tms
+        a[2] += fl
+        a[3] += _rest[-1]
+    out = {kern: {"launches": c, "avg_ms": round(t / c, 5), "algorithmic_flop_per_launch": f / c,
+                  "algorithmic_bytes_per_launch": b / c} for kern, (c, t, f, b) in by.items()}
+    print(json.dumps({"gram_probe": f"c2, D={D}, k={k}, {len(ia)} pairs", "kernels": out}), flush=True)
+
+
 def cpu_baseline(s, k: int, budget_s: float = 12.0):
     """The FP64 oracle's H_eff apply at the heaviest node, timed on the host."""
     from oracle import ttn as ottn
@@ -393,6 +438,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tts", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run the copy kernel used to scale counters")
+    ap.add_argument("--gram-probe", action="store_true", help="only the Gram step, for counter passes")
     ap.add_argument("--learned", action="store_true", help="run the learned-preconditioner experiment instead")
     ap.add_argument("--fields", type=int, default=32)
     ap.add_argument("--train-bond", type=int, default=24)
@@ -412,8 +458,9 @@ def main():
     ap.add_argument("--ens-iters", type=int, default=3)
     ap.add_argument("--ens-lmax", type=int, default=32)
     ap.add_argument("--tts", action="store_true", help="run the plain-vs-mixed time-to-all-states experiment")
-    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
-                    help="keep the heuristic tiles (default: measured tile choice on each stage's first launch)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="measured tile choice on each stage's first launch (default: the planner's heuristic, "
+                         "deterministic, so that profiles of the same command agree)")
     ap.add_argument("--graphs", action="store_true", help="replay the sweeps as HIP graphs (own stream)")
     ap.add_argument("--switch-tol", type=float, default=0.05)
     ap.add_argument("--gemm-hash", action="store_true", help="print the GEMM source hash and exit")
@@ -429,6 +476,9 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.gram_probe:
+        gram_probe(args)
         return
     if args.tts:
         tts_experiment(args)
@@ -487,11 +537,17 @@ def run_bench(args, api, k, D, stream):
     ms = (t1 - t0) * 1e3 / args.steps
     value = flops / (t1 - t0) / 1e9
 
-    # per-kernel totals of one more step, timed with HIP events on the library stream
+    # per-kernel totals of one more step, timed with HIP events on the library stream;
+    # the step is bracketed by two copies of MARKER_N doubles (a launch of a
+    # distinct grid size) so that counter and trace summaries can select it
+    mark = torch.zeros(MARKER_N, dtype=torch.float64, device="cuda")
+    api.vec_scale(ctx, mark, 1.0, mark)
     api.profile(ctx, True)
     s.lobpcg_step()
     rep = api.profile_report(ctx)
     api.profile(ctx, False)
+    api.vec_scale(ctx, mark, 1.0, mark)
+    ctx.sync()
     by_kernel = {}
     for key, st, kern, cnt, tms, fl, Mm, Nn, Kk, nz, by in rep:
         a = by_kernel.setdefault(kern, [0, 0.0, 0.0, 0.0])
@@ -517,7 +573,15 @@ def run_bench(args, api, k, D, stream):
         roof = {"bound": "hbm", "achieved": round(dby / (dms * 1e-3) / 1e9, 1), "peak": HBM_TBS * 1e3,
                 "unit": "GB/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    roof["traffic"] = measured_traffic(dkern)
+    tr = measured_traffic(dkern)
+    # the counters cover this kernel's Gram launches (rocprofv3 cannot count a
+    # whole step here): their measured / compulsory ratio applied to this
+    # step's compulsory bytes per launch
+    roof["traffic"] = None if tr is None else round(tr[0] / tr[1] * dby / dcnt, 0)
+    if tr is not None:
+        roof["traffic_unit"] = "bytes per launch"
+        roof["traffic_over_compulsory"] = round(tr[0] / tr[1], 3)
+        roof["traffic_source"] = "profiles/gram_c2_fp32_hbm_counters.md (Gram launches of this kernel)"
     roof.update({"kernel": dkern, "launches": dcnt, "avg_ms": round(dms / dcnt, 5),
                  "algorithmic_flop_per_launch": dfl / dcnt, "algorithmic_bytes_per_launch": dby / dcnt,
                  "share_of_contraction_time": round(dms / tot_ms, 3)})

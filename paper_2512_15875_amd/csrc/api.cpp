@@ -913,6 +913,32 @@ ttn_status ttn_ctx_flops(ttn_ctx* ctx, double* total, int32_t reset) {
   return TTN_OK;
 }
 
+}  // extern "C"
+
+namespace ttn {
+ttn_prof_rec* prof_begin(ttn_ctx* ctx, const char* key, const char* kernel, double flops, double bytes, int nz) {
+  if (!ctx || !ctx->profile || ctx->prof.size() >= 200000) return nullptr;
+  ctx->prof.emplace_back();
+  ttn_prof_rec* rec = &ctx->prof.back();
+  rec->key = key;
+  rec->kernel = kernel;
+  rec->flops = flops;
+  rec->bytes = bytes;
+  rec->nz = nz;
+  if (hipEventCreate(&rec->a) != hipSuccess || hipEventCreate(&rec->b) != hipSuccess) {
+    ctx->prof.pop_back();
+    return nullptr;
+  }
+  (void)hipEventRecord(rec->a, ctx->stream);
+  return rec;
+}
+void prof_end(ttn_ctx* ctx, ttn_prof_rec* rec) {
+  if (rec) (void)hipEventRecord(rec->b, ctx->stream);
+}
+}  // namespace ttn
+
+extern "C" {
+
 ttn_status ttn_ctx_autotune(ttn_ctx* ctx, int32_t on, char* buf, int64_t cap, int64_t* needed) {
   if (!ctx) return fail(nullptr, TTN_E_ARG, "null context");
   if (on >= 0) ctx->autotune = on != 0;

@@ -82,8 +82,10 @@ ttn_status rayleigh_ritz(ttn_ctx* ctx, int32_t batch, const int32_t* m, int32_t 
   double* scratch = (double*)((char*)ctx->ws + 256 + (((size_t)batch * sizeof(int32_t) + 255) / 256) * 256);
   if (hipMemcpyAsync(d_m, m, (size_t)batch * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
     return api_fail(ctx, TTN_E_DEVICE, "copy of m failed");
+  ttn_prof_rec* pr = prof_begin(ctx, "rr", "rr_kernel", 0.0, 2.0 * 8.0 * batch * (double)ld * ld, batch);
   hipError_t e = launch_rr(batch, d_m, ld, H, S, nev, drop_tol, allow_svqb, evals, V, rank_out, scratch, ctx->d_flag,
                            ctx->stream);
+  prof_end(ctx, pr);
   if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
   return TTN_OK;
 }
@@ -115,9 +117,17 @@ ttn_status ttn_block_move_centre(ttn_ctx* ctx, ttn_block* b, int32_t u, int32_t 
   double* wk = (double*)ctx->ws;
   double* R = (double*)((char*)ctx->ws + al(work));
   void* Y = (char*)ctx->ws + al(work) + al(rbytes);
+  // Householder QR with explicit Q: 4 m n^2 - 4 n^3 / 3 flops per state; the
+  // tensor is read and written once, R written once
+  const double fq = 4.0 * m_u * (double)n * n - 4.0 * (double)n * n * n / 3.0;
+  ttn_prof_rec* pr = prof_begin(ctx, "qr", "qr_kernel", fq * k, (double)k * (2.0 * m_u * n * es + 8.0 * n * n), k);
   hipError_t e = launch_qr(ct, b->ptr[u], b->size[u], ru, m_u, n, cs_u, wk, R, k, ctx->d_flag, ctx->stream);
+  prof_end(ctx, pr);
   if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+  pr = prof_begin(ctx, "absorb", "absorb_kernel", 2.0 * m_v * (double)n * n * k,
+                  (double)k * (2.0 * m_v * n * es + 8.0 * n * n), k);
   e = launch_absorb(ct, b->ptr[v], b->size[v], rv, m_v, n, cs_v, R, Y, k, ctx->stream);
+  prof_end(ctx, pr);
   if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
   if (hipMemcpyAsync(b->ptr[v], Y, (size_t)k * b->size[v] * es, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
     return api_fail(ctx, TTN_E_DEVICE, "copy back failed");

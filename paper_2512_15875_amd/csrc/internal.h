@@ -158,6 +158,7 @@ double min_flops(const std::vector<Tensor>& in, const std::map<int, int>& dims, 
 // ------------------------------------------------------------------ handles
 
 struct ttn_ctx;
+struct ttn_prof_rec;
 namespace ttn {
 // heff_apply_block with an output-row table (y_ids[j] = row of Y written by state j)
 ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_envs* envs, int32_t node,
@@ -165,6 +166,11 @@ ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, 
                            int32_t y_rows, const double* shift, const double* alpha, const void* X, int32_t x_rows,
                            void* Y, uint32_t flags, ttn_dtype compute);
 ttn_status api_fail(ttn_ctx* ctx, ttn_status code, const std::string& msg);
+// Profiling of a non-contraction launch (QR, Rayleigh-Ritz, MINRES vector
+// work): when the context profiles, brackets the launches between begin and
+// end with events and records algorithmic flops and compulsory bytes.
+::ttn_prof_rec* prof_begin(ttn_ctx* ctx, const char* key, const char* kernel, double flops, double bytes, int nz);
+void prof_end(ttn_ctx* ctx, ::ttn_prof_rec* rec);
 }  // namespace ttn
 
 struct ttn_tree {

@@ -8,6 +8,8 @@
 // Everything accumulates in double, whatever the storage dtype.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include <cmath>
 
 #include "internal.h"
@@ -434,6 +436,108 @@ __global__ __launch_bounds__(256) void qr_kernel(T* X, int64_t size, const int32
   }
 }
 
+// sum over the 64 lanes of a wave, result in every lane
+__device__ __forceinline__ double wave_allsum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Householder QR with the working matrix resident in LDS (dynamic shared
+// memory, FP64): column-major A (m x n); reflector k is stored in place below
+// the diagonal normalised to v_k = 1 (tau scaled to match), R is saved to a
+// small separate array, and Q is formed in place by backward accumulation of
+// the reflectors (each column finished as -tau v below, 1 - tau on, 0 above
+// the diagonal).  One workgroup per state; wave 0 builds each reflector, then
+// every wave applies it to the columns it owns (j = wave mod 8: dot product
+// as a wave sum, then the update, no barrier in between), so a reflector costs
+// two workgroup barriers.  The sign fix makes diag(R) >= 0 as in the
+// global-memory kernel above, which serves the nodes whose m x n doubles do
+// not fit.
+
+#define QR_NT 512  // threads of the LDS-resident QR (8 waves: more columns in flight per reflector)
+#define QR_NW (QR_NT / 64)
+
+template <typename T>
+__global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const int32_t* roff, int m, int n,
+                                                     int64_t cstride, double* Rout, int* flag) {
+  extern __shared__ double sm[];
+  double* A = sm;                  // m * n, column-major
+  double* Rl = A + (size_t)m * n;  // n * n, row-major
+  double* tau = Rl + (size_t)n * n;
+  const int z = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  T* Xz = X + (int64_t)z * size;
+  for (int i = t; i < m * n; i += QR_NT) {
+    const int j = i / m, r = i - j * m;
+    A[i] = (double)Xz[roff[r] + (int64_t)j * cstride];
+  }
+  for (int i = t; i < n * n; i += QR_NT) Rl[i] = 0.0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    double* a = A + (size_t)k * m;
+    // wave 0 builds reflector k: v = (1, a[k+1..] / v0), tau' = 2 v0^2 / |x - alpha e_k|^2
+    if (wv == 0) {
+      double ss = 0;
+      for (int i = k + lane; i < m; i += 64) ss += a[i] * a[i];
+      ss = wave_allsum(ss);
+      const double x0 = a[k], nrm = sqrt(ss);
+      const double alpha = nrm == 0.0 ? 0.0 : (x0 >= 0 ? -nrm : nrm);
+      const double v0 = x0 - alpha;
+      const double vn2 = ss - x0 * x0 + v0 * v0;
+      const double inv = v0 != 0.0 ? 1.0 / v0 : 0.0;
+      for (int i = k + 1 + lane; i < m; i += 64) a[i] *= inv;
+      if (lane == 0) {
+        tau[k] = (vn2 > 0 && v0 != 0.0) ? 2.0 * v0 * v0 / vn2 : 0.0;
+        Rl[k * n + k] = alpha;
+      }
+    }
+    __syncthreads();
+    // every wave applies the reflector to its own columns j > k (dot, then update)
+    const double tk = tau[k];
+    for (int j = k + 1 + wv; j < n; j += QR_NW) {
+      double* aj = A + (size_t)j * m;
+      double d = lane == 0 ? aj[k] : 0.0;
+      for (int i = k + 1 + lane; i < m; i += 64) d += a[i] * aj[i];
+      d = tk * wave_allsum(d);
+      if (lane == 0) aj[k] -= d;
+      for (int i = k + 1 + lane; i < m; i += 64) aj[i] -= d * a[i];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < n * n; e += QR_NT) {
+    const int r = e / n, c = e - r * n;
+    if (c > r) Rl[e] = A[(size_t)c * m + r];
+  }
+  __syncthreads();
+  // Q in place: backward accumulation of the reflectors
+  for (int i = n - 1; i >= 0; --i) {
+    double* ai = A + (size_t)i * m;
+    const double ti = tau[i];
+    for (int j = i + 1 + wv; j < n; j += QR_NW) {
+      double* aj = A + (size_t)j * m;
+      double d = lane == 0 ? aj[i] : 0.0;
+      for (int r = i + 1 + lane; r < m; r += 64) d += ai[r] * aj[r];
+      d = ti * wave_allsum(d);
+      if (lane == 0) aj[i] -= d;
+      for (int r = i + 1 + lane; r < m; r += 64) aj[r] -= d * ai[r];
+    }
+    __syncthreads();
+    for (int r = t; r < m; r += QR_NT) ai[r] = r > i ? -ti * ai[r] : (r == i ? 1.0 - ti : 0.0);
+    __syncthreads();
+  }
+  // sign fix diag(R) >= 0, R out (row-major), Q back to the node tensor
+  double* R = Rout + (size_t)z * n * n;
+  for (int e = t; e < n * n; e += QR_NT) {
+    const int r = e / n;
+    R[e] = Rl[r * n + r] < 0 ? -Rl[e] : Rl[e];
+  }
+  for (int i = t; i < m * n; i += QR_NT) {
+    const int j = i / m, r = i - j * m;
+    const double q = Rl[j * n + j] < 0 ? -A[i] : A[i];
+    if (!isfinite(q)) atomicOr(flag, 1);
+    Xz[roff[r] + (int64_t)j * cstride] = (T)q;
+  }
+}
+
 // Y[z][roff[r] + i*cstride] = sum_j R[z][i][j] X[z][roff[r] + j*cstride]   (into a separate buffer)
 template <typename T>
 __global__ void absorb_kernel(const T* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride,
@@ -458,8 +562,30 @@ static hipError_t qr_t(void* X, int64_t size, const int32_t* roff, int m, int n,
   return hipGetLastError();
 }
 
+// LDS budget of the resident-matrix QR (the CU has 160 KiB)
+static constexpr size_t QR_LDS_MAX = 150 * 1024;
+
+template <typename T>
+static bool qr_lds(void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride, double* R, int nz,
+                   int* flag, hipStream_t s) {
+  const size_t bytes = ((size_t)m * n + (size_t)n * n + (size_t)n) * sizeof(double);
+  if (bytes > QR_LDS_MAX) return false;
+  static const bool enabled = hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_lds_kernel<T>),
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  (int)QR_LDS_MAX) == hipSuccess;
+  if (!enabled) return false;
+  hipLaunchKernelGGL(qr_lds_kernel<T>, dim3(nz), dim3(QR_NT), bytes, s, (T*)X, size, roff, m, n, cstride, R, flag);
+  return hipGetLastError() == hipSuccess;
+}
+
 hipError_t launch_qr(int ctype, void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride, double* work,
                      double* R, int nz, int* flag, hipStream_t s) {
+  static const bool global_only = getenv("TTN_QR_GLOBAL") != nullptr;
+  if (!global_only) {
+    if (ctype == 0 ? qr_lds<double>(X, size, roff, m, n, cstride, R, nz, flag, s)
+                   : qr_lds<float>(X, size, roff, m, n, cstride, R, nz, flag, s))
+      return hipSuccess;
+  }
   if (ctype == 0) return qr_t<double>(X, size, roff, m, n, cstride, work, R, nz, flag, s);
   return qr_t<float>(X, size, roff, m, n, cstride, work, R, nz, flag, s);
 }

@@ -75,12 +75,16 @@ def test_rayleigh_ritz_not_pd_reports_error(api, ctx):
         ctx.sync()
 
 
+@pytest.mark.parametrize("D", [7, 40])
 @pytest.mark.parametrize("dt", [0, 1])
-def test_qr_move_matches_oracle(api, ctx, dt):
+def test_qr_move_matches_oracle(api, ctx, dt, D):
+    """QR gauge moves against the oracle's; D=7 keeps every node's matrix in
+    LDS, D=40 also sends the large backbone nodes through the global-memory
+    kernel."""
     m = wl.quartic_force_field(8, 21, 20, 30)
     tree = wl.fork_tree(m.dims, 4, 1)
-    bonds = wl.bond_dims(tree, 7)
-    k = 3
+    bonds = wl.bond_dims(tree, D)
+    k = 3 if D < 20 else 2
     blk_np = wl.random_block(tree, bonds, k, 44)
     gt = api.Tree(tree.parent, tree.phys)
     tdt = torch.float64 if dt == 0 else torch.float32
