@@ -354,6 +354,65 @@ def tts_experiment(args):
     print(json.dumps(out), flush=True)
 
 
+def ii_experiment(args):
+    """Inverse-iteration refinement on a large workload: the mixed LOBPCG
+    (FP32 iterations, promotion, FP64 iterations) brings the block close,
+    then block inverse iteration in FP64 runs from the same block twice --
+    local MINRES in FP64, and FP64 iterative refinement around MINRES in FP32
+    matrix-core arithmetic -- each followed by the final global
+    Rayleigh-Ritz."""
+    import torch
+    from paper_2512_15875_amd import ttn as api
+    from paper_2512_15875_amd.solver import IIOpts, LobpcgOpts, MixedEigensolver, build_ttno
+
+    wl_name = args.workload
+    k = args.k or (50 if wl_name == "c2" else 84)
+    D = args.bond or (24 if wl_name == "c2" else 40)
+    model, tree, x0 = make_problem(wl_name, k, D)
+    ctx = api.Context(0, workspace_bytes=8 << 30)
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
+    ms = MixedEigensolver(ctx, tree, model, D=D, k=k, low="fp32",
+                          ttno=build_ttno(api.Tree(tree.parent, tree.phys), tree, model))
+    ms.load_block(x0)
+    t0 = time.perf_counter()
+    ms.lo.lobpcg_start(LobpcgOpts(n_iter=args.ii_lo + args.ii_hi))
+    for i in range(args.ii_lo):
+        ms.lo.lobpcg_step()
+        log(f"  fp32 LOBPCG {i + 1}: {time.perf_counter() - t0:.1f} s")
+    ms.promote()
+    for i in range(args.ii_hi):
+        ms.hi.lobpcg_step()
+        log(f"  fp64 LOBPCG {i + 1}: {time.perf_counter() - t0:.1f} s")
+    s = ms.hi
+    lam0 = np.sort(s.lam_d.cpu().numpy() + s.zpe)
+    snap = [s.B.t[u][:k].clone() for u in range(s.gt.n)]
+    lam_snap = s.lam_d.clone()
+    out = {"experiment": "inverse iteration", "workload": f"{wl_name}, D={D}, k={k}",
+           "lobpcg": f"{args.ii_lo} FP32 + {args.ii_hi} FP64 iterations, {time.perf_counter() - t0:.1f} s"}
+    res = {}
+    for name, refine in (("fp64_minres", 0), ("refined_fp32_minres", 2)):
+        for u in range(s.gt.n):
+            s.B.t[u][:k].copy_(snap[u])
+        s.lam_d.copy_(lam_snap)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        theta = s.inverse_iteration(IIOpts(n_iter=args.ii_iters, minres_maxiter=args.ii_maxiter, minres_rtol=1e-10,
+                                           refine=refine),
+                                    log=lambda r: log(f"  {name} II {r['iter'] + 1}: {time.perf_counter() - t1:.1f} s"))
+        ctx.sync()
+        dt = time.perf_counter() - t1
+        res[name] = np.sort(theta)
+        out[name] = {"seconds": round(dt, 2), "iters": args.ii_iters,
+                     "reverted_states": [len(h.get("reverted", [])) for h in s.history[-args.ii_iters:]],
+                     "sum_lambda_change_cm-1": round(float(np.sum(res[name] - lam0)), 5),
+                     "max_lambda_drop_cm-1": round(float(np.max(lam0 - res[name])), 5),
+                     "max_lambda_rise_cm-1": round(float(np.max(res[name] - lam0)), 5)}
+        log(f"{name}: {dt:.1f} s")
+    out["max_difference_fp64_vs_refined_cm-1"] = float(np.max(np.abs(res["fp64_minres"] - res["refined_fp32_minres"])))
+    out["speedup_refined"] = round(out["fp64_minres"]["seconds"] / out["refined_fp32_minres"]["seconds"], 3)
+    print(json.dumps(out), flush=True)
+
+
 def gram_probe(args):
     """The Gram step of one LOBPCG iteration alone (environment updates and
     closures over all pairs of the 3k basis) at the bench workload, bracketed
@@ -439,6 +498,11 @@ def main():
     ap.add_argument("--no-tts", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run the copy kernel used to scale counters")
     ap.add_argument("--gram-probe", action="store_true", help="only the Gram step, for counter passes")
+    ap.add_argument("--ii", action="store_true", help="run the inverse-iteration experiment instead")
+    ap.add_argument("--ii-lo", type=int, default=10)
+    ap.add_argument("--ii-hi", type=int, default=4)
+    ap.add_argument("--ii-iters", type=int, default=2)
+    ap.add_argument("--ii-maxiter", type=int, default=200)
     ap.add_argument("--learned", action="store_true", help="run the learned-preconditioner experiment instead")
     ap.add_argument("--fields", type=int, default=32)
     ap.add_argument("--train-bond", type=int, default=24)
@@ -479,6 +543,9 @@ def main():
         return
     if args.gram_probe:
         gram_probe(args)
+        return
+    if args.ii:
+        ii_experiment(args)
         return
     if args.tts:
         tts_experiment(args)

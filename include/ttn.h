@@ -62,7 +62,11 @@ enum {
   TTN_E_NONFINITE = 8   /* NaN/Inf flagged by a kernel (surfaced at ttn_ctx_sync) */
 };
 
-typedef enum { TTN_F64 = 0, TTN_F32 = 1, TTN_BF16 = 2 } ttn_dtype;
+/* TTN_F64_F32 is a compute dtype only: FP64 tensors, FP32 matrix-core
+ * arithmetic (operands rounded to FP32 as they are staged, FP32 accumulation,
+ * results stored as FP64) -- the inner solves of the mixed-precision local
+ * refinement. */
+typedef enum { TTN_F64 = 0, TTN_F32 = 1, TTN_BF16 = 2, TTN_F64_F32 = 3 } ttn_dtype;
 
 typedef struct ttn_ctx ttn_ctx;
 typedef struct ttn_tree ttn_tree;
@@ -206,7 +210,9 @@ typedef struct {
   double rtol;               /* MINRES: stop when |residual| <= rtol * |b| */
   const float* mlp_params;   /* LEARNED: device FP32 parameters (ttn_mlp_num_params() floats) */
   int32_t mlp_compute;       /* LEARNED: TTN_BF16 or TTN_F32 matrix-core arithmetic */
-  int32_t pad_;
+  int32_t refine;            /* MINRES on an FP64 sweep, > 0: mixed-precision iterative refinement with this
+                                many steps: r = b - (H_eff - s) y in FP64, c from MINRES with TTN_F64_F32
+                                applies (rtol max(rtol, 1e-6), maxiter iterations), y += c in FP64 */
   double* learned_coef;      /* LEARNED, optional: device double[k][2], (a, c) of the last local step */
 } ttn_solve_opts;
 

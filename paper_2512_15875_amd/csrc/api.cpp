@@ -27,11 +27,16 @@ ttn_status fail(ttn_ctx* ctx, ttn_status code, const std::string& msg) {
     if (_e != hipSuccess) return fail(ctx, TTN_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(_e)); \
   } while (0)
 
-int ctype_of(ttn_dtype compute) { return compute == TTN_F64 ? 0 : (compute == TTN_F32 ? 1 : 2); }
-size_t esize(int ct) { return ct == 0 ? 8 : 4; }
+// engine compute types: 0 f64, 1 f32, 2 f32 storage with bf16 MFMA, 3 f64 storage with f32 MFMA
+int ctype_of(ttn_dtype compute) {
+  return compute == TTN_F64 ? 0 : (compute == TTN_F32 ? 1 : (compute == TTN_BF16 ? 2 : 3));
+}
+size_t esize(int ct) { return (ct == 0 || ct == 3) ? 8 : 4; }
+// element type of the storage for the non-GEMM kernels (0 double, 1 float)
+int stype(int ct) { return (ct == 0 || ct == 3) ? 0 : 1; }
 
 bool dtype_ok(ttn_dtype storage, ttn_dtype compute) {
-  if (compute == TTN_F64) return storage == TTN_F64;
+  if (compute == TTN_F64 || compute == TTN_F64_F32) return storage == TTN_F64;
   return storage == TTN_F32;
 }
 
@@ -714,7 +719,7 @@ ttn_status ttno_env_close(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, c
   if (!Ev) return fail(ctx, TTN_E_ARG, "missing incoming environment");
   for (int z0 = 0; z0 < n_pairs; z0 += 65535) {
     const int nz = std::min(65535, n_pairs - z0);
-    hipError_t he = launch_batched_dot(ct, (const char*)Ev, nullptr, se, (const char*)ctx->ws + (size_t)z0 * se * esize(ct),
+    hipError_t he = launch_batched_dot(stype(ct), (const char*)Ev, nullptr, se, (const char*)ctx->ws + (size_t)z0 * se * esize(ct),
                                        se, se, nz, z0, out, ctx->stream);
     if (he != hipSuccess) return fail(ctx, TTN_E_LAUNCH, hipGetErrorString(he));
   }
@@ -766,7 +771,8 @@ ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, 
       if (envs->eb(c, u) != envs->ea(c, u)) return fail(ctx, TTN_E_SHAPE, "DIAG needs square environments");
     // gather diagonals into the workspace, then contract the small network
     // Wd[w..., p] (shared) and Ed_i[z][b_i, w_i] (batched)
-    const size_t es = esize(ct);
+    const int cd = ct == 3 ? 0 : ct;  // the diagonal is gathered and contracted at the storage precision
+    const size_t es = esize(cd);
     int64_t wd_elems = t->phys[u];
     for (int c : t->nb[u]) wd_elems *= op->bond(u, c);
     std::vector<int64_t> ed_off(kap);
@@ -793,7 +799,7 @@ ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, 
       dd.E[i] = envs->slot[ttn_envs::dslot(t, c, u)];
       dd.Estride[i] = envs->slot_elems(c, u);
     }
-    hipError_t he = launch_diag_gather(ct, dd, ctx->ws, ed_off.data(), k, ctx->stream);
+    hipError_t he = launch_diag_gather(cd, dd, ctx->ws, ed_off.data(), k, ctx->stream);
     if (he != hipSuccess) return fail(ctx, TTN_E_LAUNCH, hipGetErrorString(he));
     Net net;
     std::vector<int> wl, wd, yl, yd;
@@ -822,7 +828,7 @@ ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, 
     net.key = key.str();
     out_layout(yl, yd, net.out_lab, net.out_str);
     ttn_status code = TTN_OK;
-    Plan* P = get_plan(ctx, net, ct == 2 ? 1 : ct, k, code);
+    Plan* P = get_plan(ctx, net, cd == 2 ? 1 : cd, k, code);
     if (!P) return code;
     std::vector<OpAddr> in;
     std::vector<int64_t> ne;
@@ -849,7 +855,7 @@ ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, 
     ep.shift = (flags & TTN_HEFF_NO_SHIFT) ? nullptr : shift;
     ep.shift_const = true;
     ep.accum = flags & TTN_HEFF_ACCUM;
-    return exec_plan(ctx, *P, ct == 2 ? 1 : ct, in, o, ep, k, ne, n_loc, (gather_bytes + 255) / 256 * 256);
+    return exec_plan(ctx, *P, cd == 2 ? 1 : cd, in, o, ep, k, ne, n_loc, (gather_bytes + 255) / 256 * 256);
   }
   Net net;
   std::string why;

@@ -79,6 +79,12 @@ struct Types<2> {
   typedef __bf16 L;
   typedef floatx4 Acc;
 };
+template <>
+struct Types<3> {  // FP64 tensors, FP32 matrix cores
+  typedef double T;
+  typedef float L;
+  typedef floatx4 Acc;
+};
 
 // k-offset tables up to this many entries are staged in LDS
 #define KCAP 1536
@@ -664,7 +670,7 @@ static hipError_t launch_tile(const GemmDesc& gd, KArgs& a, int nz, hipStream_t 
 // k-slice depth: 16 for FP32 and FP64 (measured on the hot-path shapes: the
 // deeper FP32 slice costs occupancy and never paid), 32 for bf16 (one MFMA).
 static int pick_bk(int ctype, const GemmDesc& gd) {
-  if (ctype == 0) return 16;
+  if (ctype == 0 || ctype == 3) return 16;
   if (ctype == 2) return 32;
   static const int mode = env_int("TTN_BK_MODE", 16);  // measured: 16 is as good or better everywhere
   (void)gd;
@@ -712,12 +718,20 @@ static hipError_t launch_ct(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s)
     g2.tile = 5;  // operands not 16-byte aligned: the general 64 x 32 tile
     return launch_ct<CT>(g2, a, nz, s);
   }
-  if (gd.tile == 7) return launch_wave<CT>(gd, a, nz, s);
+  if (gd.tile == 7) {
+    if constexpr (CT == 3) {
+      GemmDesc g2 = gd;
+      g2.tile = 6;  // no wave-per-item variant for FP64 storage with FP32 arithmetic
+      return launch_tile<CT, 16>(g2, a, nz, s);
+    } else {
+      return launch_wave<CT>(gd, a, nz, s);
+    }
+  }
   if constexpr (CT == 1) {
     if (pick_bk(CT, gd) == 16) return launch_tile<CT, 16>(gd, a, nz, s);
     return launch_tile<CT, 32>(gd, a, nz, s);
   } else {
-    return launch_tile<CT, (CT == 0) ? 16 : 32>(gd, a, nz, s);
+    return launch_tile<CT, (CT == 0 || CT == 3) ? 16 : 32>(gd, a, nz, s);
   }
 }
 
@@ -766,13 +780,14 @@ hipError_t launch_gemm(int ctype, const GemmDesc& gd, const OpAddr& A, const OpA
     a.z0 = z0 + zz;
     // chunk-local operands are indexed by z relative to the launch chunk
     KArgs b = a;
-    if (b.A.mode == 3) b.A.base = (const char*)b.A.base + (int64_t)zz * b.A.bs * (ctype == 0 ? 8 : 4);
-    if (b.B.mode == 3) b.B.base = (const char*)b.B.base + (int64_t)zz * b.B.bs * (ctype == 0 ? 8 : 4);
-    if (b.C.mode == 3) b.C.base = (const char*)b.C.base + (int64_t)zz * b.C.bs * (ctype == 0 ? 8 : 4);
+    if (b.A.mode == 3) b.A.base = (const char*)b.A.base + (int64_t)zz * b.A.bs * ((ctype == 0 || ctype == 3) ? 8 : 4);
+    if (b.B.mode == 3) b.B.base = (const char*)b.B.base + (int64_t)zz * b.B.bs * ((ctype == 0 || ctype == 3) ? 8 : 4);
+    if (b.C.mode == 3) b.C.base = (const char*)b.C.base + (int64_t)zz * b.C.bs * ((ctype == 0 || ctype == 3) ? 8 : 4);
     hipError_t e;
     if (ctype == 0) e = launch_ct<0>(gd, b, cnt, s);
     else if (ctype == 1) e = launch_ct<1>(gd, b, cnt, s);
-    else e = launch_ct<2>(gd, b, cnt, s);
+    else if (ctype == 2) e = launch_ct<2>(gd, b, cnt, s);
+    else e = launch_ct<3>(gd, b, cnt, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

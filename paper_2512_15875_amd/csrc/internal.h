@@ -49,13 +49,13 @@ struct GemmDesc {
 
 // the split-K skinny kernel (tile 8) applies: M, N <= 32, long unit-stride k (K % 4 == 0)
 inline bool splitk_eligible(const GemmDesc& g, int ctype) {
-  return ctype != 0 && g.M <= 32 && g.N <= 32 && g.K >= 64 && g.K % 4 == 0 && !g.a_mfast && !g.b_nfast &&
+  return (ctype == 1 || ctype == 2) && g.M <= 32 && g.N <= 32 && g.K >= 64 && g.K % 4 == 0 && !g.a_mfast && !g.b_nfast &&
          g.k_unit && g.rows_al4;
 }
 
 // the narrow kernel (tile 9) applies: tall M, N <= 32, short unit-stride k (K <= 32, K % 4 == 0)
 inline bool narrow_eligible(const GemmDesc& g, int ctype) {
-  return ctype != 0 && g.M >= 64 && g.N <= 32 && g.K <= 32 && g.K % 4 == 0 && !g.a_mfast && !g.b_nfast &&
+  return (ctype == 1 || ctype == 2) && g.M >= 64 && g.N <= 32 && g.K <= 32 && g.K % 4 == 0 && !g.a_mfast && !g.b_nfast &&
          g.k_unit && g.rows_al4;
 }
 
@@ -67,7 +67,7 @@ struct Epilogue {
   bool shift_const = false;       // subtract alpha*shift (no D read)
 };
 
-// dtype: 0 f64, 1 f32 storage with f32 MFMA, 2 f32 storage with bf16 MFMA
+// dtype: 0 f64, 1 f32 storage with f32 MFMA, 2 f32 storage with bf16 MFMA, 3 f64 storage with f32 MFMA
 hipError_t launch_gemm(int ctype, const GemmDesc& g, const OpAddr& A, const OpAddr& B, const OpAddr& C,
                        const Epilogue& ep, int z0, int nz, int* flag, hipStream_t s);
 

@@ -245,6 +245,26 @@ __global__ void add_kernel(const T* x, T* y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = (T)((double)y[i] + (double)x[i]);
 }
+// r = b - p (the FP64 residual of a refinement step); z = 0
+template <typename T>
+__global__ void resid_zero_kernel(const T* b, const T* p, T* r, T* zero, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    r[i] = (T)((double)b[i] - (double)p[i]);
+    zero[i] = (T)0;
+  }
+}
+hipError_t launch_resid_zero(int ctype, const void* b, const void* p, void* r, void* zero, int64_t n, hipStream_t s) {
+  const unsigned g = (unsigned)((n + 255) / 256);
+  if (ctype == 0)
+    hipLaunchKernelGGL(resid_zero_kernel<double>, dim3(g), dim3(256), 0, s, (const double*)b, (const double*)p,
+                       (double*)r, (double*)zero, n);
+  else
+    hipLaunchKernelGGL(resid_zero_kernel<float>, dim3(g), dim3(256), 0, s, (const float*)b, (const float*)p, (float*)r,
+                       (float*)zero, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_axpy_rows(int ctype, const void* x, void* y, int64_t n, hipStream_t s) {
   const unsigned g = (unsigned)((n + 255) / 256);
   if (ctype == 0) hipLaunchKernelGGL(add_kernel<double>, dim3(g), dim3(256), 0, s, (const double*)x, (double*)y, n);

@@ -29,6 +29,7 @@ hipError_t launch_gather_coef(const double* coef, const int32_t* perm, int n, do
 hipError_t launch_seg_sum(int ctype, const void* S, const int32_t* ptr, const int32_t* terms, const double* coef,
                           void* y, int64_t n, int k, bool accumulate_first, hipStream_t s);
 hipError_t launch_axpy_rows(int ctype, const void* x, void* y, int64_t n, hipStream_t s);
+hipError_t launch_resid_zero(int ctype, const void* b, const void* p, void* r, void* zero, int64_t n, hipStream_t s);
 hipError_t launch_features(int ctype, const void* b, const void* d, int64_t n, int nz, double* scales, float* X,
                            hipStream_t s);
 hipError_t launch_targets(int ctype, const void* y, const void* b, const void* d, int64_t n, int nz,
@@ -559,38 +560,65 @@ ttn_status sweep_step(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, int32_t next, c
         if (r != TTN_OK) return r;
       }
     } else {
-      if (opts->maxiter < 0 || !(opts->rtol >= 0)) return api_fail(ctx, TTN_E_ARG, "bad MINRES options");
+      if (opts->maxiter < 0 || !(opts->rtol >= 0) || opts->refine < 0)
+        return api_fail(ctx, TTN_E_ARG, "bad MINRES options");
+      if (opts->refine > 0 && ct != 0)
+        return api_fail(ctx, TTN_E_DTYPE, "mixed-precision refinement needs an FP64 sweep");
       void *v = vbuf(1), *vp = vbuf(2), *p = vbuf(3), *d1 = vbuf(4), *d2 = vbuf(5);
-      // p = (H_eff - s) y_u  (warm start)
-      r = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, y_u, k, p,
-                           TTN_HEFF_APPLY, sw->compute);
-      if (r != TTN_OK) return r;
-      hipError_t e = launch_minres_init(ct, b, p, v, vp, d1, d2, n, k, opts->rtol, sw->st, ctx->stream);
-      if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
-      void* dp = d1;
-      void* dpp = d2;
-      const int check_every = 25;
-      for (int it = 0; it < opts->maxiter; ++it) {
-        r = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, v, k, p,
+      // batched MINRES on (H_eff - s) x = rhs, warm start x with Ax0 = (H_eff - s) x
+      auto minres = [&](void* x, const void* rhs, const void* ax0, ttn_dtype comp, double rtol) -> ttn_status {
+        hipError_t e = launch_minres_init(ct, rhs, ax0, v, vp, d1, d2, n, k, rtol, sw->st, ctx->stream);
+        if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+        void *vv = v, *vvp = vp, *dp = d1, *dpp = d2;
+        const int check_every = 25;
+        for (int it = 0; it < opts->maxiter; ++it) {
+          ttn_status rr = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, vv, k,
+                                           p, TTN_HEFF_APPLY, comp);
+          if (rr != TTN_OK) return rr;
+          e = launch_minres_step(ct, x, vv, vvp, p, dp, dpp, n, k, sw->st, ctx->stream);
+          if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+          std::swap(vv, vvp);
+          std::swap(dp, dpp);
+          if ((it + 1) % check_every == 0 && it + 1 < opts->maxiter) {
+            int32_t act = 0;
+            if (hipMemsetAsync(sw->d_active, 0, 4, ctx->stream) != hipSuccess)
+              return api_fail(ctx, TTN_E_DEVICE, "memset");
+            e = launch_minres_report(sw->st, k, nullptr, nullptr, sw->d_active, ctx->stream);
+            if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+            if (hipMemcpyAsync(&act, sw->d_active, 4, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+                hipStreamSynchronize(ctx->stream) != hipSuccess)
+              return api_fail(ctx, TTN_E_DEVICE, "convergence check failed");
+            if (act == 0) break;
+          }
+        }
+        return TTN_OK;
+      };
+      if (opts->refine == 0) {
+        // p = (H_eff - s) y_u  (warm start)
+        r = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, y_u, k, p,
                              TTN_HEFF_APPLY, sw->compute);
         if (r != TTN_OK) return r;
-        e = launch_minres_step(ct, y_u, v, vp, p, dp, dpp, n, k, sw->st, ctx->stream);
-        if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
-        std::swap(v, vp);
-        std::swap(dp, dpp);
-        if ((it + 1) % check_every == 0 && it + 1 < opts->maxiter) {
-          int32_t act = 0;
-          if (hipMemsetAsync(sw->d_active, 0, 4, ctx->stream) != hipSuccess) return api_fail(ctx, TTN_E_DEVICE, "memset");
-          e = launch_minres_report(sw->st, k, nullptr, nullptr, sw->d_active, ctx->stream);
+        r = minres(y_u, b, p, sw->compute, opts->rtol);
+        if (r != TTN_OK) return r;
+      } else {
+        // iterative refinement: FP64 residual, correction by MINRES in FP32
+        // matrix-core arithmetic on the FP64 tensors, FP64 update
+        void *res = vbuf(6), *cor = vbuf(7);
+        const double rtol_in = opts->rtol > 1e-6 ? opts->rtol : 1e-6;
+        for (int step = 0; step < opts->refine; ++step) {
+          r = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, y_u, k, p,
+                               TTN_HEFF_APPLY, TTN_F64);
+          if (r != TTN_OK) return r;
+          hipError_t e = launch_resid_zero(ct, b, p, res, cor, n * k, ctx->stream);
           if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
-          if (hipMemcpyAsync(&act, sw->d_active, 4, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-              hipStreamSynchronize(ctx->stream) != hipSuccess)
-            return api_fail(ctx, TTN_E_DEVICE, "convergence check failed");
-          if (act == 0) break;
+          r = minres(cor, res, cor, TTN_F64_F32, rtol_in);
+          if (r != TTN_OK) return r;
+          e = launch_axpy_rows(ct, cor, y_u, n * k, ctx->stream);
+          if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
         }
       }
       if (iters_out || resid_out) {
-        e = launch_minres_report(sw->st, k, iters_out, resid_out, nullptr, ctx->stream);
+        hipError_t e = launch_minres_report(sw->st, k, iters_out, resid_out, nullptr, ctx->stream);
         if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
       }
     }

@@ -50,6 +50,7 @@ class IIOpts:
     dlam_tol: Optional[float] = None
     monotone: bool = True   # a cluster whose update raised a Rayleigh quotient keeps its previous states
     mono_tol: float = 1e-7  # cm^-1
+    refine: int = 0         # > 0: local solves by FP64 refinement around FP32-arithmetic MINRES (FP64 solver)
 
 
 def post_order_edges(tree: ttn.Tree):
@@ -351,7 +352,7 @@ class TTNEigensolver:
             col = []
             for _ in range(opts.sweeps):
                 ttn.run_sweep(self._sw_ii, self.gt, ttn.SOLVE_MINRES, opts.minres_maxiter, opts.minres_rtol,
-                              collect=col)
+                              collect=col, refine=opts.refine)
             ttn.block_normalize_node(ctx, self.Y, root)
             self._copy_rows(self.B, 0, self.Y, 0, k)
             if big:

@@ -36,4 +36,4 @@ def rel_err(got, ref):
     return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
 
 
-TOL = {0: 1e-12, 1: 2e-5, 2: 3e-2}  # F64, F32, BF16 norm-wise relative
+TOL = {0: 1e-12, 1: 2e-5, 2: 3e-2, 3: 2e-5}  # F64, F32, BF16, F64 storage with F32 arithmetic (norm-wise relative)

@@ -41,8 +41,9 @@ CASES = [
 
 def _setup(api, ctx, kappa, d, Db, M, Da, k, seed, dt, op=True):
     tree, W, X, E = node_case(kappa, d, Db, M, Da, k, seed, op=op)
-    tdt = torch.float64 if dt == api.F64 else torch.float32
-    sdt = api.F64 if dt == api.F64 else api.F32
+    f64 = dt in (api.F64, api.F64_F32)  # FP64 tensors (the F64_F32 compute type reads FP64 storage)
+    tdt = torch.float64 if f64 else torch.float32
+    sdt = api.F64 if f64 else api.F32
     gt = api.Tree(tree.parent, tree.phys)
     bond = [0] + [0] * tree.n
     bond = [0] * tree.n
@@ -70,7 +71,7 @@ def _setup(api, ctx, kappa, d, Db, M, Da, k, seed, dt, op=True):
 
 
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("dt", [0, 1, 2])
+@pytest.mark.parametrize("dt", [0, 1, 2, 3])
 def test_heff_apply_matches_oracle(api, ctx, case, dt):
     kappa, d, Db, M, Da, k = case
     tree, W, X, E, gt, gW, envs, tdt = _setup(api, ctx, kappa, d, Db, M, Da, k, 100 + kappa, dt)

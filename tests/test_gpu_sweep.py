@@ -66,7 +66,12 @@ def test_als_sweep_matches_oracle(api, ctx, tree_kind):
     assert int(iters.max()) == 6
 
 
-def test_als_sweep_converges_with_rtol(api, ctx):
+@pytest.mark.parametrize("refine", [0, 3])
+def test_als_sweep_converges_with_rtol(api, ctx, refine):
+    """Converged ALS against the oracle's; refine > 0 solves every local
+    system by FP64 iterative refinement around MINRES in FP32 matrix-core
+    arithmetic (FP64 residuals and updates) and must reach the same FP64
+    solution."""
     k = 2
     m, tree, W, M, bonds, gt, op, phi = _setup(api, ctx, k=k)
     y0 = [ottn.canonicalize(tree, p, tree.root) for p in phi]
@@ -79,7 +84,7 @@ def test_als_sweep_converges_with_rtol(api, ctx):
     iters = torch.zeros(k, dtype=torch.int32, device="cuda")
     resid = torch.zeros(k, dtype=torch.float64, device="cuda")
     for _ in range(2):
-        api.run_sweep(sw, gt, api.SOLVE_MINRES, maxiter=400, rtol=1e-10, iters=iters, resid=resid)
+        api.run_sweep(sw, gt, api.SOLVE_MINRES, maxiter=400, rtol=1e-10, iters=iters, resid=resid, refine=refine)
     ctx.sync()
     for j in range(k):
         ref = osol.als_solve(tree, W, shifts[j], phi[j], phi[j], sweeps=2, maxiter=400, rtol=1e-10)
