@@ -631,6 +631,23 @@ def run_bench(args, api, k, D, stream):
               f"{by / tms / 1e6:.0f} GB/s intensity {fl / max(by, 1):.1f} flop/B", file=sys.stderr)
     dkern, (dcnt, dms, dfl, dby) = max(by_kernel.items(), key=lambda kv: kv[1][1])
     tot_ms = sum(v[1] for v in by_kernel.values())
+    # the H_eff block applies of the step (every heff_apply_block with the TTNO:
+    # the ALS preconditioner's MINRES products), grouped per call shape
+    heff = {}
+    for key, st, kern, cnt, tms, fl, Mm, Nn, Kk, nz, by in rep:
+        parts = key.split(":")
+        if parts[0] == "heff" and parts[2] == "1":
+            a = heff.setdefault(parts[1], [0.0, 0.0])
+            a[0] += fl
+            a[1] += tms
+    heff_fl = sum(v[0] for v in heff.values())
+    heff_ms = sum(v[1] for v in heff.values())
+    heavy_u, (hfl, hms) = max(heff.items(), key=lambda kv: kv[1][0]) if heff else ("-", (0.0, 1.0))
+    heff_line = {"tflop_per_s": round(heff_fl / (heff_ms * 1e-3) / 1e12, 2) if heff_ms else None,
+                 "frac_of_peak": round(heff_fl / (heff_ms * 1e-3) / 1e12 / PEAK[args.precision], 4) if heff_ms else None,
+                 "ms_in_step": round(heff_ms, 1), "share_of_contraction_time": round(heff_ms / tot_ms, 3),
+                 "heaviest_node": {"node": heavy_u, "tflop_per_s": round(hfl / (hms * 1e-3) / 1e12, 2),
+                                   "frac_of_peak": round(hfl / (hms * 1e-3) / 1e12 / PEAK[args.precision], 4)}}
     peak_tf = PEAK[args.precision]
     ridge = peak_tf * 1e12 / (HBM_TBS * 1e12)
     if dfl / max(dby, 1.0) >= ridge:
@@ -677,6 +694,7 @@ def run_bench(args, api, k, D, stream):
                    "precision": args.precision, "gflop_per_step": round(flops / args.steps / 1e9, 2),
                    "autotune": bool(args.autotune), "graphs": bool(args.graphs)},
         "roofline": roof,
+        "heff_apply_block": heff_line,
     }
     if not args.no_tts:
         tts = {}
