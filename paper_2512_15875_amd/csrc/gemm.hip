@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -90,7 +91,7 @@ struct Types<3> {  // FP64 tensors, FP32 matrix cores
 #define KCAP 1536
 
 // occupancy floor: 3 waves / SIMD for FP32 tiles, 2 for FP64 and bf16 tiles
-template <int CT, int BM, int BN, int BK, bool AMF, bool BNF>
+template <int CT, int BM, int BN, int BK, bool AMF, bool BNF, bool CMF>
 __global__ __launch_bounds__(256, (CT == 1) ? 3 : 2) void ogemm_kernel(KArgs g) {
   typedef typename Types<CT>::T T;
   typedef typename Types<CT>::L L;
@@ -185,58 +186,53 @@ __global__ __launch_bounds__(256, (CT == 1) ? 3 : 2) void ogemm_kernel(KArgs g) 
     }
   }
   __syncthreads();
-  auto koff_a = [&](int kg) { return k_in_lds ? sk_a[kg] : g.a_ok[kg]; };
-  auto koff_b = [&](int kg) { return k_in_lds ? sk_b[kg] : g.b_ok[kg]; };
 
+  // Next-slice loads are issued unconditionally from clamped, always valid
+  // addresses (out-of-range k take the last table entry, out-of-range rows
+  // offset 0; offsets are non-negative, so every sum stays inside the operand)
+  // and the masks are applied only when the values are staged to LDS, after
+  // the matrix-core work of the current slice: the loads of a slice are all in
+  // flight together instead of each waiting for its own select.
   T ra[EA], rb[EB];
-  auto load = [&](int k0) {
+  bool kva[AMF ? EA : 1], kvb[BNF ? EB : 1];
+  const int klast = K - 1;
+  auto load = [&](int k0, auto lds_tab) {
+    constexpr bool KL = decltype(lds_tab)::value;
+    const int* __restrict__ ta = KL ? sk_a : g.a_ok;
+    const int* __restrict__ tb = KL ? sk_b : g.b_ok;
     if (AMF) {
       int ko[EA];
-      bool kv[EA];
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
         const int kg = k0 + tid / BM + i * (256 / BM);
-        kv[i] = kg < K;
-        ko[i] = kv[i] ? koff_a(kg) : 0;
+        kva[i] = kg < K;
+        ko[i] = ta[kva[i] ? kg : klast];
       }
 #pragma unroll
-      for (int i = 0; i < EA; ++i) {
-        const T v = A[a_fix[0] + ko[i]];
-        ra[i] = (a_ok_row[0] && kv[i]) ? v : (T)0;
-      }
+      for (int i = 0; i < EA; ++i) ra[i] = A[a_fix[0] + ko[i]];
     } else {
       const int kg = k0 + tid % BK;
-      const bool kv = kg < K;
-      const int ko = kv ? koff_a(kg) : 0;
+      kva[0] = kg < K;
+      const int ko = ta[kva[0] ? kg : klast];
 #pragma unroll
-      for (int i = 0; i < EA; ++i) {
-        const T v = A[a_fix[i] + ko];
-        ra[i] = (kv && a_ok_row[i]) ? v : (T)0;
-      }
+      for (int i = 0; i < EA; ++i) ra[i] = A[a_fix[i] + ko];
     }
     if (BNF) {
       int ko[EB];
-      bool kv[EB];
 #pragma unroll
       for (int i = 0; i < EB; ++i) {
         const int kg = k0 + tid / BN + i * (256 / BN);
-        kv[i] = kg < K;
-        ko[i] = kv[i] ? koff_b(kg) : 0;
+        kvb[i] = kg < K;
+        ko[i] = tb[kvb[i] ? kg : klast];
       }
 #pragma unroll
-      for (int i = 0; i < EB; ++i) {
-        const T v = B[b_fix[0] + ko[i]];
-        rb[i] = (b_ok_col[0] && kv[i]) ? v : (T)0;
-      }
+      for (int i = 0; i < EB; ++i) rb[i] = B[b_fix[0] + ko[i]];
     } else {
       const int kg = k0 + tid % BK;
-      const bool kv = kg < K;
-      const int ko = kv ? koff_b(kg) : 0;
+      kvb[0] = kg < K;
+      const int ko = tb[kvb[0] ? kg : klast];
 #pragma unroll
-      for (int i = 0; i < EB; ++i) {
-        const T v = B[b_fix[i] + ko];
-        rb[i] = (kv && b_ok_col[i]) ? v : (T)0;
-      }
+      for (int i = 0; i < EB; ++i) rb[i] = B[b_fix[i] + ko];
     }
   };
   auto aidx = [&](int m, int k) { return A_KMAJOR ? k * (BM + PM) + m : m * (BK + PK) + k; };
@@ -246,13 +242,15 @@ __global__ __launch_bounds__(256, (CT == 1) ? 3 : 2) void ogemm_kernel(KArgs g) 
     for (int i = 0; i < EA; ++i) {
       const int ml = AMF ? tid % BM : tid / BK + i * (256 / BK);
       const int kl = AMF ? tid / BM + i * (256 / BM) : tid % BK;
-      As[buf][aidx(ml, kl)] = (L)ra[i];
+      const bool ok = AMF ? (a_ok_row[0] && kva[i]) : (a_ok_row[i] && kva[0]);
+      As[buf][aidx(ml, kl)] = ok ? (L)ra[i] : (L)0;
     }
 #pragma unroll
     for (int i = 0; i < EB; ++i) {
       const int nl = BNF ? tid % BN : tid / BK + i * (256 / BK);
       const int kl = BNF ? tid / BN + i * (256 / BN) : tid % BK;
-      Bs[buf][bidx(nl, kl)] = (L)rb[i];
+      const bool ok = BNF ? (b_ok_col[0] && kvb[i]) : (b_ok_col[i] && kvb[0]);
+      Bs[buf][bidx(nl, kl)] = ok ? (L)rb[i] : (L)0;
     }
   };
 
@@ -263,73 +261,93 @@ __global__ __launch_bounds__(256, (CT == 1) ? 3 : 2) void ogemm_kernel(KArgs g) 
     for (int b = 0; b < TN; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
   const int nk = (K + BK - 1) / BK;
-  load(0);
-  store(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) load((kt + 1) * BK);
-    if constexpr (CT == 2) {
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += 32) {
-        bf16x8 af[TM], bfr[TN];
-#pragma unroll
-        for (int a = 0; a < TM; ++a)
-          af[a] = *(const bf16x8*)&As[buf][aidx(wm * WTM + a * 16 + (lane & 15), kk + 8 * (lane >> 4))];
-#pragma unroll
-        for (int b = 0; b < TN; ++b)
-          bfr[b] = *(const bf16x8*)&Bs[buf][bidx(wn * WTN + b * 16 + (lane & 15), kk + 8 * (lane >> 4))];
-#pragma unroll
-        for (int a = 0; a < TM; ++a)
-#pragma unroll
-          for (int b = 0; b < TN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
-      }
-    } else {
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        L af[TM], bfr[TN];
-#pragma unroll
-        for (int a = 0; a < TM; ++a) af[a] = As[buf][aidx(wm * WTM + a * 16 + (lane & 15), kk + (lane >> 4))];
-#pragma unroll
-        for (int b = 0; b < TN; ++b) bfr[b] = Bs[buf][bidx(wn * WTN + b * 16 + (lane & 15), kk + (lane >> 4))];
-#pragma unroll
-        for (int a = 0; a < TM; ++a)
-#pragma unroll
-          for (int b = 0; b < TN; ++b) {
-            if constexpr (CT == 0)
-              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bfr[b], acc[a][b], 0, 0, 0);
-            else
-              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a], bfr[b], acc[a][b], 0, 0, 0);
-          }
-      }
-    }
-    if (kt + 1 < nk) store(buf ^ 1);
+  auto main_loop = [&](auto lds_tab) {
+    if (nk <= 0) return;
+    load(0, lds_tab);
+    store(0);
     __syncthreads();
-  }
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) load((kt + 1) * BK, lds_tab);
+      if constexpr (CT == 2) {
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 32) {
+          bf16x8 af[TM], bfr[TN];
+#pragma unroll
+          for (int a = 0; a < TM; ++a)
+            af[a] = *(const bf16x8*)&As[buf][aidx(wm * WTM + a * 16 + (lane & 15), kk + 8 * (lane >> 4))];
+#pragma unroll
+          for (int b = 0; b < TN; ++b)
+            bfr[b] = *(const bf16x8*)&Bs[buf][bidx(wn * WTN + b * 16 + (lane & 15), kk + 8 * (lane >> 4))];
+#pragma unroll
+          for (int a = 0; a < TM; ++a)
+#pragma unroll
+            for (int b = 0; b < TN; ++b)
+              acc[a][b] = CMF ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[b], af[a], acc[a][b], 0, 0, 0)
+                              : __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+        }
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+          L af[TM], bfr[TN];
+#pragma unroll
+          for (int a = 0; a < TM; ++a) af[a] = As[buf][aidx(wm * WTM + a * 16 + (lane & 15), kk + (lane >> 4))];
+#pragma unroll
+          for (int b = 0; b < TN; ++b) bfr[b] = Bs[buf][bidx(wn * WTN + b * 16 + (lane & 15), kk + (lane >> 4))];
+#pragma unroll
+          for (int a = 0; a < TM; ++a)
+#pragma unroll
+            for (int b = 0; b < TN; ++b) {
+              const L x = CMF ? bfr[b] : af[a], y = CMF ? af[a] : bfr[b];
+              if constexpr (CT == 0)
+                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[a][b], 0, 0, 0);
+              else
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, acc[a][b], 0, 0, 0);
+            }
+        }
+      }
+      if (kt + 1 < nk) store(buf ^ 1);
+      __syncthreads();
+    }
+  };
+  // the table source is uniform over the launch: one specialised loop each
+  if (k_in_lds)
+    main_loop(std::true_type{});
+  else
+    main_loop(std::false_type{});
 
   // ---- epilogue: C = alpha (acc - shift * D) (+ C); output offsets loaded in
-  // one batch, then branch-free stores (masked rows / columns skipped)
+  // one batch, then the stores (masked rows / columns skipped).  Without CMF
+  // a lane holds four rows of one column of each 16 x 16 block (lanes along
+  // columns: coalesced when C's columns are its unit-stride direction); with
+  // CMF the operands went into the matrix cores swapped, and a lane holds four
+  // columns of one row (lanes along rows: coalesced when rows are unit-stride).
   T* __restrict__ C = (T*)g.C.base + batch_off(g.C, z, g.z0, g.flag);
   const T* __restrict__ Dp = g.has_d ? (const T*)g.D.base + batch_off(g.D, z, g.z0, g.flag) : nullptr;
   const double alpha = g.alpha ? g.alpha[g.z0 + z] : 1.0;
   const double sh = g.shift ? g.shift[g.z0 + z] : 0.0;
-  int cm[TM][4], cn[TN];
-  bool rv[TM][4], cv[TN];
+  constexpr int RI = CMF ? 1 : 4, CI = CMF ? 4 : 1;
+  auto quad = [&](int i) { return (CT == 0) ? ((lane >> 4) + 4 * i) : (4 * (lane >> 4) + i); };
+  auto ri = [](int i) { return CMF ? 0 : i; };
+  auto ci = [](int i) { return CMF ? i : 0; };
+  int cm[TM][RI], cn[TN][CI];
+  bool rv[TM][RI], cv[TN][CI];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = wm * WTM + a * 16 + ((CT == 0) ? ((lane >> 4) + 4 * i) : (4 * (lane >> 4) + i));
-      const int mg = m0 + row;
+    for (int i = 0; i < RI; ++i) {
+      const int mg = m0 + wm * WTM + a * 16 + (CMF ? (lane & 15) : quad(i));
       rv[a][i] = mg < M;
       cm[a][i] = rv[a][i] ? g.c_om[mg] : 0;
     }
 #pragma unroll
-  for (int b = 0; b < TN; ++b) {
-    const int ng = n0 + wn * WTN + b * 16 + (lane & 15);
-    cv[b] = ng < N;
-    cn[b] = cv[b] ? g.c_on[ng] : 0;
-  }
+  for (int b = 0; b < TN; ++b)
+#pragma unroll
+    for (int i = 0; i < CI; ++i) {
+      const int ng = n0 + wn * WTN + b * 16 + (CMF ? quad(i) : (lane & 15));
+      cv[b][i] = ng < N;
+      cn[b][i] = cv[b][i] ? g.c_on[ng] : 0;
+    }
   const bool plain = !Dp && !g.d_const && !g.accum;
   if (plain) {
 #pragma unroll
@@ -338,23 +356,33 @@ __global__ __launch_bounds__(256, (CT == 1) ? 3 : 2) void ogemm_kernel(KArgs g) 
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int b = 0; b < TN; ++b)
-          if (rv[a][i] && cv[b]) C[cm[a][i] + cn[b]] = (T)(alpha * (double)acc[a][b][i]);
+          if (rv[a][ri(i)] && cv[b][ci(i)]) C[cm[a][ri(i)] + cn[b][ci(i)]] = (T)(alpha * (double)acc[a][b][i]);
   } else {
+    // per 16-row block: every read of the block first (masked rows and
+    // columns read offset 0; a missing D reads C in its place and is replaced
+    // by its constant afterwards), then its writes
+    const T* __restrict__ ds = Dp ? Dp : (const T*)C;
 #pragma unroll
-    for (int a = 0; a < TM; ++a)
+    for (int a = 0; a < TM; ++a) {
+      T dv[4][TN], cvv[4][TN];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        double dv[TN], cvv[TN];
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int b = 0; b < TN; ++b) {
-          const int o = cm[a][i] + cn[b];
-          dv[b] = Dp ? (double)Dp[o] : (g.d_const ? 1.0 : 0.0);
-          cvv[b] = g.accum ? (double)C[o] : 0.0;
+          const int o = cm[a][ri(i)] + cn[b][ci(i)];
+          dv[i][b] = ds[o];
+          cvv[i][b] = C[o];
         }
 #pragma unroll
-        for (int b = 0; b < TN; ++b)
-          if (rv[a][i] && cv[b]) C[cm[a][i] + cn[b]] = (T)(alpha * ((double)acc[a][b][i] - sh * dv[b]) + cvv[b]);
-      }
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          const double d = Dp ? (double)dv[i][b] : (g.d_const ? 1.0 : 0.0);
+          const double c0 = g.accum ? (double)cvv[i][b] : 0.0;
+          if (rv[a][ri(i)] && cv[b][ci(i)])
+            C[cm[a][ri(i)] + cn[b][ci(i)]] = (T)(alpha * ((double)acc[a][b][i] - sh * d) + c0);
+        }
+    }
   }
 }
 
@@ -546,10 +574,11 @@ __global__ __launch_bounds__(256) void ogemm_splitk_kernel(KArgs g) {
 // walk the M rows in 16-row blocks, loading each lane's A row as 16-byte runs
 // of k (next block prefetched before the current block's MFMAs), and write C
 // through the output offset tables.  FP32 arithmetic.
+template <bool CMF>
 __global__ __launch_bounds__(256) void ogemm_narrow_kernel(KArgs g) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int z = blockIdx.x;
-  if (z >= g.nz) return;
+  if (z >= g.nz) return;  // no barriers below: waves may leave independently
   const int M = g.M, N = g.N, K = g.K;
   const float* __restrict__ A = (const float*)g.A.base + batch_off(g.A, z, g.z0, g.flag);
   const float* __restrict__ B = (const float*)g.B.base + batch_off(g.B, z, g.z0, g.flag);
@@ -559,64 +588,119 @@ __global__ __launch_bounds__(256) void ogemm_narrow_kernel(KArgs g) {
   const double sh = g.shift ? g.shift[g.z0 + z] : 0.0;
   const int r = lane & 15, q = lane >> 4;
   const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+  // k quads of this lane (K % 4 == 0: a quad lies wholly inside or outside [0, K));
+  // quads past K read quad 0 and are zeroed before use
+  const bool kq[2] = {4 * q < K, 16 + 4 * q < K};
+  const int kof[2] = {kq[0] ? 4 * q : 0, kq[1] ? 16 + 4 * q : 0};
   // B fragments: column r (+16), k = 16 h + 4 q .. +3
   floatx4 bq[2][2];
-  int cn[2];
-  bool cok[2];
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
     const int col = nb * 16 + r;
-    cok[nb] = col < N;
-    cn[nb] = cok[nb] ? g.c_on[col] : 0;
-    const float* bp = B + (cok[nb] ? g.b_on[col] : 0);
+    const bool ok = col < N;
+    const float* bp = B + (ok ? g.b_on[col] : 0);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int k = 16 * h + 4 * q;
-      bq[nb][h] = (cok[nb] && k < K) ? *(const floatx4*)(bp + k) : zero;
+      const floatx4 v = *(const floatx4*)(bp + kof[h]);
+      bq[nb][h] = (ok && kq[h]) ? v : zero;
     }
   }
-  auto load_a = [&](int mb, floatx4* aq) {
-    const int row = mb * 16 + r;
-    const bool ok = row < M;
-    const float* ap = A + (ok ? g.a_om[row] : 0);
+  // Output placement of acc[nb][e] for the 16-row block mb: without CMF row
+  // 16 mb + 4 q + e, column 16 nb + r (lanes along columns); with CMF the
+  // matrix-core operands are swapped and it is row 16 mb + r, column
+  // 16 nb + 4 q + e (lanes along rows, for outputs whose rows are unit-stride).
+  constexpr int RI = CMF ? 1 : 4, CI = CMF ? 4 : 1;
+  int cn[2][CI];
+  bool cok[2][CI];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = 16 * h + 4 * q;
-      aq[h] = (ok && k < K) ? *(const floatx4*)(ap + k) : zero;
+  for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+    for (int i = 0; i < CI; ++i) {
+      const int col = nb * 16 + (CMF ? 4 * q + i : r);
+      cok[nb][i] = col < N;
+      cn[nb][i] = cok[nb][i] ? g.c_on[col] : 0;
     }
-  };
+  auto ri = [](int e) { return CMF ? 0 : e; };
+  auto ci = [](int e) { return CMF ? e : 0; };
+  auto out_row = [&](int blk, int i) { return blk * 16 + (CMF ? r : 4 * q + i); };
   const int nmb = (M + 15) / 16;
-  floatx4 aq[2], an[2];
   int mb = wid;
-  if (mb < nmb) load_a(mb, aq);
+  if (mb >= nmb) return;
+  // Software pipeline over this wave's 16-row blocks mb, mb + 4, ...: while the
+  // current block is multiplied and written, the next block's A rows and output
+  // row offsets are in flight, and the row offset of the block after that.
+  // Rows past M are clamped to row 0 (read, never written).
+  auto clamp_row = [&](int row) { return row < M ? row : 0; };
+  int ao_next = g.a_om[clamp_row((mb + 4) * 16 + r)];
+  const float* ap = A + g.a_om[clamp_row(mb * 16 + r)];
+  floatx4 aq[2] = {*(const floatx4*)(ap + kof[0]), *(const floatx4*)(ap + kof[1])};
+  int cm[RI];
+#pragma unroll
+  for (int i = 0; i < RI; ++i) cm[i] = g.c_om[clamp_row(out_row(mb, i))];
+  const bool plain = !Dp && !g.d_const && !g.accum;
   for (; mb < nmb; mb += 4) {
-    if (mb + 4 < nmb) load_a(mb + 4, an);
+    // issue: the offset two blocks ahead first (the oldest load of this round
+    // is then the one the next round waits on), then the next block's data
+    const int ao_after = g.a_om[clamp_row((mb + 8) * 16 + r)];
+    const float* apn = A + ao_next;
+    floatx4 an[2] = {*(const floatx4*)(apn + kof[0]), *(const floatx4*)(apn + kof[1])};
+    int cmn[RI];
+#pragma unroll
+    for (int i = 0; i < RI; ++i) cmn[i] = g.c_om[clamp_row(out_row(mb + 4, i))];
     floatx4 acc[2] = {zero, zero};
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (16 * h >= K) break;
+      const floatx4 a = kq[h] ? aq[h] : zero;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[h][t], bq[0][h][t], acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[h][t], bq[1][h][t], acc[1], 0, 0, 0);
+        if constexpr (CMF) {
+          acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(bq[0][h][t], a[t], acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(bq[1][h][t], a[t], acc[1], 0, 0, 0);
+        } else {
+          acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], bq[0][h][t], acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], bq[1][h][t], acc[1], 0, 0, 0);
+        }
       }
     }
+    bool rok[RI];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int row = mb * 16 + 4 * q + e;
-      if (row >= M) continue;
-      const int cm = g.c_om[row];
+    for (int i = 0; i < RI; ++i) rok[i] = out_row(mb, i) < M;
+    if (plain) {
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        if (!cok[nb]) continue;
-        const int o = cm + cn[nb];
-        const double dv = Dp ? (double)Dp[o] : (g.d_const ? 1.0 : 0.0);
-        const double cv = g.accum ? (double)C[o] : 0.0;
-        C[o] = (float)(alpha * ((double)acc[nb][e] - sh * dv) + cv);
-      }
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          if (rok[ri(e)] && cok[nb][ci(e)]) C[cm[ri(e)] + cn[nb][ci(e)]] = (float)(alpha * (double)acc[nb][e]);
+    } else {
+      // all reads of the epilogue first (unconditional: a missing D reads C
+      // in its place and is replaced by its constant afterwards), then the writes
+      const float* __restrict__ ds = Dp ? Dp : C;
+      const float dc = g.d_const ? 1.f : 0.f;
+      float dv[4][2], cv[4][2];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          const int o = cm[ri(e)] + cn[nb][ci(e)];
+          dv[e][nb] = ds[o];
+          cv[e][nb] = C[o];
+        }
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          const double d = Dp ? (double)dv[e][nb] : (double)dc;
+          const double c0 = g.accum ? (double)cv[e][nb] : 0.0;
+          if (rok[ri(e)] && cok[nb][ci(e)])
+            C[cm[ri(e)] + cn[nb][ci(e)]] = (float)(alpha * ((double)acc[nb][e] - sh * d) + c0);
+        }
     }
     aq[0] = an[0];
     aq[1] = an[1];
+#pragma unroll
+    for (int i = 0; i < RI; ++i) cm[i] = cmn[i];
+    ao_next = ao_after;
   }
 }
 
@@ -647,10 +731,17 @@ static hipError_t launch_cfg(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s
   static const int remap_min = env_int("TTN_XCD_REMAP_MIN", 256);
   a.xcd_remap = nz >= remap_min ? 1 : 0;
   dim3 grid = a.xcd_remap ? dim3((unsigned)(((nz + 7) / 8) * 8 * a.tiles), 1) : dim3(tm * tn, nz);
-  if (gd.a_mfast && gd.b_nfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, true, true>), grid, dim3(256), 0, s, a);
-  else if (gd.a_mfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, true, false>), grid, dim3(256), 0, s, a);
-  else if (gd.b_nfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, false, true>), grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, false, false>), grid, dim3(256), 0, s, a);
+  if (gd.c_mfast) {
+    if (gd.a_mfast && gd.b_nfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, true, true, true>), grid, dim3(256), 0, s, a);
+    else if (gd.a_mfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, true, false, true>), grid, dim3(256), 0, s, a);
+    else if (gd.b_nfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, false, true, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, false, false, true>), grid, dim3(256), 0, s, a);
+  } else {
+    if (gd.a_mfast && gd.b_nfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, true, true, false>), grid, dim3(256), 0, s, a);
+    else if (gd.a_mfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, true, false, false>), grid, dim3(256), 0, s, a);
+    else if (gd.b_nfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, false, true, false>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, false, false, false>), grid, dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -667,15 +758,9 @@ static hipError_t launch_tile(const GemmDesc& gd, KArgs& a, int nz, hipStream_t 
   }
 }
 
-// k-slice depth: 16 for FP32 and FP64 (measured on the hot-path shapes: the
+// k-slice depth: 16 for FP32 and FP64 (measured on the hot-path shapes: a
 // deeper FP32 slice costs occupancy and never paid), 32 for bf16 (one MFMA).
-static int pick_bk(int ctype, const GemmDesc& gd) {
-  if (ctype == 0 || ctype == 3) return 16;
-  if (ctype == 2) return 32;
-  static const int mode = env_int("TTN_BK_MODE", 16);  // measured: 16 is as good or better everywhere
-  (void)gd;
-  return mode == 32 ? 32 : 16;
-}
+static int pick_bk(int ctype) { return ctype == 2 ? 32 : 16; }
 
 template <int CT>
 static hipError_t launch_wave(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s) {
@@ -711,7 +796,8 @@ static hipError_t launch_ct(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s)
     if (CT != 0 && narrow_eligible(gd, CT) && aligned16(a.A) && aligned16(a.B)) {
       a.nz = nz;
       a.xcd_remap = 0;
-      hipLaunchKernelGGL(ogemm_narrow_kernel, dim3((unsigned)nz), dim3(256), 0, s, a);
+      if (gd.c_mfast) hipLaunchKernelGGL(ogemm_narrow_kernel<true>, dim3((unsigned)nz), dim3(256), 0, s, a);
+      else hipLaunchKernelGGL(ogemm_narrow_kernel<false>, dim3((unsigned)nz), dim3(256), 0, s, a);
       return hipGetLastError();
     }
     GemmDesc g2 = gd;
@@ -727,30 +813,25 @@ static hipError_t launch_ct(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s)
       return launch_wave<CT>(gd, a, nz, s);
     }
   }
-  if constexpr (CT == 1) {
-    if (pick_bk(CT, gd) == 16) return launch_tile<CT, 16>(gd, a, nz, s);
-    return launch_tile<CT, 32>(gd, a, nz, s);
-  } else {
-    return launch_tile<CT, (CT == 0 || CT == 3) ? 16 : 32>(gd, a, nz, s);
-  }
+  return launch_tile<CT, (CT == 2) ? 32 : 16>(gd, a, nz, s);
 }
 
-static int pick_bk(int ctype, const GemmDesc& gd);
 
 std::string gemm_kernel_name(int ctype, const GemmDesc& gd) {
   static const int bm[] = {128, 64, 128, 64, 32, 64, 32};
   static const int bn[] = {128, 64, 64, 128, 64, 32, 32};
   if (gd.tile == 8) return "ogemm_splitk_kernel";
-  if (gd.tile == 9) return "ogemm_narrow_kernel";
+  if (gd.tile == 9) return std::string("ogemm_narrow_kernel<") + (gd.c_mfast ? "true" : "false") + ">";
   if (gd.tile == 7) {
     const int tmw = gd.M <= 16 ? 1 : 2, tnw = gd.N <= 16 ? 1 : 2;
     return "ogemm_wave_kernel<" + std::to_string(ctype == 2 ? 1 : ctype) + ", " + std::to_string(tmw) + ", " +
            std::to_string(tnw) + ">";
   }
   const int t = gd.tile < 0 || gd.tile > 6 ? 6 : gd.tile;
-  const int bk = pick_bk(ctype, gd);
+  const int bk = pick_bk(ctype);
   return "ogemm_kernel<" + std::to_string(ctype) + ", " + std::to_string(bm[t]) + ", " + std::to_string(bn[t]) + ", " +
-         std::to_string(bk) + ", " + (gd.a_mfast ? "true" : "false") + ", " + (gd.b_nfast ? "true" : "false") + ">";
+         std::to_string(bk) + ", " + (gd.a_mfast ? "true" : "false") + ", " + (gd.b_nfast ? "true" : "false") + ", " +
+         (gd.c_mfast ? "true" : "false") + ">";
 }
 
 hipError_t launch_gemm(int ctype, const GemmDesc& gd, const OpAddr& A, const OpAddr& B, const OpAddr& C,

@@ -39,6 +39,7 @@ struct GemmDesc {
   const int32_t* c_om = nullptr;  // [M]
   const int32_t* c_on = nullptr;  // [N]
   bool a_mfast = false, b_nfast = true;
+  bool c_mfast = false;  // the output's unit-stride label is a row label (lanes should run along rows)
   int tile = 0;                   // tile configuration id (8: split-K skinny kernel, 9: narrow kernel)
   // host facts about the tables, for the split-K skinny kernel: k offsets are
   // exactly k (a_ok[k] == k, b_ok[k] == k) and every row (column) offset of A

@@ -290,22 +290,6 @@ std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<in
     g.M = (int)M;
     g.N = (int)N;
     g.K = (int)K;
-    // fast flags: where is each operand's smallest stride
-    auto smallest = [&](const Live& l) {
-      int best = -1;
-      int64_t bs = INT64_MAX;
-      for (int x : l.lab)
-        if (l.str.at(x) < bs) {
-          bs = l.str.at(x);
-          best = x;
-        }
-      return best;
-    };
-    const int sa_min = smallest(la), sb_min = smallest(lb);
-    g.a_mfast = std::find(ml.begin(), ml.end(), sa_min) != ml.end();
-    g.b_nfast = std::find(nl.begin(), nl.end(), sb_min) != nl.end();
-    if (ml.empty()) g.a_mfast = false;
-    if (nl.empty()) g.b_nfast = false;
 
     // output layout
     Live lo;
@@ -370,6 +354,45 @@ std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<in
     }
     lo.str = ostr;
     stp.out = lo.id;
+    // Row and column order.  The matrix rows run over ml in the order listed
+    // (last label fastest), likewise the columns over nl; they start sorted by
+    // the operand's own strides.  The output's unit-stride label f should be
+    // the fastest row (or column) index, or the kernels write one element per
+    // memory run; it is moved there unless that breaks an m-fast (n-fast) read
+    // of a larger operand (A read M*K against C written M*N).
+    auto smallest = [&](const std::map<int, int64_t>& str, const std::vector<int>& labs) {
+      int best = -1;
+      int64_t bs = INT64_MAX;
+      for (int x : labs) {
+        auto it = str.find(x);
+        if (it != str.end() && it->second < bs) {
+          bs = it->second;
+          best = x;
+        }
+      }
+      return best;
+    };
+    {
+      std::vector<int> mn(ml);
+      mn.insert(mn.end(), nl.begin(), nl.end());
+      const int f = smallest(ostr, mn);
+      auto move_last = [&](std::vector<int>& v, int x) {
+        v.erase(std::find(v.begin(), v.end(), x));
+        v.push_back(x);
+      };
+      const int sa = smallest(la.str, la.lab), sb = smallest(lb.str, lb.lab);
+      if (f >= 0 && std::find(ml.begin(), ml.end(), f) != ml.end() && ml.back() != f) {
+        const bool a_rows_fast = ml.back() == sa;
+        if (!a_rows_fast || N >= K) move_last(ml, f);
+      } else if (f >= 0 && std::find(nl.begin(), nl.end(), f) != nl.end() && nl.back() != f) {
+        const bool b_cols_fast = nl.back() == sb;
+        if (!b_cols_fast || M >= K) move_last(nl, f);
+      }
+      // fast flags: is an operand's unit-stride label its fastest row / column
+      g.a_mfast = !ml.empty() && ml.back() == sa;
+      g.b_nfast = !nl.empty() && nl.back() == sb;
+      g.c_mfast = !ml.empty() && (nl.empty() || ml.back() == f);
+    }
     // tables
     std::vector<int32_t> t_am, t_ak, t_bk, t_bn, t_cm, t_cn;
     group_offsets(ml, dims, la.str, t_am);
