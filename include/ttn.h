@@ -59,7 +59,8 @@ enum {
   TTN_E_WORKSPACE = 5,  /* workspace too small even for one state */
   TTN_E_LAUNCH = 6,     /* kernel launch failed */
   TTN_E_NOT_PD = 7,     /* overlap matrix not positive definite and SVQB disabled */
-  TTN_E_NONFINITE = 8   /* NaN/Inf flagged by a kernel (surfaced at ttn_ctx_sync) */
+  TTN_E_NONFINITE = 8,  /* NaN/Inf flagged by a kernel (surfaced at ttn_ctx_sync) */
+  TTN_E_NOCONV = 9      /* an iterative dense eigensolver did not converge (surfaced at ttn_ctx_sync) */
 };
 
 /* TTN_F64_F32 is a compute dtype only: FP64 tensors, FP32 matrix-core
@@ -177,7 +178,9 @@ ttn_status heff_apply_block(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
  * (column j = eigenvector j, V^T S~ V = I, largest-magnitude entry of each
  * column positive); rank_out int32[batch] (m[b] or the SVQB rank).
  * allow_svqb = 0 makes a non-positive-definite S~ an error (TTN_E_NOT_PD,
- * reported at ttn_ctx_sync). */
+ * reported at ttn_ctx_sync).  The symmetric eigenproblems are solved by
+ * Householder tridiagonalisation and implicit QL; a QL iteration that does not
+ * converge is reported as TTN_E_NOCONV at ttn_ctx_sync. */
 ttn_status rayleigh_ritz(ttn_ctx* ctx, int32_t batch, const int32_t* m, int32_t ld, const double* H,
                          const double* S, int32_t nev, double drop_tol, int32_t allow_svqb,
                          double* evals, double* V, int32_t* rank_out);

@@ -413,11 +413,12 @@ ttn_status ttn_ctx_sync(ttn_ctx* ctx) {
   int f[4];
   HIPCHK(ctx, hipMemcpyAsync(f, ctx->d_flag, sizeof(f), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  if (f[0] || f[1] || f[2]) {
+  if (f[0] || f[1] || f[2] || f[3]) {
     HIPCHK(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(f), ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     if (f[2]) return fail(ctx, TTN_E_ARG, "a pair / row index table held an out-of-range index (clamped)");
     if (f[0]) return fail(ctx, TTN_E_NONFINITE, "a kernel produced a non-finite value");
+    if (f[3]) return fail(ctx, TTN_E_NOCONV, "the symmetric eigensolver of Rayleigh-Ritz did not converge");
     return fail(ctx, TTN_E_NOT_PD, "overlap matrix not positive definite (SVQB disabled)");
   }
   return TTN_OK;

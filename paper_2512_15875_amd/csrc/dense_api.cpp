@@ -4,6 +4,8 @@
 #include <cstring>
 #include <sstream>
 
+#include <string>
+
 #include "internal.h"
 
 using namespace ttn;
@@ -120,11 +122,13 @@ ttn_status ttn_block_move_centre(ttn_ctx* ctx, ttn_block* b, int32_t u, int32_t 
   // Householder QR with explicit Q: 4 m n^2 - 4 n^3 / 3 flops per state; the
   // tensor is read and written once, R written once
   const double fq = 4.0 * m_u * (double)n * n - 4.0 * (double)n * n * n / 3.0;
-  ttn_prof_rec* pr = prof_begin(ctx, "qr", "qr_kernel", fq * k, (double)k * (2.0 * m_u * n * es + 8.0 * n * n), k);
+  const std::string qkey = "qr:" + std::to_string(m_u) + "x" + std::to_string(n);
+  ttn_prof_rec* pr = prof_begin(ctx, qkey.c_str(), "qr_kernel", fq * k, (double)k * (2.0 * m_u * n * es + 8.0 * n * n), k);
   hipError_t e = launch_qr(ct, b->ptr[u], b->size[u], ru, m_u, n, cs_u, wk, R, k, ctx->d_flag, ctx->stream);
   prof_end(ctx, pr);
   if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
-  pr = prof_begin(ctx, "absorb", "absorb_kernel", 2.0 * m_v * (double)n * n * k,
+  const std::string akey = "absorb:" + std::to_string(m_v) + "x" + std::to_string(n);
+  pr = prof_begin(ctx, akey.c_str(), "absorb_kernel", 2.0 * m_v * (double)n * n * k,
                   (double)k * (2.0 * m_v * n * es + 8.0 * n * n), k);
   e = launch_absorb(ct, b->ptr[v], b->size[v], rv, m_v, n, cs_v, R, Y, k, ctx->stream);
   prof_end(ctx, pr);

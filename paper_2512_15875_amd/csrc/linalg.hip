@@ -1,8 +1,8 @@
 // FP64 dense linear algebra of the hot path, on the device:
 //  * Rayleigh-Ritz for the LOBPCG / inverse-iteration subspaces (one
 //    workgroup per problem): Cholesky of the overlap (SVQB fallback through a
-//    Jacobi eigendecomposition of the overlap), reduction to a standard
-//    symmetric problem, cyclic parallel Jacobi eigensolver, back-transform;
+//    eigendecomposition of the overlap), reduction to a standard symmetric
+//    problem, tridiagonalisation + implicit QL eigensolver, back-transform;
 //  * the QR gauge move of a block (one workgroup per state, Householder);
 //  * per-state norms and scaling of node tensors.
 // Everything accumulates in double, whatever the storage dtype.
@@ -31,83 +31,184 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return r;
 }
 
-// Cyclic Jacobi on the symmetric n x n matrix A (row-major, leading dim ld) in
-// global memory; V (n x n, ld) receives the eigenvectors (columns).  Parallel
-// ordering: round-robin tournament of n' = n rounded up to even players.
-__device__ void jacobi_eig(double* A, double* V, int n, int ld, double* sh_c, double* sh_s, int* sh_p, int* sh_q,
-                           double* red) {
-  const int t = threadIdx.x;
-  for (int i = t; i < n * n; i += blockDim.x) {
-    const int r = i / n, c = i - r * n;
-    V[r * ld + c] = (r == c) ? 1.0 : 0.0;
+__device__ __forceinline__ double wave_sum64(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Symmetric eigendecomposition of the n x n matrix A (row-major, leading dim
+// ld, global memory; destroyed).  Householder reduction to tridiagonal form
+// A = Q T Q^T with Q formed explicitly in Z (backward accumulation), then the
+// implicit QL iteration with a Wilkinson-type shift on T (the classical
+// tql2-type scheme, Bowdler, Martin, Reinsch and Wilkinson 1968): one thread
+// chases each bulge and records the sweep's plane rotations, then every
+// thread applies them to its own rows of Z.  On return the eigenvalues are
+// on the diagonal of A and the eigenvectors are the columns of Z.  A QL
+// iteration that has not converged after 30 sweeps for one eigenvalue raises
+// flag[3].  Shared arrays of at least n doubles: rc, rs, v, w, d, e, tv.
+__device__ void sym_eig(double* A, double* Z, int n, int ld, double* rc, double* rs, double* v, double* w,
+                        double* d, double* e, double* tv, double* red, int* flag) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
+  __shared__ int s_lo, s_hi;
+  // ---- tridiagonalisation: step k zeroes column k below the subdiagonal
+  for (int k = 0; k + 2 < n; ++k) {
+    const int len = n - k - 1;  // x = A[k+1 .. n-1][k]
+    double s2 = 0;
+    for (int i = t; i < len; i += blockDim.x) {
+      const double x = A[(size_t)(k + 1 + i) * ld + k];
+      s2 += x * x;
+    }
+    s2 = block_sum(s2, red);
+    const double x0 = A[(size_t)(k + 1) * ld + k];
+    const double nrm = sqrt(s2);
+    const double alpha = nrm == 0.0 ? 0.0 : (x0 >= 0 ? -nrm : nrm);
+    const double v0 = x0 - alpha;
+    const double vn2 = s2 - x0 * x0 + v0 * v0;
+    const double tk = vn2 > 0 ? 2.0 / vn2 : 0.0;  // reflector I - tk v v^T, v = x - alpha e_1
+    for (int i = t; i < len; i += blockDim.x) v[i] = i == 0 ? v0 : A[(size_t)(k + 1 + i) * ld + k];
+    if (t == 0) {
+      d[k] = A[(size_t)k * ld + k];
+      e[k] = tk == 0.0 ? x0 : alpha;
+      tv[k] = tk;
+    }
+    __syncthreads();
+    if (tk == 0.0) continue;  // uniform: nothing to reflect
+    // w = tk * A_sub v (one wave per row, lanes along the row)
+    for (int i = wv; i < len; i += nw) {
+      const double* row = A + (size_t)(k + 1 + i) * ld + (k + 1);
+      double sacc = 0;
+      for (int j = lane; j < len; j += 64) sacc += row[j] * v[j];
+      sacc = wave_sum64(sacc);
+      if (lane == 0) w[i] = tk * sacc;
+    }
+    __syncthreads();
+    double pv = 0;
+    for (int i = t; i < len; i += blockDim.x) pv += w[i] * v[i];
+    pv = block_sum(pv, red);
+    const double kc = 0.5 * tk * pv;
+    for (int i = t; i < len; i += blockDim.x) w[i] -= kc * v[i];
+    __syncthreads();
+    // A_sub -= v w^T + w v^T; v kept in column k for Q
+    for (int q = t; q < len * len; q += blockDim.x) {
+      const int i = q / len, j = q - i * len;
+      A[(size_t)(k + 1 + i) * ld + (k + 1 + j)] -= v[i] * w[j] + w[i] * v[j];
+    }
+    for (int i = t; i < len; i += blockDim.x) A[(size_t)(k + 1 + i) * ld + k] = v[i];
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (n >= 2) {
+      d[n - 2] = A[(size_t)(n - 2) * ld + (n - 2)];
+      e[n - 2] = A[(size_t)(n - 1) * ld + (n - 2)];
+    }
+    d[n - 1] = A[(size_t)(n - 1) * ld + (n - 1)];
+    if (n >= 2) tv[n - 2] = 0.0;
+  }
+  // ---- Q = H_0 H_1 ... H_{n-3}, accumulated backward into Z
+  for (int q = t; q < n * n; q += blockDim.x) {
+    const int r = q / n, c = q - r * n;
+    Z[(size_t)r * ld + c] = r == c ? 1.0 : 0.0;
   }
   __syncthreads();
-  const int np = (n + 1) & ~1;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    double off = 0, tot = 0;
-    for (int i = t; i < n * n; i += blockDim.x) {
-      const int r = i / n, c = i - r * n;
-      const double a = A[r * ld + c];
-      if (r != c) off += a * a;
-      tot += a * a;
+  for (int k = n - 3; k >= 0; --k) {
+    const double tk = tv[k];
+    if (tk == 0.0) continue;  // uniform
+    const int len = n - k - 1;
+    for (int i = t; i < len; i += blockDim.x) v[i] = A[(size_t)(k + 1 + i) * ld + k];
+    __syncthreads();
+    // w_j = sum_i v_i Z[k+1+i][k+1+j]  (thread per column: coalesced along rows of Z)
+    for (int j = t; j < len; j += blockDim.x) {
+      double sacc = 0;
+      for (int i = 0; i < len; ++i) sacc += v[i] * Z[(size_t)(k + 1 + i) * ld + (k + 1 + j)];
+      w[j] = tk * sacc;
     }
-    off = block_sum(off, red);
-    tot = block_sum(tot, red);
-    if (off <= 1e-30 * tot || off == 0.0) break;
-    for (int round = 0; round < np - 1; ++round) {
-      // pairing: player 0 fixed, the rest rotate
-      for (int i = t; i < np / 2; i += blockDim.x) {
-        int a = (i == 0) ? 0 : 1 + (i - 1 + round) % (np - 1);
-        int b = 1 + (np - 2 - i + round) % (np - 1);
-        if (a > b) {
-          const int x = a;
-          a = b;
-          b = x;
+    __syncthreads();
+    for (int q = t; q < len * len; q += blockDim.x) {
+      const int i = q / len, j = q - i * len;
+      Z[(size_t)(k + 1 + i) * ld + (k + 1 + j)] -= v[i] * w[j];
+    }
+    __syncthreads();
+  }
+  // ---- implicit QL on (d, e), rotations accumulated into the columns of Z.
+  // A subdiagonal entry is negligible below eps times the larger of its two
+  // diagonal neighbours and the norm of T (the norm-wise test keeps zero or
+  // tiny eigenvalue clusters from stalling the relative one).
+  __shared__ double s_tn;
+  if (t == 0) {
+    double tn = 0;
+    for (int i = 0; i < n; ++i) tn = fmax(tn, fabs(d[i]) + (i + 1 < n ? fabs(e[i]) : 0.0));
+    s_tn = tn;
+  }
+  __syncthreads();
+  const double tnorm = s_tn;
+  for (int l = 0; l < n; ++l) {
+    for (int iter = 0;; ++iter) {
+      if (t == 0) {
+        int m = l;
+        for (; m + 1 < n; ++m) {
+          const double dd = fabs(d[m]) + fabs(d[m + 1]);
+          if (fabs(e[m]) <= 2.220446049250313e-16 * fmax(dd, tnorm)) break;
         }
-        sh_p[i] = a;
-        sh_q[i] = b;
-        double c = 1.0, s = 0.0;
-        if (b < n) {
-          const double apq = A[a * ld + b];
-          if (apq != 0.0) {
-            const double app = A[a * ld + a], aqq = A[b * ld + b];
-            const double theta = (aqq - app) / (2.0 * apq);
-            const double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
-            c = 1.0 / sqrt(1.0 + tt * tt);
-            s = tt * c;
+        s_lo = 1;
+        s_hi = 0;  // empty: converged
+        if (m != l && iter >= 30) {
+          atomicOr(flag + 3, 1);
+        } else if (m != l) {
+          // shift from the leading 2 x 2 block, then chase the bulge upward from m
+          double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+          double r = hypot(g, 1.0);
+          g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+          double sn = 1.0, cs = 1.0, pp = 0.0;
+          int i = m - 1;
+          bool split = false;
+          for (; i >= l; --i) {
+            const double f = sn * e[i], b = cs * e[i];
+            r = hypot(f, g);
+            e[i + 1] = r;
+            if (r == 0.0) {  // the rotation would be undefined: T splits here
+              d[i + 1] -= pp;
+              e[m] = 0.0;
+              split = true;
+              break;
+            }
+            sn = f / r;
+            cs = g / r;
+            g = d[i + 1] - pp;
+            r = (d[i] - g) * sn + 2.0 * cs * b;
+            pp = sn * r;
+            d[i + 1] = g + pp;
+            g = cs * r - b;
+            rc[i] = cs;
+            rs[i] = sn;
           }
+          if (!split) {
+            d[l] -= pp;
+            e[l] = g;
+            e[m] = 0.0;
+          }
+          s_hi = m - 1;
+          s_lo = split ? i + 1 : l;
         }
-        sh_c[i] = c;
-        sh_s[i] = s;
       }
       __syncthreads();
-      // rows: A <- J^T A
-      for (int e = t; e < (np / 2) * n; e += blockDim.x) {
-        const int i = e / n, col = e - i * n;
-        const int p = sh_p[i], q = sh_q[i];
-        if (q >= n) continue;
-        const double c = sh_c[i], s = sh_s[i];
-        const double ap = A[p * ld + col], aq = A[q * ld + col];
-        A[p * ld + col] = c * ap - s * aq;
-        A[q * ld + col] = s * ap + c * aq;
+      const int lo = s_lo, hi = s_hi;
+      if (lo > hi) {
+        __syncthreads();
+        break;  // uniform: eigenvalue l converged (or gave up)
       }
-      __syncthreads();
-      // columns: A <- A J ; V <- V J
-      for (int e = t; e < (np / 2) * n; e += blockDim.x) {
-        const int i = e / n, row = e - i * n;
-        const int p = sh_p[i], q = sh_q[i];
-        if (q >= n) continue;
-        const double c = sh_c[i], s = sh_s[i];
-        const double ap = A[row * ld + p], aq = A[row * ld + q];
-        A[row * ld + p] = c * ap - s * aq;
-        A[row * ld + q] = s * ap + c * aq;
-        const double vp = V[row * ld + p], vq = V[row * ld + q];
-        V[row * ld + p] = c * vp - s * vq;
-        V[row * ld + q] = s * vp + c * vq;
+      for (int r = t; r < n; r += blockDim.x) {
+        double* zr = Z + (size_t)r * ld;
+        for (int i = hi; i >= lo; --i) {
+          const double f = zr[i + 1];
+          zr[i + 1] = rs[i] * zr[i] + rc[i] * f;
+          zr[i] = rc[i] * zr[i] - rs[i] * f;
+        }
       }
       __syncthreads();
     }
   }
+  for (int i = t; i < n; i += blockDim.x) A[(size_t)i * ld + i] = d[i];
+  __syncthreads();
 }
 
 // One problem per workgroup.  Scratch per problem: 4 ld^2 doubles.
@@ -115,8 +216,7 @@ __global__ __launch_bounds__(NT) void rr_kernel(const int32_t* m_arr, int ld, co
                                                 int nev, double drop_tol, int allow_svqb, double* evals, double* Vout,
                                                 int32_t* rank_out, double* scratch, int* flag) {
   __shared__ double red[NT];
-  __shared__ double sh_c[512], sh_s[512];
-  __shared__ int sh_p[512], sh_q[512];
+  __shared__ double sh_c[512], sh_s[512], sh_v[512], sh_w[512], sh_d[512], sh_e[512], sh_t[512];
   __shared__ double piv[512];
   __shared__ int sh_ord[512];
   __shared__ int use_chol, rank_sh;
@@ -209,7 +309,7 @@ __global__ __launch_bounds__(NT) void rr_kernel(const int32_t* m_arr, int ld, co
       C[a * ld + c] = 0.5 * (Sb[a * ld + c] + Sb[c * ld + a]);
     }
     __syncthreads();
-    jacobi_eig(C, Y, m, ld, sh_c, sh_s, sh_p, sh_q, red);
+    sym_eig(C, Y, m, ld, sh_c, sh_s, sh_v, sh_w, sh_d, sh_e, sh_t, red, flag);
     // eigenvalues on the diagonal of C; select kept columns (in index order)
     if (t == 0) {
       double smax = 0;
@@ -257,7 +357,7 @@ __global__ __launch_bounds__(NT) void rr_kernel(const int32_t* m_arr, int ld, co
     __syncthreads();
   }
   // eigen-decomposition of the reduced r x r problem: C -> diag, Y eigenvectors
-  jacobi_eig(C, Y, r, ld, sh_c, sh_s, sh_p, sh_q, red);
+  sym_eig(C, Y, r, ld, sh_c, sh_s, sh_v, sh_w, sh_d, sh_e, sh_t, red, flag);
   // order eigenvalues ascending
   if (t == 0) {
     for (int i = 0; i < r; ++i) sh_ord[i] = i;

@@ -105,6 +105,68 @@ def test_qr_move_matches_oracle(api, ctx, dt, D):
             assert np.linalg.norm(got[j] - ref) <= tol * max(1.0, np.linalg.norm(ref)), (u, j)
 
 
+@pytest.mark.parametrize("kind", ["cond1e3", "cond1e10", "rank_deficient"])
+@pytest.mark.parametrize("dt", [0, 1])
+def test_qr_move_conditioning(api, ctx, dt, kind):
+    """Gauge moves on node matrices of controlled conditioning (condition
+    number 1e3, 1e10, and half the singular values zero): the moved centre is
+    an isometry toward v and the two-site tensor of u and v is unchanged; the
+    well-conditioned case also matches the oracle's QR."""
+    m = wl.quartic_force_field(8, 21, 20, 30)
+    tree = wl.fork_tree(m.dims, 4, 1)
+    bonds = wl.bond_dims(tree, 7)
+    k = 3
+    blk_np = wl.random_block(tree, bonds, k, 45)
+    u, v = 10, 3  # a 91 x 7 node matrix
+    lu, lv = ottn.leg_of(tree, u, v), ottn.leg_of(tree, v, u)
+    rng = np.random.default_rng(7)
+    if dt == 1 and kind == "cond1e10":
+        pytest.skip("FP32 storage rounds such a matrix to a lower rank")
+    for j in range(k):
+        T = np.moveaxis(blk_np[j][u], lu, -1)
+        sh = T.shape
+        rows, De = int(np.prod(sh[:-1])), sh[-1]
+        U, _ = np.linalg.qr(rng.normal(size=(rows, De)))
+        V, _ = np.linalg.qr(rng.normal(size=(De, De)))
+        if kind == "cond1e3":
+            sv = np.geomspace(1.0, 1e-3, De)
+        elif kind == "cond1e10":
+            sv = np.geomspace(1.0, 1e-10, De)
+        else:
+            sv = np.linspace(1.0, 0.5, De)
+            sv[De // 2:] = 0.0
+        B = (U * sv) @ V.T
+        blk_np[j][u] = np.moveaxis(B.reshape(sh), -1, lu)
+    gt = api.Tree(tree.parent, tree.phys)
+    tdt = torch.float64 if dt == 0 else torch.float32
+    blk = api.Block(ctx, gt, k, [max(1, b) for b in bonds], dt)
+    for w in range(tree.n):
+        blk.t[w].copy_(to_dev(np.stack([blk_np[j][w] for j in range(k)]), tdt))
+    before = [np.tensordot(blk_np[j][u], blk_np[j][v], axes=([lu], [lv])) for j in range(k)]
+    api.block_move_centre(ctx, blk, u, v)
+    ctx.sync()
+    gu = blk.t[u].double().cpu().numpy()
+    gv = blk.t[v].double().cpu().numpy()
+    eps = 1e-13 if dt == 0 else 3e-6
+    for j in range(k):
+        Q = np.moveaxis(gu[j], lu, -1).reshape(-1, gu[j].shape[lu])
+        if kind != "rank_deficient":
+            assert np.abs(Q.T @ Q - np.eye(Q.shape[1])).max() < 50 * eps, (kind, j)
+        else:
+            # columns past the rank carry no weight; those that do stay orthonormal
+            G = Q.T @ Q
+            nz = np.abs(np.diag(G)) > 0.5
+            assert np.abs(G[np.ix_(nz, nz)] - np.eye(int(nz.sum()))).max() < 50 * eps, (kind, j)
+        after = np.tensordot(gu[j], gv[j], axes=([lu], [lv]))
+        assert np.linalg.norm(after - before[j]) <= 50 * eps * np.linalg.norm(before[j]), (kind, j)
+        if kind == "cond1e3":
+            ref = [a.copy() for a in blk_np[j]]
+            ottn.move_centre(tree, ref, u, v)
+            tol = 1e-9 if dt == 0 else 5e-3
+            assert np.linalg.norm(gu[j] - ref[u]) <= tol * np.linalg.norm(ref[u]), (kind, j)
+            assert np.linalg.norm(gv[j] - ref[v]) <= tol * np.linalg.norm(ref[v]), (kind, j)
+
+
 def test_node_norms_and_scale(api, ctx):
     tree = wl.binary_tree([3, 4, 5])
     bonds = wl.bond_dims(tree, 4)
