@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <sstream>
@@ -603,11 +604,70 @@ ttn_status ttno_env_update(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, 
   for (int c : t->nb[u])
     if (c != v && !envs->slot[ttn_envs::dslot(t, c, u)]) return fail(ctx, TTN_E_ARG, "missing incoming environment");
   if (!envs->slot[ttn_envs::dslot(t, u, v)]) return fail(ctx, TTN_E_ARG, "missing output environment");
+  const int ct = ctype_of(compute);
+  const int kap = (int)t->nb[u].size();
+  {
+    // three virtual legs, no physical leg, identity operator, FP32 storage,
+    // equal bra / ket bonds <= 32: the fused kernel (intermediates in LDS)
+    bool fuse = !op && kap == 3 && t->phys[u] == 1 && (ct == 1 || ct == 2) && bra->dt == TTN_F32 &&
+                ket->dt == TTN_F32 && envs->dt == TTN_F32;
+    const char* fe = getenv("TTN_FUSED_IENV");
+    if (fe && fe[0] == '0') fuse = false;
+    IEnv3Args fa;
+    if (fuse) {
+      for (int i = 0; i < 3 && fuse; ++i) {
+        const int c = t->nb[u][i];
+        fa.dim[i] = bra->bond(u, c);
+        fuse = fa.dim[i] == ket->bond(u, c) && fa.dim[i] >= 1 && fa.dim[i] <= 32 && envs->eb(u, c) == fa.dim[i] &&
+               envs->ea(u, c) == fa.dim[i];
+      }
+    }
+    if (fuse) {
+      const int iv = t->leg_of(u, v);
+      fa.o = iv;
+      fa.p = iv == 0 ? 1 : 0;
+      fa.q = iv == 2 ? 1 : 2;
+      fuse = ienv3_lds_bytes(fa.dim[fa.o], fa.dim[fa.p], fa.dim[fa.q]) <= IENV3_LDS_MAX;
+    }
+    if (fuse) {
+      fa.stride[2] = 1;
+      fa.stride[1] = fa.dim[2];
+      fa.stride[0] = fa.dim[1] * fa.dim[2];
+      fa.bra = (const float*)bra->ptr[u];
+      fa.ket = (const float*)ket->ptr[u];
+      fa.bra_size = bra->size[u];
+      fa.ket_size = ket->size[u];
+      fa.pb = pair_bra;
+      fa.pk = pair_ket;
+      fa.bra_rows = bra->k;
+      fa.ket_rows = ket->k;
+      const int cp = t->nb[u][fa.p], cq = t->nb[u][fa.q];
+      fa.Ep = (const float*)envs->slot[ttn_envs::dslot(t, cp, u)];
+      fa.Eq = (const float*)envs->slot[ttn_envs::dslot(t, cq, u)];
+      fa.Eo = (float*)envs->slot[ttn_envs::dslot(t, u, v)];
+      fa.ep_stride = envs->slot_elems(cp, u);
+      fa.eq_stride = envs->slot_elems(cq, u);
+      fa.eo_stride = envs->slot_elems(u, v);
+      fa.n = n_pairs;
+      fa.flag = ctx->d_flag;
+      const double Do = fa.dim[fa.o], Dp = fa.dim[fa.p], Dq = fa.dim[fa.q];
+      const double per = 2.0 * Do * Dp * Dq * (Dp + Dq + Do);  // the three products of the staged path
+      ctx->flops_done += per * n_pairs;
+      std::ostringstream key;
+      key << "ienv:" << u << ">" << v;
+      const std::string ks = key.str();
+      // compulsory bytes: bra and ket tensors, two environments in, one out
+      const double bytes = 4.0 * n_pairs * (2.0 * Do * Dp * Dq + Dp * Dp + Dq * Dq + Do * Do);
+      ttn_prof_rec* pr = prof_begin(ctx, ks.c_str(), "ienv3_kernel", per * n_pairs, bytes, n_pairs);
+      hipError_t he = launch_ienv3(fa, ctx->stream);
+      prof_end(ctx, pr);
+      if (he != hipSuccess) return fail(ctx, TTN_E_LAUNCH, std::string("fused environment: ") + hipGetErrorString(he));
+      return TTN_OK;
+    }
+  }
   Net net;
   std::string why;
   if (!build_env_net(t, op, bra, ket, envs, u, v, net, why)) return fail(ctx, TTN_E_SHAPE, why);
-  const int ct = ctype_of(compute);
-  const int kap = (int)t->nb[u].size();
   if (net.in.size() < 2) {
     // degenerate network (all legs trivial): not reachable for a tree node with a bond
     return fail(ctx, TTN_E_SHAPE, "degenerate environment network");

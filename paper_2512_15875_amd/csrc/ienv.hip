@@ -1,0 +1,247 @@
+// Fused identity-operator environment update for a node with three virtual
+// legs and no physical leg (the internal nodes of a binary tree whose modes sit
+// on the leaves), FP32 storage and FP32 matrix cores.
+//
+// The environment toward leg o of node u (Sec. II.B, the overlap
+// environments of the Gram step) is, for one (bra, ket) pair,
+//   E_o[x_o][y_o] = sum bra[x_o, x_p, x_q] E_p[x_p][y_p] E_q[x_q][y_q] ket[y_o, y_p, y_q],
+// with p, q the other two legs and E_p, E_q the incoming environments
+// (rows: bra bond, columns: ket bond).  One workgroup per pair:
+//   1. the ket tensor is staged in LDS as rows K_y = ket[y, :, :] (Dp x Dq);
+//   2. every wave takes rows y and replaces K_y in place by
+//      V_y = E_p K_y E_q^T (two small matrix-core products through a per-wave
+//      LDS tile);
+//   3. E_o = Bra V^T with Bra = bra viewed as Do x (Dp Dq): the Dp Dq
+//      contraction is split over the four waves, partial 32 x 32 blocks are
+//      summed through LDS and written.
+// The staged contraction path computes the same three products through HBM
+// intermediates; here they never leave the workgroup.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace ttn {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+#define IE_LD 33  // row stride of the 32 x 32 LDS tiles (one pad word)
+
+__global__ __launch_bounds__(256) void ienv3_kernel(IEnv3Args g) {
+  extern __shared__ float smem[];
+  const int Do = g.dim[g.o], Dp = g.dim[g.p], Dq = g.dim[g.q];
+  const int PQ = Dp * Dq;
+  const int PQS = PQ | 1;             // odd row stride: 16 consecutive rows in 16 LDS banks
+  float* sV = smem;                   // [Do][PQS]: K_y rows, then V_y rows
+  float* sEp = sV + Do * PQS;         // [32][IE_LD] zero-padded E_p[x_p][y_p]
+  float* sEq = sEp + 32 * IE_LD;      // [32][IE_LD] zero-padded E_q[x_q][y_q]
+  float* sT = sEq + 32 * IE_LD;       // 4 x [32][IE_LD] per-wave tiles
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int r = lane & 15, gq = lane >> 4;
+  const int z = blockIdx.x;
+  if (z >= g.n) return;  // uniform per workgroup, before any barrier
+  int ib = g.pb[z], ik = g.pk[z];
+  if (ib < 0 || ib >= g.bra_rows || ik < 0 || ik >= g.ket_rows) {  // clamp and report
+    if (tid == 0) atomicOr(g.flag + 2, 1);
+    ib = ib < 0 ? 0 : (ib >= g.bra_rows ? g.bra_rows - 1 : ib);
+    ik = ik < 0 ? 0 : (ik >= g.ket_rows ? g.ket_rows - 1 : ik);
+  }
+  const float* __restrict__ bra = g.bra + (int64_t)ib * g.bra_size;
+  const float* __restrict__ ket = g.ket + (int64_t)ik * g.ket_size;
+  const float* __restrict__ Ep = g.Ep + (int64_t)z * g.ep_stride;
+  const float* __restrict__ Eq = g.Eq + (int64_t)z * g.eq_stride;
+  float* __restrict__ Eo = g.Eo + (int64_t)z * g.eo_stride;
+
+  // ---- stage: ket in memory order -> sV[y_o][y_p * Dq + y_q]; environments zero-padded
+  const int D1 = g.dim[1], D2 = g.dim[2], D1D2 = D1 * D2;
+  const int n3 = g.dim[0] * D1D2;
+  // LDS strides of the three tensor legs, and the thread's tensor index
+  // advanced by 256 elements per round without divisions
+  int ls[3];
+  ls[g.o] = PQS;
+  ls[g.p] = Dq;
+  ls[g.q] = 1;
+  const int c0 = 256 / D1D2, c1 = (256 - c0 * D1D2) / D2, c2 = 256 - c0 * D1D2 - c1 * D2;
+  int i0 = tid / D1D2, i1 = (tid - i0 * D1D2) / D2, i2 = tid - i0 * D1D2 - i1 * D2;
+  // eight loads in flight per thread, then their stores
+  for (int e0 = tid; e0 < n3; e0 += 256 * 8) {
+    float kv8[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = e0 + 256 * j;
+      kv8[j] = ket[e < n3 ? e : 0];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = e0 + 256 * j;
+      if (e < n3) sV[i0 * ls[0] + i1 * ls[1] + i2 * ls[2]] = kv8[j];
+      i2 += c2;
+      if (i2 >= D2) {
+        i2 -= D2;
+        ++i1;
+      }
+      i1 += c1;
+      if (i1 >= D1) {
+        i1 -= D1;
+        ++i0;
+      }
+      i0 += c0;
+    }
+  }
+  for (int e = tid; e < 32 * 32; e += 256) {
+    const int a = e >> 5, b = e & 31;
+    sEp[a * IE_LD + b] = (a < Dp && b < Dp) ? Ep[a * Dp + b] : 0.f;
+    sEq[a * IE_LD + b] = (a < Dq && b < Dq) ? Eq[a * Dq + b] : 0.f;
+  }
+  __syncthreads();
+
+  // ---- per row y (wave-owned): V_y = E_p K_y E_q^T, in place
+  float* T = sT + wid * 32 * IE_LD;
+  const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+  const int sp_steps = (Dp + 3) >> 2, sq_steps = (Dq + 3) >> 2;
+  for (int y = wid; y < Do; y += 4) {
+    float* Ky = sV + y * PQS;
+    // T[x_p][y_q] = sum_{y_p} E_p[x_p][y_p] K_y[y_p][y_q]
+    floatx4 acc[2][2] = {{zero, zero}, {zero, zero}};
+    for (int s = 0; s < sp_steps; ++s) {
+      const int k = 4 * s + gq;
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[i] = sEp[(16 * i + r) * IE_LD + k];  // zero past Dp (padded)
+        const int col = 16 * i + r;
+        b[i] = (k < Dp && col < Dq) ? Ky[k * Dq + col] : 0.f;
+      }
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+    }
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) T[(16 * mi + 4 * gq + i) * IE_LD + 16 * ni + r] = acc[mi][ni][i];
+    __builtin_amdgcn_wave_barrier();
+    // V[x_p][x_q] = sum_{y_q} T[x_p][y_q] E_q[x_q][y_q]
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = zero;
+    for (int s = 0; s < sq_steps; ++s) {
+      const int k = 4 * s + gq;
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[i] = k < Dq ? T[(16 * i + r) * IE_LD + k] : 0.f;
+        b[i] = sEq[(16 * i + r) * IE_LD + k];  // E_q^T[k][x_q]; zero past Dq (padded)
+      }
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int xp = 16 * mi + 4 * gq + i, xq = 16 * ni + r;
+          if (xp < Dp && xq < Dq) Ky[xp * Dq + xq] = acc[mi][ni][i];
+        }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+
+  // ---- E_o[x_o][y_o] = sum_k Bra[x_o][k] V[y_o][k], k = x_p * Dq + x_q split over the waves
+  const int steps = (PQ + 3) >> 2;
+  const int s0 = (steps * wid) >> 2, s1 = (steps * (wid + 1)) >> 2;
+  floatx4 acc[2][2] = {{zero, zero}, {zero, zero}};
+  // this lane's k = 4 s + gq as (x_p, x_q), advanced by 4 per step
+  int k = 4 * s0 + gq;
+  int kp = k / Dq, kq = k - (k / Dq) * Dq;
+  const int so = g.stride[g.o], sp = g.stride[g.p], sq = g.stride[g.q];
+  int ro[2];
+  bool rv[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int xo = 16 * i + r;
+    rv[i] = xo < Do;
+    ro[i] = rv[i] ? xo * so : 0;
+  }
+  // bra fragments eight steps ahead: batch c + 1 is loaded while batch c is multiplied
+  constexpr int SB = 8;
+  float an[SB][2], ac[SB][2];
+  auto load_batch = [&](int sb, float (&dst)[SB][2]) {
+#pragma unroll
+    for (int j = 0; j < SB; ++j) {
+      const bool kv = sb + j < s1 && k < PQ;
+      const int ko = kv ? kp * sp + kq * sq : 0;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) dst[j][i] = bra[ro[i] + ko];  // raw (clamped address); masked at use
+      k += 4;
+      kq += 4;
+      while (kq >= Dq) {
+        kq -= Dq;
+        ++kp;
+      }
+    }
+  };
+  load_batch(s0, ac);
+  int kb = 4 * s0 + gq;  // k of the batch being multiplied
+  for (int sb = s0; sb < s1; sb += SB) {
+    if (sb + SB < s1) load_batch(sb + SB, an);
+#pragma unroll
+    for (int j = 0; j < SB; ++j) {
+      const bool kv = sb + j < s1 && kb < PQ;
+      float b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int yo = 16 * i + r;
+        b[i] = (kv && yo < Do) ? sV[yo * PQS + kb] : 0.f;
+      }
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32((rv[mi] && kv) ? ac[j][mi] : 0.f, b[ni], acc[mi][ni], 0, 0,
+                                                             0);
+      kb += 4;
+    }
+#pragma unroll
+    for (int j = 0; j < SB; ++j)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) ac[j][i] = an[j][i];
+  }
+  // partial blocks through the per-wave tiles (free now), summed by all threads
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) T[(16 * mi + 4 * gq + i) * IE_LD + 16 * ni + r] = acc[mi][ni][i];
+  __syncthreads();
+  for (int e = tid; e < Do * Do; e += 256) {
+    const int xo = e / Do, yo = e - xo * Do;
+    const int o = xo * IE_LD + yo;
+    Eo[e] = sT[o] + sT[32 * IE_LD + o] + sT[2 * 32 * IE_LD + o] + sT[3 * 32 * IE_LD + o];
+  }
+}
+
+size_t ienv3_lds_bytes(int Do, int Dp, int Dq) {
+  return sizeof(float) * ((size_t)Do * ((Dp * Dq) | 1) + 6 * 32 * IE_LD);
+}
+
+hipError_t launch_ienv3(const IEnv3Args& a, hipStream_t s) {
+  const size_t bytes = ienv3_lds_bytes(a.dim[a.o], a.dim[a.p], a.dim[a.q]);
+  static const bool attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&ienv3_kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)IENV3_LDS_MAX) == hipSuccess;
+  if (!attr || bytes > IENV3_LDS_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(ienv3_kernel, dim3((unsigned)a.n), dim3(256), bytes, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace ttn

@@ -77,6 +77,28 @@ std::string gemm_kernel_name(int ctype, const GemmDesc& g);
 hipError_t launch_batched_dot(int ctype, const void* X, const int32_t* xtab, int64_t xstride, const void* Y,
                               int64_t ystride, int64_t n, int nz, int z0, double* out, hipStream_t s);
 
+// fused identity environment of a three-leg node without a physical leg (ienv.hip)
+struct IEnv3Args {
+  const float* bra = nullptr;  // bra block node tensors [bra_rows][D0][D1][D2]
+  const float* ket = nullptr;  // ket block node tensors [ket_rows][D0][D1][D2]
+  int64_t bra_size = 0, ket_size = 0;
+  const int32_t* pb = nullptr;  // pair -> bra state
+  const int32_t* pk = nullptr;  // pair -> ket state
+  int bra_rows = 0, ket_rows = 0;
+  const float* Ep = nullptr;  // incoming environment of leg p, slot = pair
+  const float* Eq = nullptr;  // incoming environment of leg q
+  float* Eo = nullptr;        // outgoing environment of leg o
+  int64_t ep_stride = 0, eq_stride = 0, eo_stride = 0;
+  int dim[3] = {0, 0, 0};     // leg dims (bra == ket)
+  int stride[3] = {0, 0, 0};  // leg strides in the node tensor
+  int o = 0, p = 1, q = 2;    // output leg, the two contracted legs (p < q)
+  int n = 0;                  // pairs
+  int* flag = nullptr;
+};
+#define IENV3_LDS_MAX (96 * 1024)
+size_t ienv3_lds_bytes(int Do, int Dp, int Dq);
+hipError_t launch_ienv3(const IEnv3Args& a, hipStream_t s);
+
 // diag(H_eff): out[z][b_N, p] = sum_w Wd[w, p] prod_i Ed_i[z][b_i, w_i] - shift[z]
 struct DiagDesc {
   int kappa = 0;

@@ -240,11 +240,15 @@ def test_rejects_bad_arguments(api, ctx):
 
 @pytest.mark.parametrize("case", CASES)
 @pytest.mark.parametrize("dt", [1, 2])
-def test_identity_env_update_fp32_paths(api, ctx, case, dt):
+@pytest.mark.parametrize("fused", [True, False])
+def test_identity_env_update_fp32_paths(api, ctx, case, dt, fused, monkeypatch):
     """Identity-operator environment updates (the overlap environments of the
     Gram step and of fitting) in FP32 / BF16 compute, every direction, against
-    the oracle; the binary-tree node shape goes through the split-K skinny
-    kernel (checked in the stage profile)."""
+    the oracle.  Three-leg nodes without a physical leg take the fused kernel
+    (intermediates in LDS) unless it is switched off; staged, the binary-tree
+    node shape goes through the split-K skinny kernel (both checked in the
+    stage profile)."""
+    monkeypatch.setenv("TTN_FUSED_IENV", "1" if fused else "0")
     kappa, d, Db, M, Da, _ = case
     tree, gt, bra, ket, A_b, A_k, W, gW, envs, E, pairs, pb, pk, tdt = _env_setup(
         api, ctx, kappa, d, Db, M, Db, 3, 4, 400 + kappa, dt, op=False)
@@ -260,5 +264,7 @@ def test_identity_env_update_fp32_paths(api, ctx, case, dt):
             assert rel_err(got[p], ref) < TOL[dt], (case, dt, v, p)
     kernels = {r[2] for r in api.profile_report(ctx)}
     api.profile(ctx, False)
-    if Db == [24, 24, 24]:  # the binary-tree node: a 24 x 24 x 576 closing stage
+    if kappa == 3 and d == 1:
+        assert ("ienv3_kernel" in kernels) == fused, kernels
+    if Db == [24, 24, 24] and not fused:  # the binary-tree node: a 24 x 24 x 576 closing stage
         assert "ogemm_splitk_kernel" in kernels, kernels
