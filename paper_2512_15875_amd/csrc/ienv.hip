@@ -26,9 +26,16 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 #define IE_LD 33  // row stride of the 32 x 32 LDS tiles (one pad word)
 
+// DU > 0: every leg of dimension DU and output leg OU known at compile time
+// (loop trip counts and strides become constants); DU = 0: read from g.
+template <int DU, int OU>
 __global__ __launch_bounds__(256) void ienv3_kernel(IEnv3Args g) {
   extern __shared__ float smem[];
-  const int Do = g.dim[g.o], Dp = g.dim[g.p], Dq = g.dim[g.q];
+  const int lo = DU ? OU : g.o, lp = DU ? (OU == 0 ? 1 : 0) : g.p, lq = DU ? (OU == 2 ? 1 : 2) : g.q;
+  const int dm0 = DU ? DU : g.dim[0], dm1 = DU ? DU : g.dim[1], dm2 = DU ? DU : g.dim[2];
+  const int st0 = DU ? DU * DU : g.stride[0], st1 = DU ? DU : g.stride[1], st2 = DU ? 1 : g.stride[2];
+  const int dims[3] = {dm0, dm1, dm2}, strides[3] = {st0, st1, st2};
+  const int Do = dims[lo], Dp = dims[lp], Dq = dims[lq];
   const int PQ = Dp * Dq;
   const int PQS = PQ | 1;             // odd row stride: 16 consecutive rows in 16 LDS banks
   float* sV = smem;                   // [Do][PQS]: K_y rows, then V_y rows
@@ -52,14 +59,14 @@ __global__ __launch_bounds__(256) void ienv3_kernel(IEnv3Args g) {
   float* __restrict__ Eo = g.Eo + (int64_t)z * g.eo_stride;
 
   // ---- stage: ket in memory order -> sV[y_o][y_p * Dq + y_q]; environments zero-padded
-  const int D1 = g.dim[1], D2 = g.dim[2], D1D2 = D1 * D2;
-  const int n3 = g.dim[0] * D1D2;
+  const int D1 = dm1, D2 = dm2, D1D2 = D1 * D2;
+  const int n3 = dm0 * D1D2;
   // LDS strides of the three tensor legs, and the thread's tensor index
   // advanced by 256 elements per round without divisions
   int ls[3];
-  ls[g.o] = PQS;
-  ls[g.p] = Dq;
-  ls[g.q] = 1;
+  ls[lo] = PQS;
+  ls[lp] = Dq;
+  ls[lq] = 1;
   const int c0 = 256 / D1D2, c1 = (256 - c0 * D1D2) / D2, c2 = 256 - c0 * D1D2 - c1 * D2;
   int i0 = tid / D1D2, i1 = (tid - i0 * D1D2) / D2, i2 = tid - i0 * D1D2 - i1 * D2;
   // eight loads in flight per thread, then their stores
@@ -102,6 +109,7 @@ __global__ __launch_bounds__(256) void ienv3_kernel(IEnv3Args g) {
     float* Ky = sV + y * PQS;
     // T[x_p][y_q] = sum_{y_p} E_p[x_p][y_p] K_y[y_p][y_q]
     floatx4 acc[2][2] = {{zero, zero}, {zero, zero}};
+#pragma unroll
     for (int s = 0; s < sp_steps; ++s) {
       const int k = 4 * s + gq;
       float a[2], b[2];
@@ -128,6 +136,7 @@ __global__ __launch_bounds__(256) void ienv3_kernel(IEnv3Args g) {
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
       for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = zero;
+#pragma unroll
     for (int s = 0; s < sq_steps; ++s) {
       const int k = 4 * s + gq;
       float a[2], b[2];
@@ -162,7 +171,7 @@ __global__ __launch_bounds__(256) void ienv3_kernel(IEnv3Args g) {
   // this lane's k = 4 s + gq as (x_p, x_q), advanced by 4 per step
   int k = 4 * s0 + gq;
   int kp = k / Dq, kq = k - (k / Dq) * Dq;
-  const int so = g.stride[g.o], sp = g.stride[g.p], sq = g.stride[g.q];
+  const int so = strides[lo], sp = strides[lp], sq = strides[lq];
   int ro[2];
   bool rv[2];
 #pragma unroll
@@ -171,49 +180,90 @@ __global__ __launch_bounds__(256) void ienv3_kernel(IEnv3Args g) {
     rv[i] = xo < Do;
     ro[i] = rv[i] ? xo * so : 0;
   }
-  // bra fragments eight steps ahead: batch c + 1 is loaded while batch c is multiplied
-  constexpr int SB = 8;
-  float an[SB][2], ac[SB][2];
-  auto load_batch = [&](int sb, float (&dst)[SB][2]) {
+  if constexpr (DU > 0 && DU % 4 == 0 && (OU == 0 || OU == 1)) {
+    // the last contracted leg is unit-stride in the tensor: each lane loads its
+    // bra rows as 16-byte runs of k (4 consecutive x_q, never crossing an x_p
+    // row since DU % 4 == 0) and MFMA t of a 16-k chunk takes element t of
+    // every lane's run, the V operand read the same way (the sum over k is
+    // complete whichever k each MFMA sees, as long as A and B agree)
+    constexpr int KW = DU * DU / 4;  // k per wave
+    static_assert(KW % 16 == 0, "k range of a wave must be whole 16-k chunks");
+    const int kbase = KW * wid;
+    floatx4 bq[2], bn[2];
+    auto load_q = [&](int c, floatx4 (&dst)[2]) {
+      const int kk = kbase + 16 * c + 4 * gq;
+      const int xp = kk / DU, xq = kk - xp * DU;
 #pragma unroll
-    for (int j = 0; j < SB; ++j) {
-      const bool kv = sb + j < s1 && k < PQ;
-      const int ko = kv ? kp * sp + kq * sq : 0;
+      for (int i = 0; i < 2; ++i) dst[i] = *(const floatx4*)(bra + ro[i] + xp * sp + xq);  // raw; masked at use
+    };
+    load_q(0, bq);
 #pragma unroll
-      for (int i = 0; i < 2; ++i) dst[j][i] = bra[ro[i] + ko];  // raw (clamped address); masked at use
-      k += 4;
-      kq += 4;
-      while (kq >= Dq) {
-        kq -= Dq;
-        ++kp;
+    for (int c = 0; c < KW / 16; ++c) {
+      if (c + 1 < KW / 16) load_q(c + 1, bn);
+      const int kk = kbase + 16 * c + 4 * gq;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        float bv[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int yo = 16 * i + r;
+          bv[i] = yo < Do ? sV[yo * PQS + kk + t] : 0.f;
+        }
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < 2; ++ni)
+            acc[mi][ni] =
+                __builtin_amdgcn_mfma_f32_16x16x4f32(rv[mi] ? bq[mi][t] : 0.f, bv[ni], acc[mi][ni], 0, 0, 0);
       }
+      bq[0] = bn[0];
+      bq[1] = bn[1];
     }
-  };
-  load_batch(s0, ac);
-  int kb = 4 * s0 + gq;  // k of the batch being multiplied
-  for (int sb = s0; sb < s1; sb += SB) {
-    if (sb + SB < s1) load_batch(sb + SB, an);
+  } else {
+    // bra fragments eight steps ahead: batch c + 1 is loaded while batch c is multiplied
+    constexpr int SB = 8;
+    float an[SB][2], ac[SB][2];
+    auto load_batch = [&](int sb, float (&dst)[SB][2]) {
 #pragma unroll
-    for (int j = 0; j < SB; ++j) {
-      const bool kv = sb + j < s1 && kb < PQ;
-      float b[2];
+      for (int j = 0; j < SB; ++j) {
+        const bool kv = sb + j < s1 && k < PQ;
+        const int ko = kv ? kp * sp + kq * sq : 0;
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int yo = 16 * i + r;
-        b[i] = (kv && yo < Do) ? sV[yo * PQS + kb] : 0.f;
+        for (int i = 0; i < 2; ++i) dst[j][i] = bra[ro[i] + ko];  // raw (clamped address); masked at use
+        k += 4;
+        kq += 4;
+        while (kq >= Dq) {
+          kq -= Dq;
+          ++kp;
+        }
+      }
+    };
+    load_batch(s0, ac);
+    int kb = 4 * s0 + gq;  // k of the batch being multiplied
+    for (int sb = s0; sb < s1; sb += SB) {
+      if (sb + SB < s1) load_batch(sb + SB, an);
+#pragma unroll
+      for (int j = 0; j < SB; ++j) {
+        const bool kv = sb + j < s1 && kb < PQ;
+        float b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int yo = 16 * i + r;
+          b[i] = (kv && yo < Do) ? sV[yo * PQS + kb] : 0.f;
+        }
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < 2; ++ni)
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32((rv[mi] && kv) ? ac[j][mi] : 0.f, b[ni], acc[mi][ni], 0, 0,
+                                                               0);
+        kb += 4;
       }
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int j = 0; j < SB; ++j)
 #pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
-          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32((rv[mi] && kv) ? ac[j][mi] : 0.f, b[ni], acc[mi][ni], 0, 0,
-                                                             0);
-      kb += 4;
+        for (int i = 0; i < 2; ++i) ac[j][i] = an[j][i];
     }
-#pragma unroll
-    for (int j = 0; j < SB; ++j)
-#pragma unroll
-      for (int i = 0; i < 2; ++i) ac[j][i] = an[j][i];
   }
   // partial blocks through the per-wave tiles (free now), summed by all threads
 #pragma unroll
@@ -236,11 +286,19 @@ size_t ienv3_lds_bytes(int Do, int Dp, int Dq) {
 
 hipError_t launch_ienv3(const IEnv3Args& a, hipStream_t s) {
   const size_t bytes = ienv3_lds_bytes(a.dim[a.o], a.dim[a.p], a.dim[a.q]);
-  static const bool attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&ienv3_kernel),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)IENV3_LDS_MAX) == hipSuccess;
+  auto set_lds = [](const void* f) {
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)IENV3_LDS_MAX) == hipSuccess;
+  };
+  static const bool attr = set_lds(reinterpret_cast<const void*>(&ienv3_kernel<24, 0>)) &&
+                           set_lds(reinterpret_cast<const void*>(&ienv3_kernel<24, 1>)) &&
+                           set_lds(reinterpret_cast<const void*>(&ienv3_kernel<24, 2>)) &&
+                           set_lds(reinterpret_cast<const void*>(&ienv3_kernel<0, 0>));
   if (!attr || bytes > IENV3_LDS_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(ienv3_kernel, dim3((unsigned)a.n), dim3(256), bytes, s, a);
+  const bool u24 = a.dim[0] == 24 && a.dim[1] == 24 && a.dim[2] == 24;
+  if (u24 && a.o == 0) hipLaunchKernelGGL((ienv3_kernel<24, 0>), dim3((unsigned)a.n), dim3(256), bytes, s, a);
+  else if (u24 && a.o == 1) hipLaunchKernelGGL((ienv3_kernel<24, 1>), dim3((unsigned)a.n), dim3(256), bytes, s, a);
+  else if (u24 && a.o == 2) hipLaunchKernelGGL((ienv3_kernel<24, 2>), dim3((unsigned)a.n), dim3(256), bytes, s, a);
+  else hipLaunchKernelGGL((ienv3_kernel<0, 0>), dim3((unsigned)a.n), dim3(256), bytes, s, a);
   return hipGetLastError();
 }
 
