@@ -557,7 +557,10 @@ __device__ __forceinline__ double wave_allsum(double v) {
 #define QR_NT 512  // threads of the LDS-resident QR (8 waves: more columns in flight per reflector)
 #define QR_NW (QR_NT / 64)
 
-template <typename T>
+// ITM > 0: every row loop of a lane has at most ITM iterations (m <= 64 ITM),
+// unrolled so that a lane's LDS loads are all in flight before its FMAs;
+// ITM = 0: runtime-bounded loops.
+template <typename T, int ITM>
 __global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const int32_t* roff, int m, int n,
                                                      int64_t cstride, double* Rout, int* flag) {
   extern __shared__ double sm[];
@@ -565,6 +568,8 @@ __global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const
   double* Rl = A + (size_t)m * n;  // n * n, row-major
   double* tau = Rl + (size_t)n * n;
   const int z = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  constexpr int IT = ITM > 0 ? ITM : 1;
+  const int nit = ITM > 0 ? ITM : (m + 63) / 64;  // iterations of the runtime form
   T* Xz = X + (int64_t)z * size;
   for (int i = t; i < m * n; i += QR_NT) {
     const int j = i / m, r = i - j * m;
@@ -572,19 +577,68 @@ __global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const
   }
   for (int i = t; i < n * n; i += QR_NT) Rl[i] = 0.0;
   __syncthreads();
+  // y_i -= d v_i and d = sum v_i y_i over rows i = s + lane + 64 it (< m), with
+  // the v rows loaded once per reflector
+  auto dot_update = [&](const double* v, double* y, int s, int kd, double tk) {
+    if constexpr (ITM > 0) {
+      double vv[IT], yv[IT];
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int i = s + lane + 64 * it;
+        vv[it] = i < m ? v[i] : 0.0;
+        yv[it] = i < m ? y[i] : 0.0;
+      }
+      double d = lane == 0 ? y[kd] : 0.0;
+#pragma unroll
+      for (int it = 0; it < IT; ++it) d += vv[it] * yv[it];
+      d = tk * wave_allsum(d);
+      if (lane == 0) y[kd] -= d;
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int i = s + lane + 64 * it;
+        if (i < m) y[i] = yv[it] - d * vv[it];
+      }
+    } else {
+      double d = lane == 0 ? y[kd] : 0.0;
+      for (int i = s + lane; i < m; i += 64) d += v[i] * y[i];
+      d = tk * wave_allsum(d);
+      if (lane == 0) y[kd] -= d;
+      for (int i = s + lane; i < m; i += 64) y[i] -= d * v[i];
+    }
+  };
+  (void)nit;
   for (int k = 0; k < n; ++k) {
     double* a = A + (size_t)k * m;
     // wave 0 builds reflector k: v = (1, a[k+1..] / v0), tau' = 2 v0^2 / |x - alpha e_k|^2
     if (wv == 0) {
+      double xv[IT];
       double ss = 0;
-      for (int i = k + lane; i < m; i += 64) ss += a[i] * a[i];
+      if constexpr (ITM > 0) {
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+          const int i = k + lane + 64 * it;
+          xv[it] = i < m ? a[i] : 0.0;
+        }
+#pragma unroll
+        for (int it = 0; it < IT; ++it) ss += xv[it] * xv[it];
+      } else {
+        for (int i = k + lane; i < m; i += 64) ss += a[i] * a[i];
+      }
       ss = wave_allsum(ss);
       const double x0 = a[k], nrm = sqrt(ss);
       const double alpha = nrm == 0.0 ? 0.0 : (x0 >= 0 ? -nrm : nrm);
       const double v0 = x0 - alpha;
       const double vn2 = ss - x0 * x0 + v0 * v0;
       const double inv = v0 != 0.0 ? 1.0 / v0 : 0.0;
-      for (int i = k + 1 + lane; i < m; i += 64) a[i] *= inv;
+      if constexpr (ITM > 0) {
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+          const int i = k + lane + 64 * it;
+          if (i > k && i < m) a[i] = xv[it] * inv;
+        }
+      } else {
+        for (int i = k + 1 + lane; i < m; i += 64) a[i] *= inv;
+      }
       if (lane == 0) {
         tau[k] = (vn2 > 0 && v0 != 0.0) ? 2.0 * v0 * v0 / vn2 : 0.0;
         Rl[k * n + k] = alpha;
@@ -593,14 +647,7 @@ __global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const
     __syncthreads();
     // every wave applies the reflector to its own columns j > k (dot, then update)
     const double tk = tau[k];
-    for (int j = k + 1 + wv; j < n; j += QR_NW) {
-      double* aj = A + (size_t)j * m;
-      double d = lane == 0 ? aj[k] : 0.0;
-      for (int i = k + 1 + lane; i < m; i += 64) d += a[i] * aj[i];
-      d = tk * wave_allsum(d);
-      if (lane == 0) aj[k] -= d;
-      for (int i = k + 1 + lane; i < m; i += 64) aj[i] -= d * a[i];
-    }
+    for (int j = k + 1 + wv; j < n; j += QR_NW) dot_update(a, A + (size_t)j * m, k + 1, k, tk);
     __syncthreads();
   }
   for (int e = t; e < n * n; e += QR_NT) {
@@ -612,14 +659,7 @@ __global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const
   for (int i = n - 1; i >= 0; --i) {
     double* ai = A + (size_t)i * m;
     const double ti = tau[i];
-    for (int j = i + 1 + wv; j < n; j += QR_NW) {
-      double* aj = A + (size_t)j * m;
-      double d = lane == 0 ? aj[i] : 0.0;
-      for (int r = i + 1 + lane; r < m; r += 64) d += ai[r] * aj[r];
-      d = ti * wave_allsum(d);
-      if (lane == 0) aj[i] -= d;
-      for (int r = i + 1 + lane; r < m; r += 64) aj[r] -= d * ai[r];
-    }
+    for (int j = i + 1 + wv; j < n; j += QR_NW) dot_update(ai, A + (size_t)j * m, i + 1, i, ti);
     __syncthreads();
     for (int r = t; r < m; r += QR_NT) ai[r] = r > i ? -ti * ai[r] : (r == i ? 1.0 - ti : 0.0);
     __syncthreads();
@@ -665,17 +705,33 @@ static hipError_t qr_t(void* X, int64_t size, const int32_t* roff, int m, int n,
 // LDS budget of the resident-matrix QR (the CU has 160 KiB)
 static constexpr size_t QR_LDS_MAX = 150 * 1024;
 
+template <typename T, int ITM>
+static bool qr_lds_it(void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride, double* R, int nz,
+                      int* flag, size_t bytes, hipStream_t s) {
+  static const bool enabled = hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_lds_kernel<T, ITM>),
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  (int)QR_LDS_MAX) == hipSuccess;
+  if (!enabled) return false;
+  hipLaunchKernelGGL((qr_lds_kernel<T, ITM>), dim3(nz), dim3(QR_NT), bytes, s, (T*)X, size, roff, m, n, cstride, R,
+                     flag);
+  return hipGetLastError() == hipSuccess;
+}
+
 template <typename T>
 static bool qr_lds(void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride, double* R, int nz,
                    int* flag, hipStream_t s) {
   const size_t bytes = ((size_t)m * n + (size_t)n * n + (size_t)n) * sizeof(double);
   if (bytes > QR_LDS_MAX) return false;
-  static const bool enabled = hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_lds_kernel<T>),
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                  (int)QR_LDS_MAX) == hipSuccess;
-  if (!enabled) return false;
-  hipLaunchKernelGGL(qr_lds_kernel<T>, dim3(nz), dim3(QR_NT), bytes, s, (T*)X, size, roff, m, n, cstride, R, flag);
-  return hipGetLastError() == hipSuccess;
+  const int need = (m + 63) / 64;  // row iterations of a lane
+  if (need <= 1) return qr_lds_it<T, 1>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
+  if (need <= 2) return qr_lds_it<T, 2>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
+  if (need <= 3) return qr_lds_it<T, 3>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
+  if (need <= 4) return qr_lds_it<T, 4>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
+  if (need <= 6) return qr_lds_it<T, 6>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
+  if (need <= 9) return qr_lds_it<T, 9>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
+  if (need <= 12) return qr_lds_it<T, 12>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
+  if (need <= 16) return qr_lds_it<T, 16>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
+  return qr_lds_it<T, 0>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
 }
 
 hipError_t launch_qr(int ctype, void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride, double* work,
