@@ -918,6 +918,47 @@ ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, 
     ep.accum = flags & TTN_HEFF_ACCUM;
     return exec_plan(ctx, *P, cd == 2 ? 1 : cd, in, o, ep, k, ne, n_loc, (gather_bytes + 255) / 256 * 256);
   }
+  {
+    // identity operator at a three-leg node without a physical leg, FP32, plain
+    // output (no shift, scale or accumulation), environment slot = item, output
+    // row = item, bonds <= 32: the fused kernel
+    bool fuse = !op && kap == 3 && t->phys[u] == 1 && (ct == 1 || ct == 2) && envs->dt == TTN_F32 && !pair_ids &&
+                !y_ids && !alpha && !(flags & TTN_HEFF_ACCUM) && ((flags & TTN_HEFF_NO_SHIFT) || !shift);
+    const char* fe = getenv("TTN_FUSED_IENV");
+    if (fe && fe[0] == '0') fuse = false;
+    IHeff3Args fa;
+    for (int i = 0; i < 3 && fuse; ++i) {
+      const int c = t->nb[u][i];
+      fa.dim[i] = envs->eb(c, u);
+      fuse = fa.dim[i] == envs->ea(c, u) && fa.dim[i] >= 1 && fa.dim[i] <= 32;
+      fa.E[i] = (const float*)envs->slot[ttn_envs::dslot(t, c, u)];
+      fa.e_stride[i] = envs->slot_elems(c, u);
+    }
+    if (fuse) fuse = ienv3_lds_bytes(fa.dim[0], fa.dim[1], fa.dim[2]) <= IENV3_LDS_MAX;
+    if (fuse) {
+      fa.X = (const float*)X;
+      fa.x_size = n_in;
+      fa.x_ids = x_ids;
+      fa.x_rows = x_rows;
+      fa.Y = (float*)Y;
+      fa.y_stride = n_loc;
+      fa.n = k;
+      fa.flag = ctx->d_flag;
+      const double D0 = fa.dim[0], D1 = fa.dim[1], D2 = fa.dim[2];
+      const double per = 2.0 * D0 * D1 * D2 * (D0 + D1 + D2);
+      ctx->flops_done += per * k;
+      std::ostringstream key;
+      key << "iheff:" << u;
+      const std::string ks = key.str();
+      // compulsory bytes: X row and Y row, three environments per item
+      const double bytes = 4.0 * k * (2.0 * D0 * D1 * D2 + D0 * D0 + D1 * D1 + D2 * D2);
+      ttn_prof_rec* pr = prof_begin(ctx, ks.c_str(), "iheff3_kernel", per * k, bytes, k);
+      hipError_t he = launch_iheff3(fa, ctx->stream);
+      prof_end(ctx, pr);
+      if (he != hipSuccess) return fail(ctx, TTN_E_LAUNCH, std::string("fused identity H_eff: ") + hipGetErrorString(he));
+      return TTN_OK;
+    }
+  }
   Net net;
   std::string why;
   if (!build_heff_net(t, op, envs, u, net, why)) return fail(ctx, TTN_E_SHAPE, why);

@@ -26,39 +26,17 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 #define IE_LD 33  // row stride of the 32 x 32 LDS tiles (one pad word)
 
-// DU > 0: every leg of dimension DU and output leg OU known at compile time
-// (loop trip counts and strides become constants); DU = 0: read from g.
-template <int DU, int OU>
-__global__ __launch_bounds__(256) void ienv3_kernel(IEnv3Args g) {
-  extern __shared__ float smem[];
-  const int lo = DU ? OU : g.o, lp = DU ? (OU == 0 ? 1 : 0) : g.p, lq = DU ? (OU == 2 ? 1 : 2) : g.q;
-  const int dm0 = DU ? DU : g.dim[0], dm1 = DU ? DU : g.dim[1], dm2 = DU ? DU : g.dim[2];
-  const int st0 = DU ? DU * DU : g.stride[0], st1 = DU ? DU : g.stride[1], st2 = DU ? 1 : g.stride[2];
-  const int dims[3] = {dm0, dm1, dm2}, strides[3] = {st0, st1, st2};
-  const int Do = dims[lo], Dp = dims[lp], Dq = dims[lq];
-  const int PQ = Dp * Dq;
-  const int PQS = PQ | 1;             // odd row stride: 16 consecutive rows in 16 LDS banks
-  float* sV = smem;                   // [Do][PQS]: K_y rows, then V_y rows
-  float* sEp = sV + Do * PQS;         // [32][IE_LD] zero-padded E_p[x_p][y_p]
-  float* sEq = sEp + 32 * IE_LD;      // [32][IE_LD] zero-padded E_q[x_q][y_q]
-  float* sT = sEq + 32 * IE_LD;       // 4 x [32][IE_LD] per-wave tiles
+// Shared first phase: the tensor X (legs 0, 1, 2 of dims dm0..dm2 in memory
+// order, no physical leg) is staged in LDS as rows K_y = X[y over leg lo, :, :]
+// (Dp x Dq, row stride PQS), E_p and E_q zero-padded to 32 x 32, and every wave
+// replaces its rows y = wid, wid + 4, ... by V_y = E_p K_y E_q^T (two MFMA
+// products through the wave's LDS tile).  Ends with a workgroup barrier.
+__device__ __forceinline__ void ie_stage_v(const float* __restrict__ ket, const float* __restrict__ Ep,
+                                           const float* __restrict__ Eq, float* sV, float* sEp, float* sEq,
+                                           float* sT, int dm0, int dm1, int dm2, int lo, int lp, int lq, int Do,
+                                           int Dp, int Dq, int PQS) {
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int r = lane & 15, gq = lane >> 4;
-  const int z = blockIdx.x;
-  if (z >= g.n) return;  // uniform per workgroup, before any barrier
-  int ib = g.pb[z], ik = g.pk[z];
-  if (ib < 0 || ib >= g.bra_rows || ik < 0 || ik >= g.ket_rows) {  // clamp and report
-    if (tid == 0) atomicOr(g.flag + 2, 1);
-    ib = ib < 0 ? 0 : (ib >= g.bra_rows ? g.bra_rows - 1 : ib);
-    ik = ik < 0 ? 0 : (ik >= g.ket_rows ? g.ket_rows - 1 : ik);
-  }
-  const float* __restrict__ bra = g.bra + (int64_t)ib * g.bra_size;
-  const float* __restrict__ ket = g.ket + (int64_t)ik * g.ket_size;
-  const float* __restrict__ Ep = g.Ep + (int64_t)z * g.ep_stride;
-  const float* __restrict__ Eq = g.Eq + (int64_t)z * g.eq_stride;
-  float* __restrict__ Eo = g.Eo + (int64_t)z * g.eo_stride;
-
-  // ---- stage: ket in memory order -> sV[y_o][y_p * Dq + y_q]; environments zero-padded
   const int D1 = dm1, D2 = dm2, D1D2 = D1 * D2;
   const int n3 = dm0 * D1D2;
   // LDS strides of the three tensor legs, and the thread's tensor index
@@ -163,6 +141,44 @@ __global__ __launch_bounds__(256) void ienv3_kernel(IEnv3Args g) {
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
+
+}
+
+// DU > 0: every leg of dimension DU and output leg OU known at compile time
+// (loop trip counts and strides become constants); DU = 0: read from g.
+template <int DU, int OU>
+__global__ __launch_bounds__(256) void ienv3_kernel(IEnv3Args g) {
+  extern __shared__ float smem[];
+  const int lo = DU ? OU : g.o, lp = DU ? (OU == 0 ? 1 : 0) : g.p, lq = DU ? (OU == 2 ? 1 : 2) : g.q;
+  const int dm0 = DU ? DU : g.dim[0], dm1 = DU ? DU : g.dim[1], dm2 = DU ? DU : g.dim[2];
+  const int st0 = DU ? DU * DU : g.stride[0], st1 = DU ? DU : g.stride[1], st2 = DU ? 1 : g.stride[2];
+  const int dims[3] = {dm0, dm1, dm2}, strides[3] = {st0, st1, st2};
+  const int Do = dims[lo], Dp = dims[lp], Dq = dims[lq];
+  const int PQ = Dp * Dq;
+  const int PQS = PQ | 1;             // odd row stride: 16 consecutive rows in 16 LDS banks
+  float* sV = smem;                   // [Do][PQS]: K_y rows, then V_y rows
+  float* sEp = sV + Do * PQS;         // [32][IE_LD] zero-padded E_p[x_p][y_p]
+  float* sEq = sEp + 32 * IE_LD;      // [32][IE_LD] zero-padded E_q[x_q][y_q]
+  float* sT = sEq + 32 * IE_LD;       // 4 x [32][IE_LD] per-wave tiles
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int r = lane & 15, gq = lane >> 4;
+  const int z = blockIdx.x;
+  if (z >= g.n) return;  // uniform per workgroup, before any barrier
+  int ib = g.pb[z], ik = g.pk[z];
+  if (ib < 0 || ib >= g.bra_rows || ik < 0 || ik >= g.ket_rows) {  // clamp and report
+    if (tid == 0) atomicOr(g.flag + 2, 1);
+    ib = ib < 0 ? 0 : (ib >= g.bra_rows ? g.bra_rows - 1 : ib);
+    ik = ik < 0 ? 0 : (ik >= g.ket_rows ? g.ket_rows - 1 : ik);
+  }
+  const float* __restrict__ bra = g.bra + (int64_t)ib * g.bra_size;
+  const float* __restrict__ ket = g.ket + (int64_t)ik * g.ket_size;
+  const float* __restrict__ Ep = g.Ep + (int64_t)z * g.ep_stride;
+  const float* __restrict__ Eq = g.Eq + (int64_t)z * g.eq_stride;
+  float* __restrict__ Eo = g.Eo + (int64_t)z * g.eo_stride;
+
+  ie_stage_v(ket, Ep, Eq, sV, sEp, sEq, sT, dm0, dm1, dm2, lo, lp, lq, Do, Dp, Dq, PQS);
+  const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+  float* T = sT + wid * 32 * IE_LD;
 
   // ---- E_o[x_o][y_o] = sum_k Bra[x_o][k] V[y_o][k], k = x_p * Dq + x_q split over the waves
   const int steps = (PQ + 3) >> 2;
@@ -278,6 +294,86 @@ __global__ __launch_bounds__(256) void ienv3_kernel(IEnv3Args g) {
     const int o = xo * IE_LD + yo;
     Eo[e] = sT[o] + sT[32 * IE_LD + o] + sT[2 * 32 * IE_LD + o] + sT[3 * 32 * IE_LD + o];
   }
+}
+
+// Identity-operator effective-Hamiltonian product at the same node type (the
+// fitting sweep's per-term local products, Sec. II.C):
+//   Y[z][x_0, x_1, x_2] = sum E_0[x_0][y_0] E_1[x_1][y_1] E_2[x_2][y_2] X[xr][y_0, y_1, y_2],
+// xr = x_ids[z] (or z), environment slot z.  One workgroup per item: the shared
+// phase with leg 0 as the row leg (V_y = E_1 K_y E_2^T), then
+// Y = E_0 V (M = D_0, N = D_1 D_2, K = D_0), the N columns split over the waves
+// and written straight to Y (rows of D_1 D_2 contiguous floats).
+template <int DU>
+__global__ __launch_bounds__(256) void iheff3_kernel(IHeff3Args g) {
+  extern __shared__ float smem[];
+  const int dm0 = DU ? DU : g.dim[0], dm1 = DU ? DU : g.dim[1], dm2 = DU ? DU : g.dim[2];
+  const int Do = dm0, Dp = dm1, Dq = dm2;
+  const int PQ = Dp * Dq;
+  const int PQS = PQ | 1;
+  float* sV = smem;
+  float* sEp = sV + Do * PQS;
+  float* sEq = sEp + 32 * IE_LD;
+  float* sT = sEq + 32 * IE_LD;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int r = lane & 15, gq = lane >> 4;
+  const int z = blockIdx.x;
+  if (z >= g.n) return;  // uniform per workgroup, before any barrier
+  int xr = g.x_ids ? g.x_ids[z] : z;
+  if (xr < 0 || xr >= g.x_rows) {  // clamp and report
+    if (tid == 0) atomicOr(g.flag + 2, 1);
+    xr = xr < 0 ? 0 : g.x_rows - 1;
+  }
+  const float* __restrict__ X = g.X + (int64_t)xr * g.x_size;
+  const float* __restrict__ E0 = g.E[0] + (int64_t)z * g.e_stride[0];
+  float* __restrict__ Y = g.Y + (int64_t)z * g.y_stride;
+  ie_stage_v(X, g.E[1] + (int64_t)z * g.e_stride[1], g.E[2] + (int64_t)z * g.e_stride[2], sV, sEp, sEq, sT, dm0, dm1,
+             dm2, 0, 1, 2, Do, Dp, Dq, PQS);
+  // E_0 zero-padded into the (now free) tile area
+  float* sE0 = sT;
+  for (int e = tid; e < 32 * 32; e += 256) {
+    const int a = e >> 5, b = e & 31;
+    sE0[a * IE_LD + b] = (a < Do && b < Do) ? E0[a * Do + b] : 0.f;
+  }
+  __syncthreads();
+  const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+  const int ntiles = (PQ + 15) >> 4, ksteps = (Do + 3) >> 2;
+  for (int nt = wid; nt < ntiles; nt += 4) {
+    const int n = 16 * nt + r;
+    floatx4 acc[2] = {zero, zero};
+#pragma unroll
+    for (int s = 0; s < (DU ? (DU + 3) / 4 : 8); ++s) {
+      if (!DU && s >= ksteps) break;
+      const int k = 4 * s + gq;
+      const float b = (k < Do && n < PQ) ? sV[k * PQS + n] : 0.f;
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+        acc[mi] = __builtin_amdgcn_mfma_f32_16x16x4f32(sE0[(16 * mi + r) * IE_LD + k], b, acc[mi], 0, 0, 0);
+    }
+    if (n < PQ) {
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int x0 = 16 * mi + 4 * gq + i;
+          if (x0 < Do) Y[x0 * PQ + n] = acc[mi][i];
+        }
+    }
+  }
+}
+
+hipError_t launch_iheff3(const IHeff3Args& a, hipStream_t s) {
+  const size_t bytes = ienv3_lds_bytes(a.dim[0], a.dim[1], a.dim[2]);
+  auto set_lds = [](const void* f) {
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)IENV3_LDS_MAX) == hipSuccess;
+  };
+  static const bool attr = set_lds(reinterpret_cast<const void*>(&iheff3_kernel<24>)) &&
+                           set_lds(reinterpret_cast<const void*>(&iheff3_kernel<0>));
+  if (!attr || bytes > IENV3_LDS_MAX) return hipErrorInvalidValue;
+  if (a.dim[0] == 24 && a.dim[1] == 24 && a.dim[2] == 24)
+    hipLaunchKernelGGL((iheff3_kernel<24>), dim3((unsigned)a.n), dim3(256), bytes, s, a);
+  else
+    hipLaunchKernelGGL((iheff3_kernel<0>), dim3((unsigned)a.n), dim3(256), bytes, s, a);
+  return hipGetLastError();
 }
 
 size_t ienv3_lds_bytes(int Do, int Dp, int Dq) {

@@ -95,9 +95,23 @@ struct IEnv3Args {
   int n = 0;                  // pairs
   int* flag = nullptr;
 };
+struct IHeff3Args {
+  const float* X = nullptr;      // block node tensors [x_rows][D0][D1][D2]
+  int64_t x_size = 0;
+  const int32_t* x_ids = nullptr;  // item -> X row (null: the item index)
+  int x_rows = 0;
+  const float* E[3] = {nullptr, nullptr, nullptr};  // incoming environments per leg, slot = item
+  int64_t e_stride[3] = {0, 0, 0};
+  float* Y = nullptr;            // output rows [n][D0][D1][D2]
+  int64_t y_stride = 0;
+  int dim[3] = {0, 0, 0};
+  int n = 0;
+  int* flag = nullptr;
+};
 #define IENV3_LDS_MAX (96 * 1024)
 size_t ienv3_lds_bytes(int Do, int Dp, int Dq);
 hipError_t launch_ienv3(const IEnv3Args& a, hipStream_t s);
+hipError_t launch_iheff3(const IHeff3Args& a, hipStream_t s);
 
 // diag(H_eff): out[z][b_N, p] = sum_w Wd[w, p] prod_i Ed_i[z][b_i, w_i] - shift[z]
 struct DiagDesc {

@@ -110,6 +110,35 @@ def test_heff_identity_operator_and_accumulate(api, ctx, case):
         assert rel_err(Y[j], ref) < 1e-12
 
 
+@pytest.mark.parametrize("dims", [[24, 24, 24], [12, 11, 10], [24, 8, 8]])
+@pytest.mark.parametrize("dt", [1, 2])
+@pytest.mark.parametrize("fused", [True, False])
+def test_identity_heff_rows_fp32(api, ctx, dims, dt, fused, monkeypatch):
+    """Identity-operator H_eff products of the fitting form (environment slot =
+    item, X rows through a table, plain output) at three-leg nodes without a
+    physical leg, in FP32 / BF16 compute against the oracle: the fused kernel
+    and the staged path (switched by TTN_FUSED_IENV), checked in the profile."""
+    monkeypatch.setenv("TTN_FUSED_IENV", "1" if fused else "0")
+    n, kx = 7, 3
+    tree, W, X, E, gt, gW, envs, tdt = _setup(api, ctx, 3, 1, dims, [1, 1, 1], dims, n, 61, dt, op=False)
+    rng = np.random.default_rng(62)
+    Xs = rng.normal(size=(kx,) + tuple(dims) + (1,))
+    ids = np.array([2, 0, 1, 1, 0, 2, 2], dtype=np.int32)
+    gY = torch.zeros((n,) + tuple(dims) + (1,), dtype=tdt, device="cuda")
+    api.profile(ctx, True)
+    api.heff_apply_block(ctx, gt, None, envs, 1, n, to_dev(Xs, tdt), gY,
+                         x_ids=torch.from_numpy(ids).cuda(), flags=api.HEFF_NO_SHIFT, compute=dt)
+    ctx.sync()
+    kernels = {r[2] for r in api.profile_report(ctx)}
+    api.profile(ctx, False)
+    assert ("iheff3_kernel" in kernels) == fused, kernels
+    Y = gY.double().cpu().numpy()
+    for j in range(n):
+        ein = {c: E[c][j] for c in tree.neighbours(1)}
+        ref = ottn.heff_apply(tree, 1, None, Xs[ids[j]], ein)
+        assert rel_err(Y[j], ref) < TOL[dt], (dims, dt, fused, j)
+
+
 @pytest.mark.parametrize("case", CASES[:6])
 def test_heff_pair_and_row_indirection(api, ctx, case):
     kappa, d, Db, M, Da, k = case
