@@ -1,9 +1,10 @@
 // Batched MINRES for the k local systems (H_eff,j - s_j) y_j = b_j of a sweep
 // step (Sec. II.C.4: local solves by MINRES), after Paige and Saunders:
 // Lanczos tridiagonalisation with the least-squares problem solved by Givens
-// rotations.  One workgroup owns one state: its dot products and norms are
-// workgroup reductions in double, its scalar recurrence lives in `st`, and the
-// vector updates of an iteration are fused into one pass.  The matrix-vector
+// rotations.  One workgroup of 1024 threads owns one state: its dot products
+// and norms are workgroup reductions in double (wave sums, then 16 partials),
+// its scalar recurrence lives in `st`, and the vector updates of an iteration
+// are fused into one pass.  The matrix-vector
 // product between iterations is heff_apply_block over all k states.
 // Converged states are masked (their workgroups return at once).
 #include <hip/hip_runtime.h>
@@ -14,30 +15,32 @@
 
 namespace ttn {
 
+#define MR_NT 1024  // threads per state (16 wave64s)
+
+// workgroup sum: wave reductions, then the 16 wave partials (red: >= 16 doubles)
 __device__ __forceinline__ double wg_sum(double v, double* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (lane == 0) red[w] = v;
   __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (t < w) red[t] += red[t + w];
-    __syncthreads();
-  }
-  const double r = red[0];
+  double r = 0;
+#pragma unroll
+  for (int i = 0; i < MR_NT / 64; ++i) r += red[i];
   __syncthreads();
   return r;
 }
 
 // r = b - Ax0 -> v = r/beta1 ; zero v_prev, d buffers ; scalars
 template <typename T>
-__global__ __launch_bounds__(256) void minres_init(const T* b, const T* Ax, T* v, T* vprev, T* d1, T* d2, int64_t n,
+__global__ __launch_bounds__(MR_NT) void minres_init(const T* b, const T* Ax, T* v, T* vprev, T* d1, T* d2, int64_t n,
                                                    double rtol, MinresState* st) {
-  __shared__ double red[256];
+  __shared__ double red[MR_NT / 64];
   const int z = blockIdx.x, t = threadIdx.x;
   const T* bz = b + (int64_t)z * n;
   const T* az = Ax + (int64_t)z * n;
   T* vz = v + (int64_t)z * n;
   double rr = 0, bb = 0;
-  for (int64_t i = t; i < n; i += 256) {
+  for (int64_t i = t; i < n; i += MR_NT) {
     const double r = (double)bz[i] - (double)az[i];
     rr += r * r;
     bb += (double)bz[i] * (double)bz[i];
@@ -46,7 +49,7 @@ __global__ __launch_bounds__(256) void minres_init(const T* b, const T* Ax, T* v
   bb = wg_sum(bb, red);
   const double beta1 = sqrt(rr), tol = rtol * sqrt(bb);
   const bool done = !(beta1 > tol) || beta1 == 0.0;
-  for (int64_t i = t; i < n; i += 256) {
+  for (int64_t i = t; i < n; i += MR_NT) {
     const double r = (double)bz[i] - (double)az[i];
     vz[i] = done ? (T)0 : (T)(r / beta1);
     vprev[(int64_t)z * n + i] = (T)0;
@@ -72,9 +75,9 @@ __global__ __launch_bounds__(256) void minres_init(const T* b, const T* Ax, T* v
 // d_new is written into dpp (whose old contents, d_{k-2}, are consumed first);
 // v_new = p / beta_next is written into vprev (old v_{k-1} consumed first).
 template <typename T>
-__global__ __launch_bounds__(256) void minres_step(T* x, T* v, T* vprev, T* p, const T* dp, T* dpp, int64_t n,
+__global__ __launch_bounds__(MR_NT) void minres_step(T* x, T* v, T* vprev, T* p, const T* dp, T* dpp, int64_t n,
                                                    MinresState* st) {
-  __shared__ double red[256];
+  __shared__ double red[MR_NT / 64];
   __shared__ MinresState s;
   __shared__ double sh[6];  // eps, delta, gamma, tau, beta_next, alive
   const int z = blockIdx.x, t = threadIdx.x;
@@ -88,10 +91,10 @@ __global__ __launch_bounds__(256) void minres_step(T* x, T* v, T* vprev, T* p, c
   const T* dz = dp + (int64_t)z * n;
   T* dppz = dpp + (int64_t)z * n;
   double a = 0;
-  for (int64_t i = t; i < n; i += 256) a += (double)vz[i] * (double)pz[i];
+  for (int64_t i = t; i < n; i += MR_NT) a += (double)vz[i] * (double)pz[i];
   const double alpha = wg_sum(a, red);
   double nn = 0;
-  for (int64_t i = t; i < n; i += 256) {
+  for (int64_t i = t; i < n; i += MR_NT) {
     const double q = (double)pz[i] - alpha * (double)vz[i] - s.beta * (double)vpz[i];
     pz[i] = (T)q;
     nn += q * q;
@@ -127,7 +130,7 @@ __global__ __launch_bounds__(256) void minres_step(T* x, T* v, T* vprev, T* p, c
   __syncthreads();
   if (sh[5] != 0) {
     const double eps = sh[0], delta = sh[1], gamma = sh[2], tau = sh[3], bnext = sh[4];
-    for (int64_t i = t; i < n; i += 256) {
+    for (int64_t i = t; i < n; i += MR_NT) {
       const double dn = ((double)vz[i] - delta * (double)dz[i] - eps * (double)dppz[i]) / gamma;
       dppz[i] = (T)dn;
       xz[i] = (T)((double)xz[i] + tau * dn);
@@ -149,10 +152,10 @@ __global__ void minres_report(const MinresState* st, int k, int32_t* iters, doub
 hipError_t launch_minres_init(int ctype, const void* b, const void* Ax, void* v, void* vprev, void* d1, void* d2,
                               int64_t n, int k, double rtol, MinresState* st, hipStream_t s) {
   if (ctype == 0)
-    hipLaunchKernelGGL(minres_init<double>, dim3(k), dim3(256), 0, s, (const double*)b, (const double*)Ax, (double*)v,
+    hipLaunchKernelGGL(minres_init<double>, dim3(k), dim3(MR_NT), 0, s, (const double*)b, (const double*)Ax, (double*)v,
                        (double*)vprev, (double*)d1, (double*)d2, n, rtol, st);
   else
-    hipLaunchKernelGGL(minres_init<float>, dim3(k), dim3(256), 0, s, (const float*)b, (const float*)Ax, (float*)v,
+    hipLaunchKernelGGL(minres_init<float>, dim3(k), dim3(MR_NT), 0, s, (const float*)b, (const float*)Ax, (float*)v,
                        (float*)vprev, (float*)d1, (float*)d2, n, rtol, st);
   return hipGetLastError();
 }
@@ -160,10 +163,10 @@ hipError_t launch_minres_init(int ctype, const void* b, const void* Ax, void* v,
 hipError_t launch_minres_step(int ctype, void* x, void* v, void* vprev, void* p, const void* dp, void* dpp, int64_t n,
                               int k, MinresState* st, hipStream_t s) {
   if (ctype == 0)
-    hipLaunchKernelGGL(minres_step<double>, dim3(k), dim3(256), 0, s, (double*)x, (double*)v, (double*)vprev,
+    hipLaunchKernelGGL(minres_step<double>, dim3(k), dim3(MR_NT), 0, s, (double*)x, (double*)v, (double*)vprev,
                        (double*)p, (const double*)dp, (double*)dpp, n, st);
   else
-    hipLaunchKernelGGL(minres_step<float>, dim3(k), dim3(256), 0, s, (float*)x, (float*)v, (float*)vprev, (float*)p,
+    hipLaunchKernelGGL(minres_step<float>, dim3(k), dim3(MR_NT), 0, s, (float*)x, (float*)v, (float*)vprev, (float*)p,
                        (const float*)dp, (float*)dpp, n, st);
   return hipGetLastError();
 }
@@ -219,7 +222,23 @@ __global__ void seg_sum_kernel(const T* S, const int32_t* ptr, const int32_t* te
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= k || i >= n) return;
   double acc = 0.0;
-  for (int q = ptr[t]; q < ptr[t + 1]; ++q) {
+  int q = ptr[t];
+  const int qe = ptr[t + 1];
+  // eight terms' loads in flight, summed in term order (same result as one at a time)
+  for (; q + 8 <= qe; q += 8) {
+    int jj[8];
+    double cc[8], sv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) jj[u] = terms[q + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      cc[u] = coef[jj[u]];
+      sv[u] = (double)S[(int64_t)jj[u] * n + i];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += cc[u] * sv[u];
+  }
+  for (; q < qe; ++q) {
     const int j = terms[q];
     acc += coef[j] * (double)S[(int64_t)j * n + i];
   }
