@@ -119,6 +119,7 @@ __device__ void sym_eig(double* A, double* Z, int n, int ld, double* rc, double*
     // w_j = sum_i v_i Z[k+1+i][k+1+j]  (thread per column: coalesced along rows of Z)
     for (int j = t; j < len; j += blockDim.x) {
       double sacc = 0;
+#pragma unroll 8
       for (int i = 0; i < len; ++i) sacc += v[i] * Z[(size_t)(k + 1 + i) * ld + (k + 1 + j)];
       w[j] = tk * sacc;
     }
@@ -249,18 +250,24 @@ __global__ __launch_bounds__(NT) void rr_kernel(const int32_t* m_arr, int ld, co
   if (t == 0) use_chol = 1;
   __syncthreads();
   // Cholesky in place (lower triangle of L), column by column
+  // (the pivot's sum over k by wave 0's lanes; inner loops unrolled so that
+  // their independent loads are in flight together)
   for (int j = 0; j < m; ++j) {
-    if (t == 0) {
-      double d = L[j * ld + j];
-      for (int k = 0; k < j; ++k) d -= L[j * ld + k] * L[j * ld + k];
-      if (!(d > drop_tol * dmax)) use_chol = 0;
-      piv[j] = d > 0 ? sqrt(d) : 0.0;
-      L[j * ld + j] = piv[j];
+    if (t < 64) {
+      double part = 0;
+      for (int k = t; k < j; k += 64) part += L[j * ld + k] * L[j * ld + k];
+      const double d = L[j * ld + j] - wave_sum64(part);
+      if (t == 0) {
+        if (!(d > drop_tol * dmax)) use_chol = 0;
+        piv[j] = d > 0 ? sqrt(d) : 0.0;
+        L[j * ld + j] = piv[j];
+      }
     }
     __syncthreads();
     if (!use_chol) break;
     for (int i = j + 1 + t; i < m; i += NT) {
       double s = L[i * ld + j];
+#pragma unroll 8
       for (int k = 0; k < j; ++k) s -= L[i * ld + k] * L[j * ld + k];
       L[i * ld + j] = s / piv[j];
     }
@@ -273,6 +280,7 @@ __global__ __launch_bounds__(NT) void rr_kernel(const int32_t* m_arr, int ld, co
     for (int c = t; c < m; c += NT) {
       for (int i = 0; i < m; ++i) {
         double s = T[i * ld + c];
+#pragma unroll 8
         for (int k = 0; k < i; ++k) s -= L[i * ld + k] * Y[k * ld + c];
         Y[i * ld + c] = s / L[i * ld + i];
       }
@@ -281,6 +289,7 @@ __global__ __launch_bounds__(NT) void rr_kernel(const int32_t* m_arr, int ld, co
     for (int c = t; c < m; c += NT) {
       for (int i = 0; i < m; ++i) {
         double s = Y[c * ld + i];  // X^T[i][c] = X[c][i]
+#pragma unroll 8
         for (int k = 0; k < i; ++k) s -= L[i * ld + k] * C[k * ld + c];
         C[i * ld + c] = s / L[i * ld + i];
       }
@@ -384,6 +393,7 @@ __global__ __launch_bounds__(NT) void rr_kernel(const int32_t* m_arr, int ld, co
       const int col = sh_ord[j];
       for (int i = m - 1; i >= 0; --i) {
         double s = Y[i * ld + col];
+#pragma unroll 8
         for (int k = i + 1; k < m; ++k) s -= L[k * ld + i] * T[k * ld + j];
         T[i * ld + j] = s / L[i * ld + i];
       }

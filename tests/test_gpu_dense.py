@@ -52,6 +52,33 @@ def test_rayleigh_ritz_cholesky_matches_oracle(api, ctx, m, nev):
         np.testing.assert_allclose(G, np.eye(ne), atol=1e-10)
 
 
+@pytest.mark.parametrize("m", [40, 150])
+def test_rayleigh_ritz_degenerate_spectrum(api, ctx, m):
+    """H with a large cluster of zero eigenvalues and repeated nonzero ones (S
+    well conditioned): the tridiagonal QL eigensolver must deflate the zero
+    cluster (a purely relative test stalls there).  Eigenvalues against
+    numpy.linalg.eigh; eigenvectors are not unique inside the clusters, so the
+    check is the generalized residual and S-orthonormality."""
+    rng = np.random.default_rng(40 + m)
+    Q, _ = np.linalg.qr(rng.normal(size=(m, m)))
+    w = np.zeros(m)
+    w[: m // 4] = np.repeat([3.0, -2.0], (m // 4 + 1) // 2)[: m // 4]
+    Hs = (Q * w) @ Q.T
+    B = rng.normal(size=(m, m))
+    S = B @ B.T / m + np.eye(m)
+    L = np.linalg.cholesky(S)
+    H = L @ Hs @ L.T  # generalized eigenvalues of (H, S) = w
+    nev = m // 2
+    ev, V, rank = api.rayleigh_ritz(ctx, to_dev(H[None]), to_dev(S[None]), [m], nev)
+    ctx.sync()
+    ev, V = ev.cpu().numpy()[0], V.cpu().numpy()[0][:m, :nev]
+    ref = np.sort(w)[:nev]
+    np.testing.assert_allclose(ev, ref, rtol=0, atol=1e-10)
+    res = H @ V - S @ V * ev[None, :]
+    assert np.abs(res).max() < 1e-9
+    np.testing.assert_allclose(V.T @ S @ V, np.eye(nev), atol=1e-10)
+
+
 def test_rayleigh_ritz_svqb_rank_deficient(api, ctx):
     rng = np.random.default_rng(3)
     n, m = 40, 12
