@@ -144,14 +144,16 @@ __device__ __forceinline__ void ie_stage_v(const float* __restrict__ ket, const 
 
 }
 
-// DU > 0: every leg of dimension DU and output leg OU known at compile time
-// (loop trip counts and strides become constants); DU = 0: read from g.
-template <int DU, int OU>
+// C0, C1, C2 > 0: the three leg dimensions and the output leg OU known at
+// compile time (loop trip counts and strides become constants); all zero:
+// read from g.
+template <int C0, int C1, int C2, int OU>
 __global__ __launch_bounds__(256) void ienv3_kernel(IEnv3Args g) {
   extern __shared__ float smem[];
-  const int lo = DU ? OU : g.o, lp = DU ? (OU == 0 ? 1 : 0) : g.p, lq = DU ? (OU == 2 ? 1 : 2) : g.q;
-  const int dm0 = DU ? DU : g.dim[0], dm1 = DU ? DU : g.dim[1], dm2 = DU ? DU : g.dim[2];
-  const int st0 = DU ? DU * DU : g.stride[0], st1 = DU ? DU : g.stride[1], st2 = DU ? 1 : g.stride[2];
+  constexpr bool CT = C0 > 0;
+  const int lo = CT ? OU : g.o, lp = CT ? (OU == 0 ? 1 : 0) : g.p, lq = CT ? (OU == 2 ? 1 : 2) : g.q;
+  const int dm0 = CT ? C0 : g.dim[0], dm1 = CT ? C1 : g.dim[1], dm2 = CT ? C2 : g.dim[2];
+  const int st0 = CT ? C1 * C2 : g.stride[0], st1 = CT ? C2 : g.stride[1], st2 = CT ? 1 : g.stride[2];
   const int dims[3] = {dm0, dm1, dm2}, strides[3] = {st0, st1, st2};
   const int Do = dims[lo], Dp = dims[lp], Dq = dims[lq];
   const int PQ = Dp * Dq;
@@ -196,19 +198,23 @@ __global__ __launch_bounds__(256) void ienv3_kernel(IEnv3Args g) {
     rv[i] = xo < Do;
     ro[i] = rv[i] ? xo * so : 0;
   }
-  if constexpr (DU > 0 && DU % 4 == 0 && (OU == 0 || OU == 1)) {
+  // compile-time dims of the output leg and the two contracted legs
+  constexpr int CDo = OU == 0 ? C0 : (OU == 1 ? C1 : C2);
+  constexpr int CDp = OU == 0 ? C1 : C0;
+  constexpr int CDq = OU == 2 ? C1 : C2;
+  if constexpr (CT && (OU == 0 || OU == 1) && CDq % 4 == 0 && (CDp * CDq / 4) % 16 == 0) {
     // the last contracted leg is unit-stride in the tensor: each lane loads its
     // bra rows as 16-byte runs of k (4 consecutive x_q, never crossing an x_p
-    // row since DU % 4 == 0) and MFMA t of a 16-k chunk takes element t of
+    // row since D_q % 4 == 0) and MFMA t of a 16-k chunk takes element t of
     // every lane's run, the V operand read the same way (the sum over k is
     // complete whichever k each MFMA sees, as long as A and B agree)
-    constexpr int KW = DU * DU / 4;  // k per wave
+    constexpr int KW = CDp * CDq / 4;  // k per wave
     static_assert(KW % 16 == 0, "k range of a wave must be whole 16-k chunks");
     const int kbase = KW * wid;
     floatx4 bq[2], bn[2];
     auto load_q = [&](int c, floatx4 (&dst)[2]) {
       const int kk = kbase + 16 * c + 4 * gq;
-      const int xp = kk / DU, xq = kk - xp * DU;
+      const int xp = kk / CDq, xq = kk - xp * CDq;
 #pragma unroll
       for (int i = 0; i < 2; ++i) dst[i] = *(const floatx4*)(bra + ro[i] + xp * sp + xq);  // raw; masked at use
     };
@@ -385,16 +391,27 @@ hipError_t launch_ienv3(const IEnv3Args& a, hipStream_t s) {
   auto set_lds = [](const void* f) {
     return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)IENV3_LDS_MAX) == hipSuccess;
   };
-  static const bool attr = set_lds(reinterpret_cast<const void*>(&ienv3_kernel<24, 0>)) &&
-                           set_lds(reinterpret_cast<const void*>(&ienv3_kernel<24, 1>)) &&
-                           set_lds(reinterpret_cast<const void*>(&ienv3_kernel<24, 2>)) &&
-                           set_lds(reinterpret_cast<const void*>(&ienv3_kernel<0, 0>));
+  static const bool attr = set_lds(reinterpret_cast<const void*>(&ienv3_kernel<24, 24, 24, 0>)) &&
+                           set_lds(reinterpret_cast<const void*>(&ienv3_kernel<24, 24, 24, 1>)) &&
+                           set_lds(reinterpret_cast<const void*>(&ienv3_kernel<24, 24, 24, 2>)) &&
+                           set_lds(reinterpret_cast<const void*>(&ienv3_kernel<24, 8, 8, 0>)) &&
+                           set_lds(reinterpret_cast<const void*>(&ienv3_kernel<24, 8, 8, 1>)) &&
+                           set_lds(reinterpret_cast<const void*>(&ienv3_kernel<24, 8, 8, 2>)) &&
+                           set_lds(reinterpret_cast<const void*>(&ienv3_kernel<0, 0, 0, 0>));
   if (!attr || bytes > IENV3_LDS_MAX) return hipErrorInvalidValue;
-  const bool u24 = a.dim[0] == 24 && a.dim[1] == 24 && a.dim[2] == 24;
-  if (u24 && a.o == 0) hipLaunchKernelGGL((ienv3_kernel<24, 0>), dim3((unsigned)a.n), dim3(256), bytes, s, a);
-  else if (u24 && a.o == 1) hipLaunchKernelGGL((ienv3_kernel<24, 1>), dim3((unsigned)a.n), dim3(256), bytes, s, a);
-  else if (u24 && a.o == 2) hipLaunchKernelGGL((ienv3_kernel<24, 2>), dim3((unsigned)a.n), dim3(256), bytes, s, a);
-  else hipLaunchKernelGGL((ienv3_kernel<0, 0>), dim3((unsigned)a.n), dim3(256), bytes, s, a);
+  const dim3 grid((unsigned)a.n), blk(256);
+#define IENV3_CASE(A0, A1, A2)                                                                      \
+  if (a.dim[0] == A0 && a.dim[1] == A1 && a.dim[2] == A2) {                                         \
+    if (a.o == 0) hipLaunchKernelGGL((ienv3_kernel<A0, A1, A2, 0>), grid, blk, bytes, s, a);        \
+    else if (a.o == 1) hipLaunchKernelGGL((ienv3_kernel<A0, A1, A2, 1>), grid, blk, bytes, s, a);   \
+    else hipLaunchKernelGGL((ienv3_kernel<A0, A1, A2, 2>), grid, blk, bytes, s, a);                 \
+    return hipGetLastError();                                                                       \
+  }
+  // the binary-tree nodes: uniform 24 bonds, and 24 to the parent with two 8-bond leaves
+  IENV3_CASE(24, 24, 24)
+  IENV3_CASE(24, 8, 8)
+#undef IENV3_CASE
+  hipLaunchKernelGGL((ienv3_kernel<0, 0, 0, 0>), grid, blk, bytes, s, a);
   return hipGetLastError();
 }
 

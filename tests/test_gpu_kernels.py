@@ -267,7 +267,11 @@ def test_rejects_bad_arguments(api, ctx):
     api.heff_apply_block(ctx, gt, gW, envs, 1, 0, to_dev(X), gY, compute=api.F64)
 
 
-@pytest.mark.parametrize("case", CASES)
+# the binary-tree node above two leaves (24 to the parent, 8 to each leaf)
+IENV_EXTRA = [(3, 1, [24, 8, 8], [1, 1, 1], [24, 8, 8], 2)]
+
+
+@pytest.mark.parametrize("case", CASES + IENV_EXTRA)
 @pytest.mark.parametrize("dt", [1, 2])
 @pytest.mark.parametrize("fused", [True, False])
 def test_identity_env_update_fp32_paths(api, ctx, case, dt, fused, monkeypatch):
