@@ -309,10 +309,11 @@ __global__ __launch_bounds__(256) void ienv3_kernel(IEnv3Args g) {
 // phase with leg 0 as the row leg (V_y = E_1 K_y E_2^T), then
 // Y = E_0 V (M = D_0, N = D_1 D_2, K = D_0), the N columns split over the waves
 // and written straight to Y (rows of D_1 D_2 contiguous floats).
-template <int DU>
+template <int C0, int C1, int C2>
 __global__ __launch_bounds__(256) void iheff3_kernel(IHeff3Args g) {
   extern __shared__ float smem[];
-  const int dm0 = DU ? DU : g.dim[0], dm1 = DU ? DU : g.dim[1], dm2 = DU ? DU : g.dim[2];
+  constexpr int DU = C0;  // > 0: dims known at compile time
+  const int dm0 = DU ? C0 : g.dim[0], dm1 = DU ? C1 : g.dim[1], dm2 = DU ? C2 : g.dim[2];
   const int Do = dm0, Dp = dm1, Dq = dm2;
   const int PQ = Dp * Dq;
   const int PQS = PQ | 1;
@@ -347,7 +348,7 @@ __global__ __launch_bounds__(256) void iheff3_kernel(IHeff3Args g) {
     const int n = 16 * nt + r;
     floatx4 acc[2] = {zero, zero};
 #pragma unroll
-    for (int s = 0; s < (DU ? (DU + 3) / 4 : 8); ++s) {
+    for (int s = 0; s < (DU ? (C0 + 3) / 4 : 8); ++s) {
       if (!DU && s >= ksteps) break;
       const int k = 4 * s + gq;
       const float b = (k < Do && n < PQ) ? sV[k * PQS + n] : 0.f;
@@ -372,13 +373,17 @@ hipError_t launch_iheff3(const IHeff3Args& a, hipStream_t s) {
   auto set_lds = [](const void* f) {
     return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)IENV3_LDS_MAX) == hipSuccess;
   };
-  static const bool attr = set_lds(reinterpret_cast<const void*>(&iheff3_kernel<24>)) &&
-                           set_lds(reinterpret_cast<const void*>(&iheff3_kernel<0>));
+  static const bool attr = set_lds(reinterpret_cast<const void*>(&iheff3_kernel<24, 24, 24>)) &&
+                           set_lds(reinterpret_cast<const void*>(&iheff3_kernel<24, 8, 8>)) &&
+                           set_lds(reinterpret_cast<const void*>(&iheff3_kernel<0, 0, 0>));
   if (!attr || bytes > IENV3_LDS_MAX) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)a.n), blk(256);
   if (a.dim[0] == 24 && a.dim[1] == 24 && a.dim[2] == 24)
-    hipLaunchKernelGGL((iheff3_kernel<24>), dim3((unsigned)a.n), dim3(256), bytes, s, a);
+    hipLaunchKernelGGL((iheff3_kernel<24, 24, 24>), grid, blk, bytes, s, a);
+  else if (a.dim[0] == 24 && a.dim[1] == 8 && a.dim[2] == 8)
+    hipLaunchKernelGGL((iheff3_kernel<24, 8, 8>), grid, blk, bytes, s, a);
   else
-    hipLaunchKernelGGL((iheff3_kernel<0>), dim3((unsigned)a.n), dim3(256), bytes, s, a);
+    hipLaunchKernelGGL((iheff3_kernel<0, 0, 0>), grid, blk, bytes, s, a);
   return hipGetLastError();
 }
 
