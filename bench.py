@@ -144,16 +144,29 @@ def learned_experiment(args):
     pairs from plain FP64 MINRES solves of the ALS preconditioner's systems
     on seeded force fields of the 12-mode generator (seeds 5000...), train the
     network on the GPU, then run block LOBPCG on the held-out 12-mode
-    workload (seed 3) with the DIAG, LEARNED and MINRES local maps and report
-    iterations and time against a longer FP64 MINRES-preconditioned run."""
+    workload (seed 3) with the DIAG, LEARNED and MINRES local maps, and MINRES
+    from DIAG- or learned-corrected starts, and report iterations and time
+    against a longer FP64 MINRES-preconditioned run."""
     import torch
-    import workloads as wl
     from paper_2512_15875_amd import ttn as api
-    from paper_2512_15875_amd.learned import Trainer, TrainOpts
-    from paper_2512_15875_amd.solver import LobpcgOpts, TTNEigensolver
 
     ctx = api.Context(0, workspace_bytes=8 << 30)
     out = {"experiment": "learned local preconditioner", "train": {}, "test": {}}
+    if args.learned_params:
+        # parameters of an earlier training run (saved by this experiment)
+        p = torch.from_numpy(np.load(args.learned_params)).to(device="cuda", dtype=torch.float32)
+        out["train"] = {"params": os.path.basename(args.learned_params)}
+    else:
+        p = _learned_train(args, ctx, out)
+    _learned_test(args, ctx, out, p)
+
+
+def _learned_train(args, ctx, out):
+    import torch
+    import workloads as wl
+    from paper_2512_15875_amd.learned import Trainer, TrainOpts
+    from paper_2512_15875_amd.solver import LobpcgOpts, TTNEigensolver
+
     t0 = time.perf_counter()
     Xs, Ts = [], []
     for f in range(args.fields):
@@ -188,22 +201,35 @@ def learned_experiment(args):
                     "harvest_s": round(t_h, 1), "train_s": round(time.perf_counter() - t1, 1),
                     "final": hist[-1]}
     np.save(os.path.join(args.out_dir, "learned_params.npy"), tr.p.cpu().numpy())
+    return tr.p
 
-    # held-out test: LOBPCG on the 12-mode workload (seed 3)
+
+def _learned_test(args, ctx, out, params):
+    """Held-out test: LOBPCG on the 12-mode workload (seed 3) with each local
+    map of the preconditioner; errors against the last iterate of a longer
+    plain FP64 MINRES run.  In FP64 the MINRES test run is the reference run's
+    own first iterations (the same computation)."""
+    import torch
+    import workloads as wl
+    from paper_2512_15875_amd.solver import LobpcgOpts, TTNEigensolver
+
     model = wl.make_config_model("c3")
     tree = wl.fork_tree(model.dims, 4, 1)
     k, D = args.k or 84, args.bond or 40
     bonds = wl.bond_dims(tree, D)
     x0 = wl.initial_block(tree, bonds, model.omega, model.dims, k, model.seed + 17)
     runs = {}
+    maps = args.learned_maps.split(",")
+    reuse = args.precision == "fp64" and "minres" in maps and args.test_iters <= args.ref_iters
     plan = [("reference_fp64_minres", "fp64", "minres", args.ref_iters)] + [
-        (f"{pc}_{args.precision}", args.precision, pc, args.test_iters) for pc in ("diag", "learned", "minres")]
+        (f"{pc}_{args.precision}", args.precision, pc, args.test_iters) for pc in maps
+        if not (reuse and pc == "minres")]
     for name, prec, pc, iters in plan:
         s = TTNEigensolver(ctx, tree, model, D=D, k=k, precision=prec)
         s.load_block(x0)
         torch.cuda.synchronize()
         ts = time.perf_counter()
-        s.lobpcg_start(LobpcgOpts(n_iter=iters, precond=pc, mlp=tr.p if pc == "learned" else None))
+        s.lobpcg_start(LobpcgOpts(n_iter=iters, precond=pc, mlp=params if "learned" in pc else None))
         lam_hist, t_hist = [], []
         for it in range(iters):
             s.lobpcg_step()
@@ -216,6 +242,9 @@ def learned_experiment(args):
               f"lam[-1]={lam_hist[-1][-1]:.4f}", file=sys.stderr, flush=True)
         del s
     ref = runs["reference_fp64_minres"][0][-1]
+    if reuse:
+        lh, th = runs["reference_fp64_minres"]
+        runs["minres_fp64"] = (lh[:args.test_iters], th[:args.test_iters])
     for name, (lh, th) in runs.items():
         err = [float(np.max(np.abs(l - ref))) for l in lh]
         hit = next((i for i, e in enumerate(err) if e <= 1e-3), None)
@@ -511,6 +540,10 @@ def main():
     ap.add_argument("--harvest-maxiter", type=int, default=300)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--test-iters", type=int, default=12)
+    ap.add_argument("--learned-maps", default="diag,learned,minres,minres+diag,minres+learned",
+                    help="local maps of the held-out LOBPCG runs (comma-separated)")
+    ap.add_argument("--learned-params", default="",
+                    help="saved network parameters (.npy) to test instead of harvesting and training")
     ap.add_argument("--ref-iters", type=int, default=24)
     ap.add_argument("--out-dir", default=os.path.join(ROOT, "gpurun_out"))
     ap.add_argument("--ensemble", action="store_true", help="run the many-Hamiltonian ensemble experiment instead")

@@ -193,7 +193,7 @@ ttn_status rayleigh_ritz(ttn_ctx* ctx, int32_t batch, const int32_t* m, int32_t 
  * LEARNED (the learned local preconditioner; not in the paper, which names
  * better preconditioners as future work in its outlook): the MLP of
  * ttn_mlp_forward maps the tile features of (b, diag(H_eff) - s_j) to a
- * candidate y_L; the DIAG solution y_D stays the fallback and the judge: the
+ * candidate y_L; the DIAG solution y_D stays the fallback and the yardstick: the
  * local result is the minimal-residual combination a y_D + c y_L, y_L the
  * network's correction (2x2 least
  * squares on |(H_eff - s_j)(a y_D + c y_L) - b|, FP64), and c = 0 whenever
@@ -207,6 +207,15 @@ typedef enum {
   TTN_SOLVE_LEARNED = 4
 } ttn_solve_mode;
 
+/* Start of the local MINRES (mode MINRES): NONE starts from the current y_u
+ * (the paper's warm start).  DIAG and LEARNED first correct it: with
+ * r0 = b - (H_eff - s_j) y_u, the correction c is the DIAG step r0 / (diag -
+ * s_j) at its minimal-residual scale (DIAG), or the LEARNED map applied to
+ * r0 in place of b (LEARNED, needs mlp_params); y_u += c and MINRES runs its
+ * maxiter iterations from there.  Costs one (DIAG) or two (LEARNED) extra
+ * H_eff applications of the k states per local solve.  Not in the paper. */
+typedef enum { TTN_WARM_NONE = 0, TTN_WARM_DIAG = 1, TTN_WARM_LEARNED = 2 } ttn_warm_start;
+
 typedef struct {
   int32_t mode;              /* ttn_solve_mode */
   int32_t maxiter;           /* MINRES iterations per local solve */
@@ -217,6 +226,7 @@ typedef struct {
                                 many steps: r = b - (H_eff - s) y in FP64, c from MINRES with TTN_F64_F32
                                 applies (rtol max(rtol, 1e-6), maxiter iterations), y += c in FP64 */
   double* learned_coef;      /* LEARNED, optional: device double[k][2], (a, c) of the last local step */
+  int32_t warm;              /* ttn_warm_start; MINRES with refine = 0 only */
 } ttn_solve_opts;
 
 typedef struct ttn_sweep ttn_sweep;

@@ -60,7 +60,9 @@ def als_solve(tree, W, shift: float, phi, y0, sweeps: int, maxiter: int, rtol: f
     """Approximate y with (H - shift) y = phi (Sec. II.C.4, Fig. als).
 
     local: the local map -- "minres" (the paper's), "diag" (y = b / (diag(H_eff)
-    - s)), or ("learned", params) for the learned map of ``oracle.mlp``."""
+    - s)), or ("learned", params) for the learned map of ``oracle.mlp``;
+    "minres+diag" or ("minres+learned", params): MINRES from a start corrected
+    by ``start_correction`` (not in the paper)."""
     root = tree.root
     y = ttn.canonicalize(tree, y0, root)
     phi_c = phi
@@ -75,8 +77,14 @@ def als_solve(tree, W, shift: float, phi, y0, sweeps: int, maxiter: int, rtol: f
                 b = ttn.heff_apply(tree, u, None, phi_c[u], Rc.incoming(u))
                 Hin = Hc.incoming(u)
                 Wu = W[u]
-                if local == "minres":
-                    x, it, res = minres(lambda v: ttn.heff_apply(tree, u, Wu, v, Hin, shift), b, y[u], rtol, maxiter)
+                kind = local if isinstance(local, str) else local[0]
+                if kind in ("minres", "minres+diag", "minres+learned"):
+                    A = lambda v: ttn.heff_apply(tree, u, Wu, v, Hin, shift)
+                    x0 = y[u]
+                    if kind != "minres":
+                        dg = ttn.heff_diag(tree, u, Wu, Hin, shift)
+                        x0 = x0 + start_correction(A, b - A(x0), dg, None if kind == "minres+diag" else local[1])
+                    x, it, res = minres(A, b, x0, rtol, maxiter)
                     if stats is not None:
                         stats.iters.append(it)
                         stats.resid.append(res)
@@ -96,6 +104,22 @@ def als_solve(tree, W, shift: float, phi, y0, sweeps: int, maxiter: int, rtol: f
                 Hc.update(u, v)
                 Rc.update(u, v)
     return y
+
+
+def start_correction(apply_A, r0: np.ndarray, d: np.ndarray, params=None) -> np.ndarray:
+    """Correction c of a MINRES start y0 for A y = b, from r0 = b - A y0 and
+    the diagonal d of A (an extension, not in the paper).  params None: the
+    DIAG step r0 / d at its minimal-residual scale a = <A(r0/d), r0> /
+    |A(r0/d)|^2 (a = 1 where that image vanishes); otherwise the learned local
+    map of ``oracle.mlp`` applied to the system A c = r0."""
+    if params is None:
+        g = r0 / d
+        Ag = apply_A(g)
+        gg = float(np.vdot(Ag, Ag))
+        return (float(np.vdot(Ag, r0)) / gg if gg > 0 else 1.0) * g
+    shp = r0.shape
+    c, _ = mlp.learned_local(params, lambda v: apply_A(v.reshape(shp)).ravel(), r0.ravel(), d.ravel())
+    return c.reshape(shp)
 
 
 # ------------------------------------------------------------- fitting

@@ -183,7 +183,8 @@ ttn_status local_diag(ttn_sweep* sw, int u, void* dg) {
 
 // LEARNED local step: y_D = b / d, y_L = MLP tiles, y_u = a y_D + c y_L with
 // (a, c) minimising the local residual of the shifted system.
-ttn_status learned_step(ttn_sweep* sw, int u, const ttn_solve_opts* opts, void* b, void* dg, void* cand, void* img) {
+ttn_status learned_step(ttn_sweep* sw, int u, const ttn_solve_opts* opts, void* b, void* dg, void* cand, void* img,
+                        void* out) {
   ttn_ctx* ctx = sw->ctx;
   const int k = sw->k, ct = sw->ct;
   const int64_t n = sw->y->size[u];
@@ -223,7 +224,7 @@ ttn_status learned_step(ttn_sweep* sw, int u, const ttn_solve_opts* opts, void* 
                                   2 * k, img, TTN_HEFF_APPLY, sw->compute);
   if (r != TTN_OK) return r;
   HIPCHK(ctx, launch_mr2(ct, img, (char*)img + (size_t)k * n * es, b, n, k, sw->d_coef, ctx->stream));
-  HIPCHK(ctx, launch_mr2_combine(ct, yD, yL, sw->d_coef, sw->y->ptr[u], n, k, ctx->stream));
+  HIPCHK(ctx, launch_mr2_combine(ct, yD, yL, sw->d_coef, out, n, k, ctx->stream));
   if (opts->learned_coef &&
       hipMemcpyAsync(opts->learned_coef, sw->d_coef, (size_t)2 * k * 8, hipMemcpyDeviceToDevice, ctx->stream) !=
           hipSuccess)
@@ -437,7 +438,8 @@ ttn_status ttn_sweep_run(ttn_ctx* ctx, ttn_sweep* sw, const ttn_solve_opts* opts
   if (!capturable) return run();
   std::ostringstream key;
   key << opts->mode << ":" << opts->maxiter << ":" << opts->rtol << ":" << (const void*)opts->mlp_params << ":"
-      << opts->mlp_compute << ":" << (const void*)opts->learned_coef << ":" << n_sweeps << ":" << init_first << ":"
+      << opts->mlp_compute << ":" << (const void*)opts->learned_coef << ":" << opts->refine << ":" << opts->warm << ":"
+      << n_sweeps << ":" << init_first << ":"
       << (const void*)iters_out << ":" << (const void*)resid_out;
   const std::string k = key.str();
   for (auto& g : sw->graphs)
@@ -556,7 +558,7 @@ ttn_status sweep_step(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, int32_t next, c
         if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
       } else {
         // candidates [2k][n] span vbuf(2..3), their images vbuf(4..5)
-        r = learned_step(sw, u, opts, b, dg, vbuf(2), vbuf(4));
+        r = learned_step(sw, u, opts, b, dg, vbuf(2), vbuf(4), y_u);
         if (r != TTN_OK) return r;
       }
     } else {
@@ -564,6 +566,8 @@ ttn_status sweep_step(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, int32_t next, c
         return api_fail(ctx, TTN_E_ARG, "bad MINRES options");
       if (opts->refine > 0 && ct != 0)
         return api_fail(ctx, TTN_E_DTYPE, "mixed-precision refinement needs an FP64 sweep");
+      if (opts->warm < TTN_WARM_NONE || opts->warm > TTN_WARM_LEARNED || (opts->warm != TTN_WARM_NONE && opts->refine > 0))
+        return api_fail(ctx, TTN_E_ARG, "corrected MINRES start: warm 0..2, and only without refinement");
       void *v = vbuf(1), *vp = vbuf(2), *p = vbuf(3), *d1 = vbuf(4), *d2 = vbuf(5);
       // batched MINRES on (H_eff - s) x = rhs, warm start x with Ax0 = (H_eff - s) x
       auto minres = [&](void* x, const void* rhs, const void* ax0, ttn_dtype comp, double rtol) -> ttn_status {
@@ -593,12 +597,46 @@ ttn_status sweep_step(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, int32_t next, c
         }
         return TTN_OK;
       };
-      if (opts->refine == 0) {
+      if (opts->refine == 0 && opts->warm == TTN_WARM_NONE) {
         // p = (H_eff - s) y_u  (warm start)
         r = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, y_u, k, p,
                              TTN_HEFF_APPLY, sw->compute);
         if (r != TTN_OK) return r;
         r = minres(y_u, b, p, sw->compute, opts->rtol);
+        if (r != TTN_OK) return r;
+      } else if (opts->refine == 0) {
+        // corrected start: r0 = b - (H_eff - s) y_u, a minimal-residual DIAG
+        // or learned correction c of r0, y_u += c, then MINRES from there
+        void *ax = vbuf(6), *res = vbuf(7), *dg = vbuf(1), *cor = vbuf(2), *acor = vbuf(3);
+        r = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, y_u, k, ax,
+                             TTN_HEFF_APPLY, sw->compute);
+        if (r != TTN_OK) return r;
+        HIPCHK(ctx, launch_resid_zero(ct, b, ax, res, cor, n * k, ctx->stream));
+        r = local_diag(sw, u, dg);
+        if (r != TTN_OK) return r;
+        if (opts->warm == TTN_WARM_DIAG) {
+          HIPCHK(ctx, launch_diag_solve(ct, res, dg, cor, n * k, ctx->stream));
+          r = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, cor, k, acor,
+                               TTN_HEFF_APPLY, sw->compute);
+          if (r != TTN_OK) return r;
+          // best scale of the DIAG step (a 2x2 system with two equal images keeps c = 0)
+          HIPCHK(ctx, launch_mr2(ct, acor, acor, res, n, k, sw->d_coef, ctx->stream));
+          HIPCHK(ctx, launch_mr2_combine(ct, cor, cor, sw->d_coef, cor, n, k, ctx->stream));
+          HIPCHK(ctx, launch_mr2_combine(ct, acor, acor, sw->d_coef, acor, n, k, ctx->stream));
+        } else {
+          // candidates [2k][n] packed from vbuf(2), their images packed from
+          // vbuf(4) (the learned image starts k*n entries in); the correction
+          // lands in vbuf(1), its image in vbuf(3)
+          void* img = vbuf(4);
+          r = learned_step(sw, u, opts, res, dg, vbuf(2), img, dg);
+          if (r != TTN_OK) return r;
+          cor = dg;
+          HIPCHK(ctx, launch_mr2_combine(ct, img, (char*)img + (size_t)k * n * es, sw->d_coef, acor, n, k,
+                                         ctx->stream));
+        }
+        HIPCHK(ctx, launch_axpy_rows(ct, cor, y_u, n * k, ctx->stream));
+        HIPCHK(ctx, launch_axpy_rows(ct, acor, ax, n * k, ctx->stream));
+        r = minres(y_u, b, ax, sw->compute, opts->rtol);
         if (r != TTN_OK) return r;
       } else {
         // iterative refinement: FP64 residual, correction by MINRES in FP32

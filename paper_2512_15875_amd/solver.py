@@ -33,7 +33,8 @@ class LobpcgOpts:
     fit_sweeps: int = 2
     drop_tol: float = 1e-12
     resid_tol: Optional[float] = None
-    precond: str = "minres"           # local map of the ALS preconditioner: "minres", "diag" or "learned"
+    precond: str = "minres"           # local map of the ALS preconditioner: "minres", "diag", "learned", or
+                                      # "minres+diag" / "minres+learned" (MINRES from a corrected start)
     mlp: Optional[torch.Tensor] = None  # learned map parameters (device FP32)
     mlp_compute: int = ttn.BF16
 
@@ -229,9 +230,12 @@ class TTNEigensolver:
         ttn.block_node_norms2(ctx, self.R, root, rn)
         # preconditioned residual: (H - s) w = r by ALS
         self._copy_rows(self.Wp, 0, self.R, 0, k)
-        mode = {"minres": ttn.SOLVE_MINRES, "diag": ttn.SOLVE_DIAG, "learned": ttn.SOLVE_LEARNED}[opts.precond]
+        mode, warm = {"minres": (ttn.SOLVE_MINRES, ttn.WARM_NONE), "diag": (ttn.SOLVE_DIAG, ttn.WARM_NONE),
+                      "learned": (ttn.SOLVE_LEARNED, ttn.WARM_NONE),
+                      "minres+diag": (ttn.SOLVE_MINRES, ttn.WARM_DIAG),
+                      "minres+learned": (ttn.SOLVE_MINRES, ttn.WARM_LEARNED)}[opts.precond]
         self.sw_pre.run(mode, opts.als_sweeps, init=True, graph=self.graphs, maxiter=opts.minres_maxiter,
-                        rtol=opts.minres_rtol, mlp=opts.mlp, mlp_compute=opts.mlp_compute)
+                        rtol=opts.minres_rtol, mlp=opts.mlp, mlp_compute=opts.mlp_compute, warm=warm)
         ttn.block_normalize_node(ctx, self.Wp, root)
         self._copy_rows(self.B, k, self.Wp, 0, k)
         rnorm = torch.sqrt(rn).cpu().numpy()

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libttn.so")
 F64, F32, BF16, F64_F32 = 0, 1, 2, 3
 HEFF_APPLY, HEFF_NO_SHIFT, HEFF_DIAG, HEFF_ACCUM = 0, 1, 2, 4
 SOLVE_MINRES, SOLVE_DIAG, SOLVE_FIT, SOLVE_SKIP, SOLVE_LEARNED = 0, 1, 2, 3, 4
+WARM_NONE, WARM_DIAG, WARM_LEARNED = 0, 1, 2
 
 _lib = None
 
@@ -359,7 +360,7 @@ def sop_build(tree: Tree, node_mode: Sequence[int], omega, dims, monomials, coef
 
 class SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("maxiter", C.c_int32), ("rtol", C.c_double), ("mlp_params", C.c_void_p),
-                ("mlp_compute", C.c_int32), ("refine", C.c_int32), ("learned_coef", C.c_void_p)]
+                ("mlp_compute", C.c_int32), ("refine", C.c_int32), ("learned_coef", C.c_void_p), ("warm", C.c_int32)]
 
 
 class Sweep:
@@ -390,16 +391,17 @@ class Sweep:
         _check(lib().ttn_sweep_init(self.h, centre), self.ctx)
 
     def step(self, node: int, nxt: int, mode: int, maxiter: int = 0, rtol: float = 0.0, iters=None, resid=None,
-             mlp: Optional[torch.Tensor] = None, mlp_compute: int = BF16, learned_coef=None, refine: int = 0):
+             mlp: Optional[torch.Tensor] = None, mlp_compute: int = BF16, learned_coef=None, refine: int = 0,
+             warm: int = 0):
         o = SolveOpts(mode, maxiter, rtol, None if mlp is None else mlp.data_ptr(), mlp_compute, refine,
-                      None if learned_coef is None else learned_coef.data_ptr())
+                      None if learned_coef is None else learned_coef.data_ptr(), warm)
         _check(lib().sweep_step(self.ctx.h, self.h, node, nxt, C.byref(o), _ptr(iters), _ptr(resid)), self.ctx)
 
     def run(self, mode: int, n_sweeps: int = 1, init: bool = False, graph: bool = False, maxiter: int = 0,
             rtol: float = 0.0, iters=None, resid=None, mlp: Optional[torch.Tensor] = None, mlp_compute: int = BF16,
-            refine: int = 0):
+            refine: int = 0, warm: int = 0):
         """n_sweeps native sweeps (see ttn_sweep_run), optionally replayed as a HIP graph."""
-        o = SolveOpts(mode, maxiter, rtol, None if mlp is None else mlp.data_ptr(), mlp_compute, refine, None)
+        o = SolveOpts(mode, maxiter, rtol, None if mlp is None else mlp.data_ptr(), mlp_compute, refine, None, warm)
         _check(lib().ttn_sweep_run(self.ctx.h, self.h, C.byref(o), n_sweeps, int(init), int(graph), _ptr(iters),
                                    _ptr(resid)), self.ctx)
 

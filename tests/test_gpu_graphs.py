@@ -49,7 +49,7 @@ def _restore(blk, snap):
         blk.t[u].copy_(t)
 
 
-@pytest.mark.parametrize("mode", ["fit", "minres", "diag"])
+@pytest.mark.parametrize("mode", ["fit", "minres", "diag", "minres_diag_start"])
 def test_graph_replays_match_eager(api, mode):
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -65,7 +65,8 @@ def test_graph_replays_match_eager(api, mode):
         else:
             sh = to_dev(np.array([-300.0, -100.0, -700.0]))
             sw = api.Sweep(ctx, gt, op, Y, [(None, P, idx, idx, None)], shift=sh, compute=api.F64)
-            m, kw = (api.SOLVE_MINRES, {"maxiter": 6}) if mode == "minres" else (api.SOLVE_DIAG, {})
+            m, kw = {"minres": (api.SOLVE_MINRES, {"maxiter": 6}), "diag": (api.SOLVE_DIAG, {}),
+                     "minres_diag_start": (api.SOLVE_MINRES, {"maxiter": 6, "warm": api.WARM_DIAG})}[mode]
         start = _snapshot(Y, tree.n)
         # eager reference
         sw.run(m, 2, init=True, graph=False, **kw)

@@ -237,6 +237,46 @@ def test_als_local_maps_match_oracle(api, ctx, local):
             assert rel_err(Y.t[u][j].cpu().numpy(), ref[u]) < tol, (j, u)
 
 
+@pytest.mark.parametrize("warm", ["diag", "learned"])
+def test_als_corrected_minres_start_matches_oracle(api, ctx, warm):
+    """MINRES local solves from a DIAG- or learned-corrected start (fixed
+    iteration count) against the oracle's ALS with the same start."""
+    k = 3
+    tree, W, bonds, gt, op, phi = _setup(api, ctx, k)
+    y0 = [ottn.canonicalize(tree, p, tree.root) for p in phi]
+    shifts = [-400.0, -150.0, -900.0]
+    p = _params(34)
+    Y = _upload(api, ctx, gt, tree, bonds, y0, k)
+    P = _upload(api, ctx, gt, tree, bonds, phi, k)
+    sw = api.Sweep(ctx, gt, op, Y, [(None, P, list(range(k)), list(range(k)), None)],
+                   shift=to_dev(np.array(shifts)), compute=api.F64)
+    w = api.WARM_DIAG if warm == "diag" else api.WARM_LEARNED
+    kw = dict(maxiter=4, rtol=0.0, mlp=_f32(p), mlp_compute=api.F32, warm=w)
+    sw.run(api.SOLVE_MINRES, 1, init=True, **kw)
+    ctx.sync()
+    tol = 1e-8 if warm == "diag" else 1e-4
+    for j in range(k):
+        ref = osol.als_solve(tree, W, shifts[j], phi[j], phi[j], sweeps=1, maxiter=4, rtol=0.0,
+                             local="minres+diag" if warm == "diag" else ("minres+learned", p))
+        for u in range(tree.n):
+            assert rel_err(Y.t[u][j].cpu().numpy(), ref[u]) < tol, (j, u)
+
+
+def test_corrected_start_rejects_refinement(api, ctx):
+    k = 2
+    tree, W, bonds, gt, op, phi = _setup(api, ctx, k)
+    y0 = [ottn.canonicalize(tree, p, tree.root) for p in phi]
+    Y = _upload(api, ctx, gt, tree, bonds, y0, k)
+    P = _upload(api, ctx, gt, tree, bonds, phi, k)
+    sw = api.Sweep(ctx, gt, op, Y, [(None, P, [0, 1], [0, 1], None)], shift=to_dev(np.array([-300.0, -300.0])),
+                   compute=api.F64)
+    sw.init(tree.root)
+    with pytest.raises(api.TTNError):
+        sw.step(tree.root, -1, api.SOLVE_MINRES, maxiter=3, rtol=0.0, refine=2, warm=api.WARM_DIAG)
+    with pytest.raises(api.TTNError):
+        sw.step(tree.root, -1, api.SOLVE_MINRES, maxiter=3, rtol=0.0, warm=7)
+
+
 def test_learned_step_never_worse_than_scaled_diag(api, ctx):
     """With corrupted (huge random) weights the combination falls back to the
     DIAG direction: the local residual is no larger than DIAG's at its best
