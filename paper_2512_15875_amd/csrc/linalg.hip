@@ -557,14 +557,16 @@ __device__ __forceinline__ double wave_allsum(double v) {
 // the diagonal normalised to v_k = 1 (tau scaled to match), R is saved to a
 // small separate array, and Q is formed in place by backward accumulation of
 // the reflectors (each column finished as -tau v below, 1 - tau on, 0 above
-// the diagonal).  One workgroup per state; wave 0 builds each reflector, then
-// every wave applies it to the columns it owns (j = wave mod 8: dot product
-// as a wave sum, then the update, no barrier in between), so a reflector costs
-// two workgroup barriers.  The sign fix makes diag(R) >= 0 as in the
-// global-memory kernel above, which serves the nodes whose m x n doubles do
-// not fit.
+// the diagonal).  One workgroup per state, one barrier per reflector, with
+// look-ahead: while waves 1..15 apply reflector k to columns k+2.. (dot product
+// as a wave sum, then the update), wave 0 applies it to column k+1 and at once
+// builds reflector k+1 from that column, which no other wave touches in the
+// step.  The Q formation mirrors it: wave 0 finishes column i+1 as a column
+// of Q and applies reflector i to it while the other waves take columns i+2..
+// The sign fix makes diag(R) >= 0 as in the global-memory kernel above, which
+// serves the nodes whose m x n doubles do not fit.
 
-#define QR_NT 512  // threads of the LDS-resident QR (8 waves: more columns in flight per reflector)
+#define QR_NT 1024  // threads of the LDS-resident QR (16 waves: more columns in flight per reflector)
 #define QR_NW (QR_NT / 64)
 
 // ITM > 0: every row loop of a lane has at most ITM iterations (m <= 64 ITM),
@@ -617,47 +619,60 @@ __global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const
     }
   };
   (void)nit;
-  for (int k = 0; k < n; ++k) {
+  // reflector k from column k (rows k..m-1), by one wave: v = (1, a[k+1..] / v0),
+  // tau' = 2 v0^2 / |x - alpha e_k|^2; each lane reads the rows i = k + lane + 64 it
+  auto build = [&](int k) {
     double* a = A + (size_t)k * m;
-    // wave 0 builds reflector k: v = (1, a[k+1..] / v0), tau' = 2 v0^2 / |x - alpha e_k|^2
-    if (wv == 0) {
-      double xv[IT];
-      double ss = 0;
-      if constexpr (ITM > 0) {
+    double xv[IT];
+    double ss = 0;
+    if constexpr (ITM > 0) {
 #pragma unroll
-        for (int it = 0; it < IT; ++it) {
-          const int i = k + lane + 64 * it;
-          xv[it] = i < m ? a[i] : 0.0;
-        }
+      for (int it = 0; it < IT; ++it) {
+        const int i = k + lane + 64 * it;
+        xv[it] = i < m ? a[i] : 0.0;
+      }
 #pragma unroll
-        for (int it = 0; it < IT; ++it) ss += xv[it] * xv[it];
-      } else {
-        for (int i = k + lane; i < m; i += 64) ss += a[i] * a[i];
-      }
-      ss = wave_allsum(ss);
-      const double x0 = a[k], nrm = sqrt(ss);
-      const double alpha = nrm == 0.0 ? 0.0 : (x0 >= 0 ? -nrm : nrm);
-      const double v0 = x0 - alpha;
-      const double vn2 = ss - x0 * x0 + v0 * v0;
-      const double inv = v0 != 0.0 ? 1.0 / v0 : 0.0;
-      if constexpr (ITM > 0) {
-#pragma unroll
-        for (int it = 0; it < IT; ++it) {
-          const int i = k + lane + 64 * it;
-          if (i > k && i < m) a[i] = xv[it] * inv;
-        }
-      } else {
-        for (int i = k + 1 + lane; i < m; i += 64) a[i] *= inv;
-      }
-      if (lane == 0) {
-        tau[k] = (vn2 > 0 && v0 != 0.0) ? 2.0 * v0 * v0 / vn2 : 0.0;
-        Rl[k * n + k] = alpha;
-      }
+      for (int it = 0; it < IT; ++it) ss += xv[it] * xv[it];
+    } else {
+      for (int i = k + lane; i < m; i += 64) ss += a[i] * a[i];
     }
-    __syncthreads();
-    // every wave applies the reflector to its own columns j > k (dot, then update)
+    ss = wave_allsum(ss);
+    const double x0 = a[k], nrm = sqrt(ss);
+    const double alpha = nrm == 0.0 ? 0.0 : (x0 >= 0 ? -nrm : nrm);
+    const double v0 = x0 - alpha;
+    const double vn2 = ss - x0 * x0 + v0 * v0;
+    const double inv = v0 != 0.0 ? 1.0 / v0 : 0.0;
+    if constexpr (ITM > 0) {
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int i = k + lane + 64 * it;
+        if (i > k && i < m) a[i] = xv[it] * inv;
+      }
+    } else {
+      for (int i = k + 1 + lane; i < m; i += 64) a[i] *= inv;
+    }
+    if (lane == 0) {
+      tau[k] = (vn2 > 0 && v0 != 0.0) ? 2.0 * v0 * v0 / vn2 : 0.0;
+      Rl[k * n + k] = alpha;
+    }
+  };
+  // LDS writes of this wave's lanes visible to its other lanes
+  auto wave_lds_sync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+  };
+  if (wv == 0) build(0);
+  __syncthreads();
+  for (int k = 0; k + 1 < n; ++k) {
+    const double* a = A + (size_t)k * m;
     const double tk = tau[k];
-    for (int j = k + 1 + wv; j < n; j += QR_NW) dot_update(a, A + (size_t)j * m, k + 1, k, tk);
+    if (wv == 0) {
+      dot_update(a, A + (size_t)(k + 1) * m, k + 1, k, tk);
+      wave_lds_sync();
+      build(k + 1);
+    } else {
+      for (int j = k + 1 + wv; j < n; j += QR_NW - 1) dot_update(a, A + (size_t)j * m, k + 1, k, tk);
+    }
     __syncthreads();
   }
   for (int e = t; e < n * n; e += QR_NT) {
@@ -665,15 +680,27 @@ __global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const
     if (c > r) Rl[e] = A[(size_t)c * m + r];
   }
   __syncthreads();
-  // Q in place: backward accumulation of the reflectors
-  for (int i = n - 1; i >= 0; --i) {
+  // Q in place: backward accumulation of the reflectors; column i is finished
+  // as e_i - tau_i v_i once every dot with reflector i is done
+  auto finish = [&](int i, int t0, int stride) {
     double* ai = A + (size_t)i * m;
     const double ti = tau[i];
-    for (int j = i + 1 + wv; j < n; j += QR_NW) dot_update(ai, A + (size_t)j * m, i + 1, i, ti);
-    __syncthreads();
-    for (int r = t; r < m; r += QR_NT) ai[r] = r > i ? -ti * ai[r] : (r == i ? 1.0 - ti : 0.0);
+    for (int r = t0; r < m; r += stride) ai[r] = r > i ? -ti * ai[r] : (r == i ? 1.0 - ti : 0.0);
+  };
+  for (int i = n - 2; i >= 0; --i) {
+    const double* ai = A + (size_t)i * m;
+    const double ti = tau[i];
+    if (wv == 0) {
+      finish(i + 1, lane, 64);
+      wave_lds_sync();
+      dot_update(ai, A + (size_t)(i + 1) * m, i + 1, i, ti);
+    } else {
+      for (int j = i + 1 + wv; j < n; j += QR_NW - 1) dot_update(ai, A + (size_t)j * m, i + 1, i, ti);
+    }
     __syncthreads();
   }
+  finish(0, t, QR_NT);
+  __syncthreads();
   // sign fix diag(R) >= 0, R out (row-major), Q back to the node tensor
   double* R = Rout + (size_t)z * n * n;
   for (int e = t; e < n * n; e += QR_NT) {
