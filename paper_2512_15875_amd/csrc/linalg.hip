@@ -31,10 +31,34 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return r;
 }
 
-__device__ __forceinline__ double wave_sum64(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+// v + (v moved by the DPP pattern CTRL), the two 32-bit halves moved separately
+template <int CTRL>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return v + __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wave sum without the LDS crossbar: within each row of 16 lanes by DPP
+// (rotate by 8 and by 4, then swap pairs of 2 and of 1), then the four row sums
+// read from lanes 0, 16, 32, 48.  The result is wave-uniform.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v = dpp_add<0x128>(v);  // row_ror:8
+  v = dpp_add<0x124>(v);  // row_ror:4
+  v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
+__device__ __forceinline__ double wave_sum64(double v) { return wave_sum_dpp(v); }
 
 // Symmetric eigendecomposition of the n x n matrix A (row-major, leading dim
 // ld, global memory; destroyed).  Householder reduction to tridiagonal form
@@ -547,10 +571,7 @@ __global__ __launch_bounds__(256) void qr_kernel(T* X, int64_t size, const int32
 }
 
 // sum over the 64 lanes of a wave, result in every lane
-__device__ __forceinline__ double wave_allsum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
+
 
 // Householder QR with the working matrix resident in LDS (dynamic shared
 // memory, FP64): column-major A (m x n); reflector k is stored in place below
@@ -603,7 +624,7 @@ __global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const
       double d = lane == 0 ? y[kd] : 0.0;
 #pragma unroll
       for (int it = 0; it < IT; ++it) d += vv[it] * yv[it];
-      d = tk * wave_allsum(d);
+      d = tk * wave_sum_dpp(d);
       if (lane == 0) y[kd] -= d;
 #pragma unroll
       for (int it = 0; it < IT; ++it) {
@@ -613,7 +634,7 @@ __global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const
     } else {
       double d = lane == 0 ? y[kd] : 0.0;
       for (int i = s + lane; i < m; i += 64) d += v[i] * y[i];
-      d = tk * wave_allsum(d);
+      d = tk * wave_sum_dpp(d);
       if (lane == 0) y[kd] -= d;
       for (int i = s + lane; i < m; i += 64) y[i] -= d * v[i];
     }
@@ -636,7 +657,7 @@ __global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const
     } else {
       for (int i = k + lane; i < m; i += 64) ss += a[i] * a[i];
     }
-    ss = wave_allsum(ss);
+    ss = wave_sum_dpp(ss);
     const double x0 = a[k], nrm = sqrt(ss);
     const double alpha = nrm == 0.0 ? 0.0 : (x0 >= 0 ? -nrm : nrm);
     const double v0 = x0 - alpha;
