@@ -677,6 +677,68 @@ __global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const
       Rl[k * n + k] = alpha;
     }
   };
+  // ITM > 0, one wave: reflector k applied to column k+1 (y), then reflector
+  // k+1 built from the updated column while it is still in registers (the
+  // same rows per lane as dot_update and build, so the same arithmetic)
+  auto update_build = [&](const double* v, double* y, int k, double tk) {
+    const int s = k + 1;
+    double vv[IT], xv[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int i = s + lane + 64 * it;
+      vv[it] = i < m ? v[i] : 0.0;
+      xv[it] = i < m ? y[i] : 0.0;
+    }
+    double d = lane == 0 ? y[k] : 0.0;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) d += vv[it] * xv[it];
+    d = tk * wave_sum_dpp(d);
+    if (lane == 0) y[k] -= d;
+    double ss = 0;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      xv[it] = xv[it] - d * vv[it];
+      ss += xv[it] * xv[it];
+    }
+    ss = wave_sum_dpp(ss);
+    const double x0 = lane_value(xv[0], 0), nrm = sqrt(ss);
+    const double alpha = nrm == 0.0 ? 0.0 : (x0 >= 0 ? -nrm : nrm);
+    const double v0 = x0 - alpha;
+    const double vn2 = ss - x0 * x0 + v0 * v0;
+    const double inv = v0 != 0.0 ? 1.0 / v0 : 0.0;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int i = s + lane + 64 * it;
+      if (i < m) y[i] = i > s ? xv[it] * inv : xv[it];
+    }
+    if (lane == 0) {
+      tau[s] = (vn2 > 0 && v0 != 0.0) ? 2.0 * v0 * v0 / vn2 : 0.0;
+      Rl[s * n + s] = alpha;
+    }
+  };
+  // ITM > 0, one wave: column i+1 (y, holding reflector i+1 below its
+  // diagonal) finished as e_{i+1} - tn v_{i+1}, then reflector i (v, ti)
+  // applied to it, in one pass over the rows
+  auto finish_update = [&](const double* v, double* y, int i, double ti, double tn) {
+    const int s = i + 1;
+    double vv[IT], yv[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int r = s + lane + 64 * it;
+      vv[it] = r < m ? v[r] : 0.0;
+      yv[it] = r < m ? (r > s ? -tn * y[r] : 1.0 - tn) : 0.0;
+    }
+    double d = 0.0;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) d += vv[it] * yv[it];
+    d = ti * wave_sum_dpp(d);
+    for (int r = lane; r < s; r += 64) y[r] = r == i ? -d : 0.0;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int r = s + lane + 64 * it;
+      if (r < m) y[r] = yv[it] - d * vv[it];
+    }
+  };
   // LDS writes of this wave's lanes visible to its other lanes
   auto wave_lds_sync = [] {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -688,9 +750,13 @@ __global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const
     const double* a = A + (size_t)k * m;
     const double tk = tau[k];
     if (wv == 0) {
-      dot_update(a, A + (size_t)(k + 1) * m, k + 1, k, tk);
-      wave_lds_sync();
-      build(k + 1);
+      if constexpr (ITM > 0) {
+        update_build(a, A + (size_t)(k + 1) * m, k, tk);
+      } else {
+        dot_update(a, A + (size_t)(k + 1) * m, k + 1, k, tk);
+        wave_lds_sync();
+        build(k + 1);
+      }
     } else {
       for (int j = k + 1 + wv; j < n; j += QR_NW - 1) dot_update(a, A + (size_t)j * m, k + 1, k, tk);
     }
@@ -712,9 +778,13 @@ __global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const
     const double* ai = A + (size_t)i * m;
     const double ti = tau[i];
     if (wv == 0) {
-      finish(i + 1, lane, 64);
-      wave_lds_sync();
-      dot_update(ai, A + (size_t)(i + 1) * m, i + 1, i, ti);
+      if constexpr (ITM > 0) {
+        finish_update(ai, A + (size_t)(i + 1) * m, i, ti, tau[i + 1]);
+      } else {
+        finish(i + 1, lane, 64);
+        wave_lds_sync();
+        dot_update(ai, A + (size_t)(i + 1) * m, i + 1, i, ti);
+      }
     } else {
       for (int j = i + 1 + wv; j < n; j += QR_NW - 1) dot_update(ai, A + (size_t)j * m, i + 1, i, ti);
     }
