@@ -16,6 +16,7 @@ hipError_t launch_rr(int batch, const int32_t* d_m, int ld, const double* H, con
                      hipStream_t s);
 hipError_t launch_qr(int ctype, void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride, double* work,
                      double* R, int nz, int* flag, hipStream_t s);
+bool absorb_in_place(int m, int n);
 hipError_t launch_absorb(int ctype, const void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride,
                          const double* R, void* Y, int nz, hipStream_t s);
 hipError_t launch_norms2(int ctype, const void* X, int64_t n, int nz, double* out, hipStream_t s);
@@ -130,10 +131,12 @@ ttn_status ttn_block_move_centre(ttn_ctx* ctx, ttn_block* b, int32_t u, int32_t 
   const std::string akey = "absorb:" + std::to_string(m_v) + "x" + std::to_string(n);
   pr = prof_begin(ctx, akey.c_str(), "absorb_kernel", 2.0 * m_v * (double)n * n * k,
                   (double)k * (2.0 * m_v * n * es + 8.0 * n * n), k);
-  e = launch_absorb(ct, b->ptr[v], b->size[v], rv, m_v, n, cs_v, R, Y, k, ctx->stream);
+  const bool in_place = absorb_in_place(m_v, n);
+  e = launch_absorb(ct, b->ptr[v], b->size[v], rv, m_v, n, cs_v, R, in_place ? b->ptr[v] : Y, k, ctx->stream);
   prof_end(ctx, pr);
   if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
-  if (hipMemcpyAsync(b->ptr[v], Y, (size_t)k * b->size[v] * es, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
+  if (!in_place &&
+      hipMemcpyAsync(b->ptr[v], Y, (size_t)k * b->size[v] * es, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
     return api_fail(ctx, TTN_E_DEVICE, "copy back failed");
   return TTN_OK;
 }

@@ -916,15 +916,22 @@ static hipError_t absorb_rows(int ctype, const void* X, int64_t size, const int3
   return hipGetLastError();
 }
 
+// The row-wise kernel reads a whole row before writing it and rows are
+// disjoint, so it may write over its input (Y == X): no copy back.
+bool absorb_in_place(int m, int n) {
+  (void)m;
+  return n <= 48;
+}
+
 hipError_t launch_absorb(int ctype, const void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride,
                          const double* R, void* Y, int nz, hipStream_t s) {
-  // row-wise kernel for tall matrices (measured: 576 x 24 28 -> 20 us per 50 states;
-  // for a few dozen rows the element-wise kernel keeps more threads busy)
-  if (m >= 256 && n <= 8) return absorb_rows<8>(ctype, X, size, roff, m, n, cstride, R, Y, nz, s);
-  if (m >= 256 && n <= 16) return absorb_rows<16>(ctype, X, size, roff, m, n, cstride, R, Y, nz, s);
-  if (m >= 256 && n <= 24) return absorb_rows<24>(ctype, X, size, roff, m, n, cstride, R, Y, nz, s);
-  if (m >= 256 && n <= 32) return absorb_rows<32>(ctype, X, size, roff, m, n, cstride, R, Y, nz, s);
-  if (m >= 256 && n <= 48) return absorb_rows<48>(ctype, X, size, roff, m, n, cstride, R, Y, nz, s);
+  // row-wise kernel (measured: 576 x 24 28 -> 20 us per 50 states), in place
+  // for every bond it covers; the element-wise kernel for larger bonds
+  if (n <= 8) return absorb_rows<8>(ctype, X, size, roff, m, n, cstride, R, Y, nz, s);
+  if (n <= 16) return absorb_rows<16>(ctype, X, size, roff, m, n, cstride, R, Y, nz, s);
+  if (n <= 24) return absorb_rows<24>(ctype, X, size, roff, m, n, cstride, R, Y, nz, s);
+  if (n <= 32) return absorb_rows<32>(ctype, X, size, roff, m, n, cstride, R, Y, nz, s);
+  if (n <= 48) return absorb_rows<48>(ctype, X, size, roff, m, n, cstride, R, Y, nz, s);
   const int64_t tot = (int64_t)m * n * nz;
   const unsigned g = (unsigned)((tot + 255) / 256);
   if (ctype == 0)
