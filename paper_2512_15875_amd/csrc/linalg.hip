@@ -60,6 +60,8 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
 
 __device__ __forceinline__ double wave_sum64(double v) { return wave_sum_dpp(v); }
 
+#define QL_CH 16  // loads of a row of Z in flight together during the QL rotations
+
 // Symmetric eigendecomposition of the n x n matrix A (row-major, leading dim
 // ld, global memory; destroyed).  Householder reduction to tridiagonal form
 // A = Q T Q^T with Q formed explicitly in Z (backward accumulation), then the
@@ -221,13 +223,31 @@ __device__ void sym_eig(double* A, double* Z, int n, int ld, double* rc, double*
         __syncthreads();
         break;  // uniform: eigenvalue l converged (or gave up)
       }
+      // each row of Z through the rotations hi..lo; column i+1 is final after
+      // rotation i, column i carries into the next one.  Chunks of QL_CH
+      // loads are issued together instead of one dependent load per rotation.
       for (int r = t; r < n; r += blockDim.x) {
         double* zr = Z + (size_t)r * ld;
-        for (int i = hi; i >= lo; --i) {
-          const double f = zr[i + 1];
-          zr[i + 1] = rs[i] * zr[i] + rc[i] * f;
-          zr[i] = rc[i] * zr[i] - rs[i] * f;
+        double carry = zr[hi + 1];
+        for (int i = hi; i >= lo; i -= QL_CH) {
+          const int cnt = i - lo + 1 < QL_CH ? i - lo + 1 : QL_CH;
+          double buf[QL_CH];
+#pragma unroll
+          for (int c = 0; c < QL_CH; ++c)
+            if (c < cnt) buf[c] = zr[i - c];
+#pragma unroll
+          for (int c = 0; c < QL_CH; ++c)
+            if (c < cnt) {
+              const int ii = i - c;
+              const double a = buf[c];
+              buf[c] = rs[ii] * a + rc[ii] * carry;
+              carry = rc[ii] * a - rs[ii] * carry;
+            }
+#pragma unroll
+          for (int c = 0; c < QL_CH; ++c)
+            if (c < cnt) zr[i - c + 1] = buf[c];
         }
+        zr[lo] = carry;
       }
       __syncthreads();
     }
