@@ -8,9 +8,9 @@
 // with p, q the other two legs and E_p, E_q the incoming environments
 // (rows: bra bond, columns: ket bond).  One workgroup per pair:
 //   1. the ket tensor is staged in LDS as rows K_y = ket[y, :, :] (Dp x Dq);
-//   2. every wave takes rows y and replaces K_y in place by
-//      V_y = E_p K_y E_q^T (two small matrix-core products through a per-wave
-//      LDS tile);
+//   2. K_y is replaced in place by V_y = E_p K_y E_q^T for every y, as two
+//      wide matrix-core products (E_p times all rows of the ket, then the
+//      stacked result times E_q^T) split into 16-wide blocks over the waves;
 //   3. E_o = Bra V^T with Bra = bra viewed as Do x (Dp Dq): the Dp Dq
 //      contraction is split over the four waves, partial 32 x 32 blocks are
 //      summed through LDS and written.
@@ -28,13 +28,15 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // Shared first phase: the tensor X (legs 0, 1, 2 of dims dm0..dm2 in memory
 // order, no physical leg) is staged in LDS as rows K_y = X[y over leg lo, :, :]
-// (Dp x Dq, row stride PQS), E_p and E_q zero-padded to 32 x 32, and every wave
-// replaces its rows y = wid, wid + 4, ... by V_y = E_p K_y E_q^T (two MFMA
-// products through the wave's LDS tile).  Ends with a workgroup barrier.
+// (Dp x Dq, row stride PQS), E_p and E_q zero-padded to 32 x 32, and the rows
+// are replaced by V_y = E_p K_y E_q^T (two MFMA products over all y at once,
+// 16-wide blocks dealt to the waves).  Ends with a workgroup barrier; sT is
+// not used here.
 __device__ __forceinline__ void ie_stage_v(const float* __restrict__ ket, const float* __restrict__ Ep,
                                            const float* __restrict__ Eq, float* sV, float* sEp, float* sEq,
                                            float* sT, int dm0, int dm1, int dm2, int lo, int lp, int lq, int Do,
                                            int Dp, int Dq, int PQS) {
+  (void)sT;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int r = lane & 15, gq = lane >> 4;
   const int D1 = dm1, D2 = dm2, D1D2 = D1 * D2;
@@ -79,66 +81,84 @@ __device__ __forceinline__ void ie_stage_v(const float* __restrict__ ket, const 
   }
   __syncthreads();
 
-  // ---- per row y (wave-owned): V_y = E_p K_y E_q^T, in place
-  float* T = sT + wid * 32 * IE_LD;
+  // ---- V_y = E_p K_y E_q^T for every y as two wide products over 16-wide
+  // blocks (only the E dimension of each product is padded to 16 or 32):
+  //   A: T[x_p][(y, y_q)] = sum_{y_p} E_p[x_p][y_p] K[y_p][(y, y_q)], one column
+  //      block (16 columns (y, y_q)) per job, written over its own K columns;
+  //   B: V[(y, x_p)][x_q] = sum_{y_q} T[(y, x_p)][y_q] E_q[x_q][y_q], one row
+  //      block (16 rows (y, x_p)) per job, written over its own T rows.
+  // A job's reads all precede its writes (one wave, in order), and jobs touch
+  // disjoint columns (rows), so both run in place; a barrier separates them.
   const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
   const int sp_steps = (Dp + 3) >> 2, sq_steps = (Dq + 3) >> 2;
-  for (int y = wid; y < Do; y += 4) {
-    float* Ky = sV + y * PQS;
-    // T[x_p][y_q] = sum_{y_p} E_p[x_p][y_p] K_y[y_p][y_q]
-    floatx4 acc[2][2] = {{zero, zero}, {zero, zero}};
+  const int mta = (Dp + 15) >> 4, ntb = (Dq + 15) >> 4;
+  const int ncol = Do * Dq, nrow = Do * Dp;
+  {
+    float ea[8][2];  // E_p fragments of this lane (zero-padded), shared by every job
 #pragma unroll
-    for (int s = 0; s < sp_steps; ++s) {
-      const int k = 4 * s + gq;
-      float a[2], b[2];
+    for (int s = 0; s < 8; ++s)
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        a[i] = sEp[(16 * i + r) * IE_LD + k];  // zero past Dp (padded)
-        const int col = 16 * i + r;
-        b[i] = (k < Dp && col < Dq) ? Ky[k * Dq + col] : 0.f;
+      for (int mi = 0; mi < 2; ++mi) ea[s][mi] = s < sp_steps ? sEp[(16 * mi + r) * IE_LD + 4 * s + gq] : 0.f;
+    for (int cb = wid; cb * 16 < ncol; cb += 4) {
+      const int c = 16 * cb + r;
+      const bool cv = c < ncol;
+      const int y = cv ? c / Dq : 0, yq = cv ? c - y * Dq : 0;
+      float* col = sV + y * PQS + yq;  // element y_p of column c at col[y_p * Dq]
+      floatx4 acc[2] = {zero, zero};
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        if (s >= sp_steps) break;
+        const int k = 4 * s + gq;
+        const float b = (cv && k < Dp) ? col[k * Dq] : 0.f;
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+          if (mi < mta) acc[mi] = __builtin_amdgcn_mfma_f32_16x16x4f32(ea[s][mi], b, acc[mi], 0, 0, 0);
       }
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
-    }
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) T[(16 * mi + 4 * gq + i) * IE_LD + 16 * ni + r] = acc[mi][ni][i];
-    __builtin_amdgcn_wave_barrier();
-    // V[x_p][x_q] = sum_{y_q} T[x_p][y_q] E_q[x_q][y_q]
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = zero;
-#pragma unroll
-    for (int s = 0; s < sq_steps; ++s) {
-      const int k = 4 * s + gq;
-      float a[2], b[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        a[i] = k < Dq ? T[(16 * i + r) * IE_LD + k] : 0.f;
-        b[i] = sEq[(16 * i + r) * IE_LD + k];  // E_q^T[k][x_q]; zero past Dq (padded)
-      }
-#pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
-    }
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int xp = 16 * mi + 4 * gq + i, xq = 16 * ni + r;
-          if (xp < Dp && xq < Dq) Ky[xp * Dq + xq] = acc[mi][ni][i];
+          const int xp = 16 * mi + 4 * gq + i;
+          if (mi < mta && cv && xp < Dp) col[xp * Dq] = acc[mi][i];
         }
-    __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  {
+    float eb[8][2];  // E_q^T fragments: E_q^T[k][x_q] = E_q[x_q][k] (zero-padded)
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) eb[s][ni] = s < sq_steps ? sEq[(16 * ni + r) * IE_LD + 4 * s + gq] : 0.f;
+    for (int rb = wid; rb * 16 < nrow; rb += 4) {
+      const int R = 16 * rb + r;
+      const bool rv = R < nrow;
+      const int y = rv ? R / Dp : 0, xp = rv ? R - y * Dp : 0;
+      const float* row = sV + y * PQS + xp * Dq;
+      floatx4 acc[2] = {zero, zero};
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        if (s >= sq_steps) break;
+        const int k = 4 * s + gq;
+        const float a = (rv && k < Dq) ? row[k] : 0.f;
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+          if (ni < ntb) acc[ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, eb[s][ni], acc[ni], 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int R2 = 16 * rb + 4 * gq + i;
+        if (R2 < nrow) {
+          const int y2 = R2 / Dp, xp2 = R2 - y2 * Dp;
+          float* orow = sV + y2 * PQS + xp2 * Dq;
+#pragma unroll
+          for (int ni = 0; ni < 2; ++ni) {
+            const int xq = 16 * ni + r;
+            if (ni < ntb && xq < Dq) orow[xq] = acc[ni][i];
+          }
+        }
+      }
+    }
   }
   __syncthreads();
 
