@@ -12,15 +12,17 @@
 #include <cmath>
 
 #include "internal.h"
+#include "wave.h"
 
 namespace ttn {
 
 #define MR_NT 1024  // threads per state (16 wave64s)
 
-// workgroup sum: wave reductions, then the 16 wave partials (red: >= 16 doubles)
+// workgroup sum: wave reductions (DPP, wave-uniform), then the 16 wave
+// partials (red: >= 16 doubles); every thread of the workgroup takes part
 __device__ __forceinline__ double wg_sum(double v, double* red) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  v = wave_sum_dpp(v);
   if (lane == 0) red[w] = v;
   __syncthreads();
   double r = 0;
