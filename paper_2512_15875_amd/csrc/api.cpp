@@ -959,11 +959,62 @@ ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, 
       return TTN_OK;
     }
   }
+  if (!(flags & TTN_HEFF_NO_SHIFT) && shift && n_in != n_loc)
+    return fail(ctx, TTN_E_SHAPE, "a shift needs equal bra and ket bonds");
+  {
+    // operator product at a node with one virtual leg and a physical leg,
+    // FP64 or FP32 arithmetic on its own storage: the fused kernel
+    const int c = t->nb[u][0];
+    bool fuse = op && kap == 1 && t->phys[u] > 1 && (ct == 0 || ct == 1);
+    const char* fe = getenv("TTN_FUSED_LEAF");
+    if (fe && fe[0] == '0') fuse = false;
+    LeafHeffArgs la;
+    if (fuse) {
+      la.Db = envs->eb(c, u);
+      la.M = envs->em(c, u);
+      la.Da = envs->ea(c, u);
+      la.d = t->phys[u];
+      fuse = la.M == op->bond(u, c) &&
+             leaf_heff_lds_bytes(la.Db, la.M, la.Da, la.d, ct == 0 ? 8 : 4) <= LEAF_HEFF_LDS_MAX;
+    }
+    if (fuse) {
+      la.X = X;
+      la.x_stride = n_in;
+      la.x_ids = x_ids;
+      la.x_rows = x_ids ? x_rows : k;
+      la.E = envs->slot[ttn_envs::dslot(t, c, u)];
+      la.e_stride = envs->slot_elems(c, u);
+      la.pair_ids = pair_ids;
+      la.n_slots = pair_ids ? envs->n_slots : k;
+      la.W = op->W[u];
+      la.Y = Y;
+      la.y_stride = n_loc;
+      la.y_ids = y_ids;
+      la.y_rows = y_ids ? y_rows : k;
+      la.shift = (flags & TTN_HEFF_NO_SHIFT) ? nullptr : shift;
+      la.alpha = alpha;
+      la.accum = (flags & TTN_HEFF_ACCUM) ? 1 : 0;
+      la.n = k;
+      la.flag = ctx->d_flag;
+      const double Db = la.Db, Mw = la.M, Da = la.Da, d = la.d;
+      const double per = 2.0 * (Db * Mw * Da * d + Db * d * Mw * d);
+      ctx->flops_done += per * k;
+      const size_t es = ct == 0 ? 8 : 4;
+      // compulsory bytes: X row, Y row and one environment per item, W once
+      const double bytes = (double)es * (k * (Da * d + Db * d + Db * Mw * Da) + Mw * d * d);
+      std::ostringstream key;
+      key << "heff:" << u << ":1:leaf";
+      const std::string ks = key.str();
+      ttn_prof_rec* pr = prof_begin(ctx, ks.c_str(), "leaf_heff_kernel", per * k, bytes, k);
+      hipError_t he = launch_leaf_heff(ct, la, ctx->stream);
+      prof_end(ctx, pr);
+      if (he != hipSuccess) return fail(ctx, TTN_E_LAUNCH, std::string("fused leaf H_eff: ") + hipGetErrorString(he));
+      return TTN_OK;
+    }
+  }
   Net net;
   std::string why;
   if (!build_heff_net(t, op, envs, u, net, why)) return fail(ctx, TTN_E_SHAPE, why);
-  if (!(flags & TTN_HEFF_NO_SHIFT) && shift && n_in != n_loc)
-    return fail(ctx, TTN_E_SHAPE, "a shift needs equal bra and ket bonds");
   ttn_status code = TTN_OK;
   Plan* P = get_plan(ctx, net, ct, k, code);
   if (!P) return code;

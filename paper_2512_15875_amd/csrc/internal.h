@@ -113,6 +113,33 @@ size_t ienv3_lds_bytes(int Do, int Dp, int Dq);
 hipError_t launch_ienv3(const IEnv3Args& a, hipStream_t s);
 hipError_t launch_iheff3(const IHeff3Args& a, hipStream_t s);
 
+// fused H_eff product at a node with one virtual leg and a physical leg (leaf.hip)
+struct LeafHeffArgs {
+  const void* X = nullptr;     // [x_rows][Da][d]
+  int64_t x_stride = 0;
+  const int32_t* x_ids = nullptr;
+  int x_rows = 0;
+  const void* E = nullptr;     // environment slots [n_slots][Db][M][Da]
+  int64_t e_stride = 0;
+  const int32_t* pair_ids = nullptr;
+  int n_slots = 0;
+  const void* W = nullptr;     // [M][d][d] (operator bond, output, input)
+  void* Y = nullptr;           // [y_rows][Db][d]
+  int64_t y_stride = 0;
+  const int32_t* y_ids = nullptr;
+  int y_rows = 0;
+  const double* shift = nullptr;  // per item (needs Db == Da), null = none
+  const double* alpha = nullptr;  // per item, null = 1
+  int accum = 0;
+  int Db = 0, M = 0, Da = 0, d = 0;
+  int n = 0;
+  int* flag = nullptr;
+};
+#define LEAF_HEFF_LDS_MAX (64 * 1024)
+size_t leaf_heff_lds_bytes(int Db, int M, int Da, int d, int esize);
+// ctype 0: FP64 storage and arithmetic; 1: FP32
+hipError_t launch_leaf_heff(int ctype, const LeafHeffArgs& a, hipStream_t s);
+
 // diag(H_eff): out[z][b_N, p] = sum_w Wd[w, p] prod_i Ed_i[z][b_i, w_i] - shift[z]
 struct DiagDesc {
   int kappa = 0;

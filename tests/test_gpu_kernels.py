@@ -139,6 +139,50 @@ def test_identity_heff_rows_fp32(api, ctx, dims, dt, fused, monkeypatch):
         assert rel_err(Y[j], ref) < TOL[dt], (dims, dt, fused, j)
 
 
+# (d, Db, M, Da, k): binary-tree leaf, fork chain tail, ragged, bra != ket bonds
+LEAF_CASES = [(8, 8, 3, 8, 7), (14, 14, 5, 14, 4), (6, 5, 4, 5, 3), (9, 12, 7, 10, 5)]
+
+
+@pytest.mark.parametrize("case", LEAF_CASES)
+@pytest.mark.parametrize("dt", [0, 1])
+@pytest.mark.parametrize("fused", [True, False])
+def test_leaf_heff_fused_and_staged(api, ctx, case, dt, fused, monkeypatch):
+    """Operator H_eff products at a node with one virtual leg and a physical
+    leg (tree leaves, MPS ends): the fused kernel and the staged path (switched
+    by TTN_FUSED_LEAF, checked in the profile) against the oracle, with
+    environment-slot and X-row tables, per-item scale, shift (square bonds)
+    and accumulation into Y."""
+    monkeypatch.setenv("TTN_FUSED_LEAF", "1" if fused else "0")
+    d, Db, M, Da, k = case
+    n_slots = k + 2
+    tree, W, X, E = node_case(1, d, [Db], [M], [Da], k, 70 + d, op=True, n_slots=n_slots)
+    _, _, _, _, gt, gW, envs, tdt = _setup(api, ctx, 1, d, [Db], [M], [Da], n_slots, 70 + d, dt)
+    for c in tree.neighbours(1):
+        envs.get(c, 1).copy_(to_dev(E[c], tdt))
+    gW.W[1].copy_(to_dev(W, tdt))
+    pair = np.array([(2 * j + 1) % n_slots for j in range(k)], dtype=np.int32)
+    xid = np.array([k - 1 - j for j in range(k)], dtype=np.int32)
+    base = np.random.default_rng(71).normal(size=(k, Db, d))
+    gY = to_dev(base, tdt)
+    square = Db == Da
+    shift = np.linspace(-2.0, 3.0, k)
+    alpha = np.linspace(0.5, 1.5, k)
+    flags = api.HEFF_ACCUM | (0 if square else api.HEFF_NO_SHIFT)
+    api.profile(ctx, True)
+    api.heff_apply_block(ctx, gt, gW, envs, 1, k, to_dev(X, tdt), gY, pair_ids=torch.from_numpy(pair).cuda(),
+                         x_ids=torch.from_numpy(xid).cuda(), shift=to_dev(shift) if square else None,
+                         alpha=to_dev(alpha), flags=flags, compute=dt)
+    ctx.sync()
+    kernels = {r[2] for r in api.profile_report(ctx)}
+    api.profile(ctx, False)
+    assert ("leaf_heff_kernel" in kernels) == fused, kernels
+    Y = gY.double().cpu().numpy()
+    for j in range(k):
+        ein = {c: E[c][pair[j]] for c in tree.neighbours(1)}
+        ref = base[j] + alpha[j] * ottn.heff_apply(tree, 1, W, X[xid[j]], ein, shift[j] if square else 0.0)
+        assert rel_err(Y[j], ref) < TOL[dt], (case, dt, fused, j)
+
+
 @pytest.mark.parametrize("case", CASES[:6])
 def test_heff_pair_and_row_indirection(api, ctx, case):
     kappa, d, Db, M, Da, k = case
