@@ -132,6 +132,43 @@ def test_qr_move_matches_oracle(api, ctx, dt, D):
             assert np.linalg.norm(got[j] - ref) <= tol * max(1.0, np.linalg.norm(ref)), (u, j)
 
 
+@pytest.mark.parametrize("shape", ["mps_d1", "mps_full", "binary_d3"])
+@pytest.mark.parametrize("dt", [0, 1])
+def test_qr_move_edge_shapes(api, ctx, shape, dt):
+    """Gauge moves along a whole Euler tour on edge shapes: bond 1 (one
+    column, no reflector update), exact bonds where node matrices are square
+    (m = n), and a ragged binary tree with bond 3, against the oracle's QR; the
+    absorption of R into the next node runs in place."""
+    from oracle import ttn as ottn2
+    if shape == "binary_d3":
+        tree = wl.binary_tree([2, 3, 2, 5, 3])
+        D = 3
+    else:
+        tree = wl.mps_tree([2, 5, 3, 7, 2], 2)
+        D = 1 if shape == "mps_d1" else 64
+    bonds = wl.bond_dims(tree, D)
+    k = 3
+    blk_np = wl.random_block(tree, bonds, k, 46)
+    blk_np = [ottn2.canonicalize(tree, st, tree.root) for st in blk_np]
+    gt = api.Tree(tree.parent, tree.phys)
+    tdt = torch.float64 if dt == 0 else torch.float32
+    blk = api.Block(ctx, gt, k, [max(1, b) for b in bonds], dt)
+    for u in range(tree.n):
+        blk.t[u].copy_(to_dev(np.stack([blk_np[j][u] for j in range(k)]), tdt))
+    tour = ottn2.euler_tour(tree)
+    for a, b in zip(tour[:-1], tour[1:]):
+        api.block_move_centre(ctx, blk, a, b)
+        for j in range(k):
+            ottn2.move_centre(tree, blk_np[j], a, b)
+    ctx.sync()
+    tol = 1e-11 if dt == 0 else 2e-4
+    for u in range(tree.n):
+        got = blk.t[u].double().cpu().numpy()
+        for j in range(k):
+            ref = blk_np[j][u]
+            assert np.linalg.norm(got[j] - ref) <= tol * max(1.0, np.linalg.norm(ref)), (shape, u, j)
+
+
 @pytest.mark.parametrize("kind", ["cond1e3", "cond1e10", "rank_deficient"])
 @pytest.mark.parametrize("dt", [0, 1])
 def test_qr_move_conditioning(api, ctx, dt, kind):
