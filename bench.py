@@ -343,26 +343,6 @@ def tts_experiment(args):
         log(f"  plain fp64 iteration {it + 1}: {plain[-1][0]:.1f} s")
     del s
     ref = plain[-1][1]
-    # mixed
-    ms = MixedEigensolver(ctx, tree, model, D=D, k=k, low=args.precision, ttno=ttno)
-    ms.load_block(x0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    cur = ms.lo
-    cur.lobpcg_start(LobpcgOpts(n_iter=args.ref_iters))
-    mixed, prev, switched = [], None, None
-    for it in range(args.ref_iters):
-        cur.lobpcg_step()
-        lam = np.sort(cur.lam_d.cpu().numpy() + cur.zpe)
-        mixed.append((time.perf_counter() - t0, lam, "lo" if cur is ms.lo else "fp64"))
-        log(f"  mixed iteration {it + 1} ({mixed[-1][2]}): {mixed[-1][0]:.1f} s, max err {np.max(np.abs(lam - ref)):.4f}")
-        if np.max(np.abs(lam - ref)) <= 1e-3 and cur is ms.hi:
-            break
-        if cur is ms.lo and prev is not None and np.max(np.abs(lam - prev)) < args.switch_tol:
-            ms.promote()
-            cur = ms.hi
-            switched = it + 1
-        prev = lam
 
     def first_hit(traj):
         for i, t in enumerate(traj):
@@ -371,15 +351,40 @@ def tts_experiment(args):
         return None, None
 
     pi, pt = first_hit(plain)
-    mi, mt = first_hit(mixed)
     out = {"experiment": "time to all states", "workload": f"{wl_name}, D={D}, k={k}", "tol_cm-1": 1e-3,
            "reference": f"plain FP64 LOBPCG iterate {args.ref_iters}",
            "plain_fp64": {"iters": pi, "seconds": pt, "s_per_iter": round(plain[-1][0] / len(plain), 3),
-                          "max_err_per_iter": [round(float(np.max(np.abs(t[1] - ref))), 5) for t in plain]},
-           "mixed": {"low": args.precision, "switch_at_iter": switched, "iters": mi, "seconds": mt,
-                     "max_err_per_iter": [round(float(np.max(np.abs(t[1] - ref))), 5) for t in mixed]}}
-    if pt and mt:
-        out["speedup"] = round(pt / mt, 3)
+                          "max_err_per_iter": [round(float(np.max(np.abs(t[1] - ref))), 5) for t in plain]}}
+    # mixed, once per arithmetic of the FP64 phase's preconditioner sweeps
+    for pre in args.tts_pre.split(","):
+        hi_pre = {"f64": None, "f64_f32": api.F64_F32}[pre]
+        ms = MixedEigensolver(ctx, tree, model, D=D, k=k, low=args.precision, ttno=ttno, hi_pre_compute=hi_pre)
+        ms.load_block(x0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cur = ms.lo
+        cur.lobpcg_start(LobpcgOpts(n_iter=args.ref_iters))
+        mixed, prev, switched = [], None, None
+        for it in range(args.ref_iters):
+            cur.lobpcg_step()
+            lam = np.sort(cur.lam_d.cpu().numpy() + cur.zpe)
+            mixed.append((time.perf_counter() - t0, lam, "lo" if cur is ms.lo else "fp64"))
+            log(f"  mixed ({pre} preconditioner) iteration {it + 1} ({mixed[-1][2]}): {mixed[-1][0]:.1f} s, "
+                f"max err {np.max(np.abs(lam - ref)):.4f}")
+            if np.max(np.abs(lam - ref)) <= 1e-3 and cur is ms.hi:
+                break
+            if cur is ms.lo and prev is not None and np.max(np.abs(lam - prev)) < args.switch_tol:
+                ms.promote()
+                cur = ms.hi
+                switched = it + 1
+            prev = lam
+        del ms
+        mi, mt = first_hit(mixed)
+        key = "mixed" if pre == "f64" else f"mixed_pre_{pre}"
+        out[key] = {"low": args.precision, "fp64_phase_preconditioner": pre, "switch_at_iter": switched, "iters": mi,
+                    "seconds": mt, "max_err_per_iter": [round(float(np.max(np.abs(t[1] - ref))), 5) for t in mixed]}
+        if pt and mt:
+            out["speedup" if pre == "f64" else f"speedup_pre_{pre}"] = round(pt / mt, 3)
     print(json.dumps(out), flush=True)
 
 
@@ -560,6 +565,9 @@ def main():
                          "deterministic, so that profiles of the same command agree)")
     ap.add_argument("--graphs", action="store_true", help="replay the sweeps as HIP graphs (own stream)")
     ap.add_argument("--switch-tol", type=float, default=0.05)
+    ap.add_argument("--tts-pre", default="f64",
+                    help="arithmetic of the mixed form's FP64-phase preconditioner sweeps: f64, f64_f32 "
+                         "(FP32 matrix cores on the FP64 tensors), or both comma-separated")
     ap.add_argument("--gemm-hash", action="store_true", help="print the GEMM source hash and exit")
     args = ap.parse_args()
     if args.graphs and args.warmup < 2:

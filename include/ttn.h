@@ -241,7 +241,9 @@ typedef struct ttn_sweep ttn_sweep;
  * The library allocates the environment storage, the RHS scratch and the
  * MINRES vectors at creation.  The target block must be in canonical form
  * with its orthogonality centre at `centre`; ttn_sweep_init computes every
- * environment toward the centre. */
+ * environment toward the centre.  compute: TTN_F64 or TTN_F64_F32 for an FP64
+ * target (the latter contracts on FP32 matrix cores; storage, environments and
+ * the local vectors stay FP64), TTN_F32 or TTN_BF16 for an FP32 target. */
 /* term_target / term_source are HOST int32 arrays (copied); term_coef are
  * DEVICE double arrays read at every FIT step (so coefficients may change
  * between sweeps, e.g. the Rayleigh-Ritz vectors of an LOBPCG iteration). */

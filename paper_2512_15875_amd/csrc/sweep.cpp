@@ -257,7 +257,9 @@ ttn_status ttn_sweep_create(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
   if (!ctx || !t || !target || !out || n_src < 0 || n_src > 2 || (n_src > 0 && (!src_block || !n_terms)))
     return api_fail(ctx, TTN_E_ARG, "bad sweep arguments");
   if (target->t != t) return api_fail(ctx, TTN_E_ARG, "tree mismatch");
-  const bool f64 = compute == TTN_F64;
+  // FP64 storage with FP64 or FP32 matrix-core arithmetic; FP32 storage with
+  // FP32 or BF16 arithmetic
+  const bool f64 = compute == TTN_F64 || compute == TTN_F64_F32;
   if ((f64 && target->dt != TTN_F64) || (!f64 && target->dt != TTN_F32))
     return api_fail(ctx, TTN_E_DTYPE, "target dtype does not match the compute dtype");
   ttn_sweep* sw = new (std::nothrow) ttn_sweep();

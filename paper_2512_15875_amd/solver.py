@@ -84,7 +84,7 @@ class TTNEigensolver:
 
     def __init__(self, ctx: ttn.Context, tree, model, D: int, k: int, precision: str = "fp64",
                  workspace_pairs: int = 4096, graphs: bool = False, ttno=None,
-                 env_budget_bytes: Optional[int] = None):
+                 env_budget_bytes: Optional[int] = None, pre_compute: Optional[int] = None):
         import workloads as wl
         self.ctx, self.k = ctx, k
         self.graphs = graphs  # replay the sweeps as HIP graphs (needs a non-null context stream)
@@ -131,8 +131,10 @@ class TTNEigensolver:
                                 [(self.op, self.B, idx, idx, ones), (None, self.B, idx, idx, self.neglam_d)],
                                 compute=self.compute)
         self.shift_d = torch.zeros(k, dtype=torch.float64, device=dev)
+        # the preconditioner's ALS only shapes the search directions: it may run
+        # on FP32 matrix cores over the FP64 tensors (pre_compute=F64_F32)
         self.sw_pre = ttn.Sweep(ctx, self.gt, self.op, self.Wp, [(None, self.R, idx, idx, None)], shift=self.shift_d,
-                                compute=self.compute)
+                                compute=self.compute if pre_compute is None else pre_compute)
         # recombination fits: x_j = sum_l V[l, j] B_l ; p_j = sum_{l >= k} V[l, j] B_l
         m3 = 3 * k
         self.cx_t = [j for j in range(k) for l in range(m3)]
@@ -449,12 +451,12 @@ class MixedEigensolver:
     eigenvectors close, the FP64 phase recovers full accuracy."""
 
     def __init__(self, ctx: ttn.Context, tree, model, D: int, k: int, low: str = "fp32", ttno=None,
-                 env_budget_bytes: Optional[int] = None):
+                 env_budget_bytes: Optional[int] = None, hi_pre_compute: Optional[int] = None):
         if ttno is None:
             ttno = build_ttno(ttn.Tree(tree.parent, tree.phys), tree, model)
         self.lo = TTNEigensolver(ctx, tree, model, D, k, precision=low, ttno=ttno, env_budget_bytes=env_budget_bytes)
         self.hi = TTNEigensolver(ctx, tree, model, D, k, precision="fp64", ttno=ttno,
-                                 env_budget_bytes=env_budget_bytes)
+                                 env_budget_bytes=env_budget_bytes, pre_compute=hi_pre_compute)
         self.k = k
         self.history: List[dict] = []
 
