@@ -447,6 +447,45 @@ def ii_experiment(args):
     print(json.dumps(out), flush=True)
 
 
+def ienv_probe(args):
+    """The fused identity overlap environment alone, for counter passes: a
+    three-leg node with 24-dimensional bonds and no physical leg (the c2
+    internal nodes), 150 random FP32 states, 20 000 random (bra, ket) pairs,
+    one environment update toward each leg, timed and printed per leg."""
+    import torch
+    import workloads as wl
+    from paper_2512_15875_amd import ttn as api
+
+    ctx = api.Context(0, workspace_bytes=2 << 30)
+    n, reps, ks, Dn = args.probe_pairs, args.probe_reps, 150, 24
+    tree = wl.Tree("star3", [-1, 0, 1, 1], [2, 1, 2, 2], [0, 1, 2, 3])  # node 1: parent 0, children 2, 3
+    gt = api.Tree(tree.parent, tree.phys)
+    nb = tree.neighbours(1)
+    bb = [1] * tree.n
+    for c in nb:
+        bb[1 if c == 0 else c] = Dn
+    bra = api.Block(ctx, gt, ks, bb, api.F32)
+    g = torch.Generator(device="cpu")
+    g.manual_seed(0)
+    bra.t[1].copy_(torch.randn(bra.t[1].shape, generator=g))
+    envs = api.Envs(ctx, gt, n, bb, None, bb, api.F32)
+    for c in nb:
+        envs.get(c, 1).copy_(torch.randn(envs.get(c, 1).shape, generator=g))
+    pb = torch.randint(0, ks, (n,), generator=g, dtype=torch.int32).cuda()
+    pk = torch.randint(0, ks, (n,), generator=g, dtype=torch.int32).cuda()
+    for v in nb:
+        api.ttno_env_update(ctx, gt, None, bra, bra, pb, pk, 1, v, envs, api.F32)
+    ctx.sync()
+    for v in nb:
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            api.ttno_env_update(ctx, gt, None, bra, bra, pb, pk, 1, v, envs, api.F32)
+        ctx.sync()
+        dt = (time.perf_counter() - t0) / reps
+        print(f"toward {v}: {dt * 1e3:.3f} ms for {n} pairs = {dt / n * 1e9:.1f} ns/pair, "
+              f"{2 * Dn ** 4 * 3 * n / dt / 1e12:.1f} TFLOP/s", flush=True)
+
+
 def gram_probe(args):
     """The Gram step of one LOBPCG iteration alone (environment updates and
     closures over all pairs of the 3k basis) at the bench workload, bracketed
@@ -532,6 +571,10 @@ def main():
     ap.add_argument("--no-tts", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run the copy kernel used to scale counters")
     ap.add_argument("--gram-probe", action="store_true", help="only the Gram step, for counter passes")
+    ap.add_argument("--ienv-probe", action="store_true",
+                    help="only the fused identity overlap environment at a 24x24x24 node, for counter passes")
+    ap.add_argument("--probe-pairs", type=int, default=20000)
+    ap.add_argument("--probe-reps", type=int, default=5)
     ap.add_argument("--ii", action="store_true", help="run the inverse-iteration experiment instead")
     ap.add_argument("--ii-lo", type=int, default=10)
     ap.add_argument("--ii-hi", type=int, default=4)
@@ -584,6 +627,9 @@ def main():
         return
     if args.gram_probe:
         gram_probe(args)
+        return
+    if args.ienv_probe:
+        ienv_probe(args)
         return
     if args.ii:
         ii_experiment(args)
