@@ -593,7 +593,8 @@ def main():
     ap.add_argument("--learned-params", default="",
                     help="saved network parameters (.npy) to test instead of harvesting and training")
     ap.add_argument("--ref-iters", type=int, default=24)
-    ap.add_argument("--out-dir", default=os.path.join(ROOT, "gpurun_out"))
+    ap.add_argument("--out-dir", default=os.path.join(ROOT, "out"),
+                    help="where experiments write their side files (learned parameters, per-iteration data)")
     ap.add_argument("--ensemble", action="store_true", help="run the many-Hamiltonian ensemble experiment instead")
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--ens-dmin", type=int, default=12)
@@ -619,8 +620,8 @@ def main():
         print(gemm_source_hash())
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (DESIGN.md describes how the "
-              "hot path would shard)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path, so --gpus must be 1",
+              file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
