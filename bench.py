@@ -570,6 +570,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tts", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run the copy kernel used to scale counters")
+    ap.add_argument("--workspace-gb", type=float, default=8.0,
+                    help="library workspace of the bench step (stage intermediates; bounds the items per launch)")
     ap.add_argument("--gram-probe", action="store_true", help="only the Gram step, for counter passes")
     ap.add_argument("--ienv-probe", action="store_true",
                     help="only the fused identity overlap environment at a 24x24x24 node, for counter passes")
@@ -668,7 +670,7 @@ def run_bench(args, api, k, D, stream):
     import torch
     from paper_2512_15875_amd.solver import LobpcgOpts
 
-    ctx = api.Context(0, workspace_bytes=8 << 30, stream=stream)
+    ctx = api.Context(0, workspace_bytes=int(args.workspace_gb * (1 << 30)), stream=stream)
     api.autotune(ctx, args.autotune)
     s, model, tree = make_solver(api, ctx, args.workload, args.precision, k, D)
     s.graphs = args.graphs
