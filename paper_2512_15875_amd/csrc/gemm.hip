@@ -147,7 +147,11 @@ __global__ __launch_bounds__(256, (CT == 1) ? 3 : 2) void ogemm_kernel(KArgs g) 
 
   // ---- k-offset tables staged in LDS once (K <= KCAP), so the per-tile
   // address of an element costs an LDS read instead of a dependent global load
-  __shared__ int sk_a[KCAP], sk_b[KCAP];
+  // (dynamic LDS of 2 K ints, sized by the launch: a short-K stage keeps its
+  // occupancy instead of reserving the table cap)
+  extern __shared__ int sk_dyn[];
+  int* sk_a = sk_dyn;
+  int* sk_b = sk_dyn + K;
   const bool k_in_lds = K <= KCAP;
   if (k_in_lds) {
     for (int i = tid; i < K; i += 256) {
@@ -731,16 +735,17 @@ static hipError_t launch_cfg(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s
   static const int remap_min = env_int("TTN_XCD_REMAP_MIN", 256);
   a.xcd_remap = nz >= remap_min ? 1 : 0;
   dim3 grid = a.xcd_remap ? dim3((unsigned)(((nz + 7) / 8) * 8 * a.tiles), 1) : dim3(tm * tn, nz);
+  const size_t kt = gd.K <= KCAP ? (size_t)2 * gd.K * sizeof(int) : 0;  // k-offset tables in LDS
   if (gd.c_mfast) {
-    if (gd.a_mfast && gd.b_nfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, true, true, true>), grid, dim3(256), 0, s, a);
-    else if (gd.a_mfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, true, false, true>), grid, dim3(256), 0, s, a);
-    else if (gd.b_nfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, false, true, true>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, false, false, true>), grid, dim3(256), 0, s, a);
+    if (gd.a_mfast && gd.b_nfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, true, true, true>), grid, dim3(256), kt, s, a);
+    else if (gd.a_mfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, true, false, true>), grid, dim3(256), kt, s, a);
+    else if (gd.b_nfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, false, true, true>), grid, dim3(256), kt, s, a);
+    else hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, false, false, true>), grid, dim3(256), kt, s, a);
   } else {
-    if (gd.a_mfast && gd.b_nfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, true, true, false>), grid, dim3(256), 0, s, a);
-    else if (gd.a_mfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, true, false, false>), grid, dim3(256), 0, s, a);
-    else if (gd.b_nfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, false, true, false>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, false, false, false>), grid, dim3(256), 0, s, a);
+    if (gd.a_mfast && gd.b_nfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, true, true, false>), grid, dim3(256), kt, s, a);
+    else if (gd.a_mfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, true, false, false>), grid, dim3(256), kt, s, a);
+    else if (gd.b_nfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, false, true, false>), grid, dim3(256), kt, s, a);
+    else hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, false, false, false>), grid, dim3(256), kt, s, a);
   }
   return hipGetLastError();
 }
