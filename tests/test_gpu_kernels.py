@@ -275,6 +275,30 @@ def test_env_update_matches_oracle(api, ctx, case, dt):
             assert rel_err(got[p], ref) < TOL[dt], (case, dt, v, p)
 
 
+@pytest.mark.parametrize("dt", [0, 1])
+def test_env_update_long_contraction(api, ctx, dt):
+    """Operator environments at a node with three 40-dimensional bonds, where
+    a stage contracts two bonds at once (K = 1600, beyond the 1536 entries up
+    to which the GEMM stages its k-offset tables in LDS): the global-table
+    main loop, checked in the profile, against the oracle."""
+    kappa, d, Db, M, Da = 3, 1, [40, 40, 40], [3, 4, 2], [40, 40, 40]
+    tree, gt, bra, ket, A_b, A_k, W, gW, envs, E, pairs, pb, pk, tdt = _env_setup(
+        api, ctx, kappa, d, Db, M, Da, 2, 2, 207, dt)
+    nb = tree.neighbours(1)
+    api.profile(ctx, True)
+    for v in nb:
+        api.ttno_env_update(ctx, gt, gW, bra, ket, pb, pk, 1, v, envs, dt)
+        ctx.sync()
+        got = envs.get(1, v).double().cpu().numpy()
+        for p, (i, j) in enumerate(pairs):
+            ein = {c: E[c][p] for c in nb if c != v}
+            ref = ottn.env_update(tree, 1, v, A_b[i], W, A_k[j], ein)
+            assert rel_err(got[p], ref) < TOL[dt], (dt, v, p)
+    ks = [r[8] for r in api.profile_report(ctx)]
+    api.profile(ctx, False)
+    assert max(ks) > 1536, ks
+
+
 @pytest.mark.parametrize("case", CASES[:5])
 def test_env_update_identity_and_closure(api, ctx, case):
     kappa, d, Db, M, Da, _ = case
