@@ -132,17 +132,22 @@ def test_qr_move_matches_oracle(api, ctx, dt, D):
             assert np.linalg.norm(got[j] - ref) <= tol * max(1.0, np.linalg.norm(ref)), (u, j)
 
 
-@pytest.mark.parametrize("shape", ["mps_d1", "mps_full", "binary_d3"])
+@pytest.mark.parametrize("shape", ["mps_d1", "mps_full", "binary_d3", "chain_tall"])
 @pytest.mark.parametrize("dt", [0, 1])
 def test_qr_move_edge_shapes(api, ctx, shape, dt):
     """Gauge moves along a whole Euler tour on edge shapes: bond 1 (one
     column, no reflector update), exact bonds where node matrices are square
-    (m = n), and a ragged binary tree with bond 3, against the oracle's QR; the
-    absorption of R into the next node runs in place."""
+    (m = n), a ragged binary tree with bond 3, and a 1200 x 2 node matrix (more
+    rows than the unrolled LDS instances cover: the runtime-bounded one),
+    against the oracle's QR; the absorption of R into the next node runs in
+    place."""
     from oracle import ttn as ottn2
     if shape == "binary_d3":
         tree = wl.binary_tree([2, 3, 2, 5, 3])
         D = 3
+    elif shape == "chain_tall":
+        tree = wl.Tree("chain3", [-1, 0, 1], [2, 40, 30], [0, 1, 2])
+        D = 64
     else:
         tree = wl.mps_tree([2, 5, 3, 7, 2], 2)
         D = 1 if shape == "mps_d1" else 64
