@@ -6,7 +6,7 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
   LOBPCG subspace (Alg. lobpcg_block, Eq. for the coefficients alpha, beta,
   gamma) and of the inverse-iteration clusters (Alg. block_inverse_iteration).
 * ``minres`` -- the local symmetric (possibly indefinite) solver used inside
-  ALS (Sec. II.C.4), after Paige and Saunders: Lanczos tridiagonalisation with
+  ALS (Sec. II.C.3), after Paige and Saunders: Lanczos tridiagonalisation with
   the least-squares problem solved by Givens rotations.
 * ``lanczos_lowest`` -- Lanczos with full reorthogonalisation, for exact
   references on small spaces.

@@ -6,11 +6,11 @@ All states live on one tree with the bond dimensions of the block; states are
 lists of node tensors (legs [parent, children..., p]).  Every routine follows
 the paper's algorithm in its order, with the readings listed in the design doc:
 
-* ``als_solve``   -- ALS for (H - s I) y = phi (Sec. II.C.4): node-by-node
+* ``als_solve``   -- ALS for (H - s I) y = phi (Sec. II.C.3): node-by-node
   local solves with MINRES on (H_eff - s) y_u = b_u, b_u from the (y, phi)
   identity environments; one sweep = one depth-first Euler tour from the root,
   solving each node at its first visit; QR moves the centre along the tour.
-* ``fit``         -- variational fitting of sum_i c_i O_i phi_i (Sec. II.C.3):
+* ``fit``         -- variational fitting of sum_i c_i O_i phi_i (Sec. II.C.2):
   with the target's centre at u, the local solution is
   sum_i c_i (O_i)_eff phi_{i,u} (identity-gauge form of the local system).
 * ``lobpcg``      -- Alg. lobpcg_block with the three-term recurrence.
@@ -57,7 +57,7 @@ class SolveStats:
 
 def als_solve(tree, W, shift: float, phi, y0, sweeps: int, maxiter: int, rtol: float,
               stats: Optional[SolveStats] = None, local="minres"):
-    """Approximate y with (H - shift) y = phi (Sec. II.C.4, Fig. als).
+    """Approximate y with (H - shift) y = phi (Sec. II.C.3, Fig. als).
 
     local: the local map -- "minres" (the paper's), "diag" (y = b / (diag(H_eff)
     - s)), or ("learned", params) for the learned map of ``oracle.mlp``;
@@ -126,7 +126,7 @@ def start_correction(apply_A, r0: np.ndarray, d: np.ndarray, params=None) -> np.
 
 def fit(tree, sources: Sequence[Tuple[float, Optional[list], list]], init, sweeps: int = 2):
     """Variational fitting of sum_i c_i O_i phi_i (O_i a TTNO or None for the
-    identity) into a state with init's bond dimensions (Sec. II.C.3)."""
+    identity) into a state with init's bond dimensions (Sec. II.C.2)."""
     root = tree.root
     y = ttn.canonicalize(tree, init, root)
     caches = [EnvCache(tree, y, Wi, phi, root) for (_, Wi, phi) in sources]
@@ -236,8 +236,11 @@ class IIOptions:
     gap: float = 5.0
     drop_tol: float = 1e-12
     dlam_tol: Optional[float] = None  # stop when every |d lambda| < tol
-    monotone: bool = True             # keep a cluster's previous states when its update raised a Rayleigh quotient
-    mono_tol: float = 1e-7            # cm^-1
+    # Optional safeguard, NOT part of Alg. block_inverse_iteration (off by
+    # default): keep a cluster's previous states when its update raised a
+    # Rayleigh quotient by more than mono_tol (cm^-1).
+    monotone: bool = False
+    mono_tol: float = 1e-7
 
 
 def inverse_iteration(tree, W, xs, lam, opts: IIOptions, history: Optional[list] = None):
@@ -245,10 +248,17 @@ def inverse_iteration(tree, W, xs, lam, opts: IIOptions, history: Optional[list]
     from the input Rayleigh quotients, shift = cluster mean, followed by one
     global Rayleigh-Ritz over all states.  Returns (states, Ritz values).
 
-    With opts.monotone (a safeguard, not in the paper): at a fixed bond
-    dimension the ALS solve of a nearly singular shifted system can move a
-    state away from its eigenvector, so a cluster whose update raised any
-    Rayleigh quotient by more than mono_tol keeps its previous states."""
+    Per outer iteration and cluster: s = mean Rayleigh quotient of the
+    cluster; each state is replaced by its normalised ALS solution of
+    (H - s) y = x_j; a cluster of more than one state is then orthogonalised
+    by its own Rayleigh-Ritz problem (x_j <- sum_k V[k, j] x_k, fitted), and
+    the Rayleigh quotients are recomputed.
+
+    opts.monotone (off by default; a safeguard that is not in the paper): at
+    a fixed bond dimension the ALS solve of a nearly singular shifted system
+    can move a state away from its eigenvector; with the option on, a cluster
+    whose update raised any Rayleigh quotient by more than mono_tol keeps its
+    previous states."""
     xs = [normalized(tree, x) for x in xs]
     lam = np.array(lam, dtype=np.float64)
     cl = clusters_of(lam, opts.gap)

@@ -15,7 +15,7 @@ symmetric, so all conjugations are identities).
                                prod_{c in N(u)\\v} E^{ij}_{c->u}[b_c, w_c, a_c]
   with the bra bond b, operator bond w and ket bond a on the edge (u, v).
   op=None means the identity operator (W = delta_pq, every w of dimension 1).
-* H_eff at node u (Sec. II.C.3-4): with the orthogonality centre of the bra
+* H_eff at node u (Sec. II.C.2-3): with the orthogonality centre of the bra
   and ket at u,
       Y[b_N, p] = sum W[w_N, p, q] X[a_N, q] prod_{c in N(u)} E_{c->u}[b_c, w_c, a_c]
                   - s X[b_N, p].

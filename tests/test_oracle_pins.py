@@ -434,3 +434,86 @@ def test_lobpcg_c1_reaches_closed_form():
     lam = np.sort(lam)
     assert np.max(np.abs(lam - ex)) < 1e-3
     assert np.all(lam >= ex - 1e-9)  # variational (Galerkin) bound
+
+
+def _near_degenerate_model():
+    """Three modes whose two fundamentals lie 2.5 cm^-1 apart and are mixed by
+    a bilinear coupling (2 x 2 block [[1000, 1], [1, 1002.5]] in the
+    {|100>, |010>} pair: levels 2.5 +- 3.2 cm^-1 apart after mixing), plus
+    couplings to the third mode and a cubic term."""
+    omega = np.array([1000.0, 1002.5, 1500.0])
+    monos = [((0, 1), (1, 1)), ((1, 1), (2, 1)), ((0, 1), (2, 1)), ((0, 2), (2, 1))]
+    coefs = np.array([2.0, 15.0, -9.0, 4.0])
+    return wl.SOPModel("near_degenerate", omega, [4, 4, 4], monos, coefs, 0)
+
+
+def _dense_block_inverse_iteration(H, X, lam, clusters):
+    """One outer iteration of Alg. block_inverse_iteration on dense vectors:
+    per cluster, s = mean Rayleigh quotient, x_j <- (H - s)^{-1} x_j
+    normalised, then (clusters of more than one state) the cluster's
+    generalized eigenproblem and x_j <- sum_k V[k, j] x_k, normalised."""
+    X = [x.copy() for x in X]
+    n = len(H)
+    for c in clusters:
+        s = sum(float(lam[j]) for j in c) / len(c)
+        for j in c:
+            y = np.linalg.solve(H - s * np.eye(n), X[j])
+            X[j] = y / np.linalg.norm(y)
+        if len(c) > 1:
+            B = np.stack([X[j] for j in c], axis=1)
+            _, V = scipy.linalg.eigh(B.T @ H @ B, B.T @ B)
+            newx = [B @ V[:, jj] for jj in range(len(c))]
+            for jj, j in enumerate(c):
+                X[j] = newx[jj] / np.linalg.norm(newx[jj])
+    return X, np.array([x @ H @ x for x in X])
+
+
+def test_inverse_iteration_full_bond_near_degenerate_pair():
+    """Full bond dimension, so one ALS sweep solves the shifted system exactly
+    and the fits are exact: every outer iteration of the oracle must equal the
+    same iteration done on dense vectors (brute force, 64 dimensions),
+    including the in-cluster Rayleigh-Ritz of the near-degenerate pair, and
+    the final Ritz values must reach the dense eigenvalues.  Two outer
+    iterations: a third would shift a converged singleton by its own
+    eigenvalue to ~1e-10, where (H - s) is numerically singular and MINRES
+    cannot meet its tolerance (a degenerate case of the algorithm itself)."""
+    m = _near_degenerate_model()
+    tree = wl.mps_tree(m.dims, 1)
+    W = ttno.build_ttno(tree, m)
+    bonds = wl.bond_dims(tree, 100)
+    k = 4
+    x0 = wl.initial_block(tree, bonds, m.omega, m.dims, k, 33)
+    xs = [solvers.normalized(tree, x) for x in x0]
+    lam0 = solvers.rayleigh_quotients(tree, W, xs)
+    cl = solvers.clusters_of(lam0, 5.0)
+    assert sorted(len(c) for c in cl) == [1, 1, 2]  # the pair shares one shift
+    assert solvers.IIOptions().monotone is False     # Alg. block_inverse_iteration as printed by default
+    hist = []
+    _, theta = solvers.inverse_iteration(tree, W, xs, lam0, solvers.IIOptions(n_iter=2), hist)
+    H = exact.sop_dense_matrix(m)
+    X = [ttn.to_dense(tree, x) for x in xs]
+    lam = lam0.copy()
+    for it in range(2):
+        X, lam = _dense_block_inverse_iteration(H, X, lam, cl)
+        np.testing.assert_allclose(hist[it]["lam"], lam, rtol=0, atol=1e-7)
+    ev = np.linalg.eigvalsh(H)[:k]
+    np.testing.assert_allclose(theta, ev, rtol=0, atol=1e-8)
+    assert np.all(theta >= ev - 1e-9)
+
+
+@pytest.mark.slow
+def test_lobpcg_then_inverse_iteration_c1_reaches_closed_form():
+    """c1: three LOBPCG iterations, then two outer iterations of block inverse
+    iteration and the final global Rayleigh-Ritz: every level within 1e-3
+    cm^-1 of the normal-mode closed form and variationally above it."""
+    m = wl.make_config_model("c1")
+    tree = wl.mps_tree(m.dims, 2)
+    W = ttno.build_ttno(tree, m)
+    bonds = wl.bond_dims(tree, 8)
+    x0 = wl.initial_block(tree, bonds, m.omega, m.dims, 10, m.seed + 17)
+    lam0 = solvers.rayleigh_quotients(tree, W, [solvers.normalized(tree, x) for x in x0])
+    xs, lam = solvers.lobpcg(tree, W, x0, solvers.LobpcgOptions(n_iter=3, shift=float(np.min(lam0)) - 837.0))
+    _, theta = solvers.inverse_iteration(tree, W, xs, lam, solvers.IIOptions(n_iter=2))
+    ex = exact.normal_mode_levels(m, 10)
+    assert np.max(np.abs(theta - ex)) < 1e-3
+    assert np.all(theta >= ex - 1e-7)
