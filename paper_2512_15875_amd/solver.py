@@ -49,8 +49,10 @@ class IIOpts:
     gap: float = 5.0
     drop_tol: float = 1e-12
     dlam_tol: Optional[float] = None
-    monotone: bool = True   # a cluster whose update raised a Rayleigh quotient keeps its previous states
-    mono_tol: float = 1e-7  # cm^-1
+    # optional safeguard, not part of Alg. block_inverse_iteration (off by default): a cluster whose
+    # update raised a Rayleigh quotient by more than mono_tol (cm^-1) keeps its previous states
+    monotone: bool = False
+    mono_tol: float = 1e-7
     refine: int = 0         # > 0: local solves by FP64 refinement around FP32-arithmetic MINRES (FP64 solver)
 
 
@@ -151,6 +153,7 @@ class TTNEigensolver:
         self.ip_gather = torch.tensor([l * k + j for j, l in zip(self.cp_t, self.cp_s)], device=dev)
         self.history: List[dict] = []
         self._sw_ii = None
+        self.cluster_rr_calls = 0  # in-cluster Rayleigh-Ritz steps of inverse iteration (clusters of > 1 state)
 
     # ------------------------------------------------------------ block plumbing
 
@@ -384,6 +387,7 @@ class TTNEigensolver:
 
     def _cluster_rr(self, big, opts: IIOpts):
         ctx, k, root = self.ctx, self.k, self.root
+        self.cluster_rr_calls += 1
         ld = max(len(c) for c in big)
         ia, ib, la, lb = [], [], [], []
         for ci, c in enumerate(big):

@@ -100,14 +100,20 @@ def lib():
     return _lib
 
 
+# ttn_status codes (include/ttn.h)
+OK, E_ARG, E_SHAPE, E_DTYPE, E_DEVICE, E_WORKSPACE, E_LAUNCH, E_NOT_PD, E_NONFINITE, E_NOCONV = range(10)
+
+
 class TTNError(RuntimeError):
-    pass
+    def __init__(self, msg: str, status: int = -1):
+        super().__init__(msg)
+        self.status = status
 
 
 def _check(status, ctx=None):
     if status != 0:
         msg = lib().ttn_last_error(ctx.h if ctx is not None else None)
-        raise TTNError(f"ttn status {status}: {msg.decode() if msg else ''}")
+        raise TTNError(f"ttn status {status}: {msg.decode() if msg else ''}", int(status))
 
 
 def _i32(seq) -> C.Array:

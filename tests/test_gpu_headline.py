@@ -1,0 +1,171 @@
+"""Parity at the node shapes the benchmark times, and error reporting.
+
+* heff_apply_block (U1) at the two headline nodes -- the level-1 node of the
+  64-mode binary tree (three 24-dimensional bonds, operator bonds 63 / 42 /
+  36, k = 50) and backbone node b2 of the fork-4 comb (three 40-dimensional
+  bonds, operator bonds 18 / 32 / 17, k = 84) -- in FP32 and BF16, sampled
+  states element by element against the oracle's K2.
+* ttno_env_update (U2) on the level-1 -> root edge of the binary tree with
+  1056 (bra, ket) pairs in FP32: the 128 x 128 tile, the XCD-aware item
+  mapping (>= 256 items per launch) and workspace chunking all run (checked
+  in the stage profile); sampled pairs against the oracle's K1.
+* Sweeps replayed as HIP graphs against the oracle's ALS and fitting.
+* A non-finite tensor surfaces as TTN_E_NONFINITE at ttn_ctx_sync.
+
+Gates (norm-wise relative): FP32 1e-5, BF16 operands with FP32 accumulation
+3e-2.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import solvers as osol
+from oracle import ttn as ottn
+from oracle import ttno as ottno
+from tests.gpu_util import env_setup, heff_setup, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+GATE = {1: 1e-5, 2: 3e-2}
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2512_15875_amd import ttn
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ttn.lib()
+    return ttn
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    return api.Context(0, workspace_bytes=2 << 30)
+
+
+# (name, kappa, d, bonds, operator bonds, k)
+HEADLINE_U1 = [
+    ("binary64_level1", 3, 1, [24, 24, 24], [63, 42, 36], 50),
+    ("fork4_b2", 3, 1, [40, 40, 40], [18, 32, 17], 84),
+]
+
+
+@pytest.mark.parametrize("case", HEADLINE_U1, ids=[c[0] for c in HEADLINE_U1])
+@pytest.mark.parametrize("dt", [1, 2])
+def test_heff_apply_headline_node(api, ctx, case, dt):
+    name, kappa, d, Db, M, k = case
+    tree, W, X, E, gt, gW, envs, tdt = heff_setup(api, ctx, kappa, d, Db, M, Db, k, 71, dt)
+    shift = np.linspace(-2.0, 3.0, k)
+    gX = to_dev(X, tdt)
+    gY = torch.zeros((k,) + tuple(Db) + (d,), dtype=tdt, device="cuda")
+    api.heff_apply_block(ctx, gt, gW, envs, 1, k, gX, gY, shift=to_dev(shift), flags=api.HEFF_APPLY, compute=dt)
+    ctx.sync()
+    errs = []
+    for j in (0, k // 2, k - 1):
+        ein = {c: E[c][j] for c in tree.neighbours(1)}
+        ref = ottn.heff_apply(tree, 1, W, X[j], ein, shift[j])
+        got = gY[j].double().cpu().numpy()
+        errs.append(rel_err(got, ref))
+    print(f"{name} compute={dt}: relative errors of sampled states {errs}")
+    assert max(errs) < GATE[dt], (name, dt, errs)
+
+
+def test_env_update_gram_edge_binary64_level1(api, ctx):
+    """Operator environments level-1 node -> root for 32 x 33 pairs (FP32)."""
+    kappa, d, Db, M = 3, 1, [24, 24, 24], [63, 42, 36]
+    kb, kk = 32, 33
+    tree, gt, bra, ket, A_b, A_k, W, gW, envs, E, pairs, pb, pk, tdt = env_setup(
+        api, ctx, kappa, d, Db, M, Db, kb, kk, 72, api.F32)
+    nb = tree.neighbours(1)
+    v = 0  # the parent (root)
+    api.profile(ctx, True)
+    api.ttno_env_update(ctx, gt, gW, bra, ket, pb, pk, 1, v, envs, api.F32)
+    ctx.sync()
+    recs = api.profile_report(ctx)
+    api.profile(ctx, False)
+    got = envs.get(1, v)
+    errs = []
+    for p in (0, 517, len(pairs) - 1):
+        i, j = pairs[p]
+        ein = {c: E[c][p] for c in nb if c != v}
+        ref = ottn.env_update(tree, 1, v, A_b[i], W, A_k[j], ein)
+        errs.append(rel_err(got[p].double().cpu().numpy(), ref))
+    print(f"U2 level-1 -> root, {len(pairs)} pairs: relative errors {errs}")
+    assert max(errs) < GATE[1], errs
+    kernels = {r[2] for r in recs}
+    assert any(kn.startswith("ogemm_kernel<1, 128, 128") for kn in kernels), kernels
+    batched = [r for r in recs if r[9] > 1]
+    assert any(r[9] >= 256 for r in batched), [r[9] for r in batched]          # XCD-aware mapping
+    assert any(r[3] > 1 for r in batched), [(r[2], r[3], r[9]) for r in batched]  # chunked: several launches
+
+
+def _fork_problem(api, ctx, k=3, D=6, seed=5):
+    m = wl.quartic_force_field(8, 21, 20, 30)
+    tree = wl.fork_tree(m.dims, 4, 1)
+    W = ottno.build_ttno(tree, m)
+    M = ottno.ttno_bonds(tree, W)
+    bonds = wl.bond_dims(tree, D)
+    gt = api.Tree(tree.parent, tree.phys)
+    op = api.TTNO(ctx, gt, [to_dev(w) for w in W], [max(1, x) for x in M], api.F64)
+    phi = wl.random_block(tree, bonds, k, seed)
+    y0 = [ottn.canonicalize(tree, p, tree.root) for p in phi]
+
+    def block(states):
+        b = api.Block(ctx, gt, k, [max(1, x) for x in bonds], api.F64)
+        for u in range(tree.n):
+            b.t[u].copy_(to_dev(np.stack([states[j][u] for j in range(k)])))
+        return b
+    return tree, gt, W, op, phi, y0, block
+
+
+@pytest.mark.parametrize("mode", ["als_minres", "fit"])
+def test_graph_replayed_sweeps_match_oracle(api, mode):
+    """Two sweeps captured once and replayed as a HIP graph (eager work and
+    synchronisations between replays); every replay against the oracle."""
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = api.Context(0, workspace_bytes=1 << 28, stream=stream)
+        k = 3
+        tree, gt, W, op, phi, y0, block = _fork_problem(api, ctx, k)
+        Y, P = block(y0), block(phi)
+        idx = list(range(k))
+        if mode == "fit":
+            coefs = [0.5, -1.0, 2.0]
+            sw = api.Sweep(ctx, gt, None, Y, [(op, P, idx, idx, to_dev(np.array(coefs)))], compute=api.F64)
+            m, kw = api.SOLVE_FIT, {}
+            refs = [osol.fit(tree, [(coefs[j], W, phi[j])], y0[j], sweeps=2) for j in range(k)]
+        else:
+            shifts = [-300.0, -100.0, -700.0]
+            sw = api.Sweep(ctx, gt, op, Y, [(None, P, idx, idx, None)], shift=to_dev(np.array(shifts)),
+                           compute=api.F64)
+            m, kw = api.SOLVE_MINRES, {"maxiter": 6}
+            refs = [osol.als_solve(tree, W, shifts[j], phi[j], y0[j], sweeps=2, maxiter=6, rtol=0.0)
+                    for j in range(k)]
+        start = [Y.t[u].clone() for u in range(tree.n)]
+        for rep in range(4):  # eager, capture + launch, replay, replay
+            for u in range(tree.n):
+                Y.t[u].copy_(start[u])
+            sw.run(m, 2, init=True, graph=True, **kw)
+            ctx.sync()
+            for j in range(k):
+                for u in range(tree.n):
+                    assert rel_err(Y.t[u][j].cpu().numpy(), refs[j][u]) < 1e-8, (rep, j, u)
+            x = torch.randn(1 << 16, device="cuda", dtype=torch.float64)
+            (x * 2).sum().item()
+        ctx.sync()
+
+
+def test_nonfinite_value_raises_at_sync(api, ctx):
+    """A NaN in a state tensor flows through the QR gauge move, whose output
+    check raises the device flag; ttn_ctx_sync reports TTN_E_NONFINITE once
+    and clears it."""
+    tree, gt, W, op, phi, y0, block = _fork_problem(api, ctx, 2)
+    B = block(phi)
+    ctx.sync()
+    u = tree.children(tree.root)[0] if tree.children(tree.root) else 0
+    B.t[u][0].view(-1)[3] = float("nan")
+    api.block_move_centre(ctx, B, u, tree.parent[u])
+    with pytest.raises(api.TTNError) as ei:
+        ctx.sync()
+    assert ei.value.status == api.E_NONFINITE, ei.value
+    ctx.sync()  # the flag was cleared

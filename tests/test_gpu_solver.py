@@ -88,3 +88,35 @@ def test_two_hamiltonians_on_one_context(api, ctx):
             ref = ottn.expectation(tree, x, W, x) / ottn.expectation(tree, x, None, x)
             # both sides work in the zero-point-shifted frame
             assert abs(lam[j] - ref) < 1e-8 * max(1.0, abs(ref)), (seed, j)
+
+
+GOLD_C3 = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c3s7_cluster_oracle_runs.json")))
+
+
+def test_inverse_iteration_with_clusters_fork4(api, ctx):
+    """Fork-4 comb (quartic force field, seed 7, D=8, k=12): three LOBPCG
+    iterations, then two outer iterations of block inverse iteration in which
+    two clusters hold two states each (the in-cluster Rayleigh-Ritz and the
+    fitted recombination of Alg. block_inverse_iteration run), then the final
+    global Rayleigh-Ritz -- every recorded value against the oracle run."""
+    from paper_2512_15875_amd.solver import IIOpts, LobpcgOpts, TTNEigensolver
+    g = GOLD_C3
+    m = wl.make_config_model("c3", seed=g["seed"])
+    tree = wl.fork_tree(m.dims, 4, 1)
+    bonds = wl.bond_dims(tree, g["D"])
+    x0 = wl.initial_block(tree, bonds, m.omega, m.dims, g["k"], m.seed + 17)
+    s = TTNEigensolver(ctx, tree, m, D=g["D"], k=g["k"], precision="fp64")
+    s.load_block(x0)
+    zpe = g["zpe"]
+    lam3 = s.lobpcg(LobpcgOpts(n_iter=3, shift=g["shift"]))
+    for it in range(3):
+        assert np.max(np.abs(s.history[it]["lam"] - (np.array(g["lam_history"][it]) + zpe))) < 1e-4, it
+    assert np.max(np.abs(lam3 - (np.array(g["lobpcg3_lam"]) + zpe))) < 1e-4
+    theta = s.inverse_iteration(IIOpts(n_iter=2))
+    assert s.cluster_rr_calls == 2
+    assert [sorted(c) for c in s._clusters] == [sorted(c) for c in g["clusters"]]
+    for it in range(2):
+        got = s.history[3 + it]["lam"]
+        ref = np.array(g["ii2_lam_history"][it]) + zpe
+        assert np.max(np.abs(got - ref)) < 1e-4, (it, np.max(np.abs(got - ref)))
+    assert np.max(np.abs(theta - (np.array(g["ii2_final_rr"]) + zpe))) < 1e-4
