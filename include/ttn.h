@@ -7,7 +7,7 @@
  * (TTNO, Eq. ttno) and applied to a block of k tree tensor network states
  * (TTNS, Eq. ttns) inside block LOBPCG (Alg. lobpcg_block) and block inverse
  * iteration (Alg. block_inverse_iteration), whose local problems are the
- * variational-fitting and ALS systems of Sec. II.C.3-4 (Fig. variational,
+ * variational-fitting and ALS systems of Sec. II.C.2-3 (Fig. variational,
  * Fig. als).
  *
  * Conventions shared by every call
@@ -29,15 +29,24 @@
  * Ownership: the caller owns every tensor buffer (device memory) and every
  *   host array it passes; the library keeps pointers to device buffers given
  *   at *_create time and copies host arrays.  The library owns its handles,
- *   contraction plans and the workspace sized at ttn_ctx_create.
+ *   contraction plans, the workspace sized at ttn_ctx_create and a 64 MiB
+ *   offset-table pool allocated there.  Device (and pinned host) memory is
+ *   allocated only by ttn_ctx_create and ttn_sweep_create; ttn_alloc_count
+ *   counts those allocations.  Every other call -- the hot-path calls, sweep
+ *   steps and sweep runs included -- allocates nothing: a contraction planned
+ *   for the first time carves its offset tables from the pool and enqueues
+ *   their upload without waiting (the host copy stays with the context), so
+ *   the calls can be captured into a HIP graph.
  * Streams: every call enqueues on the context's HIP stream and returns
  *   without synchronising unless stated.
  * Errors: every call returns ttn_status; arguments are validated on the host
  *   before any launch and out-parameters are written only on success; the
  *   message of the last failure is returned by ttn_last_error.  No exception
- *   or abort crosses this boundary.  A call that plans a contraction for the
- *   first time for a given node and shape allocates its offset tables once;
- *   ttn_ctx_prepare_* calls do that ahead of time.
+ *   or abort crosses this boundary.  Host waits: ttn_ctx_sync,
+ *   ttn_ctx_set_stream (drains the old stream), ttn_ctx_profile_report, the
+ *   autotuner's timed launches, the *_create / *_destroy calls of sweeps and
+ *   contexts, and an eager MINRES sweep step, which may wait on an event it
+ *   recorded four convergence checks earlier (never under stream capture).
  */
 #ifndef TTN_H
 #define TTN_H
@@ -88,8 +97,13 @@ ttn_status ttn_ctx_set_stream(ttn_ctx* ctx, void* hip_stream);
 ttn_status ttn_ctx_sync(ttn_ctx* ctx);
 ttn_status ttn_ctx_destroy(ttn_ctx* ctx);
 const char* ttn_last_error(const ttn_ctx* ctx);
-/* Library version string and the number of exported entry points. */
+/* Library version string. */
 const char* ttn_version(void);
+/* Number of device and pinned-host allocations the library has made in this
+ * process (ttn_ctx_create: workspace, table pool, flags; ttn_sweep_create:
+ * environments, vectors, convergence ring).  A caller checks that a sequence
+ * of calls allocates nothing by reading it before and after. */
+ttn_status ttn_alloc_count(int64_t* out);
 
 /* Tree (Eq. ttns / Appendix B topologies).  Host arrays are copied. */
 ttn_status ttn_tree_create(int32_t n_nodes, const int32_t* parent, const int32_t* phys, ttn_tree** out);
@@ -122,7 +136,7 @@ ttn_status ttn_envs_destroy(ttn_envs* e);
 
 /* ------------------------------------------------------------ the hot path */
 
-/* Environment update (Sec. II.C.3-4; the shaded blocks of Fig. variational
+/* Environment update (Sec. II.C.2-3; the shaded blocks of Fig. variational
  * and Fig. als), for every pair p < n_pairs:
  *   E^p_{u->v}[b,w,a] = sum A^{bra[p]}_u[b_N,p] W_u[w_N,p,q] A^{ket[p]}_u[a_N,q]
  *                       prod_{c in N(u)\v} E^p_{c->u}[b_c,w_c,a_c]
@@ -150,7 +164,7 @@ ttn_status ttno_env_close(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, c
 #define TTN_HEFF_DIAG 2u      /* Y = diag(H_eff) - shift (X unused)            */
 #define TTN_HEFF_ACCUM 4u     /* add into Y instead of overwriting it          */
 
-/* Local effective-Hamiltonian product for k states at node u (Sec. II.C.3-4):
+/* Local effective-Hamiltonian product for k states at node u (Sec. II.C.2-3):
  *   Y_j[b_N,p] = alpha_j * ( sum W_u[w_N,p,q] X_{x(j)}[a_N,q]
  *                prod_{c in N(u)} E^{pair(j)}_{c->u}[b_c,w_c,a_c] - s_j X_{x(j)}[b_N,p] )
  * op NULL = identity operator (the fitting / ALS right-hand side when the
@@ -232,8 +246,8 @@ typedef struct {
 typedef struct ttn_sweep ttn_sweep;
 
 /* A sweep over a target block y (k states) solving, node by node,
- *   MINRES / DIAG:  (H - s_j) y_j = phi_j           (ALS, Sec. II.C.4)
- *   FIT:            y_t = sum_terms c * O phi_s     (fitting, Sec. II.C.3)
+ *   MINRES / DIAG:  (H - s_j) y_j = phi_j           (ALS, Sec. II.C.3)
+ *   FIT:            y_t = sum_terms c * O phi_s     (fitting, Sec. II.C.2)
  * Source terms: up to 2 (op_i, block_i, n_i terms (target t, source s,
  * coefficient c)); for MINRES/DIAG exactly one identity-operator term with
  * n = k and targets 0..k-1.  `shift` device double[k] (MINRES/DIAG).
@@ -291,6 +305,23 @@ ttn_status ttn_scatter_sym(ttn_ctx* ctx, int32_t n, const int32_t* idx_a, const 
 /* y = alpha * x for device double vectors of length n. */
 ttn_status ttn_vec_scale(ttn_ctx* ctx, int32_t n, const double* x, double alpha, double* y);
 
+/* y = sqrt(x) elementwise for device double vectors of length n (the residual
+ * norms of Alg. lobpcg_block from their squares). */
+ttn_status ttn_vec_sqrt(ttn_ctx* ctx, int32_t n, const double* x, double* y);
+
+/* dst[i] = src[idx[i]] for idx[i] >= 0, else `fill` (device arrays; idx
+ * int32[n], src double[src_n], dst double[n]): the recombination coefficients
+ * V[l, j] of Alg. lobpcg_block and Alg. block_inverse_iteration laid out in a
+ * fitting sweep's term order.  An index >= src_n writes `fill` and is
+ * reported as TTN_E_ARG by the next ttn_ctx_sync. */
+ttn_status ttn_vec_gather(ttn_ctx* ctx, int32_t n, const int32_t* idx, const double* src, int32_t src_n, double fill,
+                          double* dst);
+
+/* Rows [0, rows) of every node tensor of `src` converted into `dst` (same
+ * tree structure and bonds; FP32 <-> FP64 or a plain copy): the promotion of a
+ * low-precision block to FP64 for refinement. */
+ttn_status ttn_block_convert(ttn_ctx* ctx, const ttn_block* src, ttn_block* dst, int32_t rows);
+
 /* ------------------------------------------------------------ operator compiler (host) */
 
 /* Sum-of-products -> TTNO in FP64 on the host (Sec. II.A.3, Eq. sum_of_tp):
@@ -323,6 +354,18 @@ ttn_status ttn_sop_destroy(ttn_sop* s);
  * `buf` and then cleared only when cap >= needed (call once with buf NULL to
  * size the buffer). */
 ttn_status ttn_ctx_profile(ttn_ctx* ctx, int32_t on);
+/* Restrict the stage profile to plans whose key starts with one of the n
+ * prefixes (n = 0: every plan).  H_eff plans at node u with the operator have
+ * keys starting "heff:<u>:1", environment updates "env:<u>>". */
+ttn_status ttn_ctx_profile_filter(ttn_ctx* ctx, int32_t n, const char* const* prefixes);
+/* Call probe: every later heff_apply_block call with the operator (not DIAG)
+ * at one of the n nodes is bracketed by HIP events on the context stream --
+ * the whole call, all its stages and the gaps between them (n = 0: off).
+ * ttn_ctx_probe_report synchronises the stream and returns the number of
+ * probed calls, their algorithmic flops (the minimum-order count) and the sum
+ * of their event times in ms, then clears the records. */
+ttn_status ttn_ctx_probe_heff(ttn_ctx* ctx, int32_t n, const int32_t* nodes);
+ttn_status ttn_ctx_probe_report(ttn_ctx* ctx, int64_t* calls, double* flops, double* ms);
 /* Tile autotuner.  on = 1: the first launch of every contraction stage that
  * overwrites its output runs each tile shape (128x128, 64x64, 128x64,
  * 64x128, 32x64, 64x32, 32x32) twice, times the second run with HIP events (synchronising), and keeps the
@@ -344,9 +387,11 @@ ttn_status ttn_ctx_profile_report(ttn_ctx* ctx, char* buf, int64_t cap, int64_t*
  * the whole sequence as one HIP graph on the context stream: the first call
  * with an option set runs eagerly (building plans and tables), the second
  * captures and launches, later ones replay.  Graphs need a non-null context
- * stream and are skipped under profiling and for MINRES with maxiter > 25
- * (host-side convergence checks); the algorithmic flop counter is advanced
- * by the captured amount on each replay.  Every pointer reachable from the
+ * stream and are skipped under profiling.  A captured MINRES step records all
+ * maxiter iterations; every 25 iterations a device count of the unconverged
+ * states gates the following iterations' kernels, which return at once when
+ * it is zero.  The algorithmic flop counter is advanced by the captured
+ * amount on each replay (an upper bound for gated MINRES work).  Every pointer reachable from the
  * sweep (blocks, coefficients, shifts, opts' device arrays, iters/resid) must
  * keep its address between replays. */
 ttn_status ttn_sweep_run(ttn_ctx* ctx, ttn_sweep* sw, const ttn_solve_opts* opts, int32_t n_sweeps,

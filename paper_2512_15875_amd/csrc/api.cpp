@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -11,6 +12,54 @@
 #include "internal.h"
 
 using namespace ttn;
+
+namespace ttn {
+
+namespace {
+std::atomic<int64_t> g_allocs{0};  // device and pinned-host allocations made by the library
+constexpr size_t kPoolEntries = (size_t)16 << 20;  // 64 MiB of int32 table entries per context
+}  // namespace
+
+bool dev_malloc(void** p, size_t bytes) {
+  if (hipMalloc(p, bytes ? bytes : 16) != hipSuccess) return false;
+  g_allocs.fetch_add(1);
+  return true;
+}
+
+bool pinned_malloc(void** p, size_t bytes) {
+  if (hipHostMalloc(p, bytes ? bytes : 16, hipHostMallocDefault) != hipSuccess) return false;
+  g_allocs.fetch_add(1);
+  return true;
+}
+
+const int32_t* pool_upload(ttn_ctx* ctx, std::vector<int32_t>&& h, ttn_status& code) {
+  const size_t n = h.empty() ? 1 : h.size();
+  const size_t start = (ctx->pool_used + 63) / 64 * 64;  // 256-byte alignment
+  if (start + n > ctx->pool_cap) {
+    code = api_fail(ctx, TTN_E_WORKSPACE, "offset-table pool exhausted (64 MiB per context)");
+    return nullptr;
+  }
+  if (h.empty()) h.push_back(0);
+  ctx->pool_host.push_back(std::move(h));
+  const std::vector<int32_t>& keep = ctx->pool_host.back();
+  int32_t* d = ctx->pool + start;
+  if (hipMemcpyAsync(d, keep.data(), keep.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream) !=
+      hipSuccess) {
+    code = api_fail(ctx, TTN_E_DEVICE, "offset-table upload failed");
+    return nullptr;
+  }
+  ctx->pool_used = start + n;
+  return d;
+}
+
+bool prof_selected(const ttn_ctx* ctx, const std::string& key) {
+  if (ctx->prof_filter.empty()) return true;
+  for (const std::string& f : ctx->prof_filter)
+    if (key.compare(0, f.size(), f) == 0) return true;
+  return false;
+}
+
+}  // namespace ttn
 
 namespace {
 
@@ -190,7 +239,7 @@ ttn_status exec_plan(ttn_ctx* ctx, Plan& P, int ct, const std::vector<OpAddr>& i
         }
       }
       ttn_prof_rec* rec = nullptr;
-      if (ctx->profile && ctx->prof.size() < 200000) {
+      if (ctx->profile && ctx->prof.size() < 200000 && prof_selected(ctx, P.key)) {
         ctx->prof.emplace_back();
         rec = &ctx->prof.back();
         rec->key = P.key;
@@ -211,7 +260,7 @@ ttn_status exec_plan(ttn_ctx* ctx, Plan& P, int ct, const std::vector<OpAddr>& i
           return fail(ctx, TTN_E_DEVICE, "hipEventCreate failed");
         (void)hipEventRecord(rec->a, ctx->stream);
       }
-      hipError_t he = launch_gemm(ct, st.g, A, B, C, e, st.batched ? z0 : 0, cnt, ctx->d_flag, ctx->stream);
+      hipError_t he = launch_gemm(ct, st.g, A, B, C, e, st.batched ? z0 : 0, cnt, ctx->d_flag, ctx->stream, ctx->gate);
       if (he != hipSuccess) return fail(ctx, TTN_E_LAUNCH, std::string("gemm launch: ") + hipGetErrorString(he));
       if (rec) (void)hipEventRecord(rec->b, ctx->stream);
     }
@@ -351,11 +400,14 @@ Plan* get_plan(ttn_ctx* ctx, const Net& net, int ct, double batch, ttn_status& c
   auto it = ctx->plans.find(k.str());
   if (it != ctx->plans.end()) return it->second.get();
   Status st;
-  auto p = make_plan(net.in, net.dims, net.out_lab, net.out_str, batch, ct, st, ctx->stream);
+  auto p = make_plan(net.in, net.dims, net.out_lab, net.out_str, batch, ct, st);
   if (!p) {
     code = fail(ctx, st.code, st.msg);
     return nullptr;
   }
+  const int32_t* d_tabs = pool_upload(ctx, std::move(p->h_tabs), code);
+  if (!d_tabs) return nullptr;
+  bind_plan_tables(*p, d_tabs);
   Plan* raw = p.get();
   raw->key = k.str();
   ctx->plans[k.str()] = std::move(p);
@@ -387,14 +439,21 @@ ttn_status ttn_ctx_create(int device, void* hip_stream, size_t workspace_bytes, 
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
   c->ws_bytes = workspace_bytes ? workspace_bytes : ((size_t)1 << 30);
-  if (hipMalloc(&c->ws, c->ws_bytes) != hipSuccess) {
+  if (!dev_malloc(&c->ws, c->ws_bytes)) {
     delete c;
     return fail(nullptr, TTN_E_DEVICE, "workspace hipMalloc failed");
   }
-  if (hipMalloc(&c->d_flag, 4 * sizeof(int)) != hipSuccess ||
+  if (!dev_malloc((void**)&c->pool, kPoolEntries * sizeof(int32_t))) {
+    (void)hipFree(c->ws);
+    delete c;
+    return fail(nullptr, TTN_E_DEVICE, "table pool hipMalloc failed");
+  }
+  c->pool_cap = kPoolEntries;
+  if (!dev_malloc((void**)&c->d_flag, 4 * sizeof(int)) ||
       hipMemsetAsync(c->d_flag, 0, 4 * sizeof(int), c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
     (void)hipFree(c->ws);
+    (void)hipFree(c->pool);
     delete c;
     return fail(nullptr, TTN_E_DEVICE, "flag hipMalloc failed");
   }
@@ -404,7 +463,15 @@ ttn_status ttn_ctx_create(int device, void* hip_stream, size_t workspace_bytes, 
 
 ttn_status ttn_ctx_set_stream(ttn_ctx* ctx, void* s) {
   if (!ctx) return fail(nullptr, TTN_E_ARG, "null context");
+  // table uploads already enqueued are ordered on the old stream only
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   ctx->stream = (hipStream_t)s;
+  return TTN_OK;
+}
+
+ttn_status ttn_alloc_count(int64_t* out) {
+  if (!out) return fail(nullptr, TTN_E_ARG, "null argument");
+  *out = g_allocs.load();
   return TTN_OK;
 }
 
@@ -428,9 +495,17 @@ ttn_status ttn_ctx_sync(ttn_ctx* ctx) {
 ttn_status ttn_ctx_destroy(ttn_ctx* ctx) {
   if (!ctx) return TTN_OK;
   (void)hipStreamSynchronize(ctx->stream);
+  for (auto& c : ctx->calls) {
+    (void)hipEventDestroy(c.a);
+    (void)hipEventDestroy(c.b);
+  }
+  for (auto& r : ctx->prof) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
   ctx->plans.clear();
-  for (auto& kv : ctx->tables) (void)hipFree(kv.second);
   ctx->tables.clear();
+  if (ctx->pool) (void)hipFree(ctx->pool);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->d_flag) (void)hipFree(ctx->d_flag);
   delete ctx;
@@ -791,8 +866,22 @@ ttn_status heff_apply_block(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
                             int32_t k, const int32_t* pair_ids, const int32_t* x_ids, const double* shift,
                             const double* alpha, const void* X, int32_t x_rows, void* Y, uint32_t flags,
                             ttn_dtype compute) {
-  return ttn::heff_apply_rows(ctx, t, op, envs, node, k, pair_ids, x_ids, nullptr, k, shift, alpha, X, x_rows, Y,
-                              flags, compute);
+  const bool probe = ctx && op && !(flags & TTN_HEFF_DIAG) && k > 0 &&
+                     std::find(ctx->probe_nodes.begin(), ctx->probe_nodes.end(), node) != ctx->probe_nodes.end();
+  ttn_ctx::CallRec rec;
+  const double f0 = ctx ? ctx->flops_done : 0.0;
+  if (probe && hipEventCreate(&rec.a) == hipSuccess && hipEventCreate(&rec.b) == hipSuccess)
+    (void)hipEventRecord(rec.a, ctx->stream);
+  const ttn_status r = ttn::heff_apply_rows(ctx, t, op, envs, node, k, pair_ids, x_ids, nullptr, k, shift, alpha, X,
+                                            x_rows, Y, flags, compute);
+  if (rec.b) {
+    (void)hipEventRecord(rec.b, ctx->stream);
+    rec.flops = ctx->flops_done - f0;
+    ctx->calls.push_back(rec);
+  } else if (rec.a) {
+    (void)hipEventDestroy(rec.a);
+  }
+  return r;
 }
 
 }  // extern "C"
@@ -996,6 +1085,7 @@ ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, 
       la.accum = (flags & TTN_HEFF_ACCUM) ? 1 : 0;
       la.n = k;
       la.flag = ctx->d_flag;
+      la.gate = ctx->gate;
       const double Db = la.Db, Mw = la.M, Da = la.Da, d = la.d;
       const double per = 2.0 * (Db * Mw * Da * d + Db * d * Mw * d);
       ctx->flops_done += per * k;
@@ -1076,7 +1166,7 @@ ttn_status ttn_ctx_flops(ttn_ctx* ctx, double* total, int32_t reset) {
 
 namespace ttn {
 ttn_prof_rec* prof_begin(ttn_ctx* ctx, const char* key, const char* kernel, double flops, double bytes, int nz) {
-  if (!ctx || !ctx->profile || ctx->prof.size() >= 200000) return nullptr;
+  if (!ctx || !ctx->profile || ctx->prof.size() >= 200000 || !prof_selected(ctx, key)) return nullptr;
   ctx->prof.emplace_back();
   ttn_prof_rec* rec = &ctx->prof.back();
   rec->key = key;
@@ -1111,6 +1201,40 @@ ttn_status ttn_ctx_autotune(ttn_ctx* ctx, int32_t on, char* buf, int64_t cap, in
 ttn_status ttn_ctx_profile(ttn_ctx* ctx, int32_t on) {
   if (!ctx) return fail(nullptr, TTN_E_ARG, "null context");
   ctx->profile = on != 0;
+  return TTN_OK;
+}
+
+ttn_status ttn_ctx_profile_filter(ttn_ctx* ctx, int32_t n, const char* const* prefixes) {
+  if (!ctx || n < 0 || (n > 0 && !prefixes)) return fail(ctx, TTN_E_ARG, "bad filter");
+  ctx->prof_filter.clear();
+  for (int i = 0; i < n; ++i) {
+    if (!prefixes[i]) return fail(ctx, TTN_E_ARG, "null prefix");
+    ctx->prof_filter.emplace_back(prefixes[i]);
+  }
+  return TTN_OK;
+}
+
+ttn_status ttn_ctx_probe_heff(ttn_ctx* ctx, int32_t n, const int32_t* nodes) {
+  if (!ctx || n < 0 || (n > 0 && !nodes)) return fail(ctx, TTN_E_ARG, "bad probe nodes");
+  ctx->probe_nodes.assign(nodes, nodes + n);
+  return TTN_OK;
+}
+
+ttn_status ttn_ctx_probe_report(ttn_ctx* ctx, int64_t* calls, double* flops, double* ms) {
+  if (!ctx || !calls || !flops || !ms) return fail(ctx, TTN_E_ARG, "null argument");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  double f = 0, t = 0;
+  for (auto& c : ctx->calls) {
+    float e = 0;
+    if (hipEventElapsedTime(&e, c.a, c.b) == hipSuccess) t += e;
+    f += c.flops;
+    (void)hipEventDestroy(c.a);
+    (void)hipEventDestroy(c.b);
+  }
+  *calls = (int64_t)ctx->calls.size();
+  *flops = f;
+  *ms = t;
+  ctx->calls.clear();
   return TTN_OK;
 }
 

@@ -23,6 +23,10 @@ hipError_t launch_norms2(int ctype, const void* X, int64_t n, int nz, double* ou
 hipError_t launch_scale(int ctype, void* X, int64_t n, int nz, const double* sc, hipStream_t s);
 hipError_t launch_scatter2(int n, const int32_t* ia, const int32_t* ib, const double* vals, double* out, hipStream_t s);
 hipError_t launch_vscale(int n, const double* x, double a, double* y, hipStream_t s);
+hipError_t launch_vsqrt(const double* x, double* y, int n, hipStream_t s);
+hipError_t launch_vgather(const int32_t* idx, const double* src, int src_n, double fill, double* dst, int n, int* flag,
+                          hipStream_t s);
+hipError_t launch_convert(int sdt, const void* x, int ddt, void* y, int64_t n, hipStream_t s);
 hipError_t launch_normalize(int ctype, void* X, int64_t n, int nz, double* norms, hipStream_t s);
 
 ttn_status api_fail(ttn_ctx* ctx, ttn_status code, const std::string& msg);
@@ -57,12 +61,8 @@ const int32_t* leg_rows_table(ttn_ctx* ctx, const std::vector<int>& dims, int le
       idx[i] = 0;
     }
   }
-  int32_t* d = nullptr;
-  if (hipMalloc(&d, off.size() * sizeof(int32_t)) != hipSuccess ||
-      !upload_sync(d, off.data(), off.size() * sizeof(int32_t), ctx->stream)) {
-    code = api_fail(ctx, TTN_E_DEVICE, "row table upload failed");
-    return nullptr;
-  }
+  const int32_t* d = pool_upload(ctx, std::move(off), code);
+  if (!d) return nullptr;
   ctx->tables[k.str()] = d;
   return d;
 }
@@ -167,6 +167,37 @@ ttn_status ttn_scatter_sym(ttn_ctx* ctx, int32_t n, const int32_t* idx_a, const 
   if (!ctx || n < 0 || (n > 0 && (!idx_a || !idx_b || !vals || !out))) return api_fail(ctx, TTN_E_ARG, "bad arguments");
   hipError_t e = launch_scatter2(n, idx_a, idx_b, vals, out, ctx->stream);
   if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+  return TTN_OK;
+}
+
+ttn_status ttn_vec_sqrt(ttn_ctx* ctx, int32_t n, const double* x, double* y) {
+  if (!ctx || n < 0 || (n > 0 && (!x || !y))) return api_fail(ctx, TTN_E_ARG, "bad arguments");
+  hipError_t e = launch_vsqrt(x, y, n, ctx->stream);
+  if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+  return TTN_OK;
+}
+
+ttn_status ttn_vec_gather(ttn_ctx* ctx, int32_t n, const int32_t* idx, const double* src, int32_t src_n, double fill,
+                          double* dst) {
+  if (!ctx || n < 0 || src_n < 0 || (n > 0 && (!idx || !dst || (src_n > 0 && !src))))
+    return api_fail(ctx, TTN_E_ARG, "bad arguments");
+  hipError_t e = launch_vgather(idx, src, src_n, fill, dst, n, ctx->d_flag, ctx->stream);
+  if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+  return TTN_OK;
+}
+
+ttn_status ttn_block_convert(ttn_ctx* ctx, const ttn_block* src, ttn_block* dst, int32_t rows) {
+  if (!ctx || !src || !dst) return api_fail(ctx, TTN_E_ARG, "null argument");
+  if (src->t->parent != dst->t->parent || src->t->phys != dst->t->phys || src->D != dst->D)
+    return api_fail(ctx, TTN_E_SHAPE, "blocks differ in tree or bonds");
+  if (rows < 0 || rows > src->k || rows > dst->k) return api_fail(ctx, TTN_E_ARG, "rows outside both blocks");
+  if ((src->dt != TTN_F64 && src->dt != TTN_F32) || (dst->dt != TTN_F64 && dst->dt != TTN_F32))
+    return api_fail(ctx, TTN_E_DTYPE, "blocks must be FP64 or FP32");
+  const int sdt = src->dt == TTN_F64 ? 0 : 1, ddt = dst->dt == TTN_F64 ? 0 : 1;
+  for (int u = 0; u < src->t->n; ++u) {
+    hipError_t e = launch_convert(sdt, src->ptr[u], ddt, dst->ptr[u], (int64_t)rows * src->size[u], ctx->stream);
+    if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
+  }
   return TTN_OK;
 }
 

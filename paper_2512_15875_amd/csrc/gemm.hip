@@ -42,6 +42,7 @@ struct KArgs {
   int M, N, K, z0, accum, tiles_n, has_d, d_const;
   int tiles, nz, xcd_remap;
   int* flag;  // flag[2] is raised when a batch table holds an out-of-range index
+  const int32_t* gate;  // non-null: the launch does nothing when *gate == 0 (every thread reads the same word)
 };
 
 __device__ __forceinline__ int64_t batch_off(const KOp& o, int z, int z0, int* flag) {
@@ -93,6 +94,7 @@ struct Types<3> {  // FP64 tensors, FP32 matrix cores
 // occupancy floor: 3 waves / SIMD for FP32 tiles, 2 for FP64 and bf16 tiles
 template <int CT, int BM, int BN, int BK, bool AMF, bool BNF, bool CMF>
 __global__ __launch_bounds__(256, (CT == 1) ? 3 : 2) void ogemm_kernel(KArgs g) {
+  if (g.gate && *g.gate == 0) return;  // uniform, before any barrier
   typedef typename Types<CT>::T T;
   typedef typename Types<CT>::L L;
   typedef typename Types<CT>::Acc Acc;
@@ -398,6 +400,7 @@ __global__ __launch_bounds__(256, (CT == 1) ? 3 : 2) void ogemm_kernel(KArgs g) 
 // four waves of a workgroup take four consecutive items.
 template <int CT, int TMW, int TNW>
 __global__ __launch_bounds__(256) void ogemm_wave_kernel(KArgs g) {
+  if (g.gate && *g.gate == 0) return;  // uniform, before any barrier
   typedef typename Types<CT == 2 ? 1 : CT>::T T;
   typedef typename Types<CT == 2 ? 1 : CT>::Acc Acc;
   const int lane = threadIdx.x & 63;
@@ -497,6 +500,7 @@ __global__ __launch_bounds__(256) void ogemm_wave_kernel(KArgs g) {
 // four partial 32 x 32 accumulators are summed through LDS.  FP32 storage;
 // the arithmetic is FP32 also for the bf16 compute type.
 __global__ __launch_bounds__(256) void ogemm_splitk_kernel(KArgs g) {
+  if (g.gate && *g.gate == 0) return;  // uniform, before any barrier
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int z = blockIdx.x;
   if (z >= g.nz) return;  // uniform per workgroup, before any barrier
@@ -580,6 +584,7 @@ __global__ __launch_bounds__(256) void ogemm_splitk_kernel(KArgs g) {
 // through the output offset tables.  FP32 arithmetic.
 template <bool CMF>
 __global__ __launch_bounds__(256) void ogemm_narrow_kernel(KArgs g) {
+  if (g.gate && *g.gate == 0) return;  // uniform
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int z = blockIdx.x;
   if (z >= g.nz) return;  // no barriers below: waves may leave independently
@@ -840,7 +845,7 @@ std::string gemm_kernel_name(int ctype, const GemmDesc& gd) {
 }
 
 hipError_t launch_gemm(int ctype, const GemmDesc& gd, const OpAddr& A, const OpAddr& B, const OpAddr& C,
-                       const Epilogue& ep, int z0, int nz, int* flag, hipStream_t s) {
+                       const Epilogue& ep, int z0, int nz, int* flag, hipStream_t s, const int32_t* gate) {
   KArgs a;
   a.A = kop(A, 2);
   a.B = kop(B, 2);
@@ -848,6 +853,7 @@ hipError_t launch_gemm(int ctype, const GemmDesc& gd, const OpAddr& A, const OpA
   a.has_d = ep.D.base != nullptr;
   a.D = a.has_d ? kop(ep.D, 2) : KOp{nullptr, nullptr, 0, 0, 0};
   a.flag = flag;
+  a.gate = gate;
   a.a_om = gd.a_om;
   a.a_ok = gd.a_ok;
   a.b_ok = gd.b_ok;

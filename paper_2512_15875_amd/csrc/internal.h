@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <deque>
 #include <map>
 #include <memory>
 #include <string>
@@ -69,8 +70,9 @@ struct Epilogue {
 };
 
 // dtype: 0 f64, 1 f32 storage with f32 MFMA, 2 f32 storage with bf16 MFMA, 3 f64 storage with f32 MFMA
+// gate: null, or a device word; the kernels return at once when it reads zero
 hipError_t launch_gemm(int ctype, const GemmDesc& g, const OpAddr& A, const OpAddr& B, const OpAddr& C,
-                       const Epilogue& ep, int z0, int nz, int* flag, hipStream_t s);
+                       const Epilogue& ep, int z0, int nz, int* flag, hipStream_t s, const int32_t* gate = nullptr);
 
 std::string gemm_kernel_name(int ctype, const GemmDesc& g);
 
@@ -134,6 +136,7 @@ struct LeafHeffArgs {
   int Db = 0, M = 0, Da = 0, d = 0;
   int n = 0;
   int* flag = nullptr;
+  const int32_t* gate = nullptr;  // non-null: return at once when it reads zero
 };
 #define LEAF_HEFF_LDS_MAX (64 * 1024)
 size_t leaf_heff_lds_bytes(int Db, int M, int Da, int d, int esize);
@@ -190,16 +193,26 @@ struct Plan {
   int64_t ws_per_item = 0;         // elements of workspace per batch item
   int64_t ws_shared = 0;           // elements for shared intermediates
   double flops_per_item = 0, flops_shared = 0;
-  int32_t* d_tabs = nullptr;       // device copy of every table
-  ~Plan();
+  // every stage table, concatenated on the host (each padded to 16 entries);
+  // tab_refs say where each stage's six tables start
+  std::vector<int32_t> h_tabs;
+  struct TabRef {
+    size_t step;
+    int which;  // 0 a_om, 1 a_ok, 2 b_ok, 3 b_on, 4 c_om, 5 c_on
+    size_t off;
+  };
+  std::vector<TabRef> tab_refs;
 };
+
+// Point a plan's stage descriptors at the device copy of its tables.
+void bind_plan_tables(Plan& plan, const int32_t* d_tabs);
 
 // Build the min-flop plan for a network: inputs (with labels/strides), label
 // dims, final output labels + strides.  `batch` = number of batch items used
 // to weigh batched against shared work.
 std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<int, int>& dims,
                                 const std::vector<int>& out_lab, const std::vector<int64_t>& out_str,
-                                double batch, int ctype, Status& st, hipStream_t stream);
+                                double batch, int ctype, Status& st);
 
 // Host-to-device upload ordered on `stream` and waited for.  Used instead of
 // the legacy synchronous copy, which also waits on the null stream and so
@@ -300,11 +313,30 @@ struct ttn_prof_rec {
 
 struct ttn_ctx {
   bool profile = false;
+  // table pool: offset tables of contraction plans, QR row tables and dense
+  // GEMM tables are carved from one device allocation made at creation, so no
+  // later call allocates device memory; their host copies live as long as the
+  // context (the upload is enqueued on the stream without a wait)
+  int32_t* pool = nullptr;
+  size_t pool_cap = 0, pool_used = 0;  // in int32 entries
+  std::deque<std::vector<int32_t>> pool_host;
+  // while non-null, every contraction-stage kernel first reads this device
+  // word and returns at once when it is zero (the MINRES convergence gate)
+  const int32_t* gate = nullptr;
   bool autotune = false;  // time every tile shape on a stage's first launch and keep the fastest
   std::string tune_log;   // "plan-key|stage|M|N|K|items|chosen tile|us per tile..." lines
   double flops_done = 0;  // algorithmic contraction flops launched so far
   std::vector<ttn_prof_rec> prof;
   std::string prof_text;  // aggregated, not yet returned
+  std::vector<std::string> prof_filter;  // plan-key prefixes the stage profile records (empty: all)
+  // call probe: heff_apply_block calls with the operator at these nodes are
+  // bracketed by events (whole calls, every stage and gap in between)
+  std::vector<int> probe_nodes;
+  struct CallRec {
+    hipEvent_t a = nullptr, b = nullptr;
+    double flops = 0;
+  };
+  std::vector<CallRec> calls;
   int device = 0;
   hipStream_t stream = nullptr;
   void* ws = nullptr;
@@ -312,5 +344,18 @@ struct ttn_ctx {
   std::string err;
   int* d_flag = nullptr;  // non-finite / not-PD flags
   std::map<std::string, std::unique_ptr<ttn::Plan>> plans;
-  std::map<std::string, int32_t*> tables;  // device offset tables (QR rows etc.)
+  std::map<std::string, const int32_t*> tables;  // device offset tables (QR rows etc.), in the pool
 };
+
+namespace ttn {
+// Every device or pinned-host allocation of the library goes through these
+// and is counted (process-wide; ttn_alloc_count).
+bool dev_malloc(void** p, size_t bytes);
+bool pinned_malloc(void** p, size_t bytes);
+// Copy `h` into the context's table pool (256-byte aligned) with an
+// asynchronous upload on the context stream; the host copy is kept with the
+// context.  Returns null (and sets `code`) when the pool is exhausted.
+const int32_t* pool_upload(ttn_ctx* ctx, std::vector<int32_t>&& h, ttn_status& code);
+// whether the stage profile records plans with this key (prefix filter)
+bool prof_selected(const ttn_ctx* ctx, const std::string& key);
+}  // namespace ttn

@@ -1,4 +1,6 @@
-// Small memory-bound kernels of the hot path: diagonal gathers for diag(H_eff).
+// Small memory-bound kernels of the hot path: diagonal gathers for diag(H_eff),
+// and the vector helpers of the eigensolver drivers (square roots of squared
+// norms, coefficient gathers, dtype conversion of state blocks).
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -52,6 +54,56 @@ static hipError_t gather_t(const DiagDesc& dd, void* ws, const int64_t* ed_off, 
 hipError_t launch_diag_gather(int ctype, const DiagDesc& dd, void* ws, const int64_t* ed_off, int nz, hipStream_t s) {
   if (ctype == 0) return gather_t<double>(dd, ws, ed_off, nz, s);
   return gather_t<float>(dd, ws, ed_off, nz, s);
+}
+
+// y[i] = sqrt(x[i])
+__global__ void vsqrt_kernel(const double* x, double* y, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = sqrt(x[i]);
+}
+
+// dst[i] = idx[i] >= 0 ? src[idx[i]] : fill   (idx < src_n checked on the host side of the table's producer)
+__global__ void vgather_kernel(const int32_t* idx, const double* src, int src_n, double fill, double* dst, int n,
+                               int* flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int j = idx[i];
+  if (j >= src_n) {  // report instead of reading out of bounds
+    atomicOr(flag + 2, 1);
+    dst[i] = fill;
+    return;
+  }
+  dst[i] = j >= 0 ? src[j] : fill;
+}
+
+template <typename S, typename D>
+__global__ void convert_kernel(const S* x, D* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (D)x[i];
+}
+
+hipError_t launch_vsqrt(const double* x, double* y, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vsqrt_kernel, dim3((n + 255) / 256), dim3(256), 0, s, x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_vgather(const int32_t* idx, const double* src, int src_n, double fill, double* dst, int n, int* flag,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vgather_kernel, dim3((n + 255) / 256), dim3(256), 0, s, idx, src, src_n, fill, dst, n, flag);
+  return hipGetLastError();
+}
+
+// sdt / ddt: 0 double, 1 float
+hipError_t launch_convert(int sdt, const void* x, int ddt, void* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 g((unsigned)((n + 255) / 256));
+  if (sdt == 1 && ddt == 0) hipLaunchKernelGGL((convert_kernel<float, double>), g, dim3(256), 0, s, (const float*)x, (double*)y, n);
+  else if (sdt == 0 && ddt == 1) hipLaunchKernelGGL((convert_kernel<double, float>), g, dim3(256), 0, s, (const double*)x, (float*)y, n);
+  else if (sdt == 0) hipLaunchKernelGGL((convert_kernel<double, double>), g, dim3(256), 0, s, (const double*)x, (double*)y, n);
+  else hipLaunchKernelGGL((convert_kernel<float, float>), g, dim3(256), 0, s, (const float*)x, (float*)y, n);
+  return hipGetLastError();
 }
 
 }  // namespace ttn

@@ -1,5 +1,5 @@
 // Fused H_eff product at a node with one virtual leg and a physical leg (the
-// leaves of a tree, the ends of an MPS), Sec. II.C.4: for one state
+// leaves of a tree, the ends of an MPS), Sec. II.C.3: for one state
 //   Y[b][p] = alpha (sum_{w, a, q} E[b][w][a] W[w][p][q] X[a][q] - s X[b][p]) (+ Y)
 // with E the environment of the single neighbour (bra bond b, operator bond w,
 // ket bond a) and W the node's operator tensor (operator bond, output, input).
@@ -23,7 +23,7 @@ __global__ __launch_bounds__(256) void leaf_heff_kernel(LeafHeffArgs g) {
   T* sW = sE + Db * M * Da;   // [M][d][d]
   T* sT = sW + M * d * d;     // [Db][M][d]
   const int z = blockIdx.x, tid = threadIdx.x;
-  if (z >= g.n) return;  // uniform per workgroup, before any barrier
+  if (z >= g.n || (g.gate && *g.gate == 0)) return;  // uniform per workgroup, before any barrier
   int xr = g.x_ids ? g.x_ids[z] : z;
   int er = g.pair_ids ? g.pair_ids[z] : z;
   int yr = g.y_ids ? g.y_ids[z] : z;

@@ -1,5 +1,5 @@
 // Batched MINRES for the k local systems (H_eff,j - s_j) y_j = b_j of a sweep
-// step (Sec. II.C.4: local solves by MINRES), after Paige and Saunders:
+// step (Sec. II.C.3: local solves by MINRES), after Paige and Saunders:
 // Lanczos tridiagonalisation with the least-squares problem solved by Givens
 // rotations.  One workgroup of 1024 threads owns one state: its dot products
 // and norms are workgroup reductions in double (wave sums, then 16 partials),
@@ -35,7 +35,7 @@ __device__ __forceinline__ double wg_sum(double v, double* red) {
 // r = b - Ax0 -> v = r/beta1 ; zero v_prev, d buffers ; scalars
 template <typename T>
 __global__ __launch_bounds__(MR_NT) void minres_init(const T* b, const T* Ax, T* v, T* vprev, T* d1, T* d2, int64_t n,
-                                                   double rtol, MinresState* st) {
+                                                   double rtol, MinresState* st, int32_t* active) {
   __shared__ double red[MR_NT / 64];
   const int z = blockIdx.x, t = threadIdx.x;
   const T* bz = b + (int64_t)z * n;
@@ -70,6 +70,7 @@ __global__ __launch_bounds__(MR_NT) void minres_init(const T* b, const T* Ax, T*
     s.done = done ? 1 : 0;
     s.iters = 0;
     st[z] = s;
+    if (z == 0 && active) *active = (int32_t)gridDim.x;  // the gate opens; minres_count refines it
   }
 }
 
@@ -152,13 +153,30 @@ __global__ void minres_report(const MinresState* st, int k, int32_t* iters, doub
 }
 
 hipError_t launch_minres_init(int ctype, const void* b, const void* Ax, void* v, void* vprev, void* d1, void* d2,
-                              int64_t n, int k, double rtol, MinresState* st, hipStream_t s) {
+                              int64_t n, int k, double rtol, MinresState* st, int32_t* active, hipStream_t s) {
   if (ctype == 0)
     hipLaunchKernelGGL(minres_init<double>, dim3(k), dim3(MR_NT), 0, s, (const double*)b, (const double*)Ax, (double*)v,
-                       (double*)vprev, (double*)d1, (double*)d2, n, rtol, st);
+                       (double*)vprev, (double*)d1, (double*)d2, n, rtol, st, active);
   else
     hipLaunchKernelGGL(minres_init<float>, dim3(k), dim3(MR_NT), 0, s, (const float*)b, (const float*)Ax, (float*)v,
-                       (float*)vprev, (float*)d1, (float*)d2, n, rtol, st);
+                       (float*)vprev, (float*)d1, (float*)d2, n, rtol, st, active);
+  return hipGetLastError();
+}
+
+// *active = number of states whose MINRES has not converged (one workgroup;
+// written, not accumulated, so no clearing is needed before it)
+__global__ __launch_bounds__(256) void minres_count_kernel(const MinresState* st, int k, int32_t* active) {
+  __shared__ int part[4];
+  int c = 0;
+  for (int z = threadIdx.x; z < k; z += 256) c += st[z].done ? 0 : 1;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) *active = part[0] + part[1] + part[2] + part[3];
+}
+
+hipError_t launch_minres_count(const MinresState* st, int k, int32_t* active, hipStream_t s) {
+  hipLaunchKernelGGL(minres_count_kernel, dim3(1), dim3(256), 0, s, st, k, active);
   return hipGetLastError();
 }
 

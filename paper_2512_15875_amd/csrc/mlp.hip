@@ -234,6 +234,14 @@ hipError_t launch_colsum(const float* g, int n, int w, float* db, hipStream_t s)
   hipLaunchKernelGGL(colsum_kernel, dim3(w), dim3(256), 0, s, g, n, w, db);
   return hipGetLastError();
 }
+// *x = 0 by a kernel (no memset node when the caller captures a graph)
+__global__ void zero_double_kernel(double* x) { *x = 0.0; }
+
+hipError_t launch_zero_double(double* x, hipStream_t s) {
+  hipLaunchKernelGGL(zero_double_kernel, dim3(1), dim3(1), 0, s, x);
+  return hipGetLastError();
+}
+
 hipError_t launch_mse(const float* Y, const float* Tg, float* dY, int64_t total, double* loss, hipStream_t s) {
   hipLaunchKernelGGL(mse_kernel, dim3(nb256(total)), dim3(256), 0, s, Y, Tg, dY, total, 1.0 / (double)total, loss);
   return hipGetLastError();

@@ -18,6 +18,7 @@ hipError_t launch_colsum(const float* g, int n, int w, float* db, hipStream_t s)
 hipError_t launch_mse(const float* Y, const float* Tg, float* dY, int64_t total, double* loss, hipStream_t s);
 hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
                        int step, hipStream_t s);
+hipError_t launch_zero_double(double* x, hipStream_t s);
 hipError_t launch_features(int ctype, const void* b, const void* d, int64_t n, int nz, double* scales, float* X,
                            hipStream_t s);
 hipError_t launch_targets(int ctype, const void* y, const void* b, const void* d, int64_t n, int nz,
@@ -28,7 +29,7 @@ ttn_status dense_gemm(ttn_ctx* ctx, int ct, int M, int N, int K, const float* A,
                       float* C, bool accum) {
   std::ostringstream key;
   key << "dense:" << M << ":" << N << ":" << K << ":" << ta << tb;
-  int32_t* tab = nullptr;
+  const int32_t* tab = nullptr;
   auto it = ctx->tables.find(key.str());
   if (it != ctx->tables.end()) {
     tab = it->second;
@@ -46,9 +47,9 @@ ttn_status dense_gemm(ttn_ctx* ctx, int ct, int M, int N, int K, const float* A,
     push(N, 1);            // c_on
     if ((int64_t)M * K >= INT32_MAX || (int64_t)K * N >= INT32_MAX || (int64_t)M * N >= INT32_MAX)
       return api_fail(ctx, TTN_E_SHAPE, "dense GEMM too large for 32-bit offsets");
-    if (hipMalloc(&tab, h.size() * 4) != hipSuccess ||
-        !upload_sync(tab, h.data(), h.size() * 4, ctx->stream))
-      return api_fail(ctx, TTN_E_DEVICE, "table upload failed");
+    ttn_status code = TTN_OK;
+    tab = pool_upload(ctx, std::move(h), code);
+    if (!tab) return code;
     ctx->tables[key.str()] = tab;
   }
   auto pad = [](int n) { return (n + 15) / 16 * 16; };
@@ -163,7 +164,7 @@ ttn_status ttn_mlp_backward(ttn_ctx* ctx, const float* params, int32_t n, const 
 
 ttn_status ttn_mlp_loss(ttn_ctx* ctx, int32_t n, const float* Y, const float* T, float* dY, double* loss) {
   if (!ctx || !Y || !T || !dY || !loss || n < 1) return api_fail(ctx, TTN_E_ARG, "bad loss arguments");
-  if (hipMemsetAsync(loss, 0, sizeof(double), ctx->stream) != hipSuccess) return api_fail(ctx, TTN_E_DEVICE, "memset");
+  HIPL(ctx, launch_zero_double(loss, ctx->stream));
   HIPL(ctx, launch_mse(Y, T, dY, (int64_t)n * OUT, loss, ctx->stream));
   return TTN_OK;
 }

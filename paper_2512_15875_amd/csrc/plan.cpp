@@ -20,10 +20,6 @@
 
 namespace ttn {
 
-Plan::~Plan() {
-  if (d_tabs) (void)hipFree(d_tabs);
-}
-
 namespace {
 
 struct Node {
@@ -150,7 +146,7 @@ double min_flops(const std::vector<Tensor>& in, const std::map<int, int>& dims, 
 
 std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<int, int>& dims,
                                 const std::vector<int>& out_lab, const std::vector<int64_t>& out_str,
-                                double batch, int ctype, Status& st, hipStream_t stream) {
+                                double batch, int ctype, Status& st) {
   auto plan = std::make_unique<Plan>();
   plan->n_in = (int)in.size();
   std::vector<Node> ns;
@@ -217,12 +213,7 @@ std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<in
     }
   }
   std::vector<int32_t> all_tabs;
-  struct TabRef {
-    size_t step;
-    int which;
-    size_t off;
-  };
-  std::vector<TabRef> refs;
+  std::vector<Plan::TabRef> refs;
   int64_t ws_item = 0, ws_shared = 0;
   std::vector<int64_t> inter_off;  // by intermediate id - n_in
   std::vector<int> inter_shared;
@@ -443,18 +434,16 @@ std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<in
   plan->ws_shared = ws_shared;
   (void)inter_shared;
   (void)ctype;
-  // upload all tables
-  if (hipMalloc(&plan->d_tabs, all_tabs.size() * sizeof(int32_t)) != hipSuccess) {
-    st = {TTN_E_DEVICE, "hipMalloc for contraction tables failed"};
-    return nullptr;
-  }
-  if (!upload_sync(plan->d_tabs, all_tabs.data(), all_tabs.size() * sizeof(int32_t), stream)) {
-    st = {TTN_E_DEVICE, "upload of the contraction tables failed"};
-    return nullptr;
-  }
-  for (auto& r : refs) {
-    GemmDesc& g = plan->steps[r.step].g;
-    const int32_t* p = plan->d_tabs + r.off;
+  // the tables go to the device when the context binds the plan (table pool)
+  plan->h_tabs = std::move(all_tabs);
+  plan->tab_refs = std::move(refs);
+  return plan;
+}
+
+void bind_plan_tables(Plan& plan, const int32_t* d_tabs) {
+  for (const auto& r : plan.tab_refs) {
+    GemmDesc& g = plan.steps[r.step].g;
+    const int32_t* p = d_tabs + r.off;
     switch (r.which) {
       case 0: g.a_om = p; break;
       case 1: g.a_ok = p; break;
@@ -464,7 +453,6 @@ std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<in
       default: g.c_on = p; break;
     }
   }
-  return plan;
 }
 
 bool check_plan_bounds(const Plan& P, const std::vector<int64_t>& in_elems, int64_t out_elems, std::string& why) {

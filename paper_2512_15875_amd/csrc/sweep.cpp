@@ -1,6 +1,6 @@
 // C ABI: sweeps of local solves over the tree (ALS for (H - s) y = phi,
-// Sec. II.C.4, and variational fitting of sums sum_i c_i O_i phi_i,
-// Sec. II.C.3), one local step per sweep_step call.
+// Sec. II.C.3, and variational fitting of sums sum_i c_i O_i phi_i,
+// Sec. II.C.2), one local step per sweep_step call.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,7 +19,8 @@ ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, 
                            int32_t y_rows, const double* shift, const double* alpha, const void* X, int32_t x_rows,
                            void* Y, uint32_t flags, ttn_dtype compute);
 hipError_t launch_minres_init(int ctype, const void* b, const void* Ax, void* v, void* vprev, void* d1, void* d2,
-                              int64_t n, int k, double rtol, MinresState* st, hipStream_t s);
+                              int64_t n, int k, double rtol, MinresState* st, int32_t* active, hipStream_t s);
+hipError_t launch_minres_count(const MinresState* st, int k, int32_t* active, hipStream_t s);
 hipError_t launch_minres_step(int ctype, void* x, void* v, void* vprev, void* p, const void* dp, void* dpp, int64_t n,
                               int k, MinresState* st, hipStream_t s);
 hipError_t launch_minres_report(const MinresState* st, int k, int32_t* iters, double* resid, int32_t* n_active,
@@ -77,7 +78,11 @@ struct ttn_sweep {
   void* vec = nullptr;
   int64_t nmax = 0;
   MinresState* st = nullptr;
-  int32_t* d_active = nullptr;
+  int32_t* d_active = nullptr;  // number of MINRES states not yet converged (the contraction gate)
+  // eager MINRES: reads of d_active land in a pinned ring, each followed by an event
+  static constexpr int kRing = 4;
+  int32_t* h_active = nullptr;
+  hipEvent_t ev_active[kRing] = {};
   void* fit_scratch = nullptr;  // [max terms][n_loc_max] per-term local results
   // learned local map: candidate bookkeeping for 2k states (DIAG + MLP)
   int32_t* d_pair2 = nullptr;   // [2k] environment slot of each candidate (j mod k)
@@ -118,6 +123,9 @@ struct ttn_sweep {
     (void)hipFree(vec);
     (void)hipFree(st);
     (void)hipFree(d_active);
+    if (h_active) (void)hipHostFree(h_active);
+    for (hipEvent_t e : ev_active)
+      if (e) (void)hipEventDestroy(e);
   }
 };
 
@@ -125,7 +133,7 @@ namespace {
 
 template <typename T>
 bool dmalloc(T** p, size_t bytes) {
-  return hipMalloc((void**)p, bytes ? bytes : 16) == hipSuccess;
+  return dev_malloc((void**)p, bytes);
 }
 
 // environment set for (bra = target block, ket = other) with op (nullable)
@@ -147,7 +155,7 @@ ttn_envs* make_envs(const ttn_tree* t, const ttn_block* bra, const ttn_ttno* op,
     const size_t bytes = (size_t)n_slots * e->Db[u] * e->M[u] * e->Da[u] * es;
     for (int s = 0; s < 2; ++s) {
       void* p = nullptr;
-      if (hipMalloc(&p, bytes) != hipSuccess) {
+      if (!dev_malloc(&p, bytes)) {
         ok = false;
         return e;
       }
@@ -373,10 +381,16 @@ ttn_status ttn_sweep_create(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
   int max_terms = 0;
   for (auto& s : sw->src) max_terms = std::max(max_terms, s.n);
   if (!dmalloc(&sw->vec, (size_t)8 * sw->k * nmax * es) || !dmalloc(&sw->st, (size_t)sw->k * sizeof(MinresState)) ||
-      !dmalloc(&sw->d_active, 16) || !dmalloc(&sw->fit_scratch, (size_t)max_terms * nmax * es)) {
+      !dmalloc(&sw->d_active, 16) || !dmalloc(&sw->fit_scratch, (size_t)max_terms * nmax * es) ||
+      !pinned_malloc((void**)&sw->h_active, ttn_sweep::kRing * sizeof(int32_t))) {
     delete sw;
     return api_fail(ctx, TTN_E_DEVICE, "allocation failed");
   }
+  for (hipEvent_t& e : sw->ev_active)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      delete sw;
+      return api_fail(ctx, TTN_E_DEVICE, "hipEventCreate failed");
+    }
   {
     std::vector<int32_t> pair2(2 * sw->k);
     for (int i = 0; i < 2 * sw->k; ++i) pair2[i] = i % sw->k;
@@ -435,8 +449,7 @@ ttn_status ttn_sweep_run(ttn_ctx* ctx, ttn_sweep* sw, const ttn_solve_opts* opts
   };
   // graphs: not under profiling (events), not on the legacy null stream, and
   // not for MINRES runs long enough to take host-side convergence checks
-  const bool capturable = use_graph && !ctx->profile && ctx->stream != nullptr &&
-                          !(opts->mode == TTN_SOLVE_MINRES && opts->maxiter > 25);
+  const bool capturable = use_graph && !ctx->profile && ctx->stream != nullptr;
   if (!capturable) return run();
   std::ostringstream key;
   key << opts->mode << ":" << opts->maxiter << ":" << opts->rtol << ":" << (const void*)opts->mlp_params << ":"
@@ -573,28 +586,59 @@ ttn_status sweep_step(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, int32_t next, c
       void *v = vbuf(1), *vp = vbuf(2), *p = vbuf(3), *d1 = vbuf(4), *d2 = vbuf(5);
       // batched MINRES on (H_eff - s) x = rhs, warm start x with Ax0 = (H_eff - s) x
       auto minres = [&](void* x, const void* rhs, const void* ax0, ttn_dtype comp, double rtol) -> ttn_status {
-        hipError_t e = launch_minres_init(ct, rhs, ax0, v, vp, d1, d2, n, k, rtol, sw->st, ctx->stream);
+        hipError_t e = launch_minres_init(ct, rhs, ax0, v, vp, d1, d2, n, k, rtol, sw->st, sw->d_active, ctx->stream);
         if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
         void *vv = v, *vvp = vp, *dp = d1, *dpp = d2;
-        const int check_every = 25;
-        for (int it = 0; it < opts->maxiter; ++it) {
+        // Every `seg` iterations a one-workgroup kernel counts the states not
+        // yet converged into d_active; the iteration's contraction kernels read
+        // it first and do nothing once it is zero, so the work stops on the
+        // device without the host.  Eagerly, the count is also copied to a
+        // pinned ring (no wait) and the host stops enqueueing once a completed
+        // copy reads zero; it waits for the oldest copy only when it runs four
+        // segments ahead of the device.  Under stream capture all maxiter
+        // iterations are recorded and the gate alone ends the work.
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        const bool capturing =
+            hipStreamIsCapturing(ctx->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+        const int seg = 25;
+        int issued = 0, polled = 0;
+        bool stop = false;
+        struct GateGuard {
+          ttn_ctx* c;
+          ~GateGuard() { c->gate = nullptr; }
+        } guard{ctx};
+        for (int it = 0; it < opts->maxiter && !stop; ++it) {
+          ctx->gate = sw->d_active;
           ttn_status rr = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, vv, k,
                                            p, TTN_HEFF_APPLY, comp);
+          ctx->gate = nullptr;
           if (rr != TTN_OK) return rr;
           e = launch_minres_step(ct, x, vv, vvp, p, dp, dpp, n, k, sw->st, ctx->stream);
           if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
           std::swap(vv, vvp);
           std::swap(dp, dpp);
-          if ((it + 1) % check_every == 0 && it + 1 < opts->maxiter) {
-            int32_t act = 0;
-            if (hipMemsetAsync(sw->d_active, 0, 4, ctx->stream) != hipSuccess)
-              return api_fail(ctx, TTN_E_DEVICE, "memset");
-            e = launch_minres_report(sw->st, k, nullptr, nullptr, sw->d_active, ctx->stream);
+          if ((it + 1) % seg == 0 && it + 1 < opts->maxiter) {
+            e = launch_minres_count(sw->st, k, sw->d_active, ctx->stream);
             if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
-            if (hipMemcpyAsync(&act, sw->d_active, 4, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-                hipStreamSynchronize(ctx->stream) != hipSuccess)
-              return api_fail(ctx, TTN_E_DEVICE, "convergence check failed");
-            if (act == 0) break;
+            if (capturing) continue;
+            const int R = ttn_sweep::kRing;
+            if (issued - polled == R) {  // bounded run-ahead: wait for the oldest read
+              if (hipEventSynchronize(sw->ev_active[polled % R]) != hipSuccess)
+                return api_fail(ctx, TTN_E_DEVICE, "convergence read failed");
+              stop = ((volatile int32_t*)sw->h_active)[polled % R] == 0;
+              ++polled;
+              if (stop) break;
+            }
+            if (hipMemcpyAsync(sw->h_active + issued % R, sw->d_active, 4, hipMemcpyDeviceToHost, ctx->stream) !=
+                    hipSuccess ||
+                hipEventRecord(sw->ev_active[issued % R], ctx->stream) != hipSuccess)
+              return api_fail(ctx, TTN_E_DEVICE, "convergence read failed");
+            ++issued;
+            while (polled < issued && hipEventQuery(sw->ev_active[polled % R]) == hipSuccess) {
+              stop = ((volatile int32_t*)sw->h_active)[polled % R] == 0;
+              ++polled;
+              if (stop) break;
+            }
           }
         }
         return TTN_OK;

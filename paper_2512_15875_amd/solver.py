@@ -2,9 +2,10 @@
 
 Host-side control only: every tensor operation (environment updates, H_eff
 products, MINRES, QR gauge moves, fitting sums, Gram closures, Rayleigh-Ritz,
-normalisation) runs in libttn's HIP kernels through the C ABI.  The host
-reads back scalars (Rayleigh quotients, residual norms) to decide clusters and
-stopping; PyTorch provides device buffers and plain copies between them.
+normalisation, norms, coefficient gathers, precision promotion) runs in
+libttn's HIP kernels through the C ABI.  The host reads back scalars (Rayleigh
+quotients, residual norms) to decide clusters and stopping; PyTorch provides
+device buffers (allocated once per solver) and plain copies between them.
 
 Algorithms: Alg. lobpcg_block with the three-term recurrence (Eq. lobpcg
 update) and Alg. block_inverse_iteration, with the readings listed in
@@ -81,7 +82,12 @@ class TTNEigensolver:
     tree: workloads.Tree; model: workloads.SOPModel; the initial block comes
     as [state][node] host arrays (seeded input, not yet canonical).
     precision: "fp64" (plain) or "fp32" / "bf16" (contractions in FP32 / BF16
-    matrix cores, FP32 storage; Rayleigh-Ritz always FP64).
+    matrix cores, FP32 storage; Rayleigh-Ritz always FP64), or "f64_f32" (the
+    mixed form: FP64 storage, every contraction with the Hamiltonian that
+    builds the block -- the H~ Gram environments, the residual fits, the
+    preconditioner's sweeps and fits -- on FP32 matrix cores, while the
+    overlap S~, the Rayleigh quotients and Rayleigh-Ritz stay in FP64
+    arithmetic).
     """
 
     def __init__(self, ctx: ttn.Context, tree, model, D: int, k: int, precision: str = "fp64",
@@ -95,8 +101,10 @@ class TTNEigensolver:
         # the host compiler's TTNO (or a prebuilt one: (site tensors, operator bonds))
         W, M = ttno if ttno is not None else build_ttno(self.gt, tree, model)
         self.M = [max(1, m) for m in M]
-        self.sdt = ttn.F64 if precision == "fp64" else ttn.F32
-        self.compute = {"fp64": ttn.F64, "fp32": ttn.F32, "bf16": ttn.BF16}[precision]
+        self.sdt = ttn.F64 if precision in ("fp64", "f64_f32") else ttn.F32
+        # bulk compute type, and the one of the exact quantities (S~, Rayleigh quotients)
+        self.compute = {"fp64": ttn.F64, "fp32": ttn.F32, "bf16": ttn.BF16, "f64_f32": ttn.F64_F32}[precision]
+        self.compute_exact = ttn.F64 if self.sdt == ttn.F64 else self.compute
         self.tdt = ttn.torch_dtype(self.sdt)
         self.Wd = [torch.from_numpy(np.ascontiguousarray(w)).to(device="cuda", dtype=self.tdt) for w in W]
         self.op = ttn.TTNO(ctx, self.gt, self.Wd, self.M, self.sdt)
@@ -149,11 +157,18 @@ class TTNEigensolver:
                               compute=self.compute)
         self.sw_p = ttn.Sweep(ctx, self.gt, None, self.PN, [(None, self.B, self.cp_t, self.cp_s, self.cp_d)],
                               compute=self.compute)
-        self.ix_gather = torch.tensor([l * k + j for j, l in zip(self.cx_t, self.cx_s)], device=dev)
-        self.ip_gather = torch.tensor([l * k + j for j, l in zip(self.cp_t, self.cp_s)], device=dev)
+        self.ix_gather = torch.tensor([l * k + j for j, l in zip(self.cx_t, self.cx_s)], dtype=torch.int32, device=dev)
+        self.ip_gather = torch.tensor([l * k + j for j, l in zip(self.cp_t, self.cp_s)], dtype=torch.int32, device=dev)
+        self.rn2 = torch.zeros(k, dtype=torch.float64, device=dev)   # squared residual norms
+        self.rn = torch.zeros(k, dtype=torch.float64, device=dev)    # residual norms
+        ld = 3 * k
+        self.GH = torch.zeros(ld * ld, dtype=torch.float64, device=dev)  # Gram matrices (row-major ld x ld)
+        self.GS = torch.zeros(ld * ld, dtype=torch.float64, device=dev)
+        self._pairs = {}  # device pair / scatter tables and closure outputs, by pair-list name
         self.history: List[dict] = []
         self._sw_ii = None
         self.cluster_rr_calls = 0  # in-cluster Rayleigh-Ritz steps of inverse iteration (clusters of > 1 state)
+        self._cl_tables = None     # device tables of the in-cluster Rayleigh-Ritz (clusters are fixed)
 
     # ------------------------------------------------------------ block plumbing
 
@@ -178,34 +193,60 @@ class TTNEigensolver:
 
     # ------------------------------------------------------------ Gram / Rayleigh quotients
 
-    def gram(self, blk: ttn.Block, pairs_a: List[int], pairs_b: List[int], with_H=True, with_S=True):
-        """Closures <a|H|b> and <a|b> for the listed pairs (device double arrays)."""
-        n = len(pairs_a)
-        outH = torch.zeros(n, dtype=torch.float64, device="cuda")
-        outS = torch.zeros(n, dtype=torch.float64, device="cuda")
-        for c0 in range(0, n, self.pair_cap):
-            c1 = min(n, c0 + self.pair_cap)
-            pa = torch.tensor(pairs_a[c0:c1], dtype=torch.int32, device="cuda")
-            pb = torch.tensor(pairs_b[c0:c1], dtype=torch.int32, device="cuda")
-            for (op, env, out) in ((self.op, self.genv_H, outH), (None, self.genv_I, outS)):
+    def _pair_set(self, name, pairs_a: List[int], pairs_b: List[int], la=None, lb=None):
+        """Device tables of a pair list (chunked to the environment capacity),
+        its closure outputs and, with la / lb, its symmetric scatter indices;
+        built once per name."""
+        ps = self._pairs.get(name)
+        if ps is None or ps["n"] != len(pairs_a) or ps["key"] != (tuple(pairs_a), tuple(pairs_b)):
+            n = len(pairs_a)
+            i32 = dict(dtype=torch.int32, device="cuda")
+            ps = {"n": n, "key": (tuple(pairs_a), tuple(pairs_b)),
+                  "chunks": [(c0, min(n, c0 + self.pair_cap),
+                              torch.tensor(pairs_a[c0:c0 + self.pair_cap], **i32),
+                              torch.tensor(pairs_b[c0:c0 + self.pair_cap], **i32))
+                             for c0 in range(0, n, self.pair_cap)],
+                  "H": torch.zeros(n, dtype=torch.float64, device="cuda"),
+                  "S": torch.zeros(n, dtype=torch.float64, device="cuda")}
+            if la is not None:
+                ps["la"] = torch.tensor(la, **i32)
+                ps["lb"] = torch.tensor(lb, **i32)
+            self._pairs[name] = ps
+        return ps
+
+    def gram(self, blk: ttn.Block, pairs_a: List[int], pairs_b: List[int], with_H=True, with_S=True, name=None,
+             exact_H=False):
+        """Closures <a|H|b> and <a|b> for the listed pairs (device double arrays).
+        <a|H|b> in the bulk compute type unless exact_H; <a|b> in the exact one."""
+        ps = self._pair_set(name or ("pairs", len(pairs_a)), pairs_a, pairs_b)
+        outH, outS = ps["H"], ps["S"]
+        cH = self.compute_exact if exact_H else self.compute
+        for (c0, c1, pa, pb) in ps["chunks"]:
+            for (op, env, out, comp) in ((self.op, self.genv_H, outH, cH), (None, self.genv_I, outS,
+                                                                            self.compute_exact)):
                 if (op is not None and not with_H) or (op is None and not with_S):
                     continue
                 for (u, p) in self.up_edges:
-                    ttn.ttno_env_update(self.ctx, self.gt, op, blk, blk, pa, pb, u, p, env, self.compute)
+                    ttn.ttno_env_update(self.ctx, self.gt, op, blk, blk, pa, pb, u, p, env, comp)
                 ttn.ttno_env_close(self.ctx, self.gt, op, blk, blk, pa, pb, self.root, env, out[c0:c1],
-                                   self.compute)
+                                   comp)
         return outH, outS
 
     def rayleigh_quotients(self, blk: ttn.Block, rows: List[int]) -> torch.Tensor:
-        H, _ = self.gram(blk, rows, rows, with_S=False)
+        H, _ = self.gram(blk, rows, rows, with_S=False, name=("rq", len(rows)), exact_H=True)
         return H  # states are normalised
 
-    def _assemble(self, vals: torch.Tensor, ia: List[int], ib: List[int], size: int):
-        out = torch.zeros(size, dtype=torch.float64, device="cuda")
-        ta = torch.tensor(ia, dtype=torch.int32, device="cuda")
-        tb = torch.tensor(ib, dtype=torch.int32, device="cuda")
-        ttn.scatter_sym(self.ctx, ta, tb, vals, out)
-        return out
+    def _gram_matrices(self, blk: ttn.Block, name, rows_a: List[int], rows_b: List[int], la: List[int],
+                       lb: List[int], size: int, exact_H: bool = False):
+        """Gram closures of the listed pairs scattered symmetrically into the
+        preallocated H~ / S~ buffers (entries la / lb; only the problems'
+        m x m blocks are read by Rayleigh-Ritz)."""
+        ps = self._pair_set(name, rows_a, rows_b, la, lb)
+        hv, sv = self.gram(blk, rows_a, rows_b, name=name, exact_H=exact_H)
+        Hm, Sm = self.GH[:size], self.GS[:size]
+        ttn.scatter_sym(self.ctx, ps["la"], ps["lb"], hv, Hm)
+        ttn.scatter_sym(self.ctx, ps["la"], ps["lb"], sv, Sm)
+        return Hm, Sm
 
     # ------------------------------------------------------------ LOBPCG
 
@@ -231,8 +272,8 @@ class TTNEigensolver:
         ttn.vec_scale(ctx, self.lam_d, -1.0, self.neglam_d)
         self._copy_rows(self.R, 0, self.B, 0, k)
         self.sw_res.run(ttn.SOLVE_FIT, opts.fit_sweeps, init=True, graph=self.graphs)
-        rn = torch.zeros(k, dtype=torch.float64, device="cuda")
-        ttn.block_node_norms2(ctx, self.R, root, rn)
+        ttn.block_node_norms2(ctx, self.R, root, self.rn2)
+        ttn.vec_sqrt(ctx, self.rn2, self.rn)
         # preconditioned residual: (H - s) w = r by ALS
         self._copy_rows(self.Wp, 0, self.R, 0, k)
         mode, warm = {"minres": (ttn.SOLVE_MINRES, ttn.WARM_NONE), "diag": (ttn.SOLVE_DIAG, ttn.WARM_NONE),
@@ -243,7 +284,7 @@ class TTNEigensolver:
                         rtol=opts.minres_rtol, mlp=opts.mlp, mlp_compute=opts.mlp_compute, warm=warm)
         ttn.block_normalize_node(ctx, self.Wp, root)
         self._copy_rows(self.B, k, self.Wp, 0, k)
-        rnorm = torch.sqrt(rn).cpu().numpy()
+        rnorm = self.rn.cpu().numpy()
         lam_h = self.lam_d.cpu().numpy()
         rec = {"iter": it, "t": time.perf_counter() - self._t0, "lam": lam_h + self.zpe, "resid": rnorm}
         self.history.append(rec)
@@ -257,16 +298,14 @@ class TTNEigensolver:
             for b in range(a, m):
                 ia.append(a)
                 ib.append(b)
-        hv, sv = self.gram(self.B, ia, ib)
         ld = 3 * k
         la = [a * ld + b for a, b in zip(ia, ib)]
         lb = [b * ld + a for a, b in zip(ia, ib)]
-        Hm = self._assemble(hv, la, lb, ld * ld)
-        Sm = self._assemble(sv, la, lb, ld * ld)
+        Hm, Sm = self._gram_matrices(self.B, ("subspace", m), ia, ib, la, lb, ld * ld)
         ev, V, rank = ttn.rayleigh_ritz(ctx, Hm.view(1, ld, ld), Sm.view(1, ld, ld), [m], k, opts.drop_tol)
         Vf = V[0].reshape(-1)  # [ld][k] row-major: V[l, j] at l*k + j
-        self.cx_d.copy_(Vf[self.ix_gather])
-        self.cp_d.copy_(Vf[self.ip_gather])
+        ttn.vec_gather(ctx, self.ix_gather, Vf, self.cx_d)
+        ttn.vec_gather(ctx, self.ip_gather, Vf, self.cp_d)
         # p_j = sum_{l >= k} V[l, j] s_l ; x_j = sum_l V[l, j] s_l  (fitted)
         self._copy_rows(self.PN, 0, self.B, k, k)
         self.sw_p.run(ttn.SOLVE_FIT, opts.fit_sweeps, init=True, graph=self.graphs)
@@ -337,14 +376,15 @@ class TTNEigensolver:
         idx = list(range(k))
         if self._sw_ii is None:
             # target Y, source x (rows [0, k) of the basis)
+            # inverse iteration is the refinement: its solves and recombination in the exact type
             self._sw_ii = ttn.Sweep(ctx, self.gt, self.op, self.Y, [(None, self.B, idx, idx, None)],
-                                    shift=self.shift_d, compute=self.compute)
+                                    shift=self.shift_d, compute=self.compute_exact)
             # recombination inside clusters: x_j = sum_{l in c(j)} V_c[l, j] x_l
             self.ci_t = [j for c in cl for j in c for l in c]
             self.ci_s = [l for c in cl for j in c for l in c]
             self.ci_d = torch.zeros(len(self.ci_t), dtype=torch.float64, device="cuda")
             self._sw_rec = ttn.Sweep(ctx, self.gt, None, self.XN, [(None, self.B, self.ci_t, self.ci_s, self.ci_d)],
-                                     compute=self.compute)
+                                     compute=self.compute_exact)
             self._clusters = cl
         cl = self._clusters
         big = [c for c in cl if len(c) > 1]
@@ -389,42 +429,33 @@ class TTNEigensolver:
         ctx, k, root = self.ctx, self.k, self.root
         self.cluster_rr_calls += 1
         ld = max(len(c) for c in big)
-        ia, ib, la, lb = [], [], [], []
-        for ci, c in enumerate(big):
-            for a in range(len(c)):
-                for b in range(a, len(c)):
-                    ia.append(c[a])
-                    ib.append(c[b])
-                    la.append(ci * ld * ld + a * ld + b)
-                    lb.append(ci * ld * ld + b * ld + a)
-        hv, sv = self.gram(self.B, ia, ib)
-        Hm = self._assemble(hv, la, lb, len(big) * ld * ld)
-        Sm = self._assemble(sv, la, lb, len(big) * ld * ld)
+        if self._cl_tables is None:
+            ia, ib, la, lb = [], [], [], []
+            for ci, c in enumerate(big):
+                for a in range(len(c)):
+                    for b in range(a, len(c)):
+                        ia.append(c[a])
+                        ib.append(c[b])
+                        la.append(ci * ld * ld + a * ld + b)
+                        lb.append(ci * ld * ld + b * ld + a)
+            # recombination coefficients in the fitting sweep's term order:
+            # V[c][l, j] for the members of a cluster, 1 for a singleton
+            big_index = {tuple(c): i for i, c in enumerate(big)}
+            gidx = []
+            for c in self._clusters:
+                if len(c) == 1:
+                    gidx.append(-1)
+                    continue
+                ci = big_index[tuple(c)]
+                for jj in range(len(c)):
+                    for ll in range(len(c)):
+                        gidx.append(ci * ld * ld + ll * ld + jj)
+            self._cl_tables = (ia, ib, la, lb, torch.tensor(gidx, dtype=torch.int32, device="cuda"))
+        ia, ib, la, lb, gidx = self._cl_tables
+        Hm, Sm = self._gram_matrices(self.B, "clusters", ia, ib, la, lb, len(big) * ld * ld, exact_H=True)
         ev, V, rank = ttn.rayleigh_ritz(ctx, Hm.view(len(big), ld, ld), Sm.view(len(big), ld, ld),
                                         [len(c) for c in big], ld, opts.drop_tol)
-        # coefficients for the recombination fit (identity for singleton clusters)
-        coef = torch.zeros(len(self.ci_t), dtype=torch.float64, device="cuda")
-        pos = 0
-        Vh = V  # [nb][ld][ld]
-        big_index = {tuple(c): i for i, c in enumerate(big)}
-        gather_src, gather_dst, ones_dst = [], [], []
-        for c in self._clusters:
-            if len(c) == 1:
-                ones_dst.append(pos)
-                pos += 1
-                continue
-            ci = big_index[tuple(c)]
-            for jj in range(len(c)):
-                for ll in range(len(c)):
-                    gather_src.append(ci * ld * ld + ll * ld + jj)
-                    gather_dst.append(pos)
-                    pos += 1
-        flat = Vh.reshape(-1)
-        if gather_dst:
-            coef[torch.tensor(gather_dst, device="cuda")] = flat[torch.tensor(gather_src, device="cuda")]
-        if ones_dst:
-            coef[torch.tensor(ones_dst, device="cuda")] = 1.0
-        self.ci_d.copy_(coef)
+        ttn.vec_gather(ctx, gidx, V.reshape(-1), self.ci_d, fill=1.0)
         self._copy_rows(self.XN, 0, self.B, 0, k)
         self._sw_rec.run(ttn.SOLVE_FIT, opts.fit_sweeps, init=True, graph=self.graphs)
         ttn.block_normalize_node(ctx, self.XN, root)
@@ -439,9 +470,9 @@ class TTNEigensolver:
             for b in range(a, k):
                 ia.append(a)
                 ib.append(b)
-        hv, sv = self.gram(self.B, ia, ib)
-        Hm = self._assemble(hv, [a * k + b for a, b in zip(ia, ib)], [b * k + a for a, b in zip(ia, ib)], k * k)
-        Sm = self._assemble(sv, [a * k + b for a, b in zip(ia, ib)], [b * k + a for a, b in zip(ia, ib)], k * k)
+        la = [a * k + b for a, b in zip(ia, ib)]
+        lb = [b * k + a for a, b in zip(ia, ib)]
+        Hm, Sm = self._gram_matrices(self.B, "final", ia, ib, la, lb, k * k, exact_H=True)
         ev, V, rank = ttn.rayleigh_ritz(self.ctx, Hm.view(1, k, k), Sm.view(1, k, k), [k], k, drop_tol)
         return ev[0].cpu().numpy() + self.zpe
 
@@ -449,17 +480,18 @@ class TTNEigensolver:
 class MixedEigensolver:
     """Mixed-precision form: block LOBPCG with FP32 storage and FP32 (or
     BF16) matrix-core contractions as the warm start, then the block is
-    promoted to FP64 and refined by FP64 iterations (LOBPCG and / or inverse
-    iteration) whose Rayleigh quotients, Gram matrices, Rayleigh-Ritz and
-    shifted solves are all FP64 — the FP32 phase only has to get the
-    eigenvectors close, the FP64 phase recovers full accuracy."""
+    promoted to FP64 storage and refined.  hi = "f64_f32" (default) refines
+    with the bulk H contractions still on FP32 matrix cores and the overlap
+    S~, the Rayleigh quotients, Rayleigh-Ritz and the inverse-iteration
+    solves in FP64; hi = "fp64" refines with every contraction in FP64."""
 
     def __init__(self, ctx: ttn.Context, tree, model, D: int, k: int, low: str = "fp32", ttno=None,
-                 env_budget_bytes: Optional[int] = None, hi_pre_compute: Optional[int] = None):
+                 env_budget_bytes: Optional[int] = None, hi_pre_compute: Optional[int] = None,
+                 hi: str = "f64_f32"):
         if ttno is None:
             ttno = build_ttno(ttn.Tree(tree.parent, tree.phys), tree, model)
         self.lo = TTNEigensolver(ctx, tree, model, D, k, precision=low, ttno=ttno, env_budget_bytes=env_budget_bytes)
-        self.hi = TTNEigensolver(ctx, tree, model, D, k, precision="fp64", ttno=ttno,
+        self.hi = TTNEigensolver(ctx, tree, model, D, k, precision=hi, ttno=ttno,
                                  env_budget_bytes=env_budget_bytes, pre_compute=hi_pre_compute)
         self.k = k
         self.history: List[dict] = []
@@ -471,8 +503,7 @@ class MixedEigensolver:
         """Copy the x and p parts of the low-precision basis into the FP64
         solver (a cast, on the device) and continue from there."""
         k = self.k
-        for u in range(self.lo.gt.n):
-            self.hi.B.t[u].copy_(self.lo.B.t[u].to(torch.float64))
+        ttn.block_convert(self.hi.ctx, self.lo.B, self.hi.B, 3 * k)
         self.hi.lam_d.copy_(self.lo.lam_d)
         self.hi.shift_d.copy_(self.lo.shift_d)
         self.hi._opts = self.lo._opts

@@ -66,6 +66,13 @@ _SIGS = {
     "ttn_vec_scale": [_P, _I, _P, C.c_double, _P],
     "ttn_ctx_profile": [_P, _I],
     "ttn_ctx_flops": [_P, C.POINTER(C.c_double), _I],
+    "ttn_alloc_count": [C.POINTER(C.c_int64)],
+    "ttn_ctx_profile_filter": [_P, _I, _P],
+    "ttn_ctx_probe_heff": [_P, _I, _P],
+    "ttn_ctx_probe_report": [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)],
+    "ttn_vec_sqrt": [_P, _I, _P, _P],
+    "ttn_vec_gather": [_P, _I, _P, _P, _I, C.c_double, _P],
+    "ttn_block_convert": [_P, _P, _P, _I],
     "ttn_ctx_profile_report": [_P, C.c_char_p, C.c_int64, C.POINTER(C.c_int64)],
     "ttn_mlp_forward": [_P, _P, _I, _P, _P, _P, C.c_int],
     "ttn_mlp_backward": [_P, _P, _I, _P, _P, _P, _P, C.c_int],
@@ -479,6 +486,25 @@ def profile(ctx: Context, on: bool):
     _check(lib().ttn_ctx_profile(ctx.h, 1 if on else 0), ctx)
 
 
+def profile_filter(ctx: Context, prefixes: Sequence[str]):
+    """Record only plans whose key starts with one of the prefixes (empty: all)."""
+    arr = (C.c_char_p * max(1, len(prefixes)))(*[p.encode() for p in prefixes])
+    _check(lib().ttn_ctx_profile_filter(ctx.h, len(prefixes), C.cast(arr, C.c_void_p)), ctx)
+
+
+def probe_heff(ctx: Context, nodes: Sequence[int]):
+    """Bracket every heff_apply_block call with the operator at these nodes by HIP events."""
+    arr = _i32(list(nodes) or [0])
+    _check(lib().ttn_ctx_probe_heff(ctx.h, len(nodes), C.cast(arr, C.c_void_p)), ctx)
+
+
+def probe_report(ctx: Context):
+    """(calls, algorithmic flops, summed event ms) of the probed heff_apply_block calls since the last report."""
+    n, f, ms = C.c_int64(), C.c_double(), C.c_double()
+    _check(lib().ttn_ctx_probe_report(ctx.h, C.byref(n), C.byref(f), C.byref(ms)), ctx)
+    return int(n.value), float(f.value), float(ms.value)
+
+
 def profile_report(ctx: Context):
     """[(plan_key, stage, kernel, launches, total_ms, flops, M, N, K, batch_items, bytes)] since the last
     report (bytes: compulsory bytes, see ttn_ctx_profile_report)."""
@@ -501,8 +527,29 @@ def scatter_sym(ctx: Context, idx_a: torch.Tensor, idx_b: torch.Tensor, vals: to
     _check(lib().ttn_scatter_sym(ctx.h, int(idx_a.numel()), _ptr(idx_a), _ptr(idx_b), _ptr(vals), _ptr(out)), ctx)
 
 
+def vec_sqrt(ctx: Context, x: torch.Tensor, y: torch.Tensor):
+    _check(lib().ttn_vec_sqrt(ctx.h, int(x.numel()), _ptr(x), _ptr(y)), ctx)
+
+
+def vec_gather(ctx: Context, idx: torch.Tensor, src: torch.Tensor, dst: torch.Tensor, fill: float = 0.0):
+    """dst[i] = src[idx[i]] (idx[i] >= 0) else fill, on the device (ttn_vec_gather)."""
+    _check(lib().ttn_vec_gather(ctx.h, int(idx.numel()), _ptr(idx), _ptr(src), int(src.numel()), float(fill),
+                                _ptr(dst)), ctx)
+
+
+def block_convert(ctx: Context, src: "Block", dst: "Block", rows: int):
+    _check(lib().ttn_block_convert(ctx.h, src.h, dst.h, int(rows)), ctx)
+
+
 def vec_scale(ctx: Context, x: torch.Tensor, alpha: float, y: torch.Tensor):
     _check(lib().ttn_vec_scale(ctx.h, int(x.numel()), _ptr(x), float(alpha), _ptr(y)), ctx)
+
+
+def alloc_count() -> int:
+    """Device and pinned-host allocations the library has made in this process."""
+    out = C.c_int64()
+    _check(lib().ttn_alloc_count(C.byref(out)))
+    return int(out.value)
 
 
 def version() -> str:
