@@ -199,6 +199,22 @@ ttn_status rayleigh_ritz(ttn_ctx* ctx, int32_t batch, const int32_t* m, int32_t 
                          const double* S, int32_t nev, double drop_tol, int32_t allow_svqb,
                          double* evals, double* V, int32_t* rank_out);
 
+/* heff_apply_block for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, semantics, kernels and error behaviour as
+ * heff_apply_block; the contraction intermediates live in a static device
+ * array of 256 MiB per device (one state's intermediates must fit in it --
+ * TTN_E_WORKSPACE otherwise -- and the states are processed in chunks that
+ * fit), found at ttn_ctx_create and kept until the process ends.  The call
+ * makes no device or pinned allocation (offset tables of a contraction
+ * planned for the first time come from the context's table pool).  Every
+ * call on one device shares that device's array: calls that overlap in time
+ * on one device (two streams, two contexts or two threads) race. */
+ttn_status heff_apply_block_noalloc(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_envs* envs,
+                                    int32_t node, int32_t k, const int32_t* pair_ids, const int32_t* x_ids,
+                                    const double* shift, const double* alpha, const void* X, int32_t x_rows,
+                                    void* Y, uint32_t flags, ttn_dtype compute);
+
 /* ------------------------------------------------------------ sweep (ALS / fitting) */
 
 /* MINRES: local MINRES on (H_eff - s_j); DIAG: y = b / (diag(H_eff) - s_j);

@@ -457,6 +457,7 @@ ttn_status ttn_ctx_create(int device, void* hip_stream, size_t workspace_bytes, 
     delete c;
     return fail(nullptr, TTN_E_DEVICE, "flag hipMalloc failed");
   }
+  if (!noalloc_scratch_setup(device, &c->scratch)) c->scratch = nullptr;  // heff_apply_block_noalloc reports it
   *out = c;
   return TTN_OK;
 }

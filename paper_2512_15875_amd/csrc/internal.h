@@ -323,6 +323,9 @@ struct ttn_ctx {
   // while non-null, every contraction-stage kernel first reads this device
   // word and returns at once when it is zero (the MINRES convergence gate)
   const int32_t* gate = nullptr;
+  // this device's copy of the static scratch array of heff_apply_block_noalloc
+  // (looked up at creation; null if the lookup failed)
+  void* scratch = nullptr;
   bool autotune = false;  // time every tile shape on a stage's first launch and keep the fastest
   std::string tune_log;   // "plan-key|stage|M|N|K|items|chosen tile|us per tile..." lines
   double flops_done = 0;  // algorithmic contraction flops launched so far
@@ -358,4 +361,7 @@ bool pinned_malloc(void** p, size_t bytes);
 const int32_t* pool_upload(ttn_ctx* ctx, std::vector<int32_t>&& h, ttn_status& code);
 // whether the stage profile records plans with this key (prefix filter)
 bool prof_selected(const ttn_ctx* ctx, const std::string& key);
+// the device address of heff_apply_block_noalloc's static scratch array on
+// `device` (which must be current); false if it cannot be found
+bool noalloc_scratch_setup(int device, void** out);
 }  // namespace ttn

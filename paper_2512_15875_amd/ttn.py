@@ -45,6 +45,7 @@ _SIGS = {
     "ttno_env_update": [_P, _P, _P, _P, _P, _I, _P, _P, _I, _I, _P, C.c_int],
     "ttno_env_close": [_P, _P, _P, _P, _P, _I, _P, _P, _I, _P, _P, C.c_int],
     "heff_apply_block": [_P, _P, _P, _P, _I, _I, _P, _P, _P, _P, _P, _I, _P, C.c_uint32, C.c_int],
+    "heff_apply_block_noalloc": [_P, _P, _P, _P, _I, _I, _P, _P, _P, _P, _P, _I, _P, C.c_uint32, C.c_int],
     "rayleigh_ritz": [_P, _I, _PI, _I, _P, _P, _I, C.c_double, _I, _P, _P, _P],
     "ttn_block_move_centre": [_P, _P, _I, _I],
     "ttn_block_scale_node": [_P, _P, _I, _P],
@@ -298,6 +299,16 @@ def heff_apply_block(ctx: Context, tree: Tree, op: Optional[TTNO], envs: Envs, n
     _check(lib().heff_apply_block(ctx.h, tree.h, None if op is None else op.h, envs.h, node, k, _ptr(pair_ids),
                                   _ptr(x_ids), _ptr(shift), _ptr(alpha), _ptr(X), x_rows, _ptr(Y), flags,
                                   compute), ctx)
+
+
+def heff_apply_block_noalloc(ctx: Context, tree: Tree, op: Optional[TTNO], envs: Envs, node: int, k: int,
+                             X: Optional[torch.Tensor], Y: torch.Tensor, pair_ids=None, x_ids=None, shift=None,
+                             alpha=None, flags: int = HEFF_APPLY, compute: int = F64):
+    """heff_apply_block with the library's static device scratch as workspace (allocates nothing)."""
+    x_rows = int(X.shape[0]) if X is not None else 0
+    _check(lib().heff_apply_block_noalloc(ctx.h, tree.h, None if op is None else op.h, envs.h, node, k,
+                                          _ptr(pair_ids), _ptr(x_ids), _ptr(shift), _ptr(alpha), _ptr(X), x_rows,
+                                          _ptr(Y), flags, compute), ctx)
 
 
 def flops_heff(tree: Tree, op: Optional[TTNO], envs: Envs, node: int, k: int) -> float:
