@@ -103,12 +103,13 @@ def make_solver(api, ctx, workload: str, precision: str, k: int, D: int):
     return s, model, tree
 
 
-def time_to_all_states(api, ctx, precision: str, tol: float = 1e-3, max_iter: int = 12, switch_tol: float = 1e-2):
+def time_to_all_states(api, ctx, form: str, tol: float = 1e-3, max_iter: int = 12, switch_tol: float = 1e-2):
     """Solver start (block on the device) to the first LOBPCG iteration whose
     Rayleigh quotients all lie within tol of the exact levels (6-mode
-    workload, MPS, D=8, k=10).  precision "mixed": FP32 LOBPCG until the
-    largest change of a Rayleigh quotient between iterations drops below
-    switch_tol, then promotion to FP64 and FP64 LOBPCG."""
+    workload, MPS, D=8, k=10).  form: "fp64" (plain), "fp32", "f64_f32", or
+    "mixed" (FP32-storage LOBPCG until the largest change of a Rayleigh
+    quotient between iterations drops below switch_tol, then promotion and
+    f64_f32 LOBPCG)."""
     import torch
     from paper_2512_15875_amd.solver import LobpcgOpts, MixedEigensolver
 
@@ -116,13 +117,13 @@ def time_to_all_states(api, ctx, precision: str, tol: float = 1e-3, max_iter: in
     gold = json.load(open(os.path.join(ROOT, "tests", "golden", "c1_oracle_runs.json")))
     ref = np.array(gold["exact"]) + gold["zpe"]
     opts = LobpcgOpts(n_iter=max_iter)
-    if precision == "mixed":
+    if form == "mixed":
         model, tree, x0 = make_problem("c1", 10, 8)
-        ms = MixedEigensolver(ctx, tree, model, D=8, k=10, low="fp32")
+        ms = MixedEigensolver(ctx, tree, model, D=8, k=10, low="fp32", hi="f64_f32")
         ms.load_block(x0)
         s = ms.lo
     else:
-        s, model, tree = make_solver(api, ctx, "c1", precision, 10, 8)
+        s, model, tree = make_solver(api, ctx, "c1", form, 10, 8)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.lobpcg_start(opts)
@@ -130,13 +131,34 @@ def time_to_all_states(api, ctx, precision: str, tol: float = 1e-3, max_iter: in
     for it in range(max_iter):
         s.lobpcg_step()
         lam = np.sort(s.lam_d.cpu().numpy() + s.zpe)
-        if np.max(np.abs(lam - ref)) <= tol:
+        if np.max(np.abs(lam - ref)) <= tol and (form != "mixed" or s is ms.hi):
             return it + 1, time.perf_counter() - t0, float(np.max(np.abs(lam - ref)))
-        if precision == "mixed" and s is ms.lo and prev is not None and np.max(np.abs(lam - prev)) < switch_tol:
+        if form == "mixed" and s is ms.lo and prev is not None and np.max(np.abs(lam - prev)) < switch_tol:
             ms.promote()
             s = ms.hi
         prev = lam
     return None
+
+
+def time_to_solution_block(args, api):
+    """Time-to-all-states entries of the bench line: the 6-mode workload
+    against its exact levels, every form; and, unless --no-tts-c3, the
+    12-mode fork-4 workload (k=84, D=40), plain FP64 against the mixed form,
+    both against the plain FP64 run's own iterate --tts-c3-ref (the FP64 GPU
+    path is pinned to the oracle on the small workloads)."""
+    out = {"c1": {"workload": "6-mode coupled oscillators, MPS, D=8, k=10 (exact reference)", "tol_cm-1": 1e-3}}
+    for form in ("fp64", "fp32", "f64_f32", "mixed"):
+        c = api.Context(0, workspace_bytes=1 << 30)
+        hit = time_to_all_states(api, c, form)
+        out["c1"][form] = None if hit is None else {"iters": hit[0], "seconds": round(hit[1], 3),
+                                                    "max_err_cm-1": hit[2]}
+        c.close()
+    if not args.no_tts_c3:
+        a = argparse.Namespace(**vars(args))
+        a.workload, a.k, a.bond, a.ref_iters, a.tts_forms = "c3", 84, 40, args.tts_c3_ref, args.tts_c3_forms
+        a.precision = "fp32"
+        out["c3"] = tts_run(a)
+    return out
 
 
 def learned_experiment(args):
@@ -314,11 +336,17 @@ def ensemble_experiment(args):
 
 
 def tts_experiment(args):
+    print(json.dumps(tts_run(args)), flush=True)
+
+
+def tts_run(args):
     """Time to all states at 1e-3 cm^-1 on a large workload: plain FP64 block
     LOBPCG for ref_iters iterations (its last iterate is the reference), then
-    the mixed form (FP32 iterations until the largest change of a Rayleigh
-    quotient between iterations drops below switch_tol, promotion, FP64
-    iterations) from the same initial block; both timed from solver start."""
+    each form of --tts-forms from the same initial block, timed from solver
+    start.  Forms with an FP32-storage phase run it until the largest change
+    of a Rayleigh quotient between iterations drops below switch_tol, then
+    promote the block to FP64 storage; only iterations after that count as
+    hits."""
     import torch
     from paper_2512_15875_amd import ttn as api
     from paper_2512_15875_amd.solver import LobpcgOpts, MixedEigensolver, TTNEigensolver, build_ttno
@@ -330,6 +358,7 @@ def tts_experiment(args):
     ctx = api.Context(0, workspace_bytes=8 << 30)
     ttno = build_ttno(api.Tree(tree.parent, tree.phys), tree, model)
     log = lambda msg: print(msg, file=sys.stderr, flush=True)
+    log(f"time to all states: {wl_name}, D={D}, k={k}, reference = plain FP64 iterate {args.ref_iters}")
     # plain FP64
     s = TTNEigensolver(ctx, tree, model, D=D, k=k, precision="fp64", ttno=ttno)
     s.load_block(x0)
@@ -355,37 +384,50 @@ def tts_experiment(args):
            "reference": f"plain FP64 LOBPCG iterate {args.ref_iters}",
            "plain_fp64": {"iters": pi, "seconds": pt, "s_per_iter": round(plain[-1][0] / len(plain), 3),
                           "max_err_per_iter": [round(float(np.max(np.abs(t[1] - ref))), 5) for t in plain]}}
-    # mixed, once per arithmetic of the FP64 phase's preconditioner sweeps
-    for pre in args.tts_pre.split(","):
-        hi_pre = {"f64": None, "f64_f32": api.F64_F32}[pre]
-        ms = MixedEigensolver(ctx, tree, model, D=D, k=k, low=args.precision, ttno=ttno, hi_pre_compute=hi_pre)
-        ms.load_block(x0)
+    # the other forms from the same initial block:
+    #   f64_f32      FP64 storage, bulk H contractions on FP32 matrix cores, S~ / Rayleigh quotients / RR in FP64
+    #   mixed        FP32-storage LOBPCG, then promotion and f64_f32 iterations
+    #   mixed_fp64   FP32-storage LOBPCG, then promotion and all-FP64 iterations
+    for form in args.tts_forms.split(","):
+        if form == "f64_f32":
+            lo, hi = None, TTNEigensolver(ctx, tree, model, D=D, k=k, precision="f64_f32", ttno=ttno)
+            hi.load_block(x0)
+        else:
+            hi_kind = {"mixed": "f64_f32", "mixed_fp64": "fp64"}[form]
+            ms = MixedEigensolver(ctx, tree, model, D=D, k=k, low=args.precision, ttno=ttno, hi=hi_kind)
+            ms.load_block(x0)
+            lo, hi = ms.lo, ms.hi
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        cur = ms.lo
+        cur = lo if lo is not None else hi
         cur.lobpcg_start(LobpcgOpts(n_iter=args.ref_iters))
-        mixed, prev, switched = [], None, None
+        traj, prev, switched = [], None, None
         for it in range(args.ref_iters):
             cur.lobpcg_step()
             lam = np.sort(cur.lam_d.cpu().numpy() + cur.zpe)
-            mixed.append((time.perf_counter() - t0, lam, "lo" if cur is ms.lo else "fp64"))
-            log(f"  mixed ({pre} preconditioner) iteration {it + 1} ({mixed[-1][2]}): {mixed[-1][0]:.1f} s, "
-                f"max err {np.max(np.abs(lam - ref)):.4f}")
-            if np.max(np.abs(lam - ref)) <= 1e-3 and cur is ms.hi:
+            traj.append((time.perf_counter() - t0, lam, "lo" if cur is lo else "fp64"))
+            log(f"  {form} iteration {it + 1} ({traj[-1][2]}): {traj[-1][0]:.1f} s, "
+                f"max err {np.max(np.abs(lam - ref)):.5f}")
+            if np.max(np.abs(lam - ref)) <= 1e-3 and cur is hi:
                 break
-            if cur is ms.lo and prev is not None and np.max(np.abs(lam - prev)) < args.switch_tol:
+            if cur is lo and prev is not None and np.max(np.abs(lam - prev)) < args.switch_tol:
                 ms.promote()
-                cur = ms.hi
+                cur = hi
                 switched = it + 1
             prev = lam
-        del ms
-        mi, mt = first_hit(mixed)
-        key = "mixed" if pre == "f64" else f"mixed_pre_{pre}"
-        out[key] = {"low": args.precision, "fp64_phase_preconditioner": pre, "switch_at_iter": switched, "iters": mi,
-                    "seconds": mt, "max_err_per_iter": [round(float(np.max(np.abs(t[1] - ref))), 5) for t in mixed]}
+        del lo, hi
+        if form != "f64_f32":
+            del ms
+        mi, mt = first_hit(traj)
+        out[form] = {"switch_at_iter": switched, "iters": mi, "seconds": mt,
+                     "s_per_iter": round(traj[-1][0] / len(traj), 3),
+                     "max_err_per_iter": [round(float(np.max(np.abs(t[1] - ref))), 5) for t in traj]}
+        if form != "f64_f32":
+            out[form]["low"] = args.precision
         if pt and mt:
-            out["speedup" if pre == "f64" else f"speedup_pre_{pre}"] = round(pt / mt, 3)
-    print(json.dumps(out), flush=True)
+            out[form]["speedup_vs_plain"] = round(pt / mt, 3)
+    ctx.close()
+    return out
 
 
 def ii_experiment(args):
@@ -526,27 +568,143 @@ def gram_probe(args):
     print(json.dumps({"gram_probe": f"c2, D={D}, k={k}, {len(ia)} pairs", "kernels": out}), flush=True)
 
 
-def cpu_baseline(s, k: int, budget_s: float = 12.0):
-    """The FP64 oracle's H_eff apply at the heaviest node, timed on the host."""
+def heff_probe(args):
+    """The headline U1 alone: heff_apply_block with the TTNO at the headline
+    node for k states (random FP32 inputs at the node's exact shapes: the
+    same plan, kernels and grids as the bench step's MINRES products there),
+    repeated --probe-reps times between the markers.  Prints the per-kernel
+    algorithmic flops and bytes per launch, for rocprofv3 counter passes,
+    which take a short program."""
+    import torch
+    from paper_2512_15875_amd import ttn as api
+
+    k = args.k or (50 if args.workload == "c2" else 84)
+    D = args.bond or (24 if args.workload == "c2" else 40)
+    ctx = api.Context(0, workspace_bytes=8 << 30)
+    s, model, tree = make_solver(api, ctx, args.workload, args.precision, k, D)
+    u = headline_nodes(s, args.workload)[0]
+    nb = s.gt.nbrs(u)
+    envs = api.Envs(ctx, s.gt, k, s.bonds, s.M, s.bonds, s.sdt, edges=[api.dslot(s.gt, c, u) for c in nb])
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    for c in nb:
+        e = envs.get(c, u)
+        e.copy_(torch.randn(e.shape, generator=g, device="cuda", dtype=e.dtype))
+    n_loc = int(np.prod(s.B.legdims(u)))
+    X = torch.randn(k, n_loc, generator=g, device="cuda", dtype=s.tdt)
+    Y = torch.empty_like(X)
+    shift = torch.full((k,), -837.0, dtype=torch.float64, device="cuda")
+    call = lambda: api.heff_apply_block(ctx, s.gt, s.op, envs, u, k, X, Y, shift=shift, compute=s.compute)
+    call()  # plan and tables
+    ctx.sync()
+    mark = torch.zeros(MARKER_N, dtype=torch.float64, device="cuda")
+    api.vec_scale(ctx, mark, 1.0, mark)
+    api.probe_heff(ctx, [u])
+    api.profile(ctx, True)
+    for _ in range(args.probe_reps):
+        call()
+    n_calls, fl, ms = api.probe_report(ctx)
+    rep = api.profile_report(ctx)
+    api.profile(ctx, False)
+    api.vec_scale(ctx, mark, 1.0, mark)
+    ctx.sync()
+    roof, by_kernel = stage_roofline(rep, args.precision)
+    kern = {kn: {"launches": d["launches"], "avg_ms": round(d["ms"] / d["launches"], 5),
+                 "algorithmic_flop_per_launch": d["flops"] / d["launches"],
+                 "algorithmic_bytes_per_launch": d["bytes"] / d["launches"],
+                 "tflop_per_s": round(d["flops"] / (d["ms"] * 1e-3) / 1e12, 2),
+                 "stage_shapes_MNK_items": sorted(d["shapes"])} for kn, d in by_kernel.items()}
+    print(json.dumps({"heff_probe": f"{args.workload} node {u}, D={D}, k={k}, {args.precision}, {n_calls} calls",
+                      "tflop_per_s": round(fl / (ms * 1e-3) / 1e12, 2), "ms_per_call": round(ms / n_calls, 4),
+                      "gflop_per_call": round(fl / n_calls / 1e9, 3), "kernels": kern}), flush=True)
+
+
+def trace_summary(path: str, kernel: str):
+    """Summary of a rocprofv3 kernel-trace CSV (kernel_trace.csv of
+    --kernel-trace): per kernel name, dispatch count and mean / median
+    duration, and for `kernel` (a prefix of the name) the same per grid
+    size -- the launches of one contraction stage share a grid."""
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    by = {}
+    for r in rows:
+        name = r.get("Kernel_Name", "")
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3  # us
+        grid = (r.get("Grid_Size_X", r.get("Grid_Size", "")), r.get("Grid_Size_Y", ""), r.get("Grid_Size_Z", ""))
+        by.setdefault(name, []).append((dur, grid))
+    print("| kernel | dispatches | mean us | median us | total ms |")
+    print("|---|---|---|---|---|")
+    for name, v in sorted(by.items(), key=lambda kv: -sum(d for d, _ in kv[1]))[:15]:
+        d = [x for x, _ in v]
+        print(f"| {name[:110]} | {len(d)} | {np.mean(d):.1f} | {np.median(d):.1f} | {sum(d) / 1e3:.1f} |")
+    for name, v in by.items():
+        if not name.startswith(kernel):
+            continue
+        print(f"\n{name}: by grid (X, Y, Z threads)")
+        print("| grid | dispatches | mean us | median us |")
+        print("|---|---|---|---|")
+        grids = {}
+        for dur, grid in v:
+            grids.setdefault(grid, []).append(dur)
+        for grid, d in sorted(grids.items(), key=lambda kv: -len(kv[1])):
+            print(f"| {grid} | {len(d)} | {np.mean(d):.1f} | {np.median(d):.1f} |")
+
+
+def cpu_baseline(api, ctx, s, u: int, k: int, reps: int = 5):
+    """The FP64 oracle timed on the host at the headline node u: U1 = K2
+    (one state's H_eff apply) and U2 = K1 (one pair's environment update
+    u -> parent(u)), each on all the BLAS threads the process has and on one
+    thread, median of `reps` samples.  Inputs are random at the node's exact
+    shapes (bonds, operator bonds); flops are the library's algorithmic counts
+    of the same operations, so the rates compare with the GPU's."""
+    from threadpoolctl import threadpool_limits
+
     from oracle import ttn as ottn
 
     tree = s.wtree
-    u = tree.children(tree.root)[0]
     nb = tree.neighbours(u)
+    v = tree.parent[u]
     rng = np.random.default_rng(7)
     edge = lambda c: u if c == tree.parent[u] else c
-    W = rng.normal(size=tuple(s.M[edge(c)] for c in nb) + (1, 1))
     Db = [s.bonds[edge(c)] for c in nb]
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        X = rng.normal(size=tuple(Db) + (1,))
-        E = {c: rng.normal(size=(Db[i], s.M[edge(c)], Db[i])) for i, c in enumerate(nb)}
-        ottn.heff_apply(tree, u, W, X, E)
-        n += 1
-        if time.perf_counter() - t0 > budget_s or n >= k:
-            break
-    return u, n, time.perf_counter() - t0
+    W = rng.normal(size=tuple(s.M[edge(c)] for c in nb) + (1, 1))
+    X = rng.normal(size=tuple(Db) + (1,))
+    A2 = rng.normal(size=tuple(Db) + (1,))
+    E = {c: rng.normal(size=(Db[i], s.M[edge(c)], Db[i])) for i, c in enumerate(nb)}
+    envs = api.Envs(ctx, s.gt, 1, s.bonds, s.M, s.bonds, s.sdt, edges=[api.dslot(s.gt, c, u) for c in s.gt.nbrs(u)])
+    f_u1 = api.flops_heff(s.gt, s.op, envs, u, 1)
+    f_u2 = api.flops_env(s.gt, s.op, s.B, s.B, u, v)
+    ein2 = {c: E[c] for c in nb if c != v}
+    units = {"U1": (lambda: ottn.heff_apply(tree, u, W, X, E), f_u1),
+             "U2": (lambda: ottn.env_update(tree, u, v, X, W, A2, ein2), f_u2)}
+    all_threads = blas_threads()
+    out = {}
+    for name, (fn, fl) in units.items():
+        for label, nt in (("all", all_threads), ("one", 1)):
+            with threadpool_limits(limits=nt, user_api="blas"):
+                fn()  # warm
+                ts = []
+                for _ in range(reps):
+                    t0 = time.perf_counter()
+                    fn()
+                    ts.append(time.perf_counter() - t0)
+            med = float(np.median(ts))
+            out[f"{name}_{label}"] = {"gflop_per_s": round(fl / med / 1e9, 3), "median_s": round(med, 4),
+                                      "threads": nt, "gflop": round(fl / 1e9, 3)}
+    u1 = out["U1_all"]
+    return {"value": u1["gflop_per_s"], "unit": "GFLOP/s", "cores": all_threads, "kind": "oracle",
+            "sample": f"FP64 NumPy oracle at the headline node {u} (n_loc={int(np.prod(Db))}): U1 = one state's "
+                      f"H_eff apply, U2 = one pair's environment update {u}->{v}; median of {reps} samples each on "
+                      f"{all_threads} BLAS threads and on 1; value = U1 on {all_threads} threads",
+            "affinity_cores": len(os.sched_getaffinity(0)), "blas": blas_vendor(), **out}
+
+
+def blas_vendor():
+    try:
+        from threadpoolctl import threadpool_info
+        return ",".join(sorted({f"{i.get('internal_api')}" for i in threadpool_info() if i.get("user_api") == "blas"}))
+    except Exception:
+        return "unknown"
 
 
 def blas_threads():
@@ -569,6 +727,9 @@ def main():
     ap.add_argument("--bond", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tts", action="store_true")
+    ap.add_argument("--no-tts-c3", action="store_true", help="skip the 12-mode time-to-all-states comparison")
+    ap.add_argument("--tts-c3-ref", type=int, default=34)
+    ap.add_argument("--tts-c3-forms", default="mixed")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run the copy kernel used to scale counters")
     ap.add_argument("--workspace-gb", type=float, default=8.0,
                     help="library workspace of the bench step (stage intermediates; bounds the items per launch)")
@@ -611,15 +772,21 @@ def main():
                          "deterministic, so that profiles of the same command agree)")
     ap.add_argument("--graphs", action="store_true", help="replay the sweeps as HIP graphs (own stream)")
     ap.add_argument("--switch-tol", type=float, default=0.05)
-    ap.add_argument("--tts-pre", default="f64",
-                    help="arithmetic of the mixed form's FP64-phase preconditioner sweeps: f64, f64_f32 "
-                         "(FP32 matrix cores on the FP64 tensors), or both comma-separated")
+    ap.add_argument("--tts-forms", default="f64_f32,mixed,mixed_fp64",
+                    help="forms compared with plain FP64 in --tts: f64_f32, mixed (FP32 storage, then f64_f32), "
+                         "mixed_fp64 (FP32 storage, then all-FP64)")
     ap.add_argument("--gemm-hash", action="store_true", help="print the GEMM source hash and exit")
+    ap.add_argument("--heff-probe", action="store_true", help="run only the headline heff_apply_block calls")
+    ap.add_argument("--trace-summary", default=None, help="summarise a rocprofv3 kernel_trace.csv and exit")
+    ap.add_argument("--trace-kernel", default="ogemm_kernel", help="kernel-name prefix broken down by grid")
     args = ap.parse_args()
     if args.graphs and args.warmup < 2:
         args.warmup = 2  # first step runs eagerly, the second captures: keep both untimed
     if args.gemm_hash:
         print(gemm_source_hash())
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.trace_kernel)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path, so --gpus must be 1",
@@ -630,6 +797,9 @@ def main():
         return
     if args.gram_probe:
         gram_probe(args)
+        return
+    if args.heff_probe:
+        heff_probe(args)
         return
     if args.ienv_probe:
         ienv_probe(args)
@@ -666,6 +836,44 @@ def main():
         run_bench(args, api, k, D, None)
 
 
+def headline_nodes(s, workload: str):
+    """The node class the metric is quoted on: the level-1 nodes of the binary
+    tree (children of the root), or backbone node b2 (the root) of the fork-4
+    comb."""
+    return list(s.gt.children[s.root]) if workload == "c2" else [s.root]
+
+
+def stage_roofline(rep, precision):
+    """Roofline object of the kernel with the largest time among stage
+    records `rep` (algorithmic flops and bytes per launch over its average
+    launch duration, both from HIP events on the library stream)."""
+    by_kernel = {}
+    for key, st, kern, cnt, tms, fl, Mm, Nn, Kk, nz, by in rep:
+        a = by_kernel.setdefault(kern, {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0, "shapes": set()})
+        a["launches"] += cnt
+        a["ms"] += tms
+        a["flops"] += fl
+        a["bytes"] += by
+        a["shapes"].add((Mm, Nn, Kk, nz // max(cnt, 1)))
+    kern, d = max(by_kernel.items(), key=lambda kv: kv[1]["ms"])
+    tot = sum(v["ms"] for v in by_kernel.values())
+    peak_tf = PEAK[precision]
+    ridge = peak_tf * 1e12 / (HBM_TBS * 1e12)
+    if d["flops"] / max(d["bytes"], 1.0) >= ridge:
+        roof = {"bound": "mfma", "achieved": round(d["flops"] / (d["ms"] * 1e-3) / 1e12, 3), "peak": peak_tf,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": round(d["bytes"] / (d["ms"] * 1e-3) / 1e9, 1), "peak": HBM_TBS * 1e3,
+                "unit": "GB/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof.update({"kernel": kern, "launches": d["launches"], "avg_ms": round(d["ms"] / d["launches"], 5),
+                 "algorithmic_flop_per_launch": d["flops"] / d["launches"],
+                 "algorithmic_bytes_per_launch": d["bytes"] / d["launches"],
+                 "stage_shapes_MNK_items": sorted(d["shapes"]),
+                 "share_of_time": round(d["ms"] / tot, 3)})
+    return roof, by_kernel
+
+
 def run_bench(args, api, k, D, stream):
     import torch
     from paper_2512_15875_amd.solver import LobpcgOpts
@@ -674,13 +882,25 @@ def run_bench(args, api, k, D, stream):
     api.autotune(ctx, args.autotune)
     s, model, tree = make_solver(api, ctx, args.workload, args.precision, k, D)
     s.graphs = args.graphs
-    s.lobpcg_start(LobpcgOpts(n_iter=args.warmup + args.steps + 1))
-    print(f"setup done: {tree.n} nodes, k={k}, D={D}, precision={args.precision}", file=sys.stderr, flush=True)
+    s.lobpcg_start(LobpcgOpts(n_iter=args.warmup + args.steps + 2))
+    hn = headline_nodes(s, args.workload)
+    print(f"setup done: {tree.n} nodes, k={k}, D={D}, precision={args.precision}, headline nodes {hn}",
+          file=sys.stderr, flush=True)
     for i in range(args.warmup):
         s.lobpcg_step()
         print(f"warmup step {i} done", file=sys.stderr, flush=True)
     ctx.sync()
     torch.cuda.synchronize()
+    # Timed region: K whole LOBPCG iterations.  Every heff_apply_block call with
+    # the operator at the headline nodes is bracketed by HIP events (the whole
+    # call), and the stages of those calls by per-launch events; nothing else
+    # is profiled.  Marker launches (vec_scale on MARKER_N doubles) bracket the
+    # region for trace summaries.
+    mark = torch.zeros(MARKER_N, dtype=torch.float64, device="cuda")
+    api.vec_scale(ctx, mark, 1.0, mark)
+    api.probe_heff(ctx, hn)
+    api.profile_filter(ctx, [f"heff:{u}:1" for u in hn])
+    api.profile(ctx, True)
     api.ctx_flops(ctx, reset=True)
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -690,14 +910,30 @@ def run_bench(args, api, k, D, stream):
     ctx.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    api.vec_scale(ctx, mark, 1.0, mark)
     flops = api.ctx_flops(ctx)
+    n_calls, call_fl, call_ms = api.probe_report(ctx)
+    rep_u1 = api.profile_report(ctx)
+    api.profile(ctx, False)
+    api.profile_filter(ctx, [])
+    api.probe_heff(ctx, [])
     ms = (t1 - t0) * 1e3 / args.steps
-    value = flops / (t1 - t0) / 1e9
+    value = call_fl / (call_ms * 1e-3) / 1e9
+    roof, u1_kernels = stage_roofline(rep_u1, args.precision)
+    stage_ms = sum(v["ms"] for v in u1_kernels.values())
+    tr = measured_traffic(roof["kernel"])
+    roof["traffic"] = None if tr is None else round(tr[0], 0)
+    if tr is not None:
+        roof["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+        roof["traffic_over_algorithmic_bytes"] = round(tr[0] / tr[1], 3)
+    for kern, d in sorted(u1_kernels.items(), key=lambda kv: -kv[1]["ms"]):
+        print(f"  U1 kernel {kern}: {d['launches']} launches {d['ms']:.1f} ms "
+              f"{d['flops'] / (d['ms'] * 1e-3) / 1e12:.1f} TFLOP/s shapes {sorted(d['shapes'])}", file=sys.stderr)
+    print(f"headline H_eff applies: {n_calls} calls, {call_ms:.1f} ms ({stage_ms:.1f} ms in stages), "
+          f"{value / 1e3:.1f} TFLOP/s", file=sys.stderr, flush=True)
 
-    # per-kernel totals of one more step, timed with HIP events on the library stream;
-    # the step is bracketed by two copies of MARKER_N doubles (a launch of a
-    # distinct grid size) so that counter and trace summaries can select it
-    mark = torch.zeros(MARKER_N, dtype=torch.float64, device="cuda")
+    # one more step with every stage profiled (outside the timed region): the
+    # step's kernel mix, its dominant kernel and all H_eff applies
     api.vec_scale(ctx, mark, 1.0, mark)
     api.profile(ctx, True)
     s.lobpcg_step()
@@ -705,66 +941,24 @@ def run_bench(args, api, k, D, stream):
     api.profile(ctx, False)
     api.vec_scale(ctx, mark, 1.0, mark)
     ctx.sync()
-    by_kernel = {}
-    for key, st, kern, cnt, tms, fl, Mm, Nn, Kk, nz, by in rep:
-        a = by_kernel.setdefault(kern, [0, 0.0, 0.0, 0.0])
-        a[0] += cnt
-        a[1] += tms
-        a[2] += fl
-        a[3] += by
-    for r in sorted(rep, key=lambda r: -r[4])[:12]:
-        key, st, kern, cnt, tms, fl, Mm, Nn, Kk, nz, by = r
-        print(f"  stage {key}#{st} {kern} M={Mm} N={Nn} K={Kk} items={nz} launches={cnt}: {tms:.1f} ms, "
-              f"{fl / tms / 1e9:.1f} TFLOP/s, {by / tms / 1e6:.0f} GB/s", file=sys.stderr)
-    for kern, (cnt, tms, fl, by) in sorted(by_kernel.items(), key=lambda kv: -kv[1][1])[:8]:
-        print(f"  kernel {kern}: {cnt} launches {tms:.1f} ms {fl / tms / 1e9:.1f} TFLOP/s "
-              f"{by / tms / 1e6:.0f} GB/s intensity {fl / max(by, 1):.1f} flop/B", file=sys.stderr)
-    dkern, (dcnt, dms, dfl, dby) = max(by_kernel.items(), key=lambda kv: kv[1][1])
-    tot_ms = sum(v[1] for v in by_kernel.values())
-    # the H_eff block applies of the step (every heff_apply_block with the TTNO:
-    # the ALS preconditioner's MINRES products), grouped per call shape
-    heff = {}
-    for key, st, kern, cnt, tms, fl, Mm, Nn, Kk, nz, by in rep:
+    step_roof, by_kernel = stage_roofline(rep, args.precision)
+    tot_ms = sum(v["ms"] for v in by_kernel.values())
+    for kern, d in sorted(by_kernel.items(), key=lambda kv: -kv[1]["ms"])[:8]:
+        print(f"  step kernel {kern}: {d['launches']} launches {d['ms']:.1f} ms "
+              f"{d['flops'] / (d['ms'] * 1e-3) / 1e12:.1f} TFLOP/s {d['bytes'] / (d['ms'] * 1e-3) / 1e9:.0f} GB/s",
+              file=sys.stderr)
+    heff_fl = heff_ms = 0.0
+    for key, st, kern, cnt, tms, fl, *_r in rep:
         parts = key.split(":")
         if parts[0] == "heff" and parts[2] == "1":
-            a = heff.setdefault(parts[1], [0.0, 0.0])
-            a[0] += fl
-            a[1] += tms
-    heff_fl = sum(v[0] for v in heff.values())
-    heff_ms = sum(v[1] for v in heff.values())
-    heavy_u, (hfl, hms) = max(heff.items(), key=lambda kv: kv[1][0]) if heff else ("-", (0.0, 1.0))
-    heff_line = {"tflop_per_s": round(heff_fl / (heff_ms * 1e-3) / 1e12, 2) if heff_ms else None,
-                 "frac_of_peak": round(heff_fl / (heff_ms * 1e-3) / 1e12 / PEAK[args.precision], 4) if heff_ms else None,
-                 "ms_in_step": round(heff_ms, 1), "share_of_contraction_time": round(heff_ms / tot_ms, 3),
-                 "heaviest_node": {"node": heavy_u, "tflop_per_s": round(hfl / (hms * 1e-3) / 1e12, 2),
-                                   "frac_of_peak": round(hfl / (hms * 1e-3) / 1e12 / PEAK[args.precision], 4)}}
+            heff_fl += fl
+            heff_ms += tms
     peak_tf = PEAK[args.precision]
-    ridge = peak_tf * 1e12 / (HBM_TBS * 1e12)
-    if dfl / max(dby, 1.0) >= ridge:
-        roof = {"bound": "mfma", "achieved": round(dfl / (dms * 1e-3) / 1e12, 3), "peak": peak_tf,
-                "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "hbm", "achieved": round(dby / (dms * 1e-3) / 1e9, 1), "peak": HBM_TBS * 1e3,
-                "unit": "GB/s"}
-    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    tr = measured_traffic(dkern)
-    # the counters cover this kernel's Gram launches (rocprofv3 cannot count a
-    # whole step here): their measured / compulsory ratio applied to this
-    # step's compulsory bytes per launch
-    roof["traffic"] = None if tr is None else round(tr[0] / tr[1] * dby / dcnt, 0)
-    if tr is not None:
-        roof["traffic_unit"] = "bytes per launch"
-        roof["traffic_over_compulsory"] = round(tr[0] / tr[1], 3)
-        roof["traffic_source"] = "profiles/gram_c2_fp32_hbm_counters.md (Gram launches of this kernel)"
-    roof.update({"kernel": dkern, "launches": dcnt, "avg_ms": round(dms / dcnt, 5),
-                 "algorithmic_flop_per_launch": dfl / dcnt, "algorithmic_bytes_per_launch": dby / dcnt,
-                 "share_of_contraction_time": round(dms / tot_ms, 3)})
-    print(f"dominant kernel {dkern}: {dcnt} launches, {dms:.1f} ms total ({dms / dcnt:.4f} ms avg); all "
-          f"contraction stages {tot_ms:.1f} ms", file=sys.stderr, flush=True)
 
     workload_name = ("64-mode coupled oscillators + 200 cubic terms, binary leaf-only tree (127 nodes)"
                      if args.workload == "c2" else
                      "12-mode synthetic quartic force field (108 cubic + 191 quartic), fork-4 comb (16 nodes)")
+    node_name = "level-1 nodes (24^3, operator bonds 63/42/36)" if args.workload == "c2" else "backbone node b2"
     out = {
         "metric": "H_eff block-apply GFLOP/s (% MFMA peak); time-to-all-states at 1e-3 cm^-1 vs plain",
         "value": round(value, 2),
@@ -778,34 +972,30 @@ def run_bench(args, api, k, D, stream):
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"{workload_name}, D={D}, k={k}: one block-LOBPCG iteration (residual fit, ALS "
-                               f"preconditioner 2 sweeps x MINRES<=10, 3k-subspace Gram + Rayleigh-Ritz, fitted "
-                               f"recombination)",
-                   "precision": args.precision, "gflop_per_step": round(flops / args.steps / 1e9, 2),
-                   "autotune": bool(args.autotune), "graphs": bool(args.graphs)},
+        "config": {"workload": f"{workload_name}, D={D}, k={k}: heff_apply_block with the TTNO at the {node_name}, "
+                               f"k={k} states per call, as issued inside K timed block-LOBPCG iterations (residual "
+                               f"fit, ALS preconditioner 2 sweeps x MINRES<=10, 3k-subspace Gram + Rayleigh-Ritz, "
+                               f"fitted recombination)",
+                   "precision": args.precision, "autotune": bool(args.autotune), "graphs": bool(args.graphs)},
+        "frac_of_peak": round(value / 1e3 / peak_tf, 4),
+        "heff_headline": {"calls": n_calls, "call_ms": round(call_ms, 2), "stage_ms": round(stage_ms, 2),
+                          "algorithmic_gflop": round(call_fl / 1e9, 2), "nodes": hn,
+                          "gflop_per_call": round(call_fl / max(n_calls, 1) / 1e9, 3)},
+        "step_rate": {"gflop_per_s": round(flops / (t1 - t0) / 1e9, 2),
+                      "gflop_per_step": round(flops / args.steps / 1e9, 2)},
         "roofline": roof,
-        "heff_apply_block": heff_line,
+        "step_profile": {"note": "one extra profiled step after the timed region",
+                         "dominant_kernel": step_roof,
+                         "heff_all_nodes_tflop_per_s": round(heff_fl / (heff_ms * 1e-3) / 1e12, 2) if heff_ms else None,
+                         "heff_all_nodes_frac_of_peak": round(heff_fl / (heff_ms * 1e-3) / 1e12 / peak_tf, 4)
+                         if heff_ms else None,
+                         "dispatches": int(sum(v["launches"] for v in by_kernel.values())),
+                         "contraction_ms": round(tot_ms, 1)},
     }
     if not args.no_tts:
-        tts = {}
-        for prec in ("fp64", "fp32", "mixed"):
-            c2 = api.Context(0, workspace_bytes=1 << 30)
-            hit = time_to_all_states(api, c2, prec)
-            tts[prec] = None if hit is None else {"iters": hit[0], "seconds": round(hit[1], 3),
-                                                  "max_err_cm-1": hit[2]}
-            c2.close()
-        out["time_to_all_states"] = {"workload": "6-mode coupled oscillators, MPS, D=8, k=10 (exact reference)",
-                                     "tol_cm-1": 1e-3, **tts}
+        out["time_to_all_states"] = time_to_solution_block(args, api)
     if not args.no_cpu_baseline:
-        u, n, dt = cpu_baseline(s, k)
-        # flops of one state's H_eff apply at node u (library count)
-        envs = api.Envs(ctx, s.gt, 1, s.bonds, s.M, s.bonds, s.sdt,
-                        edges=[api.dslot(s.gt, c, u) for c in s.gt.nbrs(u)])
-        f1 = api.flops_heff(s.gt, s.op, envs, u, 1)
-        out["cpu_baseline"] = {"value": round(f1 * n / dt / 1e9, 3), "unit": "GFLOP/s", "cores": blas_threads(),
-                               "kind": "oracle",
-                               "sample": f"FP64 NumPy H_eff apply at the level-1 node (n_loc="
-                                         f"{int(np.prod(s.B.legdims(u)))}), {n} states in {dt:.1f} s"}
+        out["cpu_baseline"] = cpu_baseline(api, ctx, s, hn[0], k)
     print(json.dumps(out), flush=True)
 
 
