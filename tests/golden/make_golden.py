@@ -82,8 +82,61 @@ def c3_cluster_runs(seed=7, D=8, k=12):
     }
 
 
+def topology_runs(D=4, k=4, n_iter=2):
+    """The 12-mode quartic force field (seed 3) on every topology of the
+    paper's comparison (Appendix B), two oracle LOBPCG iterations at a small
+    bond dimension: Rayleigh quotients and residual norms per iteration."""
+    m = wl.make_config_model("c3")
+    out = {"cite": f"oracle block LOBPCG (Alg. lobpcg_block), {n_iter} iterations, quartic force field seed 3 on "
+                   f"the topologies of Appendix B, D={D}, k={k}; shifted frame",
+           "D": D, "k": k, "zpe": m.zpe_harmonic, "runs": {}}
+    for name in ("mps", "ttree", "leafonly", "fork3", "fork4", "fork6", "t3ns"):
+        tree = wl.paper_topology(name, m.dims)
+        W = ttno.build_ttno(tree, m)
+        bonds = wl.bond_dims(tree, D)
+        x0 = wl.initial_block(tree, bonds, m.omega, m.dims, k, m.seed + 17)
+        lam0 = solvers.rayleigh_quotients(tree, W, [solvers.normalized(tree, x) for x in x0])
+        shift = float(np.min(lam0)) - 837.0
+        hist = []
+        xs, lam = solvers.lobpcg(tree, W, x0, solvers.LobpcgOptions(n_iter=n_iter, shift=shift), hist)
+        out["runs"][name] = {"shift": shift, "lam_history": [list(map(float, h["lam"])) for h in hist],
+                             "resid_history": [list(map(float, h["resid"])) for h in hist],
+                             "lam_final": list(map(float, lam))}
+        print(name, "done", flush=True)
+    return out
+
+
+def e1_runs(D=5, k=8, n_iter=2, n_exact=30):
+    """The paper's 64-mode bilinearly coupled oscillators (Sec. III.A,
+    Eq. coupled_harmonic_oscillator: omega_j = sqrt(j/2), alpha = 0.1 for every
+    pair), 8 harmonic-oscillator functions per mode, on the MPS and the T
+    tree of Appendix B (arms of 22, 22 and 20 modes): two oracle LOBPCG
+    iterations at D=5 for k=8 states, and the 30 lowest levels of the normal-mode
+    closed form.  Preconditioner shift: lowest initial Rayleigh quotient - 1
+    (the model's frequencies are of order 1)."""
+    m = wl.paper_64d_model()
+    out = {"cite": f"paper's 64-mode model (Sec. III.A), FBR d=8, oracle block LOBPCG {n_iter} iterations, D={D}, "
+                   f"k={k}, MPS and T tree; normal-mode levels (shifted frame)",
+           "D": D, "k": k, "zpe": m.zpe_harmonic, "exact": list(map(float, exact.normal_mode_levels(m, n_exact))),
+           "runs": {}}
+    for name in ("mps", "ttree"):
+        tree = wl.paper_topology(name, m.dims)
+        W = ttno.build_ttno(tree, m)
+        bonds = wl.bond_dims(tree, D)
+        x0 = wl.initial_block(tree, bonds, m.omega, m.dims, k, 117)
+        lam0 = solvers.rayleigh_quotients(tree, W, [solvers.normalized(tree, x) for x in x0])
+        shift = float(np.min(lam0)) - 1.0
+        hist = []
+        xs, lam = solvers.lobpcg(tree, W, x0, solvers.LobpcgOptions(n_iter=n_iter, shift=shift), hist)
+        out["runs"][name] = {"shift": shift, "lam_history": [list(map(float, h["lam"])) for h in hist],
+                             "resid_history": [list(map(float, h["resid"])) for h in hist],
+                             "lam_final": list(map(float, lam)), "ttno_max_bond": int(max(ttno.ttno_bonds(tree, W)))}
+        print(name, "done", flush=True)
+    return out
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["c1", "c3_cluster"]
+    which = sys.argv[1:] or ["c1", "c3_cluster", "topologies", "e1"]
     if "c1" in which:
         res = c1_runs()
         with open(os.path.join(HERE, "c1_oracle_runs.json"), "w") as f:
@@ -94,3 +147,13 @@ if __name__ == "__main__":
         with open(os.path.join(HERE, "c3s7_cluster_oracle_runs.json"), "w") as f:
             json.dump(res, f, indent=1)
         print("wrote c3s7_cluster_oracle_runs.json")
+    if "topologies" in which:
+        res = topology_runs()
+        with open(os.path.join(HERE, "topology_oracle_runs.json"), "w") as f:
+            json.dump(res, f, indent=1)
+        print("wrote topology_oracle_runs.json")
+    if "e1" in which:
+        res = e1_runs()
+        with open(os.path.join(HERE, "e1_oracle_runs.json"), "w") as f:
+            json.dump(res, f, indent=1)
+        print("wrote e1_oracle_runs.json")

@@ -80,3 +80,31 @@ def test_sop_build_rejects_bad_input():
         ttn.sop_build(gt, [0, 1], [1.0, 2.0], [3, 3], [((5, 1),)], [1.0])
     with pytest.raises(ttn.TTNError):  # physical dim differs from the basis size
         ttn.sop_build(gt, [0, 1], [1.0, 2.0], [3, 4], [], [])
+
+
+TOPOLOGIES = ["mps", "ttree", "leafonly", "fork3", "fork4", "fork6", "t3ns"]
+
+
+@pytest.mark.parametrize("name", TOPOLOGIES)
+def test_paper_topologies_operator_on_tiny_basis(name):
+    """Every topology of the paper's 12-mode comparison (Appendix B): a valid
+    tree carrying each mode once, and both TTNO constructions -- the oracle's
+    automaton with SVD compression and the library's host compiler -- act as
+    the Kronecker sum of products (12 modes, 2 basis functions each, a
+    4096-dimensional space) on 8 random vectors, with the same operator
+    bonds."""
+    from paper_2512_15875_amd import ttn
+    m = wl.quartic_force_field(12, 3, 20, 25)
+    m.dims = [2] * 12
+    tree = wl.paper_topology(name, m.dims)
+    assert sorted(x for x in tree.mode if x >= 0) == list(range(12))
+    assert all((tree.mode[u] < 0) == (tree.phys[u] == 1) for u in range(tree.n))
+    assert max(len(tree.neighbours(u)) for u in range(tree.n)) <= 3
+    V = np.random.default_rng(4).normal(size=(4096, 8))
+    HV = np.stack([exact.sop_apply_dense(m, V[:, i]) for i in range(8)], axis=1)
+    Wo = ttno.build_ttno(tree, m)
+    assert np.abs(ttno.ttno_to_dense(tree, Wo) @ V - HV).max() <= 1e-11 * np.abs(HV).max()
+    gt = ttn.Tree(tree.parent, tree.phys)
+    W, M = ttn.sop_build(gt, tree.mode, m.omega, m.dims, m.monomials, m.coefs)
+    assert np.abs(ttno.ttno_to_dense(tree, W) @ V - HV).max() <= 1e-11 * np.abs(HV).max()
+    assert M == ttno.ttno_bonds(tree, Wo)
