@@ -193,7 +193,30 @@ ttn_status exec_plan(ttn_ctx* ctx, Plan& P, int ct, const std::vector<OpAddr>& i
     chunk = std::min<int64_t>(chunk, nb);
   }
   char* ws = (char*)ctx->ws + ws_off_bytes;
-  ctx->flops_done += P.flops_per_item * nb + P.flops_shared;
+  // stages whose operands do not depend on input 0 (X of an H_eff product)
+  std::vector<char> dep_x((size_t)P.n_in + P.steps.size(), 0);
+  dep_x[0] = 1;
+  {
+    int nid = P.n_in;
+    for (const Step& st : P.steps)
+      if (st.out >= 0) dep_x[nid++] = dep_x[st.a] || dep_x[st.b];
+  }
+  auto step_dep_x = [&](const Step& st) { return dep_x[st.a] || dep_x[st.b]; };
+  std::vector<const void*> in_bases;
+  for (const OpAddr& o : inputs) in_bases.push_back(o.base);
+  in_bases.push_back(out.base);
+  // every X-independent intermediate of this plan is still in the workspace
+  // (same plan, same inputs, same single chunk, nothing else ran since)
+  const bool reuse = ctx->reuse_free && chunk >= nb && ctx->ws_last_plan == (const void*)&P &&
+                     ctx->ws_last_nb == nb && ctx->ws_last_base == (const void*)ws &&
+                     ctx->ws_last_inputs.size() == in_bases.size() &&
+                     std::equal(in_bases.begin() + 1, in_bases.end() - 1, ctx->ws_last_inputs.begin() + 1);
+  ctx->ws_last_plan = nullptr;  // the workspace is about to change
+  double skipped = 0;
+  if (reuse)
+    for (const Step& st : P.steps)
+      if (st.out >= 0 && !step_dep_x(st)) skipped += st.batched ? st.flops * nb : st.flops;
+  ctx->flops_done += P.flops_per_item * nb + P.flops_shared - skipped;
   // shared intermediates are computed once (first chunk) and kept
   bool shared_done = false;
   for (int z0 = 0; z0 < nb; z0 += (int)chunk) {
@@ -226,6 +249,7 @@ ttn_status exec_plan(ttn_ctx* ctx, Plan& P, int ct, const std::vector<OpAddr>& i
     for (size_t s = 0; s < P.steps.size(); ++s) {
       const Step& st = P.steps[s];
       if (!st.batched && shared_done) continue;
+      if (reuse && st.out >= 0 && !step_dep_x(st)) continue;  // still in the workspace
       const OpAddr A = addr(st.a), B = addr(st.b);
       const bool last = st.out < 0;
       OpAddr C = last ? out : addr(st.out);
@@ -265,6 +289,12 @@ ttn_status exec_plan(ttn_ctx* ctx, Plan& P, int ct, const std::vector<OpAddr>& i
       if (rec) (void)hipEventRecord(rec->b, ctx->stream);
     }
     shared_done = true;
+  }
+  if (chunk >= nb) {
+    ctx->ws_last_plan = (const void*)&P;
+    ctx->ws_last_nb = nb;
+    ctx->ws_last_base = (const void*)ws;
+    ctx->ws_last_inputs = in_bases;
   }
   return TTN_OK;
 }
@@ -807,6 +837,7 @@ ttn_status ttno_env_close(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, c
   const size_t scratch_bytes = (size_t)se * n_pairs * esize(ct);
   const size_t off = (scratch_bytes + 255) / 256 * 256;
   if (off >= ctx->ws_bytes) return fail(ctx, TTN_E_WORKSPACE, "workspace too small for closure scratch");
+  ctx->ws_last_plan = nullptr;
   scratch.slot[ttn_envs::dslot(t, u, v)] = ctx->ws;  // scratch at the start of the workspace
   Net net;
   std::string why;
@@ -950,6 +981,7 @@ ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, 
       dd.E[i] = envs->slot[ttn_envs::dslot(t, c, u)];
       dd.Estride[i] = envs->slot_elems(c, u);
     }
+    ctx->ws_last_plan = nullptr;
     hipError_t he = launch_diag_gather(cd, dd, ctx->ws, ed_off.data(), k, ctx->stream);
     if (he != hipSuccess) return fail(ctx, TTN_E_LAUNCH, hipGetErrorString(he));
     Net net;

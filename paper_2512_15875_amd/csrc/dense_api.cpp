@@ -81,6 +81,7 @@ ttn_status rayleigh_ritz(ttn_ctx* ctx, int32_t batch, const int32_t* m, int32_t 
   if (batch == 0) return TTN_OK;
   const size_t need = (size_t)batch * 4 * ld * ld * sizeof(double) + 256 + (size_t)batch * sizeof(int32_t);
   if (need > ctx->ws_bytes) return api_fail(ctx, TTN_E_WORKSPACE, "workspace too small for Rayleigh-Ritz");
+  ctx->ws_last_plan = nullptr;
   int32_t* d_m = (int32_t*)ctx->ws;
   double* scratch = (double*)((char*)ctx->ws + 256 + (((size_t)batch * sizeof(int32_t) + 255) / 256) * 256);
   if (hipMemcpyAsync(d_m, m, (size_t)batch * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
@@ -117,6 +118,7 @@ ttn_status ttn_block_move_centre(ttn_ctx* ctx, ttn_block* b, int32_t u, int32_t 
   const size_t ybytes = (size_t)k * b->size[v] * es;
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   if (al(work) + al(rbytes) + al(ybytes) > ctx->ws_bytes) return api_fail(ctx, TTN_E_WORKSPACE, "workspace too small for QR");
+  ctx->ws_last_plan = nullptr;
   double* wk = (double*)ctx->ws;
   double* R = (double*)((char*)ctx->ws + al(work));
   void* Y = (char*)ctx->ws + al(work) + al(rbytes);

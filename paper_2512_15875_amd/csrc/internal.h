@@ -323,6 +323,14 @@ struct ttn_ctx {
   // while non-null, every contraction-stage kernel first reads this device
   // word and returns at once when it is zero (the MINRES convergence gate)
   const int32_t* gate = nullptr;
+  // reuse of X-independent intermediates across the H_eff applies of one
+  // MINRES solve: requested by the MINRES loop (reuse_free), honoured when
+  // the same plan with the same inputs ran last on the workspace in one chunk
+  bool reuse_free = false;
+  const void* ws_last_plan = nullptr;
+  std::vector<const void*> ws_last_inputs;
+  const void* ws_last_base = nullptr;
+  int ws_last_nb = -1;
   // this device's copy of the static scratch array of heff_apply_block_noalloc
   // (looked up at creation; null if the lookup failed)
   void* scratch = nullptr;

@@ -116,6 +116,7 @@ ttn_status ttn_mlp_forward(ttn_ctx* ctx, const float* params, int32_t n, const f
   float* A = acts;
   if (!A) {
     if ((size_t)n * 4 * HID * 4 > ctx->ws_bytes) return api_fail(ctx, TTN_E_WORKSPACE, "workspace too small for MLP");
+    ctx->ws_last_plan = nullptr;
     A = (float*)ctx->ws;
   }
   float *pre1 = A, *post1 = A + (int64_t)n * HID, *pre2 = A + 2 * (int64_t)n * HID, *post2 = A + 3 * (int64_t)n * HID;
@@ -139,6 +140,7 @@ ttn_status ttn_mlp_backward(ttn_ctx* ctx, const float* params, int32_t n, const 
   if ((size_t)n * 2 * HID * 4 > ctx->ws_bytes) return api_fail(ctx, TTN_E_WORKSPACE, "workspace too small for MLP");
   const float *pre1 = acts, *post1 = acts + (int64_t)n * HID, *pre2 = acts + 2 * (int64_t)n * HID,
               *post2 = acts + 3 * (int64_t)n * HID;
+  ctx->ws_last_plan = nullptr;
   float* d2 = (float*)ctx->ws;
   float* d1 = d2 + (int64_t)n * HID;
   // layer 3

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <sstream>
@@ -210,6 +211,7 @@ ttn_status learned_step(ttn_sweep* sw, int u, const ttn_solve_opts* opts, void* 
   const int64_t cap_rows = std::min<int64_t>((int64_t)(ctx->ws_bytes / row_bytes), INT32_MAX / 1024);
   if (cap_rows < ntiles) return api_fail(ctx, TTN_E_WORKSPACE, "workspace too small for the learned preconditioner");
   const int g = (int)std::max<int64_t>(1, std::min<int64_t>(k, cap_rows / ntiles));
+  ctx->ws_last_plan = nullptr;
   float* acts = (float*)ctx->ws;
   for (int z0 = 0; z0 < k; z0 += g) {
     const int gz = std::min(g, k - z0);
@@ -605,13 +607,23 @@ ttn_status sweep_step(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, int32_t next, c
         bool stop = false;
         struct GateGuard {
           ttn_ctx* c;
-          ~GateGuard() { c->gate = nullptr; }
+          ~GateGuard() {
+            c->gate = nullptr;
+            c->reuse_free = false;
+          }
         } guard{ctx};
+        const char* re = getenv("TTN_REUSE_FREE");
+        const bool reuse_on = !(re && re[0] == '0');
         for (int it = 0; it < opts->maxiter && !stop; ++it) {
+          // the environments are fixed during the solve: from the second
+          // product on, the stages that do not involve the Krylov vector (the
+          // operator-environment partials) are reused from the workspace
           ctx->gate = sw->d_active;
+          ctx->reuse_free = reuse_on && it > 0;
           ttn_status rr = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, vv, k,
                                            p, TTN_HEFF_APPLY, comp);
           ctx->gate = nullptr;
+          ctx->reuse_free = false;
           if (rr != TTN_OK) return rr;
           e = launch_minres_step(ct, x, vv, vvp, p, dp, dpp, n, k, sw->st, ctx->stream);
           if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));

@@ -160,3 +160,36 @@ def test_fit_sweep_matches_oracle(api, ctx):
     for j in range(k):
         for u in range(tree.n):
             assert rel_err(Y.t[u][j].cpu().numpy(), refs[j][u]) < 1e-9, (j, u)
+
+
+def test_minres_reuses_operator_partials(api, ctx, monkeypatch):
+    """Within one local MINRES solve the environments are fixed, so the H_eff
+    stages that do not involve the Krylov vector are computed on the first
+    product only (TTN_REUSE_FREE=0 switches that off): the same states bit for
+    bit, fewer algorithmic flops, and the oracle's ALS as before."""
+    k = 3
+    m, tree, W, M, bonds, gt, op, phi = _setup(api, ctx, k=k)
+    y0 = [ottn.canonicalize(tree, p, tree.root) for p in phi]
+    shifts = [-200.0, 50.0, 900.0]
+    res, flops = {}, {}
+    for flag in ("0", "1"):
+        monkeypatch.setenv("TTN_REUSE_FREE", flag)
+        Y = _upload(api, ctx, gt, tree, bonds, y0, k)
+        P = _upload(api, ctx, gt, tree, bonds, phi, k)
+        sw = api.Sweep(ctx, gt, op, Y, [(None, P, list(range(k)), list(range(k)), None)],
+                       shift=to_dev(np.array(shifts)), compute=api.F64)
+        sw.init(tree.root)
+        ctx.sync()
+        api.ctx_flops(ctx, reset=True)
+        api.run_sweep(sw, gt, api.SOLVE_MINRES, maxiter=12, rtol=0.0)
+        ctx.sync()
+        flops[flag] = api.ctx_flops(ctx)
+        res[flag] = [Y.t[u].clone() for u in range(tree.n)]
+        sw.close()
+    for u in range(tree.n):
+        assert torch.equal(res["0"][u], res["1"][u]), u
+    assert flops["1"] < flops["0"], flops
+    for j in range(k):
+        ref = osol.als_solve(tree, W, shifts[j], phi[j], phi[j], sweeps=1, maxiter=12, rtol=0.0)
+        for u in range(tree.n):
+            assert rel_err(res["1"][u][j].cpu().numpy(), ref[u]) < 1e-8, (j, u)
