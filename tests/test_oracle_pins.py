@@ -517,3 +517,54 @@ def test_lobpcg_then_inverse_iteration_c1_reaches_closed_form():
     ex = exact.normal_mode_levels(m, 10)
     assert np.max(np.abs(theta - ex)) < 1e-3
     assert np.all(theta >= ex - 1e-7)
+
+
+# ------------------------------------------------------------------ SRC
+
+@pytest.mark.parametrize("kind", ["mps", "binary", "fork"])
+def test_src_recovers_product_exactly_at_full_sketch(kind):
+    """Successive randomized compression (Sec. II.C.1): once the sketch size
+    chi reaches the rank of every unfolding of H x, the randomized range
+    finder captures the range exactly (Gaussian test matrices), so the
+    compressed state equals the dense product H x; every non-root tensor is
+    an isometry toward its parent (canonical at the root); below that rank
+    the error is nonzero and the bonds never exceed chi."""
+    from oracle import src
+    m = wl.coupled_oscillators(4, 5, 500, 3000, 3, n_cubic=2)
+    tree = {"mps": wl.mps_tree(m.dims, 1), "binary": wl.binary_tree(m.dims), "fork": wl.fork_tree(m.dims, 2, 1)}[kind]
+    W = ttno.build_ttno(tree, m)
+    x = wl.random_block(tree, [max(1, b) for b in wl.bond_dims(tree, 2)], 1, 3)[0]
+    ref = exact.sop_dense_matrix(m) @ ttn.to_dense(tree, x)
+    rng = np.random.default_rng(1)
+    for chi, tol in ((3, None), (9, 1e-12), (20, 1e-12)):
+        om = [rng.normal(size=(tree.phys[u], chi)) for u in range(tree.n)]
+        y, bonds = src.src_apply(tree, W, x, om, chi)
+        err = np.linalg.norm(ttn.to_dense(tree, y) - ref) / np.linalg.norm(ref)
+        assert max(bonds) <= chi
+        if tol is None:
+            assert err > 1e-6
+        else:
+            assert err < tol, (chi, err)
+        for u in range(tree.n):
+            if u != tree.root:
+                Q = y[u].reshape(y[u].shape[0], -1)
+                np.testing.assert_allclose(Q @ Q.T, np.eye(Q.shape[0]), atol=1e-12)
+        assert abs(np.linalg.norm(y[tree.root]) - np.linalg.norm(ttn.to_dense(tree, y))) < 1e-12 * np.linalg.norm(ref)
+
+
+def test_src_of_identity_operator_returns_the_state():
+    """With the identity as operator and chi at least the state's bonds, SRC
+    returns the state itself (in its canonical gauge)."""
+    from oracle import src
+    m = wl.make_config_model("c3")
+    tree = wl.fork_tree(m.dims, 4, 1)
+    bonds = [max(1, b) for b in wl.bond_dims(tree, 3)]
+    x = wl.random_block(tree, bonds, 1, 8)[0]
+    Wid = [ttn.identity_op(tree, u) for u in range(tree.n)]
+    rng = np.random.default_rng(2)
+    om = [rng.normal(size=(tree.phys[u], 3)) for u in range(tree.n)]
+    y, yb = src.src_apply(tree, Wid, x, om, 3)
+    ov = ttn.expectation(tree, y, None, x)
+    nx = ttn.expectation(tree, x, None, x)
+    assert abs(ov - nx) < 1e-10 * nx
+    assert abs(ttn.expectation(tree, y, None, y) - nx) < 1e-10 * nx
