@@ -338,6 +338,34 @@ ttn_status ttn_vec_gather(ttn_ctx* ctx, int32_t n, const int32_t* idx, const dou
  * low-precision block to FP64 for refinement. */
 ttn_status ttn_block_convert(ttn_ctx* ctx, const ttn_block* src, ttn_block* dst, int32_t rows);
 
+/* ------------------------------------------------------------ successive randomized compression */
+
+/* y_j ~ H x_j for the k states of a block by successive randomized
+ * compression (Sec. II.C.1; Eq. matrix random compression, Fig. random
+ * tensor, Fig. src), sketch size chi.  The test matrix of the method is a
+ * Khatri-Rao product: column l is the product over the physical nodes u of
+ * row l of omega[u] (device, [chi][phys_u] in the tensors' dtype; ignored at
+ * auxiliary nodes), drawn by the caller.  Steps: the environments of
+ * <omega_l|H|x_j> on every edge; then, from the leaves to the root, each
+ * non-root node's local sketch (its H and x tensors contracted with the
+ * compressed children and with the sketch of everything outside its subtree,
+ * one column per l) is QR-factorised (Householder, diag(R) >= 0) and Q becomes
+ * y's tensor there -- a node whose local space has at most chi dimensions
+ * keeps it whole (identity) -- and finally the root's tensors are contracted
+ * with the compressed children.  y comes out canonical at the root.
+ * y's bonds must be ttn_src_bonds(tree, chi): edge (u, parent) keeps
+ * min(chi, prod of u's children's bonds * phys[u]).  x, y and the operator
+ * share one dtype; compute TTN_F64 (FP64) or TTN_F32 (FP32).  ttn_src_create
+ * allocates the sketch environments (k * chi slots per directed edge) and the
+ * compressed environments; ttn_src_apply allocates nothing. */
+typedef struct ttn_src ttn_src;
+ttn_status ttn_src_bonds(const ttn_tree* t, int32_t chi, int32_t* bonds_out);
+ttn_status ttn_src_create(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_block* x, ttn_block* y,
+                          int32_t chi, ttn_dtype compute, ttn_src** out);
+ttn_status ttn_src_apply(ttn_ctx* ctx, ttn_src* s, const void* const* omega);
+/* Synchronises the context stream, then frees the handle. */
+ttn_status ttn_src_destroy(ttn_src* s);
+
 /* ------------------------------------------------------------ operator compiler (host) */
 
 /* Sum-of-products -> TTNO in FP64 on the host (Sec. II.A.3, Eq. sum_of_tp):

@@ -424,9 +424,24 @@ bool build_env_net(const ttn_tree* t, const ttn_ttno* op, const ttn_block* bra, 
   return true;
 }
 
+// The plan cache key ends with the whole network written out (every operand's
+// labels, extents, strides and batching, the output's labels and strides):
+// the readable prefix alone does not say through which leg an environment
+// leaves, and contexts serve several trees whose node numbers coincide.
+void net_signature(const Net& net, std::ostringstream& k) {
+  for (const Tensor& t : net.in) {
+    k << "|" << t.batched;
+    for (size_t i = 0; i < t.lab.size(); ++i) k << "," << t.lab[i] << "=" << net.dims.at(t.lab[i]) << "/" << t.str[i];
+  }
+  k << "|>";
+  for (size_t i = 0; i < net.out_lab.size(); ++i)
+    k << "," << net.out_lab[i] << "=" << net.dims.at(net.out_lab[i]) << "/" << net.out_str[i];
+}
+
 Plan* get_plan(ttn_ctx* ctx, const Net& net, int ct, double batch, ttn_status& code) {
   std::ostringstream k;
-  k << net.key << ":ct" << ct << ":b" << (batch <= 1 ? 0 : (batch < 256 ? 1 : 2));
+  k << net.key << ":ct" << ct << ":b" << (batch <= 1 ? 0 : (batch < 256 ? 1 : 2)) << "#";
+  net_signature(net, k);
   auto it = ctx->plans.find(k.str());
   if (it != ctx->plans.end()) return it->second.get();
   Status st;
@@ -1087,7 +1102,7 @@ ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, 
     // operator product at a node with one virtual leg and a physical leg,
     // FP64 or FP32 arithmetic on its own storage: the fused kernel
     const int c = t->nb[u][0];
-    bool fuse = op && kap == 1 && t->phys[u] > 1 && (ct == 0 || ct == 1);
+    bool fuse = op && kap == 1 && t->phys[u] > 1 && (ct == 0 || ct == 1) && ctx->leg_tabs.empty();
     const char* fe = getenv("TTN_FUSED_LEAF");
     if (fe && fe[0] == '0') fuse = false;
     LeafHeffArgs la;
@@ -1157,12 +1172,13 @@ ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, 
     in.push_back(w);
     ne.push_back(w_elems(t, op, u));
   }
+  const bool per_leg = (int)ctx->leg_tabs.size() == kap;
   for (int i = 0; i < kap; ++i) {
     const int c = t->nb[u][i];
     OpAddr e;
     e.base = envs->slot[ttn_envs::dslot(t, c, u)];
-    e.tab = pair_ids;
-    e.tab_max = envs->n_slots;
+    e.tab = per_leg ? ctx->leg_tabs[i].first : pair_ids;
+    e.tab_max = per_leg ? ctx->leg_tabs[i].second : envs->n_slots;
     e.bstride = envs->slot_elems(c, u);
     in.push_back(e);
     ne.push_back(envs->slot_elems(c, u));

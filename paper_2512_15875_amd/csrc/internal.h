@@ -331,6 +331,11 @@ struct ttn_ctx {
   std::vector<const void*> ws_last_inputs;
   const void* ws_last_base = nullptr;
   int ws_last_nb = -1;
+  // per-leg batch tables of the next H_eff product (leg i = neighbour i of
+  // the node): {table, valid entries}; a null table means the identity.  Empty:
+  // every leg uses the call's pair_ids (successive randomized compression
+  // mixes k-slot and k*chi-slot environments in one product)
+  std::vector<std::pair<const int32_t*, int>> leg_tabs;
   // this device's copy of the static scratch array of heff_apply_block_noalloc
   // (looked up at creation; null if the lookup failed)
   void* scratch = nullptr;
@@ -367,6 +372,10 @@ bool pinned_malloc(void** p, size_t bytes);
 // asynchronous upload on the context stream; the host copy is kept with the
 // context.  Returns null (and sets `code`) when the pool is exhausted.
 const int32_t* pool_upload(ttn_ctx* ctx, std::vector<int32_t>&& h, ttn_status& code);
+// offsets of the rows of a node tensor with dims `dims` when leg `leg` is the
+// column index (a table in the pool, cached per shape); cstride = leg stride
+const int32_t* leg_rows_table(ttn_ctx* ctx, const std::vector<int>& dims, int leg, int64_t& cstride, int& m,
+                              ttn_status& code);
 // whether the stage profile records plans with this key (prefix filter)
 bool prof_selected(const ttn_ctx* ctx, const std::string& key);
 // the device address of heff_apply_block_noalloc's static scratch array on

@@ -95,6 +95,24 @@ hipError_t launch_vgather(const int32_t* idx, const double* src, int src_n, doub
   return hipGetLastError();
 }
 
+// X[z][i][j] = (i == j) for z < k, i, j < n
+template <typename T>
+__global__ void set_identity_kernel(T* X, int n, int64_t total) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int64_t r = e % ((int64_t)n * n);
+  X[e] = (T)((r / n) == (r % n) ? 1.0 : 0.0);
+}
+
+hipError_t launch_set_identity(int ctype, void* X, int n, int k, hipStream_t s) {
+  const int64_t total = (int64_t)k * n * n;
+  if (total <= 0) return hipSuccess;
+  const dim3 g((unsigned)((total + 255) / 256));
+  if (ctype == 0) hipLaunchKernelGGL(set_identity_kernel<double>, g, dim3(256), 0, s, (double*)X, n, total);
+  else hipLaunchKernelGGL(set_identity_kernel<float>, g, dim3(256), 0, s, (float*)X, n, total);
+  return hipGetLastError();
+}
+
 // sdt / ddt: 0 double, 1 float
 hipError_t launch_convert(int sdt, const void* x, int ddt, void* y, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;

@@ -38,6 +38,9 @@ class LobpcgOpts:
                                       # "minres+diag" / "minres+learned" (MINRES from a corrected start)
     mlp: Optional[torch.Tensor] = None  # learned map parameters (device FP32)
     mlp_compute: int = ttn.BF16
+    residual: str = "fit"             # H x_j by variational fitting ("fit") or successive randomized
+                                      # compression with sketch size D ("src", Sec. II.C.1)
+    src_seed: int = 1234              # seed of the SRC test matrices (one draw per iteration)
 
 
 @dataclasses.dataclass
@@ -169,6 +172,7 @@ class TTNEigensolver:
         self._sw_ii = None
         self.cluster_rr_calls = 0  # in-cluster Rayleigh-Ritz steps of inverse iteration (clusters of > 1 state)
         self._cl_tables = None     # device tables of the in-cluster Rayleigh-Ritz (clusters are fixed)
+        self._src = None           # successive randomized compression of H x (created on first use)
 
     # ------------------------------------------------------------ block plumbing
 
@@ -268,10 +272,14 @@ class TTNEigensolver:
         ctx, k, root, opts = self.ctx, self.k, self.root, self._opts
         it = self._it
         self._it += 1
-        # residual r_j = H x_j - lambda_j x_j by fitting
+        # residual r_j = H x_j - lambda_j x_j by fitting, or H x_j by SRC then
+        # r_j = y_j - lambda_j x_j by an identity fit
         ttn.vec_scale(ctx, self.lam_d, -1.0, self.neglam_d)
         self._copy_rows(self.R, 0, self.B, 0, k)
-        self.sw_res.run(ttn.SOLVE_FIT, opts.fit_sweeps, init=True, graph=self.graphs)
+        if opts.residual == "src":
+            self._src_residual(opts)
+        else:
+            self.sw_res.run(ttn.SOLVE_FIT, opts.fit_sweeps, init=True, graph=self.graphs)
         ttn.block_node_norms2(ctx, self.R, root, self.rn2)
         ttn.vec_sqrt(ctx, self.rn2, self.rn)
         # preconditioned residual: (H - s) w = r by ALS
@@ -319,6 +327,29 @@ class TTNEigensolver:
         lam = self.rayleigh_quotients(self.B, list(range(k)))
         self.lam_d.copy_(lam)
         return True
+
+    def _src_residual(self, opts: LobpcgOpts):
+        """y_j ~ H x_j by successive randomized compression (sketch size D),
+        then r_j = y_j - lambda_j x_j fitted into the residual block."""
+        k = self.k
+        if self._src is None:
+            D = max(self.bonds)
+            self.XS = ttn.Block(self.ctx, self.gt, k, self.bonds, self.sdt)
+            self.YS = ttn.Block(self.ctx, self.gt, k, [max(1, b) for b in ttn.src_bonds(self.gt, D)], self.sdt)
+            sc = ttn.F64 if self.sdt == ttn.F64 else ttn.F32
+            self._src = ttn.Src(self.ctx, self.gt, self.op, self.XS, self.YS, D, sc)
+            self._src_chi = D
+            idx = list(range(k))
+            self.sw_res_src = ttn.Sweep(self.ctx, self.gt, None, self.R,
+                                        [(None, self.YS, idx, idx, self._ones), (None, self.XS, idx, idx, self.neglam_d)],
+                                        compute=self.compute_exact if self.sdt == ttn.F64 else self.compute)
+            self._src_gen = torch.Generator(device="cuda")
+            self._src_gen.manual_seed(opts.src_seed)
+        self._copy_rows(self.XS, 0, self.B, 0, k)
+        om = [torch.randn(self._src_chi, self.gt.phys[u], generator=self._src_gen, device="cuda", dtype=self.tdt)
+              if self.gt.phys[u] > 1 else None for u in range(self.gt.n)]
+        self._src.apply(om)
+        self.sw_res_src.run(ttn.SOLVE_FIT, opts.fit_sweeps, init=True, graph=self.graphs)
 
     def harvest(self, rows_per_node: int, maxiter: int = 300, rtol: float = 1e-10, seed: int = 0):
         """Training pairs for the learned local map: one ALS sweep of plain

@@ -68,6 +68,10 @@ _SIGS = {
     "ttn_ctx_profile": [_P, _I],
     "ttn_ctx_flops": [_P, C.POINTER(C.c_double), _I],
     "ttn_alloc_count": [C.POINTER(C.c_int64)],
+    "ttn_src_bonds": [_P, _I, _P],
+    "ttn_src_create": [_P, _P, _P, _P, _P, _I, C.c_int, _P],
+    "ttn_src_apply": [_P, _P, _P],
+    "ttn_src_destroy": [_P],
     "ttn_ctx_profile_filter": [_P, _I, _P],
     "ttn_ctx_probe_heff": [_P, _I, _P],
     "ttn_ctx_probe_report": [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)],
@@ -554,6 +558,39 @@ def block_convert(ctx: Context, src: "Block", dst: "Block", rows: int):
 
 def vec_scale(ctx: Context, x: torch.Tensor, alpha: float, y: torch.Tensor):
     _check(lib().ttn_vec_scale(ctx.h, int(x.numel()), _ptr(x), float(alpha), _ptr(y)), ctx)
+
+
+def src_bonds(tree: Tree, chi: int) -> List[int]:
+    """Bonds of the state successive randomized compression produces with sketch size chi."""
+    out = (C.c_int32 * tree.n)()
+    _check(lib().ttn_src_bonds(tree.h, int(chi), C.cast(out, C.c_void_p)))
+    return list(out)
+
+
+class Src:
+    """Successive randomized compression y_j ~ H x_j of a block (ttn_src_*)."""
+
+    def __init__(self, ctx: Context, tree: Tree, op: "TTNO", x: "Block", y: "Block", chi: int, compute: int):
+        self.ctx, self.tree, self.chi = ctx, tree, chi
+        self.h = C.c_void_p()
+        _check(lib().ttn_src_create(ctx.h, tree.h, op.h, x.h, y.h, int(chi), int(compute), C.byref(self.h)), ctx)
+
+    def apply(self, omegas: Sequence[Optional[torch.Tensor]]):
+        """omegas[u]: device [chi][phys_u] test matrix rows of physical node u (None at auxiliary nodes)."""
+        self._keep = list(omegas)
+        arr = _ptrs([None if o is None else o.data_ptr() for o in omegas])
+        _check(lib().ttn_src_apply(self.ctx.h, self.h, C.cast(arr, C.c_void_p)), self.ctx)
+
+    def close(self):
+        if self.h:
+            lib().ttn_src_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def alloc_count() -> int:
