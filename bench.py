@@ -702,6 +702,9 @@ def heff_probe(args):
         for line in api.autotune(ctx, None).splitlines():
             if line.startswith(f"heff:{u}:1"):
                 print("  tuned " + line, file=sys.stderr)
+    for _ in range(20):  # steady clocks before the measured calls
+        call()
+    ctx.sync()
     mark = torch.zeros(MARKER_N, dtype=torch.float64, device="cuda")
     api.vec_scale(ctx, mark, 1.0, mark)
     api.probe_heff(ctx, [u])

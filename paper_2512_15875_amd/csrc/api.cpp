@@ -138,6 +138,8 @@ ttn_status tune_stage(ttn_ctx* ctx, Plan& P, size_t s, int ct, const OpAddr& A, 
   std::vector<int> cand{0, 1, 2, 3, 4, 5, 6};
   if (splitk_eligible(st.g, ct)) cand.push_back(8);
   if (narrow_eligible(st.g, ct)) cand.push_back(9);
+  if (tn_eligible(st.g, ct))
+    for (int c = 10; c <= 16; ++c) cand.push_back(c);
   hipEvent_t ev[2];
   if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
     return fail(ctx, TTN_E_DEVICE, "hipEventCreate failed");
@@ -199,9 +201,9 @@ ttn_status exec_plan(ttn_ctx* ctx, Plan& P, int ct, const std::vector<OpAddr>& i
   {
     int nid = P.n_in;
     for (const Step& st : P.steps)
-      if (st.out >= 0) dep_x[nid++] = dep_x[st.a] || dep_x[st.b];
+      if (st.out >= 0) dep_x[nid++] = dep_x[st.a] || (st.b >= 0 && dep_x[st.b]);
   }
-  auto step_dep_x = [&](const Step& st) { return dep_x[st.a] || dep_x[st.b]; };
+  auto step_dep_x = [&](const Step& st) { return dep_x[st.a] || (st.b >= 0 && dep_x[st.b]); };
   std::vector<const void*> in_bases;
   for (const OpAddr& o : inputs) in_bases.push_back(o.base);
   in_bases.push_back(out.base);
@@ -250,6 +252,12 @@ ttn_status exec_plan(ttn_ctx* ctx, Plan& P, int ct, const std::vector<OpAddr>& i
       const Step& st = P.steps[s];
       if (!st.batched && shared_done) continue;
       if (reuse && st.out >= 0 && !step_dep_x(st)) continue;  // still in the workspace
+      if (st.kind == 1) {  // relayout of a shared input into its slot
+        hipError_t he = launch_relayout(ct, addr(st.a).base, st.g.a_om, st.g.a_ok, st.g.M, st.g.K,
+                                        (void*)addr(st.out).base, ctx->stream, ctx->gate);
+        if (he != hipSuccess) return fail(ctx, TTN_E_LAUNCH, std::string("relayout launch: ") + hipGetErrorString(he));
+        continue;
+      }
       const OpAddr A = addr(st.a), B = addr(st.b);
       const bool last = st.out < 0;
       OpAddr C = last ? out : addr(st.out);
@@ -425,15 +433,16 @@ bool build_env_net(const ttn_tree* t, const ttn_ttno* op, const ttn_block* bra, 
 }
 
 // The plan cache key ends with the whole network written out (every operand's
-// labels, extents, strides and batching, the output's labels and strides):
+// labels, extents, strides and batching, the output's labels and strides; no
+// '|', which separates the fields of the profile and autotune reports):
 // the readable prefix alone does not say through which leg an environment
 // leaves, and contexts serve several trees whose node numbers coincide.
 void net_signature(const Net& net, std::ostringstream& k) {
   for (const Tensor& t : net.in) {
-    k << "|" << t.batched;
+    k << ";" << t.batched;
     for (size_t i = 0; i < t.lab.size(); ++i) k << "," << t.lab[i] << "=" << net.dims.at(t.lab[i]) << "/" << t.str[i];
   }
-  k << "|>";
+  k << ";>";
   for (size_t i = 0; i < net.out_lab.size(); ++i)
     k << "," << net.out_lab[i] << "=" << net.dims.at(net.out_lab[i]) << "/" << net.out_str[i];
 }

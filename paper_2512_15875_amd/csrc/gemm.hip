@@ -15,6 +15,7 @@
 // The bf16 form reads FP32 tensors and rounds to bfloat16 when staging to LDS.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <type_traits>
 
@@ -191,6 +192,35 @@ __global__ __launch_bounds__(256, (CT == 1) ? 3 : 2) void ogemm_kernel(KArgs g) 
       b_fix[i] = b_ok_col[i] ? g.b_on[ng] : 0;
     }
   }
+  // The epilogue's output offsets are loaded here, before the first barrier:
+  // their latency overlaps the first slice's loads instead of following the
+  // last slice (short-K stages are bound by that chain).
+  T* __restrict__ C = (T*)g.C.base + batch_off(g.C, z, g.z0, g.flag);
+  const T* __restrict__ Dp = g.has_d ? (const T*)g.D.base + batch_off(g.D, z, g.z0, g.flag) : nullptr;
+  const double alpha = g.alpha ? g.alpha[g.z0 + z] : 1.0;
+  const double sh = g.shift ? g.shift[g.z0 + z] : 0.0;
+  constexpr int RI = CMF ? 1 : 4, CI = CMF ? 4 : 1;
+  auto quad = [&](int i) { return (CT == 0) ? ((lane >> 4) + 4 * i) : (4 * (lane >> 4) + i); };
+  auto ri = [](int i) { return CMF ? 0 : i; };
+  auto ci = [](int i) { return CMF ? i : 0; };
+  int cm[TM][RI], cn[TN][CI];
+  bool rv[TM][RI], cv[TN][CI];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int i = 0; i < RI; ++i) {
+      const int mg = m0 + wm * WTM + a * 16 + (CMF ? (lane & 15) : quad(i));
+      rv[a][i] = mg < M;
+      cm[a][i] = rv[a][i] ? g.c_om[mg] : 0;
+    }
+#pragma unroll
+  for (int b = 0; b < TN; ++b)
+#pragma unroll
+    for (int i = 0; i < CI; ++i) {
+      const int ng = n0 + wn * WTN + b * 16 + (CMF ? quad(i) : (lane & 15));
+      cv[b][i] = ng < N;
+      cn[b][i] = cv[b][i] ? g.c_on[ng] : 0;
+    }
   __syncthreads();
 
   // Next-slice loads are issued unconditionally from clamped, always valid
@@ -328,32 +358,6 @@ __global__ __launch_bounds__(256, (CT == 1) ? 3 : 2) void ogemm_kernel(KArgs g) 
   // columns: coalesced when C's columns are its unit-stride direction); with
   // CMF the operands went into the matrix cores swapped, and a lane holds four
   // columns of one row (lanes along rows: coalesced when rows are unit-stride).
-  T* __restrict__ C = (T*)g.C.base + batch_off(g.C, z, g.z0, g.flag);
-  const T* __restrict__ Dp = g.has_d ? (const T*)g.D.base + batch_off(g.D, z, g.z0, g.flag) : nullptr;
-  const double alpha = g.alpha ? g.alpha[g.z0 + z] : 1.0;
-  const double sh = g.shift ? g.shift[g.z0 + z] : 0.0;
-  constexpr int RI = CMF ? 1 : 4, CI = CMF ? 4 : 1;
-  auto quad = [&](int i) { return (CT == 0) ? ((lane >> 4) + 4 * i) : (4 * (lane >> 4) + i); };
-  auto ri = [](int i) { return CMF ? 0 : i; };
-  auto ci = [](int i) { return CMF ? i : 0; };
-  int cm[TM][RI], cn[TN][CI];
-  bool rv[TM][RI], cv[TN][CI];
-#pragma unroll
-  for (int a = 0; a < TM; ++a)
-#pragma unroll
-    for (int i = 0; i < RI; ++i) {
-      const int mg = m0 + wm * WTM + a * 16 + (CMF ? (lane & 15) : quad(i));
-      rv[a][i] = mg < M;
-      cm[a][i] = rv[a][i] ? g.c_om[mg] : 0;
-    }
-#pragma unroll
-  for (int b = 0; b < TN; ++b)
-#pragma unroll
-    for (int i = 0; i < CI; ++i) {
-      const int ng = n0 + wn * WTN + b * 16 + (CMF ? quad(i) : (lane & 15));
-      cv[b][i] = ng < N;
-      cn[b][i] = cv[b][i] ? g.c_on[ng] : 0;
-    }
   const bool plain = !Dp && !g.d_const && !g.accum;
   if (plain) {
 #pragma unroll
@@ -387,6 +391,232 @@ __global__ __launch_bounds__(256, (CT == 1) ? 3 : 2) void ogemm_kernel(KArgs g) 
           const double c0 = g.accum ? (double)cvv[i][b] : 0.0;
           if (rv[a][ri(i)] && cv[b][ci(i)])
             C[cm[a][ri(i)] + cn[b][ci(i)]] = (T)(alpha * ((double)acc[a][b][i] - sh * d) + c0);
+        }
+    }
+  }
+}
+
+// Unit-stride-k tile kernel, FP32 storage and arithmetic.  Both operands run
+// contiguously along k (k offsets are exactly k, every row offset of A and
+// column offset of B a multiple of 4 elements, 16-byte aligned bases,
+// K % 4 == 0): the largest H_eff stages, where two intermediates meet over a
+// (bond x operator bond) group.  Same 2 x 2 wave grid, XCD mapping and
+// epilogue as ogemm_kernel, but every thread moves 16-byte runs of 4
+// consecutive k: global loads are 16 bytes wide (8 lanes cover a 128-byte run
+// of one row), an LDS row holds the slice's 8 runs of one row, written with
+// one 16-byte store each, and a fragment read takes 4 consecutive k of one
+// row in one 16-byte LDS read -- lane group q = l/16 supplies
+// k = 16c + 4q + t to the t-th of the four MFMAs of 16-deep chunk c, for A
+// and B alike, so every k is summed exactly once.  Run j of row r is stored
+// at position j ^ (r & 7) of its LDS row: the 16 rows of a fragment read then
+// hit distinct bank groups without padding (measured on the 864 x 576 x 1008
+// stage: no bank-conflict cycles, 12% faster than a padded row).  BK = 32:
+// one barrier per 32 k.
+template <int BM, int BN, bool CMF>
+__global__ __launch_bounds__(256, 2) void ogemm_tn_kernel(KArgs g) {
+  if (g.gate && *g.gate == 0) return;  // uniform, before any barrier
+  constexpr int BK = 32, LR = BK / 4;  // LDS row: the slice's 8 runs of 4 k (float4), XOR-swizzled
+  constexpr int EA = BM * BK / 4 / 256, EB = BN * BK / 4 / 256;
+  constexpr int WTM = BM / 2, WTN = BN / 2;
+  constexpr int TM = WTM / 16, TN = WTN / 16;
+  static_assert(EA >= 1 && EB >= 1 && TM >= 1 && TN >= 1, "tile too small");
+  __shared__ floatx4 As[2][BM * LR];
+  __shared__ floatx4 Bs[2][BN * LR];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  int z, tile;
+  if (g.xcd_remap) {
+    const int gid = blockIdx.x;
+    const int local = gid >> 3;
+    const int grp = local / g.tiles;
+    tile = local - grp * g.tiles;
+    z = grp * 8 + (gid & 7);
+    if (z >= g.nz) return;
+  } else {
+    z = blockIdx.y;
+    tile = blockIdx.x;
+  }
+  const int tmi = tile / g.tiles_n;
+  const int tni = tile - tmi * g.tiles_n;
+  const int m0 = tmi * BM, n0 = tni * BN;
+  const int M = g.M, N = g.N, K = g.K;
+  const float* __restrict__ A = (const float*)g.A.base + batch_off(g.A, z, g.z0, g.flag);
+  const float* __restrict__ B = (const float*)g.B.base + batch_off(g.B, z, g.z0, g.flag);
+
+  // staging map: thread t moves k run jq = t % 8 of rows t / 8 + 32 i; rows
+  // past M (N) read offset 0 (always addressable) and are zeroed in LDS
+  const int jq = tid & 7, r0 = tid >> 3;
+  int a_fix[EA], b_fix[EB];
+  bool a_in[EA], b_in[EB];
+#pragma unroll
+  for (int i = 0; i < EA; ++i) {
+    const int mg = m0 + r0 + 32 * i;
+    a_in[i] = mg < M;
+    a_fix[i] = a_in[i] ? g.a_om[mg] : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < EB; ++i) {
+    const int ng = n0 + r0 + 32 * i;
+    b_in[i] = ng < N;
+    b_fix[i] = b_in[i] ? g.b_on[ng] : 0;
+  }
+  // Two register sets, so a slice's global loads are issued two slices
+  // before they are staged: the wait at staging covers the matrix-core work
+  // of two slices instead of one (the loop body is unrolled by two to keep
+  // the sets in registers).  Tiles below 128 x 128 only.
+  constexpr bool DEEP = BM * BN < 128 * 128;
+  floatx4 ra0[EA], rb0[EB], ra1[DEEP ? EA : 1], rb1[DEEP ? EB : 1];
+  bool kv0 = false, kv1 = false;
+  auto load = [&](floatx4* ra, floatx4* rb, bool& kv, int k0) {
+    const int kg = k0 + 4 * jq;
+    kv = kg < K;  // K % 4 == 0: a run lies wholly inside or outside [0, K)
+    const int ko = kv ? kg : 0;
+#pragma unroll
+    for (int i = 0; i < EA; ++i) ra[i] = *(const floatx4*)(A + a_fix[i] + ko);
+#pragma unroll
+    for (int i = 0; i < EB; ++i) rb[i] = *(const floatx4*)(B + b_fix[i] + ko);
+  };
+  auto store = [&](const floatx4* ra, const floatx4* rb, bool kv, int buf) {
+    const floatx4 z4 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < EA; ++i) {
+      const int r = r0 + 32 * i;
+      As[buf][r * LR + (jq ^ (r & 7))] = (a_in[i] && kv) ? ra[i] : z4;
+    }
+#pragma unroll
+    for (int i = 0; i < EB; ++i) {
+      const int r = r0 + 32 * i;
+      Bs[buf][r * LR + (jq ^ (r & 7))] = (b_in[i] && kv) ? rb[i] : z4;
+    }
+  };
+
+  floatx4 acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = (K + BK - 1) / BK;
+  const int fr = lane & 15, fq = lane >> 4;
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      floatx4 fa[TM], fb[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) {
+        const int r = wm * WTM + a * 16 + fr;
+        fa[a] = As[buf][r * LR + ((4 * c + fq) ^ (r & 7))];
+      }
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        const int r = wn * WTN + b * 16 + fr;
+        fb[b] = Bs[buf][r * LR + ((4 * c + fq) ^ (r & 7))];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+          for (int b = 0; b < TN; ++b)
+            acc[a][b] = CMF ? __builtin_amdgcn_mfma_f32_16x16x4f32(fb[b][t], fa[a][t], acc[a][b], 0, 0, 0)
+                            : __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a][t], fb[b][t], acc[a][b], 0, 0, 0);
+    }
+  };
+  if constexpr (DEEP) {
+    // slice s lives in register set s % 2 and LDS buffer s % 2
+    if (nk > 0) {
+      load(ra0, rb0, kv0, 0);
+      if (nk > 1) load(ra1, rb1, kv1, BK);
+      store(ra0, rb0, kv0, 0);
+      __syncthreads();
+    }
+    for (int kt = 0; kt < nk; kt += 2) {
+      if (kt + 2 < nk) load(ra0, rb0, kv0, (kt + 2) * BK);
+      compute(0);
+      if (kt + 1 < nk) store(ra1, rb1, kv1, 1);
+      __syncthreads();
+      if (kt + 1 >= nk) break;
+      if (kt + 3 < nk) load(ra1, rb1, kv1, (kt + 3) * BK);
+      compute(1);
+      if (kt + 2 < nk) store(ra0, rb0, kv0, 0);
+      __syncthreads();
+    }
+  } else {
+    // one register set (the 128 x 128 tile has no registers for two)
+    if (nk > 0) {
+      load(ra0, rb0, kv0, 0);
+      store(ra0, rb0, kv0, 0);
+      __syncthreads();
+    }
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) load(ra0, rb0, kv0, (kt + 1) * BK);
+      compute(buf);
+      if (kt + 1 < nk) store(ra0, rb0, kv0, buf ^ 1);
+      __syncthreads();
+    }
+  }
+
+  // ---- epilogue (as ogemm_kernel): C = alpha (acc - shift * D) (+ C)
+  float* __restrict__ C = (float*)g.C.base + batch_off(g.C, z, g.z0, g.flag);
+  const float* __restrict__ Dp = g.has_d ? (const float*)g.D.base + batch_off(g.D, z, g.z0, g.flag) : nullptr;
+  const double alpha = g.alpha ? g.alpha[g.z0 + z] : 1.0;
+  const double sh = g.shift ? g.shift[g.z0 + z] : 0.0;
+  constexpr int RI = CMF ? 1 : 4, CI = CMF ? 4 : 1;
+  auto quad = [&](int i) { return 4 * fq + i; };
+  auto ri = [](int i) { return CMF ? 0 : i; };
+  auto ci = [](int i) { return CMF ? i : 0; };
+  int cm[TM][RI], cn[TN][CI];
+  bool rv[TM][RI], cv[TN][CI];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int i = 0; i < RI; ++i) {
+      const int mg = m0 + wm * WTM + a * 16 + (CMF ? fr : quad(i));
+      rv[a][i] = mg < M;
+      cm[a][i] = rv[a][i] ? g.c_om[mg] : 0;
+    }
+#pragma unroll
+  for (int b = 0; b < TN; ++b)
+#pragma unroll
+    for (int i = 0; i < CI; ++i) {
+      const int ng = n0 + wn * WTN + b * 16 + (CMF ? quad(i) : fr);
+      cv[b][i] = ng < N;
+      cn[b][i] = cv[b][i] ? g.c_on[ng] : 0;
+    }
+  const bool plain = !Dp && !g.d_const && !g.accum;
+  if (plain) {
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+          if (rv[a][ri(i)] && cv[b][ci(i)]) C[cm[a][ri(i)] + cn[b][ci(i)]] = (float)(alpha * (double)acc[a][b][i]);
+  } else {
+    const float* __restrict__ ds = Dp ? Dp : (const float*)C;
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      float dv[4][TN], cvv[4][TN];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          const int o = cm[a][ri(i)] + cn[b][ci(i)];
+          dv[i][b] = ds[o];
+          cvv[i][b] = C[o];
+        }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          const double d = Dp ? (double)dv[i][b] : (g.d_const ? 1.0 : 0.0);
+          const double c0 = g.accum ? (double)cvv[i][b] : 0.0;
+          if (rv[a][ri(i)] && cv[b][ci(i)])
+            C[cm[a][ri(i)] + cn[b][ci(i)]] = (float)(alpha * ((double)acc[a][b][i] - sh * d) + c0);
         }
     }
   }
@@ -768,6 +998,38 @@ static hipError_t launch_tile(const GemmDesc& gd, KArgs& a, int nz, hipStream_t 
   }
 }
 
+// unit-stride-k tiles (ids 10..16) and the general tile each falls back to
+// when a launch's operands are not 16-byte aligned
+template <int BM, int BN>
+static hipError_t launch_tn(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s) {
+  const int tm = (gd.M + BM - 1) / BM, tn = (gd.N + BN - 1) / BN;
+  a.tiles_n = tn;
+  a.tiles = tm * tn;
+  a.nz = nz;
+  static const int remap_min = env_int("TTN_XCD_REMAP_MIN", 256);
+  a.xcd_remap = nz >= remap_min ? 1 : 0;
+  dim3 grid = a.xcd_remap ? dim3((unsigned)(((nz + 7) / 8) * 8 * a.tiles), 1) : dim3(tm * tn, nz);
+  if (gd.c_mfast) hipLaunchKernelGGL((ogemm_tn_kernel<BM, BN, true>), grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((ogemm_tn_kernel<BM, BN, false>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+static hipError_t launch_tn_tile(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s) {
+  switch (gd.tile) {
+    case 10: return launch_tn<128, 128>(gd, a, nz, s);
+    case 11: return launch_tn<128, 64>(gd, a, nz, s);
+    case 12: return launch_tn<64, 128>(gd, a, nz, s);
+    case 13: return launch_tn<64, 64>(gd, a, nz, s);
+    case 14: return launch_tn<96, 96>(gd, a, nz, s);
+    case 15: return launch_tn<64, 32>(gd, a, nz, s);
+    default: return launch_tn<128, 32>(gd, a, nz, s);
+  }
+}
+
+static const int kTnBM[] = {128, 128, 64, 64, 96, 64, 128};
+static const int kTnBN[] = {128, 64, 128, 64, 96, 32, 32};
+static const int kTnFallback[] = {0, 2, 3, 1, 0, 5, 2};
+
 // k-slice depth: 16 for FP32 and FP64 (measured on the hot-path shapes: a
 // deeper FP32 slice costs occupancy and never paid), 32 for bf16 (one MFMA).
 static int pick_bk(int ctype) { return ctype == 2 ? 32 : 16; }
@@ -814,6 +1076,12 @@ static hipError_t launch_ct(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s)
     g2.tile = 5;  // operands not 16-byte aligned: the general 64 x 32 tile
     return launch_ct<CT>(g2, a, nz, s);
   }
+  if (gd.tile >= 10 && gd.tile <= 16) {
+    if (CT == 1 && tn_eligible(gd, CT) && aligned16(a.A) && aligned16(a.B)) return launch_tn_tile(gd, a, nz, s);
+    GemmDesc g2 = gd;
+    g2.tile = kTnFallback[gd.tile - 10];
+    return launch_ct<CT>(g2, a, nz, s);
+  }
   if (gd.tile == 7) {
     if constexpr (CT == 3) {
       GemmDesc g2 = gd;
@@ -831,6 +1099,14 @@ std::string gemm_kernel_name(int ctype, const GemmDesc& gd) {
   static const int bm[] = {128, 64, 128, 64, 32, 64, 32};
   static const int bn[] = {128, 64, 64, 128, 64, 32, 32};
   if (gd.tile == 8) return "ogemm_splitk_kernel";
+  if (gd.tile >= 10 && gd.tile <= 16) {
+    if (tn_eligible(gd, ctype))
+      return "ogemm_tn_kernel<" + std::to_string(kTnBM[gd.tile - 10]) + ", " + std::to_string(kTnBN[gd.tile - 10]) +
+             ", " + (gd.c_mfast ? "true" : "false") + ">";
+    GemmDesc g2 = gd;
+    g2.tile = kTnFallback[gd.tile - 10];
+    return gemm_kernel_name(ctype, g2);
+  }
   if (gd.tile == 9) return std::string("ogemm_narrow_kernel<") + (gd.c_mfast ? "true" : "false") + ">";
   if (gd.tile == 7) {
     const int tmw = gd.M <= 16 ? 1 : 2, tnw = gd.N <= 16 ? 1 : 2;
@@ -883,6 +1159,35 @@ hipError_t launch_gemm(int ctype, const GemmDesc& gd, const OpAddr& A, const OpA
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// ---------------------------------------------------------------- relayout
+// dst[k * M + m] = src[om[m] + ok[k]]: a shared operand copied into the
+// row-fast order its GEMM reads (consecutive threads write consecutive m).
+template <typename T>
+__global__ __launch_bounds__(256) void relayout_kernel(const T* __restrict__ src, const int32_t* __restrict__ om,
+                                                       const int32_t* __restrict__ ok, int M, int K,
+                                                       T* __restrict__ dst, const int32_t* gate) {
+  if (gate && *gate == 0) return;
+  const int64_t total = (int64_t)M * K;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+    const int k = (int)(i / M), m = (int)(i - (int64_t)k * M);
+    dst[i] = src[om[m] + ok[k]];
+  }
+}
+
+hipError_t launch_relayout(int ctype, const void* src, const int32_t* om, const int32_t* ok, int M, int K, void* dst,
+                           hipStream_t s, const int32_t* gate) {
+  const int64_t total = (int64_t)M * K;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+  if (total <= 0) return hipSuccess;
+  if (ctype == 0 || ctype == 3)
+    hipLaunchKernelGGL(relayout_kernel<double>, dim3(blocks), dim3(256), 0, s, (const double*)src, om, ok, M, K,
+                       (double*)dst, gate);
+  else
+    hipLaunchKernelGGL(relayout_kernel<float>, dim3(blocks), dim3(256), 0, s, (const float*)src, om, ok, M, K,
+                       (float*)dst, gate);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- batched dot

@@ -41,7 +41,8 @@ struct GemmDesc {
   const int32_t* c_on = nullptr;  // [N]
   bool a_mfast = false, b_nfast = true;
   bool c_mfast = false;  // the output's unit-stride label is a row label (lanes should run along rows)
-  int tile = 0;                   // tile configuration id (8: split-K skinny kernel, 9: narrow kernel)
+  int tile = 0;                   // tile configuration id (8: split-K skinny kernel, 9: narrow kernel,
+                                  // 10..16: unit-stride-k tiles)
   // host facts about the tables, for the split-K skinny kernel: k offsets are
   // exactly k (a_ok[k] == k, b_ok[k] == k) and every row (column) offset of A
   // (B) is a multiple of 4 elements
@@ -59,6 +60,12 @@ inline bool splitk_eligible(const GemmDesc& g, int ctype) {
 inline bool narrow_eligible(const GemmDesc& g, int ctype) {
   return (ctype == 1 || ctype == 2) && g.M >= 64 && g.N <= 32 && g.K <= 32 && g.K % 4 == 0 && !g.a_mfast && !g.b_nfast &&
          g.k_unit && g.rows_al4;
+}
+
+// the unit-stride-k tile kernel (tiles 10..16) applies: FP32, both operands
+// contiguous along k (K % 4 == 0), row / column offsets multiples of 4
+inline bool tn_eligible(const GemmDesc& g, int ctype) {
+  return ctype == 1 && g.K >= 32 && g.K % 4 == 0 && !g.a_mfast && !g.b_nfast && g.k_unit && g.rows_al4;
 }
 
 struct Epilogue {
@@ -183,6 +190,10 @@ struct Step {
   bool batched = true;
   int64_t max_a = 0, max_b = 0, max_c = 0;  // largest element offset addressed in A, B, C
   bool tuned = false;        // tile picked by measurement (autotuner)
+  // 0: GEMM stage.  1: relayout of a shared input (b == -1): out[k * M + m] =
+  // a[a_om[m] + a_ok[k]], so the GEMM after it reads that operand m-fast
+  // (or n-fast) and contiguous instead of through strided offsets
+  int kind = 0;
 };
 
 struct Plan {
@@ -203,6 +214,10 @@ struct Plan {
   };
   std::vector<TabRef> tab_refs;
 };
+
+// relayout stage: dst[k * M + m] = src[om[m] + ok[k]] (ctype's storage type)
+hipError_t launch_relayout(int ctype, const void* src, const int32_t* om, const int32_t* ok, int M, int K, void* dst,
+                           hipStream_t s, const int32_t* gate);
 
 // Point a plan's stage descriptors at the device copy of its tables.
 void bind_plan_tables(Plan& plan, const int32_t* d_tabs);

@@ -96,7 +96,7 @@ void group_offsets(const std::vector<int>& labs, const std::map<int, int>& dims,
   }
 }
 
-int pick_tile(int M, int N, int K, double nblocks_other) {
+int pick_tile(int M, int N, int K, double nblocks_other, bool tn) {
   // tiny per-item products over many items: one wave per item (tile id 7).
   // Measured on the fitting environments it does not beat the 32x32 tile
   // (those stages are bound by their intermediates' memory traffic), so it is
@@ -106,10 +106,22 @@ int pick_tile(int M, int N, int K, double nblocks_other) {
   // prefer big tiles when the grid stays large enough to fill 256 CUs
   struct C {
     int id, bm, bn;
-  } cs[] = {{0, 128, 128}, {2, 128, 64}, {3, 64, 128}, {1, 64, 64}, {5, 64, 32}, {4, 32, 64}, {6, 32, 32}};
-  int best = 6;
+  };
+  static const std::vector<C> general{{0, 128, 128}, {2, 128, 64}, {3, 64, 128}, {1, 64, 64},
+                                      {5, 64, 32},   {4, 32, 64},  {6, 32, 32}};
+  // unit-stride-k operands: the 16-byte-run tiles (no 32-row tiles there)
+  static const std::vector<C> unit_k{{10, 128, 128}, {11, 128, 64}, {12, 64, 128}, {14, 96, 96},
+                                     {13, 64, 64},   {16, 128, 32}, {15, 64, 32}};
+  static const bool unit_k_on = !getenv("TTN_NO_UNIT_K_TILES");
+  tn = tn && unit_k_on;
+  const std::vector<C>& cs = tn ? unit_k : general;
+  int best = tn ? 15 : 6;
   double best_score = -1;
   for (auto& c : cs) {
+    // a short contraction (K <= 64) is bound by writing its output, not by
+    // operand reuse: tiles up to 64 x 64 keep more workgroups per CU in flight
+    // (measured on the 24-deep and 63-deep H_eff stages of the binary tree)
+    if (K <= 64 && c.bm * c.bn > 64 * 64) continue;
     const double tm = std::ceil((double)M / c.bm), tn = std::ceil((double)N / c.bn);
     const double eff = (double)M * N / (tm * c.bm * tn * c.bn);  // useful fraction of the tile area
     const double wgs = tm * tn * nblocks_other;
@@ -182,7 +194,10 @@ std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<in
     l.batched = in[i].batched;
     live.push_back(l);
   }
-  int next_id = (int)in.size();
+  int next_id = (int)in.size();      // intermediate ids of the contraction sequence (lookahead keys)
+  int next_actual = (int)in.size();  // ids of the plan's stage outputs (relayout stages included)
+  std::map<int, int> act;            // sequence id -> stage output id
+  for (size_t i = 0; i < in.size(); ++i) act[(int)i] = (int)i;
   // Lookahead: which step consumes each intermediate, and with which other
   // operand.  An intermediate stores the legs its consumer contracts last, in
   // the other operand's order, so both operands of the consumer run
@@ -261,8 +276,8 @@ std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<in
     kk = by_stride_desc(la, kl);
 
     Step stp;
-    stp.a = la.id;
-    stp.b = lb.id;
+    stp.a = act.at(la.id);
+    stp.b = act.at(lb.id);
     stp.batched = la.batched || lb.batched;
     double un = 1;
     for (int x : uni(sa, sb)) un *= dims.at(x);
@@ -333,18 +348,8 @@ std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<in
         st = {TTN_E_SHAPE, "intermediate too large for 32-bit offsets"};
         return nullptr;
       }
-      if (stp.batched) {
-        inter_off.push_back(ws_item);
-        inter_shared.push_back(0);
-        ws_item += (acc + 63) / 64 * 64;
-      } else {
-        inter_off.push_back(ws_shared);
-        inter_shared.push_back(1);
-        ws_shared += (acc + 63) / 64 * 64;
-      }
     }
     lo.str = ostr;
-    stp.out = lo.id;
     // Row and column order.  The matrix rows run over ml in the order listed
     // (last label fastest), likewise the columns over nl; they start sorted by
     // the operand's own strides.  The output's unit-stride label f should be
@@ -384,6 +389,93 @@ std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<in
       g.b_nfast = !nl.empty() && nl.back() == sb;
       g.c_mfast = !ml.empty() && (nl.empty() || ml.back() == f);
     }
+    // A small shared input (an operator tensor) read neither along its unit
+    // stride nor contiguously along k is first copied, once per call, into
+    // [k][rows] order, so that the GEMM reads it row-fast and coalesced; the
+    // same for B ([k][columns]).
+    auto vmax = [](const std::vector<int32_t>& v) {
+      int64_t m = 0;
+      for (int32_t x : v) m = std::max<int64_t>(m, x);
+      return m;
+    };
+    auto relayout = [&](Live& l, const std::vector<int>& rows, int64_t R) {
+      std::vector<int32_t> t_r, t_k;
+      group_offsets(rows, dims, l.str, t_r);
+      group_offsets(kk, dims, l.str, t_k);
+      bool ku = true, al = true;
+      for (int i = 0; i < (int)t_k.size() && ku; ++i) ku = t_k[i] == i;
+      for (int32_t x : t_r) al = al && x % 4 == 0;
+      if ((ku && al) || R * K > (int64_t)1 << 24) return -1;  // already contiguous along k, or too big
+      Step rs;
+      rs.kind = 1;
+      rs.a = act.at(l.id);
+      rs.b = -1;
+      rs.batched = false;
+      rs.g.M = (int)R;
+      rs.g.N = 1;
+      rs.g.K = (int)K;
+      rs.out_size = R * K;
+      rs.max_a = vmax(t_r) + vmax(t_k);
+      rs.max_b = 0;
+      rs.max_c = R * K - 1;
+      refs.push_back({plan->steps.size(), 0, all_tabs.size()});
+      all_tabs.insert(all_tabs.end(), t_r.begin(), t_r.end());
+      while (all_tabs.size() % 16) all_tabs.push_back(0);
+      refs.push_back({plan->steps.size(), 1, all_tabs.size()});
+      all_tabs.insert(all_tabs.end(), t_k.begin(), t_k.end());
+      while (all_tabs.size() % 16) all_tabs.push_back(0);
+      rs.out = next_actual++;
+      inter_off.push_back(ws_shared);
+      inter_shared.push_back(1);
+      ws_shared += (R * K + 63) / 64 * 64;
+      plan->steps.push_back(rs);
+      // the copy's strides: rows in the listed order (last fastest), then k * R
+      std::map<int, int64_t> ns;
+      int64_t acc = 1;
+      for (int j = (int)rows.size() - 1; j >= 0; --j) {
+        ns[rows[j]] = acc;
+        acc *= dims.at(rows[j]);
+      }
+      for (int j = (int)kk.size() - 1; j >= 0; --j) {
+        ns[kk[j]] = acc;
+        acc *= dims.at(kk[j]);
+      }
+      l.str = ns;
+      return rs.out;
+    };
+    static const bool relayout_on = !getenv("TTN_PLAN_NO_RELAYOUT");
+    if (relayout_on && !g.a_mfast && la.id < (int)in.size() && !la.batched && !ml.empty()) {
+      const int r = relayout(la, ml, M);
+      if (r >= 0) {
+        stp.a = r;
+        g.a_mfast = true;
+      }
+    }
+    if (relayout_on && !g.b_nfast && lb.id < (int)in.size() && !lb.batched && !nl.empty()) {
+      const int r = relayout(lb, nl, N);
+      if (r >= 0) {
+        stp.b = r;
+        g.b_nfast = true;
+      }
+    }
+    // the stage's own output slot (after any relayout slots: stage outputs
+    // are numbered in stage order)
+    if (!last) {
+      stp.out = next_actual++;
+      act[lo.id] = stp.out;
+      const int64_t acc = stp.out_size;
+      if (stp.batched) {
+        inter_off.push_back(ws_item);
+        inter_shared.push_back(0);
+        ws_item += (acc + 63) / 64 * 64;
+      } else {
+        inter_off.push_back(ws_shared);
+        inter_shared.push_back(1);
+        ws_shared += (acc + 63) / 64 * 64;
+      }
+    } else {
+      stp.out = -1;
+    }
     // tables
     std::vector<int32_t> t_am, t_ak, t_bk, t_bn, t_cm, t_cn;
     group_offsets(ml, dims, la.str, t_am);
@@ -400,11 +492,6 @@ std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<in
       // pad each table to 16 entries for alignment
       while (all_tabs.size() % 16) all_tabs.push_back(0);
     }
-    auto vmax = [](const std::vector<int32_t>& v) {
-      int64_t m = 0;
-      for (int32_t x : v) m = std::max<int64_t>(m, x);
-      return m;
-    };
     stp.max_a = vmax(t_am) + vmax(t_ak);
     stp.max_b = vmax(t_bk) + vmax(t_bn);
     stp.max_c = vmax(t_cm) + vmax(t_cn);
@@ -418,7 +505,15 @@ std::unique_ptr<Plan> make_plan(const std::vector<Tensor>& in, const std::map<in
     }
     g.tile = splitk_eligible(g, ctype)   ? 8
              : narrow_eligible(g, ctype) ? 9
-                                         : pick_tile(g.M, g.N, g.K, stp.batched ? batch : 1.0);
+                                         : pick_tile(g.M, g.N, g.K, stp.batched ? batch : 1.0, tn_eligible(g, ctype));
+    // a tile forced for tests and tuning experiments (read at planning time),
+    // taken where the stage admits it
+    if (const char* ft = getenv("TTN_FORCE_TILE")) {
+      const int t = atoi(ft);
+      const bool ok = (t >= 0 && t <= 6) || (t == 8 && splitk_eligible(g, ctype)) ||
+                      (t == 9 && narrow_eligible(g, ctype)) || (t >= 10 && t <= 16 && tn_eligible(g, ctype));
+      if (ok) g.tile = t;
+    }
     if (stp.batched) plan->flops_per_item += stp.flops;
     else plan->flops_shared += stp.flops;
     plan->steps.push_back(stp);
@@ -466,7 +561,7 @@ bool check_plan_bounds(const Plan& P, const std::vector<int64_t>& in_elems, int6
     if (s.out >= 0) size[s.out] = s.out_size;
   for (const Step& s : P.steps) {
     const int64_t cs = s.out >= 0 ? s.out_size : out_elems;
-    if (s.max_a >= size.at(s.a) || s.max_b >= size.at(s.b) || s.max_c >= cs) {
+    if (s.max_a >= size.at(s.a) || (s.b >= 0 && s.max_b >= size.at(s.b)) || s.max_c >= cs) {
       why = "contraction stage would address outside its operands";
       return false;
     }

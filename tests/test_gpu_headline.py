@@ -93,7 +93,8 @@ def test_env_update_gram_edge_binary64_level1(api, ctx):
     print(f"U2 level-1 -> root, {len(pairs)} pairs: relative errors {errs}")
     assert max(errs) < GATE[1], errs
     kernels = {r[2] for r in recs}
-    assert any(kn.startswith("ogemm_kernel<1, 128, 128") for kn in kernels), kernels
+    # a 128 x 128 tile: the general one, or the unit-stride-k one where both operands run along k
+    assert any(kn.startswith(("ogemm_kernel<1, 128, 128", "ogemm_tn_kernel<128, 128")) for kn in kernels), kernels
     batched = [r for r in recs if r[9] > 1]
     assert any(r[9] >= 256 for r in batched), [r[9] for r in batched]          # XCD-aware mapping
     assert any(r[3] > 1 for r in batched), [(r[2], r[3], r[9]) for r in batched]  # chunked: several launches
