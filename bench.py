@@ -758,6 +758,68 @@ def trace_summary(path: str, kernel: str):
             print(f"| {grid} | {len(d)} | {np.mean(d):.1f} | {np.median(d):.1f} |")
 
 
+def pmc_summary(out: str):
+    """Markdown summary of rocprofv3 counter passes over `bench.py
+    --heff-probe` (directories out/heff_p*/ with heff_counter_collection.csv,
+    the probe's JSON line in out/heff_p1.log) and of the copy calibration
+    (out/copy_FETCH_SIZE/, out/copy_WRITE_SIZE/): per kernel, the mean per
+    dispatch of every counter, HBM bytes from FETCH_SIZE / WRITE_SIZE scaled by
+    the copy, MFMA utilisation and executed MFMA flops; then one
+    traffic|kernel|gemm hash|measured bytes|algorithmic bytes line per kernel."""
+    import csv
+    import glob
+    per = {}
+    for f in sorted(glob.glob(os.path.join(out, "heff_p*", "heff_counter_collection.csv"))):
+        for r in csv.DictReader(open(f)):
+            per.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    cal = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        f = os.path.join(out, f"copy_{c}", "copy_counter_collection.csv")
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(f)) if "copyBuffer" in r["Kernel_Name"]]
+        cal[c] = (256 << 20) / (float(np.median(vals)) * 1024)  # bytes per KiB reported, for a 256 MiB copy
+    probe = None
+    for line in open(os.path.join(out, "heff_p1.log")):
+        if line.startswith('{"heff_probe"'):
+            probe = json.loads(line)
+    short = lambda k: k.replace("void ttn::", "").split("(")[0]
+    print(f"Copy calibration (256 MiB device copy): FETCH_SIZE x {cal['FETCH_SIZE']:.3f} KiB, "
+          f"WRITE_SIZE x {cal['WRITE_SIZE']:.3f} KiB = bytes\n")
+    print("| kernel | dispatches | HBM read MB | HBM write MB | algorithmic MB | traffic / algorithmic | MFMA busy "
+          "(of GRBM_GUI_ACTIVE x 1024 SIMDs) | MFMA flops executed / algorithmic |")
+    print("|---|---|---|---|---|---|---|---|")
+    lines = []
+    h = gemm_source_hash()
+    for name, cs in per.items():
+        kn = short(name)
+        if not (kn.startswith("ogemm") or kn.startswith("relayout")):
+            continue
+        m = {c: float(np.mean(v)) for c, v in cs.items()}
+        rd = m.get("FETCH_SIZE", 0.0) * 1024 * cal["FETCH_SIZE"]
+        wr = m.get("WRITE_SIZE", 0.0) * 1024 * cal["WRITE_SIZE"]
+        pk = (probe or {}).get("kernels", {}).get(kn)
+        alg = pk["algorithmic_bytes_per_launch"] if pk else None
+        alg_fl = pk["algorithmic_flop_per_launch"] if pk else None
+        util = (m["SQ_VALU_MFMA_BUSY_CYCLES"] / (m["GRBM_GUI_ACTIVE"] / 8 * 1024)
+                if m.get("GRBM_GUI_ACTIVE") else float("nan"))
+        exe = m.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) * 512
+        print(f"| {kn} | {len(next(iter(cs.values())))} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | "
+              f"{alg / 1e6 if alg else float('nan'):.1f} | {(rd + wr) / alg if alg else float('nan'):.3f} | "
+              f"{util:.3f} | {exe / alg_fl if alg_fl else float('nan'):.3f} |")
+        if alg:
+            lines.append(f"traffic|{kn}|{h}|{rd + wr:.6e}|{alg:.6e}")
+    print("\nOther counters, mean per dispatch:\n")
+    for name, cs in per.items():
+        kn = short(name)
+        if not kn.startswith("ogemm"):
+            continue
+        print(f"* {kn}: " + ", ".join(f"{c} {np.mean(v):.4g}" for c, v in sorted(cs.items())))
+    print("\nGEMM source hash (sha256[:16] of csrc/gemm.hip): " + h + "\n")
+    print("```")
+    for l in lines:
+        print(l)
+    print("```")
+
+
 def cpu_baseline(api, ctx, s, u: int, k: int, reps: int = 5):
     """The FP64 oracle timed on the host at the headline node u: U1 = K2
     (one state's H_eff apply) and U2 = K1 (one pair's environment update
@@ -895,6 +957,8 @@ def main():
     ap.add_argument("--heff-probe", action="store_true", help="run only the headline heff_apply_block calls")
     ap.add_argument("--trace-summary", default=None, help="summarise a rocprofv3 kernel_trace.csv and exit")
     ap.add_argument("--trace-kernel", default="ogemm_kernel", help="kernel-name prefix broken down by grid")
+    ap.add_argument("--pmc-summary", default=None,
+                    help="summarise rocprofv3 counter passes over --heff-probe (directory of the passes) and exit")
     args = ap.parse_args()
     if args.graphs and args.warmup < 2:
         args.warmup = 2  # first step runs eagerly, the second captures: keep both untimed
@@ -903,6 +967,9 @@ def main():
         return
     if args.trace_summary:
         trace_summary(args.trace_summary, args.trace_kernel)
+        return
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path, so --gpus must be 1",

@@ -62,6 +62,30 @@ __device__ __forceinline__ int64_t batch_off(const KOp& o, int z, int z0, int* f
   }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2): linear id g runs on XCD g % 8.  With the XCD mapping on, the launch's
+// (item, tile) list -- items in order, tiles of an item row by row -- is cut
+// into 8 contiguous chunks and XCD x walks chunk x in order, so the
+// workgroups in flight on one XCD work on one or two items and share their
+// operand panels in that XCD's L2, and the XCDs get equal shares (measured
+// on the 50-item 864 x 576 x 1008 stage: HBM reads 1.6 GB -> 0.46 GB per
+// launch).  Off: a 2-D grid (tile, item).  Returns false for the padding
+// workgroups of the last chunk.
+__device__ __forceinline__ bool xcd_tile(const KArgs& g, int& z, int& tile) {
+  if (g.xcd_remap) {
+    const int total = g.tiles * g.nz;
+    const int chunk = (total + 7) / 8;
+    const int lin = (int)(blockIdx.x & 7) * chunk + (int)(blockIdx.x >> 3);
+    if (lin >= total) return false;
+    z = lin / g.tiles;
+    tile = lin - z * g.tiles;
+  } else {
+    z = blockIdx.y;
+    tile = blockIdx.x;
+  }
+  return true;
+}
+
 template <int CT>
 struct Types;
 template <>
@@ -124,22 +148,8 @@ __global__ __launch_bounds__(256, (CT == 1) ? 3 : 2) void ogemm_kernel(KArgs g) 
   const int lane = tid & 63;
   const int wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
-  // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-  // L2).  With many batch items, linear id g runs on XCD g % 8, so items are
-  // dealt to XCDs (item = 8 * (local / tiles) + g % 8) and every tile of one
-  // item shares one L2; with few items the tiles of an item spread instead.
   int z, tile;
-  if (g.xcd_remap) {
-    const int gid = blockIdx.x;
-    const int local = gid >> 3;
-    const int grp = local / g.tiles;
-    tile = local - grp * g.tiles;
-    z = grp * 8 + (gid & 7);
-    if (z >= g.nz) return;
-  } else {
-    z = blockIdx.y;
-    tile = blockIdx.x;
-  }
+  if (!xcd_tile(g, z, tile)) return;
   const int tmi = tile / g.tiles_n;
   const int tni = tile - tmi * g.tiles_n;
   const int m0 = tmi * BM, n0 = tni * BN;
@@ -428,17 +438,7 @@ __global__ __launch_bounds__(256, 2) void ogemm_tn_kernel(KArgs g) {
   const int wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
   int z, tile;
-  if (g.xcd_remap) {
-    const int gid = blockIdx.x;
-    const int local = gid >> 3;
-    const int grp = local / g.tiles;
-    tile = local - grp * g.tiles;
-    z = grp * 8 + (gid & 7);
-    if (z >= g.nz) return;
-  } else {
-    z = blockIdx.y;
-    tile = blockIdx.x;
-  }
+  if (!xcd_tile(g, z, tile)) return;
   const int tmi = tile / g.tiles_n;
   const int tni = tile - tmi * g.tiles_n;
   const int m0 = tmi * BM, n0 = tni * BN;
@@ -967,9 +967,9 @@ static hipError_t launch_cfg(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s
   a.tiles_n = tn;
   a.tiles = tm * tn;
   a.nz = nz;
-  static const int remap_min = env_int("TTN_XCD_REMAP_MIN", 256);
-  a.xcd_remap = nz >= remap_min ? 1 : 0;
-  dim3 grid = a.xcd_remap ? dim3((unsigned)(((nz + 7) / 8) * 8 * a.tiles), 1) : dim3(tm * tn, nz);
+  static const int remap_min = env_int("TTN_XCD_REMAP_MIN", 16);  // workgroups: below that one XCD round
+  a.xcd_remap = (int64_t)a.tiles * nz >= remap_min ? 1 : 0;
+  dim3 grid = a.xcd_remap ? dim3((unsigned)(((int64_t)a.tiles * nz + 7) / 8 * 8), 1) : dim3(tm * tn, nz);
   const size_t kt = gd.K <= KCAP ? (size_t)2 * gd.K * sizeof(int) : 0;  // k-offset tables in LDS
   if (gd.c_mfast) {
     if (gd.a_mfast && gd.b_nfast) hipLaunchKernelGGL((ogemm_kernel<CT, BM, BN, BK, true, true, true>), grid, dim3(256), kt, s, a);
@@ -1006,9 +1006,9 @@ static hipError_t launch_tn(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s)
   a.tiles_n = tn;
   a.tiles = tm * tn;
   a.nz = nz;
-  static const int remap_min = env_int("TTN_XCD_REMAP_MIN", 256);
-  a.xcd_remap = nz >= remap_min ? 1 : 0;
-  dim3 grid = a.xcd_remap ? dim3((unsigned)(((nz + 7) / 8) * 8 * a.tiles), 1) : dim3(tm * tn, nz);
+  static const int remap_min = env_int("TTN_XCD_REMAP_MIN", 16);  // workgroups: below that one XCD round
+  a.xcd_remap = (int64_t)a.tiles * nz >= remap_min ? 1 : 0;
+  dim3 grid = a.xcd_remap ? dim3((unsigned)(((int64_t)a.tiles * nz + 7) / 8 * 8), 1) : dim3(tm * tn, nz);
   if (gd.c_mfast) hipLaunchKernelGGL((ogemm_tn_kernel<BM, BN, true>), grid, dim3(256), 0, s, a);
   else hipLaunchKernelGGL((ogemm_tn_kernel<BM, BN, false>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
