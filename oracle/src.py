@@ -59,17 +59,13 @@ def _post_order(tree) -> List[int]:
     return out
 
 
-def src_apply(tree, W, x, omegas: Sequence[np.ndarray], chi: int):
-    """y ~ H x with bond dimension chi (Sec. II.C.1).  omegas[u] is the
-    d_u x chi Gaussian test matrix of physical node u (ignored at auxiliary
-    nodes).  Returns (y, bonds) with y canonical at the root and bonds[u] the
-    dimension of edge (u, parent(u))."""
-    # 1. all environments of <omega_l| H |x>
+def sketch_envs(tree, W, x, omegas: Sequence[np.ndarray], n: int) -> List[Dict[Tuple[int, int], np.ndarray]]:
+    """Step 1: for every sketch column l < n, the environments of
+    <omega_l| H |x> on every directed edge (toward the root, then away)."""
     sk: List[Dict[Tuple[int, int], np.ndarray]] = []
-    for l in range(chi):
+    for l in range(n):
         om = _omega_state(tree, omegas, l)
         envs: Dict[Tuple[int, int], np.ndarray] = {}
-        # upward (toward the root), then downward
         for u in _post_order(tree):
             p = tree.parent[u]
             if p >= 0:
@@ -80,6 +76,16 @@ def src_apply(tree, W, x, omegas: Sequence[np.ndarray], chi: int):
                 ein = {v: envs[(v, u)] for v in ttn.nbrs(tree, u) if v != c}
                 envs[(u, c)] = ttn.env_update(tree, u, c, om[u], W[u], x[u], ein)
         sk.append(envs)
+    return sk
+
+
+def src_apply(tree, W, x, omegas: Sequence[np.ndarray], chi: int):
+    """y ~ H x with bond dimension chi (Sec. II.C.1).  omegas[u] is the
+    d_u x chi Gaussian test matrix of physical node u (ignored at auxiliary
+    nodes).  Returns (y, bonds) with y canonical at the root and bonds[u] the
+    dimension of edge (u, parent(u))."""
+    # 1. all environments of <omega_l| H |x>
+    sk = sketch_envs(tree, W, x, omegas, chi)
     # 2.-3. leaves to root
     y: List[np.ndarray] = [None] * tree.n  # type: ignore[list-item]
     B: Dict[int, np.ndarray] = {}           # B_{u -> parent(u)}[q, w, a]

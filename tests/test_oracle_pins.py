@@ -568,3 +568,91 @@ def test_src_of_identity_operator_returns_the_state():
     nx = ttn.expectation(tree, x, None, x)
     assert abs(ov - nx) < 1e-10 * nx
     assert abs(ttn.expectation(tree, y, None, y) - nx) < 1e-10 * nx
+
+
+# ------------------------------------------------------------- bond expansion (Sec. II.C.2, III.B)
+
+def _expansion_trees(dims):
+    return {"mps": wl.mps_tree(dims, 1), "binary": wl.binary_tree(dims), "fork": wl.fork_tree(dims, 2, 1)}
+
+
+@pytest.mark.parametrize("kind", ["mps", "binary", "fork"])
+def test_expansion_keeps_the_state(kind):
+    """Growing every bond (1 -> up to 9) keeps the state exactly, every
+    non-root tensor an isometry toward its parent, the bonds as requested."""
+    from oracle import expand
+    m = wl.coupled_oscillators(4, 5, 500, 3000, 3, n_cubic=2)
+    tree = _expansion_trees(m.dims)[kind]
+    W = ttno.build_ttno(tree, m)
+    lo = [max(1, b) for b in wl.bond_dims(tree, 1)]
+    hi = [max(1, b) for b in wl.bond_dims(tree, 9)]
+    x = ttn.canonicalize(tree, wl.random_block(tree, lo, 1, 3)[0], tree.root)
+    y = expand.expand_bonds(tree, W, x, hi, wl.sketch_matrices(tree, 10, 4), 10)
+    dx, dy = ttn.to_dense(tree, x), ttn.to_dense(tree, y)
+    assert np.linalg.norm(dy - dx) < 1e-12 * np.linalg.norm(dx)
+    for u in range(tree.n):
+        if u == tree.root:
+            continue
+        assert y[u].shape[0] == hi[u]
+        Y = y[u].reshape(hi[u], -1)
+        assert np.abs(Y @ Y.T - np.eye(hi[u])).max() < 1e-12
+
+
+def _grown_basis(tree, y):
+    """Dense images of the root's unit tensors: the span of states that share
+    y's non-root tensors."""
+    r = tree.root
+    cols = []
+    for i in range(y[r].size):
+        e = np.zeros(y[r].size)
+        e[i] = 1.0
+        z = list(y)
+        z[r] = e.reshape(y[r].shape)
+        cols.append(ttn.to_dense(tree, z))
+    return np.stack(cols, axis=1)
+
+
+@pytest.mark.parametrize("kind", ["mps", "binary", "fork"])
+def test_expansion_captures_hx_of_a_one_body_model(kind):
+    """For a Hamiltonian of one-body terms and a product state x, H x has
+    Schmidt rank 2 across every edge (x on one side, the one-body part applied
+    on the other), so growing every bond from 1 by one direction must make H x
+    exactly representable in the grown basis.  A wrong leg, a stale <y|H|x>
+    environment or a missing projection leaves part of H x outside."""
+    from oracle import expand
+    rng = np.random.default_rng(11)
+    L = 4
+    model = wl.SOPModel("one-body", omega=np.array([700.0, 1300.0, 1900.0, 2600.0]), dims=[3] * L,
+                        monomials=[((i, 1),) for i in range(L)] + [((i, 3),) for i in range(L)],
+                        coefs=rng.normal(0.0, 30.0, size=2 * L))
+    tree = _expansion_trees(model.dims)[kind]
+    W = ttno.build_ttno(tree, model)
+    one = [1] * tree.n
+    two = [max(1, b) for b in wl.bond_dims(tree, 2)]
+    x = ttn.canonicalize(tree, wl.random_block(tree, one, 1, 5)[0], tree.root)
+    y = expand.expand_bonds(tree, W, x, two, wl.sketch_matrices(tree, 2, 6), 2)
+    h = exact.sop_dense_matrix(model) @ ttn.to_dense(tree, x)
+    Phi = _grown_basis(tree, y)
+    proj = Phi @ (Phi.T @ h)
+    assert np.linalg.norm(proj - h) < 1e-10 * np.linalg.norm(h)
+    # without growth H x is not representable (the test is not vacuous)
+    Phi0 = _grown_basis(tree, x)
+    assert np.linalg.norm(Phi0 @ (Phi0.T @ h) - h) > 1e-3 * np.linalg.norm(h)
+
+
+def test_pivoted_completion_reduces_to_lapack_pivoted_qr():
+    """With the leading block Q and a sketch S of full rank, the completion is
+    the column-pivoted QR (LAPACK dgeqp3) of S projected outside span(Q):
+    same pivot order, same orthonormal columns once diag(R) >= 0."""
+    import scipy.linalg
+    from oracle import expand
+    rng = np.random.default_rng(3)
+    m, D, n, grow = 40, 5, 9, 7
+    Q, _ = np.linalg.qr(rng.normal(size=(m, D)))
+    S = rng.normal(size=(m, n)) * np.linspace(1.0, 3.0, n)[None, :]
+    P = expand.pivoted_completion(Q, S, grow)
+    Sp = S - Q @ (Q.T @ S)
+    Qs, Rs, _ = scipy.linalg.qr(Sp, mode="economic", pivoting=True)
+    ref = Qs[:, :grow] * np.where(np.diag(Rs)[:grow] < 0, -1.0, 1.0)[None, :]
+    assert np.abs(P - ref).max() < 1e-12
+    assert np.abs(Q.T @ P).max() < 1e-13

@@ -11,7 +11,7 @@ block to canonical form with its own QR.
 from __future__ import annotations
 
 import heapq
-from typing import List, Sequence, Tuple
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -79,3 +79,10 @@ def random_block(tree: Tree, bonds: Sequence[int], k: int, seed: int) -> List[Li
     """k dense random states (N(0,1) entries) with the tree's shapes."""
     rng = np.random.default_rng(seed)
     return [[rng.normal(0.0, 1.0, size=node_shape(tree, bonds, u)) for u in range(tree.n)] for _ in range(k)]
+
+
+def sketch_matrices(tree: Tree, n: int, seed: int) -> List[Optional[np.ndarray]]:
+    """Gaussian test matrices of a Khatri-Rao sketch: [d_u x n] N(0, 1) at
+    every physical node (None at auxiliary nodes), drawn node by node."""
+    rng = np.random.default_rng(seed)
+    return [rng.normal(0.0, 1.0, size=(tree.phys[u], n)) if tree.phys[u] > 1 else None for u in range(tree.n)]
