@@ -366,6 +366,33 @@ ttn_status ttn_src_apply(ttn_ctx* ctx, ttn_src* s, const void* const* omega);
 /* Synchronises the context stream, then frees the handle. */
 ttn_status ttn_src_destroy(ttn_src* s);
 
+/* ------------------------------------------------------------ bond expansion */
+
+/* Grows the bonds of the k states of x into y (y's bonds >= x's, at most
+ * n_sketch larger on every edge, each within its node's local space) keeping
+ * every state exactly: the dynamic bond dimensions of variational fitting
+ * (Sec. II.C.2: local residual, rank-revealing QR, expansion), applied where
+ * the maximum bond grows between the LOBPCG and inverse-iteration stages
+ * (Sec. III.B).  From the leaves to the root, at each non-root node u: the
+ * local x_u with its children legs in y's bases and its parent leg open is
+ * QR-factorised (basis Q_x); the local H x is sketched on the parent leg with
+ * n_sketch Khatri-Rao columns (row l of omega[u], device, [n_sketch][phys_u]
+ * in the tensors' dtype, drawn by the caller; ignored at auxiliary nodes --
+ * the same sketch as ttn_src); a Householder QR of [Q_x | sketch] with Q_x
+ * first and unpivoted, then y->D[u] - x->D[u] steps pivoting on the largest
+ * remaining column norm (first on ties), gives the new directions (diag(R) >= 0)
+ * and y_u = [Q_x, new directions].  The root takes x_root in the children's new
+ * bases, so y is canonical at the root and equal to x as a vector.  x, y and
+ * the operator share one dtype; compute TTN_F64 or TTN_F32.  ttn_expand_create
+ * allocates the sketch environments (k * n_sketch slots per directed edge) and
+ * the per-node work buffers; ttn_expand_apply allocates nothing. */
+typedef struct ttn_expand ttn_expand;
+ttn_status ttn_expand_create(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_block* x, ttn_block* y,
+                             int32_t n_sketch, ttn_dtype compute, ttn_expand** out);
+ttn_status ttn_expand_apply(ttn_ctx* ctx, ttn_expand* e, const void* const* omega);
+/* Synchronises the context stream, then frees the handle. */
+ttn_status ttn_expand_destroy(ttn_expand* e);
+
 /* ------------------------------------------------------------ operator compiler (host) */
 
 /* Sum-of-products -> TTNO in FP64 on the host (Sec. II.A.3, Eq. sum_of_tp):

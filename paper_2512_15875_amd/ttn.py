@@ -72,6 +72,9 @@ _SIGS = {
     "ttn_src_create": [_P, _P, _P, _P, _P, _I, C.c_int, _P],
     "ttn_src_apply": [_P, _P, _P],
     "ttn_src_destroy": [_P],
+    "ttn_expand_create": [_P, _P, _P, _P, _P, _I, C.c_int, _P],
+    "ttn_expand_apply": [_P, _P, _P],
+    "ttn_expand_destroy": [_P],
     "ttn_ctx_profile_filter": [_P, _I, _P],
     "ttn_ctx_probe_heff": [_P, _I, _P],
     "ttn_ctx_probe_report": [_P, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)],
@@ -584,6 +587,34 @@ class Src:
     def close(self):
         if self.h:
             lib().ttn_src_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Expand:
+    """Bond expansion x -> y (larger bonds, same states) from the residual of
+    the local H x (ttn_expand_*)."""
+
+    def __init__(self, ctx: Context, tree: Tree, op: "TTNO", x: "Block", y: "Block", n_sketch: int, compute: int):
+        self.ctx, self.tree, self.n = ctx, tree, n_sketch
+        self.h = C.c_void_p()
+        _check(lib().ttn_expand_create(ctx.h, tree.h, op.h, x.h, y.h, int(n_sketch), int(compute),
+                                       C.byref(self.h)), ctx)
+
+    def apply(self, omegas: Sequence[Optional[torch.Tensor]]):
+        """omegas[u]: device [n_sketch][phys_u] sketch rows of physical node u (None at auxiliary nodes)."""
+        self._keep = list(omegas)
+        arr = _ptrs([None if o is None else o.data_ptr() for o in omegas])
+        _check(lib().ttn_expand_apply(self.ctx.h, self.h, C.cast(arr, C.c_void_p)), self.ctx)
+
+    def close(self):
+        if self.h:
+            lib().ttn_expand_destroy(self.h)
             self.h = C.c_void_p()
 
     def __del__(self):
