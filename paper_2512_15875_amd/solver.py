@@ -104,6 +104,7 @@ class TTNEigensolver:
         # the host compiler's TTNO (or a prebuilt one: (site tensors, operator bonds))
         W, M = ttno if ttno is not None else build_ttno(self.gt, tree, model)
         self.M = [max(1, m) for m in M]
+        self._model, self._precision, self._ttno_host, self._pre_compute = model, precision, (W, M), pre_compute
         self.sdt = ttn.F64 if precision in ("fp64", "f64_f32") else ttn.F32
         # bulk compute type, and the one of the exact quantities (S~, Rayleigh quotients)
         self.compute = {"fp64": ttn.F64, "fp32": ttn.F32, "bf16": ttn.BF16, "f64_f32": ttn.F64_F32}[precision]
@@ -385,6 +386,48 @@ class TTNEigensolver:
             if not self.lobpcg_step(log):
                 break
         return self.lam_d.cpu().numpy() + self.zpe
+
+    # ------------------------------------------------------------ bond growth
+
+    def grow(self, D: int, n_sketch: Optional[int] = None, omegas=None, seed: int = 0) -> "TTNEigensolver":
+        """A solver at the larger bond dimension D holding this solver's k
+        states grown by the residual-driven expansion (ttn_expand: the current
+        bases kept, each bond's new directions from a rank-revealing QR of the
+        local residual of H x), with the same Rayleigh quotients, shift and
+        options; the LOBPCG search directions are not carried over.  omegas:
+        host [d_u x n_sketch] sketch matrices per node (None at auxiliary
+        nodes), else drawn on the device from `seed`."""
+        ctx, k = self.ctx, self.k
+        hi = TTNEigensolver(ctx, self.wtree, self._model, D, k, self._precision, graphs=self.graphs,
+                            ttno=self._ttno_host, pre_compute=self._pre_compute)
+        growth = max(h - l for u, (h, l) in enumerate(zip(hi.bonds, self.bonds)) if u != self.root)
+        n = n_sketch if n_sketch is not None else max(1, growth)
+        XS = ttn.Block(ctx, self.gt, k, self.bonds, self.sdt)
+        YS = ttn.Block(ctx, self.gt, k, hi.bonds, self.sdt)
+        self._copy_rows(XS, 0, self.B, 0, k)
+        if omegas is None:
+            gen = torch.Generator(device="cuda")
+            gen.manual_seed(seed)
+            om = [torch.randn(n, self.gt.phys[u], generator=gen, device="cuda", dtype=self.tdt)
+                  if self.gt.phys[u] > 1 else None for u in range(self.gt.n)]
+        else:
+            om = [torch.from_numpy(np.ascontiguousarray(np.asarray(o).T)).to(device="cuda", dtype=self.tdt)
+                  if o is not None else None for u, o in enumerate(omegas)]
+        ex = ttn.Expand(ctx, self.gt, self.op, XS, YS, n, ttn.F64 if self.sdt == ttn.F64 else ttn.F32)
+        ex.apply(om)
+        for u in range(self.gt.n):
+            hi.B.t[u][:k].copy_(YS.t[u])
+            hi.B.t[u][k:].zero_()
+        ex.close()
+        hi._canonicalize(hi.B)
+        ttn.block_normalize_node(ctx, hi.B, hi.root, hi.norms)
+        hi.lam_d.copy_(hi.rayleigh_quotients(hi.B, list(range(k))))
+        hi.shift_d.copy_(self.shift_d)
+        hi._opts = getattr(self, "_opts", None)
+        hi._have_p = False
+        hi._it = getattr(self, "_it", 0)
+        hi._t0 = getattr(self, "_t0", time.perf_counter())
+        return hi
 
     # ------------------------------------------------------------ inverse iteration
 

@@ -48,6 +48,37 @@ def c1_runs():
     return out
 
 
+def c1_grow_runs(D_lo=4, D_hi=8, n_sketch=6, sketch_seed=31):
+    """c1: LOBPCG (3 iterations) at D_lo, every bond grown to D_hi by the
+    residual-driven expansion (Sec. II.C.2; the D 12 -> 20 step of Sec. III.B),
+    inverse iteration (2 iterations) at D_hi; and the same inverse iteration
+    at D_lo for comparison.  Sketch matrices: workloads.sketch_matrices."""
+    from oracle import expand
+    m = wl.make_config_model("c1")
+    tree = wl.mps_tree(m.dims, 2)
+    W = ttno.build_ttno(tree, m)
+    lo = wl.bond_dims(tree, D_lo)
+    hi = [max(1, b) for b in wl.bond_dims(tree, D_hi)]
+    x0 = wl.initial_block(tree, lo, m.omega, m.dims, 10, m.seed + 17)
+    lam0 = solvers.rayleigh_quotients(tree, W, [solvers.normalized(tree, x) for x in x0])
+    shift = float(np.min(lam0)) - 837.0
+    xs, lam = solvers.lobpcg(tree, W, x0, solvers.LobpcgOptions(n_iter=3, shift=shift))
+    om = wl.sketch_matrices(tree, n_sketch, sketch_seed)
+    ys = [expand.expand_bonds(tree, W, solvers.normalized(tree, x), hi, om, n_sketch) for x in xs]
+    iih = []
+    _, theta = solvers.inverse_iteration(tree, W, ys, lam, solvers.IIOptions(n_iter=2, monotone=False), iih)
+    _, theta_lo = solvers.inverse_iteration(tree, W, xs, lam, solvers.IIOptions(n_iter=2, monotone=False))
+    return {"cite": f"c1 oracle: block LOBPCG 3 iterations at D={D_lo}, bonds grown to D={D_hi} by the residual-"
+                    f"driven expansion (sketch {n_sketch} columns, workloads.sketch_matrices seed {sketch_seed}), "
+                    f"block inverse iteration 2 iterations at D={D_hi} (and at D={D_lo} for comparison)",
+            "zpe": m.zpe_harmonic, "shift": shift, "D_lo": D_lo, "D_hi": D_hi, "n_sketch": n_sketch,
+            "sketch_seed": sketch_seed, "lobpcg3_lam": list(map(float, lam)),
+            "grown_lam": list(map(float, solvers.rayleigh_quotients(tree, W, ys))),
+            "ii_lam_history": [list(map(float, h["lam"])) for h in iih],
+            "ii_final_rr": list(map(float, theta)), "ii_lo_final_rr": list(map(float, theta_lo)),
+            "exact": list(map(float, exact.normal_mode_levels(m, 10)))}
+
+
 def c3_cluster_runs(seed=7, D=8, k=12):
     """Fork-4 comb from the quartic-force-field generator at a small bond
     dimension, with a seed whose Rayleigh quotients after LOBPCG hold two
@@ -136,12 +167,17 @@ def e1_runs(D=5, k=8, n_iter=2, n_exact=30):
 
 
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["c1", "c3_cluster", "topologies", "e1"]
+    which = sys.argv[1:] or ["c1", "c1_grow", "c3_cluster", "topologies", "e1"]
     if "c1" in which:
         res = c1_runs()
         with open(os.path.join(HERE, "c1_oracle_runs.json"), "w") as f:
             json.dump(res, f, indent=1)
         print("wrote c1_oracle_runs.json")
+    if "c1_grow" in which:
+        res = c1_grow_runs()
+        with open(os.path.join(HERE, "c1_grow_oracle_runs.json"), "w") as f:
+            json.dump(res, f, indent=1)
+        print("wrote c1_grow_oracle_runs.json")
     if "c3_cluster" in which:
         res = c3_cluster_runs()
         with open(os.path.join(HERE, "c3s7_cluster_oracle_runs.json"), "w") as f:
