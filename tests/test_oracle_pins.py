@@ -656,3 +656,54 @@ def test_pivoted_completion_reduces_to_lapack_pivoted_qr():
     ref = Qs[:, :grow] * np.where(np.diag(Rs)[:grow] < 0, -1.0, 1.0)[None, :]
     assert np.abs(P - ref).max() < 1e-12
     assert np.abs(Q.T @ P).max() < 1e-13
+
+
+# ------------------------------------------------------------- state-diagram TTNO (Sec. II.A.3)
+
+@pytest.mark.parametrize("case", [(4, 3, 2), (5, 2, 4), (6, 2, 10)])
+@pytest.mark.parametrize("kind", ["mps", "binary", "fork"])
+def test_state_diagram_ttno_is_the_sop_operator(case, kind):
+    """The state-diagram TTNO contracts to the Kronecker sum of products on
+    tiny trees (chains and branching trees; without the forced
+    coefficient-free channels of merged items the branching trees fail by
+    ~2e3 relative), and its bonds are the operator Schmidt ranks (SVD of the
+    dense operator's bipartitions, via the compressed build) -- terms with
+    generic coefficients have no algebraic shortcut that a vertex cover
+    misses."""
+    from oracle import statediagram as sd
+    L, d, nc = case
+    m = wl.coupled_oscillators(L, L + 3, 500, 3000, d, n_cubic=nc)
+    tree = {"mps": wl.mps_tree(m.dims, 1), "binary": wl.binary_tree(m.dims), "fork": wl.fork_tree(m.dims, 2, 1)}[kind]
+    W = sd.state_diagram_ttno(tree, m)
+    H = exact.sop_dense_matrix(m)
+    assert np.abs(ttno.ttno_to_dense(tree, W) - H).max() < 1e-13 * np.abs(H).max()
+    assert ttno.ttno_bonds(tree, W) == ttno.ttno_bonds(tree, ttno.build_ttno(tree, m))
+
+
+def test_min_vertex_cover_against_brute_force():
+    """Konig's cover from the augmenting-path matching is a vertex cover of
+    minimum size (all subsets enumerated on random bipartite graphs up to
+    6 + 6 vertices), also with forced left vertices."""
+    import itertools
+    from oracle import statediagram as sd
+    rng = np.random.default_rng(5)
+    for trial in range(200):
+        nl, nr = rng.integers(1, 7, size=2)
+        adj = [sorted(set(rng.choice(nr, size=rng.integers(0, nr + 1), replace=True).tolist())) for _ in range(nl)]
+        forced = [l for l in range(nl) if rng.random() < 0.2]
+        cl, cr = sd.min_vertex_cover(nl, nr, adj, forced)
+        edges = [(l, r) for l in range(nl) for r in adj[l]]
+        assert all(l in cl or r in cr for l, r in edges), trial
+        assert set(forced) <= set(cl)
+        best = None
+        verts = [("l", l) for l in range(nl) if l not in forced] + [("r", r) for r in range(nr)]
+        for size in range(len(verts) + 1):
+            for S in itertools.combinations(verts, size):
+                L = set(forced) | {v for t, v in S if t == "l"}
+                R = {v for t, v in S if t == "r"}
+                if all(l in L or r in R for l, r in edges):
+                    best = len(L) + len(R)
+                    break
+            if best is not None:
+                break
+        assert len(cl) + len(cr) == best, (trial, nl, nr, adj, forced)
