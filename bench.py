@@ -446,12 +446,15 @@ def e1_experiment(args):
     m = wl.paper_64d_model()
     out = {"experiment": "64-mode coupled oscillators (Sec. III.A)", "D": args.e1_bond, "k": args.e1_k,
            "iterations": args.e1_iters, "basis": "8 harmonic-oscillator functions per mode (FBR)", "runs": {}}
+    out["ttno"] = args.ttno_method
     for name in ("mps", "ttree"):
         ctx = api.Context(0, workspace_bytes=2 << 30)
         tree = wl.paper_topology(name, m.dims)
         bonds = wl.bond_dims(tree, args.e1_bond)
         x0 = wl.initial_block(tree, bonds, m.omega, m.dims, args.e1_k, 117)
-        s = TTNEigensolver(ctx, tree, m, D=args.e1_bond, k=args.e1_k, precision="fp64")
+        gt = api.Tree(tree.parent, tree.phys)
+        ttno = api.sop_build(gt, tree.mode, m.omega, m.dims, m.monomials, m.coefs, method=args.ttno_method)
+        s = TTNEigensolver(ctx, tree, m, D=args.e1_bond, k=args.e1_k, precision="fp64", ttno=ttno)
         s.load_block(x0)
         lam0 = s.rayleigh_quotients(s.B, list(range(args.e1_k))).cpu().numpy()
         torch.cuda.synchronize()
@@ -973,6 +976,8 @@ def main():
     ap.add_argument("--ii", action="store_true", help="run the inverse-iteration experiment instead")
     ap.add_argument("--e1", action="store_true", help="the paper's 64-mode coupled-oscillator reproduction")
     ap.add_argument("--e1-k", type=int, default=30)
+    ap.add_argument("--ttno-method", default="svd", choices=["svd", "state_diagram"],
+                    help="operator compiler of the --e1 runs")
     ap.add_argument("--e1-bond", type=int, default=5)
     ap.add_argument("--e1-iters", type=int, default=6)
     ap.add_argument("--topologies", action="store_true", help="the 12-mode topology comparison")

@@ -406,6 +406,21 @@ ttn_status ttn_sop_build(const ttn_tree* t, const int32_t* node_mode, int32_t n_
                          const int32_t* dims, int32_t n_mono, const int32_t* mono_ptr,
                          const int32_t* mono_mode, const int32_t* mono_pow, const double* coef,
                          double rel_tol, ttn_sop** out);
+/* The same operator from a state diagram (Sec. II.A.3): edges leaves to
+ * root, every term (or group of terms merged below) an edge of the bipartite
+ * graph between its descriptor inside the subtree (operator at the node and
+ * child channels) and its operator string outside; a minimum vertex cover
+ * (Konig, from an augmenting-path matching in order of first appearance)
+ * gives the channels -- covered descriptors coefficient-free, covered outside
+ * strings carrying the summed coefficient x descriptor of their terms, which
+ * merge there; terms merged in another branch take coefficient-free channels.
+ * No compression: the tensors keep the diagram's sparsity.  Bonds equal the
+ * operator Schmidt ranks for terms with generic coefficients; algebraic
+ * redundancy between coefficients (e.g. all couplings equal) is not seen.
+ * Same arguments as ttn_sop_build without rel_tol. */
+ttn_status ttn_sop_build_sd(const ttn_tree* t, const int32_t* node_mode, int32_t n_modes, const double* omega,
+                            const int32_t* dims, int32_t n_mono, const int32_t* mono_ptr,
+                            const int32_t* mono_mode, const int32_t* mono_pow, const double* coef, ttn_sop** out);
 /* op_bond[u] for every edge e(u) (root entry 0). */
 ttn_status ttn_sop_bonds(const ttn_sop* s, int32_t* op_bond);
 /* Copy node u's tensor (layout W_u above, FP64) into host buffer `out` of

@@ -21,6 +21,7 @@
 // zero-point energy removed) and q^k = the d x d block of (Q_{d+k})^k with
 // Q_m the position matrix in a basis of size m (an exact projection).
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -557,6 +558,281 @@ extern "C" ttn_status ttn_sop_build(const ttn_tree* t, const int32_t* node_mode,
         }
       }
     }
+  }
+  ttn_sop* S = new (std::nothrow) ttn_sop();
+  if (!S) return TTN_E_ARG;
+  S->n = n;
+  S->bond = bond;
+  for (int u = 0; u < n; ++u) {
+    S->shape.push_back(W[u].sh);
+    S->W.push_back(W[u].a);
+  }
+  *out = S;
+  return TTN_OK;
+}
+
+// ---------------------------------------------------------------- state diagram
+//
+// The state-diagram construction of Sec. II.A.3: leaves to root, every item (a
+// term, or a group of terms merged further down) is an edge of the bipartite
+// graph between its descriptor inside the subtree (operator at the node, or the
+// identity, and its channel on each child edge) and its operator string outside
+// the subtree.  A minimum vertex cover (Konig's construction from a maximum
+// matching by augmenting paths; left vertices in order of first appearance,
+// neighbours in order) gives the edge's channels: a covered descriptor is a
+// coefficient-free channel, a covered outside string carries the sum of
+// coefficient x descriptor of its items, which merge there into one item of
+// coefficient 1 (the coefficients are placed once).  Items merged in another
+// branch must reach the edge through a coefficient-free channel (forced into the
+// cover).  Channels: covered descriptors in order of first appearance, then
+// covered strings.  The root sums what is left.  No compression: the tensors
+// keep the diagram's sparsity.
+
+namespace {
+
+// minimum vertex cover containing the forced left vertices (returns sorted lists)
+void min_vertex_cover(int nl, int nr, const std::vector<std::vector<int>>& adj, const std::vector<char>& forced,
+                      std::vector<int>& cl, std::vector<int>& cr) {
+  std::vector<std::vector<int>> a2(nl);
+  for (int l = 0; l < nl; ++l)
+    if (!forced[l]) a2[l] = adj[l];
+  std::vector<int> ml(nl, -1), mr(nr, -1);
+  for (int l0 = 0; l0 < nl; ++l0) {
+    if (a2[l0].empty()) continue;
+    std::vector<char> seen(nr, 0);
+    std::vector<std::pair<int, int>> stk{{l0, 0}}, path;
+    bool found = false;
+    while (!stk.empty() && !found) {
+      const int l = stk.back().first, i = stk.back().second;
+      if (i >= (int)a2[l].size()) {
+        stk.pop_back();
+        if (!path.empty()) path.pop_back();
+        continue;
+      }
+      stk.back().second = i + 1;
+      const int r = a2[l][i];
+      if (seen[r]) continue;
+      seen[r] = 1;
+      path.push_back({l, r});
+      if (mr[r] < 0) found = true;
+      else stk.push_back({mr[r], 0});
+    }
+    if (found)
+      for (auto& pr : path) {
+        ml[pr.first] = pr.second;
+        mr[pr.second] = pr.first;
+      }
+  }
+  std::vector<char> vl(nl, 0), vr(nr, 0);
+  std::vector<int> stk;
+  for (int l = 0; l < nl; ++l)
+    if (ml[l] < 0 && !a2[l].empty()) {
+      vl[l] = 1;
+      stk.push_back(l);
+    }
+  while (!stk.empty()) {
+    const int l = stk.back();
+    stk.pop_back();
+    for (int r : a2[l])
+      if (!vr[r] && ml[l] != r) {
+        vr[r] = 1;
+        const int l2 = mr[r];
+        if (l2 >= 0 && !vl[l2]) {
+          vl[l2] = 1;
+          stk.push_back(l2);
+        }
+      }
+  }
+  cl.clear();
+  cr.clear();
+  for (int l = 0; l < nl; ++l)
+    if (forced[l] || (!a2[l].empty() && !vl[l])) cl.push_back(l);
+  for (int r = 0; r < nr; ++r)
+    if (vr[r]) cr.push_back(r);
+}
+
+}  // namespace
+
+extern "C" ttn_status ttn_sop_build_sd(const ttn_tree* t, const int32_t* node_mode, int32_t n_modes,
+                                       const double* omega, const int32_t* dims, int32_t n_mono,
+                                       const int32_t* mono_ptr, const int32_t* mono_mode, const int32_t* mono_pow,
+                                       const double* coef, ttn_sop** out) {
+  if (!t || !node_mode || !omega || !dims || !out || n_modes < 1 || n_mono < 0 ||
+      (n_mono > 0 && (!mono_ptr || !mono_mode || !mono_pow || !coef)))
+    return TTN_E_ARG;
+  const int n = t->n;
+  std::vector<int> node_of(n_modes, -1);
+  for (int u = 0; u < n; ++u) {
+    const int m = node_mode[u];
+    if (m >= n_modes) return TTN_E_ARG;
+    if (m >= 0) {
+      if (node_of[m] >= 0 || t->phys[u] != dims[m]) return TTN_E_SHAPE;
+      node_of[m] = u;
+    } else if (t->phys[u] != 1) {
+      return TTN_E_SHAPE;
+    }
+  }
+  for (int m = 0; m < n_modes; ++m)
+    if (node_of[m] < 0) return TTN_E_ARG;
+  typedef std::vector<std::pair<int, int>> Part;  // sorted (mode, key); key -1 = n, k > 0 = q^k
+  struct Item {
+    Part ops;
+    double c;
+    int merged_at;
+    std::map<int, int> chan;
+  };
+  std::vector<Item> items;
+  // the on-site term of mode m: coefficient 1, operator omega_m n (as the oracle writes it)
+  for (int m = 0; m < n_modes; ++m) items.push_back({{{m, -1}}, 1.0, -1, {}});
+  for (int i = 0; i < n_mono; ++i) {
+    Item it;
+    it.c = coef[i];
+    it.merged_at = -1;
+    for (int j = mono_ptr[i]; j < mono_ptr[i + 1]; ++j) {
+      if (mono_mode[j] < 0 || mono_mode[j] >= n_modes || mono_pow[j] < 1) return TTN_E_ARG;
+      it.ops.push_back({mono_mode[j], mono_pow[j]});
+    }
+    std::sort(it.ops.begin(), it.ops.end());
+    for (size_t j = 1; j < it.ops.size(); ++j)
+      if (it.ops[j].first == it.ops[j - 1].first) return TTN_E_ARG;
+    if (it.ops.empty()) return TTN_E_ARG;
+    items.push_back(it);
+  }
+  std::vector<std::vector<char>> in_sub(n, std::vector<char>(n, 0));
+  for (int u = 0; u < n; ++u)
+    for (int x = u; x >= 0; x = t->parent[x]) in_sub[x][u] = 1;
+  std::vector<int> post;
+  {
+    std::vector<std::pair<int, int>> stk{{t->root, 0}};
+    while (!stk.empty()) {
+      auto& top = stk.back();
+      if (top.second < (int)t->ch[top.first].size()) {
+        const int c = t->ch[top.first][top.second++];
+        stk.push_back({c, 0});
+      } else {
+        post.push_back(top.first);
+        stk.pop_back();
+      }
+    }
+  }
+  std::map<std::pair<int, int>, Mat> opcache;
+  auto local_op = [&](int mode, int key) -> const Mat& {
+    auto k = std::make_pair(mode, key);
+    auto it = opcache.find(k);
+    if (it != opcache.end()) return it->second;
+    const int d = dims[mode];
+    Mat M(d, d);
+    if (key < 0) {
+      for (int i = 0; i < d; ++i) M(i, i) = omega[mode] * (double)i;
+    } else {
+      M = qpow(d, key);
+    }
+    return opcache[k] = M;
+  };
+  const int NOKEY = INT32_MIN;
+  std::vector<int> bond(n, 0);
+  std::vector<Tens> W(n);
+  typedef std::pair<int, std::vector<int>> Desc;
+  for (int u : post) {
+    const auto& ch = t->ch[u];
+    const int d = t->phys[u], my = node_mode[u];
+    const bool hp = u != t->root;
+    std::vector<Desc> desc(items.size());
+    for (size_t i = 0; i < items.size(); ++i) {
+      int key = NOKEY;
+      if (my >= 0)
+        for (auto& x : items[i].ops)
+          if (x.first == my) key = x.second;
+      std::vector<int> chs;
+      for (int c : ch) chs.push_back(items[i].chan.at(c));
+      desc[i] = {key, chs};
+    }
+    // the tensor: [parent channel?, children channels..., p, q]
+    auto alloc_tensor = [&](int M) {
+      Tens T;
+      if (hp) T.sh.push_back(M);
+      for (int c : ch) T.sh.push_back(bond[c]);
+      T.sh.push_back(d);
+      T.sh.push_back(d);
+      T.a.assign((size_t)T.size(), 0.0);
+      return T;
+    };
+    auto put = [&](Tens& T, int par, const Desc& ds, double cf) {
+      std::vector<int64_t> st(T.sh.size(), 1);
+      for (int i = (int)T.sh.size() - 2; i >= 0; --i) st[i] = st[i + 1] * T.sh[i + 1];
+      const int off = hp ? 1 : 0;
+      int64_t base = hp ? (int64_t)par * st[0] : 0;
+      for (size_t i = 0; i < ch.size(); ++i) base += (int64_t)ds.second[i] * st[off + i];
+      const int64_t sp = st[off + ch.size()], sq = st[off + ch.size() + 1];
+      const Mat* op = ds.first == NOKEY ? nullptr : &local_op(my, ds.first);
+      for (int p = 0; p < d; ++p)
+        for (int q = 0; q < d; ++q) {
+          const double v = op ? (*op)(p, q) : (p == q ? 1.0 : 0.0);
+          T.a[(size_t)(base + p * sp + q * sq)] += cf * v;
+        }
+    };
+    if (!hp) {
+      Tens T = alloc_tensor(0);
+      for (size_t i = 0; i < items.size(); ++i) put(T, 0, desc[i], items[i].c);
+      W[u] = T;
+      break;
+    }
+    std::vector<Part> rights(items.size());
+    for (size_t i = 0; i < items.size(); ++i)
+      for (auto& x : items[i].ops)
+        if (!in_sub[u][node_of[x.first]]) rights[i].push_back(x);
+    std::map<Desc, int> lid;
+    std::map<Part, int> rid;
+    std::vector<const Desc*> lvec;
+    std::vector<int> li(items.size()), ri(items.size());
+    for (size_t i = 0; i < items.size(); ++i) {
+      auto a = lid.emplace(desc[i], (int)lid.size());
+      if (a.second) lvec.push_back(&a.first->first);
+      li[i] = a.first->second;
+      ri[i] = rid.emplace(rights[i], (int)rid.size()).first->second;
+    }
+    const int nl = (int)lid.size(), nr = (int)rid.size();
+    std::vector<std::vector<int>> adj(nl);
+    for (size_t i = 0; i < items.size(); ++i)
+      if (std::find(adj[li[i]].begin(), adj[li[i]].end(), ri[i]) == adj[li[i]].end()) adj[li[i]].push_back(ri[i]);
+    std::vector<char> forced(nl, 0);
+    for (size_t i = 0; i < items.size(); ++i)
+      if (items[i].merged_at >= 0 && !in_sub[u][items[i].merged_at]) forced[li[i]] = 1;
+    std::vector<int> cl, cr;
+    min_vertex_cover(nl, nr, adj, forced, cl, cr);
+    std::vector<int> chan_l(nl, -1), chan_r(nr, -1);
+    for (size_t i = 0; i < cl.size(); ++i) chan_l[cl[i]] = (int)i;
+    for (size_t i = 0; i < cr.size(); ++i) chan_r[cr[i]] = (int)(cl.size() + i);
+    const int M = (int)(cl.size() + cr.size());
+    bond[u] = M;
+    Tens T = alloc_tensor(M);
+    for (int l : cl) put(T, chan_l[l], *lvec[l], 1.0);
+    std::vector<Item> next;
+    std::map<int, size_t> merged;  // right vertex -> index in next
+    for (size_t i = 0; i < items.size(); ++i) {
+      if (chan_l[li[i]] >= 0) {
+        Item it = items[i];
+        it.chan[u] = chan_l[li[i]];
+        next.push_back(std::move(it));
+        continue;
+      }
+      const int r = ri[i];
+      if (chan_r[r] < 0) return TTN_E_ARG;  // not a cover (cannot happen)
+      put(T, chan_r[r], desc[i], items[i].c);
+      if (!merged.count(r)) {
+        Item g;
+        g.ops = rights[i];
+        g.c = 1.0;
+        g.merged_at = u;
+        for (auto& kv : items[i].chan)
+          if (!in_sub[u][kv.first]) g.chan[kv.first] = kv.second;
+        g.chan[u] = chan_r[r];
+        merged[r] = next.size();
+        next.push_back(std::move(g));
+      }
+    }
+    items.swap(next);
+    W[u] = T;
   }
   ttn_sop* S = new (std::nothrow) ttn_sop();
   if (!S) return TTN_E_ARG;

@@ -52,6 +52,8 @@ _SIGS = {
     "ttn_block_node_norms2": [_P, _P, _I, _P],
     "ttn_sop_build": [_P, _PI, _I, C.POINTER(C.c_double), _PI, _I, _PI, _PI, _PI, C.POINTER(C.c_double),
                       C.c_double, C.POINTER(_P)],
+    "ttn_sop_build_sd": [_P, _PI, _I, C.POINTER(C.c_double), _PI, _I, _PI, _PI, _PI, C.POINTER(C.c_double),
+                         C.POINTER(_P)],
     "ttn_sop_bonds": [_P, _PI],
     "ttn_sop_tensor": [_P, _I, C.POINTER(C.c_double), C.c_int64],
     "ttn_sop_destroy": [_P],
@@ -355,8 +357,11 @@ def block_node_norms2(ctx: Context, b: Block, u: int, out: torch.Tensor):
     _check(lib().ttn_block_node_norms2(ctx.h, b.h, u, _ptr(out)), ctx)
 
 
-def sop_build(tree: Tree, node_mode: Sequence[int], omega, dims, monomials, coefs, rel_tol: float = 1e-13):
-    """Compile a sum-of-products Hamiltonian to TTNO tensors on the host (FP64).
+def sop_build(tree: Tree, node_mode: Sequence[int], omega, dims, monomials, coefs, rel_tol: float = 1e-13,
+              method: str = "svd"):
+    """Compile a sum-of-products Hamiltonian to TTNO tensors on the host (FP64):
+    method "svd" (channel automaton compressed to the operator Schmidt rank) or
+    "state_diagram" (minimum vertex covers, uncompressed and sparse).
     Returns (list of numpy arrays W[u], op_bond list)."""
     import numpy as np
     n_modes = len(omega)
@@ -369,8 +374,14 @@ def sop_build(tree: Tree, node_mode: Sequence[int], omega, dims, monomials, coef
     h = C.c_void_p()
     om = (C.c_double * n_modes)(*[float(x) for x in omega])
     cf = (C.c_double * max(1, len(coefs)))(*[float(x) for x in coefs])
-    _check(lib().ttn_sop_build(tree.h, _i32(node_mode), n_modes, om, _i32(dims), len(monomials), _i32(ptr),
-                               _i32(mm if mm else [0]), _i32(pw if pw else [0]), cf, rel_tol, C.byref(h)))
+    if method == "svd":
+        _check(lib().ttn_sop_build(tree.h, _i32(node_mode), n_modes, om, _i32(dims), len(monomials), _i32(ptr),
+                                   _i32(mm if mm else [0]), _i32(pw if pw else [0]), cf, rel_tol, C.byref(h)))
+    elif method == "state_diagram":
+        _check(lib().ttn_sop_build_sd(tree.h, _i32(node_mode), n_modes, om, _i32(dims), len(monomials), _i32(ptr),
+                                      _i32(mm if mm else [0]), _i32(pw if pw else [0]), cf, C.byref(h)))
+    else:
+        raise ValueError("method: 'svd' or 'state_diagram'")
     try:
         bonds = (C.c_int32 * tree.n)()
         _check(lib().ttn_sop_bonds(h, bonds))

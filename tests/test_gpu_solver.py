@@ -183,3 +183,23 @@ def test_lobpcg_grow_inverse_iteration_c1(api, ctx):
     assert np.max(np.abs(theta - (np.array(G["ii_final_rr"]) + zpe))) < 1e-4
     exact = np.array(G["exact"]) + zpe
     assert np.max(np.abs(np.sort(theta) - exact)) < 1e-3
+
+
+def test_lobpcg_with_state_diagram_ttno_c1(api, ctx):
+    """The same c1 LOBPCG run with the operator compiled by the state diagram
+    (ttn_sop_build_sd: uncompressed, sparse site tensors) instead of the SVD
+    compiler: it is the same operator, so every iteration's Rayleigh quotients
+    match the stored oracle run (built with the oracle's compressed TTNO) to
+    1e-4 cm^-1."""
+    from paper_2512_15875_amd import ttn
+    from paper_2512_15875_amd.solver import LobpcgOpts, TTNEigensolver
+    m = wl.make_config_model("c1")
+    tree = wl.mps_tree(m.dims, 2)
+    gt = ttn.Tree(tree.parent, tree.phys)
+    W, M = ttn.sop_build(gt, tree.mode, m.omega, m.dims, m.monomials, m.coefs, method="state_diagram")
+    x0 = wl.initial_block(tree, wl.bond_dims(tree, 8), m.omega, m.dims, 10, m.seed + 17)
+    s = TTNEigensolver(ctx, tree, m, D=8, k=10, precision="fp64", ttno=(W, M))
+    s.load_block(x0)
+    s.lobpcg(LobpcgOpts(n_iter=3, shift=GOLD["shift"]))
+    for it, h in enumerate(s.history):
+        assert np.max(np.abs(h["lam"] - (np.array(GOLD["lam_history"][it]) + GOLD["zpe"]))) < 1e-4, it
