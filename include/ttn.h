@@ -246,6 +246,17 @@ typedef enum {
  * H_eff applications of the k states per local solve.  Not in the paper. */
 typedef enum { TTN_WARM_NONE = 0, TTN_WARM_DIAG = 1, TTN_WARM_LEARNED = 2 } ttn_warm_start;
 
+/* Symmetric positive-definite preconditioning of the local MINRES (mode
+ * MINRES): with d = diag(H_eff) - s_j of each state, D = |d| (DIAG) or
+ * D = sqrt(d^2 + gamma^2) (DAMPED_DIAG, gamma = precond_damp * rms(d)), MINRES
+ * runs on D^-1/2 (H_eff - s_j) D^-1/2 z = D^-1/2 b from z = D^1/2 y_u and
+ * y_u = D^-1/2 z at the end (split preconditioning: the same Krylov iterates
+ * as preconditioned MINRES with M = D; rtol and the reported residual refer
+ * to the scaled system).  Costs one diagonal and four element-wise scalings
+ * per local solve and two per iteration.  Not in the paper; DAMPED_DIAG's
+ * damping is the learned parameter (fitted on training local systems). */
+typedef enum { TTN_PRECOND_NONE = 0, TTN_PRECOND_DIAG = 1, TTN_PRECOND_DAMPED_DIAG = 2 } ttn_precond;
+
 typedef struct {
   int32_t mode;              /* ttn_solve_mode */
   int32_t maxiter;           /* MINRES iterations per local solve */
@@ -257,6 +268,8 @@ typedef struct {
                                 applies (rtol max(rtol, 1e-6), maxiter iterations), y += c in FP64 */
   double* learned_coef;      /* LEARNED, optional: device double[k][2], (a, c) of the last local step */
   int32_t warm;              /* ttn_warm_start; MINRES with refine = 0 only */
+  int32_t precond;           /* ttn_precond; MINRES with refine = 0 and warm = NONE only */
+  double precond_damp;       /* DAMPED_DIAG: gamma = precond_damp * rms(diag - s_j) of the state */
 } ttn_solve_opts;
 
 typedef struct ttn_sweep ttn_sweep;

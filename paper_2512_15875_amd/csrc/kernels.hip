@@ -124,4 +124,80 @@ hipError_t launch_convert(int sdt, const void* x, int ddt, void* y, int64_t n, h
   return hipGetLastError();
 }
 
+
+// ---- split Jacobi preconditioning of the local MINRES (one workgroup per
+// state for the scale, element-wise products gated like the contraction
+// kernels so that a converged batch stops without the host)
+namespace {
+template <typename T>
+__global__ __launch_bounds__(256) void precond_scale_kernel(const T* d, T* dsq, int64_t n, int mode, double damp) {
+  __shared__ double red[4];
+  const int z = blockIdx.x, t = threadIdx.x;
+  const T* dz = d + (int64_t)z * n;
+  T* oz = dsq + (int64_t)z * n;
+  double g2 = 0.0;
+  if (mode == 2) {
+    double s = 0.0;
+    for (int64_t i = t; i < n; i += 256) s += (double)dz[i] * (double)dz[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((t & 63) == 0) red[t >> 6] = s;
+    __syncthreads();
+    const double ms = (red[0] + red[1] + red[2] + red[3]) / (double)n;
+    g2 = damp * damp * ms;
+  }
+  for (int64_t i = t; i < n; i += 256) {
+    const double v = (double)dz[i] * (double)dz[i] + g2;
+    oz[i] = (T)(v > 0.0 ? pow(v, -0.25) : 1.0);
+  }
+}
+
+template <typename T>
+__global__ void ew_mul_kernel(const T* a, const T* b, T* out, int64_t n, const int32_t* gate) {
+  if (gate && *gate == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = a[i] * b[i];
+}
+
+template <typename T>
+__global__ void ew_div_kernel(const T* a, const T* b, T* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = a[i] / b[i];
+}
+}  // namespace
+
+hipError_t launch_precond_scale(int ctype, const void* d, void* dsq, int64_t n, int k, int mode, double damp,
+                                hipStream_t s) {
+  if (k <= 0 || n <= 0) return hipSuccess;
+  if (ctype == 0)
+    hipLaunchKernelGGL(precond_scale_kernel<double>, dim3((unsigned)k), dim3(256), 0, s, (const double*)d,
+                       (double*)dsq, n, mode, damp);
+  else
+    hipLaunchKernelGGL(precond_scale_kernel<float>, dim3((unsigned)k), dim3(256), 0, s, (const float*)d, (float*)dsq,
+                       n, mode, damp);
+  return hipGetLastError();
+}
+
+hipError_t launch_ew_mul(int ctype, const void* a, const void* b, void* out, int64_t n, const int32_t* gate,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 g((unsigned)((n + 255) / 256));
+  if (ctype == 0)
+    hipLaunchKernelGGL(ew_mul_kernel<double>, g, dim3(256), 0, s, (const double*)a, (const double*)b, (double*)out, n,
+                       gate);
+  else
+    hipLaunchKernelGGL(ew_mul_kernel<float>, g, dim3(256), 0, s, (const float*)a, (const float*)b, (float*)out, n,
+                       gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_ew_div(int ctype, const void* a, const void* b, void* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 g((unsigned)((n + 255) / 256));
+  if (ctype == 0)
+    hipLaunchKernelGGL(ew_div_kernel<double>, g, dim3(256), 0, s, (const double*)a, (const double*)b, (double*)out, n);
+  else
+    hipLaunchKernelGGL(ew_div_kernel<float>, g, dim3(256), 0, s, (const float*)a, (const float*)b, (float*)out, n);
+  return hipGetLastError();
+}
+
 }  // namespace ttn

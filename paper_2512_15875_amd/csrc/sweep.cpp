@@ -24,6 +24,11 @@ hipError_t launch_minres_init(int ctype, const void* b, const void* Ax, void* v,
 hipError_t launch_minres_count(const MinresState* st, int k, int32_t* active, hipStream_t s);
 hipError_t launch_minres_step(int ctype, void* x, void* v, void* vprev, void* p, const void* dp, void* dpp, int64_t n,
                               int k, MinresState* st, hipStream_t s);
+hipError_t launch_precond_scale(int ctype, const void* d, void* dsq, int64_t n, int k, int mode, double damp,
+                                hipStream_t s);
+hipError_t launch_ew_mul(int ctype, const void* a, const void* b, void* out, int64_t n, const int32_t* gate,
+                         hipStream_t s);
+hipError_t launch_ew_div(int ctype, const void* a, const void* b, void* out, int64_t n, hipStream_t s);
 hipError_t launch_minres_report(const MinresState* st, int k, int32_t* iters, double* resid, int32_t* n_active,
                                 hipStream_t s);
 hipError_t launch_diag_solve(int ctype, const void* b, const void* dg, void* y, int64_t n, hipStream_t s);
@@ -456,6 +461,7 @@ ttn_status ttn_sweep_run(ttn_ctx* ctx, ttn_sweep* sw, const ttn_solve_opts* opts
   std::ostringstream key;
   key << opts->mode << ":" << opts->maxiter << ":" << opts->rtol << ":" << (const void*)opts->mlp_params << ":"
       << opts->mlp_compute << ":" << (const void*)opts->learned_coef << ":" << opts->refine << ":" << opts->warm << ":"
+      << opts->precond << ":" << opts->precond_damp << ":"
       << n_sweeps << ":" << init_first << ":"
       << (const void*)iters_out << ":" << (const void*)resid_out;
   const std::string k = key.str();
@@ -585,7 +591,13 @@ ttn_status sweep_step(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, int32_t next, c
         return api_fail(ctx, TTN_E_DTYPE, "mixed-precision refinement needs an FP64 sweep");
       if (opts->warm < TTN_WARM_NONE || opts->warm > TTN_WARM_LEARNED || (opts->warm != TTN_WARM_NONE && opts->refine > 0))
         return api_fail(ctx, TTN_E_ARG, "corrected MINRES start: warm 0..2, and only without refinement");
+      const int pc = opts->precond;
+      if (pc < TTN_PRECOND_NONE || pc > TTN_PRECOND_DAMPED_DIAG ||
+          (pc != TTN_PRECOND_NONE && (opts->refine > 0 || opts->warm != TTN_WARM_NONE)) ||
+          (pc == TTN_PRECOND_DAMPED_DIAG && !(opts->precond_damp >= 0)))
+        return api_fail(ctx, TTN_E_ARG, "preconditioner: 0..2, with refine = 0 and warm = NONE, damping >= 0");
       void *v = vbuf(1), *vp = vbuf(2), *p = vbuf(3), *d1 = vbuf(4), *d2 = vbuf(5);
+      void *dsq = vbuf(6), *tv = vbuf(7);  // preconditioner D^-1/2 and the scaled Krylov vector
       // batched MINRES on (H_eff - s) x = rhs, warm start x with Ax0 = (H_eff - s) x
       auto minres = [&](void* x, const void* rhs, const void* ax0, ttn_dtype comp, double rtol) -> ttn_status {
         hipError_t e = launch_minres_init(ct, rhs, ax0, v, vp, d1, d2, n, k, rtol, sw->st, sw->d_active, ctx->stream);
@@ -618,13 +630,19 @@ ttn_status sweep_step(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, int32_t next, c
           // the environments are fixed during the solve: from the second
           // product on, the stages that do not involve the Krylov vector (the
           // operator-environment partials) are reused from the workspace
+          const void* xin = vv;
+          if (pc != TTN_PRECOND_NONE) {  // (D^-1/2 A D^-1/2) v: scale, apply, scale
+            HIPCHK(ctx, launch_ew_mul(ct, dsq, vv, tv, n * k, sw->d_active, ctx->stream));
+            xin = tv;
+          }
           ctx->gate = sw->d_active;
           ctx->reuse_free = reuse_on && it > 0;
-          ttn_status rr = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, vv, k,
+          ttn_status rr = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, xin, k,
                                            p, TTN_HEFF_APPLY, comp);
           ctx->gate = nullptr;
           ctx->reuse_free = false;
           if (rr != TTN_OK) return rr;
+          if (pc != TTN_PRECOND_NONE) HIPCHK(ctx, launch_ew_mul(ct, dsq, p, p, n * k, sw->d_active, ctx->stream));
           e = launch_minres_step(ct, x, vv, vvp, p, dp, dpp, n, k, sw->st, ctx->stream);
           if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));
           std::swap(vv, vvp);
@@ -660,8 +678,19 @@ ttn_status sweep_step(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, int32_t next, c
         r = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, y_u, k, p,
                              TTN_HEFF_APPLY, sw->compute);
         if (r != TTN_OK) return r;
+        if (pc != TTN_PRECOND_NONE) {
+          // D^-1/2 from the local diagonal, then the scaled system: b <- D^-1/2 b,
+          // z = D^1/2 y_u, its image D^-1/2 A y_u
+          r = local_diag(sw, u, dsq);
+          if (r != TTN_OK) return r;
+          HIPCHK(ctx, launch_precond_scale(ct, dsq, dsq, n, k, pc, opts->precond_damp, ctx->stream));
+          HIPCHK(ctx, launch_ew_mul(ct, dsq, p, p, n * k, nullptr, ctx->stream));
+          HIPCHK(ctx, launch_ew_mul(ct, dsq, b, b, n * k, nullptr, ctx->stream));
+          HIPCHK(ctx, launch_ew_div(ct, y_u, dsq, y_u, n * k, ctx->stream));
+        }
         r = minres(y_u, b, p, sw->compute, opts->rtol);
         if (r != TTN_OK) return r;
+        if (pc != TTN_PRECOND_NONE) HIPCHK(ctx, launch_ew_mul(ct, dsq, y_u, y_u, n * k, nullptr, ctx->stream));
       } else if (opts->refine == 0) {
         // corrected start: r0 = b - (H_eff - s) y_u, a minimal-residual DIAG
         // or learned correction c of r0, y_u += c, then MINRES from there

@@ -58,6 +58,10 @@ class IIOpts:
     monotone: bool = False
     mono_tol: float = 1e-7
     refine: int = 0         # > 0: local solves by FP64 refinement around FP32-arithmetic MINRES (FP64 solver)
+    # SPD preconditioning of the local MINRES (not in the paper): "none", "diag" (D = |diag(H_eff) - s|) or
+    # "damped" (D = sqrt((diag - s)^2 + gamma^2), gamma = precond_damp * rms(diag - s): the learned damping)
+    precond: str = "none"
+    precond_damp: float = 0.1
 
 
 def post_order_edges(tree: ttn.Tree):
@@ -475,7 +479,10 @@ class TTNEigensolver:
             col = []
             for _ in range(opts.sweeps):
                 ttn.run_sweep(self._sw_ii, self.gt, ttn.SOLVE_MINRES, opts.minres_maxiter, opts.minres_rtol,
-                              collect=col, refine=opts.refine)
+                              collect=col, refine=opts.refine,
+                              precond={"none": ttn.PRECOND_NONE, "diag": ttn.PRECOND_DIAG,
+                                       "damped": ttn.PRECOND_DAMPED_DIAG}[opts.precond],
+                              precond_damp=opts.precond_damp)
             ttn.block_normalize_node(ctx, self.Y, root)
             self._copy_rows(self.B, 0, self.Y, 0, k)
             if big:
@@ -491,7 +498,8 @@ class TTNEigensolver:
                         reverted += list(c)
             self.lam_d.copy_(torch.from_numpy(lam))
             rec = {"iter": it, "t": time.perf_counter() - t_start, "lam": lam + self.zpe, "reverted": reverted,
-                   "minres_iters": {int(u): int(t.max().item()) for u, t in col}}
+                   "minres_iters": {int(u): int(t.max().item()) for u, t in col},
+                   "minres_iters_total": [int(x) for x in sum(t.cpu() for _, t in col).tolist()] if col else []}
             self.history.append(rec)
             if log:
                 log(rec)

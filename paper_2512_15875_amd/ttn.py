@@ -20,6 +20,7 @@ F64, F32, BF16, F64_F32 = 0, 1, 2, 3
 HEFF_APPLY, HEFF_NO_SHIFT, HEFF_DIAG, HEFF_ACCUM = 0, 1, 2, 4
 SOLVE_MINRES, SOLVE_DIAG, SOLVE_FIT, SOLVE_SKIP, SOLVE_LEARNED = 0, 1, 2, 3, 4
 WARM_NONE, WARM_DIAG, WARM_LEARNED = 0, 1, 2
+PRECOND_NONE, PRECOND_DIAG, PRECOND_DAMPED_DIAG = 0, 1, 2
 
 _lib = None
 
@@ -402,7 +403,8 @@ def sop_build(tree: Tree, node_mode: Sequence[int], omega, dims, monomials, coef
 
 class SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("maxiter", C.c_int32), ("rtol", C.c_double), ("mlp_params", C.c_void_p),
-                ("mlp_compute", C.c_int32), ("refine", C.c_int32), ("learned_coef", C.c_void_p), ("warm", C.c_int32)]
+                ("mlp_compute", C.c_int32), ("refine", C.c_int32), ("learned_coef", C.c_void_p), ("warm", C.c_int32),
+                ("precond", C.c_int32), ("precond_damp", C.c_double)]
 
 
 class Sweep:
@@ -434,16 +436,17 @@ class Sweep:
 
     def step(self, node: int, nxt: int, mode: int, maxiter: int = 0, rtol: float = 0.0, iters=None, resid=None,
              mlp: Optional[torch.Tensor] = None, mlp_compute: int = BF16, learned_coef=None, refine: int = 0,
-             warm: int = 0):
+             warm: int = 0, precond: int = 0, precond_damp: float = 0.0):
         o = SolveOpts(mode, maxiter, rtol, None if mlp is None else mlp.data_ptr(), mlp_compute, refine,
-                      None if learned_coef is None else learned_coef.data_ptr(), warm)
+                      None if learned_coef is None else learned_coef.data_ptr(), warm, precond, precond_damp)
         _check(lib().sweep_step(self.ctx.h, self.h, node, nxt, C.byref(o), _ptr(iters), _ptr(resid)), self.ctx)
 
     def run(self, mode: int, n_sweeps: int = 1, init: bool = False, graph: bool = False, maxiter: int = 0,
             rtol: float = 0.0, iters=None, resid=None, mlp: Optional[torch.Tensor] = None, mlp_compute: int = BF16,
-            refine: int = 0, warm: int = 0):
+            refine: int = 0, warm: int = 0, precond: int = 0, precond_damp: float = 0.0):
         """n_sweeps native sweeps (see ttn_sweep_run), optionally replayed as a HIP graph."""
-        o = SolveOpts(mode, maxiter, rtol, None if mlp is None else mlp.data_ptr(), mlp_compute, refine, None, warm)
+        o = SolveOpts(mode, maxiter, rtol, None if mlp is None else mlp.data_ptr(), mlp_compute, refine, None, warm,
+                      precond, precond_damp)
         _check(lib().ttn_sweep_run(self.ctx.h, self.h, C.byref(o), n_sweeps, int(init), int(graph), _ptr(iters),
                                    _ptr(resid)), self.ctx)
 
@@ -477,7 +480,8 @@ def euler_tour(tree: Tree):
 
 
 def run_sweep(sw: Sweep, tree: Tree, mode: int, maxiter: int = 0, rtol: float = 0.0, iters=None, resid=None,
-              collect=None, mlp=None, mlp_compute: int = BF16, on_solved=None, refine: int = 0):
+              collect=None, mlp=None, mlp_compute: int = BF16, on_solved=None, refine: int = 0, precond: int = 0,
+              precond_damp: float = 0.0):
     """One sweep: a depth-first Euler tour from the root; a node is solved on
     its first visit, later visits only move the orthogonality centre.
     collect: optional list receiving (node, iters tensor) per local solve.
@@ -485,7 +489,7 @@ def run_sweep(sw: Sweep, tree: Tree, mode: int, maxiter: int = 0, rtol: float = 
     centre moves on (harvesting reads the local problem there)."""
     if collect is None and on_solved is None:
         sw.run(mode, 1, maxiter=maxiter, rtol=rtol, iters=iters, resid=resid, mlp=mlp, mlp_compute=mlp_compute,
-               refine=refine)
+               refine=refine, precond=precond, precond_damp=precond_damp)
         return
     tour = euler_tour(tree)
     seen = set()
@@ -498,7 +502,7 @@ def run_sweep(sw: Sweep, tree: Tree, mode: int, maxiter: int = 0, rtol: float = 
             sw.step(u, nxt, SOLVE_SKIP)
         elif collect is not None and m == SOLVE_MINRES:
             it = torch.zeros(sw.target.k, dtype=torch.int32, device="cuda")
-            sw.step(u, nxt, m, maxiter, rtol, it, resid, refine=refine)
+            sw.step(u, nxt, m, maxiter, rtol, it, resid, refine=refine, precond=precond, precond_damp=precond_damp)
             collect.append((u, it))
         else:
             sw.step(u, nxt, m, maxiter, rtol, iters, resid, mlp, mlp_compute)
