@@ -691,6 +691,13 @@ def ienv_probe(args):
         dt = (time.perf_counter() - t0) / reps
         print(f"toward {v}: {dt * 1e3:.3f} ms for {n} pairs = {dt / n * 1e9:.1f} ns/pair, "
               f"{2 * Dn ** 4 * 3 * n / dt / 1e12:.1f} TFLOP/s", flush=True)
+    # per launch: the three products of the staged path, and the compulsory
+    # bytes (bra and ket tensors, two environments in, one out, per pair)
+    fl = 2.0 * Dn ** 4 * 3 * n
+    by = 4.0 * n * (2 * Dn ** 3 + 3 * Dn ** 2)
+    print(json.dumps({"ienv_probe": f"3-leg node, bonds {Dn}, {ks} states, {n} pairs, FP32",
+                      "kernels": {"ienv3_kernel": {"algorithmic_flop_per_launch": fl,
+                                                   "algorithmic_bytes_per_launch": by}}}), flush=True)
 
 
 def gram_probe(args):
@@ -730,7 +737,22 @@ def gram_probe(args):
         a[3] += _rest[-1]
     out = {kern: {"launches": c, "avg_ms": round(t / c, 5), "algorithmic_flop_per_launch": f / c,
                   "algorithmic_bytes_per_launch": b / c} for kern, (c, t, f, b) in by.items()}
-    print(json.dumps({"gram_probe": f"c2, D={D}, k={k}, {len(ia)} pairs", "kernels": out}), flush=True)
+    # U2 compulsory bytes of the step: per environment update (u -> parent),
+    # with and without the operator, the 3k node tensors once, every pair's
+    # incoming and outgoing environments, the site operator once
+    es = 4 if args.precision != "fp64" else 8
+    n_pairs = len(ia)
+    u2 = 0.0
+    for (u, p) in s.up_edges:
+        ch = [c for c in s.gt.nbrs(u) if c != p]
+        a_u = float(np.prod(s.B.legdims(u)))
+        for with_op in (True, False):
+            m_of = (lambda c: max(1, s.M[c])) if with_op else (lambda c: 1)
+            env_in = sum(s.bonds[c] * m_of(c) * s.bonds[c] for c in ch)
+            env_out = s.bonds[u] * m_of(u) * s.bonds[u]
+            u2 += es * (m * a_u + n_pairs * (env_in + env_out) + (s.Wd[u].numel() if with_op else 0))
+    print(json.dumps({"gram_probe": f"c2, D={D}, k={k}, {len(ia)} pairs", "u2_alg_bytes_step": u2,
+                      "kernels": out}), flush=True)
 
 
 def heff_probe(args):
@@ -787,54 +809,84 @@ def heff_probe(args):
                  "algorithmic_bytes_per_launch": d["bytes"] / d["launches"],
                  "tflop_per_s": round(d["flops"] / (d["ms"] * 1e-3) / 1e12, 2),
                  "stage_shapes_MNK_items": sorted(d["shapes"])} for kn, d in by_kernel.items()}
+    # U1 compulsory bytes per call: k (|X| + |Y|), every state's incoming
+    # environments, the site operator
+    es = X.element_size()
+    u1_bytes = es * (2 * k * n_loc + sum(envs.get(c, u).numel() for c in nb) + s.Wd[u].numel())
     print(json.dumps({"heff_probe": f"{args.workload} node {u}, D={D}, k={k}, {args.precision}, {n_calls} calls",
                       "tflop_per_s": round(fl / (ms * 1e-3) / 1e12, 2), "ms_per_call": round(ms / n_calls, 4),
-                      "gflop_per_call": round(fl / n_calls / 1e9, 3), "kernels": kern}), flush=True)
+                      "gflop_per_call": round(fl / n_calls / 1e9, 3), "calls": n_calls,
+                      "u1_alg_bytes_per_call": u1_bytes, "kernels": kern}), flush=True)
 
 
 def trace_summary(path: str, kernel: str):
     """Summary of a rocprofv3 kernel-trace CSV (kernel_trace.csv of
-    --kernel-trace): per kernel name, dispatch count and mean / median
-    duration, and for `kernel` (a prefix of the name) the same per grid
-    size -- the launches of one contraction stage share a grid."""
+    --kernel-trace) of a default bench run: the bench brackets its timed
+    LOBPCG iterations and then its extra profiled iteration with vec_scale
+    launches over MARKER_N doubles (a grid no other launch uses).  Prints the
+    kernel mix of the profiled iteration (between the third and fourth
+    markers), the mean duration of the kernels named by the prefix `kernel`
+    over the timed iterations (between the first two), and the whole trace's
+    top kernels."""
     import csv
     rows = list(csv.DictReader(open(path)))
-    by = {}
+    rec = []
     for r in rows:
         name = r.get("Kernel_Name", "")
-        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3  # us
-        grid = (r.get("Grid_Size_X", r.get("Grid_Size", "")), r.get("Grid_Size_Y", ""), r.get("Grid_Size_Z", ""))
-        by.setdefault(name, []).append((dur, grid))
-    print("| kernel | dispatches | mean us | median us | total ms |")
-    print("|---|---|---|---|---|")
-    for name, v in sorted(by.items(), key=lambda kv: -sum(d for d, _ in kv[1]))[:15]:
-        d = [x for x, _ in v]
-        print(f"| {name[:110]} | {len(d)} | {np.mean(d):.1f} | {np.median(d):.1f} | {sum(d) / 1e3:.1f} |")
-    for name, v in by.items():
-        if not name.startswith(kernel):
-            continue
-        print(f"\n{name}: by grid (X, Y, Z threads)")
-        print("| grid | dispatches | mean us | median us |")
+        t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        gx = int(r.get("Grid_Size_X", r.get("Grid_Size", "0")) or 0)
+        rec.append((t0, t1, name, gx))
+    rec.sort()
+    short = lambda k: k.replace("void ttn::", "").replace("ttn::", "").split("(")[0]
+    marker_grid = -(-MARKER_N // 256) * 256
+    marks = [i for i, (_, _, n, gx) in enumerate(rec) if "vscale_kernel" in n and gx == marker_grid]
+
+    def table(sel, title):
+        by = {}
+        for t0, t1, n, _ in sel:
+            a = by.setdefault(short(n), [0, 0.0])
+            a[0] += 1
+            a[1] += (t1 - t0) * 1e-6
+        tot = sum(v[1] for v in by.values())
+        print(f"{title}: {sum(v[0] for v in by.values())} dispatches, {tot:.1f} ms of kernel time.\n")
+        print("| kernel | launches | total ms | avg us | share |")
+        print("|---|---|---|---|---|")
+        for n, (c, ms) in sorted(by.items(), key=lambda kv: -kv[1][1])[:20]:
+            print(f"| {n} | {c} | {ms:.1f} | {1e3 * ms / c:.1f} | {ms / tot:.3f} |")
+        print()
+
+    if len(marks) >= 4:
+        table(rec[marks[2] + 1:marks[3]], "Kernels in the profiled iteration")
+        timed = [x for x in rec[marks[0] + 1:marks[1]] if short(x[2]).startswith(kernel)]
+        by = {}
+        for t0, t1, n, gx in timed:
+            by.setdefault((short(n), gx), []).append((t1 - t0) * 1e-3)
+        print(f"Kernels named {kernel}* over the timed iterations (between the first two markers), by grid "
+              f"(the launches of one contraction stage share a grid):\n")
+        print("| kernel | grid (threads) | launches | avg us |")
         print("|---|---|---|---|")
-        grids = {}
-        for dur, grid in v:
-            grids.setdefault(grid, []).append(dur)
-        for grid, d in sorted(grids.items(), key=lambda kv: -len(kv[1])):
-            print(f"| {grid} | {len(d)} | {np.mean(d):.1f} | {np.median(d):.1f} |")
+        for (n, gx), d in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+            print(f"| {n} | {gx} | {len(d)} | {np.mean(d):.1f} |")
+        print()
+    else:
+        print(f"({len(marks)} marker launches found; the region tables need four)\n")
+    table(rec, "Whole trace (setup and warm-up included)")
 
 
-def pmc_summary(out: str):
+def pmc_summary(out: str, probe: str = "heff"):
     """Markdown summary of rocprofv3 counter passes over `bench.py
-    --heff-probe` (directories out/heff_p*/ with heff_counter_collection.csv,
-    the probe's JSON line in out/heff_p1.log) and of the copy calibration
-    (out/copy_FETCH_SIZE/, out/copy_WRITE_SIZE/): per kernel, the mean per
-    dispatch of every counter, HBM bytes from FETCH_SIZE / WRITE_SIZE scaled by
-    the copy, MFMA utilisation and executed MFMA flops; then one
-    traffic|kernel|gemm hash|measured bytes|algorithmic bytes line per kernel."""
+    --<probe>-probe` (directories out/<probe>_p*/ with
+    <probe>_counter_collection.csv, the probe's JSON line in out/<probe>_p1.log)
+    and of the copy calibration (out/copy_FETCH_SIZE/, out/copy_WRITE_SIZE/):
+    per kernel, the mean per dispatch of every counter, HBM bytes from
+    FETCH_SIZE / WRITE_SIZE scaled by the copy, MFMA utilisation and executed
+    MFMA flops; the whole probe's measured bytes against its compulsory
+    bytes; then one traffic|kernel|gemm hash|measured bytes|algorithmic bytes
+    line per GEMM kernel."""
     import csv
     import glob
     per = {}
-    for f in sorted(glob.glob(os.path.join(out, "heff_p*", "heff_counter_collection.csv"))):
+    for f in sorted(glob.glob(os.path.join(out, f"{probe}_p*", f"{probe}_counter_collection.csv"))):
         for r in csv.DictReader(open(f)):
             per.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
     cal = {}
@@ -842,11 +894,16 @@ def pmc_summary(out: str):
         f = os.path.join(out, f"copy_{c}", "copy_counter_collection.csv")
         vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(f)) if "copyBuffer" in r["Kernel_Name"]]
         cal[c] = (256 << 20) / (float(np.median(vals)) * 1024)  # bytes per KiB reported, for a 256 MiB copy
-    probe = None
-    for line in open(os.path.join(out, "heff_p1.log")):
-        if line.startswith('{"heff_probe"'):
-            probe = json.loads(line)
+    info = None
+    for line in open(os.path.join(out, f"{probe}_p1.log")):
+        if line.startswith('{"' + probe + '_probe"'):
+            info = json.loads(line)
+    kinfo = (info or {}).get("kernels", {})
     short = lambda k: k.replace("void ttn::", "").split("(")[0]
+
+    def lookup(kn):  # the probe names fused kernels without their template arguments
+        return kinfo.get(kn) or kinfo.get(kn.split("<")[0])
+
     print(f"Copy calibration (256 MiB device copy): FETCH_SIZE x {cal['FETCH_SIZE']:.3f} KiB, "
           f"WRITE_SIZE x {cal['WRITE_SIZE']:.3f} KiB = bytes\n")
     print("| kernel | dispatches | HBM read MB | HBM write MB | algorithmic MB | traffic / algorithmic | MFMA busy "
@@ -854,28 +911,45 @@ def pmc_summary(out: str):
     print("|---|---|---|---|---|---|---|---|")
     lines = []
     h = gemm_source_hash()
+    tot_bytes = 0.0
     for name, cs in per.items():
         kn = short(name)
-        if not (kn.startswith("ogemm") or kn.startswith("relayout")):
-            continue
         m = {c: float(np.mean(v)) for c, v in cs.items()}
+        nd = len(next(iter(cs.values())))
         rd = m.get("FETCH_SIZE", 0.0) * 1024 * cal["FETCH_SIZE"]
         wr = m.get("WRITE_SIZE", 0.0) * 1024 * cal["WRITE_SIZE"]
-        pk = (probe or {}).get("kernels", {}).get(kn)
-        alg = pk["algorithmic_bytes_per_launch"] if pk else None
-        alg_fl = pk["algorithmic_flop_per_launch"] if pk else None
+        if not (kn.startswith("vscale") or kn.startswith("copyBuffer")):
+            tot_bytes += (sum(cs.get("FETCH_SIZE", [])) * cal["FETCH_SIZE"] +
+                          sum(cs.get("WRITE_SIZE", [])) * cal["WRITE_SIZE"]) * 1024
+        pk = lookup(kn)
+        if pk is None:
+            continue
+        alg = pk["algorithmic_bytes_per_launch"]
+        alg_fl = pk["algorithmic_flop_per_launch"]
         util = (m["SQ_VALU_MFMA_BUSY_CYCLES"] / (m["GRBM_GUI_ACTIVE"] / 8 * 1024)
                 if m.get("GRBM_GUI_ACTIVE") else float("nan"))
         exe = m.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) * 512
-        print(f"| {kn} | {len(next(iter(cs.values())))} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | "
-              f"{alg / 1e6 if alg else float('nan'):.1f} | {(rd + wr) / alg if alg else float('nan'):.3f} | "
-              f"{util:.3f} | {exe / alg_fl if alg_fl else float('nan'):.3f} |")
-        if alg:
+        print(f"| {kn} | {nd} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | {alg / 1e6:.1f} | "
+              f"{(rd + wr) / alg if rd + wr else float('nan'):.3f} | {util:.3f} | "
+              f"{exe / alg_fl if alg_fl else float('nan'):.3f} |")
+        if rd + wr and (kn.startswith("ogemm") or kn.startswith("relayout")):
             lines.append(f"traffic|{kn}|{h}|{rd + wr:.6e}|{alg:.6e}")
+    # FETCH_SIZE / WRITE_SIZE passes each ran the probe once: the sum over its
+    # dispatches is the probe's measured traffic
+    if info and tot_bytes:
+        if "u1_alg_bytes_per_call" in info:
+            per_call = tot_bytes / info["calls"]
+            print(f"\nWhole U1 call: measured {per_call / 1e6:.1f} MB per call against the compulsory "
+                  f"{info['u1_alg_bytes_per_call'] / 1e6:.1f} MB (k (|X| + |Y|) + the k states' environments + W): "
+                  f"{per_call / info['u1_alg_bytes_per_call']:.2f}x")
+        if "u2_alg_bytes_step" in info:
+            print(f"\nWhole Gram step: measured {tot_bytes / 1e9:.2f} GB against the compulsory U2 bytes "
+                  f"{info['u2_alg_bytes_step'] / 1e9:.2f} GB (node tensors once, every pair's environments in and "
+                  f"out, W once, per update with and without the operator): {tot_bytes / info['u2_alg_bytes_step']:.2f}x")
     print("\nOther counters, mean per dispatch:\n")
     for name, cs in per.items():
         kn = short(name)
-        if not kn.startswith("ogemm"):
+        if lookup(kn) is None:
             continue
         print(f"* {kn}: " + ", ".join(f"{c} {np.mean(v):.4g}" for c, v in sorted(cs.items())))
     print("\nGEMM source hash (sha256[:16] of csrc/gemm.hip): " + h + "\n")
@@ -1030,9 +1104,11 @@ def main():
     ap.add_argument("--gemm-hash", action="store_true", help="print the GEMM source hash and exit")
     ap.add_argument("--heff-probe", action="store_true", help="run only the headline heff_apply_block calls")
     ap.add_argument("--trace-summary", default=None, help="summarise a rocprofv3 kernel_trace.csv and exit")
-    ap.add_argument("--trace-kernel", default="ogemm_kernel", help="kernel-name prefix broken down by grid")
+    ap.add_argument("--trace-kernel", default="ogemm_tn_kernel", help="kernel-name prefix timed over the timed iterations")
     ap.add_argument("--pmc-summary", default=None,
-                    help="summarise rocprofv3 counter passes over --heff-probe (directory of the passes) and exit")
+                    help="summarise rocprofv3 counter passes over a probe (directory of the passes) and exit")
+    ap.add_argument("--pmc-probe", default="heff", choices=["heff", "gram", "ienv"],
+                    help="which probe the counter passes ran (--heff-probe, --gram-probe, --ienv-probe)")
     args = ap.parse_args()
     if args.graphs and args.warmup < 2:
         args.warmup = 2  # first step runs eagerly, the second captures: keep both untimed
@@ -1043,7 +1119,7 @@ def main():
         trace_summary(args.trace_summary, args.trace_kernel)
         return
     if args.pmc_summary:
-        pmc_summary(args.pmc_summary)
+        pmc_summary(args.pmc_summary, args.pmc_probe)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path, so --gpus must be 1",
@@ -1214,11 +1290,33 @@ def run_bench(args, api, k, D, stream):
               f"{d['flops'] / (d['ms'] * 1e-3) / 1e12:.1f} TFLOP/s {d['bytes'] / (d['ms'] * 1e-3) / 1e9:.0f} GB/s",
               file=sys.stderr)
     heff_fl = heff_ms = 0.0
+    by_depth = {}  # H_eff applies with the TTNO, by the node's distance from the root
+    deep = {}  # their stage kernels at depth >= 3: (depth, kernel, (M, N, K, items)) -> ms, launches
+    depth = {}
+    for u in range(tree.n):
+        d, v = 0, u
+        while tree.parent[v] >= 0:
+            v, d = tree.parent[v], d + 1
+        depth[u] = d
     for key, st, kern, cnt, tms, fl, *_r in rep:
         parts = key.split(":")
         if parts[0] == "heff" and parts[2] == "1":
             heff_fl += fl
             heff_ms += tms
+            a = by_depth.setdefault(depth[int(parts[1])], [0.0, 0.0, 0])
+            a[0] += fl
+            a[1] += tms
+            a[2] += cnt
+            if depth[int(parts[1])] >= 3:
+                b = deep.setdefault((depth[int(parts[1])], kern, tuple(_r[:4])), [0.0, 0])
+                b[0] += tms
+                b[1] += cnt
+    heff_levels = {str(d): {"ms": round(v[1], 2), "tflop_per_s": round(v[0] / (v[1] * 1e-3) / 1e12, 2) if v[1] else None,
+                            "launches": v[2]} for d, v in sorted(by_depth.items())}
+    print(f"  H_eff applies by depth: {heff_levels}", file=sys.stderr)
+    for (dp, kn, shp), (tms, cnt) in sorted(deep.items(), key=lambda kv: -kv[1][0])[:16]:
+        print(f"    depth {dp} {kn} MNK/items {shp}: {cnt} launches {tms:.2f} ms ({1e3 * tms / cnt:.1f} us each)",
+              file=sys.stderr)
     peak_tf = PEAK[args.precision]
 
     workload_name = ("64-mode coupled oscillators + 200 cubic terms, binary leaf-only tree (127 nodes)"
@@ -1255,6 +1353,7 @@ def run_bench(args, api, k, D, stream):
                          "heff_all_nodes_tflop_per_s": round(heff_fl / (heff_ms * 1e-3) / 1e12, 2) if heff_ms else None,
                          "heff_all_nodes_frac_of_peak": round(heff_fl / (heff_ms * 1e-3) / 1e12 / peak_tf, 4)
                          if heff_ms else None,
+                         "heff_by_depth": heff_levels,
                          "dispatches": int(sum(v["launches"] for v in by_kernel.values())),
                          "contraction_ms": round(tot_ms, 1)},
     }
