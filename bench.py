@@ -46,10 +46,10 @@ def gemm_source_hash() -> str:
 
 
 def measured_traffic(kernel: str):
-    """(measured HBM bytes, compulsory bytes) per launch of `kernel` from the
+    """(measured HBM bytes, stage bytes) per launch of `kernel` from the
     committed counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated, on
-    the Gram launches of this workload), or None when there is none for this
-    kernel or the GEMM source changed since it was taken."""
+    the launches of the headline U1 probe), or None when there is none for
+    this kernel or the GEMM source changed since it was taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     rec = {}
@@ -60,6 +60,20 @@ def measured_traffic(kernel: str):
     if kernel not in rec or rec[kernel][0] != gemm_source_hash():
         return None
     return rec[kernel][1], rec[kernel][2]
+
+
+def measured_u1_call_traffic():
+    """(measured HBM bytes, compulsory U1 bytes) of one whole headline U1
+    call (all its stages) from the same summary, or None (absent, or the
+    GEMM source changed)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("u1call|"):
+            _, h, meas, comp = line.rstrip("\n").split("|")
+            if h == gemm_source_hash():
+                return float(meas), float(comp)
+    return None
 
 
 def calibrate_copy():
@@ -886,9 +900,18 @@ def pmc_summary(out: str, probe: str = "heff"):
     import csv
     import glob
     per = {}
+    region = {}  # counter -> sum over the dispatches between the probe's two markers
+    marker_grid = -(-MARKER_N // 256) * 256
     for f in sorted(glob.glob(os.path.join(out, f"{probe}_p*", f"{probe}_counter_collection.csv"))):
-        for r in csv.DictReader(open(f)):
+        rows = list(csv.DictReader(open(f)))
+        for r in rows:
             per.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        marks = sorted(int(r["Start_Timestamp"]) for r in rows
+                       if "vscale_kernel" in r["Kernel_Name"] and int(r["Grid_Size"]) == marker_grid)
+        if len(marks) >= 2:
+            for r in rows:
+                if marks[0] < int(r["Start_Timestamp"]) < marks[1]:
+                    region[r["Counter_Name"]] = region.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
     cal = {}
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
         f = os.path.join(out, f"copy_{c}", "copy_counter_collection.csv")
@@ -911,16 +934,14 @@ def pmc_summary(out: str, probe: str = "heff"):
     print("|---|---|---|---|---|---|---|---|")
     lines = []
     h = gemm_source_hash()
-    tot_bytes = 0.0
+    tot_bytes = (region.get("FETCH_SIZE", 0.0) * cal["FETCH_SIZE"] +
+                 region.get("WRITE_SIZE", 0.0) * cal["WRITE_SIZE"]) * 1024
     for name, cs in per.items():
         kn = short(name)
         m = {c: float(np.mean(v)) for c, v in cs.items()}
         nd = len(next(iter(cs.values())))
         rd = m.get("FETCH_SIZE", 0.0) * 1024 * cal["FETCH_SIZE"]
         wr = m.get("WRITE_SIZE", 0.0) * 1024 * cal["WRITE_SIZE"]
-        if not (kn.startswith("vscale") or kn.startswith("copyBuffer")):
-            tot_bytes += (sum(cs.get("FETCH_SIZE", [])) * cal["FETCH_SIZE"] +
-                          sum(cs.get("WRITE_SIZE", [])) * cal["WRITE_SIZE"]) * 1024
         pk = lookup(kn)
         if pk is None:
             continue
@@ -934,14 +955,15 @@ def pmc_summary(out: str, probe: str = "heff"):
               f"{exe / alg_fl if alg_fl else float('nan'):.3f} |")
         if rd + wr and (kn.startswith("ogemm") or kn.startswith("relayout")):
             lines.append(f"traffic|{kn}|{h}|{rd + wr:.6e}|{alg:.6e}")
-    # FETCH_SIZE / WRITE_SIZE passes each ran the probe once: the sum over its
-    # dispatches is the probe's measured traffic
+    # the measured region (between the probe's markers) of the FETCH_SIZE and
+    # WRITE_SIZE passes: the probe's calls, nothing of its set-up or warm-up
     if info and tot_bytes:
         if "u1_alg_bytes_per_call" in info:
             per_call = tot_bytes / info["calls"]
             print(f"\nWhole U1 call: measured {per_call / 1e6:.1f} MB per call against the compulsory "
                   f"{info['u1_alg_bytes_per_call'] / 1e6:.1f} MB (k (|X| + |Y|) + the k states' environments + W): "
                   f"{per_call / info['u1_alg_bytes_per_call']:.2f}x")
+            lines.append(f"u1call|{h}|{per_call:.6e}|{info['u1_alg_bytes_per_call']:.6e}")
         if "u2_alg_bytes_step" in info:
             print(f"\nWhole Gram step: measured {tot_bytes / 1e9:.2f} GB against the compulsory U2 bytes "
                   f"{info['u2_alg_bytes_step'] / 1e9:.2f} GB (node tensors once, every pair's environments in and "
@@ -1268,6 +1290,10 @@ def run_bench(args, api, k, D, stream):
     if tr is not None:
         roof["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
         roof["traffic_over_algorithmic_bytes"] = round(tr[0] / tr[1], 3)
+    tc = measured_u1_call_traffic()
+    if tc is not None:
+        roof["u1_call_traffic_bytes"] = round(tc[0], 0)
+        roof["u1_call_traffic_over_compulsory"] = round(tc[0] / tc[1], 2)
     for kern, d in sorted(u1_kernels.items(), key=lambda kv: -kv[1]["ms"]):
         print(f"  U1 kernel {kern}: {d['launches']} launches {d['ms']:.1f} ms "
               f"{d['flops'] / (d['ms'] * 1e-3) / 1e12:.1f} TFLOP/s shapes {sorted(d['shapes'])}", file=sys.stderr)
