@@ -166,8 +166,39 @@ def e1_runs(D=5, k=8, n_iter=2, n_exact=30):
     return out
 
 
+def c4_member_runs(n_iter=2):
+    """Two small members of the ensemble generator (seeds 4000 and 4001: the
+    coupled-oscillator generator on a balanced binary tree and the quartic
+    force field on a fork-4 comb; L, D, k drawn from the member's seed in
+    reduced ranges): oracle block LOBPCG for n_iter iterations, then a
+    restarted run of n_iter more from its states (a new shift from their
+    Rayleigh quotients, no search directions carried over), as the ensemble
+    driver runs a member twice."""
+    members = wl.ensemble_members(2, seed0=4000, D_range=(4, 6), k_range=(3, 5), L_range=(8, 10))
+    out = {"cite": f"oracle block LOBPCG (Alg. lobpcg_block), {n_iter} + {n_iter} iterations (restarted), ensemble "
+                   f"generator seeds 4000-4001 with L 8-10, D 4-6, k 3-5; shifted frame (harmonic ZPE removed)",
+           "n_iter": n_iter, "members": []}
+    for mb in members:
+        m = mb["model"]
+        tree = wl.binary_tree(m.dims) if mb["kind"] == "c4-binary" else wl.fork_tree(m.dims, 4, 1)
+        W = ttno.build_ttno(tree, m)
+        bonds = wl.bond_dims(tree, mb["D"])
+        x0 = wl.initial_block(tree, bonds, m.omega, m.dims, mb["k"], mb["seed"] + 17)
+        runs = []
+        xs = x0
+        for _ in range(2):
+            lam0 = solvers.rayleigh_quotients(tree, W, [solvers.normalized(tree, x) for x in xs])
+            shift = float(np.min(lam0)) - 837.0
+            xs, lam = solvers.lobpcg(tree, W, xs, solvers.LobpcgOptions(n_iter=n_iter, shift=shift))
+            runs.append(list(map(float, lam)))
+        out["members"].append({"seed": mb["seed"], "kind": mb["kind"], "L": mb["L"], "D": mb["D"], "k": mb["k"],
+                               "zpe": m.zpe_harmonic, "lam_after_run": runs})
+        print("member", mb["seed"], mb["kind"], mb["L"], mb["D"], mb["k"], "done", flush=True)
+    return out
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["c1", "c1_grow", "c3_cluster", "topologies", "e1"]
+    which = sys.argv[1:] or ["c1", "c1_grow", "c3_cluster", "topologies", "e1", "c4_members"]
     if "c1" in which:
         res = c1_runs()
         with open(os.path.join(HERE, "c1_oracle_runs.json"), "w") as f:
@@ -188,6 +219,11 @@ if __name__ == "__main__":
         with open(os.path.join(HERE, "topology_oracle_runs.json"), "w") as f:
             json.dump(res, f, indent=1)
         print("wrote topology_oracle_runs.json")
+    if "c4_members" in which:
+        res = c4_member_runs()
+        with open(os.path.join(HERE, "c4_member_oracle_runs.json"), "w") as f:
+            json.dump(res, f, indent=1)
+        print("wrote c4_member_oracle_runs.json")
     if "e1" in which:
         res = e1_runs()
         with open(os.path.join(HERE, "e1_oracle_runs.json"), "w") as f:
