@@ -33,7 +33,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}  # dense MFMA TFLOP/s (vendor)
+PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0, "f64_f32": 157.3}  # dense MFMA TFLOP/s (vendor)
+# (f64_f32: FP64 storage, the contractions on FP32 matrix cores)
 HBM_TBS = 8.0  # HBM3E TB/s (vendor)
 MARKER_N = 12345  # doubles scaled before and after the profiled step (grid of 49 x 256 threads)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")
@@ -754,7 +755,7 @@ def gram_probe(args):
     # U2 compulsory bytes of the step: per environment update (u -> parent),
     # with and without the operator, the 3k node tensors once, every pair's
     # incoming and outgoing environments, the site operator once
-    es = 4 if args.precision != "fp64" else 8
+    es = 8 if args.precision in ("fp64", "f64_f32") else 4
     n_pairs = len(ia)
     u2 = 0.0
     for (u, p) in s.up_edges:
@@ -1052,7 +1053,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16", "f64_f32"])
     ap.add_argument("--workload", default="c2", choices=["c2", "c3"])
     ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--bond", type=int, default=None)
@@ -1360,7 +1361,7 @@ def run_bench(args, api, k, D, stream):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[args.precision],
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16", "f64_f32": "f64/f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{workload_name}, D={D}, k={k}: heff_apply_block with the TTNO at the {node_name}, "
                                f"k={k} states per call, as issued inside K timed block-LOBPCG iterations (residual "

@@ -25,6 +25,7 @@ namespace ttn {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef double doublex2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 struct KOp {
@@ -422,7 +423,7 @@ __global__ __launch_bounds__(256, (CT == 1) ? 3 : 2) void ogemm_kernel(KArgs g) 
 // hit distinct bank groups without padding (measured on the 864 x 576 x 1008
 // stage: no bank-conflict cycles, 12% faster than a padded row).  BK = 32:
 // one barrier per 32 k.
-template <int BM, int BN, bool CMF>
+template <int BM, int BN, bool CMF, typename TS>
 __global__ __launch_bounds__(256, 2) void ogemm_tn_kernel(KArgs g) {
   if (g.gate && *g.gate == 0) return;  // uniform, before any barrier
   constexpr int BK = 32, LR = BK / 4;  // LDS row: the slice's 8 runs of 4 k (float4), XOR-swizzled
@@ -443,8 +444,24 @@ __global__ __launch_bounds__(256, 2) void ogemm_tn_kernel(KArgs g) {
   const int tni = tile - tmi * g.tiles_n;
   const int m0 = tmi * BM, n0 = tni * BN;
   const int M = g.M, N = g.N, K = g.K;
-  const float* __restrict__ A = (const float*)g.A.base + batch_off(g.A, z, g.z0, g.flag);
-  const float* __restrict__ B = (const float*)g.B.base + batch_off(g.B, z, g.z0, g.flag);
+  const TS* __restrict__ A = (const TS*)g.A.base + batch_off(g.A, z, g.z0, g.flag);
+  const TS* __restrict__ B = (const TS*)g.B.base + batch_off(g.B, z, g.z0, g.flag);
+  // a run of 4 consecutive k as loaded: FP32 storage one 16-byte load, FP64
+  // storage two (converted to FP32 when staged in LDS)
+  constexpr bool F64S = sizeof(TS) == 8;
+  typedef typename std::conditional<F64S, doublex4, floatx4>::type Run;
+  auto ld_run = [](const TS* p) -> Run {
+    if constexpr (F64S) {
+      const doublex2 lo = *(const doublex2*)p, hi = *(const doublex2*)(p + 2);
+      return Run{lo[0], lo[1], hi[0], hi[1]};
+    } else {
+      return *(const floatx4*)p;
+    }
+  };
+  auto to_f4 = [](const Run& r) -> floatx4 {
+    if constexpr (F64S) return floatx4{(float)r[0], (float)r[1], (float)r[2], (float)r[3]};
+    else return r;
+  };
 
   // staging map: thread t moves k run jq = t % 8 of rows t / 8 + 32 i; rows
   // past M (N) read offset 0 (always addressable) and are zeroed in LDS
@@ -468,28 +485,28 @@ __global__ __launch_bounds__(256, 2) void ogemm_tn_kernel(KArgs g) {
   // of two slices instead of one (the loop body is unrolled by two to keep
   // the sets in registers).  Tiles below 128 x 128 only.
   constexpr bool DEEP = BM * BN < 128 * 128;
-  floatx4 ra0[EA], rb0[EB], ra1[DEEP ? EA : 1], rb1[DEEP ? EB : 1];
+  Run ra0[EA], rb0[EB], ra1[DEEP ? EA : 1], rb1[DEEP ? EB : 1];
   bool kv0 = false, kv1 = false;
-  auto load = [&](floatx4* ra, floatx4* rb, bool& kv, int k0) {
+  auto load = [&](Run* ra, Run* rb, bool& kv, int k0) {
     const int kg = k0 + 4 * jq;
     kv = kg < K;  // K % 4 == 0: a run lies wholly inside or outside [0, K)
     const int ko = kv ? kg : 0;
 #pragma unroll
-    for (int i = 0; i < EA; ++i) ra[i] = *(const floatx4*)(A + a_fix[i] + ko);
+    for (int i = 0; i < EA; ++i) ra[i] = ld_run(A + a_fix[i] + ko);
 #pragma unroll
-    for (int i = 0; i < EB; ++i) rb[i] = *(const floatx4*)(B + b_fix[i] + ko);
+    for (int i = 0; i < EB; ++i) rb[i] = ld_run(B + b_fix[i] + ko);
   };
-  auto store = [&](const floatx4* ra, const floatx4* rb, bool kv, int buf) {
+  auto store = [&](const Run* ra, const Run* rb, bool kv, int buf) {
     const floatx4 z4 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < EA; ++i) {
       const int r = r0 + 32 * i;
-      As[buf][r * LR + (jq ^ (r & 7))] = (a_in[i] && kv) ? ra[i] : z4;
+      As[buf][r * LR + (jq ^ (r & 7))] = (a_in[i] && kv) ? to_f4(ra[i]) : z4;
     }
 #pragma unroll
     for (int i = 0; i < EB; ++i) {
       const int r = r0 + 32 * i;
-      Bs[buf][r * LR + (jq ^ (r & 7))] = (b_in[i] && kv) ? rb[i] : z4;
+      Bs[buf][r * LR + (jq ^ (r & 7))] = (b_in[i] && kv) ? to_f4(rb[i]) : z4;
     }
   };
 
@@ -561,8 +578,8 @@ __global__ __launch_bounds__(256, 2) void ogemm_tn_kernel(KArgs g) {
   }
 
   // ---- epilogue (as ogemm_kernel): C = alpha (acc - shift * D) (+ C)
-  float* __restrict__ C = (float*)g.C.base + batch_off(g.C, z, g.z0, g.flag);
-  const float* __restrict__ Dp = g.has_d ? (const float*)g.D.base + batch_off(g.D, z, g.z0, g.flag) : nullptr;
+  TS* __restrict__ C = (TS*)g.C.base + batch_off(g.C, z, g.z0, g.flag);
+  const TS* __restrict__ Dp = g.has_d ? (const TS*)g.D.base + batch_off(g.D, z, g.z0, g.flag) : nullptr;
   const double alpha = g.alpha ? g.alpha[g.z0 + z] : 1.0;
   const double sh = g.shift ? g.shift[g.z0 + z] : 0.0;
   constexpr int RI = CMF ? 1 : 4, CI = CMF ? 4 : 1;
@@ -595,12 +612,12 @@ __global__ __launch_bounds__(256, 2) void ogemm_tn_kernel(KArgs g) {
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int b = 0; b < TN; ++b)
-          if (rv[a][ri(i)] && cv[b][ci(i)]) C[cm[a][ri(i)] + cn[b][ci(i)]] = (float)(alpha * (double)acc[a][b][i]);
+          if (rv[a][ri(i)] && cv[b][ci(i)]) C[cm[a][ri(i)] + cn[b][ci(i)]] = (TS)(alpha * (double)acc[a][b][i]);
   } else {
-    const float* __restrict__ ds = Dp ? Dp : (const float*)C;
+    const TS* __restrict__ ds = Dp ? Dp : (const TS*)C;
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
-      float dv[4][TN], cvv[4][TN];
+      TS dv[4][TN], cvv[4][TN];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -616,7 +633,7 @@ __global__ __launch_bounds__(256, 2) void ogemm_tn_kernel(KArgs g) {
           const double d = Dp ? (double)dv[i][b] : (g.d_const ? 1.0 : 0.0);
           const double c0 = g.accum ? (double)cvv[i][b] : 0.0;
           if (rv[a][ri(i)] && cv[b][ci(i)])
-            C[cm[a][ri(i)] + cn[b][ci(i)]] = (float)(alpha * ((double)acc[a][b][i] - sh * d) + c0);
+            C[cm[a][ri(i)] + cn[b][ci(i)]] = (TS)(alpha * ((double)acc[a][b][i] - sh * d) + c0);
         }
     }
   }
@@ -1000,7 +1017,7 @@ static hipError_t launch_tile(const GemmDesc& gd, KArgs& a, int nz, hipStream_t 
 
 // unit-stride-k tiles (ids 10..16) and the general tile each falls back to
 // when a launch's operands are not 16-byte aligned
-template <int BM, int BN>
+template <int BM, int BN, typename TS>
 static hipError_t launch_tn(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s) {
   const int tm = (gd.M + BM - 1) / BM, tn = (gd.N + BN - 1) / BN;
   a.tiles_n = tn;
@@ -1009,20 +1026,21 @@ static hipError_t launch_tn(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s)
   static const int remap_min = env_int("TTN_XCD_REMAP_MIN", 16);  // workgroups: below that one XCD round
   a.xcd_remap = (int64_t)a.tiles * nz >= remap_min ? 1 : 0;
   dim3 grid = a.xcd_remap ? dim3((unsigned)(((int64_t)a.tiles * nz + 7) / 8 * 8), 1) : dim3(tm * tn, nz);
-  if (gd.c_mfast) hipLaunchKernelGGL((ogemm_tn_kernel<BM, BN, true>), grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((ogemm_tn_kernel<BM, BN, false>), grid, dim3(256), 0, s, a);
+  if (gd.c_mfast) hipLaunchKernelGGL((ogemm_tn_kernel<BM, BN, true, TS>), grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((ogemm_tn_kernel<BM, BN, false, TS>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
+template <typename TS>
 static hipError_t launch_tn_tile(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s) {
   switch (gd.tile) {
-    case 10: return launch_tn<128, 128>(gd, a, nz, s);
-    case 11: return launch_tn<128, 64>(gd, a, nz, s);
-    case 12: return launch_tn<64, 128>(gd, a, nz, s);
-    case 13: return launch_tn<64, 64>(gd, a, nz, s);
-    case 14: return launch_tn<96, 96>(gd, a, nz, s);
-    case 15: return launch_tn<64, 32>(gd, a, nz, s);
-    default: return launch_tn<128, 32>(gd, a, nz, s);
+    case 10: return launch_tn<128, 128, TS>(gd, a, nz, s);
+    case 11: return launch_tn<128, 64, TS>(gd, a, nz, s);
+    case 12: return launch_tn<64, 128, TS>(gd, a, nz, s);
+    case 13: return launch_tn<64, 64, TS>(gd, a, nz, s);
+    case 14: return launch_tn<96, 96, TS>(gd, a, nz, s);
+    case 15: return launch_tn<64, 32, TS>(gd, a, nz, s);
+    default: return launch_tn<128, 32, TS>(gd, a, nz, s);
   }
 }
 
@@ -1077,7 +1095,10 @@ static hipError_t launch_ct(const GemmDesc& gd, KArgs& a, int nz, hipStream_t s)
     return launch_ct<CT>(g2, a, nz, s);
   }
   if (gd.tile >= 10 && gd.tile <= 16) {
-    if (CT == 1 && tn_eligible(gd, CT) && aligned16(a.A) && aligned16(a.B)) return launch_tn_tile(gd, a, nz, s);
+    if constexpr (CT == 1 || CT == 3) {
+      if (tn_eligible(gd, CT) && aligned16(a.A) && aligned16(a.B))
+        return launch_tn_tile<typename std::conditional<CT == 3, double, float>::type>(gd, a, nz, s);
+    }
     GemmDesc g2 = gd;
     g2.tile = kTnFallback[gd.tile - 10];
     return launch_ct<CT>(g2, a, nz, s);
@@ -1102,7 +1123,7 @@ std::string gemm_kernel_name(int ctype, const GemmDesc& gd) {
   if (gd.tile >= 10 && gd.tile <= 16) {
     if (tn_eligible(gd, ctype))
       return "ogemm_tn_kernel<" + std::to_string(kTnBM[gd.tile - 10]) + ", " + std::to_string(kTnBN[gd.tile - 10]) +
-             ", " + (gd.c_mfast ? "true" : "false") + ">";
+             ", " + (gd.c_mfast ? "true" : "false") + (ctype == 3 ? ", double>" : ">");
     GemmDesc g2 = gd;
     g2.tile = kTnFallback[gd.tile - 10];
     return gemm_kernel_name(ctype, g2);

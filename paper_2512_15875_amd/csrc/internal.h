@@ -65,7 +65,8 @@ inline bool narrow_eligible(const GemmDesc& g, int ctype) {
 // the unit-stride-k tile kernel (tiles 10..16) applies: FP32, both operands
 // contiguous along k (K % 4 == 0), row / column offsets multiples of 4
 inline bool tn_eligible(const GemmDesc& g, int ctype) {
-  return ctype == 1 && g.K >= 32 && g.K % 4 == 0 && !g.a_mfast && !g.b_nfast && g.k_unit && g.rows_al4;
+  return (ctype == 1 || ctype == 3) && g.K >= 32 && g.K % 4 == 0 && !g.a_mfast && !g.b_nfast && g.k_unit &&
+         g.rows_al4;
 }
 
 struct Epilogue {

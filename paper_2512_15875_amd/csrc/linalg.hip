@@ -820,25 +820,23 @@ __global__ void absorb_kernel(const T* X, int64_t size, const int32_t* roff, int
 
 // Row-wise absorption for bonds n <= NMAX: the state's R is staged in LDS,
 // each thread owns one row r (all n outputs from one read of the row's n
-// inputs); a grid of (row blocks, states).  The row is loaded before R is
-// staged, so the two global reads are in flight together.
+// inputs); a grid of (row blocks, states).
 template <typename T, int NMAX>
 __global__ __launch_bounds__(256) void absorb_rows_kernel(const T* X, int64_t size, const int32_t* roff, int m, int n,
                                                           int64_t cstride, const double* R, T* Y) {
   __shared__ double sR[NMAX * NMAX];
   const int z = blockIdx.y, t = threadIdx.x;
-  const int r = blockIdx.x * 256 + t;
-  const bool valid = r < m;
-  const T* Xz = X + (int64_t)z * size;
-  T* Yz = Y + (int64_t)z * size;
-  const int64_t ro = valid ? roff[r] : 0;
-  double xr[NMAX];
-#pragma unroll
-  for (int j = 0; j < NMAX; ++j) xr[j] = (valid && j < n) ? (double)Xz[ro + (int64_t)j * cstride] : 0.0;
   const double* Rz = R + (size_t)z * n * n;
   for (int i = t; i < n * n; i += 256) sR[i] = Rz[i];
   __syncthreads();
-  if (!valid) return;
+  const int r = blockIdx.x * 256 + t;
+  if (r >= m) return;
+  const T* Xz = X + (int64_t)z * size;
+  T* Yz = Y + (int64_t)z * size;
+  const int64_t ro = roff[r];
+  double xr[NMAX];
+#pragma unroll
+  for (int j = 0; j < NMAX; ++j) xr[j] = j < n ? (double)Xz[ro + (int64_t)j * cstride] : 0.0;
 #pragma unroll
   for (int i = 0; i < NMAX; ++i) {
     if (i >= n) break;

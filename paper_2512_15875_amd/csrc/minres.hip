@@ -143,97 +143,6 @@ __global__ __launch_bounds__(MR_NT) void minres_step(T* x, T* v, T* vprev, T* p,
   if (t == 0) st[z] = s;
 }
 
-// The same step with the state's vectors held in registers, for n <= CI
-// MR_NT: every operand of a thread's elements (i = t + c MR_NT) is loaded at
-// once, together with the state, so an iteration pays one memory latency
-// instead of one per pass; the arithmetic and the order of every sum are
-// those of minres_step (elements past n enter as zeros at the end of a
-// thread's partial sums), so the results are identical.
-template <typename T, int CI>
-__global__ __launch_bounds__(MR_NT) void minres_step_reg(T* x, T* v, T* vprev, T* p, const T* dp, T* dpp, int64_t n,
-                                                       MinresState* st) {
-  __shared__ double red[MR_NT / 64];
-  __shared__ MinresState s;
-  __shared__ double sh[6];  // eps, delta, gamma, tau, beta_next, alive
-  const int z = blockIdx.x, t = threadIdx.x;
-  T* xz = x + (int64_t)z * n;
-  T* vz = v + (int64_t)z * n;
-  T* vpz = vprev + (int64_t)z * n;
-  T* pz = p + (int64_t)z * n;
-  const T* dz = dp + (int64_t)z * n;
-  T* dppz = dpp + (int64_t)z * n;
-  T rv[CI], rp[CI], rvp[CI], rd[CI], rdd[CI], rx[CI];
-#pragma unroll
-  for (int c = 0; c < CI; ++c) {
-    const int64_t i = t + (int64_t)c * MR_NT;
-    const bool ok = i < n;
-    rv[c] = ok ? vz[i] : T(0);
-    rp[c] = ok ? pz[i] : T(0);
-    rvp[c] = ok ? vpz[i] : T(0);
-    rd[c] = ok ? dz[i] : T(0);
-    rdd[c] = ok ? dppz[i] : T(0);
-    rx[c] = ok ? xz[i] : T(0);
-  }
-  if (t == 0) s = st[z];
-  __syncthreads();
-  if (s.done) return;
-  double a = 0;
-#pragma unroll
-  for (int c = 0; c < CI; ++c) a += (double)rv[c] * (double)rp[c];
-  const double alpha = wg_sum(a, red);
-  double nn = 0;
-#pragma unroll
-  for (int c = 0; c < CI; ++c) {
-    const int64_t i = t + (int64_t)c * MR_NT;
-    const double q = (double)rp[c] - alpha * (double)rv[c] - s.beta * (double)rvp[c];
-    rp[c] = (T)q;
-    if (i < n) pz[i] = rp[c];
-    nn += q * q;
-  }
-  const double bn = sqrt(wg_sum(nn, red));
-  if (t == 0) {
-    const double eps = s.s1 * s.beta;
-    const double dbar = s.c1 * s.beta;
-    const double delta = s.c2 * dbar + s.s2 * alpha;
-    const double gbar = -s.s2 * dbar + s.c2 * alpha;
-    const double gamma = hypot(gbar, bn);
-    sh[0] = eps;
-    sh[1] = delta;
-    sh[2] = gamma;
-    sh[4] = bn;
-    if (gamma == 0.0) {
-      s.done = 1;
-      sh[5] = 0;
-    } else {
-      const double c = gbar / gamma, sn = bn / gamma;
-      sh[3] = c * s.phibar;
-      s.phibar = -sn * s.phibar;
-      s.c1 = s.c2;
-      s.s1 = s.s2;
-      s.c2 = c;
-      s.s2 = sn;
-      s.iters += 1;
-      s.beta = bn;
-      if (fabs(s.phibar) <= s.tol || bn == 0.0) s.done = 1;
-      sh[5] = 1;
-    }
-  }
-  __syncthreads();
-  if (sh[5] != 0) {
-    const double eps = sh[0], delta = sh[1], gamma = sh[2], tau = sh[3], bnext = sh[4];
-#pragma unroll
-    for (int c = 0; c < CI; ++c) {
-      const int64_t i = t + (int64_t)c * MR_NT;
-      if (i < n) {
-        const double dn = ((double)rv[c] - delta * (double)rd[c] - eps * (double)rdd[c]) / gamma;
-        dppz[i] = (T)dn;
-        xz[i] = (T)((double)rx[c] + tau * dn);
-        vpz[i] = (T)(bnext > 0 ? (double)rp[c] / bnext : 0.0);
-      }
-    }
-  }
-  if (t == 0) st[z] = s;
-}
 
 template <typename T>
 __global__ void minres_report(const MinresState* st, int k, int32_t* iters, double* resid, int32_t* n_active) {
@@ -272,32 +181,8 @@ hipError_t launch_minres_count(const MinresState* st, int k, int32_t* active, hi
   return hipGetLastError();
 }
 
-template <typename T, int CI>
-static void minres_step_reg_launch(void* x, void* v, void* vprev, void* p, const void* dp, void* dpp, int64_t n, int k,
-                                   MinresState* st, hipStream_t s) {
-  hipLaunchKernelGGL((minres_step_reg<T, CI>), dim3(k), dim3(MR_NT), 0, s, (T*)x, (T*)v, (T*)vprev, (T*)p,
-                     (const T*)dp, (T*)dpp, n, st);
-}
-
 hipError_t launch_minres_step(int ctype, void* x, void* v, void* vprev, void* p, const void* dp, void* dpp, int64_t n,
                               int k, MinresState* st, hipStream_t s) {
-  // register-held vectors while they fit without spilling (FP64 up to 4
-  // elements per thread, FP32 up to 8: the workgroup's 16 waves leave 128
-  // VGPRs a wave): the small, latency-bound nodes; larger nodes stream
-  const int64_t ci = (n + MR_NT - 1) / MR_NT;
-  if (ctype == 0 && ci <= 4) {
-    if (ci <= 1) minres_step_reg_launch<double, 1>(x, v, vprev, p, dp, dpp, n, k, st, s);
-    else if (ci <= 2) minres_step_reg_launch<double, 2>(x, v, vprev, p, dp, dpp, n, k, st, s);
-    else minres_step_reg_launch<double, 4>(x, v, vprev, p, dp, dpp, n, k, st, s);
-    return hipGetLastError();
-  }
-  if (ctype != 0 && ci <= 8) {
-    if (ci <= 1) minres_step_reg_launch<float, 1>(x, v, vprev, p, dp, dpp, n, k, st, s);
-    else if (ci <= 2) minres_step_reg_launch<float, 2>(x, v, vprev, p, dp, dpp, n, k, st, s);
-    else if (ci <= 4) minres_step_reg_launch<float, 4>(x, v, vprev, p, dp, dpp, n, k, st, s);
-    else minres_step_reg_launch<float, 8>(x, v, vprev, p, dp, dpp, n, k, st, s);
-    return hipGetLastError();
-  }
   if (ctype == 0)
     hipLaunchKernelGGL(minres_step<double>, dim3(k), dim3(MR_NT), 0, s, (double*)x, (double*)v, (double*)vprev,
                        (double*)p, (const double*)dp, (double*)dpp, n, st);

@@ -61,32 +61,36 @@ def test_heff_apply_matches_oracle(api, ctx, case, dt):
 
 
 @pytest.mark.parametrize("tile", [10, 11, 12, 13, 14, 15, 16])
-def test_unit_k_tiles_match_oracle(api, tile, monkeypatch):
+@pytest.mark.parametrize("dt", [1, 3])
+def test_unit_k_tiles_match_oracle(api, tile, dt, monkeypatch):
     """Every tile of the unit-stride-k kernel, forced at planning time (fresh
-    context per tile), on an FP32 H_eff at a three-leg node without a physical
-    leg: M and N ragged for every tile, contractions with a K tail (K % 32 !=
-    0), against the oracle; the profile must name the kernel."""
+    context per tile), on an H_eff at a three-leg node without a physical leg,
+    FP32 storage and FP64 storage with FP32 arithmetic: M and N ragged for
+    every tile, contractions with a K tail (K % 32 != 0), against the oracle;
+    the profile must name the kernel (and its FP64-storage instance)."""
     monkeypatch.setenv("TTN_FORCE_TILE", str(tile))
     ctx = api.Context(0, workspace_bytes=1 << 28)
     Db = Da = [15, 14, 13]
     M = [20, 12, 10]
     k = 3
-    tree, W, X, E, gt, gW, envs, tdt = _setup(api, ctx, 3, 1, Db, M, Da, k, 91, api.F32)
+    tree, W, X, E, gt, gW, envs, tdt = _setup(api, ctx, 3, 1, Db, M, Da, k, 91, dt)
     shift = np.linspace(-1.0, 2.0, k)
     gX = to_dev(X, tdt)
     gY = torch.zeros((k,) + tuple(Db) + (1,), dtype=tdt, device="cuda")
     api.profile(ctx, True)
-    api.heff_apply_block(ctx, gt, gW, envs, 1, k, gX, gY, shift=to_dev(shift), compute=api.F32)
+    api.heff_apply_block(ctx, gt, gW, envs, 1, k, gX, gY, shift=to_dev(shift), compute=dt)
     rep = api.profile_report(ctx)
     api.profile(ctx, False)
     ctx.sync()
     kernels = {r[2] for r in rep}
-    assert any(kn.startswith("ogemm_tn_kernel") for kn in kernels), kernels
+    tn = [kn for kn in kernels if kn.startswith("ogemm_tn_kernel")]
+    assert tn, kernels
+    assert all(kn.endswith(", double>") == (dt == 3) for kn in tn), tn
     Y = gY.double().cpu().numpy()
     for j in range(k):
         ein = {c: E[c][j] for c in tree.neighbours(1)}
         ref = ottn.heff_apply(tree, 1, W, X[j], ein, shift[j])
-        assert rel_err(Y[j], ref) < TOL[1], (tile, j)
+        assert rel_err(Y[j], ref) < TOL[dt], (tile, dt, j)
     ctx.close()
 
 
