@@ -852,7 +852,8 @@ def trace_summary(path: str, kernel: str):
         gx = int(r.get("Grid_Size_X", r.get("Grid_Size", "0")) or 0)
         rec.append((t0, t1, name, gx))
     rec.sort()
-    short = lambda k: k.replace("void ttn::", "").replace("ttn::", "").split("(")[0]
+    # the library names the unit-stride-k tiles by their FP32 instance without the storage type
+    short = lambda k: k.replace("void ttn::", "").replace("ttn::", "").split("(")[0].replace(", float>", ">")
     marker_grid = -(-MARKER_N // 256) * 256
     marks = [i for i, (_, _, n, gx) in enumerate(rec) if "vscale_kernel" in n and gx == marker_grid]
 
@@ -923,7 +924,8 @@ def pmc_summary(out: str, probe: str = "heff"):
         if line.startswith('{"' + probe + '_probe"'):
             info = json.loads(line)
     kinfo = (info or {}).get("kernels", {})
-    short = lambda k: k.replace("void ttn::", "").split("(")[0]
+    # the library names the unit-stride-k tiles by their FP32 instance without the storage type
+    short = lambda k: k.replace("void ttn::", "").split("(")[0].replace(", float>", ">")
 
     def lookup(kn):  # the probe names fused kernels without their template arguments
         return kinfo.get(kn) or kinfo.get(kn.split("<")[0])
