@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
 All states live on one tree with the bond dimensions of the block; states are
 lists of node tensors (legs [parent, children..., p]).  Every routine follows
-the paper's algorithm in its order, with the readings listed in the design doc:
+the paper's algorithm in its order; where the paper leaves a choice open, the
+reading taken is stated at the routine:
 
 * ``als_solve``   -- ALS for (H - s I) y = phi (Sec. II.C.3): node-by-node
   local solves with MINRES on (H_eff - s) y_u = b_u, b_u from the (y, phi)

@@ -8,7 +8,7 @@ bipartite graph between their parts on the two sides; a minimum vertex cover
 of that graph gives the edge's channels (its bond dimension), and symbolic
 Gaussian elimination places the coefficients so that every term is carried
 exactly once.  The paper sketches the procedure; this is one reading of it,
-written out (the design doc lists it):
+written out:
 
 Edges are treated leaves to root.  At the edge e above node v every current
 item (a term, or a group of terms merged further down) is an edge of the

@@ -8,9 +8,9 @@ quotients, residual norms) to decide clusters and stopping; PyTorch provides
 device buffers (allocated once per solver) and plain copies between them.
 
 Algorithms: Alg. lobpcg_block with the three-term recurrence (Eq. lobpcg
-update) and Alg. block_inverse_iteration, with the readings listed in
-the design doc (subspace {x, w} on the first iteration, x_j = sum over all 3n
-basis states, clusters fixed after LOBPCG, a final global Rayleigh-Ritz).
+update) and Alg. block_inverse_iteration, read as: the subspace {x, w} on
+the first iteration, x_j a combination of all 3n basis states, clusters
+fixed after LOBPCG, and a final global Rayleigh-Ritz.
 """
 from __future__ import annotations
 
