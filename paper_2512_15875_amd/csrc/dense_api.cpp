@@ -16,6 +16,7 @@ hipError_t launch_rr(int batch, const int32_t* d_m, int ld, const double* H, con
                      hipStream_t s);
 hipError_t launch_qr(int ctype, void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride, double* work,
                      double* R, int nz, int* flag, hipStream_t s);
+const char* qr_path_name(int m, int n);
 bool absorb_in_place(int m, int n);
 hipError_t launch_absorb(int ctype, const void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride,
                          const double* R, void* Y, int nz, hipStream_t s);
@@ -126,7 +127,7 @@ ttn_status ttn_block_move_centre(ttn_ctx* ctx, ttn_block* b, int32_t u, int32_t 
   // tensor is read and written once, R written once
   const double fq = 4.0 * m_u * (double)n * n - 4.0 * (double)n * n * n / 3.0;
   const std::string qkey = "qr:" + std::to_string(m_u) + "x" + std::to_string(n);
-  ttn_prof_rec* pr = prof_begin(ctx, qkey.c_str(), "qr_kernel", fq * k, (double)k * (2.0 * m_u * n * es + 8.0 * n * n), k);
+  ttn_prof_rec* pr = prof_begin(ctx, qkey.c_str(), qr_path_name(m_u, n), fq * k, (double)k * (2.0 * m_u * n * es + 8.0 * n * n), k);
   hipError_t e = launch_qr(ct, b->ptr[u], b->size[u], ru, m_u, n, cs_u, wk, R, k, ctx->d_flag, ctx->stream);
   prof_end(ctx, pr);
   if (e != hipSuccess) return api_fail(ctx, TTN_E_LAUNCH, hipGetErrorString(e));

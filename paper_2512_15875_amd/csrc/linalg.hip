@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
+#include <type_traits>
 
 #include <cmath>
 
@@ -565,9 +566,6 @@ __global__ __launch_bounds__(256) void qr_kernel(T* X, int64_t size, const int32
   }
 }
 
-// sum over the 64 lanes of a wave, result in every lane
-
-
 // Householder QR with the working matrix resident in LDS (dynamic shared
 // memory, FP64): column-major A (m x n); reflector k is stored in place below
 // the diagonal normalised to v_k = 1 (tau scaled to match), R is saved to a
@@ -579,32 +577,52 @@ __global__ __launch_bounds__(256) void qr_kernel(T* X, int64_t size, const int32
 // builds reflector k+1 from that column, which no other wave touches in the
 // step.  The Q formation mirrors it: wave 0 finishes column i+1 as a column
 // of Q and applies reflector i to it while the other waves take columns i+2..
-// The sign fix makes diag(R) >= 0 as in the global-memory kernel above, which
-// serves the nodes whose m x n doubles do not fit.
+// The sign fix makes diag(R) >= 0 as in the global-memory kernel above.
+// Nodes whose m x n doubles do not fit go through the TSQR kernels below,
+// which factor row blocks with the same LDS routine, and the global-memory
+// kernel serves only shapes that TSQR cannot block.
 
 #define QR_NT 1024  // threads of the LDS-resident QR (16 waves: more columns in flight per reflector)
 #define QR_NW (QR_NT / 64)
+#define QR_QG 8  // loads of a thread in flight together when a matrix is gathered from or scattered to a node
 
+// A[j*rows + i] = Xz[roff[r0 + i] + j*cstride] in double (i < rows, j < n):
+// a thread loads the row offsets of QR_QG elements, then the QR_QG elements,
+// so that its loads overlap instead of waiting on one dependent pair at a time
+template <typename T>
+__device__ __forceinline__ void qr_gather(double* A, const T* Xz, const int32_t* roff, int r0, int rows, int n,
+                                          int64_t cstride) {
+  const int tot = rows * n;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += QR_QG * QR_NT) {
+    // indices past the end are clamped to the last element, so every load is
+    // unconditional (no branch between them) and only the stores are masked
+    int64_t off[QR_QG];
+#pragma unroll
+    for (int u = 0; u < QR_QG; ++u) {
+      const int e = min(e0 + u * QR_NT, tot - 1), j = e / rows, i = e - j * rows;
+      off[u] = (int64_t)roff[r0 + i] + (int64_t)j * cstride;
+    }
+    T v[QR_QG];
+#pragma unroll
+    for (int u = 0; u < QR_QG; ++u) v[u] = Xz[off[u]];
+#pragma unroll
+    for (int u = 0; u < QR_QG; ++u)
+      if (e0 + u * QR_NT < tot) A[e0 + u * QR_NT] = (double)v[u];
+  }
+}
+
+// Householder QR of the m x n (m >= n) column-major matrix A in LDS by the
+// whole workgroup.  On entry Rl (n x n, row-major) is zero; on return A holds
+// the explicit Q and Rl the upper-triangular R, both before any sign fix;
+// tau (n doubles) is scratch.
 // ITM > 0: every row loop of a lane has at most ITM iterations (m <= 64 ITM),
 // unrolled so that a lane's LDS loads are all in flight before its FMAs;
 // ITM = 0: runtime-bounded loops.
-template <typename T, int ITM>
-__global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const int32_t* roff, int m, int n,
-                                                     int64_t cstride, double* Rout, int* flag) {
-  extern __shared__ double sm[];
-  double* A = sm;                  // m * n, column-major
-  double* Rl = A + (size_t)m * n;  // n * n, row-major
-  double* tau = Rl + (size_t)n * n;
-  const int z = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+template <int ITM>
+__device__ __forceinline__ void qr_lds_factor(double* A, double* Rl, double* tau, int m, int n) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   constexpr int IT = ITM > 0 ? ITM : 1;
   const int nit = ITM > 0 ? ITM : (m + 63) / 64;  // iterations of the runtime form
-  T* Xz = X + (int64_t)z * size;
-  for (int i = t; i < m * n; i += QR_NT) {
-    const int j = i / m, r = i - j * m;
-    A[i] = (double)Xz[roff[r] + (int64_t)j * cstride];
-  }
-  for (int i = t; i < n * n; i += QR_NT) Rl[i] = 0.0;
-  __syncthreads();
   // y_i -= d v_i and d = sum v_i y_i over rows i = s + lane + 64 it (< m), with
   // the v rows loaded once per reflector
   auto dot_update = [&](const double* v, double* y, int s, int kd, double tk) {
@@ -787,17 +805,152 @@ __global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const
   }
   finish(0, t, QR_NT);
   __syncthreads();
+}
+
+template <typename T, int ITM>
+__global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const int32_t* roff, int m, int n,
+                                                     int64_t cstride, double* Rout, int* flag) {
+  extern __shared__ double sm[];
+  double* A = sm;                  // m * n, column-major
+  double* Rl = A + (size_t)m * n;  // n * n, row-major
+  double* tau = Rl + (size_t)n * n;
+  const int z = blockIdx.x, t = threadIdx.x;
+  T* Xz = X + (int64_t)z * size;
+  qr_gather(A, Xz, roff, 0, m, n, cstride);
+  for (int i = t; i < n * n; i += QR_NT) Rl[i] = 0.0;
+  __syncthreads();
+  qr_lds_factor<ITM>(A, Rl, tau, m, n);
   // sign fix diag(R) >= 0, R out (row-major), Q back to the node tensor
   double* R = Rout + (size_t)z * n * n;
   for (int e = t; e < n * n; e += QR_NT) {
     const int r = e / n;
     R[e] = Rl[r * n + r] < 0 ? -Rl[e] : Rl[e];
   }
-  for (int i = t; i < m * n; i += QR_NT) {
-    const int j = i / m, r = i - j * m;
-    const double q = Rl[j * n + j] < 0 ? -A[i] : A[i];
-    if (!isfinite(q)) atomicOr(flag, 1);
-    Xz[roff[r] + (int64_t)j * cstride] = (T)q;
+  const int tot = m * n;
+  for (int e0 = t; e0 < tot; e0 += QR_QG * QR_NT) {
+    int64_t off[QR_QG];
+#pragma unroll
+    for (int u = 0; u < QR_QG; ++u) {
+      const int e = min(e0 + u * QR_NT, tot - 1), j = e / m, r = e - j * m;
+      off[u] = (int64_t)roff[r] + (int64_t)j * cstride;
+    }
+#pragma unroll
+    for (int u = 0; u < QR_QG; ++u) {
+      const int e = e0 + u * QR_NT, j = e / m;
+      if (e < tot) {
+        const double q = Rl[j * n + j] < 0 ? -A[e] : A[e];
+        if (!isfinite(q)) atomicOr(flag, 1);
+        Xz[off[u]] = (T)q;
+      }
+    }
+  }
+}
+
+// Tall-skinny QR (TSQR) for node matrices whose m x n doubles do not fit one
+// workgroup's LDS: the rows are cut into P blocks of mb rows (the last block
+// shorter, none below n rows).  Per state z the workspace W_z (2 m n doubles)
+// holds the blocks' explicit Q_b (rows_b x n, column-major) at W_z + r0_b n,
+// then the stacked R factors S ((P n) x n, column-major) at W_z + m n.
+// Leaf: block b of state z factored in LDS with the kernel above.
+template <typename T, int ITM>
+__global__ __launch_bounds__(QR_NT) void tsqr_leaf_kernel(const T* X, int64_t size, const int32_t* roff, int m,
+                                                        int n, int64_t cstride, int mb, int P, double* work) {
+  extern __shared__ double sm[];
+  const int b = blockIdx.x, z = blockIdx.y, t = threadIdx.x;
+  const int r0 = b * mb, rows = min(mb, m - r0);
+  double* A = sm;
+  double* Rl = A + (size_t)rows * n;
+  double* tau = Rl + (size_t)n * n;
+  qr_gather(A, X + (int64_t)z * size, roff, r0, rows, n, cstride);
+  for (int i = t; i < n * n; i += QR_NT) Rl[i] = 0.0;
+  __syncthreads();
+  qr_lds_factor<ITM>(A, Rl, tau, rows, n);
+  double* Wz = work + (size_t)z * 2 * m * n;
+  double* Qb = Wz + (size_t)r0 * n;
+  for (int e = t; e < rows * n; e += QR_NT) Qb[e] = A[e];
+  double* S = Wz + (size_t)m * n;
+  const int ps = P * n;
+  for (int e = t; e < n * n; e += QR_NT) {
+    const int r = e / n, c = e - r * n;
+    S[(size_t)c * ps + b * n + r] = Rl[e];  // zero below the diagonal
+  }
+}
+
+// Root: S = Q2 R in LDS, diag(R) >= 0 by flipping rows of R and the matching
+// columns of Q2; R to Rout[z] (row-major), Q2 over S.
+template <int ITM>
+__global__ __launch_bounds__(QR_NT) void tsqr_root_kernel(int m, int n, int P, double* work, double* Rout) {
+  extern __shared__ double sm[];
+  const int z = blockIdx.x, t = threadIdx.x, ps = P * n;
+  double* A = sm;
+  double* Rl = A + (size_t)ps * n;
+  double* tau = Rl + (size_t)n * n;
+  double* S = work + (size_t)z * 2 * m * n + (size_t)m * n;
+  for (int e = t; e < ps * n; e += QR_NT) A[e] = S[e];
+  for (int i = t; i < n * n; i += QR_NT) Rl[i] = 0.0;
+  __syncthreads();
+  qr_lds_factor<ITM>(A, Rl, tau, ps, n);
+  double* R = Rout + (size_t)z * n * n;
+  for (int e = t; e < n * n; e += QR_NT) {
+    const int r = e / n;
+    R[e] = Rl[r * n + r] < 0 ? -Rl[e] : Rl[e];
+  }
+  for (int e = t; e < ps * n; e += QR_NT) {
+    const int j = e / ps;
+    S[e] = Rl[j * n + j] < 0 ? -A[e] : A[e];
+  }
+}
+
+// Apply: the rows of block b of the state's Q are Q_b times rows b n .. b n + n - 1
+// of Q2; Q_b and that n x n slice staged in LDS, a thread per (row, QR_NC
+// output columns), written into the node tensor.
+#define QR_NC 8
+template <typename T>
+__global__ __launch_bounds__(QR_NT) void tsqr_apply_kernel(T* X, int64_t size, const int32_t* roff, int m, int n,
+                                                         int64_t cstride, int mb, int P, const double* work,
+                                                         int* flag) {
+  extern __shared__ double sm[];
+  const int b = blockIdx.x, z = blockIdx.y, t = threadIdx.x;
+  const int r0 = b * mb, rows = min(mb, m - r0), ps = P * n;
+  const double* Wz = work + (size_t)z * 2 * m * n;
+  const double* Qb = Wz + (size_t)r0 * n;
+  const double* Q2 = Wz + (size_t)m * n;
+  double* sq = sm;                          // rows x n, column-major
+  double* s2 = sq + (size_t)rows * n;       // n x n: s2[l n + j] = Q2[b n + l][j]
+  const int tot = rows * n;
+  for (int e0 = t; e0 < tot; e0 += QR_QG * QR_NT) {
+    double v[QR_QG];
+#pragma unroll
+    for (int u = 0; u < QR_QG; ++u) v[u] = Qb[min(e0 + u * QR_NT, tot - 1)];
+#pragma unroll
+    for (int u = 0; u < QR_QG; ++u)
+      if (e0 + u * QR_NT < tot) sq[e0 + u * QR_NT] = v[u];
+  }
+  for (int e = t; e < n * n; e += QR_NT) {
+    const int l = e / n, j = e - l * n;
+    s2[e] = Q2[(size_t)j * ps + b * n + l];
+  }
+  __syncthreads();
+  T* Xz = X + (int64_t)z * size;
+  const int nch = (n + QR_NC - 1) / QR_NC;
+  for (int w = t; w < rows * nch; w += QR_NT) {
+    const int c = w / rows, i = w - c * rows, j0 = c * QR_NC;
+    const int64_t ro = roff[r0 + i];
+    double acc[QR_NC];
+#pragma unroll
+    for (int q = 0; q < QR_NC; ++q) acc[q] = 0.0;
+    for (int l = 0; l < n; ++l) {
+      const double a = sq[(size_t)l * rows + i];
+#pragma unroll
+      for (int q = 0; q < QR_NC; ++q) acc[q] += a * s2[l * n + min(j0 + q, n - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < QR_NC; ++q) {
+      if (j0 + q < n) {
+        if (!isfinite(acc[q])) atomicOr(flag, 1);
+        Xz[ro + (int64_t)(j0 + q) * cstride] = (T)acc[q];
+      }
+    }
   }
 }
 
@@ -857,41 +1010,125 @@ static hipError_t qr_t(void* X, int64_t size, const int32_t* roff, int m, int n,
 // LDS budget of the resident-matrix QR (the CU has 160 KiB)
 static constexpr size_t QR_LDS_MAX = 150 * 1024;
 
-template <typename T, int ITM>
-static bool qr_lds_it(void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride, double* R, int nz,
-                      int* flag, size_t bytes, hipStream_t s) {
-  static const bool enabled = hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_lds_kernel<T, ITM>),
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                  (int)QR_LDS_MAX) == hipSuccess;
-  if (!enabled) return false;
-  hipLaunchKernelGGL((qr_lds_kernel<T, ITM>), dim3(nz), dim3(QR_NT), bytes, s, (T*)X, size, roff, m, n, cstride, R,
-                     flag);
-  return hipGetLastError() == hipSuccess;
+// f(std::integral_constant<int, ITM>) for the smallest unrolled row-loop
+// bound ITM that covers `rows` (0: the runtime-bounded form)
+template <typename F>
+static bool with_itm(int rows, F&& f) {
+  const int need = (rows + 63) / 64;  // row iterations of a lane
+  if (need <= 1) return f(std::integral_constant<int, 1>{});
+  if (need <= 2) return f(std::integral_constant<int, 2>{});
+  if (need <= 3) return f(std::integral_constant<int, 3>{});
+  if (need <= 4) return f(std::integral_constant<int, 4>{});
+  if (need <= 6) return f(std::integral_constant<int, 6>{});
+  if (need <= 9) return f(std::integral_constant<int, 9>{});
+  if (need <= 12) return f(std::integral_constant<int, 12>{});
+  if (need <= 16) return f(std::integral_constant<int, 16>{});
+  return f(std::integral_constant<int, 0>{});
 }
+
+// one-time opt-in of a kernel to QR_LDS_MAX bytes of dynamic LDS
+static bool lds_opt_in(const void* fn) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)QR_LDS_MAX) == hipSuccess;
+}
+
+static size_t qr_lds_bytes(int m, int n) { return ((size_t)m * n + (size_t)n * n + (size_t)n) * sizeof(double); }
 
 template <typename T>
 static bool qr_lds(void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride, double* R, int nz,
                    int* flag, hipStream_t s) {
-  const size_t bytes = ((size_t)m * n + (size_t)n * n + (size_t)n) * sizeof(double);
+  const size_t bytes = qr_lds_bytes(m, n);
   if (bytes > QR_LDS_MAX) return false;
-  const int need = (m + 63) / 64;  // row iterations of a lane
-  if (need <= 1) return qr_lds_it<T, 1>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
-  if (need <= 2) return qr_lds_it<T, 2>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
-  if (need <= 3) return qr_lds_it<T, 3>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
-  if (need <= 4) return qr_lds_it<T, 4>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
-  if (need <= 6) return qr_lds_it<T, 6>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
-  if (need <= 9) return qr_lds_it<T, 9>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
-  if (need <= 12) return qr_lds_it<T, 12>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
-  if (need <= 16) return qr_lds_it<T, 16>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
-  return qr_lds_it<T, 0>(X, size, roff, m, n, cstride, R, nz, flag, bytes, s);
+  return with_itm(m, [&](auto I) {
+    constexpr int ITM = decltype(I)::value;
+    static const bool enabled = lds_opt_in(reinterpret_cast<const void*>(&qr_lds_kernel<T, ITM>));
+    if (!enabled) return false;
+    hipLaunchKernelGGL((qr_lds_kernel<T, ITM>), dim3(nz), dim3(QR_NT), bytes, s, (T*)X, size, roff, m, n, cstride,
+                       R, flag);
+    return hipGetLastError() == hipSuccess;
+  });
 }
 
+// Row blocking of the TSQR path for an m x n matrix too tall for qr_lds: the
+// fewest blocks whose leaf factorisation and apply fit QR_LDS_MAX, every block
+// at least n rows, and the stacked R factors of all blocks within one
+// workgroup's LDS; P = 0 when the path does not apply.
+struct TsqrPlan {
+  int P = 0, mb = 0;
+};
+
+static TsqrPlan tsqr_plan(int m, int n) {
+  TsqrPlan p;
+  if (qr_lds_bytes(m, n) <= QR_LDS_MAX) return p;
+  const size_t lim = QR_LDS_MAX / sizeof(double), nn = (size_t)n * n;
+  if (nn + n >= lim) return p;
+  const size_t mbmax = (lim - nn - n) / n;  // leaf: (mb n + n n + n) doubles; the apply stages mb n + n n
+  if (mbmax < (size_t)n) return p;
+  const int P = (int)(((size_t)m + mbmax - 1) / mbmax);
+  const int mb = (m + P - 1) / P;
+  if (P < 2 || m - (P - 1) * mb < n) return p;
+  if (qr_lds_bytes(P * n, n) > QR_LDS_MAX) return p;
+  p.P = P;
+  p.mb = mb;
+  return p;
+}
+
+// Uses W_z = work + z 2 m n: Q_b blocks (m n doubles) then S ((P n) n <= m n).
+template <typename T>
+static bool tsqr(void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride, double* work, double* R,
+                 int nz, int* flag, hipStream_t s) {
+  const TsqrPlan p = tsqr_plan(m, n);
+  if (p.P == 0) return false;
+  const bool leaf = with_itm(p.mb, [&](auto I) {
+    constexpr int ITM = decltype(I)::value;
+    static const bool enabled = lds_opt_in(reinterpret_cast<const void*>(&tsqr_leaf_kernel<T, ITM>));
+    if (!enabled) return false;
+    hipLaunchKernelGGL((tsqr_leaf_kernel<T, ITM>), dim3(p.P, nz), dim3(QR_NT), qr_lds_bytes(p.mb, n), s,
+                       (const T*)X, size, roff, m, n, cstride, p.mb, p.P, work);
+    return hipGetLastError() == hipSuccess;
+  });
+  if (!leaf) return false;
+  const bool root = with_itm(p.P * n, [&](auto I) {
+    constexpr int ITM = decltype(I)::value;
+    static const bool enabled = lds_opt_in(reinterpret_cast<const void*>(&tsqr_root_kernel<ITM>));
+    if (!enabled) return false;
+    hipLaunchKernelGGL((tsqr_root_kernel<ITM>), dim3(nz), dim3(QR_NT), qr_lds_bytes(p.P * n, n), s, m, n, p.P, work,
+                       R);
+    return hipGetLastError() == hipSuccess;
+  });
+  if (!root) return false;
+  static const bool apply_ok = lds_opt_in(reinterpret_cast<const void*>(&tsqr_apply_kernel<T>));
+  if (!apply_ok) return false;
+  const size_t abytes = ((size_t)p.mb * n + (size_t)n * n) * sizeof(double);
+  hipLaunchKernelGGL(tsqr_apply_kernel<T>, dim3(p.P, nz), dim3(QR_NT), abytes, s, (T*)X, size, roff, m, n, cstride,
+                     p.mb, p.P, (const double*)work, flag);
+  return hipGetLastError() == hipSuccess;
+}
+
+static bool qr_global_only() {
+  static const bool g = getenv("TTN_QR_GLOBAL") != nullptr;
+  return g;
+}
+
+const char* qr_path_name(int m, int n) {
+  if (qr_global_only()) return "qr_kernel";
+  if (qr_lds_bytes(m, n) <= QR_LDS_MAX) return "qr_lds_kernel";
+  if (tsqr_plan(m, n).P > 0) return "tsqr_kernels";
+  return "qr_kernel";
+}
+
+// The LDS-resident kernel when the matrix fits, else TSQR when its blocks do,
+// else the global-memory kernel; a path whose launch fails falls through to
+// the next.  The TSQR launches run only once the leaf launch succeeded, so a
+// partial TSQR never precedes the global kernel on the same data: the leaf
+// and root read the node and write only the workspace.
 hipError_t launch_qr(int ctype, void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride, double* work,
                      double* R, int nz, int* flag, hipStream_t s) {
-  static const bool global_only = getenv("TTN_QR_GLOBAL") != nullptr;
-  if (!global_only) {
+  if (!qr_global_only()) {
     if (ctype == 0 ? qr_lds<double>(X, size, roff, m, n, cstride, R, nz, flag, s)
                    : qr_lds<float>(X, size, roff, m, n, cstride, R, nz, flag, s))
+      return hipSuccess;
+    if (ctype == 0 ? tsqr<double>(X, size, roff, m, n, cstride, work, R, nz, flag, s)
+                   : tsqr<float>(X, size, roff, m, n, cstride, work, R, nz, flag, s))
       return hipSuccess;
   }
   if (ctype == 0) return qr_t<double>(X, size, roff, m, n, cstride, work, R, nz, flag, s);

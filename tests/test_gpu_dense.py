@@ -106,8 +106,8 @@ def test_rayleigh_ritz_not_pd_reports_error(api, ctx):
 @pytest.mark.parametrize("dt", [0, 1])
 def test_qr_move_matches_oracle(api, ctx, dt, D):
     """QR gauge moves against the oracle's; D=7 keeps every node's matrix in
-    LDS, D=40 also sends the large backbone nodes through the global-memory
-    kernel."""
+    LDS, D=40 also sends the 1600 x 40 backbone matrices through the TSQR
+    kernels."""
     m = wl.quartic_force_field(8, 21, 20, 30)
     tree = wl.fork_tree(m.dims, 4, 1)
     bonds = wl.bond_dims(tree, D)
@@ -172,6 +172,118 @@ def test_qr_move_edge_shapes(api, ctx, shape, dt):
         for j in range(k):
             ref = blk_np[j][u]
             assert np.linalg.norm(got[j] - ref) <= tol * max(1.0, np.linalg.norm(ref)), (shape, u, j)
+
+
+def _chain_moves(api, ctx, phys, D, dt, seed):
+    """A three-node chain 0 - 1 - 2 (root 0) with the given physical
+    dimensions and bond cap D; the centre moves along the Euler tour
+    0 -> 1 -> 2 -> 1 -> 0 on the GPU and in the oracle.  Returns the GPU and
+    oracle node tensors of every state and the QR paths the library recorded
+    ({'m x n': kernel name})."""
+    tree = wl.Tree("chain3", [-1, 0, 1], list(phys), [0, 1, 2])
+    bonds = wl.bond_dims(tree, D)
+    k = 2
+    blk_np = wl.random_block(tree, bonds, k, seed)
+    gt = api.Tree(tree.parent, tree.phys)
+    tdt = torch.float64 if dt == 0 else torch.float32
+    blk = api.Block(ctx, gt, k, [max(1, b) for b in bonds], dt)
+    for u in range(tree.n):
+        blk.t[u].copy_(to_dev(np.stack([blk_np[j][u] for j in range(k)]), tdt))
+    api.profile(ctx, True)
+    paths = {}
+    tour = [0, 1, 2, 1, 0]
+    for a, b in zip(tour[:-1], tour[1:]):
+        api.block_move_centre(ctx, blk, a, b)
+        for j in range(k):
+            ottn.move_centre(tree, blk_np[j], a, b)
+    ctx.sync()
+    for r in api.profile_report(ctx):
+        if r[0].startswith("qr:"):
+            paths[r[0][3:]] = r[2]
+    api.profile(ctx, False)
+    got = [blk.t[u].double().cpu().numpy() for u in range(tree.n)]
+    return tree, got, blk_np, paths
+
+
+@pytest.mark.parametrize("shape", ["1600x40", "1000x40", "1369x37"])
+@pytest.mark.parametrize("dt", [0, 1])
+def test_tsqr_moves_match_oracle(api, ctx, shape, dt):
+    """Node matrices too tall for one workgroup's LDS go through the TSQR
+    kernels (row blocks factored in LDS, their stacked R factors factored
+    again, the block Q factors multiplied out): 1600 x 40 (the 12-mode
+    workload's backbone nodes, four equal blocks), 1000 x 40 (three blocks,
+    the last one shorter) and 1369 x 37 (a bond that is not a multiple of the
+    eight output columns a thread of the last stage computes).  Against the
+    oracle's QR moves, with diag(R) >= 0 the factorisation is unique."""
+    phys = {"1600x40": (40, 40, 40), "1000x40": (40, 25, 40), "1369x37": (37, 37, 37)}[shape]
+    tree, got, ref, paths = _chain_moves(api, ctx, phys, 40, dt, 52)
+    assert paths.get(shape) == "tsqr_kernels", paths
+    tol = 1e-11 if dt == 0 else 2e-4
+    for u in range(tree.n):
+        for j in range(len(ref)):
+            r = ref[j][u]
+            assert np.linalg.norm(got[u][j] - r) <= tol * max(1.0, np.linalg.norm(r)), (shape, u, j)
+
+
+@pytest.mark.parametrize("dt", [0, 1])
+def test_tsqr_rank_deficient(api, ctx, dt):
+    """One move 1 -> 2 on the 40-40-40 chain whose node 1 matrix toward 2
+    (1600 x 40) has half its singular values zero, through the TSQR kernels:
+    node 1 stays an isometry on the columns that carry weight and the
+    two-site tensor of nodes 1 and 2 is unchanged."""
+    tree = wl.Tree("chain3", [-1, 0, 1], [40, 40, 40], [0, 1, 2])
+    bonds = wl.bond_dims(tree, 40)
+    k = 2
+    blk_np = wl.random_block(tree, bonds, k, 53)
+    rng = np.random.default_rng(9)
+    l1, l2 = ottn.leg_of(tree, 1, 2), ottn.leg_of(tree, 2, 1)
+    for j in range(k):
+        T = np.moveaxis(blk_np[j][1], l1, -1)
+        sh = T.shape
+        rows, De = int(np.prod(sh[:-1])), sh[-1]
+        U, _ = np.linalg.qr(rng.normal(size=(rows, De)))
+        V, _ = np.linalg.qr(rng.normal(size=(De, De)))
+        sv = np.linspace(1.0, 0.5, De)
+        sv[De // 2:] = 0.0
+        blk_np[j][1] = np.moveaxis(((U * sv) @ V.T).reshape(sh), -1, l1)
+    gt = api.Tree(tree.parent, tree.phys)
+    tdt = torch.float64 if dt == 0 else torch.float32
+    blk = api.Block(ctx, gt, k, [max(1, b) for b in bonds], dt)
+    for u in range(tree.n):
+        blk.t[u].copy_(to_dev(np.stack([blk_np[j][u] for j in range(k)]), tdt))
+    before = [np.tensordot(blk.t[1][j].double().cpu().numpy(), blk.t[2][j].double().cpu().numpy(),
+                           axes=([l1], [l2])) for j in range(k)]
+    api.profile(ctx, True)
+    api.block_move_centre(ctx, blk, 1, 2)
+    ctx.sync()
+    paths = {r[0][3:]: r[2] for r in api.profile_report(ctx) if r[0].startswith("qr:")}
+    api.profile(ctx, False)
+    assert paths.get(f"{rows}x{De}") == "tsqr_kernels", paths
+    g1 = blk.t[1].double().cpu().numpy()
+    g2 = blk.t[2].double().cpu().numpy()
+    eps = 1e-13 if dt == 0 else 3e-6
+    for j in range(k):
+        Q = np.moveaxis(g1[j], l1, -1).reshape(-1, De)
+        G = Q.T @ Q
+        nz = np.abs(np.diag(G)) > 0.5
+        assert nz.sum() >= De // 2
+        assert np.abs(G[np.ix_(nz, nz)] - np.eye(int(nz.sum()))).max() < 50 * eps, j
+        after = np.tensordot(g1[j], g2[j], axes=([l1], [l2]))
+        assert np.linalg.norm(after - before[j]) <= 50 * eps * np.linalg.norm(before[j]), j
+
+
+@pytest.mark.parametrize("dt", [0, 1])
+def test_qr_global_kernel_shape(api, ctx, dt):
+    """A 200 x 98 node matrix (chain 98-2-100): too large for LDS and with a
+    bond too wide for TSQR row blocks of at least 98 rows, so the
+    global-memory kernel runs; against the oracle's QR moves."""
+    tree, got, ref, paths = _chain_moves(api, ctx, (98, 2, 100), 100, dt, 54)
+    assert paths.get("200x98") == "qr_kernel", paths
+    tol = 1e-11 if dt == 0 else 2e-4
+    for u in range(tree.n):
+        for j in range(len(ref)):
+            r = ref[j][u]
+            assert np.linalg.norm(got[u][j] - r) <= tol * max(1.0, np.linalg.norm(r)), (u, j)
 
 
 @pytest.mark.parametrize("kind", ["cond1e3", "cond1e10", "rank_deficient"])
