@@ -1318,6 +1318,16 @@ def run_bench(args, api, k, D, stream):
         print(f"  step kernel {kern}: {d['launches']} launches {d['ms']:.1f} ms "
               f"{d['flops'] / (d['ms'] * 1e-3) / 1e12:.1f} TFLOP/s {d['bytes'] / (d['ms'] * 1e-3) / 1e9:.0f} GB/s",
               file=sys.stderr)
+    qr_shapes = {}  # QR gauge moves by node matrix shape: launches, ms
+    for key, st, kern, cnt, tms, *_r in rep:
+        if key.startswith("qr:"):
+            a = qr_shapes.setdefault(key[3:], [0, 0.0])
+            a[0] += cnt
+            a[1] += tms
+    if qr_shapes:
+        print("  QR moves by shape: " + ", ".join(f"{k} {v[0]} x {v[1] / v[0] * 1e3:.1f} us"
+                                                  for k, v in sorted(qr_shapes.items(), key=lambda kv: -kv[1][1])),
+              file=sys.stderr)
     heff_fl = heff_ms = 0.0
     by_depth = {}  # H_eff applies with the TTNO, by the node's distance from the root
     deep = {}  # their stage kernels at depth >= 3: (depth, kernel, (M, N, K, items)) -> ms, launches
@@ -1384,6 +1394,7 @@ def run_bench(args, api, k, D, stream):
                          if heff_ms else None,
                          "heff_by_depth": heff_levels,
                          "dispatches": int(sum(v["launches"] for v in by_kernel.values())),
+                         "qr_ms": round(sum(v[1] for v in qr_shapes.values()), 2),
                          "contraction_ms": round(tot_ms, 1)},
     }
     if not args.no_tts:

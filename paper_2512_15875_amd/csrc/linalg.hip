@@ -846,6 +846,161 @@ __global__ __launch_bounds__(QR_NT) void qr_lds_kernel(T* X, int64_t size, const
   }
 }
 
+// Register-resident form of the same Householder QR for m <= 64 ITM rows and
+// n <= 16 CPW columns: wave w keeps columns w, w + 16, .. in registers (lane l
+// holds rows l + 64 it), and only the reflectors go through LDS (v_k over
+// rows > k, v_k[k] = 1 implied; tau_k; alpha_k = R[k][k] before the sign
+// fix).  Factorisation step k: every wave reads v_k once and applies it to its
+// columns j > k; the owner of column k+1 updates that column first and builds
+// v_{k+1} from it at once, so a step costs one barrier and moves one column's
+// worth of LDS reads per wave instead of every column's reads and writes.  Q
+// by backward accumulation needs no barrier at all: column j of Q is
+// H_0 .. H_{j-1} (e_j - tau_j v_j), and every reflector is in LDS by then, so
+// each wave forms its own columns.
+template <typename T, int ITM, int CPW>
+__global__ __launch_bounds__(QR_NT) void qr_reg_kernel(T* X, int64_t size, const int32_t* roff, int m, int n,
+                                                     int64_t cstride, double* Rout, int* flag) {
+  extern __shared__ double sm[];
+  double* V = sm;                   // V[k m + r]
+  double* tau = V + (size_t)m * n;  // n
+  double* rd = tau + n;             // n
+  const int z = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  T* Xz = X + (int64_t)z * size;
+  double col[CPW][ITM];
+  int64_t ro[ITM];
+#pragma unroll
+  for (int it = 0; it < ITM; ++it) ro[it] = roff[min(lane + 64 * it, m - 1)];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int64_t jo = (int64_t)min(wv + QR_NW * c, n - 1) * cstride;
+#pragma unroll
+    for (int it = 0; it < ITM; ++it) col[c][it] = (double)Xz[ro[it] + jo];
+  }
+#pragma unroll
+  for (int it = 0; it < ITM; ++it)
+    if (lane + 64 * it >= m) {
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) col[c][it] = 0.0;
+    }
+  // reflector k from the owner's column x (rows >= k): v = x / v0 below row k,
+  // tau' = 2 v0^2 / |x - alpha e_k|^2, as in the LDS kernel
+  auto build = [&](const double (&x)[ITM], int k) {
+    double ss = 0.0, xk = 0.0;
+#pragma unroll
+    for (int it = 0; it < ITM; ++it) {
+      const int r = lane + 64 * it;
+      if (r >= k) ss += x[it] * x[it];
+      if (it == (k >> 6)) xk = x[it];
+    }
+    ss = wave_sum_dpp(ss);
+    const double x0 = lane_value(xk, k & 63), nrm = sqrt(ss);
+    const double alpha = nrm == 0.0 ? 0.0 : (x0 >= 0 ? -nrm : nrm);
+    const double v0 = x0 - alpha;
+    const double vn2 = ss - x0 * x0 + v0 * v0;
+    const double inv = v0 != 0.0 ? 1.0 / v0 : 0.0;
+#pragma unroll
+    for (int it = 0; it < ITM; ++it) {
+      const int r = lane + 64 * it;
+      if (r > k && r < m) V[(size_t)k * m + r] = x[it] * inv;
+    }
+    if (lane == 0) {
+      tau[k] = (vn2 > 0 && v0 != 0.0) ? 2.0 * v0 * v0 / vn2 : 0.0;
+      rd[k] = alpha;
+    }
+  };
+  // v_k over this lane's rows (zero above row k)
+  auto load_v = [&](double (&v)[ITM], int k) {
+#pragma unroll
+    for (int it = 0; it < ITM; ++it) {
+      const int r = lane + 64 * it;
+      v[it] = (r > k && r < m) ? V[(size_t)k * m + r] : (r == k ? 1.0 : 0.0);
+    }
+  };
+  auto apply = [&](double (&y)[ITM], const double (&v)[ITM], double tk) {
+    double d = 0.0;
+#pragma unroll
+    for (int it = 0; it < ITM; ++it) d += v[it] * y[it];
+    d = tk * wave_sum_dpp(d);
+#pragma unroll
+    for (int it = 0; it < ITM; ++it) y[it] -= d * v[it];
+  };
+  if (wv == 0) build(col[0], 0);
+  __syncthreads();
+  for (int k = 0; k + 1 < n; ++k) {
+    if (wv + QR_NW * (CPW - 1) > k) {  // some column of this wave is past k
+      double v[ITM];
+      load_v(v, k);
+      const double tk = tau[k];
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int j = wv + QR_NW * c;
+        if (j > k && j < n) {
+          apply(col[c], v, tk);
+          if (j == k + 1) build(col[c], k + 1);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // R (sign-fixed rows) from the owners' registers: rows above the diagonal
+  // are final since their reflectors were applied
+  double* R = Rout + (size_t)z * n * n;
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int j = wv + QR_NW * c;
+    if (j < n) {
+#pragma unroll
+      for (int it = 0; it < ITM; ++it) {
+        const int r = lane + 64 * it;
+        if (r < n) {
+          const double val = r < j ? col[c][it] : (r == j ? rd[j] : 0.0);
+          R[(size_t)r * n + j] = rd[r] < 0 ? -val : val;
+        }
+      }
+    }
+  }
+  // Q: every owned column finished as e_j - tau_j v_j, then H_i for i < j
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int j = wv + QR_NW * c;
+    if (j < n) {
+      const double tj = tau[j];
+#pragma unroll
+      for (int it = 0; it < ITM; ++it) {
+        const int r = lane + 64 * it;
+        col[c][it] = (r > j && r < m) ? -tj * V[(size_t)j * m + r] : (r == j ? 1.0 - tj : 0.0);
+      }
+    }
+  }
+  for (int i = n - 2; i >= 0; --i) {
+    if (wv + QR_NW * (CPW - 1) <= i) continue;
+    double v[ITM];
+    load_v(v, i);
+    const double ti = tau[i];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int j = wv + QR_NW * c;
+      if (j > i && j < n) apply(col[c], v, ti);
+    }
+  }
+  // Q (sign-fixed columns) back to the node tensor
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int j = wv + QR_NW * c;
+    if (j < n) {
+      const double sg = rd[j] < 0 ? -1.0 : 1.0;
+#pragma unroll
+      for (int it = 0; it < ITM; ++it) {
+        if (lane + 64 * it < m) {
+          const double q = sg * col[c][it];
+          if (!isfinite(q)) atomicOr(flag, 1);
+          Xz[ro[it] + (int64_t)j * cstride] = (T)q;
+        }
+      }
+    }
+  }
+}
+
 // Tall-skinny QR (TSQR) for node matrices whose m x n doubles do not fit one
 // workgroup's LDS: the rows are cut into P blocks of mb rows (the last block
 // shorter, none below n rows).  Per state z the workspace W_z (2 m n doubles)
@@ -1026,6 +1181,12 @@ static bool with_itm(int rows, F&& f) {
   return f(std::integral_constant<int, 0>{});
 }
 
+// TTN_QR_NOREG=1 keeps every resident matrix on the LDS kernel (for comparison)
+static bool qr_reg_on() {
+  static const bool on = getenv("TTN_QR_NOREG") == nullptr;
+  return on;
+}
+
 // one-time opt-in of a kernel to QR_LDS_MAX bytes of dynamic LDS
 static bool lds_opt_in(const void* fn) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)QR_LDS_MAX) == hipSuccess;
@@ -1033,11 +1194,46 @@ static bool lds_opt_in(const void* fn) {
 
 static size_t qr_lds_bytes(int m, int n) { return ((size_t)m * n + (size_t)n * n + (size_t)n) * sizeof(double); }
 
+// the register-resident kernel for m <= 64 ITM (ITM <= 9) and n <= 16 CPW (CPW <= 3)
+template <typename T, int ITM>
+static bool qr_reg_it(void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride, double* R, int nz,
+                      int* flag, hipStream_t s) {
+  const size_t bytes = ((size_t)m * n + 2 * (size_t)n) * sizeof(double);
+  auto go = [&](auto C) {
+    constexpr int CPW = decltype(C)::value;
+    static const bool enabled = lds_opt_in(reinterpret_cast<const void*>(&qr_reg_kernel<T, ITM, CPW>));
+    if (!enabled) return false;
+    hipLaunchKernelGGL((qr_reg_kernel<T, ITM, CPW>), dim3(nz), dim3(QR_NT), bytes, s, (T*)X, size, roff, m, n,
+                       cstride, R, flag);
+    return hipGetLastError() == hipSuccess;
+  };
+  if (n <= 16) return go(std::integral_constant<int, 1>{});
+  if (n <= 32) return go(std::integral_constant<int, 2>{});
+  return go(std::integral_constant<int, 3>{});
+}
+
+static bool qr_reg_fits(int m, int n) { return m <= 64 * 9 && n <= 48 && qr_lds_bytes(m, n) <= QR_LDS_MAX; }
+
+template <typename T>
+static bool qr_reg(void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride, double* R, int nz,
+                   int* flag, hipStream_t s) {
+  if (!qr_reg_fits(m, n)) return false;
+  return with_itm(m, [&](auto I) {
+    constexpr int ITM = decltype(I)::value;
+    if constexpr (ITM == 0 || ITM > 9) {
+      return false;
+    } else {
+      return qr_reg_it<T, ITM>(X, size, roff, m, n, cstride, R, nz, flag, s);
+    }
+  });
+}
+
 template <typename T>
 static bool qr_lds(void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride, double* R, int nz,
                    int* flag, hipStream_t s) {
   const size_t bytes = qr_lds_bytes(m, n);
   if (bytes > QR_LDS_MAX) return false;
+  if (qr_reg_on() && qr_reg<T>(X, size, roff, m, n, cstride, R, nz, flag, s)) return true;
   return with_itm(m, [&](auto I) {
     constexpr int ITM = decltype(I)::value;
     static const bool enabled = lds_opt_in(reinterpret_cast<const void*>(&qr_lds_kernel<T, ITM>));
@@ -1111,7 +1307,7 @@ static bool qr_global_only() {
 
 const char* qr_path_name(int m, int n) {
   if (qr_global_only()) return "qr_kernel";
-  if (qr_lds_bytes(m, n) <= QR_LDS_MAX) return "qr_lds_kernel";
+  if (qr_lds_bytes(m, n) <= QR_LDS_MAX) return qr_reg_on() && qr_reg_fits(m, n) ? "qr_reg_kernel" : "qr_lds_kernel";
   if (tsqr_plan(m, n).P > 0) return "tsqr_kernels";
   return "qr_kernel";
 }

@@ -225,6 +225,27 @@ def test_tsqr_moves_match_oracle(api, ctx, shape, dt):
             assert np.linalg.norm(got[u][j] - r) <= tol * max(1.0, np.linalg.norm(r)), (shape, u, j)
 
 
+@pytest.mark.parametrize("phys,D,mat,kernel", [
+    ((24, 24, 24), 24, "576x24", "qr_reg_kernel"),   # the c2 interior shape: 9 rows per lane, 2 columns per wave
+    ((40, 10, 40), 40, "400x40", "qr_reg_kernel"),   # 7 rows per lane (the 9-row instance), 3 columns per wave
+    ((8, 8, 8), 8, "64x8", "qr_reg_kernel"),         # one row per lane, waves 8.. without a column
+    ((60, 3, 60), 60, "180x60", "qr_lds_kernel"),    # bond above 48: the LDS-resident kernel
+])
+@pytest.mark.parametrize("dt", [0, 1])
+def test_qr_kernels_by_shape(api, ctx, phys, D, mat, kernel, dt):
+    """Each resident-matrix QR kernel on the shape that selects it (the
+    register-resident one for up to 576 rows and 48 columns, the LDS-resident
+    one beyond), along a whole Euler tour of a three-node chain, against the
+    oracle's QR moves."""
+    tree, got, ref, paths = _chain_moves(api, ctx, phys, D, dt, 55)
+    assert paths.get(mat) == kernel, paths
+    tol = 1e-11 if dt == 0 else 2e-4
+    for u in range(tree.n):
+        for j in range(len(ref)):
+            r = ref[j][u]
+            assert np.linalg.norm(got[u][j] - r) <= tol * max(1.0, np.linalg.norm(r)), (mat, u, j)
+
+
 @pytest.mark.parametrize("dt", [0, 1])
 def test_tsqr_rank_deficient(api, ctx, dt):
     """One move 1 -> 2 on the 40-40-40 chain whose node 1 matrix toward 2
