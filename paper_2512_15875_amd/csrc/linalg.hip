@@ -1126,32 +1126,46 @@ __global__ void absorb_kernel(const T* X, int64_t size, const int32_t* roff, int
   Y[(int64_t)z * size + roff[r] + (int64_t)i * cstride] = (T)s;
 }
 
-// Row-wise absorption for bonds n <= NMAX: the state's R is staged in LDS,
-// each thread owns one row r (all n outputs from one read of the row's n
-// inputs); a grid of (row blocks, states).
-template <typename T, int NMAX>
+// Row-wise absorption for bonds n <= 48: a workgroup takes 64 whole rows of
+// one state; lane l of wave w holds row r0 + l and columns w, w + 4, .., so
+// that a wave's loads run along consecutive rows.  The rows are staged in LDS
+// (column-major), and after the barrier each thread computes its outputs
+// Y[r][i] = sum_j R[i][j] X[r][j] (sum over j in order, as in the element-wise
+// kernel) and writes them over its elements: every element of a row is read
+// before any of them is written, so the kernel may work in place (Y == X).
+// All loads of a thread are issued unconditionally (indices clamped) so they
+// overlap.
+#define ABS_NMAX 48
+#define ABS_RB 64
+template <typename T>
 __global__ __launch_bounds__(256) void absorb_rows_kernel(const T* X, int64_t size, const int32_t* roff, int m, int n,
                                                           int64_t cstride, const double* R, T* Y) {
-  __shared__ double sR[NMAX * NMAX];
-  const int z = blockIdx.y, t = threadIdx.x;
+  __shared__ double sR[ABS_NMAX * ABS_NMAX];
+  __shared__ double sx[ABS_NMAX * ABS_RB];  // sx[j * 64 + row]
+  constexpr int QM = ABS_NMAX / 4;
+  const int z = blockIdx.y, t = threadIdx.x, lr = t & 63, w = t >> 6;
+  const int r = blockIdx.x * ABS_RB + lr;
+  const bool act = r < m;
   const double* Rz = R + (size_t)z * n * n;
-  for (int i = t; i < n * n; i += 256) sR[i] = Rz[i];
+  for (int e = t; e < n * n; e += 256) sR[e] = Rz[e];
+  const int64_t base = (int64_t)z * size + (int64_t)roff[act ? r : m - 1];
+  T v[QM];
+#pragma unroll
+  for (int q = 0; q < QM; ++q) v[q] = X[base + (int64_t)min(w + 4 * q, n - 1) * cstride];
+#pragma unroll
+  for (int q = 0; q < QM; ++q)
+    if (w + 4 * q < n) sx[(w + 4 * q) * ABS_RB + lr] = (double)v[q];
   __syncthreads();
-  const int r = blockIdx.x * 256 + t;
-  if (r >= m) return;
-  const T* Xz = X + (int64_t)z * size;
-  T* Yz = Y + (int64_t)z * size;
-  const int64_t ro = roff[r];
-  double xr[NMAX];
+  if (!act) return;
 #pragma unroll
-  for (int j = 0; j < NMAX; ++j) xr[j] = j < n ? (double)Xz[ro + (int64_t)j * cstride] : 0.0;
-#pragma unroll
-  for (int i = 0; i < NMAX; ++i) {
-    if (i >= n) break;
-    double sacc = 0;
-#pragma unroll
-    for (int j = 0; j < NMAX; ++j) sacc += sR[i * n + (j < n ? j : 0)] * xr[j];
-    Yz[ro + (int64_t)i * cstride] = (T)sacc;
+  for (int q = 0; q < QM; ++q) {
+    const int i = w + 4 * q;
+    if (i < n) {
+      const double* rr = sR + i * n;
+      double sacc = 0;
+      for (int j = 0; j < n; ++j) sacc += rr[j] * sx[j * ABS_RB + lr];
+      Y[base + (int64_t)i * cstride] = (T)sacc;
+    }
   }
 }
 
@@ -1331,16 +1345,15 @@ hipError_t launch_qr(int ctype, void* X, int64_t size, const int32_t* roff, int 
   return qr_t<float>(X, size, roff, m, n, cstride, work, R, nz, flag, s);
 }
 
-template <int NMAX>
 static hipError_t absorb_rows(int ctype, const void* X, int64_t size, const int32_t* roff, int m, int n,
                               int64_t cstride, const double* R, void* Y, int nz, hipStream_t s) {
-  const dim3 grid((unsigned)((m + 255) / 256), (unsigned)nz);
+  const dim3 grid((unsigned)((m + ABS_RB - 1) / ABS_RB), (unsigned)nz);
   if (ctype == 0)
-    hipLaunchKernelGGL((absorb_rows_kernel<double, NMAX>), grid, dim3(256), 0, s, (const double*)X, size, roff, m, n,
+    hipLaunchKernelGGL(absorb_rows_kernel<double>, grid, dim3(256), 0, s, (const double*)X, size, roff, m, n,
                        cstride, R, (double*)Y);
   else
-    hipLaunchKernelGGL((absorb_rows_kernel<float, NMAX>), grid, dim3(256), 0, s, (const float*)X, size, roff, m, n,
-                       cstride, R, (float*)Y);
+    hipLaunchKernelGGL(absorb_rows_kernel<float>, grid, dim3(256), 0, s, (const float*)X, size, roff, m, n, cstride,
+                       R, (float*)Y);
   return hipGetLastError();
 }
 
@@ -1348,18 +1361,14 @@ static hipError_t absorb_rows(int ctype, const void* X, int64_t size, const int3
 // disjoint, so it may write over its input (Y == X): no copy back.
 bool absorb_in_place(int m, int n) {
   (void)m;
-  return n <= 48;
+  return n <= ABS_NMAX;
 }
 
 hipError_t launch_absorb(int ctype, const void* X, int64_t size, const int32_t* roff, int m, int n, int64_t cstride,
                          const double* R, void* Y, int nz, hipStream_t s) {
-  // row-wise kernel (measured: 576 x 24 28 -> 20 us per 50 states), in place
-  // for every bond it covers; the element-wise kernel for larger bonds
-  if (n <= 8) return absorb_rows<8>(ctype, X, size, roff, m, n, cstride, R, Y, nz, s);
-  if (n <= 16) return absorb_rows<16>(ctype, X, size, roff, m, n, cstride, R, Y, nz, s);
-  if (n <= 24) return absorb_rows<24>(ctype, X, size, roff, m, n, cstride, R, Y, nz, s);
-  if (n <= 32) return absorb_rows<32>(ctype, X, size, roff, m, n, cstride, R, Y, nz, s);
-  if (n <= 48) return absorb_rows<48>(ctype, X, size, roff, m, n, cstride, R, Y, nz, s);
+  // row-wise kernel, in place, for every bond it covers; the element-wise
+  // kernel for larger bonds
+  if (n <= ABS_NMAX) return absorb_rows(ctype, X, size, roff, m, n, cstride, R, Y, nz, s);
   const int64_t tot = (int64_t)m * n * nz;
   const unsigned g = (unsigned)((tot + 255) / 256);
   if (ctype == 0)

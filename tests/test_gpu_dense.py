@@ -178,8 +178,8 @@ def _chain_moves(api, ctx, phys, D, dt, seed):
     """A three-node chain 0 - 1 - 2 (root 0) with the given physical
     dimensions and bond cap D; the centre moves along the Euler tour
     0 -> 1 -> 2 -> 1 -> 0 on the GPU and in the oracle.  Returns the GPU and
-    oracle node tensors of every state and the QR paths the library recorded
-    ({'m x n': kernel name})."""
+    oracle node tensors of every state and the kernels the library recorded
+    for the QR and absorption steps ({'qr:m x n' or 'absorb:m x n': name})."""
     tree = wl.Tree("chain3", [-1, 0, 1], list(phys), [0, 1, 2])
     bonds = wl.bond_dims(tree, D)
     k = 2
@@ -198,8 +198,8 @@ def _chain_moves(api, ctx, phys, D, dt, seed):
             ottn.move_centre(tree, blk_np[j], a, b)
     ctx.sync()
     for r in api.profile_report(ctx):
-        if r[0].startswith("qr:"):
-            paths[r[0][3:]] = r[2]
+        if r[0].startswith("qr:") or r[0].startswith("absorb:"):
+            paths[r[0]] = r[2]
     api.profile(ctx, False)
     got = [blk.t[u].double().cpu().numpy() for u in range(tree.n)]
     return tree, got, blk_np, paths
@@ -217,7 +217,7 @@ def test_tsqr_moves_match_oracle(api, ctx, shape, dt):
     oracle's QR moves, with diag(R) >= 0 the factorisation is unique."""
     phys = {"1600x40": (40, 40, 40), "1000x40": (40, 25, 40), "1369x37": (37, 37, 37)}[shape]
     tree, got, ref, paths = _chain_moves(api, ctx, phys, 40, dt, 52)
-    assert paths.get(shape) == "tsqr_kernels", paths
+    assert paths.get("qr:" + shape) == "tsqr_kernels", paths
     tol = 1e-11 if dt == 0 else 2e-4
     for u in range(tree.n):
         for j in range(len(ref)):
@@ -238,7 +238,7 @@ def test_qr_kernels_by_shape(api, ctx, phys, D, mat, kernel, dt):
     one beyond), along a whole Euler tour of a three-node chain, against the
     oracle's QR moves."""
     tree, got, ref, paths = _chain_moves(api, ctx, phys, D, dt, 55)
-    assert paths.get(mat) == kernel, paths
+    assert paths.get("qr:" + mat) == kernel, paths
     tol = 1e-11 if dt == 0 else 2e-4
     for u in range(tree.n):
         for j in range(len(ref)):
@@ -299,7 +299,7 @@ def test_qr_global_kernel_shape(api, ctx, dt):
     bond too wide for TSQR row blocks of at least 98 rows, so the
     global-memory kernel runs; against the oracle's QR moves."""
     tree, got, ref, paths = _chain_moves(api, ctx, (98, 2, 100), 100, dt, 54)
-    assert paths.get("200x98") == "qr_kernel", paths
+    assert paths.get("qr:200x98") == "qr_kernel", paths
     tol = 1e-11 if dt == 0 else 2e-4
     for u in range(tree.n):
         for j in range(len(ref)):
