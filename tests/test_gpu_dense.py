@@ -229,6 +229,8 @@ def test_tsqr_moves_match_oracle(api, ctx, shape, dt):
     ((24, 24, 24), 24, "576x24", "qr_reg_kernel"),   # the c2 interior shape: 9 rows per lane, 2 columns per wave
     ((40, 10, 40), 40, "400x40", "qr_reg_kernel"),   # 7 rows per lane (the 9-row instance), 3 columns per wave
     ((8, 8, 8), 8, "64x8", "qr_reg_kernel"),         # one row per lane, waves 8.. without a column
+    ((48, 6, 48), 48, "288x48", "qr_reg_kernel"),    # 48 columns: every wave holds three
+    ((17, 4, 17), 17, "68x17", "qr_reg_kernel"),     # 17 columns: wave 0 alone holds two; a ragged second row pass
     ((60, 3, 60), 60, "180x60", "qr_lds_kernel"),    # bond above 48: the LDS-resident kernel
 ])
 @pytest.mark.parametrize("dt", [0, 1])
