@@ -943,6 +943,24 @@ ttn_status heff_apply_block(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op,
 }  // extern "C"
 
 namespace ttn {
+bool leaf_heff_fusable(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_envs* envs, int u, int ct,
+                       LeafHeffArgs& la) {
+  if (!op || t->nb[u].size() != 1 || t->phys[u] <= 1 || !(ct == 0 || ct == 1) || !ctx->leg_tabs.empty()) return false;
+  const char* fe = getenv("TTN_FUSED_LEAF");
+  if (fe && fe[0] == '0') return false;
+  const int c = t->nb[u][0];
+  la.Db = envs->eb(c, u);
+  la.M = envs->em(c, u);
+  la.Da = envs->ea(c, u);
+  la.d = t->phys[u];
+  if (la.M != op->bond(u, c) || leaf_heff_lds_bytes(la.Db, la.M, la.Da, la.d, ct == 0 ? 8 : 4) > LEAF_HEFF_LDS_MAX)
+    return false;
+  la.E = envs->slot[ttn_envs::dslot(t, c, u)];
+  la.e_stride = envs->slot_elems(c, u);
+  la.W = op->W[u];
+  return true;
+}
+
 ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_envs* envs, int32_t node,
                            int32_t k, const int32_t* pair_ids, const int32_t* x_ids, const int32_t* y_ids,
                            int32_t y_rows, const double* shift, const double* alpha, const void* X, int32_t x_rows,
@@ -1110,29 +1128,15 @@ ttn_status heff_apply_rows(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, 
   {
     // operator product at a node with one virtual leg and a physical leg,
     // FP64 or FP32 arithmetic on its own storage: the fused kernel
-    const int c = t->nb[u][0];
-    bool fuse = op && kap == 1 && t->phys[u] > 1 && (ct == 0 || ct == 1) && ctx->leg_tabs.empty();
-    const char* fe = getenv("TTN_FUSED_LEAF");
-    if (fe && fe[0] == '0') fuse = false;
     LeafHeffArgs la;
-    if (fuse) {
-      la.Db = envs->eb(c, u);
-      la.M = envs->em(c, u);
-      la.Da = envs->ea(c, u);
-      la.d = t->phys[u];
-      fuse = la.M == op->bond(u, c) &&
-             leaf_heff_lds_bytes(la.Db, la.M, la.Da, la.d, ct == 0 ? 8 : 4) <= LEAF_HEFF_LDS_MAX;
-    }
+    const bool fuse = kap == 1 && leaf_heff_fusable(ctx, t, op, envs, u, ct, la);
     if (fuse) {
       la.X = X;
       la.x_stride = n_in;
       la.x_ids = x_ids;
       la.x_rows = x_ids ? x_rows : k;
-      la.E = envs->slot[ttn_envs::dslot(t, c, u)];
-      la.e_stride = envs->slot_elems(c, u);
       la.pair_ids = pair_ids;
       la.n_slots = pair_ids ? envs->n_slots : k;
-      la.W = op->W[u];
       la.Y = Y;
       la.y_stride = n_loc;
       la.y_ids = y_ids;

@@ -147,6 +147,18 @@ struct LeafHeffArgs {
   const int32_t* gate = nullptr;  // non-null: return at once when it reads zero
 };
 #define LEAF_HEFF_LDS_MAX (64 * 1024)
+// Whether the fused leaf kernel serves H_eff at node u (one virtual leg, a
+// physical leg, FP64 or FP32 arithmetic on its own storage); fills Db, M, Da,
+// d, E, e_stride and W of `la` when it does.
+bool leaf_heff_fusable(ttn_ctx* ctx, const ttn_tree* t, const ttn_ttno* op, const ttn_envs* envs, int u, int ct,
+                       LeafHeffArgs& la);
+struct MinresState;
+// The whole MINRES local solve of a leaf in one launch (one workgroup per
+// state): y holds the warm start on entry and the solution on return, b the
+// right-hand side, both [k][n] with n = Da d <= 256; la as for
+// launch_leaf_heff with X = Y = y.
+hipError_t launch_leaf_minres(int ctype, const LeafHeffArgs& la, const void* b, void* y, int64_t n, double rtol,
+                              int maxiter, MinresState* st, hipStream_t s);
 size_t leaf_heff_lds_bytes(int Db, int M, int Da, int d, int esize);
 // ctype 0: FP64 storage and arithmetic; 1: FP32
 hipError_t launch_leaf_heff(int ctype, const LeafHeffArgs& a, hipStream_t s);

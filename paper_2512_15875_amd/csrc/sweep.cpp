@@ -673,7 +673,33 @@ ttn_status sweep_step(ttn_ctx* ctx, ttn_sweep* sw, int32_t node, int32_t next, c
         }
         return TTN_OK;
       };
-      if (opts->refine == 0 && opts->warm == TTN_WARM_NONE) {
+      static const bool leaf_fused = !(getenv("TTN_LEAF_MINRES") && getenv("TTN_LEAF_MINRES")[0] == '0');
+      const bool same_prec = (sw->compute == TTN_F64 && ct == 0) || (sw->compute == TTN_F32 && ct == 1);
+      LeafHeffArgs la;
+      if (leaf_fused && pc == TTN_PRECOND_NONE && opts->refine == 0 && opts->warm == TTN_WARM_NONE && same_prec &&
+          n <= 256 && leaf_heff_fusable(ctx, t, sw->op, sw->henv, u, ct, la) && la.Da == la.Db &&
+          (int64_t)la.Da * la.d == n && k <= sw->henv->n_slots) {
+        // a leaf: warm-start product, initialisation and every iteration in
+        // one launch (the H_eff products are recorded under the node's key)
+        la.X = y_u;
+        la.x_stride = n;
+        la.x_rows = k;
+        la.n_slots = k;
+        la.Y = y_u;
+        la.y_stride = n;
+        la.y_rows = k;
+        la.shift = sw->shift;
+        la.n = k;
+        la.flag = ctx->d_flag;
+        const double Db = la.Db, Mw = la.M, Da = la.Da, d = la.d;
+        const double per = 2.0 * (Db * Mw * Da * d + Db * d * Mw * d) * k * (opts->maxiter + 1.0);
+        ctx->flops_done += per;
+        const std::string key = "heff:" + std::to_string(u) + ":1:leafminres";
+        ttn_prof_rec* pr = prof_begin(ctx, key.c_str(), "leaf_minres_kernel", per,
+                                      (double)es * (k * (3.0 * n + Db * Mw * Da) + Mw * d * d), k);
+        HIPCHK(ctx, launch_leaf_minres(ct, la, b, y_u, n, opts->rtol, opts->maxiter, sw->st, ctx->stream));
+        prof_end(ctx, pr);
+      } else if (opts->refine == 0 && opts->warm == TTN_WARM_NONE) {
         // p = (H_eff - s) y_u  (warm start)
         r = heff_apply_block(ctx, t, sw->op, sw->henv, u, k, nullptr, nullptr, sw->shift, nullptr, y_u, k, p,
                              TTN_HEFF_APPLY, sw->compute);

@@ -57,13 +57,20 @@ def test_als_sweep_matches_oracle(api, ctx, tree_kind):
     sw = api.Sweep(ctx, gt, op, Y, [(None, P, list(range(k)), list(range(k)), None)], shift=sh, compute=api.F64)
     sw.init(tree.root)
     iters = torch.zeros(k, dtype=torch.int32, device="cuda")
+    api.profile(ctx, True)
     api.run_sweep(sw, gt, api.SOLVE_MINRES, maxiter=6, rtol=0.0, iters=iters)
     ctx.sync()
+    kernels = {r[0]: r[2] for r in api.profile_report(ctx)}
+    api.profile(ctx, False)
     for j in range(k):
         ref = osol.als_solve(tree, W, shifts[j], phi[j], phi[j], sweeps=1, maxiter=6, rtol=0.0)
         for u in range(tree.n):
             assert rel_err(Y.t[u][j].cpu().numpy(), ref[u]) < 1e-8, (j, u)
     assert int(iters.max()) == 6
+    # the leaves' local solves ran as one launch each (warm start, initialisation, six iterations)
+    leaves = [u for u in range(tree.n) if len(tree.neighbours(u)) == 1 and tree.phys[u] > 1]
+    for u in leaves:
+        assert kernels.get(f"heff:{u}:1:leafminres") == "leaf_minres_kernel", (u, sorted(kernels))
 
 
 def test_als_sweep_fp64_storage_fp32_arithmetic(api, ctx):
