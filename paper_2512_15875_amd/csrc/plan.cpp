@@ -103,6 +103,14 @@ int pick_tile(int M, int N, int K, double nblocks_other, bool tn) {
   // only used when requested.
   static const int wave_on = getenv("TTN_WAVE_KERNEL") ? 1 : 0;
   if (wave_on && nblocks_other >= 256 && (double)M * N <= 64.0 * 64.0 && K <= 4096) return 7;
+  // a short contraction (K <= 64) whose output is at least 32 x 33: the
+  // general 64 x 64 tile.  The autotuner picks it on both benchmark
+  // workloads over the unit-stride-k tiles (1600 x 40 x 40 stages of the
+  // 12-mode tree: 2.05 -> 1.58 ms; 1600 x 720 x 40: 1.07 -> 0.81 ms) and over
+  // the 64 x 32 tile that fits N = 96 or 216 without padding (576 x 96 x 24:
+  // 440 -> 390 us): such a stage is bound by writing its output, and the
+  // padded columns are masked rather than written
+  if (K <= 64 && M >= 32 && N > 32) return 1;
   // prefer big tiles when the grid stays large enough to fill 256 CUs
   struct C {
     int id, bm, bn;
